@@ -1,0 +1,293 @@
+"""RealNVP flow with checkerboard affine coupling layers, FP64.
+
+Paper, Sec. 1: the untrivializing map phi = F^{-1}(z) is a composition of affine
+coupling layers on the even/odd (checkerboard) decomposition of the lattice.  A
+layer leaves one sublattice unchanged and updates the other one by a scale and a
+shift, s and t, that a convolutional network computes from the unchanged
+sublattice (coupling-layer equation); the Jacobian of a layer is triangular, so
+its log-determinant is the sum of s over the updated sites (Sec. 1, the O(N)
+Jacobian remark).  The model density is the prior density pushed through the map
+(Sec. 1, P^(ML) equation), and training minimises the shifted reverse
+Kullback-Leibler divergence E_q[ln q - ln p] - ln Z = E_q[ln q + S].
+
+Readings of the paper used here (every one is listed with its reason in the
+design notes):
+  * Direction: a layer in the sampling direction is x_A <- x_A exp(s) + t on the
+    active sites A; its log|det| is +sum_A s.  (The paper writes the layer in the
+    trivializing direction; an affine coupling's inverse is again affine, so the
+    family is the same.)
+  * Density: log q(phi) = log r(z) - log|det dF^{-1}/dz| (change of variables;
+    the paper's P^(ML) equation places the Jacobian on the other side).
+  * Masks: site parity p(n) = (sum_mu n_mu) mod 2 with 0-based coordinates;
+    layer l freezes the sites with p(n) = (l + parity0) mod 2; strict
+    alternation.
+  * Network: input is the full lattice as one channel with active sites zeroed;
+    conv(1->C) + LeakyReLU(0.01), conv(C->C) + LeakyReLU(0.01), conv(C->2);
+    channel 0 is s (tanh applied when final_tanh), channel 1 is t; kernel 3 per
+    axis, periodic padding, cross-correlation with bias; s and t are read at the
+    active sites only.  LeakyReLU'(0) is taken as 1.
+  * Loss: the batch mean of log q + S with z held fixed (path-wise gradient).
+
+Parameter layout (shared data contract): per layer W1[C][1][T], b1[C],
+W2[C][C][T], b2[C], W3[2][C][T], b3[2]; taps row-major over delta in
+{-1,0,1}^dim, axis 0 slowest.
+
+Pinned by: identity and pure-shift flows, a uniform-scale flow whose q is a known
+Gaussian (importance-sampling estimate of a free-field ln Z), invertibility,
+brute-force Jacobian determinants on L <= 4, one-hot convolution orientation,
+hand-computed single-layer values, and central finite differences of the loss
+for the adjoint gradient.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass
+
+import numpy as np
+
+from .action import action as _action, force as _force
+from .prior import log_prior
+
+LEAKY_SLOPE = 0.01
+
+
+@dataclass(frozen=True)
+class FlowShape:
+    dim: int
+    L: int
+    n_layers: int
+    hidden: int
+    final_tanh: bool = True
+    parity0: int = 0
+
+    @property
+    def V(self) -> int:
+        return self.L ** self.dim
+
+    @property
+    def T(self) -> int:
+        return 3 ** self.dim
+
+    @property
+    def lattice(self) -> tuple:
+        return (self.L,) * self.dim
+
+
+def tap_offsets(dim: int):
+    """Offsets delta in {-1,0,1}^dim, row-major (axis 0 slowest)."""
+    return list(itertools.product((-1, 0, 1), repeat=dim))
+
+
+def unpack(params, fs: FlowShape):
+    """Split the packed parameter vector into per-layer (W1, b1, W2, b2, W3, b3) in FP64."""
+    p = np.asarray(params, dtype=np.float64).ravel()
+    C, T = fs.hidden, fs.T
+    layers, off = [], 0
+
+    def take(n, shape):
+        nonlocal off
+        a = p[off:off + n].reshape(shape)
+        off += n
+        return a
+
+    for _ in range(fs.n_layers):
+        W1 = take(C * T, (C, 1, T))
+        b1 = take(C, (C,))
+        W2 = take(C * C * T, (C, C, T))
+        b2 = take(C, (C,))
+        W3 = take(2 * C * T, (2, C, T))
+        b3 = take(2, (2,))
+        layers.append((W1, b1, W2, b2, W3, b3))
+    if off != p.size:
+        raise ValueError(f"parameter vector has {p.size} entries, layout needs {off}")
+    return layers
+
+
+def pack(layers) -> np.ndarray:
+    return np.concatenate([np.concatenate([a.ravel() for a in lay]) for lay in layers])
+
+
+def shifted(u, delta, dim: int):
+    """v with v[..., n] = u[..., (n + delta) mod L] over the trailing dim axes."""
+    axes = tuple(range(u.ndim - dim, u.ndim))
+    return np.roll(u, shift=tuple(-d for d in delta), axis=axes)
+
+
+def conv(u, W, b, dim: int):
+    """Periodic cross-correlation with bias.
+
+    u: [B, Cin, *lattice], W: [Cout, Cin, T], b: [Cout]
+    out[b, co, n] = b[co] + sum_ci sum_t W[co, ci, t] u[b, ci, n + delta_t]
+    """
+    out = np.broadcast_to(b.reshape((1, -1) + (1,) * dim),
+                          (u.shape[0], W.shape[0]) + u.shape[2:]).copy()
+    for t, d in enumerate(tap_offsets(dim)):
+        out += np.einsum("oi,bi...->bo...", W[:, :, t], shifted(u, d, dim))
+    return out
+
+
+def conv_transpose(g, W, dim: int):
+    """Adjoint of `conv` w.r.t. its input: g_u[b, ci, m] = sum_co sum_t W[co,ci,t] g[b, co, m - delta_t]."""
+    out = np.zeros((g.shape[0], W.shape[1]) + g.shape[2:])
+    for t, d in enumerate(tap_offsets(dim)):
+        out += np.einsum("oi,bo...->bi...", W[:, :, t], shifted(g, tuple(-x for x in d), dim))
+    return out
+
+
+def conv_weight_grad(g, u, dim: int):
+    """dW[co, ci, t] = sum_b sum_n g[b, co, n] u[b, ci, n + delta_t]; db[co] = sum g."""
+    T = 3 ** dim
+    dW = np.zeros((g.shape[1], u.shape[1], T))
+    for t, d in enumerate(tap_offsets(dim)):
+        us = shifted(u, d, dim)
+        dW[:, :, t] = np.einsum("bon,bin->oi", g.reshape(g.shape[0], g.shape[1], -1),
+                                us.reshape(us.shape[0], us.shape[1], -1))
+    db = g.sum(axis=tuple(i for i in range(g.ndim) if i != 1))
+    return dW, db
+
+
+def leaky(a):
+    return np.where(a >= 0, a, LEAKY_SLOPE * a)
+
+
+def leaky_grad(a):
+    return np.where(a >= 0, 1.0, LEAKY_SLOPE)
+
+
+def parity(fs: FlowShape) -> np.ndarray:
+    """p(n) = (sum_mu n_mu) mod 2 on the lattice, 0-based coordinates."""
+    grids = np.meshgrid(*[np.arange(fs.L)] * fs.dim, indexing="ij")
+    return (sum(grids) % 2).astype(np.int64)
+
+
+def frozen_mask(fs: FlowShape, layer: int) -> np.ndarray:
+    return (parity(fs) == (layer + fs.parity0) % 2).astype(np.float64)
+
+
+def net(x, lay, mF, fs: FlowShape):
+    """s/t network of one layer.  Returns (a1, h1, a2, h2, o, s, t)."""
+    W1, b1, W2, b2, W3, b3 = lay
+    h0 = (x * mF)[:, None]
+    a1 = conv(h0, W1, b1, fs.dim)
+    h1 = leaky(a1)
+    a2 = conv(h1, W2, b2, fs.dim)
+    h2 = leaky(a2)
+    o = conv(h2, W3, b3, fs.dim)
+    s = np.tanh(o[:, 0]) if fs.final_tanh else o[:, 0]
+    t = o[:, 1]
+    return a1, h1, a2, h2, o, s, t
+
+
+def coupling_forward(x, lay, layer: int, fs: FlowShape):
+    """One layer in the sampling direction.  Returns (y, sum_A s per sample)."""
+    mF = frozen_mask(fs, layer)
+    mA = 1.0 - mF
+    *_, s, t = net(x, lay, mF, fs)
+    y = np.where(mA > 0, x * np.exp(s) + t, x)
+    ax = tuple(range(1, x.ndim))
+    return y, np.sum(mA * s, axis=ax)
+
+
+def coupling_inverse(y, lay, layer: int, fs: FlowShape):
+    """Inverse of `coupling_forward`: s, t depend only on the frozen sites, which are unchanged."""
+    mF = frozen_mask(fs, layer)
+    mA = 1.0 - mF
+    *_, s, t = net(y, lay, mF, fs)
+    x = np.where(mA > 0, (y - t) * np.exp(-s), y)
+    ax = tuple(range(1, y.ndim))
+    return x, np.sum(mA * s, axis=ax)
+
+
+def as_lattice(z, fs: FlowShape):
+    z = np.asarray(z, dtype=np.float64)
+    return z.reshape((z.shape[0],) + fs.lattice)
+
+
+def flow_forward(params, z, fs: FlowShape, return_saved: bool = False):
+    """phi = F^{-1}(z) with log q.  Returns dict(phi, logdet, logr, logq[, saved])."""
+    layers = unpack(params, fs)
+    x = as_lattice(z, fs)
+    logdet = np.zeros(x.shape[0])
+    saved = [x]
+    for l, lay in enumerate(layers):
+        x, ld = coupling_forward(x, lay, l, fs)
+        logdet = logdet + ld
+        saved.append(x)
+    logr = log_prior(z)
+    out = dict(phi=x, logdet=logdet, logr=logr, logq=logr - logdet)
+    if return_saved:
+        out["saved"] = saved
+    return out
+
+
+def flow_inverse(params, phi, fs: FlowShape):
+    """z = F(phi) and the log-determinant of F^{-1} at z (for tests)."""
+    layers = unpack(params, fs)
+    x = as_lattice(phi, fs)
+    logdet = np.zeros(x.shape[0])
+    for l in reversed(range(fs.n_layers)):
+        x, ld = coupling_inverse(x, layers[l], l, fs)
+        logdet = logdet + ld
+    return x, logdet
+
+
+def log_weights(S, logq):
+    """log w = log p - log q up to ln Z: w = -S - log q (FP64)."""
+    return -np.asarray(S, dtype=np.float64) - np.asarray(logq, dtype=np.float64)
+
+
+def kl_loss(params, z, fs: FlowShape, m2, lam) -> float:
+    """Shifted reverse KL, batch mean of log q + S, with z fixed."""
+    f = flow_forward(params, z, fs)
+    S = _action(f["phi"], m2, lam, fs.dim)
+    return float(np.mean(f["logq"] + S))
+
+
+def flow_vjp(params, z, fs: FlowShape, g_phi, g_logq):
+    """Vector-Jacobian product of (phi, log q) = flow_forward(params, z) w.r.t. (params, z).
+
+    g_phi: [B, *lattice] or [B, V]; g_logq: [B] or scalar.  Returns (g_params packed, g_z [B, V]).
+    Hand-derived adjoint, layer by layer in reverse, recomputing each layer's network
+    from the layer's input field.
+    """
+    layers = unpack(params, fs)
+    f = flow_forward(params, z, fs, return_saved=True)
+    saved = f["saved"]
+    B = saved[0].shape[0]
+    g_logq = np.broadcast_to(np.asarray(g_logq, dtype=np.float64), (B,))
+    g_ld = -g_logq                                   # log q = log r - logdet
+    shp = (B,) + (1,) * fs.dim
+    gx = np.asarray(g_phi, dtype=np.float64).reshape((B,) + fs.lattice)
+    grads = [None] * fs.n_layers
+    for l in reversed(range(fs.n_layers)):
+        W1, b1, W2, b2, W3, b3 = layers[l]
+        x = saved[l]
+        mF = frozen_mask(fs, l)
+        mA = 1.0 - mF
+        a1, h1, a2, h2, o, s, t = net(x, layers[l], mF, fs)
+        es = np.exp(s)
+        g_y = gx
+        g_t = mA * g_y
+        g_s = mA * (g_y * x * es + g_ld.reshape(shp))
+        g_o0 = g_s * (1.0 - s * s) if fs.final_tanh else g_s
+        g_o = np.stack([g_o0, g_t], axis=1)
+        dW3, db3 = conv_weight_grad(g_o, h2, fs.dim)
+        g_a2 = conv_transpose(g_o, W3, fs.dim) * leaky_grad(a2)
+        dW2, db2 = conv_weight_grad(g_a2, h1, fs.dim)
+        g_a1 = conv_transpose(g_a2, W2, fs.dim) * leaky_grad(a1)
+        h0 = (x * mF)[:, None]
+        dW1, db1 = conv_weight_grad(g_a1, h0, fs.dim)
+        g_h0 = conv_transpose(g_a1, W1, fs.dim)[:, 0]
+        gx = np.where(mA > 0, g_y * es, g_y + mF * g_h0)
+        grads[l] = (dW1, db1, dW2, db2, dW3, db3)
+    g_z = gx.reshape(B, -1) - g_logq[:, None] * saved[0].reshape(B, -1)   # d log r / dz = -z
+    return pack(grads), g_z
+
+
+def loss_gradient(params, z, fs: FlowShape, m2, lam):
+    """Gradient of the batch-mean reverse-KL loss w.r.t. the packed parameters, z fixed."""
+    f = flow_forward(params, z, fs)
+    B = f["phi"].shape[0]
+    g_phi = _force(f["phi"], m2, lam, fs.dim) / B
+    g_params, _ = flow_vjp(params, z, fs, g_phi, 1.0 / B)
+    return g_params
