@@ -1,0 +1,237 @@
+/*
+ * lfs.h -- C ABI of the MI355X (gfx950) library for flow-based sampling of
+ * lattice phi^4 theory, after arXiv 2208.08903 (GomalizingFlow.jl).
+ *
+ * The library computes, on one GPU, the data-parallel hot path of the method:
+ * Gaussian prior draws, the RealNVP flow of checkerboard affine coupling layers
+ * with convolutional s/t networks (forward with log q, and its hand-written
+ * backward), the lattice action and its force, log-weights and the reverse-KL
+ * loss, the independence Metropolis-Hastings chain, the HMC baseline, and Adam.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every pointer argument is a DEVICE pointer to contiguous memory, unless
+ *    the argument is documented as host memory.  The caller owns every buffer,
+ *    including the workspace; the library never allocates or frees device
+ *    memory inside these calls and keeps no mutable global state.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *    Calls are asynchronous on that stream: inputs must stay unchanged and
+ *    outputs must not be read until the stream reaches the call.
+ *  - Arguments are validated synchronously, before anything is enqueued.  An
+ *    invalid call returns a negative lfs_status and enqueues nothing.  A failed
+ *    kernel launch returns LFS_EDEVICE.  No exception, print or abort crosses
+ *    the ABI.
+ *  - Lattice fields are stored [B][n_0]...[n_{d-1}] row-major (last axis
+ *    fastest), one sample after another: index b*V + site, V = L^dim.  The
+ *    lattice is periodic in every direction.
+ *  - Site parity is p(n) = (sum_mu n_mu) mod 2 with 0-based coordinates.
+ *  - Results for sample b depend only on sample b's inputs (never on the batch
+ *    size or the sample's position in the batch), except for reductions over
+ *    the batch (g_params, loss), which use a fixed order.  All results are
+ *    bitwise reproducible run to run.
+ */
+#ifndef LFS_H
+#define LFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (negative = error). */
+typedef enum lfs_status {
+  LFS_OK = 0,
+  LFS_EINVAL = -1,       /* invalid argument: shape, null pointer, range */
+  LFS_EUNSUPPORTED = -2, /* valid but not supported (e.g. hidden not in {8,16,32}) */
+  LFS_EWORKSPACE = -3,   /* workspace smaller than lfs_workspace_bytes() */
+  LFS_EDEVICE = -4       /* HIP launch / device error */
+} lfs_status;
+
+/* Arithmetic form of the flow and of the per-sample sums.
+ *   LFS_PLAIN_FP32: convolutions with FP32 operands and FP32 accumulation;
+ *                   log-det and action sums accumulated in FP32.
+ *   LFS_BF16_CONV:  convolution operands rounded to BF16 (matrix cores),
+ *                   FP32 accumulation; log-det, action, log-weights and all
+ *                   ratios accumulated in FP64. */
+typedef enum lfs_precision { LFS_PLAIN_FP32 = 0, LFS_BF16_CONV = 1 } lfs_precision;
+
+/* Kernel family used for the flow.  AUTO picks the fused LDS-resident kernels
+ * when the shape has one, else the generic kernels (same results up to
+ * floating-point summation order). */
+typedef enum lfs_algo { LFS_ALGO_AUTO = 0, LFS_ALGO_GENERIC = 1, LFS_ALGO_FUSED = 2 } lfs_algo;
+
+/* Flow architecture (paper Sec. 1, coupling-layer and composition equations;
+ * the example parameter file fixes kernel_size 3, inC 1, outC 2).
+ *   dim        lattice dimension, 2 or 3
+ *   L          lattice extent, even and >= 2 (the checkerboard needs even L)
+ *   n_layers   number of coupling layers N >= 1; layer l freezes the sites of
+ *              parity (l + parity0) mod 2 and updates the others
+ *   hidden     channels C of the two hidden convolutions: 8, 16 or 32
+ *   final_tanh 1: s = tanh(o_0); 0: s = o_0
+ *   parity0    0 or 1
+ *   precision  lfs_precision
+ *   algo       lfs_algo */
+typedef struct lfs_flow_desc {
+  int32_t dim;
+  int32_t L;
+  int32_t n_layers;
+  int32_t hidden;
+  int32_t final_tanh;
+  int32_t parity0;
+  int32_t precision;
+  int32_t algo;
+} lfs_flow_desc;
+
+/* Persistent state of one independence Metropolis-Hastings chain (device POD,
+ * caller-owned; zero-initialise a new chain).
+ *   w_cur      log-weight of the current configuration
+ *   idx_cur    global proposal number of the current configuration
+ *   n_acc      accepted proposals (the seeding proposal is not counted)
+ *   n_seen     proposals seen so far (the global number of the next one)
+ *   has_state  0 until the first proposal has seeded the chain */
+typedef struct lfs_chain_state {
+  double w_cur;
+  int64_t idx_cur;
+  int64_t n_acc;
+  int64_t n_seen;
+  int32_t has_state;
+  int32_t reserved;
+} lfs_chain_state;
+
+/* Human-readable name of a status code (static string). */
+const char* lfs_status_string(int32_t status);
+
+/* Library version string (static). */
+const char* lfs_version(void);
+
+/* Number of FP32 parameters of the packed flow parameter vector.
+ * Layout, per layer l = 0..N-1 in order, with C = hidden and T = 3^dim taps:
+ *   W1[C][1][T]  b1[C]  W2[C][C][T]  b2[C]  W3[2][C][T]  b3[2]
+ * Taps are row-major over delta in {-1,0,1}^dim, axis 0 slowest; channel 0 of
+ * the last convolution is s, channel 1 is t.  Returns 0 for an invalid desc. */
+size_t lfs_param_count(const lfs_flow_desc* desc);
+
+/* Workspace bytes needed by lfs_flow_forward (for_backward = 0) or
+ * lfs_flow_backward (for_backward = 1) at batch size B.  Writes *bytes. */
+int32_t lfs_workspace_bytes(const lfs_flow_desc* desc, int32_t B, int32_t for_backward,
+                            size_t* bytes);
+
+/* Prior draw (paper Sec. 1, the point-wise independent trivial distribution;
+ * example parameter file: Normal{Float32}(0, 1)).
+ * Writes z[B][V] (FP32, V = sites per sample, a multiple of 4) with standard
+ * normals and, if logr is not NULL, logr[B] = -1/2 sum z^2 - (V/2) ln(2 pi)
+ * (FP64 sum of the FP32 values).  Random numbers: Philox4x32-10 (Salmon et
+ * al., SC'11) under key (lo32(key), hi32(key)); sample b, sites 4j..4j+3 use
+ * counter (j, lo32(counter0+b), hi32(counter0+b), 0); each output word x maps
+ * to u = (floor(x/2^9) + 1/2) 2^-23; words (u0,u1) and (u2,u3) give two
+ * Box-Muller pairs r cos(2 pi u_b), r sin(2 pi u_b), r = sqrt(-2 ln u_a).
+ * Errors: EINVAL if B <= 0, V <= 0, V % 4 != 0, z == NULL or z not 16-byte
+ * aligned. */
+int32_t lfs_prior_normal(uint64_t key, uint64_t counter0, int32_t B, int32_t V, float* z,
+                         double* logr, void* stream);
+
+/* Flow forward in the sampling direction, phi = F^{-1}(z) (paper Sec. 1,
+ * untrivializing map and coupling-layer equation).  For every layer the
+ * frozen sublattice is fed (active sites zeroed) through
+ * conv(1->C)+LeakyReLU(0.01), conv(C->C)+LeakyReLU(0.01), conv(C->2), all 3^dim
+ * periodic cross-correlations with bias; s = tanh(o_0) (or o_0), t = o_1; the
+ * active sites become x exp(s) + t and the log-determinant grows by the sum
+ * of s over them.
+ *   params    [lfs_param_count] FP32, packed as documented above
+ *   z         [B][V] FP32 prior sample (read only)
+ *   phi       [B][V] FP32 output (may alias z)
+ *   logq      [B] FP64 output: log r(z) - log|det dF^{-1}/dz|
+ *   logdet    [B] FP64 output or NULL: log|det dF^{-1}/dz|
+ *   saved_x   [(N+1)][B][V] FP32 output or NULL: the field entering each
+ *             layer, then phi; required later by lfs_flow_backward
+ *   ws        workspace of at least lfs_workspace_bytes(desc, B, 0) bytes
+ * Errors: EINVAL (desc, B, nulls), EUNSUPPORTED (hidden), EWORKSPACE. */
+int32_t lfs_flow_forward(const lfs_flow_desc* desc, const float* params, int32_t B,
+                         const float* z, float* phi, double* logq, double* logdet,
+                         float* saved_x, void* ws, size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of lfs_flow_forward's outputs (phi, log q) with
+ * respect to its inputs (params, z): the hand-written backward of the
+ * coupling stack.  Layers are processed in reverse; each layer recomputes its
+ * hidden activations from its saved input field (only the N+1 boundary
+ * fields are kept).  For the shifted reverse-KL loss of the paper, mean over
+ * the batch of log q + S, pass g_phi = dS/dphi / B and g_logq = 1/B.
+ *   saved_x   [(N+1)][B][V] FP32, as written by lfs_flow_forward
+ *   g_phi     [B][V] FP32 cotangent of phi
+ *   g_logq    cotangent of log q, the same for every sample
+ *   g_params  [lfs_param_count] FP32 output (overwritten, sum over the batch
+ *             in a fixed order)
+ *   g_z       [B][V] FP32 output or NULL (includes d log r / dz = -z)
+ *   ws        workspace of at least lfs_workspace_bytes(desc, B, 1) bytes
+ * Errors: as lfs_flow_forward. */
+int32_t lfs_flow_backward(const lfs_flow_desc* desc, const float* params, int32_t B,
+                          const float* saved_x, const float* g_phi, double g_logq,
+                          float* g_params, float* g_z, void* ws, size_t ws_bytes, void* stream);
+
+/* Lattice action (paper Sec. 1, action, Laplacian and potential equations):
+ *   S = sum_n [ -phi(n) sum_mu (phi(n+mu) + phi(n-mu) - 2 phi(n))
+ *               + m^2 phi(n)^2 + lambda phi(n)^4 ]
+ * and, if force != NULL, force = force_scale * dS/dphi with
+ *   dS/dphi(n) = -2 Lap phi(n) + 2 m^2 phi(n) + 4 lambda phi(n)^3.
+ *   phi        [B][V] FP32
+ *   m2, lam    FP64, [B] if per_sample else [1]
+ *   precision  LFS_BF16_CONV: per-site terms and the sum in FP64;
+ *              LFS_PLAIN_FP32: in FP32 (stored widened)
+ *   S          [B] FP64 output
+ *   force      [B][V] FP32 output or NULL
+ * Errors: EINVAL (dim not 2/3, L < 2, B <= 0, nulls). */
+int32_t lfs_action(int32_t dim, int32_t L, int32_t B, const float* phi, const double* m2,
+                   const double* lam, int32_t per_sample, int32_t precision, double* S,
+                   float* force, double force_scale, void* stream);
+
+/* Log-weights and loss (paper Sec. 1: target exp(-S)/Z, model density q, and
+ * the shifted reverse Kullback-Leibler divergence):
+ *   logw[b] = -S[b] - logq[b]   (FP64)
+ *   loss    = (1/B) sum_b (logq[b] + S[b])   (FP64 scalar, fixed order), if
+ *             loss != NULL.
+ * Errors: EINVAL (B <= 0, nulls). */
+int32_t lfs_log_weights(int32_t B, const double* S, const double* logq, double* logw,
+                        double* loss, void* stream);
+
+/* Independence Metropolis-Hastings chains (paper Sec. 1, the
+ * Metropolis-Hastings test that corrects flow proposals to exp(-S)/Z).
+ * Chain c reads proposals k = 0..n_prop-1 at logw[c*n_prop + k] and
+ * log_u[c*n_prop + k].  The first proposal a chain ever sees seeds it
+ * (accepted = 1, not counted).  Otherwise the proposal is accepted iff
+ * log_u < logw - w_cur, evaluated as one FP64 subtraction and one compare.
+ *   state     [n_chains] lfs_chain_state, read and updated
+ *   cur_idx   [n_chains][n_prop] int64 output: global proposal number of the
+ *             chain's configuration after each proposal
+ *   accepted  [n_chains][n_prop] uint8 output, or NULL
+ * Errors: EINVAL (n_chains <= 0, n_prop <= 0, nulls). */
+int32_t lfs_mh_chain(int32_t n_chains, int32_t n_prop, const double* logw, const double* log_u,
+                     lfs_chain_state* state, int64_t* cur_idx, uint8_t* accepted, void* stream);
+
+/* HMC trajectory per chain, the paper's comparison baseline (Sec. 2.2):
+ * H = 1/2 sum pi^2 + S(phi); n_steps leapfrog steps of size dt in
+ * kick-drift-kick form with the force above; dH = H_end - H_start; accept iff
+ * log_u < -dH, else phi is restored.  All arithmetic in FP64.
+ *   phi       [B][V] FP64, updated in place
+ *   pi0       [B][V] FP64 momenta (read only)
+ *   log_u     [B] FP64
+ *   m2, lam   FP64, [B] if per_sample else [1]
+ *   dH        [B] FP64 output;  accepted [B] uint8 output
+ * Errors: EINVAL (shape, n_steps < 0, nulls); EUNSUPPORTED if V > 4096. */
+int32_t lfs_hmc_step(int32_t dim, int32_t L, int32_t B, double* phi, const double* pi0,
+                     const double* log_u, const double* m2, const double* lam, int32_t per_sample,
+                     int32_t n_steps, double dt, double* dH, uint8_t* accepted, void* stream);
+
+/* Adam step t >= 1 (example parameter file: opt = Adam, base_lr = 1e-3), FP32:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+ * Errors: EINVAL (n <= 0, t < 1, nulls). */
+int32_t lfs_adam_step(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                      float b2, float eps, int64_t t, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LFS_H */

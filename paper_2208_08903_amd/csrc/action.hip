@@ -1,0 +1,103 @@
+// Lattice phi^4 action and force (paper Sec. 1, action, Laplacian and
+// potential equations), and the log-weights / reverse-KL loss.
+#include "lfs_common.hpp"
+
+namespace lfs {
+namespace {
+
+// One block per sample; the sample's field is staged in LDS (V <= 16384).
+template <int DIM, typename R>
+__global__ void __launch_bounds__(256) k_action(int L, const float* __restrict__ phi,
+                                                const double* __restrict__ m2p,
+                                                const double* __restrict__ lamp, int per_sample,
+                                                double* __restrict__ S, float* __restrict__ force,
+                                                double force_scale) {
+  extern __shared__ float f[];
+  __shared__ R sh[16];
+  const int b = blockIdx.x;
+  int V = L;
+  for (int i = 1; i < DIM; ++i) V *= L;
+  const float* pb = phi + (size_t)b * V;
+  for (int n = threadIdx.x; n < V; n += blockDim.x) f[n] = pb[n];
+  __syncthreads();
+  const R m2 = (R)m2p[per_sample ? b : 0], lam = (R)lamp[per_sample ? b : 0];
+  const R scale = (R)force_scale;
+  R acc = 0;
+  // Plus-direction neighbours are taps with exactly one +1 offset.
+  for (int n = threadIdx.x; n < V; n += blockDim.x) {
+    const R p = (R)f[n];
+    R nb = 0;
+    int stride = 1;
+#pragma unroll
+    for (int mu = DIM - 1; mu >= 0; --mu) {
+      const int c = (n / stride) % L;
+      const int up = (c == L - 1) ? n - (L - 1) * stride : n + stride;
+      const int dn = (c == 0) ? n + (L - 1) * stride : n - stride;
+      nb += (R)f[up] + (R)f[dn];
+      stride *= L;
+    }
+    const R lap = nb - (R)(2 * DIM) * p;
+    const R p2 = p * p;
+    acc += -p * lap + m2 * p2 + lam * p2 * p2;
+    if (force)
+      force[(size_t)b * V + n] = (float)(scale * ((R)-2 * lap + (R)2 * m2 * p + (R)4 * lam * p2 * p));
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) S[b] = (double)acc;
+}
+
+// logw = -S - logq per sample; loss = mean(logq + S) in a fixed order (one block).
+__global__ void __launch_bounds__(256) k_log_weights(int B, const double* __restrict__ S,
+                                                     const double* __restrict__ logq,
+                                                     double* __restrict__ logw,
+                                                     double* __restrict__ loss) {
+  __shared__ double sh[16];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    const double w = -S[b] - logq[b];
+    logw[b] = w;
+    acc += logq[b] + S[b];
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0 && loss) *loss = acc / (double)B;
+}
+
+}  // namespace
+}  // namespace lfs
+
+extern "C" int32_t lfs_action(int32_t dim, int32_t L, int32_t B, const float* phi, const double* m2,
+                              const double* lam, int32_t per_sample, int32_t precision, double* S,
+                              float* force, double force_scale, void* stream) {
+  LFS_RETURN_IF(dim != 2 && dim != 3, LFS_EINVAL);
+  LFS_RETURN_IF(L < 2 || B <= 0 || !phi || !m2 || !lam || !S, LFS_EINVAL);
+  LFS_RETURN_IF(precision != LFS_PLAIN_FP32 && precision != LFS_BF16_CONV, LFS_EINVAL);
+  const long V = dim == 2 ? (long)L * L : (long)L * L * L;
+  LFS_RETURN_IF(V > 16384, LFS_EUNSUPPORTED);
+  const size_t shm = (size_t)V * sizeof(float);
+  hipStream_t st = (hipStream_t)stream;
+  const bool f64 = precision == LFS_BF16_CONV;
+  if (dim == 2) {
+    if (f64)
+      hipLaunchKernelGGL((lfs::k_action<2, double>), dim3(B), dim3(256), shm, st, L, phi, m2, lam,
+                         per_sample, S, force, force_scale);
+    else
+      hipLaunchKernelGGL((lfs::k_action<2, float>), dim3(B), dim3(256), shm, st, L, phi, m2, lam,
+                         per_sample, S, force, force_scale);
+  } else {
+    if (f64)
+      hipLaunchKernelGGL((lfs::k_action<3, double>), dim3(B), dim3(256), shm, st, L, phi, m2, lam,
+                         per_sample, S, force, force_scale);
+    else
+      hipLaunchKernelGGL((lfs::k_action<3, float>), dim3(B), dim3(256), shm, st, L, phi, m2, lam,
+                         per_sample, S, force, force_scale);
+  }
+  return lfs::launch_status();
+}
+
+extern "C" int32_t lfs_log_weights(int32_t B, const double* S, const double* logq, double* logw,
+                                   double* loss, void* stream) {
+  LFS_RETURN_IF(B <= 0 || !S || !logq || !logw, LFS_EINVAL);
+  hipLaunchKernelGGL(lfs::k_log_weights, dim3(1), dim3(256), 0, (hipStream_t)stream, B, S, logq,
+                     logw, loss);
+  return lfs::launch_status();
+}

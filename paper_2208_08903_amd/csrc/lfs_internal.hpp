@@ -1,0 +1,47 @@
+// Host-side internal interface between the C ABI and the flow kernel families.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "lfs.h"
+
+namespace lfs {
+
+// Geometry of a validated flow descriptor and offsets into the packed
+// parameter vector (per layer: W1[C][1][T] b1[C] W2[C][C][T] b2[C] W3[2][C][T] b3[2]).
+struct FlowGeom {
+  int dim, L, V, T, N, C;
+  int final_tanh, parity0, precision, algo;
+  size_t off_W1, off_b1, off_W2, off_b2, off_W3, off_b3;  // within a layer
+  size_t P_layer, P_total;
+
+  int frozen_parity(int layer) const { return (layer + parity0) & 1; }
+  bool bf16() const { return precision == LFS_BF16_CONV; }
+};
+
+// Validates desc; returns LFS_OK and fills g, or a negative status.
+int32_t make_geom(const lfs_flow_desc* desc, FlowGeom* g);
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Generic kernels: any supported (dim, L, C), activations staged in HBM.
+size_t generic_ws_bytes(const FlowGeom& g, int B, int for_backward);
+int32_t generic_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
+                        double* logq, double* logdet, float* saved, char* ws, hipStream_t st);
+int32_t generic_backward(const FlowGeom& g, const float* params, int B, const float* saved,
+                         const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                         hipStream_t st);
+
+// Fused kernels: LDS-resident per-sample lattices, matrix-core convolutions.
+bool fused_supported(const FlowGeom& g, int for_backward);
+size_t fused_ws_bytes(const FlowGeom& g, int B, int for_backward);
+int32_t fused_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
+                      double* logq, double* logdet, float* saved, char* ws, hipStream_t st);
+int32_t fused_backward(const FlowGeom& g, const float* params, int B, const float* saved,
+                       const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                       hipStream_t st);
+
+}  // namespace lfs

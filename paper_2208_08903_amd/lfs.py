@@ -1,0 +1,211 @@
+"""ctypes binding of liblfs.so: one Python function per C entry point, same names.
+
+Argument marshalling only: tensors are checked for device, dtype and
+contiguity, their data pointers and torch's current HIP stream are passed
+through, and a negative status raises LfsError.  Every step of the computation
+runs in the library's HIP kernels; there is no fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblfs.so")
+
+LFS_PLAIN_FP32 = 0
+LFS_BF16_CONV = 1
+ALGO_AUTO, ALGO_GENERIC, ALGO_FUSED = 0, 1, 2
+
+c_i32, c_i64, c_u64, c_f32, c_f64, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                                 ctypes.c_float, ctypes.c_double, ctypes.c_void_p,
+                                                 ctypes.c_size_t)
+
+
+class LfsError(RuntimeError):
+    pass
+
+
+class FlowDesc(ctypes.Structure):
+    _fields_ = [("dim", c_i32), ("L", c_i32), ("n_layers", c_i32), ("hidden", c_i32),
+                ("final_tanh", c_i32), ("parity0", c_i32), ("precision", c_i32), ("algo", c_i32)]
+
+    def key(self):
+        return tuple(getattr(self, f) for f, _ in self._fields_)
+
+
+class ChainState(ctypes.Structure):
+    _fields_ = [("w_cur", c_f64), ("idx_cur", c_i64), ("n_acc", c_i64), ("n_seen", c_i64),
+                ("has_state", c_i32), ("reserved", c_i32)]
+
+
+CHAIN_STATE_BYTES = ctypes.sizeof(ChainState)  # 40
+
+_SIGS = {
+    "lfs_status_string": (ctypes.c_char_p, [c_i32]),
+    "lfs_version": (ctypes.c_char_p, []),
+    "lfs_param_count": (c_sz, [ctypes.POINTER(FlowDesc)]),
+    "lfs_workspace_bytes": (c_i32, [ctypes.POINTER(FlowDesc), c_i32, c_i32, ctypes.POINTER(c_sz)]),
+    "lfs_prior_normal": (c_i32, [c_u64, c_u64, c_i32, c_i32, c_vp, c_vp, c_vp]),
+    "lfs_flow_forward": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
+                                 c_vp, c_vp, c_sz, c_vp]),
+    "lfs_flow_backward": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_f64, c_vp,
+                                  c_vp, c_vp, c_sz, c_vp]),
+    "lfs_action": (c_i32, [c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_f64,
+                           c_vp]),
+    "lfs_log_weights": (c_i32, [c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lfs_mh_chain": (c_i32, [c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lfs_hmc_step": (c_i32, [c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32,
+                             c_f64, c_vp, c_vp, c_vp]),
+    "lfs_adam_step": (c_i32, [c_i64, c_vp, c_vp, c_vp, c_vp, c_f32, c_f32, c_f32, c_f32, c_i64,
+                              c_vp]),
+}
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+def load():
+    """Load liblfs.so (built in-tree).  Raises LfsError if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LfsError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype, fn.argtypes = res, args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise LfsError(load().lfs_status_string(status).decode())
+
+
+def status_string(status: int) -> str:
+    return load().lfs_status_string(status).decode()
+
+
+def version() -> str:
+    return load().lfs_version().decode()
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise LfsError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise LfsError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise LfsError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_desc(dim, L, n_layers, hidden, final_tanh=True, parity0=0,
+              precision=LFS_PLAIN_FP32, algo=ALGO_AUTO) -> FlowDesc:
+    return FlowDesc(dim, L, n_layers, hidden, int(final_tanh), parity0, precision, algo)
+
+
+def param_count(desc: FlowDesc) -> int:
+    return int(load().lfs_param_count(ctypes.byref(desc)))
+
+
+def workspace_bytes(desc: FlowDesc, B: int, for_backward: bool) -> int:
+    out = c_sz(0)
+    _check(load().lfs_workspace_bytes(ctypes.byref(desc), B, int(for_backward), ctypes.byref(out)))
+    return int(out.value)
+
+
+def prior_normal(key: int, counter0: int, z, logr=None):
+    B, V = z.shape
+    _check(load().lfs_prior_normal(key, counter0, B, V, _p(z, torch.float32, "z"),
+                                   _p(logr, torch.float64, "logr"), _stream()))
+
+
+def flow_forward(desc, params, z, phi, logq, logdet=None, saved_x=None, ws=None):
+    B = z.shape[0]
+    nbytes = ws.numel() if ws is not None else 0
+    _check(load().lfs_flow_forward(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
+                                   _p(z, torch.float32, "z"), _p(phi, torch.float32, "phi"),
+                                   _p(logq, torch.float64, "logq"),
+                                   _p(logdet, torch.float64, "logdet"),
+                                   _p(saved_x, torch.float32, "saved_x"),
+                                   _p(ws, torch.uint8, "ws"), nbytes, _stream()))
+
+
+def flow_backward(desc, params, saved_x, g_phi, g_logq: float, g_params, g_z=None, ws=None):
+    B = g_phi.shape[0]
+    nbytes = ws.numel() if ws is not None else 0
+    _check(load().lfs_flow_backward(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
+                                    _p(saved_x, torch.float32, "saved_x"),
+                                    _p(g_phi, torch.float32, "g_phi"), float(g_logq),
+                                    _p(g_params, torch.float32, "g_params"),
+                                    _p(g_z, torch.float32, "g_z"), _p(ws, torch.uint8, "ws"),
+                                    nbytes, _stream()))
+
+
+def action(dim, L, phi, m2, lam, S, force=None, force_scale=1.0, precision=LFS_BF16_CONV):
+    B = phi.shape[0]
+    per_sample = int(m2.numel() > 1)
+    if m2.numel() not in (1, B) or lam.numel() != m2.numel():
+        raise LfsError("m2 and lam must both have 1 or B entries")
+    _check(load().lfs_action(dim, L, B, _p(phi, torch.float32, "phi"), _p(m2, torch.float64, "m2"),
+                             _p(lam, torch.float64, "lam"), per_sample, precision,
+                             _p(S, torch.float64, "S"), _p(force, torch.float32, "force"),
+                             float(force_scale), _stream()))
+
+
+def log_weights(S, logq, logw, loss=None):
+    _check(load().lfs_log_weights(S.shape[0], _p(S, torch.float64, "S"),
+                                  _p(logq, torch.float64, "logq"), _p(logw, torch.float64, "logw"),
+                                  _p(loss, torch.float64, "loss"), _stream()))
+
+
+def new_chain_state(n_chains: int, device="cuda"):
+    """Zero-initialised lfs_chain_state array as raw bytes on the device."""
+    return torch.zeros(n_chains * CHAIN_STATE_BYTES, dtype=torch.uint8, device=device)
+
+
+def decode_chain_state(buf):
+    """Host view of a chain-state byte tensor: list of dicts."""
+    raw = buf.cpu().numpy().tobytes()
+    out = []
+    for i in range(len(raw) // CHAIN_STATE_BYTES):
+        cs = ChainState.from_buffer_copy(raw[i * CHAIN_STATE_BYTES:(i + 1) * CHAIN_STATE_BYTES])
+        out.append({f: getattr(cs, f) for f, _ in ChainState._fields_ if f != "reserved"})
+    return out
+
+
+def mh_chain(logw, log_u, state, cur_idx, accepted=None):
+    n_chains, n_prop = logw.shape
+    if state.numel() < n_chains * CHAIN_STATE_BYTES:
+        raise LfsError("chain state buffer too small")
+    _check(load().lfs_mh_chain(n_chains, n_prop, _p(logw, torch.float64, "logw"),
+                               _p(log_u, torch.float64, "log_u"), _p(state, torch.uint8, "state"),
+                               _p(cur_idx, torch.int64, "cur_idx"),
+                               _p(accepted, torch.uint8, "accepted"), _stream()))
+
+
+def hmc_step(dim, L, phi, pi0, log_u, m2, lam, n_steps, dt, dH, accepted):
+    B = phi.shape[0]
+    per_sample = int(m2.numel() > 1)
+    _check(load().lfs_hmc_step(dim, L, B, _p(phi, torch.float64, "phi"),
+                               _p(pi0, torch.float64, "pi0"), _p(log_u, torch.float64, "log_u"),
+                               _p(m2, torch.float64, "m2"), _p(lam, torch.float64, "lam"),
+                               per_sample, n_steps, float(dt), _p(dH, torch.float64, "dH"),
+                               _p(accepted, torch.uint8, "accepted"), _stream()))
+
+
+def adam_step(p, g, m, v, lr, b1, b2, eps, t):
+    _check(load().lfs_adam_step(p.numel(), _p(p, torch.float32, "p"), _p(g, torch.float32, "g"),
+                                _p(m, torch.float32, "m"), _p(v, torch.float32, "v"), lr, b1, b2,
+                                eps, t, _stream()))

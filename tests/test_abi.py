@@ -1,0 +1,90 @@
+"""The C-ABI library loads, exports every symbol include/lfs.h declares, and its
+host-side validation behaves as documented (no GPU call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import seeded_inputs as si
+from paper_2208_08903_amd import lfs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "lfs.h")).read()
+    return sorted(set(re.findall(r"\b(lfs_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_header_function():
+    lib = lfs.load()
+    names = header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(lfs.EXPORTED)
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(lfs.FlowDesc) == 32
+    assert lfs.CHAIN_STATE_BYTES == 40
+
+
+@pytest.mark.parametrize("dim,N,C", [(2, 16, 8), (2, 16, 16), (3, 12, 16), (3, 16, 32)])
+def test_param_count_matches_layout(dim, N, C):
+    d = lfs.make_desc(dim, 8, N, C)
+    assert lfs.param_count(d) == si.param_count(dim, N, C)
+
+
+def test_status_strings_and_version():
+    assert lfs.status_string(0) == "LFS_OK"
+    for s in (-1, -2, -3, -4):
+        assert lfs.status_string(s).startswith("LFS_E")
+    assert "gfx950" in lfs.version()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(dim=4), -1), (dict(L=7), -1), (dict(L=0), -1), (dict(n_layers=0), -1),
+    (dict(hidden=12), -2), (dict(precision=5), -1), (dict(parity0=2), -1), (dict(algo=9), -1),
+])
+def test_descriptor_validation(kw, code):
+    base = dict(dim=2, L=8, n_layers=4, hidden=8)
+    base.update({k: v for k, v in kw.items() if k in base})
+    d = lfs.make_desc(**base)
+    for k in ("precision", "parity0", "algo"):
+        if k in kw:
+            setattr(d, k, kw[k])
+    out = ctypes.c_size_t(0)
+    assert lfs.load().lfs_workspace_bytes(ctypes.byref(d), 4, 0, ctypes.byref(out)) == code
+    assert lfs.param_count(d) == 0
+
+
+def test_null_and_shape_arguments_rejected_before_any_launch():
+    lib = lfs.load()
+    d = lfs.make_desc(2, 8, 4, 8)
+    # null params / z / phi / logq
+    assert lib.lfs_flow_forward(ctypes.byref(d), None, 4, None, None, None, None, None, None, 0,
+                                None) == -1
+    assert lib.lfs_flow_backward(ctypes.byref(d), None, 4, None, None, 0.25, None, None, None, 0,
+                                 None) == -1
+    assert lib.lfs_prior_normal(1, 0, 4, 6, None, None, None) == -1          # V % 4
+    assert lib.lfs_action(4, 8, 4, None, None, None, 0, 1, None, None, 1.0, None) == -1
+    assert lib.lfs_action(2, 256, 4, 1, 1, 1, 0, 1, 1, None, 1.0, None) == -2  # V too large
+    assert lib.lfs_log_weights(0, None, None, None, None, None) == -1
+    assert lib.lfs_mh_chain(1, 0, None, None, None, None, None, None) == -1
+    assert lib.lfs_hmc_step(2, 8, 4, None, None, None, None, None, 0, -1, 0.1, None, None,
+                            None) == -1
+    assert lib.lfs_hmc_step(3, 20, 1, 1, 1, 1, 1, 1, 0, 10, 0.1, 1, 1, None) == -2  # V > 4096
+    assert lib.lfs_adam_step(0, None, None, None, None, 1e-3, 0.9, 0.999, 1e-8, 1, None) == -1
+    assert lib.lfs_adam_step(10, 1, 1, 1, 1, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1  # t < 1
+
+
+def test_workspace_too_small_is_reported():
+    lib = lfs.load()
+    d = lfs.make_desc(2, 8, 4, 8)
+    need = lfs.workspace_bytes(d, 16, False)
+    assert need > 0
+    # non-null dummies: validation must fail on the workspace size before any launch
+    assert lib.lfs_flow_forward(ctypes.byref(d), 1, 16, 1, 1, 1, None, None, 1, need - 1,
+                                None) == -3

@@ -1,0 +1,261 @@
+"""HIP path against the FP64 oracle, element by element, on seeded inputs.
+
+Tolerances (derived in the design notes):
+  prior z          |dz| <= 2e-6 (1 + |z|)       FP32 logf/sincospif vs FP64
+  action FP64 mode |dS| <= 1e-12 |S| + 1e-9     per-site FP64 on FP32 inputs
+  action FP32 mode |dS| <= 1e-4 V               (plain FP32 sums)
+  flow FP32        |dphi| <= 1e-5 (T/9) (1 + |phi|), |dlogq| <= 1e-4 V
+  flow BF16        |dphi| <= 0.02 (T/9) (1 + |phi|), |dlogq| <= 0.05 sqrt(V N) + 1e-4 V
+  gradient FP32    per-block relative 2-norm <= 1e-4
+  gradient BF16    whole-vector relative 2-norm <= 0.1, per block <= 0.4, g_z <= 0.1
+                   (BF16 unit roundoff 2^-9 times the conditioning of short sums on
+                   small lattices; 5e-3 at the 2D L=32 training shape)
+  (T = 3^dim taps: the fan-in of every convolution grows with T.)
+  MH, HMC decisions bit-exact given equal inputs
+"""
+import numpy as np
+import pytest
+import torch
+
+import seeded_inputs as si
+from oracle import action as oa
+from oracle import adam as oadam
+from oracle import flow as of
+from oracle import hmc as ohmc
+from oracle import mh as omh
+from oracle import prior as op
+from paper_2208_08903_amd import lfs
+
+from .gpu_util import DEV, dev, host, rel_norm, run_backward, run_forward
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("B,V,key,c0", [(3, 64, 12345, 0), (5, 1024, 7, 2**33 + 5), (1, 4, 1, 0),
+                                         (257, 512, 2021, 11)])
+def test_prior_matches_oracle(B, V, key, c0):
+    z = torch.empty(B, V, device=DEV, dtype=torch.float32)
+    logr = torch.empty(B, device=DEV, dtype=torch.float64)
+    lfs.prior_normal(key, c0, z, logr)
+    torch.cuda.synchronize()
+    zo = op.prior_normal(key, c0, B, V)
+    zg = host(z).astype(np.float64)
+    assert np.all(np.abs(zg - zo) <= 2e-6 * (1 + np.abs(zo)))
+    np.testing.assert_allclose(host(logr), op.log_prior(zg), rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("dim,L,B", [(2, 2, 3), (2, 8, 64), (2, 32, 16), (3, 2, 4), (3, 8, 32),
+                                     (3, 16, 8), (2, 12, 5)])
+@pytest.mark.parametrize("precision", [lfs.LFS_BF16_CONV, lfs.LFS_PLAIN_FP32])
+def test_action_and_force(dim, L, B, precision):
+    V = L ** dim
+    phi = si.normal_fields(1, B, V)
+    m2, lam = si.couplings(2, B)
+    S = torch.empty(B, device=DEV, dtype=torch.float64)
+    F = torch.empty(B, V, device=DEV, dtype=torch.float32)
+    lfs.action(dim, L, dev(phi, torch.float32), dev(m2, torch.float64), dev(lam, torch.float64), S,
+               F, 0.5, precision)
+    torch.cuda.synchronize()
+    lat = phi.reshape((B,) + (L,) * dim)
+    So = oa.action(lat, m2, lam, dim)
+    Fo = 0.5 * oa.force(lat, m2, lam, dim).reshape(B, V)
+    if precision == lfs.LFS_BF16_CONV:
+        assert np.all(np.abs(host(S) - So) <= 1e-12 * np.abs(So) + 1e-9)
+        np.testing.assert_allclose(host(F), Fo, rtol=2e-7, atol=1e-6)
+    else:
+        assert np.all(np.abs(host(S) - So) <= 1e-4 * V)
+        np.testing.assert_allclose(host(F), Fo, rtol=1e-5, atol=1e-4)
+
+
+def test_action_shared_couplings_constant_field():
+    S = torch.empty(2, device=DEV, dtype=torch.float64)
+    phi = torch.full((2, 64), 0.5, device=DEV, dtype=torch.float32)
+    lfs.action(2, 8, phi, dev([-4.0], torch.float64), dev([8.0], torch.float64), S)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(host(S), [-32.0, -32.0], rtol=0, atol=1e-12)
+
+
+def test_log_weights_and_loss():
+    B = 1000
+    S = np.random.default_rng(3).standard_normal(B) * 50
+    lq = np.random.default_rng(4).standard_normal(B) * 20
+    w = torch.empty(B, device=DEV, dtype=torch.float64)
+    loss = torch.empty(1, device=DEV, dtype=torch.float64)
+    lfs.log_weights(dev(S, torch.float64), dev(lq, torch.float64), w, loss)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(w), of.log_weights(S, lq))
+    np.testing.assert_allclose(host(loss)[0], np.mean(lq + S), rtol=1e-13)
+
+
+@pytest.mark.parametrize("n_chains,n_prop,scale", [(1, 2000, 1.0), (7, 333, 3.0), (64, 130, 0.3)])
+def test_mh_chain_bit_exact(n_chains, n_prop, scale):
+    w = si.logw_stream(5, n_chains * n_prop, scale).reshape(n_chains, n_prop)
+    lu = si.log_uniforms(6, (n_chains, n_prop))
+    state = lfs.new_chain_state(n_chains)
+    cur = torch.empty(n_chains, n_prop, device=DEV, dtype=torch.int64)
+    acc = torch.empty(n_chains, n_prop, device=DEV, dtype=torch.uint8)
+    h = n_prop // 3
+    # two calls with persistent state
+    for sl in (slice(0, h), slice(h, n_prop)):
+        c2 = torch.empty(n_chains, sl.stop - sl.start, device=DEV, dtype=torch.int64)
+        a2 = torch.empty_like(c2, dtype=torch.uint8)
+        lfs.mh_chain(dev(w[:, sl], torch.float64), dev(lu[:, sl], torch.float64), state, c2, a2)
+        cur[:, sl], acc[:, sl] = c2, a2
+    torch.cuda.synchronize()
+    states = lfs.decode_chain_state(state)
+    for c in range(n_chains):
+        co, ao, so = omh.mh_chain(w[c], lu[c])
+        np.testing.assert_array_equal(host(cur[c]), co)
+        np.testing.assert_array_equal(host(acc[c]), ao)
+        assert states[c]["n_acc"] == so.n_acc and states[c]["idx_cur"] == so.idx_cur
+        assert states[c]["n_seen"] == so.n_seen and states[c]["w_cur"] == so.w_cur
+
+
+@pytest.mark.parametrize("dim,L,B,nst,dt", [(3, 8, 16, 10, 0.1), (2, 8, 8, 10, 0.1), (2, 2, 4, 5, 0.05),
+                                            (3, 4, 3, 20, 0.02)])
+def test_hmc_matches_oracle(dim, L, B, nst, dt):
+    V = L ** dim
+    rng = np.random.default_rng(7)
+    phi0 = 0.3 * rng.standard_normal((B, V))
+    pi0 = si.momenta(8, B, V)
+    lu = si.log_uniforms(9, B)
+    m2, lam = si.couplings(10, B)
+    phi = dev(phi0, torch.float64)
+    dH = torch.empty(B, device=DEV, dtype=torch.float64)
+    acc = torch.empty(B, device=DEV, dtype=torch.uint8)
+    lfs.hmc_step(dim, L, phi, dev(pi0, torch.float64), dev(lu, torch.float64),
+                 dev(m2, torch.float64), dev(lam, torch.float64), nst, dt, dH, acc)
+    torch.cuda.synchronize()
+    shp = (B,) + (L,) * dim
+    po, dHo, ao = ohmc.hmc_step(phi0.reshape(shp), pi0.reshape(shp), lu, m2, lam, dim, nst, dt)
+    np.testing.assert_allclose(host(dH), dHo, rtol=0, atol=1e-10 * max(1, np.max(np.abs(dHo))))
+    near = np.abs(lu + dHo) < 1e-9
+    np.testing.assert_array_equal(host(acc)[~near], ao[~near])
+    np.testing.assert_allclose(host(phi)[~near], po.reshape(B, V)[~near], rtol=1e-12, atol=1e-12)
+
+
+def test_adam_matches_oracle():
+    n = 10007
+    rng = np.random.default_rng(11)
+    p0, g = rng.standard_normal(n).astype(np.float32), rng.standard_normal(n).astype(np.float32)
+    p, m, v = dev(p0, torch.float32), torch.zeros(n, device=DEV), torch.zeros(n, device=DEV)
+    po, mo, vo = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t in range(1, 6):
+        gt = dev(g * t, torch.float32)
+        lfs.adam_step(p, gt, m, v, 1e-3, 0.9, 0.999, 1e-8, t)
+        po, mo, vo = oadam.adam_step(po, g * t, mo, vo, t)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(host(p), po, rtol=0, atol=2e-6)
+
+
+FLOW_CASES = [
+    # dim, L, N, C, B
+    (2, 4, 2, 8, 4),
+    (2, 8, 16, 8, 16),      # example parameter file shape
+    (2, 2, 3, 16, 3),       # L = 2: both neighbours along an axis coincide
+    (2, 32, 2, 16, 4),
+    (3, 4, 2, 16, 3),
+    (3, 2, 2, 32, 2),
+    (3, 8, 3, 16, 2),
+    (2, 6, 3, 8, 3),        # L not a power of two
+]
+
+
+def _flow_case(dim, L, N, C, B, precision, algo, tanh=True, parity0=0):
+    desc = lfs.make_desc(dim, L, N, C, final_tanh=tanh, parity0=parity0, precision=precision,
+                         algo=algo)
+    params = si.flow_params(dim, N, C, seed=100 + L, w_std=0.1, b_std=0.05)
+    z = si.normal_fields(200 + L, B, L ** dim)
+    fs = of.FlowShape(dim, L, N, C, final_tanh=tanh, parity0=parity0)
+    return desc, params, z, fs
+
+
+def _check_forward(desc, params, z, fs, precision):
+    B, V = z.shape
+    out = run_forward(desc, params, z)
+    ref = of.flow_forward(params, z, fs, return_saved=True)
+    phi, logq = host(out["phi"]).astype(np.float64), host(out["logq"])
+    phio = ref["phi"].reshape(B, V)
+    tf = fs.T / 9
+    if precision == lfs.LFS_PLAIN_FP32:
+        assert np.all(np.abs(phi - phio) <= 1e-5 * tf * (1 + np.abs(phio)))
+        assert np.all(np.abs(logq - ref["logq"]) <= 1e-4 * V)
+    else:
+        assert np.all(np.abs(phi - phio) <= 0.02 * tf * (1 + np.abs(phio)))
+        assert np.all(np.abs(logq - ref["logq"]) <= 0.05 * np.sqrt(V * fs.n_layers) + 1e-4 * V)
+    saved = host(out["saved"]).reshape(fs.n_layers + 1, B, V)
+    np.testing.assert_array_equal(saved[0], z)
+    np.testing.assert_array_equal(saved[-1], host(out["phi"]))
+    np.testing.assert_allclose(host(out["logdet"]), ref["logdet"],
+                               atol=1e-4 * V if precision == 0 else 0.05 * np.sqrt(V * fs.n_layers) + 1e-4 * V)
+    return out, ref
+
+
+@pytest.mark.parametrize("case", FLOW_CASES)
+@pytest.mark.parametrize("precision", [lfs.LFS_PLAIN_FP32, lfs.LFS_BF16_CONV])
+def test_flow_forward_generic(case, precision):
+    desc, params, z, fs = _flow_case(*case, precision, lfs.ALGO_GENERIC)
+    _check_forward(desc, params, z, fs, precision)
+
+
+@pytest.mark.parametrize("tanh,parity0", [(False, 0), (True, 1)])
+def test_flow_forward_variants(tanh, parity0):
+    desc, params, z, fs = _flow_case(2, 4, 3, 8, 4, lfs.LFS_PLAIN_FP32, lfs.ALGO_GENERIC, tanh, parity0)
+    _check_forward(desc, params, z, fs, lfs.LFS_PLAIN_FP32)
+
+
+def test_flow_forward_aliased_output_and_no_saved():
+    desc, params, z, fs = _flow_case(2, 8, 4, 8, 5, lfs.LFS_PLAIN_FP32, lfs.ALGO_GENERIC)
+    zt = dev(z, torch.float32)
+    logq = torch.empty(5, device=DEV, dtype=torch.float64)
+    ws = torch.empty(lfs.workspace_bytes(desc, 5, False), device=DEV, dtype=torch.uint8)
+    lfs.flow_forward(desc, dev(params, torch.float32), zt, zt, logq, None, None, ws)
+    torch.cuda.synchronize()
+    ref = of.flow_forward(params, z, fs)
+    assert np.all(np.abs(host(zt) - ref["phi"].reshape(5, -1)) <= 1e-5 * (1 + np.abs(ref["phi"].reshape(5, -1))))
+    assert np.all(np.abs(host(logq) - ref["logq"]) <= 1e-4 * 64)
+
+
+def _check_backward(desc, params, z, fs, out, precision):
+    B, V = z.shape
+    rng = np.random.default_rng(300)
+    g_phi = rng.standard_normal((B, V)).astype(np.float32)
+    g_logq = 0.37
+    gp, gz = run_backward(desc, out, g_phi, g_logq)
+    gpo, gzo = of.flow_vjp(params, z, fs, g_phi.astype(np.float64), g_logq)
+    fp32 = precision == lfs.LFS_PLAIN_FP32
+    tol_block = 1e-4 if fp32 else 0.4
+    for lay_g, lay_o in zip(of.unpack(gp, fs), of.unpack(gpo, fs)):
+        for a, b in zip(lay_g, lay_o):
+            assert rel_norm(a, b) <= tol_block, (rel_norm(a, b), a.shape)
+    assert rel_norm(gp, gpo) <= (1e-4 if fp32 else 0.1)
+    assert rel_norm(gz, gzo) <= (1e-4 if fp32 else 0.1)
+    return gp, gpo
+
+
+@pytest.mark.parametrize("case", FLOW_CASES[:6])
+@pytest.mark.parametrize("precision", [lfs.LFS_PLAIN_FP32, lfs.LFS_BF16_CONV])
+def test_flow_backward_generic(case, precision):
+    desc, params, z, fs = _flow_case(*case, precision, lfs.ALGO_GENERIC)
+    out = run_forward(desc, params, z)
+    _check_backward(desc, params, z, fs, out, precision)
+
+
+def test_flow_sample_independence_generic():
+    """Sample b's outputs do not depend on the batch size or its position."""
+    desc, params, z, fs = _flow_case(2, 8, 4, 8, 9, lfs.LFS_BF16_CONV, lfs.ALGO_GENERIC)
+    full = run_forward(desc, params, z)
+    part = run_forward(desc, params, z[4:6])
+    np.testing.assert_array_equal(host(full["phi"])[4:6], host(part["phi"]))
+    np.testing.assert_array_equal(host(full["logq"])[4:6], host(part["logq"]))
+
+
+def test_flow_deterministic_generic():
+    desc, params, z, fs = _flow_case(2, 8, 4, 8, 6, lfs.LFS_PLAIN_FP32, lfs.ALGO_GENERIC)
+    a = run_forward(desc, params, z)
+    b = run_forward(desc, params, z)
+    g = np.random.default_rng(1).standard_normal(z.shape).astype(np.float32)
+    ga, _ = run_backward(desc, a, g, 0.1)
+    gb, _ = run_backward(desc, b, g, 0.1)
+    np.testing.assert_array_equal(host(a["phi"]), host(b["phi"]))
+    np.testing.assert_array_equal(ga, gb)
