@@ -1,16 +1,384 @@
-// Fused flow kernels (placeholder: no shape is covered yet).
-#include "lfs_common.hpp"
+// Fused flow forward: one workgroup per sample with the whole lattice and
+// both hidden activations resident in LDS, all coupling layers in one launch,
+// and every convolution on the matrix cores (implicit GEMM, see
+// fused_common.hpp).  Paper Sec. 1, coupling-layer and composition equations.
+//
+// Per layer l (frozen parity f = (l + parity0) mod 2, active parity 1 - f):
+//   conv1: h1 = leaky(W1 * mask_F x + b1)   over all V sites   (K = T taps)
+//   conv2: h2 = leaky(W2 * h1 + b2)         over all V sites   (K = T C)
+//   conv3: (o0, o1) = W3 * h2 + b3          at the V/2 active sites only
+//          x <- x exp(s) + t, s = tanh(o0) (or o0), t = o1; logdet += sum s
+// Three workgroup barriers per layer separate the phases.
+#include <type_traits>
+
+#include "fused_common.hpp"
 #include "lfs_internal.hpp"
 
 namespace lfs {
-bool fused_supported(const FlowGeom&, int) { return false; }
-size_t fused_ws_bytes(const FlowGeom&, int, int) { return 0; }
-int32_t fused_forward(const FlowGeom&, const float*, int, const float*, float*, double*, double*,
-                      float*, char*, hipStream_t) {
-  return LFS_EUNSUPPORTED;
+namespace fused {
+namespace {
+
+constexpr double kHalfLog2Pi = 0.91893853320467274178;
+
+// Weight fragments in the order the kernels read them (one 16-byte operand per
+// lane): per layer, conv1 [nct][k1], conv2 [nct][k2], conv3 [k2] fragments of
+// 64 lanes.  Rows beyond the output channels and k beyond T*Cin are zero.
+template <bool BF16>
+__global__ void kf_prep(const float* __restrict__ params, int N, int T, int C, int P_layer,
+                        int offW1, int offW2, int offW3, LayerFrags lf, u32x4* __restrict__ frags) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per_layer = (long)lf.total * 64;
+  if (gid >= per_layer * N) return;
+  const int layer = (int)(gid / per_layer);
+  const int rem = (int)(gid % per_layer), f = rem / 64, l = rem % 64;
+  const int j = l >> 4, m = l & 15;
+  const float* p = params + (size_t)layer * P_layer;
+  const float* W;
+  int row, c, cin, cout, kc;
+  if (f < lf.off2) {
+    W = p + offW1, cin = 1, cout = C, kc = lf.k1, row = (f / kc) * 16 + m, c = f % kc;
+  } else if (f < lf.off3) {
+    W = p + offW2, cin = C, cout = C, kc = lf.k2, row = ((f - lf.off2) / kc) * 16 + m,
+    c = (f - lf.off2) % kc;
+  } else {
+    W = p + offW3, cin = C, cout = 2, kc = lf.k2, row = m, c = f - lf.off3;
+  }
+  const int K = T * cin;
+  auto w_at = [&](int k) -> float {
+    if (row >= cout || k >= K) return 0.f;
+    return W[(row * cin + k % cin) * T + k / cin];
+  };
+  u32x4 out;
+  if constexpr (BF16) {
+    const int k0 = 32 * c + 8 * j;
+    for (int q = 0; q < 4; ++q) out[q] = pack_bf16(w_at(k0 + 2 * q), w_at(k0 + 2 * q + 1));
+  } else {
+    const int k0 = 16 * c + 4 * j;
+    for (int q = 0; q < 4; ++q) out[q] = __float_as_uint(w_at(k0 + q));
+  }
+  frags[gid] = out;
 }
+
+template <bool BF16>
+using HElem = std::conditional_t<BF16, uint16_t, float>;
+
+// B operand of a C-input convolution at output site n for K chunk (BF16) /
+// block (FP32) c: the lane's 8 (4) consecutive input channels at one tap.
+template <int DIM, int L, int C, bool BF16>
+__device__ __forceinline__ u32x4 gather_h(const HElem<BF16>* h, int n, int c, int j) {
+  using G = Geo<DIM, L>;
+  constexpr int K = G::T * C;
+  const int k0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
+  if (k0 >= K) return u32x4{0u, 0u, 0u, 0u};
+  const int tap = k0 / C, ci0 = k0 % C;
+  const int nb = G::nbr(n, tap);
+  return *reinterpret_cast<const u32x4*>(h + nb * C + ci0);
+}
+
+// B operand of conv1 (one masked input channel): taps of the lane's K slice.
+template <int DIM, int L, bool BF16>
+__device__ __forceinline__ u32x4 gather_x(const float* xs, int n, int fpar, int c, int j) {
+  using G = Geo<DIM, L>;
+  constexpr int NV = BF16 ? 8 : 4;
+  const int t0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
+  float v[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int t = t0 + i;
+    v[i] = 0.f;
+    if (t < G::T) {
+      const int nb = G::nbr(n, t);
+      if (G::parity(nb) == fpar) v[i] = xs[nb];
+    }
+  }
+  u32x4 r;
+  if constexpr (BF16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = pack_bf16(v[2 * q], v[2 * q + 1]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = __float_as_uint(v[q]);
+  }
+  return r;
+}
+
+// acc += A (fragment) x B (gathered) for one chunk / block.
+template <bool BF16>
+__device__ __forceinline__ f32x4 mma(const u32x4& a, const u32x4& b, f32x4 acc) {
+  if constexpr (BF16) {
+    return mfma(as_bf16x8(a), as_bf16x8(b), acc);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc = mfma(__uint_as_float(a[r]), __uint_as_float(b[r]), acc);
+    return acc;
+  }
+}
+
+// Store leaky(acc + bias) for rows 4j..4j+3 of output-channel tile ct at site n.
+template <int C, bool BF16>
+__device__ __forceinline__ void store_hidden(HElem<BF16>* h, int n, int ct, int j, const f32x4& acc,
+                                             const f32x4& bias) {
+  const int co0 = ct * 16 + 4 * j;
+  if (co0 >= C) return;
+  float v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = leaky(acc[i] + bias[i]);
+  if constexpr (BF16) {
+    u32x2 w{pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3])};
+    *reinterpret_cast<u32x2*>(h + n * C + co0) = w;
+  } else {
+    *reinterpret_cast<f32x4*>(h + n * C + co0) = f32x4{v[0], v[1], v[2], v[3]};
+  }
+}
+
+template <int C>
+__device__ __forceinline__ f32x4 load_bias4(const float* b, int ct, int j) {
+  const int co0 = ct * 16 + 4 * j;
+  f32x4 r{0.f, 0.f, 0.f, 0.f};
+  if (co0 < C) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i] = b[co0 + i];
+  }
+  return r;
+}
+
+template <int DIM, int L, int C, bool BF16>
+struct FwdCfg {
+  using G = Geo<DIM, L>;
+  static constexpr int V = G::V, T = G::T;
+  static constexpr LayerFrags LF = layer_frags(T, C, BF16);
+  static constexpr size_t lds_bytes = (size_t)V * 4 + 2 * (size_t)V * C * sizeof(HElem<BF16>);
+  static constexpr int NT = lds_bytes > 80 * 1024 ? 512 : 256;
+};
+
+template <int DIM, int L, int C, bool BF16, int NT>
+__global__ void __launch_bounds__(NT) kf_forward(
+    const u32x4* __restrict__ frags, const float* __restrict__ params, int P_layer, int off_b1,
+    int off_b2, int off_b3, int N, int parity0, int final_tanh, int B, const float* __restrict__ z,
+    float* __restrict__ phi, float* __restrict__ saved, double* __restrict__ logq,
+    double* __restrict__ logdet) {
+  using Cfg = FwdCfg<DIM, L, C, BF16>;
+  using G = Geo<DIM, L>;
+  using HT = HElem<BF16>;
+  using R = std::conditional_t<BF16, double, float>;
+  constexpr int V = Cfg::V;
+  constexpr LayerFrags LF = Cfg::LF;
+  constexpr int NW = NT / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ R red[16];
+  float* xs = reinterpret_cast<float*>(smem);
+  HT* h1 = reinterpret_cast<HT*>(smem + V * 4);
+  HT* h2 = h1 + V * C;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane >> 4, m = lane & 15;
+  const size_t BV = (size_t)B * V;
+
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    R zz = 0;
+    {
+      const f32x4* zb = reinterpret_cast<const f32x4*>(z + (size_t)b * V);
+      f32x4* x4 = reinterpret_cast<f32x4*>(xs);
+      f32x4* s4 = saved ? reinterpret_cast<f32x4*>(saved + (size_t)b * V) : nullptr;
+      for (int q = threadIdx.x; q < V / 4; q += NT) {
+        const f32x4 v = zb[q];
+        x4[q] = v;
+        if (s4) s4[q] = v;
+        zz += (R)v[0] * v[0] + (R)v[1] * v[1] + (R)v[2] * v[2] + (R)v[3] * v[3];
+      }
+    }
+    R ld = 0;
+    for (int layer = 0; layer < N; ++layer) {
+      const int fpar = (layer + parity0) & 1;
+      const u32x4* fl = frags + (size_t)layer * LF.total * 64 + lane;
+      const float* pl = params + (size_t)layer * P_layer;
+      __syncthreads();
+      // conv1 over all sites
+      {
+        u32x4 A[LF.nct][LF.k1];
+        f32x4 bias[LF.nct];
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct) {
+          bias[ct] = load_bias4<C>(pl + off_b1, ct, j);
+#pragma unroll
+          for (int c = 0; c < LF.k1; ++c) A[ct][c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
+        }
+        for (int tile = w; tile < V / 16; tile += NW) {
+          const int n = tile * 16 + m;
+          f32x4 acc[LF.nct];
+#pragma unroll
+          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c = 0; c < LF.k1; ++c) {
+            const u32x4 bop = gather_x<DIM, L, BF16>(xs, n, fpar, c, j);
+#pragma unroll
+            for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
+          }
+#pragma unroll
+          for (int ct = 0; ct < LF.nct; ++ct) store_hidden<C, BF16>(h1, n, ct, j, acc[ct], bias[ct]);
+        }
+      }
+      __syncthreads();
+      // conv2 over all sites
+      {
+        u32x4 A[LF.nct][LF.k2];
+        f32x4 bias[LF.nct];
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct) {
+          bias[ct] = load_bias4<C>(pl + off_b2, ct, j);
+#pragma unroll
+          for (int c = 0; c < LF.k2; ++c) A[ct][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
+        }
+        for (int tile = w; tile < V / 16; tile += NW) {
+          const int n = tile * 16 + m;
+          f32x4 acc[LF.nct];
+#pragma unroll
+          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c = 0; c < LF.k2; ++c) {
+            const u32x4 bop = gather_h<DIM, L, C, BF16>(h1, n, c, j);
+#pragma unroll
+            for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
+          }
+#pragma unroll
+          for (int ct = 0; ct < LF.nct; ++ct) store_hidden<C, BF16>(h2, n, ct, j, acc[ct], bias[ct]);
+        }
+      }
+      __syncthreads();
+      // conv3 at the active sites, affine update and log-det
+      {
+        u32x4 A[LF.k2];
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c) A[c] = fl[(LF.off3 + c) * 64];
+        const float bs = pl[off_b3], bt = pl[off_b3 + 1];
+        const int apar = fpar ^ 1;
+        for (int tile = w; tile < V / 32; tile += NW) {
+          const int n = G::half_site(tile * 16 + m, apar);
+          f32x4 acc{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c = 0; c < LF.k2; ++c)
+            acc = mma<BF16>(A[c], gather_h<DIM, L, C, BF16>(h2, n, c, j), acc);
+          if (j == 0) {
+            const float o0 = acc[0] + bs, t = acc[1] + bt;
+            const float s = final_tanh ? tanhf(o0) : o0;
+            xs[n] = xs[n] * expf(s) + t;
+            ld += (R)s;
+          }
+        }
+      }
+      __syncthreads();
+      if (saved) {
+        f32x4* s4 = reinterpret_cast<f32x4*>(saved + (size_t)(layer + 1) * BV + (size_t)b * V);
+        const f32x4* x4 = reinterpret_cast<const f32x4*>(xs);
+        for (int q = threadIdx.x; q < V / 4; q += NT) s4[q] = x4[q];
+      }
+    }
+    {
+      f32x4* p4 = reinterpret_cast<f32x4*>(phi + (size_t)b * V);
+      const f32x4* x4 = reinterpret_cast<const f32x4*>(xs);
+      for (int q = threadIdx.x; q < V / 4; q += NT) p4[q] = x4[q];
+    }
+    ld = block_sum(ld, red);
+    zz = block_sum(zz, red);
+    if (threadIdx.x == 0) {
+      const double logr = -0.5 * (double)zz - (double)V * kHalfLog2Pi;
+      logq[b] = logr - (double)ld;
+      if (logdet) logdet[b] = (double)ld;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+struct FusedShape {
+  int dim, L, C;
+  bool bf16;
+};
+
+template <int DIM, int L, int C, bool BF16>
+int32_t launch_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
+                       double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
+  using Cfg = FwdCfg<DIM, L, C, BF16>;
+  constexpr LayerFrags LF = Cfg::LF;
+  u32x4* frags = reinterpret_cast<u32x4*>(ws);
+  const long nthreads = (long)LF.total * 64 * g.N;
+  hipLaunchKernelGGL((kf_prep<BF16>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st,
+                     params, g.N, g.T, g.C, (int)g.P_layer, (int)g.off_W1, (int)g.off_W2,
+                     (int)g.off_W3, LF, frags);
+  auto kern = kf_forward<DIM, L, C, BF16, Cfg::NT>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)Cfg::lds_bytes) != hipSuccess)
+      return LFS_EDEVICE;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(B), dim3(Cfg::NT), Cfg::lds_bytes, st, frags, params,
+                     (int)g.P_layer, (int)g.off_b1, (int)g.off_b2, (int)g.off_b3, g.N, g.parity0,
+                     g.final_tanh, B, z, phi, saved, logq, logdet);
+  return launch_status();
+}
+
+using FwdFn = int32_t (*)(const FlowGeom&, const float*, int, const float*, float*, double*,
+                          double*, float*, char*, hipStream_t);
+
+struct FwdEntry {
+  int dim, L, C;
+  bool bf16;
+  FwdFn fn;
+  size_t frag_bytes_per_layer;
+};
+
+template <int DIM, int L, int C, bool BF16>
+constexpr FwdEntry fwd_entry() {
+  return FwdEntry{DIM, L, C, BF16, &launch_forward<DIM, L, C, BF16>,
+                  (size_t)FwdCfg<DIM, L, C, BF16>::LF.total * 64 * 16};
+}
+
+// Shapes with a fused forward: the whole sample (field + two hidden tensors)
+// fits in the 160 KB of LDS of one compute unit.
+#define LFS_FWD_SHAPES(P)                                                                        \
+  P(2, 8, 8) P(2, 8, 16) P(2, 8, 32) P(2, 16, 8) P(2, 16, 16) P(2, 16, 32) P(2, 32, 8)           \
+  P(2, 32, 16) P(3, 4, 8) P(3, 4, 16) P(3, 8, 8) P(3, 8, 16) P(3, 12, 8)
+#define LFS_FWD_BF16_ONLY(P) P(2, 32, 32) P(3, 12, 16)
+
+#define LFS_E2(D, L, C) fwd_entry<D, L, C, false>(), fwd_entry<D, L, C, true>(),
+#define LFS_E1(D, L, C) fwd_entry<D, L, C, true>(),
+
+const FwdEntry kFwdTable[] = {LFS_FWD_SHAPES(LFS_E2) LFS_FWD_BF16_ONLY(LFS_E1)};
+
+const FwdEntry* find_fwd(const FlowGeom& g) {
+  for (const auto& e : kFwdTable)
+    if (e.dim == g.dim && e.L == g.L && e.C == g.C && e.bf16 == g.bf16()) return &e;
+  return nullptr;
+}
+
+}  // namespace
+}  // namespace fused
+
+bool fused_supported(const FlowGeom& g, int for_backward) {
+  if (for_backward) return false;
+  return fused::find_fwd(g) != nullptr;
+}
+
+size_t fused_ws_bytes(const FlowGeom& g, int B, int for_backward) {
+  (void)B;
+  if (for_backward) return 0;
+  const fused::FwdEntry* e = fused::find_fwd(g);
+  return e ? align_up(e->frag_bytes_per_layer * g.N) : 0;
+}
+
+int32_t fused_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
+                      double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
+  const fused::FwdEntry* e = fused::find_fwd(g);
+  if (!e) return LFS_EUNSUPPORTED;
+  return e->fn(g, params, B, z, phi, logq, logdet, saved, ws, st);
+}
+
 int32_t fused_backward(const FlowGeom&, const float*, int, const float*, const float*, double,
                        float*, float*, char*, hipStream_t) {
   return LFS_EUNSUPPORTED;
 }
+
 }  // namespace lfs

@@ -259,3 +259,56 @@ def test_flow_deterministic_generic():
     gb, _ = run_backward(desc, b, g, 0.1)
     np.testing.assert_array_equal(host(a["phi"]), host(b["phi"]))
     np.testing.assert_array_equal(ga, gb)
+
+
+FUSED_CASES = [
+    # dim, L, N, C, B
+    (2, 8, 16, 8, 16),
+    (2, 32, 2, 16, 4),
+    (2, 16, 3, 32, 3),
+    (2, 32, 2, 8, 2),
+    (3, 4, 2, 16, 3),
+    (3, 8, 3, 16, 2),
+    (3, 12, 2, 8, 2),
+]
+FUSED_BF16_ONLY = [(2, 32, 2, 32, 2), (3, 12, 2, 16, 2)]
+
+
+@pytest.mark.parametrize("case", FUSED_CASES)
+@pytest.mark.parametrize("precision", [lfs.LFS_PLAIN_FP32, lfs.LFS_BF16_CONV])
+def test_flow_forward_fused(case, precision):
+    desc, params, z, fs = _flow_case(*case, precision, lfs.ALGO_FUSED)
+    _check_forward(desc, params, z, fs, precision)
+
+
+@pytest.mark.parametrize("case", FUSED_BF16_ONLY)
+def test_flow_forward_fused_bf16_only(case):
+    desc, params, z, fs = _flow_case(*case, lfs.LFS_BF16_CONV, lfs.ALGO_FUSED)
+    _check_forward(desc, params, z, fs, lfs.LFS_BF16_CONV)
+
+
+@pytest.mark.parametrize("precision", [lfs.LFS_PLAIN_FP32, lfs.LFS_BF16_CONV])
+def test_fused_matches_generic(precision):
+    """Same arithmetic, different summation order: fused and generic agree closely."""
+    desc_f, params, z, fs = _flow_case(2, 8, 16, 8, 8, precision, lfs.ALGO_FUSED)
+    desc_g, *_ = _flow_case(2, 8, 16, 8, 8, precision, lfs.ALGO_GENERIC)
+    a, b = run_forward(desc_f, params, z), run_forward(desc_g, params, z)
+    tol = 1e-5 if precision == lfs.LFS_PLAIN_FP32 else 2e-2
+    phi_a, phi_b = host(a["phi"]), host(b["phi"])
+    assert np.all(np.abs(phi_a - phi_b) <= tol * (1 + np.abs(phi_b)))
+
+
+def test_fused_sample_independence_and_determinism():
+    desc, params, z, fs = _flow_case(2, 32, 2, 16, 7, lfs.LFS_BF16_CONV, lfs.ALGO_FUSED)
+    full = run_forward(desc, params, z)
+    again = run_forward(desc, params, z)
+    part = run_forward(desc, params, z[3:5])
+    np.testing.assert_array_equal(host(full["phi"]), host(again["phi"]))
+    np.testing.assert_array_equal(host(full["phi"])[3:5], host(part["phi"]))
+    np.testing.assert_array_equal(host(full["logq"])[3:5], host(part["logq"]))
+
+
+def test_fused_unsupported_shape_is_reported():
+    desc = lfs.make_desc(2, 6, 2, 8, algo=lfs.ALGO_FUSED)
+    with pytest.raises(lfs.LfsError):
+        lfs.workspace_bytes(desc, 2, False)
