@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Benchmark of the flow-based phi^4 sampler's hot path on one MI355X.
+
+Workload (a "step"): one reverse-KL training iteration of the 2D phi^4 flow,
+L = 32, m^2 = -4, lambda = 8, 16 affine coupling layers with hidden channels 16,
+batch 1024, Adam lr 1e-3: prior draw -> flow forward with log q (saving the
+layer inputs) -> action and force -> log-weights and loss -> hand-written flow
+backward -> Adam.  Inputs are synthetic: seeded N(0, 0.1) weights (biases 0),
+Philox prior draws.  `value` is BF16-conv (FP32 accumulate, FP64 sums) training
+steps per second; the plain FP32 path, flow+MH sampling and the FP64 HMC
+baseline are reported beside it.
+
+Prints ONE JSON line.  Only one GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = dict(workload="phi4-2d-L32-train", dim=2, L=32, m2=-4.0, lam=8.0, n_layers=16,
+                hidden=16, batch=1024, lr=1e-3)
+PEAK = {"bf16_mfma_tflops": 2500.0, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
+
+
+def algorithmic_flops_per_sample_layer(dim, L, C):
+    """2 T (C^2 + 1.5 C) flops per site: conv2 dense, conv1 on the non-zero (frozen) half of
+    its taps, conv3 at the active half of the sites (forward pass)."""
+    T = 3 ** dim
+    return 2.0 * T * (C * C + 1.5 * C) * L ** dim
+
+
+def time_phases(tr, steps, warmup):
+    """Run warmup + timed steps; returns total seconds and per-phase event averages (ms)."""
+    import torch
+    for _ in range(warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    names = ["draw", "forward", "backward", "update"]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        e = ev[k]
+        e[0].record()
+        tr.draw()
+        e[1].record()
+        tr.forward()
+        e[2].record()
+        tr.backward()
+        e[3].record()
+        tr.update()
+        e[4].record()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    phase = {n: sum(ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(steps)) / steps
+             for i, n in enumerate(names)}
+    return total, phase
+
+
+def flow_forward_ms(flow, B, reps=20):
+    """Average duration (ms) of one lfs_flow_forward call (fragment prep + the fused kernel)."""
+    import torch
+    from paper_2208_08903_amd import lfs
+    z = torch.randn(B, flow.V, device="cuda")
+    phi = torch.empty_like(z)
+    lq = torch.empty(B, dtype=torch.float64, device="cuda")
+    ws = flow.workspace(B, False)
+    for _ in range(3):
+        lfs.flow_forward(flow.desc, flow.params, z, phi, lq, None, None, ws)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        lfs.flow_forward(flow.desc, flow.params, z, phi, lq, None, None, ws)
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def sampling_rate(flow, B, m2, lam, batches=10):
+    import torch
+    from paper_2208_08903_amd import flow as fl
+    import seeded_inputs as si
+    smp = fl.Sampler(flow, B, m2, lam, key=777)
+    lu = torch.as_tensor(si.log_uniforms(5, (batches + 2, 1, B)), device="cuda")
+    smp.step(lu[0])
+    smp.step(lu[1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(batches):
+        smp.step(lu[k + 2])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    acc, n_acc = smp.acceptance()
+    return dict(proposals_per_s=B * batches / dt, acceptance=acc,
+                accepted_per_s=acc * B * batches / dt, batch=B)
+
+
+def hmc_rate(reps=5):
+    """FP64 HMC baseline on the 3D L=8 theory: 512 chains x 10 leapfrog steps of 0.1."""
+    import torch
+    from paper_2208_08903_amd import lfs
+    import seeded_inputs as si
+    B, L, dim = 512, 8, 3
+    V = L ** dim
+    phi = torch.as_tensor(0.5 * si.normal_fields(3, B, V).astype("float64"), device="cuda")
+    pi = torch.as_tensor(si.momenta(4, B, V), device="cuda")
+    lu = torch.as_tensor(si.log_uniforms(5, B), device="cuda")
+    m2 = torch.tensor([-4.0], dtype=torch.float64, device="cuda")
+    lam = torch.tensor([5.0], dtype=torch.float64, device="cuda")
+    dH = torch.empty(B, dtype=torch.float64, device="cuda")
+    acc = torch.empty(B, dtype=torch.uint8, device="cuda")
+    lfs.hmc_step(dim, L, phi, pi, lu, m2, lam, 10, 0.1, dH, acc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lfs.hmc_step(dim, L, phi, pi, lu, m2, lam, 10, 0.1, dH, acc)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return dict(trajectories_per_s=B / dt, chains=B, leapfrog_steps=10, dt=0.1,
+                acceptance=float(acc.float().mean().item()))
+
+
+def cpu_baseline(target_s=15.0):
+    """The FP64 oracle's training step, one thread, on a bounded sample of the batch,
+    scaled to steps/s of the full batch (cost is linear in the batch: samples are
+    independent)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import seeded_inputs as si
+    from oracle import adam as oadam
+    from oracle import flow as of
+    w = WORKLOAD
+    fs = of.FlowShape(w["dim"], w["L"], w["n_layers"], w["hidden"])
+    p = si.flow_params(w["dim"], w["n_layers"], w["hidden"]).astype(np.float64)
+
+    def run(b):
+        z = si.normal_fields(9, b, fs.V)
+        t = time.perf_counter()
+        g = of.loss_gradient(p, z, fs, w["m2"], w["lam"])
+        oadam.adam_step(p, g, np.zeros_like(p), np.zeros_like(p), 1, lr=w["lr"])
+        return time.perf_counter() - t
+
+    with threadpool_limits(1):
+        t1 = run(4)
+        b = int(max(4, min(128, round(4 * target_s / max(t1, 1e-3)))))
+        tb = run(b)
+    per_sample = tb / b
+    return {"value": 1.0 / (per_sample * w["batch"]), "unit": "train steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"oracle loss gradient + Adam on {b} of the {w['batch']} samples "
+                      f"({tb:.1f} s, FP64 NumPy, 1 thread), scaled linearly to the full batch"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip FP32/sampling/HMC side figures")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU data-parallel design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import seeded_inputs as si
+    from paper_2208_08903_amd import flow as fl
+    from paper_2208_08903_amd import lfs
+
+    torch.cuda.set_device(0)
+    w = WORKLOAD
+    params = si.flow_params(w["dim"], w["n_layers"], w["hidden"])
+    B = w["batch"]
+
+    def make(prec):
+        f = fl.Flow(w["dim"], w["L"], w["n_layers"], w["hidden"], prec, params=params)
+        return f, fl.Trainer(f, B, w["m2"], w["lam"], lr=w["lr"])
+
+    flow, tr = make(lfs.LFS_BF16_CONV)
+    total, phase = time_phases(tr, args.steps, args.warmup)
+    ms = 1000.0 * total / args.steps
+    loss = float(tr.loss.item())
+
+    # dominant kernel: the fused forward (one launch per call) or the backward launches
+    fwd_ms = flow_forward_ms(flow, B)
+    fl_flops = algorithmic_flops_per_sample_layer(w["dim"], w["L"], w["hidden"])
+    fwd_flops = fl_flops * w["n_layers"] * B
+    bwd_launches = w["n_layers"]
+    if phase["backward"] > fwd_ms:
+        dom_name = "flow_backward (per layer launch)"
+        dom_ms = phase["backward"] / bwd_launches
+        dom_flops = 2 * fl_flops * B
+    else:
+        dom_name = "kf_forward (flow forward, all layers)"
+        dom_ms = fwd_ms
+        dom_flops = fwd_flops
+    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    roof = {"kernel": dom_name, "bound": "mfma", "achieved": round(achieved, 3),
+            "peak": PEAK["bf16_mfma_tflops"], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK["bf16_mfma_tflops"], 5), "traffic": None,
+            "flops_per_launch": dom_flops, "ms_per_launch": round(dom_ms, 5)}
+
+    out = {
+        "metric": "train steps/s (reverse-KL, BF16 conv + FP64 sums)",
+        "value": round(args.steps / total, 3),
+        "unit": "steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic (seeded N(0,0.1) weights, Philox prior draws)",
+        "config": {"workload": w["workload"], "dim": w["dim"], "L": w["L"], "m2": w["m2"],
+                   "lambda": w["lam"], "n_layers": w["n_layers"], "hidden": w["hidden"],
+                   "global_batch": B, "parallelism": "single GPU"},
+        "phases_ms": {k: round(v, 4) for k, v in phase.items()},
+        "loss_last": loss,
+        "roofline": roof,
+    }
+    if not args.no_extras:
+        f32, tr32 = make(lfs.LFS_PLAIN_FP32)
+        n32 = max(3, args.steps // 4)
+        t32, ph32 = time_phases(tr32, n32, 2)
+        out["fp32_plain"] = {"steps_per_s": round(n32 / t32, 3),
+                             "phases_ms": {k: round(v, 4) for k, v in ph32.items()},
+                             "forward_ms": round(flow_forward_ms(f32, B, 5), 4)}
+        out["bf16_speedup_vs_fp32"] = round((args.steps / total) / (n32 / t32), 3)
+        out["sampling_bf16"] = sampling_rate(fl.Flow(w["dim"], w["L"], w["n_layers"], w["hidden"],
+                                                     lfs.LFS_BF16_CONV, params=params),
+                                             B, w["m2"], w["lam"])
+        out["sampling_fp32"] = sampling_rate(fl.Flow(w["dim"], w["L"], w["n_layers"], w["hidden"],
+                                                     lfs.LFS_PLAIN_FP32, params=params),
+                                             B, w["m2"], w["lam"], batches=4)
+        out["hmc_fp64_3d_L8"] = hmc_rate()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

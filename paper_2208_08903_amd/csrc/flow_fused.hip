@@ -11,7 +11,7 @@
 // Three workgroup barriers per layer separate the phases.
 #include <type_traits>
 
-#include "fused_common.hpp"
+#include "fused_kernels.hpp"
 #include "lfs_internal.hpp"
 
 namespace lfs {
@@ -19,137 +19,6 @@ namespace fused {
 namespace {
 
 constexpr double kHalfLog2Pi = 0.91893853320467274178;
-
-// Weight fragments in the order the kernels read them (one 16-byte operand per
-// lane): per layer, conv1 [nct][k1], conv2 [nct][k2], conv3 [k2] fragments of
-// 64 lanes.  Rows beyond the output channels and k beyond T*Cin are zero.
-template <bool BF16>
-__global__ void kf_prep(const float* __restrict__ params, int N, int T, int C, int P_layer,
-                        int offW1, int offW2, int offW3, LayerFrags lf, u32x4* __restrict__ frags) {
-  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long per_layer = (long)lf.total * 64;
-  if (gid >= per_layer * N) return;
-  const int layer = (int)(gid / per_layer);
-  const int rem = (int)(gid % per_layer), f = rem / 64, l = rem % 64;
-  const int j = l >> 4, m = l & 15;
-  const float* p = params + (size_t)layer * P_layer;
-  const float* W;
-  int row, c, cin, cout, kc;
-  if (f < lf.off2) {
-    W = p + offW1, cin = 1, cout = C, kc = lf.k1, row = (f / kc) * 16 + m, c = f % kc;
-  } else if (f < lf.off3) {
-    W = p + offW2, cin = C, cout = C, kc = lf.k2, row = ((f - lf.off2) / kc) * 16 + m,
-    c = (f - lf.off2) % kc;
-  } else {
-    W = p + offW3, cin = C, cout = 2, kc = lf.k2, row = m, c = f - lf.off3;
-  }
-  const int K = T * cin;
-  auto w_at = [&](int k) -> float {
-    if (row >= cout || k >= K) return 0.f;
-    return W[(row * cin + k % cin) * T + k / cin];
-  };
-  u32x4 out;
-  if constexpr (BF16) {
-    const int k0 = 32 * c + 8 * j;
-    for (int q = 0; q < 4; ++q) out[q] = pack_bf16(w_at(k0 + 2 * q), w_at(k0 + 2 * q + 1));
-  } else {
-    const int k0 = 16 * c + 4 * j;
-    for (int q = 0; q < 4; ++q) out[q] = __float_as_uint(w_at(k0 + q));
-  }
-  frags[gid] = out;
-}
-
-template <bool BF16>
-using HElem = std::conditional_t<BF16, uint16_t, float>;
-
-// B operand of a C-input convolution at output site n for K chunk (BF16) /
-// block (FP32) c: the lane's 8 (4) consecutive input channels at one tap.
-template <int DIM, int L, int C, bool BF16>
-__device__ __forceinline__ u32x4 gather_h(const HElem<BF16>* h, int n, int c, int j) {
-  using G = Geo<DIM, L>;
-  constexpr int K = G::T * C;
-  const int k0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
-  if (k0 >= K) return u32x4{0u, 0u, 0u, 0u};
-  const int tap = k0 / C, ci0 = k0 % C;
-  const int nb = G::nbr(n, tap);
-  return *reinterpret_cast<const u32x4*>(h + nb * C + ci0);
-}
-
-// B operand of conv1 (one masked input channel): taps of the lane's K slice.
-template <int DIM, int L, bool BF16>
-__device__ __forceinline__ u32x4 gather_x(const float* xs, int n, int fpar, int c, int j) {
-  using G = Geo<DIM, L>;
-  constexpr int NV = BF16 ? 8 : 4;
-  const int t0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
-  float v[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const int t = t0 + i;
-    v[i] = 0.f;
-    if (t < G::T) {
-      const int nb = G::nbr(n, t);
-      if (G::parity(nb) == fpar) v[i] = xs[nb];
-    }
-  }
-  u32x4 r;
-  if constexpr (BF16) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = pack_bf16(v[2 * q], v[2 * q + 1]);
-  } else {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = __float_as_uint(v[q]);
-  }
-  return r;
-}
-
-// acc += A (fragment) x B (gathered) for one chunk / block.
-template <bool BF16>
-__device__ __forceinline__ f32x4 mma(const u32x4& a, const u32x4& b, f32x4 acc) {
-  if constexpr (BF16) {
-    return mfma(as_bf16x8(a), as_bf16x8(b), acc);
-  } else {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc = mfma(__uint_as_float(a[r]), __uint_as_float(b[r]), acc);
-    return acc;
-  }
-}
-
-// Store leaky(acc + bias) for rows 4j..4j+3 of output-channel tile ct at site n.
-template <int C, bool BF16>
-__device__ __forceinline__ void store_hidden(HElem<BF16>* h, int n, int ct, int j, const f32x4& acc,
-                                             const f32x4& bias) {
-  const int co0 = ct * 16 + 4 * j;
-  if (co0 >= C) return;
-  float v[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) v[i] = leaky(acc[i] + bias[i]);
-  if constexpr (BF16) {
-    u32x2 w{pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3])};
-    *reinterpret_cast<u32x2*>(h + n * C + co0) = w;
-  } else {
-    *reinterpret_cast<f32x4*>(h + n * C + co0) = f32x4{v[0], v[1], v[2], v[3]};
-  }
-}
-
-template <int C>
-__device__ __forceinline__ f32x4 load_bias4(const float* b, int ct, int j) {
-  const int co0 = ct * 16 + 4 * j;
-  f32x4 r{0.f, 0.f, 0.f, 0.f};
-  if (co0 < C) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) r[i] = b[co0 + i];
-  }
-  return r;
-}
-
-template <int DIM, int L, int C, bool BF16>
-struct FwdCfg {
-  using G = Geo<DIM, L>;
-  static constexpr int V = G::V, T = G::T;
-  static constexpr LayerFrags LF = layer_frags(T, C, BF16);
-  static constexpr size_t lds_bytes = (size_t)V * 4 + 2 * (size_t)V * C * sizeof(HElem<BF16>);
-  static constexpr int NT = lds_bytes > 80 * 1024 ? 512 : 256;
-};
 
 template <int DIM, int L, int C, bool BF16, int NT>
 __global__ void __launch_bounds__(NT) kf_forward(
@@ -290,21 +159,21 @@ __global__ void __launch_bounds__(NT) kf_forward(
 // Host side
 // ---------------------------------------------------------------------------
 
-struct FusedShape {
-  int dim, L, C;
-  bool bf16;
-};
-
 template <int DIM, int L, int C, bool BF16>
 int32_t launch_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
                        double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
   using Cfg = FwdCfg<DIM, L, C, BF16>;
   constexpr LayerFrags LF = Cfg::LF;
   u32x4* frags = reinterpret_cast<u32x4*>(ws);
+  FragTable tab{};
+  tab.count = 3;
+  tab.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, LF.nct, LF.k1, LF.off1};
+  tab.s[1] = FragSpec{0, (int)g.off_W2, C, C, C, LF.nct, LF.k2, LF.off2};
+  tab.s[2] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, LF.k2, LF.off3};
+  tab.total = LF.total;
   const long nthreads = (long)LF.total * 64 * g.N;
   hipLaunchKernelGGL((kf_prep<BF16>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st,
-                     params, g.N, g.T, g.C, (int)g.P_layer, (int)g.off_W1, (int)g.off_W2,
-                     (int)g.off_W3, LF, frags);
+                     params, g.N, g.T, (int)g.P_layer, tab, frags);
   auto kern = kf_forward<DIM, L, C, BF16, Cfg::NT>;
   static bool attr_set = false;
   if (!attr_set) {
@@ -358,13 +227,12 @@ const FwdEntry* find_fwd(const FlowGeom& g) {
 }  // namespace fused
 
 bool fused_supported(const FlowGeom& g, int for_backward) {
-  if (for_backward) return false;
+  if (for_backward) return fused::bwd_supported(g);
   return fused::find_fwd(g) != nullptr;
 }
 
 size_t fused_ws_bytes(const FlowGeom& g, int B, int for_backward) {
-  (void)B;
-  if (for_backward) return 0;
+  if (for_backward) return fused::bwd_ws_bytes(g, B);
   const fused::FwdEntry* e = fused::find_fwd(g);
   return e ? align_up(e->frag_bytes_per_layer * g.N) : 0;
 }
@@ -376,9 +244,10 @@ int32_t fused_forward(const FlowGeom& g, const float* params, int B, const float
   return e->fn(g, params, B, z, phi, logq, logdet, saved, ws, st);
 }
 
-int32_t fused_backward(const FlowGeom&, const float*, int, const float*, const float*, double,
-                       float*, float*, char*, hipStream_t) {
-  return LFS_EUNSUPPORTED;
+int32_t fused_backward(const FlowGeom& g, const float* params, int B, const float* saved,
+                       const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                       hipStream_t st) {
+  return fused::bwd_run(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
 }
 
 }  // namespace lfs

@@ -1,0 +1,766 @@
+// Fused backward of one coupling layer (the hand-written vector-Jacobian
+// product of the layer; paper Sec. 1 defines the layer, its derivative is
+// derived in the oracle's adjoint).  One launch per layer; persistent
+// workgroups each take whole samples and keep the sample in LDS:
+//
+//   recompute  h1 = leaky(W1 * mask_F x + b1), h2 = leaky(W2 * h1 + b2),
+//              (o0, o1) = W3 * h2 + b3 at the active sites, s = tanh(o0), t = o1
+//   affine     g_t = g_y, g_s = g_y x e^s + g_logdet, g_o0 = g_s (1 - s^2),
+//              g_x(active) = g_y e^s
+//   conv3^T    g_a2 = leaky'(h2) (W3^T * g_o)        dW3 += g_o (x) h2
+//   conv2^T    g_a1 = leaky'(h1) (W2^T * g_a2)       dW2 += g_a2 (x) h1
+//   conv1^T    g_x(frozen) = g_y + W1^T * g_a1       dW1 += g_a1 (x) mask_F x
+//
+// Every convolution is an implicit GEMM on the matrix cores.  The weight
+// gradients are GEMMs whose reduction runs over the sites; their operands are
+// 8 (BF16) or 4 (FP32) consecutive sites of one channel.  In BF16 mode the
+// activations are therefore also kept channel-major, so each operand is one
+// 16-byte LDS read (a +-1 offset along the fast axis is a funnel shift with one
+// extra element); FP32 operands are single values read from the site-major
+// copy.  Weight-gradient tiles accumulate in registers over all of a
+// workgroup's samples, are summed across waves in a fixed order, and written
+// as one partial per workgroup; a fixed-order reduction over workgroups gives
+// the gradient, so results are bitwise reproducible.
+#include <algorithm>
+
+#include "fused_kernels.hpp"
+#include "lfs_internal.hpp"
+
+namespace lfs {
+namespace fused {
+namespace {
+
+constexpr size_t align16(size_t x) { return (x + 15) / 16 * 16; }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr size_t cmaxz(size_t a, size_t b) { return a > b ? a : b; }
+
+template <int DIM, int L, int C, bool BF16>
+struct BwdCfg {
+  using G = Geo<DIM, L>;
+  static constexpr int V = G::V, T = G::T;
+  static constexpr LayerFrags LF = layer_frags(T, C, BF16);
+  static constexpr int KT3 = BF16 ? kchunks_bf16(2 * T) : kblocks_f32(2 * T);
+  static constexpr int OFF3T = LF.total;
+  static constexpr int OFF2T = OFF3T + LF.nct * KT3;
+  static constexpr int OFF1T = OFF2T + LF.nct * LF.k2;
+  static constexpr int FRAGS = OFF1T + LF.k2;
+  static constexpr int CSTR = V + 8;  // channel-major row stride in elements (BF16 mode)
+  static constexpr size_t SLOT = BF16 ? (size_t)C * CSTR * 2 : (size_t)V * C * 4;
+  static constexpr int NSLOT = BF16 ? 4 : 2;
+  static constexpr size_t OFF_XS = 0;
+  static constexpr size_t OFF_GY = (size_t)V * 4;
+  static constexpr size_t OFF_GOS = 2 * (size_t)V * 4;
+  static constexpr size_t GOS_BYTES = BF16 ? (size_t)V * 4 : (size_t)V * 8;
+  static constexpr size_t OFF_GOC = OFF_GOS + GOS_BYTES;
+  static constexpr size_t GOC_BYTES = BF16 ? 2 * (size_t)CSTR * 2 : 0;
+  static constexpr size_t OFF_H0C = OFF_GOC + GOC_BYTES;
+  static constexpr size_t H0C_BYTES = BF16 ? (size_t)CSTR * 2 : 0;
+  static constexpr size_t OFF_SLOT = align16(OFF_H0C + H0C_BYTES);
+  static constexpr int P_LAYER = C * T + C + C * C * T + C + 2 * C * T + 2;
+  static constexpr size_t lds_bytes = cmaxz(OFF_SLOT + NSLOT * SLOT, (size_t)P_LAYER * 4);
+  static constexpr int NT = lds_bytes > 80 * 1024 ? 512 : 256;
+  static constexpr int NW = NT / 64;
+  static constexpr int MT = (C + 15) / 16;
+  static constexpr int NKC = BF16 ? V / 32 : V / 16;  // K chunks (sites) per sample
+  static constexpr int I3 = MT * ((2 * T + 15) / 16);
+  static constexpr int I2 = MT * T * MT;
+  static constexpr int I1 = MT * ((T + 15) / 16);
+  static constexpr int ks(int I) { return I >= NW ? 1 : cmin(NW / I, NKC); }
+  static constexpr int KS3 = ks(I3), KS2 = ks(I2), KS1 = ks(I1);
+  static constexpr int S3 = (I3 * KS3 + NW - 1) / NW;
+  static constexpr int S2 = (I2 * KS2 + NW - 1) / NW;
+  static constexpr int S1 = (I1 * KS1 + NW - 1) / NW;
+};
+
+// ---- weight-gradient operands ---------------------------------------------
+
+// Row index (all axes but the last) of site s shifted by sign * delta_tap, and
+// the shift along the last axis.
+template <int DIM, int L>
+__device__ __forceinline__ void shifted_row(int s, int tap, int sign, int& rowS, int& e) {
+  using G = Geo<DIM, L>;
+  const int row = s / L;
+  if constexpr (DIM == 2) {
+    rowS = G::wrapc(row + sign * G::tap_d(tap, 0));
+    e = sign * G::tap_d(tap, 1);
+  } else {
+    const int z = row / L, y = row % L;
+    rowS = G::wrapc(z + sign * G::tap_d(tap, 0)) * L + G::wrapc(y + sign * G::tap_d(tap, 1));
+    e = sign * G::tap_d(tap, 2);
+  }
+}
+
+// BF16, channel-major row `cr` (stride CSTR): the 8 sites s0..s0+7 (one row,
+// s0 % 8 == 0) shifted by sign * delta_tap, as 4 packed BF16 pairs.
+template <int DIM, int L>
+__device__ __forceinline__ u32x4 load8_shift(const uint16_t* cr, int s0, int tap, int sign) {
+  int rowS, e;
+  shifted_row<DIM, L>(s0, tap, sign, rowS, e);
+  const int x0 = s0 % L;
+  const uint16_t* rp = cr + rowS * L;
+  const u32x4 v = *reinterpret_cast<const u32x4*>(rp + x0);
+  const uint32_t nxt = rp[(x0 + 8) & (L - 1)], prv = rp[(x0 + L - 1) & (L - 1)];
+  const u32x4 up{__builtin_amdgcn_alignbit(v[1], v[0], 16), __builtin_amdgcn_alignbit(v[2], v[1], 16),
+                 __builtin_amdgcn_alignbit(v[3], v[2], 16), __builtin_amdgcn_alignbit(nxt, v[3], 16)};
+  const u32x4 dn{__builtin_amdgcn_alignbit(v[0], prv << 16, 16), __builtin_amdgcn_alignbit(v[1], v[0], 16),
+                 __builtin_amdgcn_alignbit(v[2], v[1], 16), __builtin_amdgcn_alignbit(v[3], v[2], 16)};
+  return e > 0 ? up : (e < 0 ? dn : v);
+}
+
+// FP32, site-major [V][CH]: value of channel ch at site s shifted by sign * delta_tap.
+template <int DIM, int L, int CH>
+__device__ __forceinline__ float load1_shift(const float* h, int s, int ch, int tap, int sign) {
+  int rowS, e;
+  shifted_row<DIM, L>(s, tap, sign, rowS, e);
+  return h[(rowS * L + ((s % L + e + L) & (L - 1))) * CH + ch];
+}
+
+// ---- the kernel -------------------------------------------------------------
+
+template <int DIM, int L, int C, bool BF16, int NT>
+__global__ void __launch_bounds__(NT) kf_backward(
+    const u32x4* frags, const float* __restrict__ pl, int off_b1, int off_b2,
+    int off_b3, int off_W1, int off_W2, int off_W3, int fpar, int final_tanh, float g_ld, int B,
+    const float* __restrict__ xin, const float* __restrict__ gy, float* __restrict__ gx,
+    float* __restrict__ partial) {
+  using Cfg = BwdCfg<DIM, L, C, BF16>;
+  using G = Geo<DIM, L>;
+  using HT = HElem<BF16>;
+  constexpr int V = Cfg::V, T = Cfg::T, NW = Cfg::NW, MT = Cfg::MT, NKC = Cfg::NKC;
+  constexpr int CSTR = Cfg::CSTR;
+  constexpr LayerFrags LF = Cfg::LF;
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* xs = reinterpret_cast<float*>(smem + Cfg::OFF_XS);
+  float* gys = reinterpret_cast<float*>(smem + Cfg::OFF_GY);
+  unsigned char* slots = smem + Cfg::OFF_SLOT;
+  auto slot = [&](int i) { return slots + i * Cfg::SLOT; };
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane >> 4, m = lane & 15;
+  const u32x4* fr = frags + lane;
+  const int apar = fpar ^ 1;
+
+  // site-major activations: BF16 h1s S0, h2s S2; FP32 h1 S0, h2 S1
+  HT* h1s = reinterpret_cast<HT*>(slot(0));
+  HT* h2s = reinterpret_cast<HT*>(slot(BF16 ? 2 : 1));
+  // BF16 channel-major copies and the remaining slots
+  uint16_t* h1c = reinterpret_cast<uint16_t*>(slot(1));
+  uint16_t* h2c = reinterpret_cast<uint16_t*>(slot(BF16 ? 3 : 1));
+
+  f32x4 acc3[Cfg::S3], acc2[Cfg::S2], acc1[Cfg::S1];
+#pragma unroll
+  for (int i = 0; i < Cfg::S3; ++i) acc3[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < Cfg::S2; ++i) acc2[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < Cfg::S1; ++i) acc1[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float db3s = 0.f, db3t = 0.f;
+  f32x4 db2[LF.nct], db1[LF.nct];
+#pragma unroll
+  for (int ct = 0; ct < LF.nct; ++ct) db2[ct] = db1[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    // Weight fragments are reloaded per phase (L1/L2 hits) rather than kept live
+    // across the whole sample loop, which would need every phase's registers at once.
+    asm volatile("" ::: "memory");
+    const size_t sb = (size_t)b * V;
+    // stage x and g_y; BF16: masked field channel-major for dW1
+    for (int q = threadIdx.x; q < V / 4; q += NT) {
+      reinterpret_cast<f32x4*>(xs)[q] = reinterpret_cast<const f32x4*>(xin + sb)[q];
+      reinterpret_cast<f32x4*>(gys)[q] = reinterpret_cast<const f32x4*>(gy + sb)[q];
+    }
+    __syncthreads();
+    if constexpr (BF16) {
+      uint16_t* h0c = reinterpret_cast<uint16_t*>(smem + Cfg::OFF_H0C);
+      for (int n = threadIdx.x; n < V; n += NT)
+        h0c[n] = (uint16_t)bf16_bits(G::parity(n) == fpar ? xs[n] : 0.f);
+    }
+    // ---- recompute conv1 -> h1 ----
+    {
+      u32x4 A[LF.nct][LF.k1];
+      f32x4 bias[LF.nct];
+#pragma unroll
+      for (int ct = 0; ct < LF.nct; ++ct) {
+        bias[ct] = load_bias4<C>(pl + off_b1, ct, j);
+#pragma unroll
+        for (int c = 0; c < LF.k1; ++c) A[ct][c] = fr[(LF.off1 + ct * LF.k1 + c) * 64];
+      }
+      for (int tile = w; tile < V / 16; tile += NW) {
+        const int n = tile * 16 + m;
+        f32x4 acc[LF.nct];
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < LF.k1; ++c) {
+          const u32x4 bop = gather_x<DIM, L, BF16>(xs, n, fpar, c, j);
+#pragma unroll
+          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
+        }
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct) {
+          store_hidden<C, BF16>(h1s, n, ct, j, acc[ct], bias[ct]);
+          if constexpr (BF16) {
+            const int co0 = ct * 16 + 4 * j;
+            if (co0 < C) {
+              const uint32_t* hv = reinterpret_cast<const uint32_t*>(h1s + n * C + co0);
+              const uint32_t w0 = hv[0], w1 = hv[1];
+              h1c[(co0 + 0) * CSTR + n] = (uint16_t)w0;
+              h1c[(co0 + 1) * CSTR + n] = (uint16_t)(w0 >> 16);
+              h1c[(co0 + 2) * CSTR + n] = (uint16_t)w1;
+              h1c[(co0 + 3) * CSTR + n] = (uint16_t)(w1 >> 16);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- recompute conv2 -> h2 ----
+    {
+      u32x4 A[LF.nct][LF.k2];
+      f32x4 bias[LF.nct];
+#pragma unroll
+      for (int ct = 0; ct < LF.nct; ++ct) {
+        bias[ct] = load_bias4<C>(pl + off_b2, ct, j);
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c) A[ct][c] = fr[(LF.off2 + ct * LF.k2 + c) * 64];
+      }
+      for (int tile = w; tile < V / 16; tile += NW) {
+        const int n = tile * 16 + m;
+        f32x4 acc[LF.nct];
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c) {
+          const u32x4 bop = gather_h<DIM, L, C, BF16>(h1s, n, c, j);
+#pragma unroll
+          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
+        }
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct) {
+          store_hidden<C, BF16>(h2s, n, ct, j, acc[ct], bias[ct]);
+          if constexpr (BF16) {
+            const int co0 = ct * 16 + 4 * j;
+            if (co0 < C) {
+              const uint32_t* hv = reinterpret_cast<const uint32_t*>(h2s + n * C + co0);
+              const uint32_t w0 = hv[0], w1 = hv[1];
+              h2c[(co0 + 0) * CSTR + n] = (uint16_t)w0;
+              h2c[(co0 + 1) * CSTR + n] = (uint16_t)(w0 >> 16);
+              h2c[(co0 + 2) * CSTR + n] = (uint16_t)w1;
+              h2c[(co0 + 3) * CSTR + n] = (uint16_t)(w1 >> 16);
+            }
+          }
+        }
+      }
+    }
+    // ---- recompute conv3 at active sites; affine backward -> g_o, g_x(active) ----
+    // g_o is zero at the frozen sites.
+    uint32_t* gos_b = reinterpret_cast<uint32_t*>(smem + Cfg::OFF_GOS);  // BF16 pairs
+    float* gos_f = reinterpret_cast<float*>(smem + Cfg::OFF_GOS);        // FP32 pairs
+    uint16_t* goc = reinterpret_cast<uint16_t*>(smem + Cfg::OFF_GOC);     // BF16 [2][CSTR]
+    for (int q = threadIdx.x; q < V / 2; q += NT) {
+      const int n = G::half_site(q, fpar);
+      if constexpr (BF16) {
+        gos_b[n] = 0u;
+        goc[n] = 0;
+        goc[CSTR + n] = 0;
+      } else {
+        gos_f[2 * n] = 0.f;
+        gos_f[2 * n + 1] = 0.f;
+      }
+    }
+    __syncthreads();
+    {
+      u32x4 A[LF.k2];
+#pragma unroll
+      for (int c = 0; c < LF.k2; ++c) A[c] = fr[(LF.off3 + c) * 64];
+      const float bs = pl[off_b3], bt = pl[off_b3 + 1];
+      for (int tile = w; tile < V / 32; tile += NW) {
+        const int n = G::half_site(tile * 16 + m, apar);
+        f32x4 acc{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c)
+          acc = mma<BF16>(A[c], gather_h<DIM, L, C, BF16>(h2s, n, c, j), acc);
+        if (j == 0) {
+          const float o0 = acc[0] + bs;
+          const float s = final_tanh ? tanhf(o0) : o0;
+          const float es = expf(s);
+          const float g = gys[n];
+          const float gs = g * xs[n] * es + g_ld;
+          const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
+          db3s += go0;
+          db3t += g;
+          gx[sb + n] = g * es;
+          if constexpr (BF16) {
+            const uint32_t pr = pack_bf16(go0, g);
+            gos_b[n] = pr;
+            goc[n] = (uint16_t)pr;
+            goc[CSTR + n] = (uint16_t)(pr >> 16);
+          } else {
+            gos_f[2 * n] = go0;
+            gos_f[2 * n + 1] = g;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- dW3[co][ci][tap] += sum_m h2[m][ci] g_o[m - delta_tap][co] ----
+    {
+      constexpr int NTL = (2 * T + 15) / 16;
+#pragma unroll
+      for (int si = 0; si < Cfg::S3; ++si) {
+        const int u = w + NW * si;
+        if (u < Cfg::I3 * Cfg::KS3) {
+          const int q = u / Cfg::KS3, p = u % Cfg::KS3;
+          const int nt = q % NTL, mt = q / NTL;
+          const int ci = mt * 16 + m, col = nt * 16 + m, tap = col >> 1, co = col & 1;
+          const bool va = ci < C, vb = tap < T;
+          for (int kc = p * NKC / Cfg::KS3; kc < (p + 1) * NKC / Cfg::KS3; ++kc) {
+            if constexpr (BF16) {
+              const int s0 = kc * 32 + 8 * j;
+              const u32x4 a = va ? *reinterpret_cast<const u32x4*>(h2c + ci * CSTR + s0) : u32x4{0u, 0u, 0u, 0u};
+              const u32x4 bb = vb ? load8_shift<DIM, L>(goc + co * CSTR, s0, tap, -1) : u32x4{0u, 0u, 0u, 0u};
+              acc3[si] = mfma(as_bf16x8(a), as_bf16x8(bb), acc3[si]);
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int s = kc * 16 + 4 * j + r;
+                const float a = va ? h2s[s * C + ci] : 0.f;
+                const float bb = vb ? load1_shift<DIM, L, 2>(gos_f, s, co, tap, -1) : 0.f;
+                acc3[si] = mfma(a, bb, acc3[si]);
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- conv3^T: g_a2 = leaky'(h2) (W3^T * g_o) ----
+    // BF16: site-major into S0 (h1s is dead), channel-major into S3 (h2c is dead);
+    // FP32: in place over h2.
+    HT* ga2s = BF16 ? reinterpret_cast<HT*>(slot(0)) : h2s;
+    uint16_t* ga2c = reinterpret_cast<uint16_t*>(slot(3));
+    {
+      u32x4 A[LF.nct][Cfg::KT3];
+#pragma unroll
+      for (int ct = 0; ct < LF.nct; ++ct)
+#pragma unroll
+        for (int c = 0; c < Cfg::KT3; ++c) A[ct][c] = fr[(Cfg::OFF3T + ct * Cfg::KT3 + c) * 64];
+      for (int tile = w; tile < V / 16; tile += NW) {
+        const int n = tile * 16 + m;
+        f32x4 acc[LF.nct];
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < Cfg::KT3; ++c) {
+          u32x4 bop;
+          if constexpr (BF16) {
+            const int t0 = (32 * c + 8 * j) / 2;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              bop[q] = t0 + q < T ? gos_b[G::nbr(n, t0 + q, -1)] : 0u;
+          } else {
+            const int t0 = (16 * c + 4 * j) / 2;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const int t = t0 + q;
+              const int nb = t < T ? G::nbr(n, t, -1) : 0;
+              bop[2 * q] = t < T ? __float_as_uint(gos_f[2 * nb]) : 0u;
+              bop[2 * q + 1] = t < T ? __float_as_uint(gos_f[2 * nb + 1]) : 0u;
+            }
+          }
+#pragma unroll
+          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
+        }
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct) {
+          const int c0 = ct * 16 + 4 * j;
+          if (c0 < C) {
+            float v[4];
+            if constexpr (BF16) {
+              const uint32_t* hv = reinterpret_cast<const uint32_t*>(h2s + n * C + c0);
+              const uint32_t w0 = hv[0], w1 = hv[1];
+              const float hh[4] = {bf16_lo(w0), bf16_hi(w0), bf16_lo(w1), bf16_hi(w1)};
+#pragma unroll
+              for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
+              const uint32_t p0 = pack_bf16(v[0], v[1]), p1 = pack_bf16(v[2], v[3]);
+              *reinterpret_cast<u32x2*>(ga2s + n * C + c0) = u32x2{p0, p1};
+              ga2c[(c0 + 0) * CSTR + n] = (uint16_t)p0;
+              ga2c[(c0 + 1) * CSTR + n] = (uint16_t)(p0 >> 16);
+              ga2c[(c0 + 2) * CSTR + n] = (uint16_t)p1;
+              ga2c[(c0 + 3) * CSTR + n] = (uint16_t)(p1 >> 16);
+            } else {
+              const f32x4 hh = *reinterpret_cast<const f32x4*>(h2s + n * C + c0);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
+              *reinterpret_cast<f32x4*>(ga2s + n * C + c0) = f32x4{v[0], v[1], v[2], v[3]};
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) db2[ct][i] += v[i];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- dW2[co][ci][tap] += sum_m h1[m][ci] g_a2[m - delta_tap][co] ----
+    {
+#pragma unroll
+      for (int si = 0; si < Cfg::S2; ++si) {
+        const int u = w + NW * si;
+        if (u < Cfg::I2 * Cfg::KS2) {
+          const int q = u / Cfg::KS2, p = u % Cfg::KS2;
+          const int nt = q % MT, tap = (q / MT) % T, mt = q / (MT * T);
+          const int ci = mt * 16 + m, co = nt * 16 + m;
+          const bool va = ci < C, vb = co < C;
+          for (int kc = p * NKC / Cfg::KS2; kc < (p + 1) * NKC / Cfg::KS2; ++kc) {
+            if constexpr (BF16) {
+              const int s0 = kc * 32 + 8 * j;
+              const u32x4 a = va ? *reinterpret_cast<const u32x4*>(h1c + ci * CSTR + s0) : u32x4{0u, 0u, 0u, 0u};
+              const u32x4 bb = vb ? load8_shift<DIM, L>(ga2c + co * CSTR, s0, tap, -1) : u32x4{0u, 0u, 0u, 0u};
+              acc2[si] = mfma(as_bf16x8(a), as_bf16x8(bb), acc2[si]);
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int s = kc * 16 + 4 * j + r;
+                const float a = va ? h1s[s * C + ci] : 0.f;
+                const float bb = vb ? load1_shift<DIM, L, C>(ga2s, s, co, tap, -1) : 0.f;
+                acc2[si] = mfma(a, bb, acc2[si]);
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- conv2^T: g_a1 = leaky'(h1) (W2^T * g_a2) ----
+    // BF16: site-major into S2 (h2s is dead), channel-major into S3 (g_a2c is dead);
+    // FP32: in place over h1.
+    HT* ga1s = BF16 ? reinterpret_cast<HT*>(slot(2)) : h1s;
+    uint16_t* ga1c = reinterpret_cast<uint16_t*>(slot(3));
+    {
+      u32x4 A[LF.nct][LF.k2];
+#pragma unroll
+      for (int ct = 0; ct < LF.nct; ++ct)
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c) A[ct][c] = fr[(Cfg::OFF2T + ct * LF.k2 + c) * 64];
+      for (int tile = w; tile < V / 16; tile += NW) {
+        const int n = tile * 16 + m;
+        f32x4 acc[LF.nct];
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c) {
+          const u32x4 bop = gather_h<DIM, L, C, BF16, -1>(ga2s, n, c, j);
+#pragma unroll
+          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
+        }
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct) {
+          const int c0 = ct * 16 + 4 * j;
+          if (c0 < C) {
+            float v[4];
+            if constexpr (BF16) {
+              float hh[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) hh[i] = __uint_as_float((uint32_t)h1c[(c0 + i) * CSTR + n] << 16);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
+              const uint32_t p0 = pack_bf16(v[0], v[1]), p1 = pack_bf16(v[2], v[3]);
+              *reinterpret_cast<u32x2*>(ga1s + n * C + c0) = u32x2{p0, p1};
+              ga1c[(c0 + 0) * CSTR + n] = (uint16_t)p0;
+              ga1c[(c0 + 1) * CSTR + n] = (uint16_t)(p0 >> 16);
+              ga1c[(c0 + 2) * CSTR + n] = (uint16_t)p1;
+              ga1c[(c0 + 3) * CSTR + n] = (uint16_t)(p1 >> 16);
+            } else {
+              const f32x4 hh = *reinterpret_cast<const f32x4*>(h1s + n * C + c0);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
+              *reinterpret_cast<f32x4*>(ga1s + n * C + c0) = f32x4{v[0], v[1], v[2], v[3]};
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) db1[ct][i] += v[i];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- dW1[c][tap] += sum_n g_a1[n][c] h0[n + delta_tap] (h0 = mask_F x) ----
+    {
+      constexpr int NTL = (T + 15) / 16;
+      const uint16_t* h0c = reinterpret_cast<const uint16_t*>(smem + Cfg::OFF_H0C);
+#pragma unroll
+      for (int si = 0; si < Cfg::S1; ++si) {
+        const int u = w + NW * si;
+        if (u < Cfg::I1 * Cfg::KS1) {
+          const int q = u / Cfg::KS1, p = u % Cfg::KS1;
+          const int nt = q % NTL, mt = q / NTL;
+          const int c = mt * 16 + m, tap = nt * 16 + m;
+          const bool va = c < C, vb = tap < T;
+          for (int kc = p * NKC / Cfg::KS1; kc < (p + 1) * NKC / Cfg::KS1; ++kc) {
+            if constexpr (BF16) {
+              const int s0 = kc * 32 + 8 * j;
+              const u32x4 a = va ? *reinterpret_cast<const u32x4*>(ga1c + c * CSTR + s0) : u32x4{0u, 0u, 0u, 0u};
+              const u32x4 bb = vb ? load8_shift<DIM, L>(h0c, s0, tap, 1) : u32x4{0u, 0u, 0u, 0u};
+              acc1[si] = mfma(as_bf16x8(a), as_bf16x8(bb), acc1[si]);
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int s = kc * 16 + 4 * j + r;
+                const float a = va ? ga1s[s * C + c] : 0.f;
+                float bb = 0.f;
+                if (vb) {
+                  const int nb = G::nbr(s, tap, 1);
+                  bb = G::parity(nb) == fpar ? xs[nb] : 0.f;
+                }
+                acc1[si] = mfma(a, bb, acc1[si]);
+              }
+            }
+          }
+        }
+      }
+    }
+    // ---- conv1^T at the frozen sites: g_x = g_y + W1^T * g_a1 ----
+    {
+      u32x4 A[LF.k2];
+#pragma unroll
+      for (int c = 0; c < LF.k2; ++c) A[c] = fr[(Cfg::OFF1T + c) * 64];
+      for (int tile = w; tile < V / 32; tile += NW) {
+        const int n = G::half_site(tile * 16 + m, fpar);
+        f32x4 acc{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c)
+          acc = mma<BF16>(A[c], gather_h<DIM, L, C, BF16, -1>(ga1s, n, c, j), acc);
+        if (j == 0) gx[sb + n] = gys[n] + acc[0];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- sum the waves' weight-gradient tiles in a fixed order, write the partial ----
+  float* red = reinterpret_cast<float*>(smem);
+  for (int i = threadIdx.x; i < Cfg::P_LAYER; i += NT) red[i] = 0.f;
+  // bias partials: reduce over the 16 lanes that share j (and, for db3, over all lanes)
+#pragma unroll
+  for (int ct = 0; ct < LF.nct; ++ct)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        db2[ct][i] += __shfl_xor(db2[ct][i], o, 64);
+        db1[ct][i] += __shfl_xor(db1[ct][i], o, 64);
+      }
+  db3s = wave_sum(db3s);
+  db3t = wave_sum(db3t);
+  __syncthreads();
+  for (int ww = 0; ww < NW; ++ww) {
+    if (w == ww) {
+      constexpr int NTL3 = (2 * T + 15) / 16, NTL1 = (T + 15) / 16;
+#pragma unroll
+      for (int si = 0; si < Cfg::S3; ++si) {
+        const int u = w + NW * si;
+        if (u < Cfg::I3 * Cfg::KS3) {
+          const int q = u / Cfg::KS3, nt = q % NTL3, mt = q / NTL3;
+          const int col = nt * 16 + m, tap = col >> 1, co = col & 1;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int ci = mt * 16 + 4 * j + i;
+            if (ci < C && tap < T) red[off_W3 + (co * C + ci) * T + tap] += acc3[si][i];
+          }
+        }
+      }
+#pragma unroll
+      for (int si = 0; si < Cfg::S2; ++si) {
+        const int u = w + NW * si;
+        if (u < Cfg::I2 * Cfg::KS2) {
+          const int q = u / Cfg::KS2, nt = q % MT, tap = (q / MT) % T, mt = q / (MT * T);
+          const int co = nt * 16 + m;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int ci = mt * 16 + 4 * j + i;
+            if (ci < C && co < C) red[off_W2 + (co * C + ci) * T + tap] += acc2[si][i];
+          }
+        }
+      }
+#pragma unroll
+      for (int si = 0; si < Cfg::S1; ++si) {
+        const int u = w + NW * si;
+        if (u < Cfg::I1 * Cfg::KS1) {
+          const int q = u / Cfg::KS1, nt = q % NTL1, mt = q / NTL1;
+          const int tap = nt * 16 + m;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = mt * 16 + 4 * j + i;
+            if (c < C && tap < T) red[off_W1 + c * T + tap] += acc1[si][i];
+          }
+        }
+      }
+      if (m == 0) {
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = ct * 16 + 4 * j + i;
+            if (c < C) {
+              red[off_b2 + c] += db2[ct][i];
+              red[off_b1 + c] += db1[ct][i];
+            }
+          }
+      }
+      if (lane == 0) {
+        red[off_b3] += db3s;
+        red[off_b3 + 1] += db3t;
+      }
+    }
+    __syncthreads();
+  }
+  float* out = partial + (size_t)blockIdx.x * Cfg::P_LAYER;
+  for (int i = threadIdx.x; i < Cfg::P_LAYER; i += NT) out[i] = red[i];
+}
+
+__global__ void __launch_bounds__(256) kf_reduce(int G, int P, const float* __restrict__ partial,
+                                                 float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  float acc = 0.f;
+  for (int g = 0; g < G; ++g) acc += partial[(size_t)g * P + i];
+  out[i] = acc;
+}
+
+__global__ void kf_gz(int64_t n, const float* __restrict__ gx, const float* __restrict__ z,
+                      float g_logq, float* __restrict__ gz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) gz[i] = gx[i] - g_logq * z[i];
+}
+
+// ---- host -----------------------------------------------------------------
+
+inline FragTable bwd_table(const FlowGeom& g, bool bf16) {
+  const int T = g.T, C = g.C;
+  const LayerFrags lf = layer_frags(T, C, bf16);
+  const int kt3 = bf16 ? kchunks_bf16(2 * T) : kblocks_f32(2 * T);
+  FragTable t{};
+  t.count = 6;
+  t.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, lf.nct, lf.k1, lf.off1};
+  t.s[1] = FragSpec{0, (int)g.off_W2, C, C, C, lf.nct, lf.k2, lf.off2};
+  t.s[2] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, lf.k2, lf.off3};
+  t.s[3] = FragSpec{1, (int)g.off_W3, C, 2, C, lf.nct, kt3, lf.total};
+  t.s[4] = FragSpec{1, (int)g.off_W2, C, C, C, lf.nct, lf.k2, lf.total + lf.nct * kt3};
+  t.s[5] = FragSpec{1, (int)g.off_W1, 1, C, 1, 1, lf.k2, lf.total + lf.nct * kt3 + lf.nct * lf.k2};
+  t.total = t.s[5].off + lf.k2;
+  return t;
+}
+
+int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+  }
+  return n;
+}
+
+template <int DIM, int L, int C, bool BF16>
+int bwd_grid(int B) {
+  using Cfg = BwdCfg<DIM, L, C, BF16>;
+  const int per_cu = std::max<int>(1, std::min<int>(8, (int)((160 * 1024) / Cfg::lds_bytes)));
+  return std::min(B, num_cus() * per_cu);
+}
+
+template <int DIM, int L, int C, bool BF16>
+size_t bwd_ws(const FlowGeom& g, int B) {
+  using Cfg = BwdCfg<DIM, L, C, BF16>;
+  const size_t frags = (size_t)Cfg::FRAGS * 64 * 16 * g.N;
+  const size_t partial = (size_t)bwd_grid<DIM, L, C, BF16>(B) * Cfg::P_LAYER * 4;
+  const size_t gbuf = (size_t)B * Cfg::V * 4;
+  return align_up(frags) + align_up(partial) + 2 * align_up(gbuf);
+}
+
+template <int DIM, int L, int C, bool BF16>
+int32_t launch_backward(const FlowGeom& g, const float* params, int B, const float* saved,
+                        const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                        hipStream_t st) {
+  using Cfg = BwdCfg<DIM, L, C, BF16>;
+  const int grid = bwd_grid<DIM, L, C, BF16>(B);
+  const FragTable tab = bwd_table(g, BF16);
+  char* p = ws;
+  u32x4* frags = reinterpret_cast<u32x4*>(p);
+  p += align_up((size_t)Cfg::FRAGS * 64 * 16 * g.N);
+  float* partial = reinterpret_cast<float*>(p);
+  p += align_up((size_t)grid * Cfg::P_LAYER * 4);
+  float* gbuf[2] = {reinterpret_cast<float*>(p),
+                    reinterpret_cast<float*>(p + align_up((size_t)B * Cfg::V * 4))};
+  const long nthreads = (long)tab.total * 64 * g.N;
+  hipLaunchKernelGGL((kf_prep<BF16>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st,
+                     params, g.N, g.T, (int)g.P_layer, tab, frags);
+  auto kern = kf_backward<DIM, L, C, BF16, Cfg::NT>;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::lds_bytes) !=
+      hipSuccess)
+    return LFS_EDEVICE;
+  const size_t BV = (size_t)B * Cfg::V;
+  const float* gy = g_phi;
+  int which = 0;
+  for (int l = g.N - 1; l >= 0; --l) {
+    float* gx = gbuf[which];
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(Cfg::NT), Cfg::lds_bytes, st,
+                       frags + (size_t)l * tab.total * 64, params + (size_t)l * g.P_layer,
+                       (int)g.off_b1, (int)g.off_b2, (int)g.off_b3, (int)g.off_W1, (int)g.off_W2,
+                       (int)g.off_W3, g.frozen_parity(l), g.final_tanh, (float)(-g_logq), B,
+                       saved + (size_t)l * BV, gy, gx, partial);
+    hipLaunchKernelGGL(kf_reduce, dim3((Cfg::P_LAYER + 255) / 256), dim3(256), 0, st, grid,
+                       Cfg::P_LAYER, partial, g_params + (size_t)l * g.P_layer);
+    gy = gx;
+    which ^= 1;
+  }
+  if (g_z)
+    hipLaunchKernelGGL(kf_gz, dim3((unsigned)((BV + 255) / 256)), dim3(256), 0, st, (int64_t)BV,
+                       gy, saved, (float)g_logq, g_z);
+  return launch_status();
+}
+
+using BwdFn = int32_t (*)(const FlowGeom&, const float*, int, const float*, const float*, double,
+                          float*, float*, char*, hipStream_t);
+using BwdWsFn = size_t (*)(const FlowGeom&, int);
+
+struct BwdEntry {
+  int dim, L, C;
+  bool bf16;
+  BwdFn fn;
+  BwdWsFn ws;
+};
+
+template <int DIM, int L, int C, bool BF16>
+constexpr BwdEntry bwd_entry() {
+  static_assert(BwdCfg<DIM, L, C, BF16>::lds_bytes <= 160 * 1024, "LDS budget");
+  return BwdEntry{DIM, L, C, BF16, &launch_backward<DIM, L, C, BF16>, &bwd_ws<DIM, L, C, BF16>};
+}
+
+// Training shapes with a fused backward (L a power of two, >= 8; the sample fits
+// in LDS with both layouts in BF16 mode).
+#define LFS_BWD_SHAPES(P) P(2, 8, 8) P(2, 8, 16) P(2, 16, 8) P(2, 16, 16) P(2, 32, 8) P(2, 32, 16) P(3, 8, 8) P(3, 8, 16)
+#define LFS_B2(D, L, C) bwd_entry<D, L, C, false>(), bwd_entry<D, L, C, true>(),
+
+const BwdEntry kBwdTable[] = {LFS_BWD_SHAPES(LFS_B2)};
+
+const BwdEntry* find_bwd(const FlowGeom& g) {
+  for (const auto& e : kBwdTable)
+    if (e.dim == g.dim && e.L == g.L && e.C == g.C && e.bf16 == g.bf16()) return &e;
+  return nullptr;
+}
+
+}  // namespace
+
+bool bwd_supported(const FlowGeom& g) { return find_bwd(g) != nullptr; }
+size_t bwd_ws_bytes(const FlowGeom& g, int B) {
+  const BwdEntry* e = find_bwd(g);
+  return e ? e->ws(g, B) : 0;
+}
+int32_t bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
+                const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                hipStream_t st) {
+  const BwdEntry* e = find_bwd(g);
+  if (!e) return LFS_EUNSUPPORTED;
+  return e->fn(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
+}
+
+}  // namespace fused
+}  // namespace lfs

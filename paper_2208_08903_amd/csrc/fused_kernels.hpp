@@ -1,0 +1,152 @@
+// Device helpers shared by the fused forward and backward kernels: weight
+// fragment preparation, operand gathers from LDS-resident activations, the MFMA
+// step and the hidden-activation epilogue.
+#pragma once
+
+#include <type_traits>
+
+#include "fused_common.hpp"
+
+namespace lfs {
+namespace fused {
+
+// A convolution's weights as MFMA A-fragments.  kind: 0 = forward
+// convolution (rows = output channels, k = tap * cin + ci), 1 = its transpose
+// used by the data gradient (rows = input channels, k = tap * cout + co).
+struct FragSpec {
+  int transposed, woff, cin, cout, rows, nct, nk, off;
+};
+constexpr int kMaxSpecs = 6;
+struct FragTable {
+  FragSpec s[kMaxSpecs];
+  int count, total;  // fragments per layer
+};
+
+// One thread per (layer, fragment, lane): writes that lane's 16-byte operand.
+// Rows beyond `rows` and k beyond taps * (cin or cout) are zero.
+template <bool BF16>
+__global__ void kf_prep(const float* __restrict__ params, int N, int T, int P_layer, FragTable tab,
+                        u32x4* __restrict__ frags) {
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per_layer = (long)tab.total * 64;
+  if (gid >= per_layer * N) return;
+  const int layer = (int)(gid / per_layer);
+  const int rem = (int)(gid % per_layer), f = rem / 64, l = rem % 64;
+  const int j = l >> 4, m = l & 15;
+  int si = 0;
+  while (si + 1 < tab.count && f >= tab.s[si + 1].off) ++si;
+  const FragSpec sp = tab.s[si];
+  const int fl = f - sp.off, ct = fl / sp.nk, c = fl % sp.nk, row = ct * 16 + m;
+  const float* W = params + (size_t)layer * P_layer + sp.woff;
+  const int kdiv = sp.transposed ? sp.cout : sp.cin;
+  const int K = T * kdiv;
+  auto w_at = [&](int k) -> float {
+    if (row >= sp.rows || k >= K) return 0.f;
+    const int tap = k / kdiv, ch = k % kdiv;
+    return sp.transposed ? W[(ch * sp.cin + row) * T + tap] : W[(row * sp.cin + ch) * T + tap];
+  };
+  u32x4 out;
+  if constexpr (BF16) {
+    const int k0 = 32 * c + 8 * j;
+    for (int q = 0; q < 4; ++q) out[q] = pack_bf16(w_at(k0 + 2 * q), w_at(k0 + 2 * q + 1));
+  } else {
+    const int k0 = 16 * c + 4 * j;
+    for (int q = 0; q < 4; ++q) out[q] = __float_as_uint(w_at(k0 + q));
+  }
+  frags[gid] = out;
+}
+
+template <bool BF16>
+using HElem = std::conditional_t<BF16, uint16_t, float>;
+
+// B operand of a C-input convolution at output site n for K chunk (BF16) /
+// block (FP32) c: the lane's 8 (4) consecutive input channels at one tap.
+template <int DIM, int L, int C, bool BF16, int SIGN = 1>
+__device__ __forceinline__ u32x4 gather_h(const HElem<BF16>* h, int n, int c, int j) {
+  using G = Geo<DIM, L>;
+  constexpr int K = G::T * C;
+  const int k0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
+  if (k0 >= K) return u32x4{0u, 0u, 0u, 0u};
+  const int tap = k0 / C, ci0 = k0 % C;
+  const int nb = G::nbr(n, tap, SIGN);
+  return *reinterpret_cast<const u32x4*>(h + nb * C + ci0);
+}
+
+// B operand of conv1 (one masked input channel): taps of the lane's K slice.
+template <int DIM, int L, bool BF16>
+__device__ __forceinline__ u32x4 gather_x(const float* xs, int n, int fpar, int c, int j) {
+  using G = Geo<DIM, L>;
+  constexpr int NV = BF16 ? 8 : 4;
+  const int t0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
+  float v[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int t = t0 + i;
+    v[i] = 0.f;
+    if (t < G::T) {
+      const int nb = G::nbr(n, t);
+      if (G::parity(nb) == fpar) v[i] = xs[nb];
+    }
+  }
+  u32x4 r;
+  if constexpr (BF16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = pack_bf16(v[2 * q], v[2 * q + 1]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = __float_as_uint(v[q]);
+  }
+  return r;
+}
+
+// acc += A (fragment) x B (gathered) for one chunk / block.
+template <bool BF16>
+__device__ __forceinline__ f32x4 mma(const u32x4& a, const u32x4& b, f32x4 acc) {
+  if constexpr (BF16) {
+    return mfma(as_bf16x8(a), as_bf16x8(b), acc);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc = mfma(__uint_as_float(a[r]), __uint_as_float(b[r]), acc);
+    return acc;
+  }
+}
+
+// Store leaky(acc + bias) for rows 4j..4j+3 of output-channel tile ct at site n.
+template <int C, bool BF16>
+__device__ __forceinline__ void store_hidden(HElem<BF16>* h, int n, int ct, int j, const f32x4& acc,
+                                             const f32x4& bias) {
+  const int co0 = ct * 16 + 4 * j;
+  if (co0 >= C) return;
+  float v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = leaky(acc[i] + bias[i]);
+  if constexpr (BF16) {
+    u32x2 w{pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3])};
+    *reinterpret_cast<u32x2*>(h + n * C + co0) = w;
+  } else {
+    *reinterpret_cast<f32x4*>(h + n * C + co0) = f32x4{v[0], v[1], v[2], v[3]};
+  }
+}
+
+template <int C>
+__device__ __forceinline__ f32x4 load_bias4(const float* b, int ct, int j) {
+  const int co0 = ct * 16 + 4 * j;
+  f32x4 r{0.f, 0.f, 0.f, 0.f};
+  if (co0 < C) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i] = b[co0 + i];
+  }
+  return r;
+}
+
+template <int DIM, int L, int C, bool BF16>
+struct FwdCfg {
+  using G = Geo<DIM, L>;
+  static constexpr int V = G::V, T = G::T;
+  static constexpr LayerFrags LF = layer_frags(T, C, BF16);
+  static constexpr size_t lds_bytes = (size_t)V * 4 + 2 * (size_t)V * C * sizeof(HElem<BF16>);
+  static constexpr int NT = lds_bytes > 80 * 1024 ? 512 : 256;
+};
+
+}  // namespace fused
+}  // namespace lfs

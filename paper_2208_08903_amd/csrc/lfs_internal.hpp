@@ -44,4 +44,13 @@ int32_t fused_backward(const FlowGeom& g, const float* params, int B, const floa
                        const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
                        hipStream_t st);
 
+namespace fused {
+// Fused backward (one launch per layer), implemented next to its kernels.
+bool bwd_supported(const FlowGeom& g);
+size_t bwd_ws_bytes(const FlowGeom& g, int B);
+int32_t bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
+                const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                hipStream_t st);
+}  // namespace fused
+
 }  // namespace lfs

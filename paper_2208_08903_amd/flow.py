@@ -1,0 +1,149 @@
+"""Training and sampling drivers over the HIP library.
+
+PyTorch only provides device memory and the stream; every step of the path is
+one of the library's entry points (see ``lfs``):
+
+  train step (paper Sec. 1, reverse-KL training; example parameter file:
+  Adam, lr 1e-3, fresh prior batch per iteration)
+      prior_normal -> flow_forward (saving layer inputs) -> action (+force/B)
+      -> log_weights (loss) -> flow_backward -> adam_step
+
+  sampling (paper Sec. 1, flow proposals + Metropolis-Hastings test)
+      prior_normal -> flow_forward -> action -> log_weights -> mh_chain
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import lfs
+
+
+class Flow:
+    """A flow architecture, its packed FP32 parameters on the device, and workspaces."""
+
+    def __init__(self, dim, L, n_layers, hidden, precision=lfs.LFS_BF16_CONV, algo=lfs.ALGO_AUTO,
+                 final_tanh=True, parity0=0, params=None, device="cuda"):
+        self.dim, self.L, self.n_layers, self.hidden = dim, L, n_layers, hidden
+        self.V = L ** dim
+        self.precision = precision
+        self.desc = lfs.make_desc(dim, L, n_layers, hidden, final_tanh, parity0, precision, algo)
+        self.P = lfs.param_count(self.desc)
+        if self.P == 0:
+            raise lfs.LfsError("invalid flow description")
+        self.device = device
+        if params is None:
+            params = np.zeros(self.P, np.float32)
+        params = torch.as_tensor(np.asarray(params, np.float32))
+        if params.numel() != self.P:
+            raise lfs.LfsError(f"expected {self.P} parameters, got {params.numel()}")
+        self.params = params.to(device).contiguous()
+        self._ws = {}
+
+    def workspace(self, B, backward):
+        key = (B, bool(backward))
+        if key not in self._ws:
+            n = max(lfs.workspace_bytes(self.desc, B, backward), 1)
+            self._ws[key] = torch.empty(n, dtype=torch.uint8, device=self.device)
+        return self._ws[key]
+
+    def with_precision(self, precision):
+        f = Flow(self.dim, self.L, self.n_layers, self.hidden, precision, self.desc.algo,
+                 bool(self.desc.final_tanh), self.desc.parity0, device=self.device)
+        f.params = self.params
+        return f
+
+
+class Trainer:
+    """Reverse-KL training on fresh prior batches; all buffers allocated once."""
+
+    def __init__(self, flow: Flow, B: int, m2: float, lam: float, lr=1e-3, key=12345,
+                 betas=(0.9, 0.999), eps=1e-8):
+        self.flow, self.B = flow, B
+        dev, V, N = flow.device, flow.V, flow.n_layers
+        self.m2 = torch.tensor([m2], dtype=torch.float64, device=dev)
+        self.lam = torch.tensor([lam], dtype=torch.float64, device=dev)
+        self.lr, self.betas, self.eps, self.key = lr, betas, eps, key
+        f32, f64 = torch.float32, torch.float64
+        self.z = torch.empty(B, V, dtype=f32, device=dev)
+        self.phi = torch.empty(B, V, dtype=f32, device=dev)
+        self.logq = torch.empty(B, dtype=f64, device=dev)
+        self.saved = torch.empty((N + 1) * B * V, dtype=f32, device=dev)
+        self.S = torch.empty(B, dtype=f64, device=dev)
+        self.gphi = torch.empty(B, V, dtype=f32, device=dev)
+        self.logw = torch.empty(B, dtype=f64, device=dev)
+        self.loss = torch.zeros(1, dtype=f64, device=dev)
+        self.gparams = torch.empty(flow.P, dtype=f32, device=dev)
+        self.m = torch.zeros(flow.P, dtype=f32, device=dev)
+        self.v = torch.zeros(flow.P, dtype=f32, device=dev)
+        self.ws_f = flow.workspace(B, False)
+        self.ws_b = flow.workspace(B, True)
+        self.t = 0
+
+    # The four phases, separately callable so a caller can time them.
+    def draw(self):
+        lfs.prior_normal(self.key, self.t * self.B, self.z)
+
+    def forward(self):
+        f = self.flow
+        lfs.flow_forward(f.desc, f.params, self.z, self.phi, self.logq, None, self.saved, self.ws_f)
+        lfs.action(f.dim, f.L, self.phi, self.m2, self.lam, self.S, self.gphi, 1.0 / self.B,
+                   f.precision)
+        lfs.log_weights(self.S, self.logq, self.logw, self.loss)
+
+    def backward(self):
+        f = self.flow
+        lfs.flow_backward(f.desc, f.params, self.saved, self.gphi, 1.0 / self.B, self.gparams, None,
+                          self.ws_b)
+
+    def update(self):
+        self.t += 1
+        lfs.adam_step(self.flow.params, self.gparams, self.m, self.v, self.lr, self.betas[0],
+                      self.betas[1], self.eps, self.t)
+
+    def step(self):
+        self.draw()
+        self.forward()
+        self.backward()
+        self.update()
+
+
+class Sampler:
+    """Flow proposals and one persistent independence-MH chain per sampler."""
+
+    def __init__(self, flow: Flow, B: int, m2: float, lam: float, key=12345, n_chains=1):
+        self.flow, self.B = flow, B
+        dev, V = flow.device, flow.V
+        f32, f64 = torch.float32, torch.float64
+        if B % n_chains:
+            raise lfs.LfsError("B must be a multiple of n_chains")
+        self.n_chains = n_chains
+        self.m2 = torch.tensor([m2], dtype=f64, device=dev)
+        self.lam = torch.tensor([lam], dtype=f64, device=dev)
+        self.key = key
+        self.z = torch.empty(B, V, dtype=f32, device=dev)
+        self.phi = torch.empty(B, V, dtype=f32, device=dev)
+        self.logq = torch.empty(B, dtype=f64, device=dev)
+        self.S = torch.empty(B, dtype=f64, device=dev)
+        self.logw = torch.empty(B, dtype=f64, device=dev)
+        self.state = lfs.new_chain_state(n_chains, dev)
+        self.cur = torch.empty(n_chains, B // n_chains, dtype=torch.int64, device=dev)
+        self.acc = torch.empty(n_chains, B // n_chains, dtype=torch.uint8, device=dev)
+        self.ws = flow.workspace(B, False)
+        self.batch = 0
+
+    def step(self, log_u):
+        """One batch of B proposals; log_u is a [n_chains, B/n_chains] FP64 device tensor."""
+        f = self.flow
+        lfs.prior_normal(self.key, self.batch * self.B, self.z)
+        lfs.flow_forward(f.desc, f.params, self.z, self.phi, self.logq, None, None, self.ws)
+        lfs.action(f.dim, f.L, self.phi, self.m2, self.lam, self.S, None, 1.0, f.precision)
+        lfs.log_weights(self.S, self.logq, self.logw)
+        lfs.mh_chain(self.logw.view(self.n_chains, -1), log_u, self.state, self.cur, self.acc)
+        self.batch += 1
+
+    def acceptance(self):
+        st = lfs.decode_chain_state(self.state)
+        acc = sum(s["n_acc"] for s in st)
+        dec = sum(max(s["n_seen"] - 1, 0) for s in st)
+        return acc / max(dec, 1), acc

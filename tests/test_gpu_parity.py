@@ -312,3 +312,53 @@ def test_fused_unsupported_shape_is_reported():
     desc = lfs.make_desc(2, 6, 2, 8, algo=lfs.ALGO_FUSED)
     with pytest.raises(lfs.LfsError):
         lfs.workspace_bytes(desc, 2, False)
+
+
+FUSED_BWD_CASES = [
+    # dim, L, N, C, B
+    (2, 8, 4, 8, 16),
+    (2, 8, 3, 16, 5),
+    (2, 16, 2, 8, 3),
+    (2, 32, 2, 16, 4),
+    (2, 32, 2, 8, 3),
+    (3, 8, 2, 16, 3),
+    (3, 8, 2, 8, 2),
+]
+
+
+@pytest.mark.parametrize("case", FUSED_BWD_CASES)
+@pytest.mark.parametrize("precision", [lfs.LFS_PLAIN_FP32, lfs.LFS_BF16_CONV])
+def test_flow_backward_fused(case, precision):
+    desc, params, z, fs = _flow_case(*case, precision, lfs.ALGO_FUSED)
+    out = run_forward(desc, params, z)
+    _check_backward(desc, params, z, fs, out, precision)
+
+
+def test_flow_backward_fused_deterministic_and_batch_sum():
+    """Bitwise reproducible; the gradient of a batch is the sum of per-sample gradients
+    (up to FP32 summation order)."""
+    desc, params, z, fs = _flow_case(2, 32, 2, 16, 6, lfs.LFS_BF16_CONV, lfs.ALGO_FUSED)
+    g = np.random.default_rng(5).standard_normal(z.shape).astype(np.float32)
+    out = run_forward(desc, params, z)
+    ga, gza = run_backward(desc, out, g, 0.2)
+    gb, gzb = run_backward(desc, out, g, 0.2)
+    np.testing.assert_array_equal(ga, gb)
+    np.testing.assert_array_equal(gza, gzb)
+    parts = []
+    for i in range(6):
+        o = run_forward(desc, params, z[i:i + 1])
+        gi, gzi = run_backward(desc, o, g[i:i + 1], 0.2)
+        np.testing.assert_array_equal(gzi, gza[i:i + 1])     # per-sample outputs independent of batch
+        parts.append(gi)
+    assert rel_norm(ga, np.sum(parts, axis=0)) < 1e-5
+
+
+@pytest.mark.parametrize("precision", [lfs.LFS_PLAIN_FP32, lfs.LFS_BF16_CONV])
+def test_fused_backward_matches_generic(precision):
+    desc_f, params, z, fs = _flow_case(2, 8, 4, 8, 8, precision, lfs.ALGO_FUSED)
+    desc_g, *_ = _flow_case(2, 8, 4, 8, 8, precision, lfs.ALGO_GENERIC)
+    g = np.random.default_rng(6).standard_normal(z.shape).astype(np.float32)
+    ga, gza = run_backward(desc_f, run_forward(desc_f, params, z), g, 0.3)
+    gb, gzb = run_backward(desc_g, run_forward(desc_g, params, z), g, 0.3)
+    tol = 1e-5 if precision == lfs.LFS_PLAIN_FP32 else 2e-2
+    assert rel_norm(ga, gb) < tol and rel_norm(gza, gzb) < tol
