@@ -28,30 +28,29 @@ __global__ void __launch_bounds__(NT) kf_forward(
     double* __restrict__ logdet) {
   using Cfg = FwdCfg<DIM, L, C, BF16>;
   using G = Geo<DIM, L>;
+  using LY = typename Cfg::LY;
   using HT = HElem<BF16>;
   using R = std::conditional_t<BF16, double, float>;
-  constexpr int V = Cfg::V;
+  constexpr int V = Cfg::V, VS = LY::VS;
   constexpr LayerFrags LF = Cfg::LF;
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ R red[16];
   float* xs = reinterpret_cast<float*>(smem);
-  HT* h1 = reinterpret_cast<HT*>(smem + V * 4);
-  HT* h2 = h1 + V * C;
+  HT* h1 = reinterpret_cast<HT*>(smem + ((VS * 4 + 15) / 16) * 16);
+  HT* h2 = h1 + VS * C;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane >> 4, m = lane & 15;
   const size_t BV = (size_t)B * V;
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     R zz = 0;
     {
-      const f32x4* zb = reinterpret_cast<const f32x4*>(z + (size_t)b * V);
-      f32x4* x4 = reinterpret_cast<f32x4*>(xs);
-      f32x4* s4 = saved ? reinterpret_cast<f32x4*>(saved + (size_t)b * V) : nullptr;
-      for (int q = threadIdx.x; q < V / 4; q += NT) {
-        const f32x4 v = zb[q];
-        x4[q] = v;
-        if (s4) s4[q] = v;
-        zz += (R)v[0] * v[0] + (R)v[1] * v[1] + (R)v[2] * v[2] + (R)v[3] * v[3];
+      const float* zb = z + (size_t)b * V;
+      for (int q = threadIdx.x; q < VS; q += NT) xs[q] = zb[LY::site_of(q)];
+      for (int n = threadIdx.x; n < V; n += NT) {
+        const float v = zb[n];
+        if (saved) saved[(size_t)b * V + n] = v;
+        zz += (R)v * v;
       }
     }
     R ld = 0;
@@ -71,18 +70,18 @@ __global__ void __launch_bounds__(NT) kf_forward(
           for (int c = 0; c < LF.k1; ++c) A[ct][c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
         }
         for (int tile = w; tile < V / 16; tile += NW) {
-          const int n = tile * 16 + m;
+          const int n = tile * 16 + m, p = LY::idx(n), pn = G::parity(n);
           f32x4 acc[LF.nct];
 #pragma unroll
           for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int c = 0; c < LF.k1; ++c) {
-            const u32x4 bop = gather_x<DIM, L, BF16>(xs, n, fpar, c, j);
+            const u32x4 bop = gather_x<LY, BF16>(xs, n, p, pn, fpar, c, j);
 #pragma unroll
             for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
           }
 #pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) store_hidden<C, BF16>(h1, n, ct, j, acc[ct], bias[ct]);
+          for (int ct = 0; ct < LF.nct; ++ct) store_hidden<LY, C, BF16>(h1, n, ct, j, acc[ct], bias[ct]);
         }
       }
       __syncthreads();
@@ -97,18 +96,18 @@ __global__ void __launch_bounds__(NT) kf_forward(
           for (int c = 0; c < LF.k2; ++c) A[ct][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
         }
         for (int tile = w; tile < V / 16; tile += NW) {
-          const int n = tile * 16 + m;
+          const int n = tile * 16 + m, p = LY::idx(n);
           f32x4 acc[LF.nct];
 #pragma unroll
           for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int c = 0; c < LF.k2; ++c) {
-            const u32x4 bop = gather_h<DIM, L, C, BF16>(h1, n, c, j);
+            const u32x4 bop = gather_h<LY, C, BF16>(h1, n, p, c, j);
 #pragma unroll
             for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
           }
 #pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) store_hidden<C, BF16>(h2, n, ct, j, acc[ct], bias[ct]);
+          for (int ct = 0; ct < LF.nct; ++ct) store_hidden<LY, C, BF16>(h2, n, ct, j, acc[ct], bias[ct]);
         }
       }
       __syncthreads();
@@ -120,30 +119,29 @@ __global__ void __launch_bounds__(NT) kf_forward(
         const float bs = pl[off_b3], bt = pl[off_b3 + 1];
         const int apar = fpar ^ 1;
         for (int tile = w; tile < V / 32; tile += NW) {
-          const int n = G::half_site(tile * 16 + m, apar);
+          const int n = G::half_site(tile * 16 + m, apar), p = LY::idx(n);
           f32x4 acc{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int c = 0; c < LF.k2; ++c)
-            acc = mma<BF16>(A[c], gather_h<DIM, L, C, BF16>(h2, n, c, j), acc);
+            acc = mma<BF16>(A[c], gather_h<LY, C, BF16>(h2, n, p, c, j), acc);
           if (j == 0) {
             const float o0 = acc[0] + bs, t = acc[1] + bt;
             const float s = final_tanh ? tanhf(o0) : o0;
-            xs[n] = xs[n] * expf(s) + t;
+            const float xn = xs[p] * expf(s) + t;
+            LY::copies(n, [&](int q) { xs[q] = xn; });
             ld += (R)s;
           }
         }
       }
       __syncthreads();
       if (saved) {
-        f32x4* s4 = reinterpret_cast<f32x4*>(saved + (size_t)(layer + 1) * BV + (size_t)b * V);
-        const f32x4* x4 = reinterpret_cast<const f32x4*>(xs);
-        for (int q = threadIdx.x; q < V / 4; q += NT) s4[q] = x4[q];
+        float* sv = saved + (size_t)(layer + 1) * BV + (size_t)b * V;
+        for (int n = threadIdx.x; n < V; n += NT) sv[n] = xs[LY::idx(n)];
       }
     }
     {
-      f32x4* p4 = reinterpret_cast<f32x4*>(phi + (size_t)b * V);
-      const f32x4* x4 = reinterpret_cast<const f32x4*>(xs);
-      for (int q = threadIdx.x; q < V / 4; q += NT) p4[q] = x4[q];
+      float* pb = phi + (size_t)b * V;
+      for (int n = threadIdx.x; n < V; n += NT) pb[n] = xs[LY::idx(n)];
     }
     ld = block_sum(ld, red);
     zz = block_sum(zz, red);

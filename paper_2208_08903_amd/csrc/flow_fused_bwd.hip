@@ -34,6 +34,30 @@ constexpr size_t align16(size_t x) { return (x + 15) / 16 * 16; }
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr size_t cmaxz(size_t a, size_t b) { return a > b ? a : b; }
 
+template <int DIM, int L, int C, bool BF16, bool PAD>
+struct BwdLds {
+  using LY = Lay<DIM, L, PAD>;
+  static constexpr int V = Geo<DIM, L>::V, VS = LY::VS;
+  static constexpr int CSTR = V + 8;  // channel-major row stride in elements (BF16 mode)
+  static constexpr size_t SA = (size_t)VS * C * (BF16 ? 2 : 4);  // site-major tensor
+  static constexpr size_t SC = BF16 ? (size_t)C * CSTR * 2 : 0;  // channel-major tensor
+  static constexpr size_t OFF_XS = 0;
+  static constexpr size_t OFF_GY = align16((size_t)VS * 4);
+  static constexpr size_t OFF_GOS = OFF_GY + align16((size_t)V * 4);
+  static constexpr size_t GOS_BYTES = (size_t)VS * (BF16 ? 4 : 8);
+  static constexpr size_t OFF_GOC = OFF_GOS + align16(GOS_BYTES);
+  static constexpr size_t GOC_BYTES = BF16 ? 2 * (size_t)CSTR * 2 : 0;
+  static constexpr size_t OFF_H0C = OFF_GOC + align16(GOC_BYTES);
+  static constexpr size_t H0C_BYTES = BF16 ? (size_t)CSTR * 2 : 0;
+  static constexpr size_t OFF_SLOT = OFF_H0C + align16(H0C_BYTES);
+  // BF16: site-major, channel-major, site-major, channel-major; FP32: two site-major
+  static constexpr size_t OFF_S0 = OFF_SLOT;
+  static constexpr size_t OFF_S1 = OFF_S0 + SA;
+  static constexpr size_t OFF_S2 = OFF_S1 + (BF16 ? SC : SA);
+  static constexpr size_t OFF_S3 = OFF_S2 + (BF16 ? SA : 0);
+  static constexpr size_t MAIN = BF16 ? OFF_S3 + SC : OFF_S2;
+};
+
 template <int DIM, int L, int C, bool BF16>
 struct BwdCfg {
   using G = Geo<DIM, L>;
@@ -44,21 +68,14 @@ struct BwdCfg {
   static constexpr int OFF2T = OFF3T + LF.nct * KT3;
   static constexpr int OFF1T = OFF2T + LF.nct * LF.k2;
   static constexpr int FRAGS = OFF1T + LF.k2;
-  static constexpr int CSTR = V + 8;  // channel-major row stride in elements (BF16 mode)
-  static constexpr size_t SLOT = BF16 ? (size_t)C * CSTR * 2 : (size_t)V * C * 4;
-  static constexpr int NSLOT = BF16 ? 4 : 2;
-  static constexpr size_t OFF_XS = 0;
-  static constexpr size_t OFF_GY = (size_t)V * 4;
-  static constexpr size_t OFF_GOS = 2 * (size_t)V * 4;
-  static constexpr size_t GOS_BYTES = BF16 ? (size_t)V * 4 : (size_t)V * 8;
-  static constexpr size_t OFF_GOC = OFF_GOS + GOS_BYTES;
-  static constexpr size_t GOC_BYTES = BF16 ? 2 * (size_t)CSTR * 2 : 0;
-  static constexpr size_t OFF_H0C = OFF_GOC + GOC_BYTES;
-  static constexpr size_t H0C_BYTES = BF16 ? (size_t)CSTR * 2 : 0;
-  static constexpr size_t OFF_SLOT = align16(OFF_H0C + H0C_BYTES);
   static constexpr int P_LAYER = C * T + C + C * C * T + C + 2 * C * T + 2;
-  static constexpr size_t lds_bytes = cmaxz(OFF_SLOT + NSLOT * SLOT, (size_t)P_LAYER * 4);
-  static constexpr int NT = lds_bytes > 80 * 1024 ? 512 : 256;
+  static constexpr bool PAD = BwdLds<DIM, L, C, BF16, true>::MAIN <= 158 * 1024;
+  using M = BwdLds<DIM, L, C, BF16, PAD>;
+  using LY = typename M::LY;
+  static constexpr int CSTR = M::CSTR;
+  static constexpr size_t lds_bytes = cmaxz(M::MAIN, (size_t)P_LAYER * 4);
+  // 3D shapes need more than the 256 registers a lane gets at 2 waves per SIMD.
+  static constexpr int NT = (lds_bytes > 80 * 1024 && DIM == 2) ? 512 : 256;
   static constexpr int NW = NT / 64;
   static constexpr int MT = (C + 15) / 16;
   static constexpr int NKC = BF16 ? V / 32 : V / 16;  // K chunks (sites) per sample
@@ -107,12 +124,10 @@ __device__ __forceinline__ u32x4 load8_shift(const uint16_t* cr, int s0, int tap
   return e > 0 ? up : (e < 0 ? dn : v);
 }
 
-// FP32, site-major [V][CH]: value of channel ch at site s shifted by sign * delta_tap.
-template <int DIM, int L, int CH>
+// FP32, site-major storage (layout LY, CH channels): channel ch of site s + sign * delta_tap.
+template <class LY, int CH>
 __device__ __forceinline__ float load1_shift(const float* h, int s, int ch, int tap, int sign) {
-  int rowS, e;
-  shifted_row<DIM, L>(s, tap, sign, rowS, e);
-  return h[(rowS * L + ((s % L + e + L) & (L - 1))) * CH + ch];
+  return h[LY::nbr(s, LY::idx(s), tap, sign) * CH + ch];
 }
 
 // ---- the kernel -------------------------------------------------------------
@@ -130,20 +145,21 @@ __global__ void __launch_bounds__(NT) kf_backward(
   constexpr int CSTR = Cfg::CSTR;
   constexpr LayerFrags LF = Cfg::LF;
   extern __shared__ __align__(16) unsigned char smem[];
-  float* xs = reinterpret_cast<float*>(smem + Cfg::OFF_XS);
-  float* gys = reinterpret_cast<float*>(smem + Cfg::OFF_GY);
-  unsigned char* slots = smem + Cfg::OFF_SLOT;
-  auto slot = [&](int i) { return slots + i * Cfg::SLOT; };
+  using M = typename Cfg::M;
+  using LY = typename Cfg::LY;
+  constexpr int VS = LY::VS;
+  float* xs = reinterpret_cast<float*>(smem + M::OFF_XS);
+  float* gys = reinterpret_cast<float*>(smem + M::OFF_GY);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane >> 4, m = lane & 15;
   const u32x4* fr = frags + lane;
   const int apar = fpar ^ 1;
 
   // site-major activations: BF16 h1s S0, h2s S2; FP32 h1 S0, h2 S1
-  HT* h1s = reinterpret_cast<HT*>(slot(0));
-  HT* h2s = reinterpret_cast<HT*>(slot(BF16 ? 2 : 1));
+  HT* h1s = reinterpret_cast<HT*>(smem + M::OFF_S0);
+  HT* h2s = reinterpret_cast<HT*>(smem + (BF16 ? M::OFF_S2 : M::OFF_S1));
   // BF16 channel-major copies and the remaining slots
-  uint16_t* h1c = reinterpret_cast<uint16_t*>(slot(1));
-  uint16_t* h2c = reinterpret_cast<uint16_t*>(slot(BF16 ? 3 : 1));
+  uint16_t* h1c = reinterpret_cast<uint16_t*>(smem + M::OFF_S1);
+  uint16_t* h2c = reinterpret_cast<uint16_t*>(smem + M::OFF_S3);
 
   f32x4 acc3[Cfg::S3], acc2[Cfg::S2], acc1[Cfg::S1];
 #pragma unroll
@@ -163,15 +179,14 @@ __global__ void __launch_bounds__(NT) kf_backward(
     asm volatile("" ::: "memory");
     const size_t sb = (size_t)b * V;
     // stage x and g_y; BF16: masked field channel-major for dW1
-    for (int q = threadIdx.x; q < V / 4; q += NT) {
-      reinterpret_cast<f32x4*>(xs)[q] = reinterpret_cast<const f32x4*>(xin + sb)[q];
+    for (int q = threadIdx.x; q < VS; q += NT) xs[q] = xin[sb + LY::site_of(q)];
+    for (int q = threadIdx.x; q < V / 4; q += NT)
       reinterpret_cast<f32x4*>(gys)[q] = reinterpret_cast<const f32x4*>(gy + sb)[q];
-    }
     __syncthreads();
     if constexpr (BF16) {
-      uint16_t* h0c = reinterpret_cast<uint16_t*>(smem + Cfg::OFF_H0C);
+      uint16_t* h0c = reinterpret_cast<uint16_t*>(smem + M::OFF_H0C);
       for (int n = threadIdx.x; n < V; n += NT)
-        h0c[n] = (uint16_t)bf16_bits(G::parity(n) == fpar ? xs[n] : 0.f);
+        h0c[n] = (uint16_t)bf16_bits(G::parity(n) == fpar ? xs[LY::idx(n)] : 0.f);
     }
     // ---- recompute conv1 -> h1 ----
     {
@@ -184,23 +199,22 @@ __global__ void __launch_bounds__(NT) kf_backward(
         for (int c = 0; c < LF.k1; ++c) A[ct][c] = fr[(LF.off1 + ct * LF.k1 + c) * 64];
       }
       for (int tile = w; tile < V / 16; tile += NW) {
-        const int n = tile * 16 + m;
+        const int n = tile * 16 + m, p = LY::idx(n), pn = G::parity(n);
         f32x4 acc[LF.nct];
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < LF.k1; ++c) {
-          const u32x4 bop = gather_x<DIM, L, BF16>(xs, n, fpar, c, j);
+          const u32x4 bop = gather_x<LY, BF16>(xs, n, p, pn, fpar, c, j);
 #pragma unroll
           for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
         }
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct) {
-          store_hidden<C, BF16>(h1s, n, ct, j, acc[ct], bias[ct]);
+          const u32x2 hv = store_hidden<LY, C, BF16>(h1s, n, ct, j, acc[ct], bias[ct]);
           if constexpr (BF16) {
             const int co0 = ct * 16 + 4 * j;
             if (co0 < C) {
-              const uint32_t* hv = reinterpret_cast<const uint32_t*>(h1s + n * C + co0);
               const uint32_t w0 = hv[0], w1 = hv[1];
               h1c[(co0 + 0) * CSTR + n] = (uint16_t)w0;
               h1c[(co0 + 1) * CSTR + n] = (uint16_t)(w0 >> 16);
@@ -223,23 +237,22 @@ __global__ void __launch_bounds__(NT) kf_backward(
         for (int c = 0; c < LF.k2; ++c) A[ct][c] = fr[(LF.off2 + ct * LF.k2 + c) * 64];
       }
       for (int tile = w; tile < V / 16; tile += NW) {
-        const int n = tile * 16 + m;
+        const int n = tile * 16 + m, p = LY::idx(n);
         f32x4 acc[LF.nct];
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < LF.k2; ++c) {
-          const u32x4 bop = gather_h<DIM, L, C, BF16>(h1s, n, c, j);
+          const u32x4 bop = gather_h<LY, C, BF16>(h1s, n, p, c, j);
 #pragma unroll
           for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
         }
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct) {
-          store_hidden<C, BF16>(h2s, n, ct, j, acc[ct], bias[ct]);
+          const u32x2 hv = store_hidden<LY, C, BF16>(h2s, n, ct, j, acc[ct], bias[ct]);
           if constexpr (BF16) {
             const int co0 = ct * 16 + 4 * j;
             if (co0 < C) {
-              const uint32_t* hv = reinterpret_cast<const uint32_t*>(h2s + n * C + co0);
               const uint32_t w0 = hv[0], w1 = hv[1];
               h2c[(co0 + 0) * CSTR + n] = (uint16_t)w0;
               h2c[(co0 + 1) * CSTR + n] = (uint16_t)(w0 >> 16);
@@ -252,18 +265,20 @@ __global__ void __launch_bounds__(NT) kf_backward(
     }
     // ---- recompute conv3 at active sites; affine backward -> g_o, g_x(active) ----
     // g_o is zero at the frozen sites.
-    uint32_t* gos_b = reinterpret_cast<uint32_t*>(smem + Cfg::OFF_GOS);  // BF16 pairs
-    float* gos_f = reinterpret_cast<float*>(smem + Cfg::OFF_GOS);        // FP32 pairs
-    uint16_t* goc = reinterpret_cast<uint16_t*>(smem + Cfg::OFF_GOC);     // BF16 [2][CSTR]
+    uint32_t* gos_b = reinterpret_cast<uint32_t*>(smem + M::OFF_GOS);  // BF16 pairs, layout LY
+    float* gos_f = reinterpret_cast<float*>(smem + M::OFF_GOS);        // FP32 pairs, layout LY
+    uint16_t* goc = reinterpret_cast<uint16_t*>(smem + M::OFF_GOC);     // BF16 [2][CSTR]
     for (int q = threadIdx.x; q < V / 2; q += NT) {
       const int n = G::half_site(q, fpar);
       if constexpr (BF16) {
-        gos_b[n] = 0u;
+        LY::copies(n, [&](int pp) { gos_b[pp] = 0u; });
         goc[n] = 0;
         goc[CSTR + n] = 0;
       } else {
-        gos_f[2 * n] = 0.f;
-        gos_f[2 * n + 1] = 0.f;
+        LY::copies(n, [&](int pp) {
+          gos_f[2 * pp] = 0.f;
+          gos_f[2 * pp + 1] = 0.f;
+        });
       }
     }
     __syncthreads();
@@ -273,29 +288,31 @@ __global__ void __launch_bounds__(NT) kf_backward(
       for (int c = 0; c < LF.k2; ++c) A[c] = fr[(LF.off3 + c) * 64];
       const float bs = pl[off_b3], bt = pl[off_b3 + 1];
       for (int tile = w; tile < V / 32; tile += NW) {
-        const int n = G::half_site(tile * 16 + m, apar);
+        const int n = G::half_site(tile * 16 + m, apar), p = LY::idx(n);
         f32x4 acc{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < LF.k2; ++c)
-          acc = mma<BF16>(A[c], gather_h<DIM, L, C, BF16>(h2s, n, c, j), acc);
+          acc = mma<BF16>(A[c], gather_h<LY, C, BF16>(h2s, n, p, c, j), acc);
         if (j == 0) {
           const float o0 = acc[0] + bs;
           const float s = final_tanh ? tanhf(o0) : o0;
           const float es = expf(s);
           const float g = gys[n];
-          const float gs = g * xs[n] * es + g_ld;
+          const float gs = g * xs[p] * es + g_ld;
           const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
           db3s += go0;
           db3t += g;
           gx[sb + n] = g * es;
           if constexpr (BF16) {
             const uint32_t pr = pack_bf16(go0, g);
-            gos_b[n] = pr;
+            LY::copies(n, [&](int pp) { gos_b[pp] = pr; });
             goc[n] = (uint16_t)pr;
             goc[CSTR + n] = (uint16_t)(pr >> 16);
           } else {
-            gos_f[2 * n] = go0;
-            gos_f[2 * n + 1] = g;
+            LY::copies(n, [&](int pp) {
+              gos_f[2 * pp] = go0;
+              gos_f[2 * pp + 1] = g;
+            });
           }
         }
       }
@@ -322,8 +339,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int s = kc * 16 + 4 * j + r;
-                const float a = va ? h2s[s * C + ci] : 0.f;
-                const float bb = vb ? load1_shift<DIM, L, 2>(gos_f, s, co, tap, -1) : 0.f;
+                const float a = va ? h2s[LY::idx(s) * C + ci] : 0.f;
+                const float bb = vb ? load1_shift<LY, 2>(gos_f, s, co, tap, -1) : 0.f;
                 acc3[si] = mfma(a, bb, acc3[si]);
               }
             }
@@ -335,8 +352,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
     // ---- conv3^T: g_a2 = leaky'(h2) (W3^T * g_o) ----
     // BF16: site-major into S0 (h1s is dead), channel-major into S3 (h2c is dead);
     // FP32: in place over h2.
-    HT* ga2s = BF16 ? reinterpret_cast<HT*>(slot(0)) : h2s;
-    uint16_t* ga2c = reinterpret_cast<uint16_t*>(slot(3));
+    HT* ga2s = BF16 ? reinterpret_cast<HT*>(smem + M::OFF_S0) : h2s;
+    uint16_t* ga2c = reinterpret_cast<uint16_t*>(smem + M::OFF_S3);
     {
       u32x4 A[LF.nct][Cfg::KT3];
 #pragma unroll
@@ -344,7 +361,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
         for (int c = 0; c < Cfg::KT3; ++c) A[ct][c] = fr[(Cfg::OFF3T + ct * Cfg::KT3 + c) * 64];
       for (int tile = w; tile < V / 16; tile += NW) {
-        const int n = tile * 16 + m;
+        const int n = tile * 16 + m, p = LY::idx(n);
         f32x4 acc[LF.nct];
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -355,13 +372,13 @@ __global__ void __launch_bounds__(NT) kf_backward(
             const int t0 = (32 * c + 8 * j) / 2;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-              bop[q] = t0 + q < T ? gos_b[G::nbr(n, t0 + q, -1)] : 0u;
+              bop[q] = t0 + q < T ? gos_b[LY::nbr(n, p, t0 + q, -1)] : 0u;
           } else {
             const int t0 = (16 * c + 4 * j) / 2;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
               const int t = t0 + q;
-              const int nb = t < T ? G::nbr(n, t, -1) : 0;
+              const int nb = t < T ? LY::nbr(n, p, t, -1) : 0;
               bop[2 * q] = t < T ? __float_as_uint(gos_f[2 * nb]) : 0u;
               bop[2 * q + 1] = t < T ? __float_as_uint(gos_f[2 * nb + 1]) : 0u;
             }
@@ -375,22 +392,22 @@ __global__ void __launch_bounds__(NT) kf_backward(
           if (c0 < C) {
             float v[4];
             if constexpr (BF16) {
-              const uint32_t* hv = reinterpret_cast<const uint32_t*>(h2s + n * C + c0);
+              const uint32_t* hv = reinterpret_cast<const uint32_t*>(h2s + p * C + c0);
               const uint32_t w0 = hv[0], w1 = hv[1];
               const float hh[4] = {bf16_lo(w0), bf16_hi(w0), bf16_lo(w1), bf16_hi(w1)};
 #pragma unroll
               for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-              const uint32_t p0 = pack_bf16(v[0], v[1]), p1 = pack_bf16(v[2], v[3]);
-              *reinterpret_cast<u32x2*>(ga2s + n * C + c0) = u32x2{p0, p1};
+              const u32x2 pw = store4<LY, C, BF16>(ga2s, n, c0, v);
+              const uint32_t p0 = pw[0], p1 = pw[1];
               ga2c[(c0 + 0) * CSTR + n] = (uint16_t)p0;
               ga2c[(c0 + 1) * CSTR + n] = (uint16_t)(p0 >> 16);
               ga2c[(c0 + 2) * CSTR + n] = (uint16_t)p1;
               ga2c[(c0 + 3) * CSTR + n] = (uint16_t)(p1 >> 16);
             } else {
-              const f32x4 hh = *reinterpret_cast<const f32x4*>(h2s + n * C + c0);
+              const f32x4 hh = *reinterpret_cast<const f32x4*>(h2s + p * C + c0);
 #pragma unroll
               for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-              *reinterpret_cast<f32x4*>(ga2s + n * C + c0) = f32x4{v[0], v[1], v[2], v[3]};
+              store4<LY, C, BF16>(ga2s, n, c0, v);
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) db2[ct][i] += v[i];
@@ -419,8 +436,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int s = kc * 16 + 4 * j + r;
-                const float a = va ? h1s[s * C + ci] : 0.f;
-                const float bb = vb ? load1_shift<DIM, L, C>(ga2s, s, co, tap, -1) : 0.f;
+                const float a = va ? h1s[LY::idx(s) * C + ci] : 0.f;
+                const float bb = vb ? load1_shift<LY, C>(ga2s, s, co, tap, -1) : 0.f;
                 acc2[si] = mfma(a, bb, acc2[si]);
               }
             }
@@ -432,8 +449,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
     // ---- conv2^T: g_a1 = leaky'(h1) (W2^T * g_a2) ----
     // BF16: site-major into S2 (h2s is dead), channel-major into S3 (g_a2c is dead);
     // FP32: in place over h1.
-    HT* ga1s = BF16 ? reinterpret_cast<HT*>(slot(2)) : h1s;
-    uint16_t* ga1c = reinterpret_cast<uint16_t*>(slot(3));
+    HT* ga1s = BF16 ? reinterpret_cast<HT*>(smem + M::OFF_S2) : h1s;
+    uint16_t* ga1c = reinterpret_cast<uint16_t*>(smem + M::OFF_S3);
     {
       u32x4 A[LF.nct][LF.k2];
 #pragma unroll
@@ -441,13 +458,13 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
         for (int c = 0; c < LF.k2; ++c) A[ct][c] = fr[(Cfg::OFF2T + ct * LF.k2 + c) * 64];
       for (int tile = w; tile < V / 16; tile += NW) {
-        const int n = tile * 16 + m;
+        const int n = tile * 16 + m, p = LY::idx(n);
         f32x4 acc[LF.nct];
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < LF.k2; ++c) {
-          const u32x4 bop = gather_h<DIM, L, C, BF16, -1>(ga2s, n, c, j);
+          const u32x4 bop = gather_h<LY, C, BF16, -1>(ga2s, n, p, c, j);
 #pragma unroll
           for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
         }
@@ -462,17 +479,17 @@ __global__ void __launch_bounds__(NT) kf_backward(
               for (int i = 0; i < 4; ++i) hh[i] = __uint_as_float((uint32_t)h1c[(c0 + i) * CSTR + n] << 16);
 #pragma unroll
               for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-              const uint32_t p0 = pack_bf16(v[0], v[1]), p1 = pack_bf16(v[2], v[3]);
-              *reinterpret_cast<u32x2*>(ga1s + n * C + c0) = u32x2{p0, p1};
+              const u32x2 pw = store4<LY, C, BF16>(ga1s, n, c0, v);
+              const uint32_t p0 = pw[0], p1 = pw[1];
               ga1c[(c0 + 0) * CSTR + n] = (uint16_t)p0;
               ga1c[(c0 + 1) * CSTR + n] = (uint16_t)(p0 >> 16);
               ga1c[(c0 + 2) * CSTR + n] = (uint16_t)p1;
               ga1c[(c0 + 3) * CSTR + n] = (uint16_t)(p1 >> 16);
             } else {
-              const f32x4 hh = *reinterpret_cast<const f32x4*>(h1s + n * C + c0);
+              const f32x4 hh = *reinterpret_cast<const f32x4*>(h1s + p * C + c0);
 #pragma unroll
               for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-              *reinterpret_cast<f32x4*>(ga1s + n * C + c0) = f32x4{v[0], v[1], v[2], v[3]};
+              store4<LY, C, BF16>(ga1s, n, c0, v);
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) db1[ct][i] += v[i];
@@ -484,7 +501,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
     // ---- dW1[c][tap] += sum_n g_a1[n][c] h0[n + delta_tap] (h0 = mask_F x) ----
     {
       constexpr int NTL = (T + 15) / 16;
-      const uint16_t* h0c = reinterpret_cast<const uint16_t*>(smem + Cfg::OFF_H0C);
+      const uint16_t* h0c = reinterpret_cast<const uint16_t*>(smem + M::OFF_H0C);
 #pragma unroll
       for (int si = 0; si < Cfg::S1; ++si) {
         const int u = w + NW * si;
@@ -503,11 +520,11 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int s = kc * 16 + 4 * j + r;
-                const float a = va ? ga1s[s * C + c] : 0.f;
+                const float a = va ? ga1s[LY::idx(s) * C + c] : 0.f;
                 float bb = 0.f;
                 if (vb) {
-                  const int nb = G::nbr(s, tap, 1);
-                  bb = G::parity(nb) == fpar ? xs[nb] : 0.f;
+                  const float xv = xs[LY::nbr(s, LY::idx(s), tap, 1)];
+                  bb = (G::parity(s) ^ todd<DIM>(tap)) == fpar ? xv : 0.f;
                 }
                 acc1[si] = mfma(a, bb, acc1[si]);
               }
@@ -522,11 +539,11 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
       for (int c = 0; c < LF.k2; ++c) A[c] = fr[(Cfg::OFF1T + c) * 64];
       for (int tile = w; tile < V / 32; tile += NW) {
-        const int n = G::half_site(tile * 16 + m, fpar);
+        const int n = G::half_site(tile * 16 + m, fpar), p = LY::idx(n);
         f32x4 acc{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < LF.k2; ++c)
-          acc = mma<BF16>(A[c], gather_h<DIM, L, C, BF16, -1>(ga1s, n, c, j), acc);
+          acc = mma<BF16>(A[c], gather_h<LY, C, BF16, -1>(ga1s, n, p, c, j), acc);
         if (j == 0) gx[sb + n] = gys[n] + acc[0];
       }
     }
@@ -614,13 +631,27 @@ __global__ void __launch_bounds__(NT) kf_backward(
   for (int i = threadIdx.x; i < Cfg::P_LAYER; i += NT) out[i] = red[i];
 }
 
+// out[i] = sum over g of partial[g][i], fixed order: 32 parameters per block,
+// 8 slices of the workgroup partials per parameter summed in index order, then
+// the slices combined in index order.
 __global__ void __launch_bounds__(256) kf_reduce(int G, int P, const float* __restrict__ partial,
                                                  float* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P) return;
+  __shared__ float sh[8][33];
+  const int col = threadIdx.x & 31, sl = threadIdx.x >> 5;
+  const int i = blockIdx.x * 32 + col;
   float acc = 0.f;
-  for (int g = 0; g < G; ++g) acc += partial[(size_t)g * P + i];
-  out[i] = acc;
+  if (i < P) {
+    const int g0 = (int)((long)G * sl / 8), g1 = (int)((long)G * (sl + 1) / 8);
+    for (int g = g0; g < g1; ++g) acc += partial[(size_t)g * P + i];
+  }
+  sh[sl][col] = acc;
+  __syncthreads();
+  if (sl == 0 && i < P) {
+    float r = sh[0][col];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) r += sh[q][col];
+    out[i] = r;
+  }
 }
 
 __global__ void kf_gz(int64_t n, const float* __restrict__ gx, const float* __restrict__ z,
@@ -706,7 +737,7 @@ int32_t launch_backward(const FlowGeom& g, const float* params, int B, const flo
                        (int)g.off_b1, (int)g.off_b2, (int)g.off_b3, (int)g.off_W1, (int)g.off_W2,
                        (int)g.off_W3, g.frozen_parity(l), g.final_tanh, (float)(-g_logq), B,
                        saved + (size_t)l * BV, gy, gx, partial);
-    hipLaunchKernelGGL(kf_reduce, dim3((Cfg::P_LAYER + 255) / 256), dim3(256), 0, st, grid,
+    hipLaunchKernelGGL(kf_reduce, dim3((Cfg::P_LAYER + 31) / 32), dim3(256), 0, st, grid,
                        Cfg::P_LAYER, partial, g_params + (size_t)l * g.P_layer);
     gy = gx;
     which ^= 1;

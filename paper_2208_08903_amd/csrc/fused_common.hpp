@@ -36,15 +36,14 @@ __device__ __forceinline__ f32x4 mfma(float a, float b, const f32x4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// FP32 -> BF16 bits, round to nearest even (same rounding as bf16_round).
-__device__ __forceinline__ uint32_t bf16_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return u >> 16;
-}
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16, round to nearest even (v_cvt_pk_bf16_f32; same rounding as bf16_round).
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
-  return bf16_bits(lo) | (bf16_bits(hi) << 16);
+  const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, v);
 }
+__device__ __forceinline__ uint32_t bf16_bits(float x) { return pack_bf16(x, 0.f) & 0xFFFFu; }
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
@@ -89,6 +88,88 @@ struct Geo {
     return row * L + 2 * i + ((par + lead) & 1);
   }
 };
+
+// Storage of a site-major lattice tensor in LDS.  PAD: a one-site periodic halo
+// on every side, so the neighbour of a site is its storage index plus a
+// constant per tap, and producers also write the halo copies of boundary sites.
+// Without PAD the storage index is the site index and neighbours come from
+// periodic wrap arithmetic (for shapes whose padded lattice does not fit LDS).
+template <int DIM, int L, bool PAD>
+struct Lay {
+  using G = Geo<DIM, L>;
+  static constexpr bool padded = PAD;
+  static constexpr int LP = PAD ? L + 2 : L;
+  static constexpr int VS = DIM == 2 ? LP * LP : LP * LP * LP;  // storage sites
+
+  __device__ static __forceinline__ int idx(int n) {
+    if constexpr (!PAD) return n;
+    if constexpr (DIM == 2) return (n / L + 1) * LP + n % L + 1;
+    return ((n / (L * L) + 1) * LP + (n / L) % L + 1) * LP + n % L + 1;
+  }
+  // Storage-index offset of tap t (padded layout).
+  __device__ static __forceinline__ int toff(int t) {
+    if constexpr (DIM == 2) return G::tap_d(t, 0) * LP + G::tap_d(t, 1);
+    return (G::tap_d(t, 0) * LP + G::tap_d(t, 1)) * LP + G::tap_d(t, 2);
+  }
+  // Storage index of site n + sign * delta_t; p = idx(n).
+  __device__ static __forceinline__ int nbr(int n, int p, int t, int sign) {
+    if constexpr (PAD) return p + sign * toff(t);
+    return G::nbr(n, t, sign);
+  }
+  // Interior site held at storage index p (PAD: halo entries map to their source).
+  __device__ static __forceinline__ int site_of(int p) {
+    if constexpr (!PAD) return p;
+    if constexpr (DIM == 2) {
+      const int py = p / LP, px = p % LP;
+      return ((py + L - 1) % L) * L + (px + L - 1) % L;
+    } else {
+      const int pz = p / (LP * LP), py = (p / LP) % LP, px = p % LP;
+      return (((pz + L - 1) % L) * L + (py + L - 1) % L) * L + (px + L - 1) % L;
+    }
+  }
+  // Calls f(storage index) for every stored copy of site n.
+  template <class F>
+  __device__ static __forceinline__ void copies(int n, F&& f) {
+    f(idx(n));
+    if constexpr (PAD) {
+      int c[DIM], a[DIM];
+      int q = n;
+#pragma unroll
+      for (int mu = DIM - 1; mu >= 0; --mu) {
+        c[mu] = q % L;
+        q /= L;
+      }
+      bool any = false;
+#pragma unroll
+      for (int mu = 0; mu < DIM; ++mu) {
+        a[mu] = c[mu] == 0 ? L + 1 : (c[mu] == L - 1 ? 0 : -1);
+        any |= a[mu] >= 0;
+      }
+      if (any) {
+#pragma unroll
+        for (int msk = 1; msk < (1 << DIM); ++msk) {
+          bool ok = true;
+          int p = 0;
+#pragma unroll
+          for (int mu = 0; mu < DIM; ++mu) {
+            const bool alt = (msk >> (DIM - 1 - mu)) & 1;
+            const int pc = alt ? a[mu] : c[mu] + 1;
+            ok &= pc >= 0;
+            p = p * LP + pc;
+          }
+          if (ok) f(p);
+        }
+      }
+    }
+  }
+};
+
+// Parity of |delta_t|_1: a neighbour at tap t has parity p(n) ^ todd(t).
+template <int DIM>
+__device__ __forceinline__ int todd(int t) {
+  if constexpr (DIM == 2) return (t / 3 + t % 3) & 1;  // (d0+1) + (d1+1) has the parity of d0 + d1
+  return (t / 9 + (t / 3) % 3 + t % 3 + 1) & 1;
+}
 
 // Number of 32-wide BF16 K chunks / 16-wide FP32 K blocks of a convolution
 // with K = taps * cin.

@@ -59,23 +59,24 @@ __global__ void kf_prep(const float* __restrict__ params, int N, int T, int P_la
 template <bool BF16>
 using HElem = std::conditional_t<BF16, uint16_t, float>;
 
-// B operand of a C-input convolution at output site n for K chunk (BF16) /
-// block (FP32) c: the lane's 8 (4) consecutive input channels at one tap.
-template <int DIM, int L, int C, bool BF16, int SIGN = 1>
-__device__ __forceinline__ u32x4 gather_h(const HElem<BF16>* h, int n, int c, int j) {
-  using G = Geo<DIM, L>;
-  constexpr int K = G::T * C;
+// B operand of a C-input convolution at output site n (storage index p) for K
+// chunk (BF16) / block (FP32) c: the lane's 8 (4) consecutive input channels at
+// one tap, site n + SIGN * delta_tap.
+template <class LY, int C, bool BF16, int SIGN = 1>
+__device__ __forceinline__ u32x4 gather_h(const HElem<BF16>* h, int n, int p, int c, int j) {
+  constexpr int K = LY::G::T * C;
   const int k0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
   if (k0 >= K) return u32x4{0u, 0u, 0u, 0u};
   const int tap = k0 / C, ci0 = k0 % C;
-  const int nb = G::nbr(n, tap, SIGN);
-  return *reinterpret_cast<const u32x4*>(h + nb * C + ci0);
+  return *reinterpret_cast<const u32x4*>(h + LY::nbr(n, p, tap, SIGN) * C + ci0);
 }
 
-// B operand of conv1 (one masked input channel): taps of the lane's K slice.
-template <int DIM, int L, bool BF16>
-__device__ __forceinline__ u32x4 gather_x(const float* xs, int n, int fpar, int c, int j) {
-  using G = Geo<DIM, L>;
+// B operand of conv1: the masked field (frozen sites only) at the taps of the
+// lane's K slice; xs is stored with layout LY; pn = parity of site n.
+template <class LY, bool BF16>
+__device__ __forceinline__ u32x4 gather_x(const float* xs, int n, int p, int pn, int fpar, int c,
+                                          int j) {
+  constexpr int T = LY::G::T;
   constexpr int NV = BF16 ? 8 : 4;
   const int t0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
   float v[NV];
@@ -83,9 +84,9 @@ __device__ __forceinline__ u32x4 gather_x(const float* xs, int n, int fpar, int 
   for (int i = 0; i < NV; ++i) {
     const int t = t0 + i;
     v[i] = 0.f;
-    if (t < G::T) {
-      const int nb = G::nbr(n, t);
-      if (G::parity(nb) == fpar) v[i] = xs[nb];
+    if (t < T) {
+      const float xv = xs[LY::nbr(n, p, t, 1)];
+      v[i] = (pn ^ todd<LY::G::T == 9 ? 2 : 3>(t)) == fpar ? xv : 0.f;
     }
   }
   u32x4 r;
@@ -111,21 +112,31 @@ __device__ __forceinline__ f32x4 mma(const u32x4& a, const u32x4& b, f32x4 acc) 
   }
 }
 
+// Store 4 channel values v (rows 4j..4j+3 of output-channel tile ct) of site n
+// in every stored copy of the site; returns the packed BF16 words (BF16 mode).
+template <class LY, int C, bool BF16>
+__device__ __forceinline__ u32x2 store4(HElem<BF16>* h, int n, int co0, const float (&v)[4]) {
+  if constexpr (BF16) {
+    const u32x2 wv{pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3])};
+    LY::copies(n, [&](int p) { *reinterpret_cast<u32x2*>(h + p * C + co0) = wv; });
+    return wv;
+  } else {
+    const f32x4 fv{v[0], v[1], v[2], v[3]};
+    LY::copies(n, [&](int p) { *reinterpret_cast<f32x4*>(h + p * C + co0) = fv; });
+    return u32x2{0u, 0u};
+  }
+}
+
 // Store leaky(acc + bias) for rows 4j..4j+3 of output-channel tile ct at site n.
-template <int C, bool BF16>
-__device__ __forceinline__ void store_hidden(HElem<BF16>* h, int n, int ct, int j, const f32x4& acc,
-                                             const f32x4& bias) {
+template <class LY, int C, bool BF16>
+__device__ __forceinline__ u32x2 store_hidden(HElem<BF16>* h, int n, int ct, int j,
+                                              const f32x4& acc, const f32x4& bias) {
   const int co0 = ct * 16 + 4 * j;
-  if (co0 >= C) return;
+  if (co0 >= C) return u32x2{0u, 0u};
   float v[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) v[i] = leaky(acc[i] + bias[i]);
-  if constexpr (BF16) {
-    u32x2 w{pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3])};
-    *reinterpret_cast<u32x2*>(h + n * C + co0) = w;
-  } else {
-    *reinterpret_cast<f32x4*>(h + n * C + co0) = f32x4{v[0], v[1], v[2], v[3]};
-  }
+  return store4<LY, C, BF16>(h, n, co0, v);
 }
 
 template <int C>
@@ -144,7 +155,12 @@ struct FwdCfg {
   using G = Geo<DIM, L>;
   static constexpr int V = G::V, T = G::T;
   static constexpr LayerFrags LF = layer_frags(T, C, BF16);
-  static constexpr size_t lds_bytes = (size_t)V * 4 + 2 * (size_t)V * C * sizeof(HElem<BF16>);
+  static constexpr size_t bytes_for(int vs) {
+    return ((size_t)vs * 4 + 15) / 16 * 16 + 2 * (size_t)vs * C * sizeof(HElem<BF16>);
+  }
+  static constexpr bool PAD = bytes_for(Lay<DIM, L, true>::VS) <= 156 * 1024;
+  using LY = Lay<DIM, L, PAD>;
+  static constexpr size_t lds_bytes = bytes_for(LY::VS);
   static constexpr int NT = lds_bytes > 80 * 1024 ? 512 : 256;
 };
 
