@@ -27,6 +27,38 @@ sys.path.insert(0, ROOT)
 WORKLOAD = dict(workload="phi4-2d-L32-train", dim=2, L=32, m2=-4.0, lam=8.0, n_layers=16,
                 hidden=16, batch=1024, lr=1e-3)
 PEAK = {"bf16_mfma_tflops": 2500.0, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
+KERNEL_SOURCES = ["paper_2208_08903_amd/csrc/flow_fused_bwd.hip",
+                  "paper_2208_08903_amd/csrc/fused_kernels.hpp",
+                  "paper_2208_08903_amd/csrc/fused_common.hpp"]
+TRAFFIC_FILE = "profiles/kf_backward_phi4-2d-L32-train_traffic.txt"
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per backward launch from the committed rocprofv3 --pmc summary, if the
+    kernel sources are unchanged since the counters were taken; else None."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256_16") != kernel_source_sha():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def algorithmic_flops_per_sample_layer(dim, L, C):
@@ -165,6 +197,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP32/sampling/HMC side figures")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="after the timed region, one device-to-device copy of this many MiB "
+                         "(the known-size kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -208,7 +243,8 @@ def main():
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     roof = {"kernel": dom_name, "bound": "mfma", "achieved": round(achieved, 3),
             "peak": PEAK["bf16_mfma_tflops"], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK["bf16_mfma_tflops"], 5), "traffic": None,
+            "frac": round(achieved / PEAK["bf16_mfma_tflops"], 5),
+            "traffic": recorded_traffic() if dom_name.startswith("flow_backward") else None,
             "flops_per_launch": dom_flops, "ms_per_launch": round(dom_ms, 5)}
 
     out = {
@@ -241,6 +277,13 @@ def main():
                                                      lfs.LFS_PLAIN_FP32, params=params),
                                              B, w["m2"], w["lam"], batches=4)
         out["hmc_fp64_3d_L8"] = hmc_rate()
+    if args.copy_calibration_mb > 0:
+        nb = args.copy_calibration_mb * 2 ** 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nb
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
