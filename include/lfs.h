@@ -132,6 +132,16 @@ int32_t lfs_workspace_bytes(const lfs_flow_desc* desc, int32_t B, int32_t for_ba
 int32_t lfs_prior_normal(uint64_t key, uint64_t counter0, int32_t B, int32_t V, float* z,
                          double* logr, void* stream);
 
+/* Prior draw with one random stream per sample, for batches that mix samples of
+ * different requests (same definition as lfs_prior_normal; sample b uses key
+ * keys[b] and counter counters[b], so lfs_prior_normal(key, c0, ...) equals
+ * keys[b] = key, counters[b] = c0 + b).
+ *   keys, counters  [B] uint64, device memory
+ *   z               [B][V] FP32 output, 16-byte aligned;  logr [B] FP64 or NULL
+ * Errors: EINVAL (B <= 0, V <= 0, V % 4 != 0, nulls, misaligned z). */
+int32_t lfs_prior_normal_streams(int32_t B, int32_t V, const uint64_t* keys,
+                                 const uint64_t* counters, float* z, double* logr, void* stream);
+
 /* Flow forward in the sampling direction, phi = F^{-1}(z) (paper Sec. 1,
  * untrivializing map and coupling-layer equation).  For every layer the
  * frozen sublattice is fed (active sites zeroed) through
@@ -208,6 +218,19 @@ int32_t lfs_log_weights(int32_t B, const double* S, const double* logq, double* 
  * Errors: EINVAL (n_chains <= 0, n_prop <= 0, nulls). */
 int32_t lfs_mh_chain(int32_t n_chains, int32_t n_prop, const double* logw, const double* log_u,
                      lfs_chain_state* state, int64_t* cur_idx, uint8_t* accepted, void* stream);
+
+/* Independence Metropolis-Hastings over ragged chunks: chain c takes the
+ * proposals [offsets[c], offsets[c+1]) of the flat logw / log_u arrays, in order,
+ * with its state in states[state_index[c]]; same decision rule and outputs as
+ * lfs_mh_chain (cur_idx and accepted are written at the proposals' positions).
+ * Used by the server, where one batch holds chunks of several requests.
+ *   offsets      [n_chains + 1] int64, non-decreasing, offsets[0] >= 0
+ *   state_index  [n_chains] int32, distinct
+ * Errors: EINVAL (n_chains <= 0, nulls). */
+int32_t lfs_mh_chain_ragged(int32_t n_chains, const int64_t* offsets, const double* logw,
+                            const double* log_u, lfs_chain_state* states,
+                            const int32_t* state_index, int64_t* cur_idx, uint8_t* accepted,
+                            void* stream);
 
 /* HMC trajectory per chain, the paper's comparison baseline (Sec. 2.2):
  * H = 1/2 sum pi^2 + S(phi); n_steps leapfrog steps of size dt in

@@ -8,17 +8,24 @@ namespace {
 
 // One 64-lane block per chain.  Chunks of 64 proposals are staged through LDS
 // with coalesced loads; lane 0 makes the sequential decisions.
-__global__ void __launch_bounds__(64) k_mh_chain(int n_prop, const double* __restrict__ logw,
+// Chain c reads proposals [offsets[c], offsets[c+1]) (rectangular calls pass
+// offsets == NULL and use [c * n_prop, (c+1) * n_prop)); its state lives at
+// state[state_index[c]] (or state[c]).
+__global__ void __launch_bounds__(64) k_mh_chain(int n_prop_rect, const int64_t* __restrict__ offsets,
+                                                 const double* __restrict__ logw,
                                                  const double* __restrict__ log_u,
-                                                 lfs_chain_state* __restrict__ state,
+                                                 lfs_chain_state* __restrict__ states,
+                                                 const int32_t* __restrict__ state_index,
                                                  int64_t* __restrict__ cur_idx,
                                                  uint8_t* __restrict__ accepted) {
   __shared__ double sw[kWave], su[kWave];
   __shared__ int64_t sidx[kWave];
   __shared__ uint8_t sacc[kWave];
   const int c = blockIdx.x, lane = threadIdx.x;
-  const size_t base = (size_t)c * n_prop;
-  lfs_chain_state st = state[c];
+  const size_t base = offsets ? (size_t)offsets[c] : (size_t)c * n_prop_rect;
+  const int n_prop = offsets ? (int)(offsets[c + 1] - offsets[c]) : n_prop_rect;
+  lfs_chain_state* state = states + (state_index ? state_index[c] : c);
+  lfs_chain_state st = *state;
   const int64_t seen0 = st.n_seen;
   for (int k0 = 0; k0 < n_prop; k0 += kWave) {
     const int k = k0 + lane;
@@ -59,7 +66,7 @@ __global__ void __launch_bounds__(64) k_mh_chain(int n_prop, const double* __res
   }
   if (lane == 0) {
     st.n_seen = seen0 + n_prop;
-    state[c] = st;
+    *state = st;
   }
 }
 
@@ -165,7 +172,18 @@ extern "C" int32_t lfs_mh_chain(int32_t n_chains, int32_t n_prop, const double* 
                                 uint8_t* accepted, void* stream) {
   LFS_RETURN_IF(n_chains <= 0 || n_prop <= 0 || !logw || !log_u || !state || !cur_idx, LFS_EINVAL);
   hipLaunchKernelGGL(lfs::k_mh_chain, dim3(n_chains), dim3(lfs::kWave), 0, (hipStream_t)stream,
-                     n_prop, logw, log_u, state, cur_idx, accepted);
+                     n_prop, nullptr, logw, log_u, state, nullptr, cur_idx, accepted);
+  return lfs::launch_status();
+}
+
+extern "C" int32_t lfs_mh_chain_ragged(int32_t n_chains, const int64_t* offsets, const double* logw,
+                                       const double* log_u, lfs_chain_state* states,
+                                       const int32_t* state_index, int64_t* cur_idx,
+                                       uint8_t* accepted, void* stream) {
+  LFS_RETURN_IF(n_chains <= 0 || !offsets || !logw || !log_u || !states || !state_index || !cur_idx,
+                LFS_EINVAL);
+  hipLaunchKernelGGL(lfs::k_mh_chain, dim3(n_chains), dim3(lfs::kWave), 0, (hipStream_t)stream, 0,
+                     offsets, logw, log_u, states, state_index, cur_idx, accepted);
   return lfs::launch_status();
 }
 

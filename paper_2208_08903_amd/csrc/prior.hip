@@ -33,13 +33,18 @@ __device__ __forceinline__ float word_to_unit(uint32_t x) {
   return ((float)(x >> 9) + 0.5f) * 0x1p-23f;
 }
 
-// One block per sample; each thread produces 4 sites per Philox call.
-__global__ void __launch_bounds__(256) k_prior(uint32_t key0, uint32_t key1, uint64_t counter0,
-                                               int V, float* __restrict__ z,
-                                               double* __restrict__ logr) {
+// One block per sample; each thread produces 4 sites per Philox call.  The
+// sample's key and counter come from (key, counter0 + b) or, if keys != NULL,
+// from keys[b] and counters[b].
+__global__ void __launch_bounds__(256) k_prior(uint32_t key0_, uint32_t key1_, uint64_t counter0,
+                                               const uint64_t* __restrict__ keys,
+                                               const uint64_t* __restrict__ counters, int V,
+                                               float* __restrict__ z, double* __restrict__ logr) {
   __shared__ double sh[16];
   const int b = blockIdx.x;
-  const uint64_t cb = counter0 + (uint64_t)b;
+  const uint64_t cb = keys ? counters[b] : counter0 + (uint64_t)b;
+  const uint32_t key0 = keys ? (uint32_t)keys[b] : key0_;
+  const uint32_t key1 = keys ? (uint32_t)(keys[b] >> 32) : key1_;
   float4* zb = reinterpret_cast<float4*>(z + (size_t)b * V);
   double acc = 0.0;
   for (int j = threadIdx.x; j < V / 4; j += blockDim.x) {
@@ -71,6 +76,16 @@ extern "C" int32_t lfs_prior_normal(uint64_t key, uint64_t counter0, int32_t B, 
   LFS_RETURN_IF(B <= 0 || V <= 0 || (V % 4) != 0 || z == nullptr, LFS_EINVAL);
   LFS_RETURN_IF(((uintptr_t)z & 15u) != 0, LFS_EINVAL);  // float4 stores
   hipLaunchKernelGGL(lfs::k_prior, dim3(B), dim3(256), 0, (hipStream_t)stream, (uint32_t)key,
-                     (uint32_t)(key >> 32), counter0, V, z, logr);
+                     (uint32_t)(key >> 32), counter0, nullptr, nullptr, V, z, logr);
+  return lfs::launch_status();
+}
+
+extern "C" int32_t lfs_prior_normal_streams(int32_t B, int32_t V, const uint64_t* keys,
+                                            const uint64_t* counters, float* z, double* logr,
+                                            void* stream) {
+  LFS_RETURN_IF(B <= 0 || V <= 0 || (V % 4) != 0 || !z || !keys || !counters, LFS_EINVAL);
+  LFS_RETURN_IF(((uintptr_t)z & 15u) != 0, LFS_EINVAL);
+  hipLaunchKernelGGL(lfs::k_prior, dim3(B), dim3(256), 0, (hipStream_t)stream, 0u, 0u, 0ull, keys,
+                     counters, V, z, logr);
   return lfs::launch_status();
 }

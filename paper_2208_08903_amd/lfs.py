@@ -49,6 +49,8 @@ _SIGS = {
     "lfs_param_count": (c_sz, [ctypes.POINTER(FlowDesc)]),
     "lfs_workspace_bytes": (c_i32, [ctypes.POINTER(FlowDesc), c_i32, c_i32, ctypes.POINTER(c_sz)]),
     "lfs_prior_normal": (c_i32, [c_u64, c_u64, c_i32, c_i32, c_vp, c_vp, c_vp]),
+    "lfs_prior_normal_streams": (c_i32, [c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lfs_mh_chain_ragged": (c_i32, [c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lfs_flow_forward": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
                                  c_vp, c_vp, c_sz, c_vp]),
     "lfs_flow_backward": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_f64, c_vp,
@@ -131,6 +133,16 @@ def prior_normal(key: int, counter0: int, z, logr=None):
                                    _p(logr, torch.float64, "logr"), _stream()))
 
 
+def prior_normal_streams(keys, counters, z, logr=None):
+    B, V = z.shape
+    if keys.numel() != B or counters.numel() != B:
+        raise LfsError("keys and counters need one entry per sample")
+    _check(load().lfs_prior_normal_streams(B, V, _p(keys, torch.int64, "keys"),
+                                           _p(counters, torch.int64, "counters"),
+                                           _p(z, torch.float32, "z"),
+                                           _p(logr, torch.float64, "logr"), _stream()))
+
+
 def flow_forward(desc, params, z, phi, logq, logdet=None, saved_x=None, ws=None):
     B = z.shape[0]
     nbytes = ws.numel() if ws is not None else 0
@@ -193,6 +205,18 @@ def mh_chain(logw, log_u, state, cur_idx, accepted=None):
                                _p(log_u, torch.float64, "log_u"), _p(state, torch.uint8, "state"),
                                _p(cur_idx, torch.int64, "cur_idx"),
                                _p(accepted, torch.uint8, "accepted"), _stream()))
+
+
+def mh_chain_ragged(offsets, logw, log_u, states, state_index, cur_idx, accepted=None):
+    """offsets: int64 [n_chains+1] device tensor; states: byte buffer of chain states."""
+    n_chains = offsets.numel() - 1
+    _check(load().lfs_mh_chain_ragged(n_chains, _p(offsets, torch.int64, "offsets"),
+                                      _p(logw, torch.float64, "logw"),
+                                      _p(log_u, torch.float64, "log_u"),
+                                      _p(states, torch.uint8, "states"),
+                                      _p(state_index, torch.int32, "state_index"),
+                                      _p(cur_idx, torch.int64, "cur_idx"),
+                                      _p(accepted, torch.uint8, "accepted"), _stream()))
 
 
 def hmc_step(dim, L, phi, pi0, log_u, m2, lam, n_steps, dt, dH, accepted):

@@ -362,3 +362,40 @@ def test_fused_backward_matches_generic(precision):
     gb, gzb = run_backward(desc_g, run_forward(desc_g, params, z), g, 0.3)
     tol = 1e-5 if precision == lfs.LFS_PLAIN_FP32 else 2e-2
     assert rel_norm(ga, gb) < tol and rel_norm(gza, gzb) < tol
+
+
+def test_prior_streams_matches_single_stream_and_oracle():
+    B, V = 6, 64
+    keys = np.array([11, 11, 11, 7, 7, 2**40 + 3], np.int64)
+    ctrs = np.array([0, 1, 2, 5, 9, 123456789012], np.int64)
+    z = torch.empty(B, V, device=DEV, dtype=torch.float32)
+    lfs.prior_normal_streams(dev(keys, torch.int64), dev(ctrs, torch.int64), z)
+    z1 = torch.empty(3, V, device=DEV, dtype=torch.float32)
+    lfs.prior_normal(11, 0, z1)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(z)[:3], host(z1))
+    for b in range(B):
+        zo = op.prior_normal(int(keys[b]), int(ctrs[b]), 1, V)[0]
+        assert np.all(np.abs(host(z)[b] - zo) <= 2e-6 * (1 + np.abs(zo)))
+
+
+def test_mh_chain_ragged_bit_exact():
+    sizes = [5, 0, 130, 64, 1]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(offs[-1])
+    w = si.logw_stream(21, n, 2.0)
+    lu = si.log_uniforms(22, n)
+    slots = np.array([3, 0, 4, 1, 2], np.int32)
+    states = lfs.new_chain_state(5)
+    cur = torch.empty(n, device=DEV, dtype=torch.int64)
+    acc = torch.empty(n, device=DEV, dtype=torch.uint8)
+    lfs.mh_chain_ragged(dev(offs, torch.int64), dev(w, torch.float64), dev(lu, torch.float64),
+                        states, dev(slots, torch.int32), cur, acc)
+    torch.cuda.synchronize()
+    st = lfs.decode_chain_state(states)
+    for c in range(len(sizes)):
+        a, b = offs[c], offs[c + 1]
+        co, ao, so = omh.mh_chain(w[a:b], lu[a:b])
+        np.testing.assert_array_equal(host(cur)[a:b], co)
+        np.testing.assert_array_equal(host(acc)[a:b], ao)
+        assert st[slots[c]]["n_seen"] == sizes[c] and st[slots[c]]["n_acc"] == so.n_acc
