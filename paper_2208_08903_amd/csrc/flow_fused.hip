@@ -226,11 +226,12 @@ const FwdEntry* find_fwd(const FlowGeom& g) {
 
 bool fused_supported(const FlowGeom& g, int for_backward) {
   if (for_backward) return fused::bwd_supported(g);
-  return fused::find_fwd(g) != nullptr;
+  return fused::find_fwd(g) != nullptr || fused::ring_supported(g);
 }
 
 size_t fused_ws_bytes(const FlowGeom& g, int B, int for_backward) {
   if (for_backward) return fused::bwd_ws_bytes(g, B);
+  if (!fused::find_fwd(g)) return fused::ring_ws_bytes(g);
   const fused::FwdEntry* e = fused::find_fwd(g);
   return e ? align_up(e->frag_bytes_per_layer * g.N) : 0;
 }
@@ -238,7 +239,7 @@ size_t fused_ws_bytes(const FlowGeom& g, int B, int for_backward) {
 int32_t fused_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
                       double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
   const fused::FwdEntry* e = fused::find_fwd(g);
-  if (!e) return LFS_EUNSUPPORTED;
+  if (!e) return fused::ring_forward(g, params, B, z, phi, logq, logdet, saved, ws, st);
   return e->fn(g, params, B, z, phi, logq, logdet, saved, ws, st);
 }
 

@@ -1,0 +1,280 @@
+// Fused flow forward for 3D lattices whose hidden activations do not fit LDS
+// (L = 16: 128-256 KB per tensor per sample).  One workgroup still owns a whole
+// sample and runs every coupling layer (paper Sec. 1, coupling-layer and
+// composition equations), but the hidden activations stream along axis 0
+// through rings of three planes:
+//
+//   for output plane z:  h1[z+2]  (conv1 of the masked field, planes z+1..z+3)
+//                        h2[z+1]  (conv2 of h1 planes z..z+2)
+//                        conv3 of h2 planes z-1..z+1 at the active sites of
+//                        plane z, affine update, log-det
+//
+// Planes are indexed by a virtual plane number that runs from -2 to L+1, so the
+// ring slot of virtual plane v is v mod 3 even across the periodic seam; the
+// seam costs two extra conv1 planes and two extra conv2 planes per layer.  The
+// field x is resident for the whole sample on a padded lattice; ring planes
+// carry an in-plane periodic halo, so every gather is a base address plus a
+// per-tap constant.  conv3 only changes active sites, and conv1 only reads
+// frozen sites, so the update of plane z can overlap the next plane's conv1.
+#include <type_traits>
+
+#include "fused_kernels.hpp"
+#include "lfs_internal.hpp"
+
+namespace lfs {
+namespace fused {
+namespace {
+
+constexpr double kHalfLog2PiR = 0.91893853320467274178;
+
+template <int L, int C, bool BF16>
+struct RingCfg {
+  using G = Geo<3, L>;
+  using LX = Lay<3, L, true>;   // the field
+  using LP2 = Lay<2, L, true>;  // one plane of a ring
+  static constexpr int V = G::V, T = 27, PS = LP2::VS, LP = L + 2;
+  static constexpr LayerFrags LF = layer_frags(T, C, BF16);
+  static constexpr size_t XS_BYTES = ((size_t)LX::VS * 4 + 15) / 16 * 16;
+  static constexpr size_t RING = 3 * (size_t)PS * C * sizeof(HElem<BF16>);
+  static constexpr size_t lds_bytes = XS_BYTES + 2 * RING;
+  static constexpr int NT = 256;
+};
+
+__device__ __forceinline__ int mod3(int v) { return ((v % 3) + 3) % 3; }
+
+// B operand of a C-input convolution on a ring: in-plane storage index pq of the
+// output site, the ring slots of planes v-1, v, v+1.
+template <int L, int C, bool BF16>
+__device__ __forceinline__ u32x4 gather_ring(const HElem<BF16>* ring, int pq, int sm, int s0, int sp,
+                                             int c, int j) {
+  using Cfg = RingCfg<L, C, BF16>;
+  constexpr int K = 27 * C;
+  const int k0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
+  if (k0 >= K) return u32x4{0u, 0u, 0u, 0u};
+  const int tap = k0 / C, ci0 = k0 % C;
+  const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+  const int slot = dz < 0 ? sm : (dz > 0 ? sp : s0);
+  const int idx = slot * Cfg::PS + pq + dy * Cfg::LP + dx;
+  return *reinterpret_cast<const u32x4*>(ring + idx * C + ci0);
+}
+
+template <int L, int C, bool BF16, int NT>
+__global__ void __launch_bounds__(NT) kf_forward_ring(
+    const u32x4* __restrict__ frags, const float* __restrict__ params, int P_layer, int off_b1,
+    int off_b2, int off_b3, int N, int parity0, int final_tanh, int B, const float* __restrict__ z,
+    float* __restrict__ phi, float* __restrict__ saved, double* __restrict__ logq,
+    double* __restrict__ logdet) {
+  using Cfg = RingCfg<L, C, BF16>;
+  using G = typename Cfg::G;
+  using LX = typename Cfg::LX;
+  using LP2 = typename Cfg::LP2;
+  using HT = HElem<BF16>;
+  using R = std::conditional_t<BF16, double, float>;
+  constexpr int V = Cfg::V, PLANE = L * L, PS = Cfg::PS;
+  constexpr LayerFrags LF = Cfg::LF;
+  constexpr int NW = NT / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ R red[16];
+  float* xs = reinterpret_cast<float*>(smem);
+  HT* r1 = reinterpret_cast<HT*>(smem + Cfg::XS_BYTES);
+  HT* r2 = r1 + 3 * PS * C;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane >> 4, m = lane & 15;
+  const size_t BV = (size_t)B * V;
+
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    R zz = 0;
+    {
+      const float* zb = z + (size_t)b * V;
+      for (int q = threadIdx.x; q < LX::VS; q += NT) xs[q] = zb[LX::site_of(q)];
+      for (int n = threadIdx.x; n < V; n += NT) {
+        const float v = zb[n];
+        if (saved) saved[(size_t)b * V + n] = v;
+        zz += (R)v * v;
+      }
+    }
+    R ld = 0;
+    for (int layer = 0; layer < N; ++layer) {
+      const int fpar = (layer + parity0) & 1, apar = fpar ^ 1;
+      const u32x4* fl = frags + (size_t)layer * LF.total * 64 + lane;
+      const float* pl = params + (size_t)layer * P_layer;
+      u32x4 A1[LF.nct][LF.k1], A2[LF.nct][LF.k2], A3[LF.k2];
+      f32x4 bias1[LF.nct], bias2[LF.nct];
+#pragma unroll
+      for (int ct = 0; ct < LF.nct; ++ct) {
+        bias1[ct] = load_bias4<C>(pl + off_b1, ct, j);
+        bias2[ct] = load_bias4<C>(pl + off_b2, ct, j);
+#pragma unroll
+        for (int c = 0; c < LF.k1; ++c) A1[ct][c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c) A2[ct][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
+      }
+#pragma unroll
+      for (int c = 0; c < LF.k2; ++c) A3[c] = fl[(LF.off3 + c) * 64];
+      const float bs = pl[off_b3], bt = pl[off_b3 + 1];
+
+      // h1 of virtual plane v into ring slot v mod 3
+      auto conv1_plane = [&](int v) {
+        const int zr = ((v % L) + L) % L;
+        HT* dst = r1 + mod3(v) * PS * C;
+        for (int tile = w; tile < PLANE / 16; tile += NW) {
+          const int q = tile * 16 + m, n = zr * PLANE + q;
+          const int p = LX::idx(n), pn = G::parity(n);
+          f32x4 acc[LF.nct];
+#pragma unroll
+          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c = 0; c < LF.k1; ++c) {
+            const u32x4 bop = gather_x<LX, BF16>(xs, n, p, pn, fpar, c, j);
+#pragma unroll
+            for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A1[ct][c], bop, acc[ct]);
+          }
+#pragma unroll
+          for (int ct = 0; ct < LF.nct; ++ct) store_hidden<LP2, C, BF16>(dst, q, ct, j, acc[ct], bias1[ct]);
+        }
+      };
+      // h2 of virtual plane v from h1 planes v-1, v, v+1
+      auto conv2_plane = [&](int v) {
+        HT* dst = r2 + mod3(v) * PS * C;
+        const int sm = mod3(v - 1), s0 = mod3(v), sp = mod3(v + 1);
+        for (int tile = w; tile < PLANE / 16; tile += NW) {
+          const int q = tile * 16 + m, pq = LP2::idx(q);
+          f32x4 acc[LF.nct];
+#pragma unroll
+          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c = 0; c < LF.k2; ++c) {
+            const u32x4 bop = gather_ring<L, C, BF16>(r1, pq, sm, s0, sp, c, j);
+#pragma unroll
+            for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A2[ct][c], bop, acc[ct]);
+          }
+#pragma unroll
+          for (int ct = 0; ct < LF.nct; ++ct) store_hidden<LP2, C, BF16>(dst, q, ct, j, acc[ct], bias2[ct]);
+        }
+      };
+      // conv3 of h2 planes z-1, z, z+1 at the active sites of plane z; affine update
+      auto conv3_plane = [&](int zr) {
+        const int sm = mod3(zr - 1), s0 = mod3(zr), sp = mod3(zr + 1);
+        const int ppar = apar ^ (zr & 1);  // in-plane parity of the active sites
+        for (int tile = w; tile < PLANE / 32; tile += NW) {
+          const int q = Geo<2, L>::half_site(tile * 16 + m, ppar), pq = LP2::idx(q);
+          f32x4 acc{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c = 0; c < LF.k2; ++c)
+            acc = mma<BF16>(A3[c], gather_ring<L, C, BF16>(r2, pq, sm, s0, sp, c, j), acc);
+          if (j == 0) {
+            const int n = zr * PLANE + q;
+            const float o0 = acc[0] + bs, t = acc[1] + bt;
+            const float s = final_tanh ? tanhf(o0) : o0;
+            const float xn = xs[LX::idx(n)] * expf(s) + t;
+            LX::copies(n, [&](int qq) { xs[qq] = xn; });
+            ld += (R)s;
+          }
+        }
+      };
+
+      __syncthreads();  // field of the previous layer complete
+      conv1_plane(-2);
+      conv1_plane(-1);
+      conv1_plane(0);
+      __syncthreads();
+      conv2_plane(-1);
+      __syncthreads();
+      conv1_plane(1);
+      __syncthreads();
+      conv2_plane(0);
+      __syncthreads();
+      for (int zr = 0; zr < L; ++zr) {
+        conv1_plane(zr + 2);
+        __syncthreads();
+        conv2_plane(zr + 1);
+        __syncthreads();
+        conv3_plane(zr);
+      }
+      __syncthreads();
+      if (saved) {
+        float* sv = saved + (size_t)(layer + 1) * BV + (size_t)b * V;
+        for (int n = threadIdx.x; n < V; n += NT) sv[n] = xs[LX::idx(n)];
+      }
+    }
+    {
+      float* pb = phi + (size_t)b * V;
+      for (int n = threadIdx.x; n < V; n += NT) pb[n] = xs[LX::idx(n)];
+    }
+    ld = block_sum(ld, red);
+    zz = block_sum(zz, red);
+    if (threadIdx.x == 0) {
+      const double logr = -0.5 * (double)zz - (double)V * kHalfLog2PiR;
+      logq[b] = logr - (double)ld;
+      if (logdet) logdet[b] = (double)ld;
+    }
+  }
+}
+
+template <int L, int C, bool BF16>
+int32_t launch_ring(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
+                    double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
+  using Cfg = RingCfg<L, C, BF16>;
+  constexpr LayerFrags LF = Cfg::LF;
+  static_assert(Cfg::lds_bytes <= 160 * 1024, "LDS budget");
+  u32x4* frags = reinterpret_cast<u32x4*>(ws);
+  FragTable tab{};
+  tab.count = 3;
+  tab.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, LF.nct, LF.k1, LF.off1};
+  tab.s[1] = FragSpec{0, (int)g.off_W2, C, C, C, LF.nct, LF.k2, LF.off2};
+  tab.s[2] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, LF.k2, LF.off3};
+  tab.total = LF.total;
+  const long nthreads = (long)LF.total * 64 * g.N;
+  hipLaunchKernelGGL((kf_prep<BF16>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st,
+                     params, g.N, g.T, (int)g.P_layer, tab, frags);
+  auto kern = kf_forward_ring<L, C, BF16, Cfg::NT>;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::lds_bytes) !=
+      hipSuccess)
+    return LFS_EDEVICE;
+  hipLaunchKernelGGL(kern, dim3(B), dim3(Cfg::NT), Cfg::lds_bytes, st, frags, params,
+                     (int)g.P_layer, (int)g.off_b1, (int)g.off_b2, (int)g.off_b3, g.N, g.parity0,
+                     g.final_tanh, B, z, phi, saved, logq, logdet);
+  return launch_status();
+}
+
+struct RingEntry {
+  int L, C;
+  bool bf16;
+  int32_t (*fn)(const FlowGeom&, const float*, int, const float*, float*, double*, double*, float*,
+                char*, hipStream_t);
+  size_t frag_bytes_per_layer;
+};
+
+template <int L, int C, bool BF16>
+constexpr RingEntry ring_entry() {
+  return RingEntry{L, C, BF16, &launch_ring<L, C, BF16>,
+                   (size_t)RingCfg<L, C, BF16>::LF.total * 64 * 16};
+}
+
+const RingEntry kRingTable[] = {ring_entry<16, 8, false>(), ring_entry<16, 8, true>(),
+                                ring_entry<16, 16, false>(), ring_entry<16, 16, true>(),
+                                ring_entry<16, 32, true>()};
+
+const RingEntry* find_ring(const FlowGeom& g) {
+  if (g.dim != 3) return nullptr;
+  for (const auto& e : kRingTable)
+    if (e.L == g.L && e.C == g.C && e.bf16 == g.bf16()) return &e;
+  return nullptr;
+}
+
+}  // namespace
+
+bool ring_supported(const FlowGeom& g) { return find_ring(g) != nullptr; }
+size_t ring_ws_bytes(const FlowGeom& g) {
+  const RingEntry* e = find_ring(g);
+  return e ? align_up(e->frag_bytes_per_layer * g.N) : 0;
+}
+int32_t ring_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
+                     double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
+  const RingEntry* e = find_ring(g);
+  if (!e) return LFS_EUNSUPPORTED;
+  return e->fn(g, params, B, z, phi, logq, logdet, saved, ws, st);
+}
+
+}  // namespace fused
+}  // namespace lfs

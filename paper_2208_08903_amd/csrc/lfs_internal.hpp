@@ -45,6 +45,12 @@ int32_t fused_backward(const FlowGeom& g, const float* params, int B, const floa
                        hipStream_t st);
 
 namespace fused {
+// Fused forward streaming planes through LDS rings (3D lattices too large to
+// keep resident), implemented next to its kernel.
+bool ring_supported(const FlowGeom& g);
+size_t ring_ws_bytes(const FlowGeom& g);
+int32_t ring_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
+                     double* logq, double* logdet, float* saved, char* ws, hipStream_t st);
 // Fused backward (one launch per layer), implemented next to its kernels.
 bool bwd_supported(const FlowGeom& g);
 size_t bwd_ws_bytes(const FlowGeom& g, int B);

@@ -271,12 +271,20 @@ FUSED_CASES = [
     (3, 8, 3, 16, 2),
     (3, 12, 2, 8, 2),
 ]
-FUSED_BF16_ONLY = [(2, 32, 2, 32, 2), (3, 12, 2, 16, 2)]
+FUSED_BF16_ONLY = [(2, 32, 2, 32, 2), (3, 12, 2, 16, 2), (3, 16, 2, 32, 2)]
+RING_CASES = [(3, 16, 2, 16, 2), (3, 16, 3, 8, 2)]   # plane-streaming kernel (3D L = 16)
 
 
 @pytest.mark.parametrize("case", FUSED_CASES)
 @pytest.mark.parametrize("precision", [lfs.LFS_PLAIN_FP32, lfs.LFS_BF16_CONV])
 def test_flow_forward_fused(case, precision):
+    desc, params, z, fs = _flow_case(*case, precision, lfs.ALGO_FUSED)
+    _check_forward(desc, params, z, fs, precision)
+
+
+@pytest.mark.parametrize("case", RING_CASES)
+@pytest.mark.parametrize("precision", [lfs.LFS_PLAIN_FP32, lfs.LFS_BF16_CONV])
+def test_flow_forward_ring(case, precision):
     desc, params, z, fs = _flow_case(*case, precision, lfs.ALGO_FUSED)
     _check_forward(desc, params, z, fs, precision)
 
