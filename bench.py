@@ -159,6 +159,69 @@ def hmc_rate(reps=5):
                 acceptance=float(acc.float().mean().item()))
 
 
+def other_workloads(params_2d):
+    """Side figures for the other workloads: the 2D L=8 example shape (latency of one batch of 64,
+    a 2000-proposal chain), the 3D L=8 training step, and 3D L=16 C=32 sampling at batch 4096."""
+    import numpy as np
+    import torch
+    import seeded_inputs as si
+    from paper_2208_08903_amd import flow as fl
+    from paper_2208_08903_amd import lfs
+    out = {}
+    # 2D L=8, 16 layers, C=8, m2=-4, lambda=8: one batch of 64, then a chain of 2000 proposals
+    p8 = si.flow_params(2, 16, 8)
+    f8 = fl.Flow(2, 8, 16, 8, lfs.LFS_BF16_CONV, params=p8)
+    s64 = fl.Sampler(f8, 64, -4.0, 8.0, key=11)
+    lu = torch.as_tensor(si.log_uniforms(6, (40, 1, 64)), device="cuda")
+    for k in range(3):
+        s64.step(lu[k])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(20):
+        s64.step(lu[3 + k])
+    torch.cuda.synchronize()
+    out["2d_L8_batch64_us"] = round(1e6 * (time.perf_counter() - t0) / 20, 2)
+    s2k = fl.Sampler(f8, 2000, -4.0, 8.0, key=12)
+    lu2 = torch.as_tensor(si.log_uniforms(7, (3, 1, 2000)), device="cuda")
+    s2k.step(lu2[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s2k.step(lu2[1])
+    torch.cuda.synchronize()
+    out["2d_L8_chain2000_ms"] = round(1e3 * (time.perf_counter() - t0), 4)
+    # 3D L=8, 12 layers, C=16, batch 512 training (BF16 and FP32)
+    p3 = si.flow_params(3, 12, 16)
+    for prec, name in ((lfs.LFS_BF16_CONV, "bf16"), (lfs.LFS_PLAIN_FP32, "fp32")):
+        f3 = fl.Flow(3, 8, 12, 16, prec, params=p3)
+        tr = fl.Trainer(f3, 512, -4.0, 5.0)
+        tt, ph = time_phases(tr, 5, 2)
+        out[f"3d_L8_train_{name}_steps_per_s"] = round(5 / tt, 3)
+    # 3D L=16, 16 layers, C=32, BF16: sampling at batch 4096
+    p16 = si.flow_params(3, 16, 32)
+    f16 = fl.Flow(3, 16, 16, 32, lfs.LFS_BF16_CONV, params=p16)
+    out["3d_L16_C32_sampling_bf16"] = sampling_rate(f16, 4096, -4.0, 5.0, batches=2)
+    out["3d_L16_C32_forward_ms_b4096"] = round(flow_forward_ms(f16, 4096, reps=2), 3)
+    return out
+
+
+def serving(seconds=5.0):
+    """Poisson(200/s) sampling requests for `seconds` through the continuous-batching server."""
+    import seeded_inputs as si
+    from paper_2208_08903_amd import lfs
+    from paper_2208_08903_amd.serve import DEFAULT_ARCH, Server, run_workload
+    params = {d: si.flow_params(d, n, c, seed=2021 + d) for d, (n, c) in DEFAULT_ARCH.items()}
+    reqs = si.serving_requests(seed=2208, rate=200.0, duration=seconds)
+    srv = Server(params, precision=lfs.LFS_BF16_CONV, hbm_budget=512 << 20)
+    warm = si.serving_requests(seed=1, rate=200.0, duration=0.3)
+    run_workload(srv, warm)
+    srv.peak_used = 0
+    srv.rounds = 0
+    st = run_workload(srv, reqs)
+    st["offered_rate_req_per_s"] = 200.0
+    st["duration_s"] = seconds
+    return st
+
+
 def cpu_baseline(target_s=15.0):
     """The FP64 oracle's training step, one thread, on a bounded sample of the batch,
     scaled to steps/s of the full batch (cost is linear in the batch: samples are
@@ -277,6 +340,8 @@ def main():
                                                      lfs.LFS_PLAIN_FP32, params=params),
                                              B, w["m2"], w["lam"], batches=4)
         out["hmc_fp64_3d_L8"] = hmc_rate()
+        out["other_workloads"] = other_workloads(params)
+        out["serving"] = serving()
     if args.copy_calibration_mb > 0:
         nb = args.copy_calibration_mb * 2 ** 20
         src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
