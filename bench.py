@@ -204,6 +204,33 @@ def other_workloads(params_2d):
     return out
 
 
+def trained_example(steps=20000):
+    """The example parameter file's schedule (2D L=8, m2=-4, lambda=8, 16 layers, hidden 8,
+    batch 64, Adam lr 1e-3, 200 x 100 iterations), trained once with the BF16 path and once
+    with the plain FP32 path; MH acceptance and accepted configs/s of each trained flow,
+    sampled in both precisions with the same weights."""
+    import torch
+    import seeded_inputs as si
+    from paper_2208_08903_amd import flow as fl
+    from paper_2208_08903_amd import lfs
+    out = {"steps": steps, "batch": 64}
+    for prec, name in ((lfs.LFS_BF16_CONV, "bf16"), (lfs.LFS_PLAIN_FP32, "fp32")):
+        f = fl.Flow(2, 8, 16, 8, prec, params=si.flow_params(2, 16, 8))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr, hist = fl.train(f, steps, 64, -4.0, 8.0, lr=1e-3, record_every=steps // 4)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t0
+        row = {"train_s": round(tt, 3), "train_steps_per_s": round(steps / tt, 1),
+               "loss": [(i, round(l, 4)) for i, l in hist]}
+        for sp, sname in ((lfs.LFS_BF16_CONV, "bf16"), (lfs.LFS_PLAIN_FP32, "fp32")):
+            acc, sec = fl.acceptance_rate(f.with_precision(sp), -4.0, 8.0, batches=16, B=4096)
+            row[f"acceptance_sampled_{sname}"] = round(acc, 5)
+            row[f"accepted_per_s_sampled_{sname}"] = round(acc * 16 * 4096 / sec, 1)
+        out[f"trained_{name}"] = row
+    return out
+
+
 def serving(seconds=5.0):
     """Poisson(200/s) sampling requests for `seconds` through the continuous-batching server."""
     import seeded_inputs as si
@@ -341,6 +368,7 @@ def main():
                                              B, w["m2"], w["lam"], batches=4)
         out["hmc_fp64_3d_L8"] = hmc_rate()
         out["other_workloads"] = other_workloads(params)
+        out["trained_2d_L8_example"] = trained_example()
         out["serving"] = serving()
     if args.copy_calibration_mb > 0:
         nb = args.copy_calibration_mb * 2 ** 20

@@ -147,3 +147,32 @@ class Sampler:
         acc = sum(s["n_acc"] for s in st)
         dec = sum(max(s["n_seen"] - 1, 0) for s in st)
         return acc / max(dec, 1), acc
+
+
+def train(flow: Flow, steps: int, B: int, m2: float, lam: float, lr=1e-3, key=12345,
+          record_every: int = 0):
+    """Reverse-KL training for `steps` iterations (the example parameter file runs
+    200 epochs x 100 iterations at batch 64, lr 1e-3).  Returns the trainer and the
+    recorded (step, loss) pairs."""
+    tr = Trainer(flow, B, m2, lam, lr=lr, key=key)
+    hist = []
+    for i in range(steps):
+        tr.step()
+        if record_every and (i % record_every == 0 or i == steps - 1):
+            hist.append((i, float(tr.loss.item())))
+    return tr, hist
+
+
+def acceptance_rate(flow: Flow, m2: float, lam: float, batches: int, B: int, key=4242, u_seed=77):
+    """MH acceptance of `batches` x B proposals with one chain; returns (rate, seconds)."""
+    import time
+    rng = np.random.default_rng(u_seed)
+    u = rng.random((batches, 1, B))
+    lu = torch.as_tensor(np.log(np.where(u == 0, np.nextafter(0, 1), u)), device=flow.device)
+    smp = Sampler(flow, B, m2, lam, key=key)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(batches):
+        smp.step(lu[k])
+    torch.cuda.synchronize()
+    return smp.acceptance()[0], time.perf_counter() - t0

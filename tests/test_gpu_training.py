@@ -1,0 +1,30 @@
+"""Training through the library lowers the reverse-KL loss, and the BF16 precision form
+samples the trained flow at the plain FP32 acceptance rate (within 1% absolute)."""
+import numpy as np
+import pytest
+import torch
+
+import seeded_inputs as si
+from paper_2208_08903_amd import flow as fl
+from paper_2208_08903_amd import lfs
+
+pytestmark = pytest.mark.gpu
+
+
+def test_training_and_bf16_acceptance():
+    f = fl.Flow(2, 8, 16, 8, lfs.LFS_BF16_CONV, params=si.flow_params(2, 16, 8))
+    tr, hist = fl.train(f, 3000, 64, -4.0, 8.0, lr=1e-3, record_every=1000)
+    assert hist[-1][1] < hist[0][1] - 100          # from ~1e3 to below zero
+    a16, _ = fl.acceptance_rate(f, -4.0, 8.0, batches=8, B=2048)
+    a32, _ = fl.acceptance_rate(f.with_precision(lfs.LFS_PLAIN_FP32), -4.0, 8.0, batches=8, B=2048)
+    assert a32 > 0.1                               # the flow has actually learned
+    assert abs(a16 - a32) < 0.01
+
+
+def test_training_is_bitwise_reproducible():
+    runs = []
+    for _ in range(2):
+        f = fl.Flow(2, 8, 4, 8, lfs.LFS_BF16_CONV, params=si.flow_params(2, 4, 8))
+        fl.train(f, 50, 64, -4.0, 8.0)
+        runs.append(f.params.cpu().numpy())
+    np.testing.assert_array_equal(runs[0], runs[1])
