@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(NT) kf_forward(
   float* xs = reinterpret_cast<float*>(smem);
   HT* h1 = reinterpret_cast<HT*>(smem + ((VS * 4 + 15) / 16) * 16);
   HT* h2 = h1 + VS * C;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane >> 4, m = lane & 15;
+  const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
   const size_t BV = (size_t)B * V;
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
@@ -59,6 +59,9 @@ __global__ void __launch_bounds__(NT) kf_forward(
       const u32x4* fl = frags + (size_t)layer * LF.total * 64 + lane;
       const float* pl = params + (size_t)layer * P_layer;
       __syncthreads();
+      // masked field for conv1, kept in the (dead) h2 buffer
+      build_h0<LY, BF16, NT>(h2, xs, fpar);
+      __syncthreads();
       // conv1 over all sites
       {
         u32x4 A[LF.nct][LF.k1];
@@ -70,13 +73,13 @@ __global__ void __launch_bounds__(NT) kf_forward(
           for (int c = 0; c < LF.k1; ++c) A[ct][c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
         }
         for (int tile = w; tile < V / 16; tile += NW) {
-          const int n = tile * 16 + m, p = LY::idx(n), pn = G::parity(n);
+          const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
           f32x4 acc[LF.nct];
 #pragma unroll
           for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int c = 0; c < LF.k1; ++c) {
-            const u32x4 bop = gather_x<LY, BF16>(xs, n, p, pn, fpar, c, j);
+            const u32x4 bop = gather_h0<LY, BF16>(h2, n, p, c, j);
 #pragma unroll
             for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
           }
@@ -96,7 +99,7 @@ __global__ void __launch_bounds__(NT) kf_forward(
           for (int c = 0; c < LF.k2; ++c) A[ct][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
         }
         for (int tile = w; tile < V / 16; tile += NW) {
-          const int n = tile * 16 + m, p = LY::idx(n);
+          const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
           f32x4 acc[LF.nct];
 #pragma unroll
           for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -126,8 +129,8 @@ __global__ void __launch_bounds__(NT) kf_forward(
             acc = mma<BF16>(A[c], gather_h<LY, C, BF16>(h2, n, p, c, j), acc);
           if (j == 0) {
             const float o0 = acc[0] + bs, t = acc[1] + bt;
-            const float s = final_tanh ? tanhf(o0) : o0;
-            const float xn = xs[p] * expf(s) + t;
+            const float s = final_tanh ? fast_tanh(o0) : o0;
+            const float xn = xs[p] * fast_exp(s) + t;
             LY::copies(n, [&](int q) { xs[q] = xn; });
             ld += (R)s;
           }

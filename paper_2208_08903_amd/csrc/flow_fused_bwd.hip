@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
   constexpr int VS = LY::VS;
   float* xs = reinterpret_cast<float*>(smem + M::OFF_XS);
   float* gys = reinterpret_cast<float*>(smem + M::OFF_GY);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane >> 4, m = lane & 15;
+  const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
   const u32x4* fr = frags + lane;
   const int apar = fpar ^ 1;
 
@@ -188,6 +188,9 @@ __global__ void __launch_bounds__(NT) kf_backward(
       for (int n = threadIdx.x; n < V; n += NT)
         h0c[n] = (uint16_t)bf16_bits(G::parity(n) == fpar ? xs[LY::idx(n)] : 0.f);
     }
+    // masked field for conv1, site-major in the (not yet written) h2 slot
+    build_h0<LY, BF16, NT>(h2s, xs, fpar);
+    __syncthreads();
     // ---- recompute conv1 -> h1 ----
     {
       u32x4 A[LF.nct][LF.k1];
@@ -199,13 +202,13 @@ __global__ void __launch_bounds__(NT) kf_backward(
         for (int c = 0; c < LF.k1; ++c) A[ct][c] = fr[(LF.off1 + ct * LF.k1 + c) * 64];
       }
       for (int tile = w; tile < V / 16; tile += NW) {
-        const int n = tile * 16 + m, p = LY::idx(n), pn = G::parity(n);
+        const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
         f32x4 acc[LF.nct];
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < LF.k1; ++c) {
-          const u32x4 bop = gather_x<LY, BF16>(xs, n, p, pn, fpar, c, j);
+          const u32x4 bop = gather_h0<LY, BF16>(h2s, n, p, c, j);
 #pragma unroll
           for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
         }
@@ -237,7 +240,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
         for (int c = 0; c < LF.k2; ++c) A[ct][c] = fr[(LF.off2 + ct * LF.k2 + c) * 64];
       }
       for (int tile = w; tile < V / 16; tile += NW) {
-        const int n = tile * 16 + m, p = LY::idx(n);
+        const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
         f32x4 acc[LF.nct];
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -295,8 +298,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
           acc = mma<BF16>(A[c], gather_h<LY, C, BF16>(h2s, n, p, c, j), acc);
         if (j == 0) {
           const float o0 = acc[0] + bs;
-          const float s = final_tanh ? tanhf(o0) : o0;
-          const float es = expf(s);
+          const float s = final_tanh ? fast_tanh(o0) : o0;
+          const float es = fast_exp(s);
           const float g = gys[n];
           const float gs = g * xs[p] * es + g_ld;
           const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
@@ -361,7 +364,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
         for (int c = 0; c < Cfg::KT3; ++c) A[ct][c] = fr[(Cfg::OFF3T + ct * Cfg::KT3 + c) * 64];
       for (int tile = w; tile < V / 16; tile += NW) {
-        const int n = tile * 16 + m, p = LY::idx(n);
+        const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
         f32x4 acc[LF.nct];
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -458,7 +461,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
         for (int c = 0; c < LF.k2; ++c) A[ct][c] = fr[(Cfg::OFF2T + ct * LF.k2 + c) * 64];
       for (int tile = w; tile < V / 16; tile += NW) {
-        const int n = tile * 16 + m, p = LY::idx(n);
+        const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
         f32x4 acc[LF.nct];
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};

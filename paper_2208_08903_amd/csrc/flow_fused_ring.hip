@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
   float* xs = reinterpret_cast<float*>(smem);
   HT* r1 = reinterpret_cast<HT*>(smem + Cfg::XS_BYTES);
   HT* r2 = r1 + 3 * PS * C;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, j = lane >> 4, m = lane & 15;
+  const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
   const size_t BV = (size_t)B * V;
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
         HT* dst = r2 + mod3(v) * PS * C;
         const int sm = mod3(v - 1), s0 = mod3(v), sp = mod3(v + 1);
         for (int tile = w; tile < PLANE / 16; tile += NW) {
-          const int q = tile * 16 + m, pq = LP2::idx(q);
+          const int q = tile * 16 + m, pq = tile_p<LP2>(tile, m);
           f32x4 acc[LF.nct];
 #pragma unroll
           for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -164,8 +164,8 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
           if (j == 0) {
             const int n = zr * PLANE + q;
             const float o0 = acc[0] + bs, t = acc[1] + bt;
-            const float s = final_tanh ? tanhf(o0) : o0;
-            const float xn = xs[LX::idx(n)] * expf(s) + t;
+            const float s = final_tanh ? fast_tanh(o0) : o0;
+            const float xn = xs[LX::idx(n)] * fast_exp(s) + t;
             LX::copies(n, [&](int qq) { xs[qq] = xn; });
             ld += (R)s;
           }

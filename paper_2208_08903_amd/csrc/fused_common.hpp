@@ -49,6 +49,18 @@ __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w 
 
 __device__ __forceinline__ bf16x8 as_bf16x8(const u32x4& v) { return __builtin_bit_cast(bf16x8, v); }
 
+// e^x from the hardware base-2 exponential (v_exp_f32): e^x = 2^(x log2 e).
+__device__ __forceinline__ float fast_exp(float x) {
+  return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
+}
+// tanh(x) = 1 - 2 / (e^{2x} + 1) with v_exp_f32 and v_rcp_f32 (saturates to +-1).
+__device__ __forceinline__ float fast_tanh(float x) {
+  return 1.f - 2.f * __builtin_amdgcn_rcpf(fast_exp(2.f * x) + 1.f);
+}
+
+// Wave index as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // Compile-time lattice: V sites, T taps, row-major, axis 0 slowest.
 template <int DIM, int L>
 struct Geo {
@@ -98,6 +110,7 @@ template <int DIM, int L, bool PAD>
 struct Lay {
   using G = Geo<DIM, L>;
   static constexpr bool padded = PAD;
+  static constexpr int Ls = L;
   static constexpr int LP = PAD ? L + 2 : L;
   static constexpr int VS = DIM == 2 ? LP * LP : LP * LP * LP;  // storage sites
 
@@ -163,6 +176,14 @@ struct Lay {
     }
   }
 };
+
+// Storage index of lane m's site in tile `tile` (16 consecutive sites): when a row
+// holds whole tiles the row part is wave-uniform.
+template <class LY>
+__device__ __forceinline__ int tile_p(int tile, int m) {
+  if constexpr (LY::padded && LY::Ls % 16 == 0) return LY::idx(tile * 16) + m;
+  return LY::idx(tile * 16 + m);
+}
 
 // Parity of |delta_t|_1: a neighbour at tap t has parity p(n) ^ todd(t).
 template <int DIM>

@@ -100,6 +100,40 @@ __device__ __forceinline__ u32x4 gather_x(const float* xs, int n, int p, int pn,
   return r;
 }
 
+// B operand of conv1 from the masked field h0 (zero at active sites), stored with
+// layout LY in BF16 (BF16 mode) or FP32: the taps of the lane's K slice.
+template <class LY, bool BF16>
+__device__ __forceinline__ u32x4 gather_h0(const HElem<BF16>* h0, int n, int p, int c, int j) {
+  constexpr int T = LY::G::T;
+  u32x4 r;
+  if constexpr (BF16) {
+    const int t0 = 32 * c + 8 * j;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ta = t0 + 2 * q, tb = ta + 1;
+      const uint32_t lo = ta < T ? (uint32_t)h0[LY::nbr(n, p, ta, 1)] : 0u;
+      const uint32_t hi = tb < T ? (uint32_t)h0[LY::nbr(n, p, tb, 1)] : 0u;
+      r[q] = lo | (hi << 16);
+    }
+  } else {
+    const int t0 = 16 * c + 4 * j;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      r[q] = t0 + q < T ? __float_as_uint(h0[LY::nbr(n, p, t0 + q, 1)]) : 0u;
+  }
+  return r;
+}
+
+// h0 = the field at frozen sites, 0 at active sites, in every stored position.
+template <class LY, bool BF16, int NT>
+__device__ __forceinline__ void build_h0(HElem<BF16>* h0, const float* xs, int fpar) {
+  for (int q = threadIdx.x; q < LY::VS; q += NT) {
+    const float v = LY::G::parity(LY::site_of(q)) == fpar ? xs[q] : 0.f;
+    if constexpr (BF16) h0[q] = (uint16_t)bf16_bits(v);
+    else h0[q] = v;
+  }
+}
+
 // acc += A (fragment) x B (gathered) for one chunk / block.
 template <bool BF16>
 __device__ __forceinline__ f32x4 mma(const u32x4& a, const u32x4& b, f32x4 acc) {

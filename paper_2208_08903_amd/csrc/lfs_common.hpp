@@ -39,7 +39,8 @@ __device__ __forceinline__ float opnd(float x) {
   return x;
 }
 
-__device__ __forceinline__ float leaky(float a) { return a >= 0.f ? a : kLeakySlope * a; }
+// LeakyReLU with slope in (0, 1): max(a, slope * a).
+__device__ __forceinline__ float leaky(float a) { return fmaxf(a, kLeakySlope * a); }
 // LeakyReLU'(a) from its output h = leaky(a): sign(h) == sign(a), h == 0 iff a == 0.
 __device__ __forceinline__ float leaky_grad_from_out(float h) { return h >= 0.f ? 1.f : kLeakySlope; }
 
