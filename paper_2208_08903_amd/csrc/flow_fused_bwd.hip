@@ -22,6 +22,7 @@
 // as one partial per workgroup; a fixed-order reduction over workgroups gives
 // the gradient, so results are bitwise reproducible.
 #include <algorithm>
+#include <type_traits>
 
 #include "fused_kernels.hpp"
 #include "lfs_internal.hpp"
@@ -79,14 +80,12 @@ struct BwdCfg {
   static constexpr int NW = NT / 64;
   static constexpr int MT = (C + 15) / 16;
   static constexpr int NKC = BF16 ? V / 32 : V / 16;  // K chunks (sites) per sample
-  static constexpr int I3 = MT * ((2 * T + 15) / 16);
+  // Weight-gradient output tiles; every wave accumulates all of them over its
+  // contiguous range of K chunks, and the waves are summed in a fixed order.
+  static constexpr int NTL3 = (2 * T + 15) / 16, NTL1 = (T + 15) / 16;
+  static constexpr int I3 = MT * NTL3;
   static constexpr int I2 = MT * T * MT;
-  static constexpr int I1 = MT * ((T + 15) / 16);
-  static constexpr int ks(int I) { return I >= NW ? 1 : cmin(NW / I, NKC); }
-  static constexpr int KS3 = ks(I3), KS2 = ks(I2), KS1 = ks(I1);
-  static constexpr int S3 = (I3 * KS3 + NW - 1) / NW;
-  static constexpr int S2 = (I2 * KS2 + NW - 1) / NW;
-  static constexpr int S1 = (I1 * KS1 + NW - 1) / NW;
+  static constexpr int I1 = MT * NTL1;
 };
 
 // ---- weight-gradient operands ---------------------------------------------
@@ -130,6 +129,47 @@ __device__ __forceinline__ float load1_shift(const float* h, int s, int ch, int 
   return h[LY::nbr(s, LY::idx(s), tap, sign) * CH + ch];
 }
 
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+template <int DIM, int TAP, int MU>
+constexpr int tap_dc() {
+  return DIM == 2 ? (MU == 0 ? TAP / 3 : TAP % 3) - 1
+                  : (MU == 0 ? TAP / 9 : (MU == 1 ? (TAP / 3) % 3 : TAP % 3)) - 1;
+}
+
+// Row (all axes but the last) of site s shifted by SIGN * delta_TAP.
+template <int DIM, int L, int TAP, int SIGN>
+__device__ __forceinline__ int shifted_row_c(int s) {
+  using G = Geo<DIM, L>;
+  const int row = s / L;
+  if constexpr (DIM == 2) return G::wrapc(row + SIGN * tap_dc<DIM, TAP, 0>());
+  const int z = row / L, y = row % L;
+  return G::wrapc(z + SIGN * tap_dc<DIM, TAP, 0>()) * L + G::wrapc(y + SIGN * tap_dc<DIM, TAP, 1>());
+}
+
+// BF16: 8 sites x0 + E .. x0 + E + 7 (periodic) of row rp, x0 % 8 == 0, as 4 BF16 pairs.
+template <int L, int E>
+__device__ __forceinline__ u32x4 load8_e(const uint16_t* rp, int x0) {
+  const u32x4 v = *reinterpret_cast<const u32x4*>(rp + x0);
+  if constexpr (E == 0) {
+    return v;
+  } else if constexpr (E > 0) {
+    const uint32_t nxt = rp[(x0 + 8) & (L - 1)];
+    return u32x4{__builtin_amdgcn_alignbit(v[1], v[0], 16), __builtin_amdgcn_alignbit(v[2], v[1], 16),
+                 __builtin_amdgcn_alignbit(v[3], v[2], 16), __builtin_amdgcn_alignbit(nxt, v[3], 16)};
+  } else {
+    const uint32_t prv = rp[(x0 + L - 1) & (L - 1)];
+    return u32x4{__builtin_amdgcn_alignbit(v[0], prv << 16, 16), __builtin_amdgcn_alignbit(v[1], v[0], 16),
+                 __builtin_amdgcn_alignbit(v[2], v[1], 16), __builtin_amdgcn_alignbit(v[3], v[2], 16)};
+  }
+}
+
 // ---- the kernel -------------------------------------------------------------
 
 template <int DIM, int L, int C, bool BF16, int NT>
@@ -161,13 +201,15 @@ __global__ void __launch_bounds__(NT) kf_backward(
   uint16_t* h1c = reinterpret_cast<uint16_t*>(smem + M::OFF_S1);
   uint16_t* h2c = reinterpret_cast<uint16_t*>(smem + M::OFF_S3);
 
-  f32x4 acc3[Cfg::S3], acc2[Cfg::S2], acc1[Cfg::S1];
+  constexpr int NTL3 = Cfg::NTL3, NTL1 = Cfg::NTL1;
+  f32x4 acc3[Cfg::I3], acc2[Cfg::I2], acc1[Cfg::I1];
 #pragma unroll
-  for (int i = 0; i < Cfg::S3; ++i) acc3[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < Cfg::I3; ++i) acc3[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int i = 0; i < Cfg::S2; ++i) acc2[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < Cfg::I2; ++i) acc2[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int i = 0; i < Cfg::S1; ++i) acc1[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < Cfg::I1; ++i) acc1[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int kc0 = w * NKC / NW, kc1 = (w + 1) * NKC / NW;  // this wave's K chunks
   float db3s = 0.f, db3t = 0.f;
   f32x4 db2[LF.nct], db1[LF.nct];
 #pragma unroll
@@ -322,30 +364,30 @@ __global__ void __launch_bounds__(NT) kf_backward(
     }
     __syncthreads();
     // ---- dW3[co][ci][tap] += sum_m h2[m][ci] g_o[m - delta_tap][co] ----
-    {
-      constexpr int NTL = (2 * T + 15) / 16;
+    // tiles (mt, nt): rows ci = mt*16 + i, columns (tap, co) = nt*16 + m
+    for (int kc = kc0; kc < kc1; ++kc) {
 #pragma unroll
-      for (int si = 0; si < Cfg::S3; ++si) {
-        const int u = w + NW * si;
-        if (u < Cfg::I3 * Cfg::KS3) {
-          const int q = u / Cfg::KS3, p = u % Cfg::KS3;
-          const int nt = q % NTL, mt = q / NTL;
-          const int ci = mt * 16 + m, col = nt * 16 + m, tap = col >> 1, co = col & 1;
-          const bool va = ci < C, vb = tap < T;
-          for (int kc = p * NKC / Cfg::KS3; kc < (p + 1) * NKC / Cfg::KS3; ++kc) {
-            if constexpr (BF16) {
-              const int s0 = kc * 32 + 8 * j;
-              const u32x4 a = va ? *reinterpret_cast<const u32x4*>(h2c + ci * CSTR + s0) : u32x4{0u, 0u, 0u, 0u};
-              const u32x4 bb = vb ? load8_shift<DIM, L>(goc + co * CSTR, s0, tap, -1) : u32x4{0u, 0u, 0u, 0u};
-              acc3[si] = mfma(as_bf16x8(a), as_bf16x8(bb), acc3[si]);
-            } else {
+      for (int mt = 0; mt < MT; ++mt) {
+        const int ci = mt * 16 + m;
+        if constexpr (BF16) {
+          const int s0 = kc * 32 + 8 * j;
+          const u32x4 a = ci < C ? *reinterpret_cast<const u32x4*>(h2c + ci * CSTR + s0) : u32x4{0u, 0u, 0u, 0u};
 #pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int s = kc * 16 + 4 * j + r;
-                const float a = va ? h2s[LY::idx(s) * C + ci] : 0.f;
-                const float bb = vb ? load1_shift<LY, 2>(gos_f, s, co, tap, -1) : 0.f;
-                acc3[si] = mfma(a, bb, acc3[si]);
-              }
+          for (int nt = 0; nt < NTL3; ++nt) {
+            const int col = nt * 16 + m, tap = col >> 1, co = col & 1;
+            const u32x4 bb = tap < T ? load8_shift<DIM, L>(goc + co * CSTR, s0, tap, -1) : u32x4{0u, 0u, 0u, 0u};
+            acc3[mt * NTL3 + nt] = mfma(as_bf16x8(a), as_bf16x8(bb), acc3[mt * NTL3 + nt]);
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int sx = kc * 16 + 4 * j + r;
+            const float a = ci < C ? h2s[LY::idx(sx) * C + ci] : 0.f;
+#pragma unroll
+            for (int nt = 0; nt < NTL3; ++nt) {
+              const int col = nt * 16 + m, tap = col >> 1, co = col & 1;
+              const float bb = tap < T ? load1_shift<LY, 2>(gos_f, sx, co, tap, -1) : 0.f;
+              acc3[mt * NTL3 + nt] = mfma(a, bb, acc3[mt * NTL3 + nt]);
             }
           }
         }
@@ -420,30 +462,41 @@ __global__ void __launch_bounds__(NT) kf_backward(
     }
     __syncthreads();
     // ---- dW2[co][ci][tap] += sum_m h1[m][ci] g_a2[m - delta_tap][co] ----
-    {
+    // tiles (mt, tap, nt): rows ci = mt*16 + i, columns co = nt*16 + m; the taps are
+    // unrolled so each shift is known at compile time.
+    for (int kc = kc0; kc < kc1; ++kc) {
 #pragma unroll
-      for (int si = 0; si < Cfg::S2; ++si) {
-        const int u = w + NW * si;
-        if (u < Cfg::I2 * Cfg::KS2) {
-          const int q = u / Cfg::KS2, p = u % Cfg::KS2;
-          const int nt = q % MT, tap = (q / MT) % T, mt = q / (MT * T);
-          const int ci = mt * 16 + m, co = nt * 16 + m;
-          const bool va = ci < C, vb = co < C;
-          for (int kc = p * NKC / Cfg::KS2; kc < (p + 1) * NKC / Cfg::KS2; ++kc) {
-            if constexpr (BF16) {
-              const int s0 = kc * 32 + 8 * j;
-              const u32x4 a = va ? *reinterpret_cast<const u32x4*>(h1c + ci * CSTR + s0) : u32x4{0u, 0u, 0u, 0u};
-              const u32x4 bb = vb ? load8_shift<DIM, L>(ga2c + co * CSTR, s0, tap, -1) : u32x4{0u, 0u, 0u, 0u};
-              acc2[si] = mfma(as_bf16x8(a), as_bf16x8(bb), acc2[si]);
-            } else {
+      for (int mt = 0; mt < MT; ++mt) {
+        const int ci = mt * 16 + m;
+        if constexpr (BF16) {
+          const int s0 = kc * 32 + 8 * j, x0 = s0 % L;
+          const u32x4 a = ci < C ? *reinterpret_cast<const u32x4*>(h1c + ci * CSTR + s0) : u32x4{0u, 0u, 0u, 0u};
+          static_for<0, T>([&](auto tc) {
+            constexpr int TAP = decltype(tc)::value;
+            constexpr int E = -tap_dc<DIM, TAP, DIM - 1>();
+            const int rowS = shifted_row_c<DIM, L, TAP, -1>(s0);
 #pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int s = kc * 16 + 4 * j + r;
-                const float a = va ? h1s[LY::idx(s) * C + ci] : 0.f;
-                const float bb = vb ? load1_shift<LY, C>(ga2s, s, co, tap, -1) : 0.f;
-                acc2[si] = mfma(a, bb, acc2[si]);
-              }
+            for (int nt = 0; nt < MT; ++nt) {
+              const int co = nt * 16 + m;
+              const u32x4 bb = co < C ? load8_e<L, E>(ga2c + co * CSTR + rowS * L, x0) : u32x4{0u, 0u, 0u, 0u};
+              acc2[(mt * T + TAP) * MT + nt] = mfma(as_bf16x8(a), as_bf16x8(bb), acc2[(mt * T + TAP) * MT + nt]);
             }
+          });
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int sx = kc * 16 + 4 * j + r, px = LY::idx(sx);
+            const float a = ci < C ? h1s[px * C + ci] : 0.f;
+            static_for<0, T>([&](auto tc) {
+              constexpr int TAP = decltype(tc)::value;
+              const int nb = LY::nbr(sx, px, TAP, -1);
+#pragma unroll
+              for (int nt = 0; nt < MT; ++nt) {
+                const int co = nt * 16 + m;
+                const float bb = co < C ? ga2s[nb * C + co] : 0.f;
+                acc2[(mt * T + TAP) * MT + nt] = mfma(a, bb, acc2[(mt * T + TAP) * MT + nt]);
+              }
+            });
           }
         }
       }
@@ -502,34 +555,36 @@ __global__ void __launch_bounds__(NT) kf_backward(
     }
     __syncthreads();
     // ---- dW1[c][tap] += sum_n g_a1[n][c] h0[n + delta_tap] (h0 = mask_F x) ----
+    // tiles (mt, nt): rows c = mt*16 + i, columns tap = nt*16 + m
     {
-      constexpr int NTL = (T + 15) / 16;
       const uint16_t* h0c = reinterpret_cast<const uint16_t*>(smem + M::OFF_H0C);
+      for (int kc = kc0; kc < kc1; ++kc) {
 #pragma unroll
-      for (int si = 0; si < Cfg::S1; ++si) {
-        const int u = w + NW * si;
-        if (u < Cfg::I1 * Cfg::KS1) {
-          const int q = u / Cfg::KS1, p = u % Cfg::KS1;
-          const int nt = q % NTL, mt = q / NTL;
-          const int c = mt * 16 + m, tap = nt * 16 + m;
-          const bool va = c < C, vb = tap < T;
-          for (int kc = p * NKC / Cfg::KS1; kc < (p + 1) * NKC / Cfg::KS1; ++kc) {
-            if constexpr (BF16) {
-              const int s0 = kc * 32 + 8 * j;
-              const u32x4 a = va ? *reinterpret_cast<const u32x4*>(ga1c + c * CSTR + s0) : u32x4{0u, 0u, 0u, 0u};
-              const u32x4 bb = vb ? load8_shift<DIM, L>(h0c, s0, tap, 1) : u32x4{0u, 0u, 0u, 0u};
-              acc1[si] = mfma(as_bf16x8(a), as_bf16x8(bb), acc1[si]);
-            } else {
+        for (int mt = 0; mt < MT; ++mt) {
+          const int c = mt * 16 + m;
+          if constexpr (BF16) {
+            const int s0 = kc * 32 + 8 * j;
+            const u32x4 a = c < C ? *reinterpret_cast<const u32x4*>(ga1c + c * CSTR + s0) : u32x4{0u, 0u, 0u, 0u};
 #pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int s = kc * 16 + 4 * j + r;
-                const float a = va ? ga1s[LY::idx(s) * C + c] : 0.f;
+            for (int nt = 0; nt < NTL1; ++nt) {
+              const int tap = nt * 16 + m;
+              const u32x4 bb = tap < T ? load8_shift<DIM, L>(h0c, s0, tap, 1) : u32x4{0u, 0u, 0u, 0u};
+              acc1[mt * NTL1 + nt] = mfma(as_bf16x8(a), as_bf16x8(bb), acc1[mt * NTL1 + nt]);
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int sx = kc * 16 + 4 * j + r, px = LY::idx(sx);
+              const float a = c < C ? ga1s[px * C + c] : 0.f;
+#pragma unroll
+              for (int nt = 0; nt < NTL1; ++nt) {
+                const int tap = nt * 16 + m;
                 float bb = 0.f;
-                if (vb) {
-                  const float xv = xs[LY::nbr(s, LY::idx(s), tap, 1)];
-                  bb = (G::parity(s) ^ todd<DIM>(tap)) == fpar ? xv : 0.f;
+                if (tap < T) {
+                  const float xv = xs[LY::nbr(sx, px, tap, 1)];
+                  bb = (G::parity(sx) ^ todd<DIM>(tap)) == fpar ? xv : 0.f;
                 }
-                acc1[si] = mfma(a, bb, acc1[si]);
+                acc1[mt * NTL1 + nt] = mfma(a, bb, acc1[mt * NTL1 + nt]);
               }
             }
           }
@@ -571,46 +626,42 @@ __global__ void __launch_bounds__(NT) kf_backward(
   __syncthreads();
   for (int ww = 0; ww < NW; ++ww) {
     if (w == ww) {
-      constexpr int NTL3 = (2 * T + 15) / 16, NTL1 = (T + 15) / 16;
 #pragma unroll
-      for (int si = 0; si < Cfg::S3; ++si) {
-        const int u = w + NW * si;
-        if (u < Cfg::I3 * Cfg::KS3) {
-          const int q = u / Cfg::KS3, nt = q % NTL3, mt = q / NTL3;
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NTL3; ++nt) {
           const int col = nt * 16 + m, tap = col >> 1, co = col & 1;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int ci = mt * 16 + 4 * j + i;
-            if (ci < C && tap < T) red[off_W3 + (co * C + ci) * T + tap] += acc3[si][i];
+            if (ci < C && tap < T) red[off_W3 + (co * C + ci) * T + tap] += acc3[mt * NTL3 + nt][i];
           }
         }
-      }
 #pragma unroll
-      for (int si = 0; si < Cfg::S2; ++si) {
-        const int u = w + NW * si;
-        if (u < Cfg::I2 * Cfg::KS2) {
-          const int q = u / Cfg::KS2, nt = q % MT, tap = (q / MT) % T, mt = q / (MT * T);
-          const int co = nt * 16 + m;
+      for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int ci = mt * 16 + 4 * j + i;
-            if (ci < C && co < C) red[off_W2 + (co * C + ci) * T + tap] += acc2[si][i];
+        for (int tap = 0; tap < T; ++tap)
+#pragma unroll
+          for (int nt = 0; nt < MT; ++nt) {
+            const int co = nt * 16 + m;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int ci = mt * 16 + 4 * j + i;
+              if (ci < C && co < C)
+                red[off_W2 + (co * C + ci) * T + tap] += acc2[(mt * T + tap) * MT + nt][i];
+            }
           }
-        }
-      }
 #pragma unroll
-      for (int si = 0; si < Cfg::S1; ++si) {
-        const int u = w + NW * si;
-        if (u < Cfg::I1 * Cfg::KS1) {
-          const int q = u / Cfg::KS1, nt = q % NTL1, mt = q / NTL1;
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NTL1; ++nt) {
           const int tap = nt * 16 + m;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int c = mt * 16 + 4 * j + i;
-            if (c < C && tap < T) red[off_W1 + c * T + tap] += acc1[si][i];
+            if (c < C && tap < T) red[off_W1 + c * T + tap] += acc1[mt * NTL1 + nt][i];
           }
         }
-      }
       if (m == 0) {
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct)
