@@ -37,8 +37,9 @@ __global__ void __launch_bounds__(NT) kf_forward(
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ R red[16];
   float* xs = reinterpret_cast<float*>(smem);
-  HT* h1 = reinterpret_cast<HT*>(smem + ((VS * 4 + 15) / 16) * 16);
-  HT* h2 = h1 + VS * C;
+  HT* h1 = reinterpret_cast<HT*>(smem + ((LY::VSZ * 4 + 15) / 16) * 16);
+  HT* h2 = h1 + LY::VSZ * C;
+  for (int q = threadIdx.x; q < C; q += NT) h1[LY::ZS * C + q] = 0, h2[LY::ZS * C + q] = 0;
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
   const size_t BV = (size_t)B * V;
 
@@ -164,6 +165,7 @@ template <int DIM, int L, int C, bool BF16>
 int32_t launch_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
                        double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
   using Cfg = FwdCfg<DIM, L, C, BF16>;
+  static_assert(Cfg::lds_bytes + 16 * 8 <= 160 * 1024, "LDS budget");
   constexpr LayerFrags LF = Cfg::LF;
   u32x4* frags = reinterpret_cast<u32x4*>(ws);
   FragTable tab{};

@@ -40,12 +40,13 @@ struct BwdLds {
   using LY = Lay<DIM, L, PAD>;
   static constexpr int V = Geo<DIM, L>::V, VS = LY::VS;
   static constexpr int CSTR = V + 8;  // channel-major row stride in elements (BF16 mode)
-  static constexpr size_t SA = (size_t)VS * C * (BF16 ? 2 : 4);  // site-major tensor
+  // site-major tensors and g_o carry the layout's extra all-zero site
+  static constexpr size_t SA = (size_t)LY::VSZ * C * (BF16 ? 2 : 4);  // site-major tensor
   static constexpr size_t SC = BF16 ? (size_t)C * CSTR * 2 : 0;  // channel-major tensor
   static constexpr size_t OFF_XS = 0;
   static constexpr size_t OFF_GY = align16((size_t)VS * 4);
   static constexpr size_t OFF_GOS = OFF_GY + align16((size_t)V * 4);
-  static constexpr size_t GOS_BYTES = (size_t)VS * (BF16 ? 4 : 8);
+  static constexpr size_t GOS_BYTES = (size_t)LY::VSZ * (BF16 ? 4 : 8);
   static constexpr size_t OFF_GOC = OFF_GOS + align16(GOS_BYTES);
   static constexpr size_t GOC_BYTES = BF16 ? 2 * (size_t)CSTR * 2 : 0;
   static constexpr size_t OFF_H0C = OFF_GOC + align16(GOC_BYTES);
@@ -194,6 +195,15 @@ __global__ void __launch_bounds__(NT) kf_backward(
   const u32x4* fr = frags + lane;
   const int apar = fpar ^ 1;
 
+  // The extra zero site of the site-major slots and of g_o: cleared once, never
+  // written afterwards (every later store goes to a lattice site or its mirror).
+  {
+    HT* z0 = reinterpret_cast<HT*>(smem + M::OFF_S0);
+    HT* z1 = reinterpret_cast<HT*>(smem + (BF16 ? M::OFF_S2 : M::OFF_S1));
+    for (int q = threadIdx.x; q < C; q += NT) z0[LY::ZS * C + q] = HT(0), z1[LY::ZS * C + q] = HT(0);
+    if (threadIdx.x < (BF16 ? 1 : 2))
+      reinterpret_cast<uint32_t*>(smem + M::OFF_GOS)[LY::ZS * (BF16 ? 1 : 2) + threadIdx.x] = 0u;
+  }
   // site-major activations: BF16 h1s S0, h2s S2; FP32 h1 S0, h2 S1
   HT* h1s = reinterpret_cast<HT*>(smem + M::OFF_S0);
   HT* h2s = reinterpret_cast<HT*>(smem + (BF16 ? M::OFF_S2 : M::OFF_S1));
@@ -417,15 +427,15 @@ __global__ void __launch_bounds__(NT) kf_backward(
             const int t0 = (32 * c + 8 * j) / 2;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-              bop[q] = t0 + q < T ? gos_b[LY::nbr(n, p, t0 + q, -1)] : 0u;
+              bop[q] = gos_b[t0 + q < T ? LY::nbr(n, p, t0 + q, -1) : LY::ZS];
           } else {
             const int t0 = (16 * c + 4 * j) / 2;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
               const int t = t0 + q;
-              const int nb = t < T ? LY::nbr(n, p, t, -1) : 0;
-              bop[2 * q] = t < T ? __float_as_uint(gos_f[2 * nb]) : 0u;
-              bop[2 * q + 1] = t < T ? __float_as_uint(gos_f[2 * nb + 1]) : 0u;
+              const int nb = t < T ? LY::nbr(n, p, t, -1) : LY::ZS;
+              bop[2 * q] = __float_as_uint(gos_f[2 * nb]);
+              bop[2 * q + 1] = __float_as_uint(gos_f[2 * nb + 1]);
             }
           }
 #pragma unroll

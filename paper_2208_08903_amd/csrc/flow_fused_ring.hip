@@ -35,7 +35,8 @@ struct RingCfg {
   static constexpr int V = G::V, T = 27, PS = LP2::VS, LP = L + 2;
   static constexpr LayerFrags LF = layer_frags(T, C, BF16);
   static constexpr size_t XS_BYTES = ((size_t)LX::VS * 4 + 15) / 16 * 16;
-  static constexpr size_t RING = 3 * (size_t)PS * C * sizeof(HElem<BF16>);
+  static constexpr int ZS = 3 * PS;  // all-zero site after the three planes
+  static constexpr size_t RING = (3 * (size_t)PS + 1) * C * sizeof(HElem<BF16>);
   static constexpr size_t lds_bytes = XS_BYTES + 2 * RING;
   static constexpr int NT = 256;
 };
@@ -50,12 +51,11 @@ __device__ __forceinline__ u32x4 gather_ring(const HElem<BF16>* ring, int pq, in
   using Cfg = RingCfg<L, C, BF16>;
   constexpr int K = 27 * C;
   const int k0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
-  if (k0 >= K) return u32x4{0u, 0u, 0u, 0u};
   const int tap = k0 / C, ci0 = k0 % C;
   const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
   const int slot = dz < 0 ? sm : (dz > 0 ? sp : s0);
-  const int idx = slot * Cfg::PS + pq + dy * Cfg::LP + dx;
-  return *reinterpret_cast<const u32x4*>(ring + idx * C + ci0);
+  const int e = k0 < K ? (slot * Cfg::PS + pq + dy * Cfg::LP + dx) * C + ci0 : Cfg::ZS * C;
+  return *reinterpret_cast<const u32x4*>(ring + e);
 }
 
 template <int L, int C, bool BF16, int NT>
@@ -77,7 +77,8 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
   __shared__ R red[16];
   float* xs = reinterpret_cast<float*>(smem);
   HT* r1 = reinterpret_cast<HT*>(smem + Cfg::XS_BYTES);
-  HT* r2 = r1 + 3 * PS * C;
+  HT* r2 = r1 + (3 * PS + 1) * C;
+  for (int q = threadIdx.x; q < C; q += NT) r1[Cfg::ZS * C + q] = HT(0), r2[Cfg::ZS * C + q] = HT(0);
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
   const size_t BV = (size_t)B * V;
 

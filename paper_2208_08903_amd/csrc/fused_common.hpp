@@ -113,6 +113,10 @@ struct Lay {
   static constexpr int Ls = L;
   static constexpr int LP = PAD ? L + 2 : L;
   static constexpr int VS = DIM == 2 ? LP * LP : LP * LP * LP;  // storage sites
+  // One extra all-zero site after the lattice: gathers of taps beyond the
+  // convolution's K read it instead of branching.
+  static constexpr int ZS = VS;
+  static constexpr int VSZ = VS + 1;  // sites to allocate
 
   __device__ static __forceinline__ int idx(int n) {
     if constexpr (!PAD) return n;

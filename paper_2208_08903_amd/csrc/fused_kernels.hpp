@@ -66,9 +66,9 @@ template <class LY, int C, bool BF16, int SIGN = 1>
 __device__ __forceinline__ u32x4 gather_h(const HElem<BF16>* h, int n, int p, int c, int j) {
   constexpr int K = LY::G::T * C;
   const int k0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
-  if (k0 >= K) return u32x4{0u, 0u, 0u, 0u};
   const int tap = k0 / C, ci0 = k0 % C;
-  return *reinterpret_cast<const u32x4*>(h + LY::nbr(n, p, tap, SIGN) * C + ci0);
+  const int e = k0 < K ? LY::nbr(n, p, tap < LY::G::T ? tap : 0, SIGN) * C + ci0 : LY::ZS * C;
+  return *reinterpret_cast<const u32x4*>(h + e);
 }
 
 // B operand of conv1: the masked field (frozen sites only) at the taps of the
@@ -82,12 +82,10 @@ __device__ __forceinline__ u32x4 gather_x(const float* xs, int n, int p, int pn,
   float v[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
+    // taps past T read the site itself (always in range) and are masked to 0
     const int t = t0 + i;
-    v[i] = 0.f;
-    if (t < T) {
-      const float xv = xs[LY::nbr(n, p, t, 1)];
-      v[i] = (pn ^ todd<LY::G::T == 9 ? 2 : 3>(t)) == fpar ? xv : 0.f;
-    }
+    const float xv = xs[t < T ? LY::nbr(n, p, t, 1) : p];
+    v[i] = t < T && (pn ^ todd<LY::G::T == 9 ? 2 : 3>(t)) == fpar ? xv : 0.f;
   }
   u32x4 r;
   if constexpr (BF16) {
@@ -111,15 +109,15 @@ __device__ __forceinline__ u32x4 gather_h0(const HElem<BF16>* h0, int n, int p, 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int ta = t0 + 2 * q, tb = ta + 1;
-      const uint32_t lo = ta < T ? (uint32_t)h0[LY::nbr(n, p, ta, 1)] : 0u;
-      const uint32_t hi = tb < T ? (uint32_t)h0[LY::nbr(n, p, tb, 1)] : 0u;
-      r[q] = lo | (hi << 16);
+      const int ia = ta < T ? LY::nbr(n, p, ta, 1) : LY::ZS;
+      const int ib = tb < T ? LY::nbr(n, p, tb, 1) : LY::ZS;
+      r[q] = (uint32_t)h0[ia] | ((uint32_t)h0[ib] << 16);
     }
   } else {
     const int t0 = 16 * c + 4 * j;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      r[q] = t0 + q < T ? __float_as_uint(h0[LY::nbr(n, p, t0 + q, 1)]) : 0u;
+      r[q] = __float_as_uint(h0[t0 + q < T ? LY::nbr(n, p, t0 + q, 1) : LY::ZS]);
   }
   return r;
 }
@@ -127,8 +125,8 @@ __device__ __forceinline__ u32x4 gather_h0(const HElem<BF16>* h0, int n, int p, 
 // h0 = the field at frozen sites, 0 at active sites, in every stored position.
 template <class LY, bool BF16, int NT>
 __device__ __forceinline__ void build_h0(HElem<BF16>* h0, const float* xs, int fpar) {
-  for (int q = threadIdx.x; q < LY::VS; q += NT) {
-    const float v = LY::G::parity(LY::site_of(q)) == fpar ? xs[q] : 0.f;
+  for (int q = threadIdx.x; q < LY::VSZ; q += NT) {
+    const float v = q < LY::VS && LY::G::parity(LY::site_of(q)) == fpar ? xs[q] : 0.f;
     if constexpr (BF16) h0[q] = (uint16_t)bf16_bits(v);
     else h0[q] = v;
   }
@@ -192,9 +190,9 @@ struct FwdCfg {
   static constexpr size_t bytes_for(int vs) {
     return ((size_t)vs * 4 + 15) / 16 * 16 + 2 * (size_t)vs * C * sizeof(HElem<BF16>);
   }
-  static constexpr bool PAD = bytes_for(Lay<DIM, L, true>::VS) <= 156 * 1024;
+  static constexpr bool PAD = bytes_for(Lay<DIM, L, true>::VSZ) <= 156 * 1024;
   using LY = Lay<DIM, L, PAD>;
-  static constexpr size_t lds_bytes = bytes_for(LY::VS);
+  static constexpr size_t lds_bytes = bytes_for(LY::VSZ);
   static constexpr int NT = lds_bytes > 80 * 1024 ? 512 : 256;
 };
 
