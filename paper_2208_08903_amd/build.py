@@ -19,6 +19,13 @@ ARCH = "gfx950"
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
           "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}"]
+# The forward kernels keep few long-lived accumulators: MFMA results written
+# straight to VGPRs save one accumulator read per result.  The backward keeps
+# its weight-gradient sums in the accumulator registers and is left alone.
+PER_SOURCE_FLAGS = {
+    "flow_fused.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "flow_fused_ring.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
 
 
 def sources():
@@ -27,7 +34,8 @@ def sources():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, "-c", src, "-o", obj]
+    extra = PER_SOURCE_FLAGS.get(os.path.basename(src), [])
+    cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -73,20 +73,15 @@ __global__ void __launch_bounds__(NT) kf_forward(
 #pragma unroll
           for (int c = 0; c < LF.k1; ++c) A[ct][c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
         }
-        for (int tile = w; tile < V / 16; tile += NW) {
-          const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
-          f32x4 acc[LF.nct];
+        mma_tiles<Cfg::TU1, LF.nct, LF.k1, BF16>(
+            V / 16, w, NW, A, bias,
+            [&](int tile, int c) {
+              return gather_h0<LY, BF16>(h2, tile * 16 + m, tile_p<LY>(tile, m), c, j);
+            },
+            [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int c = 0; c < LF.k1; ++c) {
-            const u32x4 bop = gather_h0<LY, BF16>(h2, n, p, c, j);
-#pragma unroll
-            for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
-          }
-#pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) store_hidden<LY, C, BF16>(h1, n, ct, j, acc[ct], bias[ct]);
-        }
+              for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16>(h1, tile, m, ct, j, acc[ct]);
+            });
       }
       __syncthreads();
       // conv2 over all sites
@@ -99,43 +94,40 @@ __global__ void __launch_bounds__(NT) kf_forward(
 #pragma unroll
           for (int c = 0; c < LF.k2; ++c) A[ct][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
         }
-        for (int tile = w; tile < V / 16; tile += NW) {
-          const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
-          f32x4 acc[LF.nct];
+        mma_tiles<Cfg::TU2, LF.nct, LF.k2, BF16>(
+            V / 16, w, NW, A, bias,
+            [&](int tile, int c) {
+              return gather_h<LY, C, BF16>(h1, tile * 16 + m, tile_p<LY>(tile, m), c, j);
+            },
+            [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int c = 0; c < LF.k2; ++c) {
-            const u32x4 bop = gather_h<LY, C, BF16>(h1, n, p, c, j);
-#pragma unroll
-            for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
-          }
-#pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) store_hidden<LY, C, BF16>(h2, n, ct, j, acc[ct], bias[ct]);
-        }
+              for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16>(h2, tile, m, ct, j, acc[ct]);
+            });
       }
       __syncthreads();
       // conv3 at the active sites, affine update and log-det
       {
-        u32x4 A[LF.k2];
+        u32x4 A[1][LF.k2];
 #pragma unroll
-        for (int c = 0; c < LF.k2; ++c) A[c] = fl[(LF.off3 + c) * 64];
-        const float bs = pl[off_b3], bt = pl[off_b3 + 1];
+        for (int c = 0; c < LF.k2; ++c) A[0][c] = fl[(LF.off3 + c) * 64];
+        const f32x4 b3[1] = {f32x4{pl[off_b3], pl[off_b3 + 1], 0.f, 0.f}};
         const int apar = fpar ^ 1;
-        for (int tile = w; tile < V / 32; tile += NW) {
-          const int n = G::half_site(tile * 16 + m, apar), p = LY::idx(n);
-          f32x4 acc{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int c = 0; c < LF.k2; ++c)
-            acc = mma<BF16>(A[c], gather_h<LY, C, BF16>(h2, n, p, c, j), acc);
-          if (j == 0) {
-            const float o0 = acc[0] + bs, t = acc[1] + bt;
-            const float s = final_tanh ? fast_tanh(o0) : o0;
-            const float xn = xs[p] * fast_exp(s) + t;
-            LY::copies(n, [&](int q) { xs[q] = xn; });
-            ld += (R)s;
-          }
-        }
+        mma_tiles<Cfg::TU2, 1, LF.k2, BF16>(
+            V / 32, w, NW, A, b3,
+            [&](int tile, int c) {
+              const int n = G::half_site(tile * 16 + m, apar);
+              return gather_h<LY, C, BF16>(h2, n, LY::idx(n), c, j);
+            },
+            [&](int tile, const f32x4(&acc)[1]) {
+              if (j == 0) {
+                const int n = G::half_site(tile * 16 + m, apar), p = LY::idx(n);
+                const float o0 = acc[0][0], t = acc[0][1];
+                const float s = final_tanh ? fast_tanh(o0) : o0;
+                const float xn = xs[p] * fast_exp(s) + t;
+                LY::copies(n, [&](int q) { xs[q] = xn; });
+                ld += (R)s;
+              }
+            });
       }
       __syncthreads();
       if (saved) {

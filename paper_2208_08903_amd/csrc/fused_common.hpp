@@ -179,6 +179,39 @@ struct Lay {
       }
     }
   }
+  // copies(16 tile + m, f) for lane m of a 16-site tile.  When rows hold whole
+  // tiles only the x mirror depends on the lane; the row and plane mirrors
+  // are decided once per tile.  A mirror of coordinate 0 sits L storage
+  // steps above it, one of coordinate L-1 L steps below.
+  template <class F>
+  __device__ static __forceinline__ void copies_tile(int tile, int m, F&& f) {
+    if constexpr (PAD && L % 16 == 0) {
+      const int n0 = tile * 16, x = n0 % L + m, p = idx(n0) + m;
+      const int ax = x == 0 ? L : (x == L - 1 ? -L : 0);
+      const int y = (n0 / L) % L;
+      const int ay = y == 0 ? L * LP : (y == L - 1 ? -L * LP : 0);
+      f(p);
+      if (ax) f(p + ax);
+      if (ay) {
+        f(p + ay);
+        if (ax) f(p + ay + ax);
+      }
+      if constexpr (DIM == 3) {
+        const int z = n0 / (L * L);
+        const int az = z == 0 ? L * LP * LP : (z == L - 1 ? -L * LP * LP : 0);
+        if (az) {
+          f(p + az);
+          if (ax) f(p + az + ax);
+          if (ay) {
+            f(p + az + ay);
+            if (ax) f(p + az + ay + ax);
+          }
+        }
+      }
+    } else {
+      copies(tile * 16 + m, f);
+    }
+  }
 };
 
 // Storage index of lane m's site in tile `tile` (16 consecutive sites): when a row

@@ -171,6 +171,34 @@ __device__ __forceinline__ u32x2 store_hidden(HElem<BF16>* h, int n, int ct, int
   return store4<LY, C, BF16>(h, n, co0, v);
 }
 
+// store4 for lane m of a 16-site tile (all stored copies of its site).
+template <class LY, int C, bool BF16>
+__device__ __forceinline__ u32x2 store4_tile(HElem<BF16>* h, int tile, int m, int co0,
+                                             const float (&v)[4]) {
+  if constexpr (BF16) {
+    const u32x2 wv{pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3])};
+    LY::copies_tile(tile, m, [&](int p) { *reinterpret_cast<u32x2*>(h + p * C + co0) = wv; });
+    return wv;
+  } else {
+    const f32x4 fv{v[0], v[1], v[2], v[3]};
+    LY::copies_tile(tile, m, [&](int p) { *reinterpret_cast<f32x4*>(h + p * C + co0) = fv; });
+    return u32x2{0u, 0u};
+  }
+}
+
+// Store leaky(a) for rows 4j..4j+3 of output-channel tile ct at lane m of a
+// tile; a already holds the bias (the MFMA accumulator starts from it).
+template <class LY, int C, bool BF16>
+__device__ __forceinline__ u32x2 store_act_tile(HElem<BF16>* h, int tile, int m, int ct, int j,
+                                                const f32x4& a) {
+  const int co0 = ct * 16 + 4 * j;
+  if (co0 >= C) return u32x2{0u, 0u};
+  float v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = leaky(a[i]);
+  return store4_tile<LY, C, BF16>(h, tile, m, co0, v);
+}
+
 template <int C>
 __device__ __forceinline__ f32x4 load_bias4(const float* b, int ct, int j) {
   const int co0 = ct * 16 + 4 * j;
@@ -180,6 +208,42 @@ __device__ __forceinline__ f32x4 load_bias4(const float* b, int ct, int j) {
     for (int i = 0; i < 4; ++i) r[i] = b[co0 + i];
   }
   return r;
+}
+
+// One implicit-GEMM pass over ntiles output tiles of 16 sites.  Wave w owns
+// tiles w, w + nw, w + 2 nw, ... and takes TU of them per iteration: per K
+// chunk it gathers the B operands of all TU tiles, then issues their MFMAs, and
+// only after the last chunk runs the epilogues.  The TU independent chains let
+// one tile's LDS latency hide behind another's MFMAs, which the compiler cannot
+// arrange by itself (it cannot prove the epilogue's stores miss the next
+// tile's loads).  Accumulators start from init (a bias, or zeros).
+// gather(tile, c) -> u32x4; epi(tile, f32x4 (&acc)[NCT]).
+template <int TU, int NCT, int KC, bool BF16, class Gather, class Epi>
+__device__ __forceinline__ void mma_tiles(int ntiles, int w, int nw, const u32x4 (&A)[NCT][KC],
+                                          const f32x4 (&init)[NCT], Gather&& gather, Epi&& epi) {
+  for (int t0 = w; t0 < ntiles; t0 += TU * nw) {
+    int tt[TU];
+#pragma unroll
+    for (int u = 0; u < TU; ++u) tt[u] = t0 + u * nw < ntiles ? t0 + u * nw : t0;
+    f32x4 acc[TU][NCT];
+#pragma unroll
+    for (int u = 0; u < TU; ++u)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = init[ct];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      u32x4 bop[TU];
+#pragma unroll
+      for (int u = 0; u < TU; ++u) bop[u] = gather(tt[u], c);
+#pragma unroll
+      for (int u = 0; u < TU; ++u)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = mma<BF16>(A[ct][c], bop[u], acc[u][ct]);
+    }
+#pragma unroll
+    for (int u = 0; u < TU; ++u)
+      if (t0 + u * nw < ntiles) epi(tt[u], acc[u]);
+  }
 }
 
 template <int DIM, int L, int C, bool BF16>
@@ -194,6 +258,9 @@ struct FwdCfg {
   using LY = Lay<DIM, L, PAD>;
   static constexpr size_t lds_bytes = bytes_for(LY::VSZ);
   static constexpr int NT = lds_bytes > 80 * 1024 ? 512 : 256;
+  // tiles in flight per wave: conv1 (one K chunk in BF16) and conv2/conv3
+  static constexpr int TU1 = BF16 ? 4 : 2;
+  static constexpr int TU2 = (DIM == 3 && !BF16) ? 1 : 2;
 };
 
 }  // namespace fused
