@@ -60,6 +60,17 @@ struct BwdLds {
   static constexpr size_t MAIN = BF16 ? OFF_S3 + SC : OFF_S2;
 };
 
+// Channel-major BF16 copy of four channels co0..co0+3 (packed pairs in hv) of
+// site n: row co holds the V sites of channel co, CSTR elements apart.
+template <int C, int CSTR>
+__device__ __forceinline__ void store_cm4(uint16_t* hc, int n, int co0, const u32x2& hv) {
+  if (co0 >= C) return;
+  hc[(co0 + 0) * CSTR + n] = (uint16_t)hv[0];
+  hc[(co0 + 1) * CSTR + n] = (uint16_t)(hv[0] >> 16);
+  hc[(co0 + 2) * CSTR + n] = (uint16_t)hv[1];
+  hc[(co0 + 3) * CSTR + n] = (uint16_t)(hv[1] >> 16);
+}
+
 template <int DIM, int L, int C, bool BF16>
 struct BwdCfg {
   using G = Geo<DIM, L>;
@@ -79,6 +90,7 @@ struct BwdCfg {
   // 3D shapes need more than the 256 registers a lane gets at 2 waves per SIMD.
   static constexpr int NT = (lds_bytes > 80 * 1024 && DIM == 2) ? 512 : 256;
   static constexpr int NW = NT / 64;
+  static constexpr int TU = 1;  // tiles in flight per wave in the recompute passes
   static constexpr int MT = (C + 15) / 16;
   static constexpr int NKC = BF16 ? V / 32 : V / 16;  // K chunks (sites) per sample
   // Weight-gradient output tiles; every wave accumulates all of them over its
@@ -253,32 +265,18 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
         for (int c = 0; c < LF.k1; ++c) A[ct][c] = fr[(LF.off1 + ct * LF.k1 + c) * 64];
       }
-      for (int tile = w; tile < V / 16; tile += NW) {
-        const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
-        f32x4 acc[LF.nct];
+      mma_tiles<Cfg::TU, LF.nct, LF.k1, BF16>(
+          V / 16, w, NW, A, bias,
+          [&](int tile, int c) {
+            return gather_h0<LY, BF16>(h2s, tile * 16 + m, tile_p<LY>(tile, m), c, j);
+          },
+          [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
-        for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int c = 0; c < LF.k1; ++c) {
-          const u32x4 bop = gather_h0<LY, BF16>(h2s, n, p, c, j);
-#pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
-        }
-#pragma unroll
-        for (int ct = 0; ct < LF.nct; ++ct) {
-          const u32x2 hv = store_hidden<LY, C, BF16>(h1s, n, ct, j, acc[ct], bias[ct]);
-          if constexpr (BF16) {
-            const int co0 = ct * 16 + 4 * j;
-            if (co0 < C) {
-              const uint32_t w0 = hv[0], w1 = hv[1];
-              h1c[(co0 + 0) * CSTR + n] = (uint16_t)w0;
-              h1c[(co0 + 1) * CSTR + n] = (uint16_t)(w0 >> 16);
-              h1c[(co0 + 2) * CSTR + n] = (uint16_t)w1;
-              h1c[(co0 + 3) * CSTR + n] = (uint16_t)(w1 >> 16);
+            for (int ct = 0; ct < LF.nct; ++ct) {
+              const u32x2 hv = store_act_tile<LY, C, BF16>(h1s, tile, m, ct, j, acc[ct]);
+              if constexpr (BF16) store_cm4<C, CSTR>(h1c, tile * 16 + m, ct * 16 + 4 * j, hv);
             }
-          }
-        }
-      }
+          });
     }
     __syncthreads();
     // ---- recompute conv2 -> h2 ----
@@ -291,32 +289,18 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
         for (int c = 0; c < LF.k2; ++c) A[ct][c] = fr[(LF.off2 + ct * LF.k2 + c) * 64];
       }
-      for (int tile = w; tile < V / 16; tile += NW) {
-        const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
-        f32x4 acc[LF.nct];
+      mma_tiles<Cfg::TU, LF.nct, LF.k2, BF16>(
+          V / 16, w, NW, A, bias,
+          [&](int tile, int c) {
+            return gather_h<LY, C, BF16>(h1s, tile * 16 + m, tile_p<LY>(tile, m), c, j);
+          },
+          [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
-        for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int c = 0; c < LF.k2; ++c) {
-          const u32x4 bop = gather_h<LY, C, BF16>(h1s, n, p, c, j);
-#pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
-        }
-#pragma unroll
-        for (int ct = 0; ct < LF.nct; ++ct) {
-          const u32x2 hv = store_hidden<LY, C, BF16>(h2s, n, ct, j, acc[ct], bias[ct]);
-          if constexpr (BF16) {
-            const int co0 = ct * 16 + 4 * j;
-            if (co0 < C) {
-              const uint32_t w0 = hv[0], w1 = hv[1];
-              h2c[(co0 + 0) * CSTR + n] = (uint16_t)w0;
-              h2c[(co0 + 1) * CSTR + n] = (uint16_t)(w0 >> 16);
-              h2c[(co0 + 2) * CSTR + n] = (uint16_t)w1;
-              h2c[(co0 + 3) * CSTR + n] = (uint16_t)(w1 >> 16);
+            for (int ct = 0; ct < LF.nct; ++ct) {
+              const u32x2 hv = store_act_tile<LY, C, BF16>(h2s, tile, m, ct, j, acc[ct]);
+              if constexpr (BF16) store_cm4<C, CSTR>(h2c, tile * 16 + m, ct * 16 + 4 * j, hv);
             }
-          }
-        }
-      }
+          });
     }
     // ---- recompute conv3 at active sites; affine backward -> g_o, g_x(active) ----
     // g_o is zero at the frozen sites.
@@ -338,18 +322,20 @@ __global__ void __launch_bounds__(NT) kf_backward(
     }
     __syncthreads();
     {
-      u32x4 A[LF.k2];
+      u32x4 A[1][LF.k2];
 #pragma unroll
-      for (int c = 0; c < LF.k2; ++c) A[c] = fr[(LF.off3 + c) * 64];
-      const float bs = pl[off_b3], bt = pl[off_b3 + 1];
-      for (int tile = w; tile < V / 32; tile += NW) {
+      for (int c = 0; c < LF.k2; ++c) A[0][c] = fr[(LF.off3 + c) * 64];
+      const f32x4 b3[1] = {f32x4{pl[off_b3], 0.f, 0.f, 0.f}};
+      mma_tiles<Cfg::TU, 1, LF.k2, BF16>(
+          V / 32, w, NW, A, b3,
+          [&](int tile, int c) {
+            const int n = G::half_site(tile * 16 + m, apar);
+            return gather_h<LY, C, BF16>(h2s, n, LY::idx(n), c, j);
+          },
+          [&](int tile, const f32x4(&acc3r)[1]) {
         const int n = G::half_site(tile * 16 + m, apar), p = LY::idx(n);
-        f32x4 acc{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int c = 0; c < LF.k2; ++c)
-          acc = mma<BF16>(A[c], gather_h<LY, C, BF16>(h2s, n, p, c, j), acc);
         if (j == 0) {
-          const float o0 = acc[0] + bs;
+          const float o0 = acc3r[0][0];
           const float s = final_tanh ? fast_tanh(o0) : o0;
           const float es = fast_exp(s);
           const float g = gys[n];
@@ -370,7 +356,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
             });
           }
         }
-      }
+          });
     }
     __syncthreads();
     // ---- dW3[co][ci][tap] += sum_m h2[m][ci] g_o[m - delta_tap][co] ----
