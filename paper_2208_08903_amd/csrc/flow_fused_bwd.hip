@@ -90,7 +90,9 @@ struct BwdCfg {
   // 3D shapes need more than the 256 registers a lane gets at 2 waves per SIMD.
   static constexpr int NT = (lds_bytes > 80 * 1024 && DIM == 2) ? 512 : 256;
   static constexpr int NW = NT / 64;
-  static constexpr int TU = 1;  // tiles in flight per wave in the recompute passes
+  // Tiles in flight per wave in the tile passes: two where the registers allow
+  // (3D shapes, and FP32 C=16 at two waves per SIMD, are already at the limit).
+  static constexpr int TU = DIM == 2 && (BF16 || NT == 256 || C < 16) ? 2 : 1;
   static constexpr int MT = (C + 15) / 16;
   static constexpr int NKC = BF16 ? V / 32 : V / 16;  // K chunks (sites) per sample
   // Weight-gradient output tiles; every wave accumulates all of them over its
@@ -401,60 +403,53 @@ __global__ void __launch_bounds__(NT) kf_backward(
       for (int ct = 0; ct < LF.nct; ++ct)
 #pragma unroll
         for (int c = 0; c < Cfg::KT3; ++c) A[ct][c] = fr[(Cfg::OFF3T + ct * Cfg::KT3 + c) * 64];
-      for (int tile = w; tile < V / 16; tile += NW) {
-        const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
-        f32x4 acc[LF.nct];
-#pragma unroll
-        for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int c = 0; c < Cfg::KT3; ++c) {
-          u32x4 bop;
-          if constexpr (BF16) {
-            const int t0 = (32 * c + 8 * j) / 2;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              bop[q] = gos_b[t0 + q < T ? LY::nbr(n, p, t0 + q, -1) : LY::ZS];
-          } else {
-            const int t0 = (16 * c + 4 * j) / 2;
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-              const int t = t0 + q;
-              const int nb = t < T ? LY::nbr(n, p, t, -1) : LY::ZS;
-              bop[2 * q] = __float_as_uint(gos_f[2 * nb]);
-              bop[2 * q + 1] = __float_as_uint(gos_f[2 * nb + 1]);
-            }
-          }
-#pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
-        }
-#pragma unroll
-        for (int ct = 0; ct < LF.nct; ++ct) {
-          const int c0 = ct * 16 + 4 * j;
-          if (c0 < C) {
-            float v[4];
+      const f32x4 zero[LF.nct] = {};
+      mma_tiles<Cfg::TU, LF.nct, Cfg::KT3, BF16>(
+          V / 16, w, NW, A, zero,
+          [&](int tile, int c) {
+            const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
+            u32x4 bop;
             if constexpr (BF16) {
-              const uint32_t* hv = reinterpret_cast<const uint32_t*>(h2s + p * C + c0);
-              const uint32_t w0 = hv[0], w1 = hv[1];
-              const float hh[4] = {bf16_lo(w0), bf16_hi(w0), bf16_lo(w1), bf16_hi(w1)};
+              const int t0 = (32 * c + 8 * j) / 2;
 #pragma unroll
-              for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-              const u32x2 pw = store4<LY, C, BF16>(ga2s, n, c0, v);
-              const uint32_t p0 = pw[0], p1 = pw[1];
-              ga2c[(c0 + 0) * CSTR + n] = (uint16_t)p0;
-              ga2c[(c0 + 1) * CSTR + n] = (uint16_t)(p0 >> 16);
-              ga2c[(c0 + 2) * CSTR + n] = (uint16_t)p1;
-              ga2c[(c0 + 3) * CSTR + n] = (uint16_t)(p1 >> 16);
+              for (int q = 0; q < 4; ++q)
+                bop[q] = gos_b[t0 + q < T ? LY::nbr(n, p, t0 + q, -1) : LY::ZS];
             } else {
-              const f32x4 hh = *reinterpret_cast<const f32x4*>(h2s + p * C + c0);
+              const int t0 = (16 * c + 4 * j) / 2;
 #pragma unroll
-              for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-              store4<LY, C, BF16>(ga2s, n, c0, v);
+              for (int q = 0; q < 2; ++q) {
+                const int t = t0 + q;
+                const int nb = t < T ? LY::nbr(n, p, t, -1) : LY::ZS;
+                bop[2 * q] = __float_as_uint(gos_f[2 * nb]);
+                bop[2 * q + 1] = __float_as_uint(gos_f[2 * nb + 1]);
+              }
             }
+            return bop;
+          },
+          [&](int tile, const f32x4(&acc)[LF.nct]) {
+            const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) db2[ct][i] += v[i];
-          }
-        }
-      }
+            for (int ct = 0; ct < LF.nct; ++ct) {
+              const int c0 = ct * 16 + 4 * j;
+              if (c0 < C) {
+                float v[4];
+                if constexpr (BF16) {
+                  const u32x2 hv = *reinterpret_cast<const u32x2*>(h2s + p * C + c0);
+                  const float hh[4] = {bf16_lo(hv[0]), bf16_hi(hv[0]), bf16_lo(hv[1]), bf16_hi(hv[1])};
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
+                  store_cm4<C, CSTR>(ga2c, n, c0, store4_tile<LY, C, BF16>(ga2s, tile, m, c0, v));
+                } else {
+                  const f32x4 hh = *reinterpret_cast<const f32x4*>(h2s + p * C + c0);
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
+                  store4_tile<LY, C, BF16>(ga2s, tile, m, c0, v);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) db2[ct][i] += v[i];
+              }
+            }
+          });
     }
     __syncthreads();
     // ---- dW2[co][ci][tap] += sum_m h1[m][ci] g_a2[m - delta_tap][co] ----
@@ -509,45 +504,37 @@ __global__ void __launch_bounds__(NT) kf_backward(
       for (int ct = 0; ct < LF.nct; ++ct)
 #pragma unroll
         for (int c = 0; c < LF.k2; ++c) A[ct][c] = fr[(Cfg::OFF2T + ct * LF.k2 + c) * 64];
-      for (int tile = w; tile < V / 16; tile += NW) {
-        const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
-        f32x4 acc[LF.nct];
+      const f32x4 zero[LF.nct] = {};
+      mma_tiles<Cfg::TU, LF.nct, LF.k2, BF16>(
+          V / 16, w, NW, A, zero,
+          [&](int tile, int c) {
+            return gather_h<LY, C, BF16, -1>(ga2s, tile * 16 + m, tile_p<LY>(tile, m), c, j);
+          },
+          [&](int tile, const f32x4(&acc)[LF.nct]) {
+            const int n = tile * 16 + m, p = tile_p<LY>(tile, m);
 #pragma unroll
-        for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int ct = 0; ct < LF.nct; ++ct) {
+              const int c0 = ct * 16 + 4 * j;
+              if (c0 < C) {
+                float v[4];
+                if constexpr (BF16) {
+                  float hh[4];
 #pragma unroll
-        for (int c = 0; c < LF.k2; ++c) {
-          const u32x4 bop = gather_h<LY, C, BF16, -1>(ga2s, n, p, c, j);
+                  for (int i = 0; i < 4; ++i) hh[i] = __uint_as_float((uint32_t)h1c[(c0 + i) * CSTR + n] << 16);
 #pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A[ct][c], bop, acc[ct]);
-        }
+                  for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
+                  store_cm4<C, CSTR>(ga1c, n, c0, store4_tile<LY, C, BF16>(ga1s, tile, m, c0, v));
+                } else {
+                  const f32x4 hh = *reinterpret_cast<const f32x4*>(h1s + p * C + c0);
 #pragma unroll
-        for (int ct = 0; ct < LF.nct; ++ct) {
-          const int c0 = ct * 16 + 4 * j;
-          if (c0 < C) {
-            float v[4];
-            if constexpr (BF16) {
-              float hh[4];
+                  for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
+                  store4_tile<LY, C, BF16>(ga1s, tile, m, c0, v);
+                }
 #pragma unroll
-              for (int i = 0; i < 4; ++i) hh[i] = __uint_as_float((uint32_t)h1c[(c0 + i) * CSTR + n] << 16);
-#pragma unroll
-              for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-              const u32x2 pw = store4<LY, C, BF16>(ga1s, n, c0, v);
-              const uint32_t p0 = pw[0], p1 = pw[1];
-              ga1c[(c0 + 0) * CSTR + n] = (uint16_t)p0;
-              ga1c[(c0 + 1) * CSTR + n] = (uint16_t)(p0 >> 16);
-              ga1c[(c0 + 2) * CSTR + n] = (uint16_t)p1;
-              ga1c[(c0 + 3) * CSTR + n] = (uint16_t)(p1 >> 16);
-            } else {
-              const f32x4 hh = *reinterpret_cast<const f32x4*>(h1s + p * C + c0);
-#pragma unroll
-              for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-              store4<LY, C, BF16>(ga1s, n, c0, v);
+                for (int i = 0; i < 4; ++i) db1[ct][i] += v[i];
+              }
             }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) db1[ct][i] += v[i];
-          }
-        }
-      }
+          });
     }
     __syncthreads();
     // ---- dW1[c][tap] += sum_n g_a1[n][c] h0[n + delta_tap] (h0 = mask_F x) ----
