@@ -60,8 +60,8 @@ __global__ void __launch_bounds__(NT) kf_forward(
       const u32x4* fl = frags + (size_t)layer * LF.total * 64 + lane;
       const float* pl = params + (size_t)layer * P_layer;
       __syncthreads();
-      // masked field for conv1, kept in the (dead) h2 buffer
-      build_h0<LY, BF16, NT>(h2, xs, fpar);
+      // conv1 operands (row triples of the masked field) in the (dead) h2 buffer
+      build_tri<LY, BF16, NT>(h2, xs, fpar);
       __syncthreads();
       // conv1 over all sites
       {
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(NT) kf_forward(
         mma_tiles<Cfg::TU1, LF.nct, LF.k1, BF16>(
             V / 16, w, NW, A, bias,
             [&](int tile, int c) {
-              return gather_h0<LY, BF16>(h2, tile * 16 + m, tile_p<LY>(tile, m), c, j);
+              return gather_tri<LY, BF16>(h2, tile * 16 + m, tile_p<LY>(tile, m), c, j);
             },
             [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
@@ -162,7 +162,7 @@ int32_t launch_forward(const FlowGeom& g, const float* params, int B, const floa
   u32x4* frags = reinterpret_cast<u32x4*>(ws);
   FragTable tab{};
   tab.count = 3;
-  tab.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, LF.nct, LF.k1, LF.off1};
+  tab.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, LF.nct, LF.k1, LF.off1, 1};
   tab.s[1] = FragSpec{0, (int)g.off_W2, C, C, C, LF.nct, LF.k2, LF.off2};
   tab.s[2] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, LF.k2, LF.off3};
   tab.total = LF.total;

@@ -254,8 +254,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
       for (int n = threadIdx.x; n < V; n += NT)
         h0c[n] = (uint16_t)bf16_bits(G::parity(n) == fpar ? xs[LY::idx(n)] : 0.f);
     }
-    // masked field for conv1, site-major in the (not yet written) h2 slot
-    build_h0<LY, BF16, NT>(h2s, xs, fpar);
+    // conv1 operands (row triples of the masked field) in the (not yet written) h2 slot
+    build_tri<LY, BF16, NT>(h2s, xs, fpar);
     __syncthreads();
     // ---- recompute conv1 -> h1 ----
     {
@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
       mma_tiles<Cfg::TU, LF.nct, LF.k1, BF16>(
           V / 16, w, NW, A, bias,
           [&](int tile, int c) {
-            return gather_h0<LY, BF16>(h2s, tile * 16 + m, tile_p<LY>(tile, m), c, j);
+            return gather_tri<LY, BF16>(h2s, tile * 16 + m, tile_p<LY>(tile, m), c, j);
           },
           [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
@@ -705,7 +705,7 @@ inline FragTable bwd_table(const FlowGeom& g, bool bf16) {
   const int kt3 = bf16 ? kchunks_bf16(2 * T) : kblocks_f32(2 * T);
   FragTable t{};
   t.count = 6;
-  t.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, lf.nct, lf.k1, lf.off1};
+  t.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, lf.nct, lf.k1, lf.off1, 1};
   t.s[1] = FragSpec{0, (int)g.off_W2, C, C, C, lf.nct, lf.k2, lf.off2};
   t.s[2] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, lf.k2, lf.off3};
   t.s[3] = FragSpec{1, (int)g.off_W3, C, 2, C, lf.nct, kt3, lf.total};

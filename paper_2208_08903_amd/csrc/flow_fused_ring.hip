@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
           for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int c = 0; c < LF.k1; ++c) {
-            const u32x4 bop = gather_x<LX, BF16>(xs, n, p, pn, fpar, c, j);
+            const u32x4 bop = gather_tri_x<LX, BF16>(xs, n, p, pn, fpar, c, j);
 #pragma unroll
             for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A1[ct][c], bop, acc[ct]);
           }
@@ -220,7 +220,7 @@ int32_t launch_ring(const FlowGeom& g, const float* params, int B, const float* 
   u32x4* frags = reinterpret_cast<u32x4*>(ws);
   FragTable tab{};
   tab.count = 3;
-  tab.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, LF.nct, LF.k1, LF.off1};
+  tab.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, LF.nct, LF.k1, LF.off1, 1};
   tab.s[1] = FragSpec{0, (int)g.off_W2, C, C, C, LF.nct, LF.k2, LF.off2};
   tab.s[2] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, LF.k2, LF.off3};
   tab.total = LF.total;

@@ -64,6 +64,7 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // Compile-time lattice: V sites, T taps, row-major, axis 0 slowest.
 template <int DIM, int L>
 struct Geo {
+  static constexpr int Dim = DIM;
   static constexpr int V = DIM == 2 ? L * L : L * L * L;
   static constexpr int T = DIM == 2 ? 9 : 27;
   static constexpr int HALF = V / 2;
@@ -122,6 +123,13 @@ struct Lay {
     if constexpr (!PAD) return n;
     if constexpr (DIM == 2) return (n / L + 1) * LP + n % L + 1;
     return ((n / (L * L) + 1) * LP + (n / L) % L + 1) * LP + n % L + 1;
+  }
+  // Parity of the site stored at index q (halo entries hold sites of the same
+  // parity as their storage coordinates minus one, since L is even).
+  __device__ static __forceinline__ int spar(int q) {
+    if constexpr (!PAD) return G::parity(q);
+    if constexpr (DIM == 2) return (q / LP + q % LP) & 1;
+    return (q / (LP * LP) + (q / LP) % LP + q % LP + 1) & 1;
   }
   // Storage-index offset of tap t (padded layout).
   __device__ static __forceinline__ int toff(int t) {
@@ -232,6 +240,9 @@ __device__ __forceinline__ int todd(int t) {
 // Number of 32-wide BF16 K chunks / 16-wide FP32 K blocks of a convolution
 // with K = taps * cin.
 __host__ __device__ constexpr int kchunks_bf16(int K) { return (K + 31) / 32; }
+// K of conv1 in row-triple order: one slot per (row offset, dx) with dx in
+// {-1, 0, +1, pad}; T / 3 row offsets (the taps of all axes but the fastest).
+__host__ __device__ constexpr int k_tri(int T) { return T / 3 * 4; }
 __host__ __device__ constexpr int kblocks_f32(int K) { return (K + 15) / 16; }
 
 // Fragment bookkeeping for one layer (counts of 1 KB fragments = 64 lanes x 16 B).
@@ -244,7 +255,7 @@ struct LayerFrags {
 __host__ __device__ constexpr LayerFrags layer_frags(int T, int C, bool bf16) {
   LayerFrags f{};
   f.nct = C >= 16 ? C / 16 : 1;
-  f.k1 = bf16 ? kchunks_bf16(T) : kblocks_f32(T);
+  f.k1 = bf16 ? kchunks_bf16(k_tri(T)) : kblocks_f32(k_tri(T));
   f.k2 = bf16 ? kchunks_bf16(T * C) : kblocks_f32(T * C);
   f.off1 = 0;
   f.off2 = f.nct * f.k1;

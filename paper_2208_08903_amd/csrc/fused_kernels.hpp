@@ -10,11 +10,13 @@
 namespace lfs {
 namespace fused {
 
-// A convolution's weights as MFMA A-fragments.  kind: 0 = forward
-// convolution (rows = output channels, k = tap * cin + ci), 1 = its transpose
+// A convolution's weights as MFMA A-fragments.  transposed = 0: forward
+// convolution (rows = output channels, k = tap * cin + ci); 1: its transpose
 // used by the data gradient (rows = input channels, k = tap * cout + co).
+// tri = 1 (single-input-channel forward convolution only): k in row-triple
+// order, k = 4 * (tap / 3) + tap % 3, the slots 4 r + 3 being zero.
 struct FragSpec {
-  int transposed, woff, cin, cout, rows, nct, nk, off;
+  int transposed, woff, cin, cout, rows, nct, nk, off, tri;
 };
 constexpr int kMaxSpecs = 6;
 struct FragTable {
@@ -41,6 +43,11 @@ __global__ void kf_prep(const float* __restrict__ params, int N, int T, int P_la
   const int kdiv = sp.transposed ? sp.cout : sp.cin;
   const int K = T * kdiv;
   auto w_at = [&](int k) -> float {
+    if (sp.tri) {
+      const int r = k >> 2, dx = k & 3;
+      if (row >= sp.rows || dx == 3 || r >= T / 3) return 0.f;
+      return W[row * T + 3 * r + dx];
+    }
     if (row >= sp.rows || k >= K) return 0.f;
     const int tap = k / kdiv, ch = k % kdiv;
     return sp.transposed ? W[(ch * sp.cin + row) * T + tap] : W[(row * sp.cin + ch) * T + tap];
@@ -71,68 +78,88 @@ __device__ __forceinline__ u32x4 gather_h(const HElem<BF16>* h, int n, int p, in
   return *reinterpret_cast<const u32x4*>(h + e);
 }
 
-// B operand of conv1: the masked field (frozen sites only) at the taps of the
-// lane's K slice; xs is stored with layout LY; pn = parity of site n.
+// conv1 operands in row-triple order.  A row triple of storage index q holds
+// the masked field (frozen parity fpar kept, the rest 0) at q's site and its
+// two neighbours along the fastest axis, plus a zero: (x[q-1], x[q], x[q+1], 0)
+// as 4 BF16 (8 bytes) or 4 FP32 (16 bytes).  The K slice of lane j in chunk c
+// (BF16: 8 slots, row offsets 8c + 2j and 8c + 2j + 1) or block c (FP32: 4
+// slots, row offset 4c + j) is then whole triples at fixed per-lane offsets.
+// Row offsets past T / 3 meet zero weights and read the site's own triple.
 template <class LY, bool BF16>
-__device__ __forceinline__ u32x4 gather_x(const float* xs, int n, int p, int pn, int fpar, int c,
-                                          int j) {
-  constexpr int T = LY::G::T;
-  constexpr int NV = BF16 ? 8 : 4;
-  const int t0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
-  float v[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    // taps past T read the site itself (always in range) and are masked to 0
-    const int t = t0 + i;
-    const float xv = xs[t < T ? LY::nbr(n, p, t, 1) : p];
-    v[i] = t < T && (pn ^ todd<LY::G::T == 9 ? 2 : 3>(t)) == fpar ? xv : 0.f;
-  }
-  u32x4 r;
+__device__ __forceinline__ u32x4 gather_tri(const HElem<BF16>* tri, int n, int p, int c, int j) {
+  constexpr int NR = LY::G::T / 3;
+  auto at = [&](int r) { return r < NR ? LY::nbr(n, p, 3 * r + 1, 1) : p; };
   if constexpr (BF16) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = pack_bf16(v[2 * q], v[2 * q + 1]);
+    const int r0 = 8 * c + 2 * j;
+    const u32x2 a = *reinterpret_cast<const u32x2*>(tri + 4 * at(r0));
+    const u32x2 b = *reinterpret_cast<const u32x2*>(tri + 4 * at(r0 + 1));
+    return u32x4{a[0], a[1], b[0], b[1]};
   } else {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = __float_as_uint(v[q]);
+    return *reinterpret_cast<const u32x4*>(tri + 4 * at(4 * c + j));
   }
-  return r;
 }
 
-// B operand of conv1 from the masked field h0 (zero at active sites), stored with
-// layout LY in BF16 (BF16 mode) or FP32: the taps of the lane's K slice.
-template <class LY, bool BF16>
-__device__ __forceinline__ u32x4 gather_h0(const HElem<BF16>* h0, int n, int p, int c, int j) {
-  constexpr int T = LY::G::T;
-  u32x4 r;
-  if constexpr (BF16) {
-    const int t0 = 32 * c + 8 * j;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int ta = t0 + 2 * q, tb = ta + 1;
-      const int ia = ta < T ? LY::nbr(n, p, ta, 1) : LY::ZS;
-      const int ib = tb < T ? LY::nbr(n, p, tb, 1) : LY::ZS;
-      r[q] = (uint32_t)h0[ia] | ((uint32_t)h0[ib] << 16);
-    }
-  } else {
-    const int t0 = 16 * c + 4 * j;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      r[q] = __float_as_uint(h0[t0 + q < T ? LY::nbr(n, p, t0 + q, 1) : LY::ZS]);
-  }
-  return r;
-}
-
-// h0 = the field at frozen sites, 0 at active sites, in every stored position.
+// Row triples of every stored position from the field xs (layout LY).  Padded
+// layouts skip the halo columns, which no gather reads.
 template <class LY, bool BF16, int NT>
-__device__ __forceinline__ void build_h0(HElem<BF16>* h0, const float* xs, int fpar) {
-  for (int q = threadIdx.x; q < LY::VSZ; q += NT) {
-    const float v = q < LY::VS && LY::G::parity(LY::site_of(q)) == fpar ? xs[q] : 0.f;
-    if constexpr (BF16) h0[q] = (uint16_t)bf16_bits(v);
-    else h0[q] = v;
+__device__ __forceinline__ void build_tri(HElem<BF16>* tri, const float* xs, int fpar) {
+  constexpr int TC = (LY::G::T - 1) / 2;  // the centre tap; TC -+ 1 step along the fastest axis
+  for (int q = threadIdx.x; q < LY::VS; q += NT) {
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    bool live = true;
+    int qm, qp;
+    if constexpr (LY::padded) {
+      const int px = q % LY::LP;
+      live = px != 0 && px != LY::LP - 1;
+      qm = q - 1;
+      qp = q + 1;
+    } else {
+      qm = LY::G::nbr(q, TC - 1, 1);
+      qp = LY::G::nbr(q, TC + 1, 1);
+    }
+    if (live) {
+      const bool frozen = LY::spar(q) == fpar;  // the x neighbours have the other parity
+      v[0] = frozen ? 0.f : xs[qm];
+      v[1] = frozen ? xs[q] : 0.f;
+      v[2] = frozen ? 0.f : xs[qp];
+    }
+    if constexpr (BF16) {
+      *reinterpret_cast<u32x2*>(tri + 4 * q) = u32x2{pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3])};
+    } else {
+      *reinterpret_cast<f32x4*>(tri + 4 * q) = f32x4{v[0], v[1], v[2], v[3]};
+    }
   }
 }
 
-// acc += A (fragment) x B (gathered) for one chunk / block.
+// conv1 operands in row-triple order straight from the field xs (layout LY)
+// for the site n (storage index p, parity pn): the same values gather_tri
+// reads from a built triple array.
+template <class LY, bool BF16>
+__device__ __forceinline__ u32x4 gather_tri_x(const float* xs, int n, int p, int pn, int fpar,
+                                              int c, int j) {
+  constexpr int NR = LY::G::T / 3;
+  constexpr int DIM = LY::G::Dim;
+  auto triple = [&](int r, float (&v)[3]) {
+    const int rr = r < NR ? r : (NR - 1) / 2;
+    const int t = 3 * rr + 1, q = LY::nbr(n, p, t, 1);
+    const bool frozen = (pn ^ todd<DIM>(t)) == fpar;
+    const float xm = xs[LY::nbr(n, p, t - 1, 1)], xc = xs[q], xp = xs[LY::nbr(n, p, t + 1, 1)];
+    v[0] = frozen ? 0.f : xm;
+    v[1] = frozen ? xc : 0.f;
+    v[2] = frozen ? 0.f : xp;
+  };
+  if constexpr (BF16) {
+    float a[3], b[3];
+    triple(8 * c + 2 * j, a);
+    triple(8 * c + 2 * j + 1, b);
+    return u32x4{pack_bf16(a[0], a[1]), pack_bf16(a[2], 0.f), pack_bf16(b[0], b[1]), pack_bf16(b[2], 0.f)};
+  } else {
+    float a[3];
+    triple(4 * c + j, a);
+    return u32x4{__float_as_uint(a[0]), __float_as_uint(a[1]), __float_as_uint(a[2]), 0u};
+  }
+}
+
 template <bool BF16>
 __device__ __forceinline__ f32x4 mma(const u32x4& a, const u32x4& b, f32x4 acc) {
   if constexpr (BF16) {
