@@ -239,15 +239,47 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
   for (int ct = 0; ct < LF.nct; ++ct) db2[ct] = db1[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  // 2D: a sample's x (in layout LY) and g_y are loaded into registers while the
+  // previous sample is still being processed, so staging them is LDS writes
+  // only.  3D shapes have no registers to spare and load them when staging.
+  constexpr bool PF = DIM == 2;
+  constexpr int NPX = PF ? (VS + NT - 1) / NT : 1, NPG = PF ? (V / 4 + NT - 1) / NT : 1;
+  float pfx[NPX];
+  f32x4 pfg[NPG];
+  auto prefetch = [&](int bb) {
+    if (bb >= B) return;
+    const size_t s0 = (size_t)bb * V;
+#pragma unroll
+    for (int i = 0; i < NPX; ++i) {
+      const int q = threadIdx.x + i * NT;
+      pfx[i] = q < VS ? xin[s0 + LY::site_of(q)] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < NPG; ++i) {
+      const int q = threadIdx.x + i * NT;
+      pfg[i] = q < V / 4 ? reinterpret_cast<const f32x4*>(gy + s0)[q] : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  if constexpr (PF) prefetch(blockIdx.x);
+
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     // Weight fragments are reloaded per phase (L1/L2 hits) rather than kept live
     // across the whole sample loop, which would need every phase's registers at once.
     asm volatile("" ::: "memory");
     const size_t sb = (size_t)b * V;
     // stage x and g_y; BF16: masked field channel-major for dW1
-    for (int q = threadIdx.x; q < VS; q += NT) xs[q] = xin[sb + LY::site_of(q)];
-    for (int q = threadIdx.x; q < V / 4; q += NT)
-      reinterpret_cast<f32x4*>(gys)[q] = reinterpret_cast<const f32x4*>(gy + sb)[q];
+    if constexpr (PF) {
+#pragma unroll
+      for (int i = 0; i < NPX; ++i)
+        if (threadIdx.x + i * NT < VS) xs[threadIdx.x + i * NT] = pfx[i];
+#pragma unroll
+      for (int i = 0; i < NPG; ++i)
+        if (threadIdx.x + i * NT < V / 4) reinterpret_cast<f32x4*>(gys)[threadIdx.x + i * NT] = pfg[i];
+    } else {
+      for (int q = threadIdx.x; q < VS; q += NT) xs[q] = xin[sb + LY::site_of(q)];
+      for (int q = threadIdx.x; q < V / 4; q += NT)
+        reinterpret_cast<f32x4*>(gys)[q] = reinterpret_cast<const f32x4*>(gy + sb)[q];
+    }
     __syncthreads();
     if constexpr (BF16) {
       uint16_t* h0c = reinterpret_cast<uint16_t*>(smem + M::OFF_H0C);
@@ -504,6 +536,9 @@ __global__ void __launch_bounds__(NT) kf_backward(
       for (int ct = 0; ct < LF.nct; ++ct)
 #pragma unroll
         for (int c = 0; c < LF.k2; ++c) A[ct][c] = fr[(Cfg::OFF2T + ct * LF.k2 + c) * 64];
+      // next sample's inputs: issued after this phase's fragment loads, so only
+      // the next phase's fragment loads wait for them
+      if constexpr (PF) prefetch(b + gridDim.x);
       const f32x4 zero[LF.nct] = {};
       mma_tiles<Cfg::TU, LF.nct, LF.k2, BF16>(
           V / 16, w, NW, A, zero,

@@ -39,8 +39,15 @@ __device__ __forceinline__ float opnd(float x) {
   return x;
 }
 
-// LeakyReLU with slope in (0, 1): max(a, slope * a).
-__device__ __forceinline__ float leaky(float a) { return fmaxf(a, kLeakySlope * a); }
+// LeakyReLU with slope in (0, 1): max(a, slope * a).  One v_max_f32: fmaxf
+// would first canonicalise an operand the compiler cannot prove canonical
+// (an MFMA result), a third instruction for nothing, as a is never a
+// signalling NaN here.
+__device__ __forceinline__ float leaky(float a) {
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(kLeakySlope * a));
+  return r;
+}
 // LeakyReLU'(a) from its output h = leaky(a): sign(h) == sign(a), h == 0 iff a == 0.
 __device__ __forceinline__ float leaky_grad_from_out(float h) { return h >= 0.f ? 1.f : kLeakySlope; }
 
