@@ -29,7 +29,8 @@ WORKLOAD = dict(workload="phi4-2d-L32-train", dim=2, L=32, m2=-4.0, lam=8.0, n_l
 PEAK = {"bf16_mfma_tflops": 2500.0, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
 KERNEL_SOURCES = ["paper_2208_08903_amd/csrc/flow_fused_bwd.hip",
                   "paper_2208_08903_amd/csrc/fused_kernels.hpp",
-                  "paper_2208_08903_amd/csrc/fused_common.hpp"]
+                  "paper_2208_08903_amd/csrc/fused_common.hpp",
+                  "paper_2208_08903_amd/csrc/lfs_common.hpp"]
 TRAFFIC_FILE = "profiles/kf_backward_phi4-2d-L32-train_traffic.txt"
 
 

@@ -704,16 +704,21 @@ __global__ void __launch_bounds__(NT) kf_backward(
 }
 
 // out[i] = sum over g of partial[g][i], fixed order: 32 parameters per block,
-// 8 slices of the workgroup partials per parameter summed in index order, then
-// the slices combined in index order.
-__global__ void __launch_bounds__(256) kf_reduce(int G, int P, const float* __restrict__ partial,
-                                                 float* __restrict__ out) {
-  __shared__ float sh[8][33];
-  const int col = threadIdx.x & 31, sl = threadIdx.x >> 5;
-  const int i = blockIdx.x * 32 + col;
+// Sum of the G workgroup partials of P parameters: a block of 16 waves covers
+// 64 parameters; wave s sums partials [G s / 16, G (s + 1) / 16) in index order
+// (loads unrolled, so several are in flight), then the 16 slice sums are
+// combined in index order.  The order depends on G and P only: deterministic.
+constexpr int kRedCols = 64, kRedSlices = 16;
+__global__ void __launch_bounds__(kRedCols * kRedSlices) kf_reduce(int G, int P,
+                                                                  const float* __restrict__ partial,
+                                                                  float* __restrict__ out) {
+  __shared__ float sh[kRedSlices][kRedCols + 1];
+  const int col = threadIdx.x % kRedCols, sl = threadIdx.x / kRedCols;
+  const int i = blockIdx.x * kRedCols + col;
   float acc = 0.f;
   if (i < P) {
-    const int g0 = (int)((long)G * sl / 8), g1 = (int)((long)G * (sl + 1) / 8);
+    const int g0 = (int)((long)G * sl / kRedSlices), g1 = (int)((long)G * (sl + 1) / kRedSlices);
+#pragma unroll 8
     for (int g = g0; g < g1; ++g) acc += partial[(size_t)g * P + i];
   }
   sh[sl][col] = acc;
@@ -721,7 +726,7 @@ __global__ void __launch_bounds__(256) kf_reduce(int G, int P, const float* __re
   if (sl == 0 && i < P) {
     float r = sh[0][col];
 #pragma unroll
-    for (int q = 1; q < 8; ++q) r += sh[q][col];
+    for (int q = 1; q < kRedSlices; ++q) r += sh[q][col];
     out[i] = r;
   }
 }
@@ -809,7 +814,8 @@ int32_t launch_backward(const FlowGeom& g, const float* params, int B, const flo
                        (int)g.off_b1, (int)g.off_b2, (int)g.off_b3, (int)g.off_W1, (int)g.off_W2,
                        (int)g.off_W3, g.frozen_parity(l), g.final_tanh, (float)(-g_logq), B,
                        saved + (size_t)l * BV, gy, gx, partial);
-    hipLaunchKernelGGL(kf_reduce, dim3((Cfg::P_LAYER + 31) / 32), dim3(256), 0, st, grid,
+    hipLaunchKernelGGL(kf_reduce, dim3((Cfg::P_LAYER + kRedCols - 1) / kRedCols),
+                       dim3(kRedCols * kRedSlices), 0, st, grid,
                        Cfg::P_LAYER, partial, g_params + (size_t)l * g.P_layer);
     gy = gx;
     which ^= 1;
