@@ -32,6 +32,14 @@ Parameter layout (shared data contract): per layer W1[C][1][T], b1[C],
 W2[C][C][T], b2[C], W3[2][C][T], b3[2]; taps row-major over delta in
 {-1,0,1}^dim, axis 0 slowest.
 
+Emulated storage precision (emulate = "fp32" or "bf16"; None is plain FP64):
+every convolution's operands -- the input tensor and the weights, in the
+forward and in the adjoint -- are rounded to that precision, the field (and its
+gradient) is rounded to FP32 after each layer, and the weight and bias
+gradients are accumulated in FP32; the convolutions' own sums, biases, tanh,
+exp, s, t and log-det stay FP64.  Used only to size the parity tolerances of
+implementations that store and accumulate so.
+
 Pinned by: identity and pure-shift flows, a uniform-scale flow whose q is a known
 Gaussian (importance-sampling estimate of a free-field ln Z), invertibility,
 brute-force Jacobian determinants on L <= 4, one-hot convolution orientation,
@@ -47,6 +55,7 @@ import numpy as np
 
 from .action import action as _action, force as _force
 from .prior import log_prior
+from .rounding import ROUNDERS, to_fp32
 
 LEAKY_SLOPE = 0.01
 
@@ -164,26 +173,38 @@ def frozen_mask(fs: FlowShape, layer: int) -> np.ndarray:
     return (parity(fs) == (layer + fs.parity0) % 2).astype(np.float64)
 
 
-def net(x, lay, mF, fs: FlowShape):
+def _identity(a):
+    return a
+
+
+def _rounders(emulate):
+    """(operand rounding, field rounding) for an emulated storage precision."""
+    if emulate is None:
+        return _identity, _identity
+    return ROUNDERS[emulate], to_fp32
+
+
+def net(x, lay, mF, fs: FlowShape, emulate=None):
     """s/t network of one layer.  Returns (a1, h1, a2, h2, o, s, t)."""
+    R, _ = _rounders(emulate)
     W1, b1, W2, b2, W3, b3 = lay
     h0 = (x * mF)[:, None]
-    a1 = conv(h0, W1, b1, fs.dim)
+    a1 = conv(R(h0), R(W1), b1, fs.dim)
     h1 = leaky(a1)
-    a2 = conv(h1, W2, b2, fs.dim)
+    a2 = conv(R(h1), R(W2), b2, fs.dim)
     h2 = leaky(a2)
-    o = conv(h2, W3, b3, fs.dim)
+    o = conv(R(h2), R(W3), b3, fs.dim)
     s = np.tanh(o[:, 0]) if fs.final_tanh else o[:, 0]
     t = o[:, 1]
     return a1, h1, a2, h2, o, s, t
 
 
-def coupling_forward(x, lay, layer: int, fs: FlowShape):
+def coupling_forward(x, lay, layer: int, fs: FlowShape, emulate=None):
     """One layer in the sampling direction.  Returns (y, sum_A s per sample)."""
     mF = frozen_mask(fs, layer)
     mA = 1.0 - mF
-    *_, s, t = net(x, lay, mF, fs)
-    y = np.where(mA > 0, x * np.exp(s) + t, x)
+    *_, s, t = net(x, lay, mF, fs, emulate)
+    y = _rounders(emulate)[1](np.where(mA > 0, x * np.exp(s) + t, x))
     ax = tuple(range(1, x.ndim))
     return y, np.sum(mA * s, axis=ax)
 
@@ -203,14 +224,14 @@ def as_lattice(z, fs: FlowShape):
     return z.reshape((z.shape[0],) + fs.lattice)
 
 
-def flow_forward(params, z, fs: FlowShape, return_saved: bool = False):
+def flow_forward(params, z, fs: FlowShape, return_saved: bool = False, emulate=None):
     """phi = F^{-1}(z) with log q.  Returns dict(phi, logdet, logr, logq[, saved])."""
     layers = unpack(params, fs)
     x = as_lattice(z, fs)
     logdet = np.zeros(x.shape[0])
     saved = [x]
     for l, lay in enumerate(layers):
-        x, ld = coupling_forward(x, lay, l, fs)
+        x, ld = coupling_forward(x, lay, l, fs, emulate)
         logdet = logdet + ld
         saved.append(x)
     logr = log_prior(z)
@@ -243,7 +264,7 @@ def kl_loss(params, z, fs: FlowShape, m2, lam) -> float:
     return float(np.mean(f["logq"] + S))
 
 
-def flow_vjp(params, z, fs: FlowShape, g_phi, g_logq):
+def flow_vjp(params, z, fs: FlowShape, g_phi, g_logq, emulate=None):
     """Vector-Jacobian product of (phi, log q) = flow_forward(params, z) w.r.t. (params, z).
 
     g_phi: [B, *lattice] or [B, V]; g_logq: [B] or scalar.  Returns (g_params packed, g_z [B, V]).
@@ -251,7 +272,8 @@ def flow_vjp(params, z, fs: FlowShape, g_phi, g_logq):
     from the layer's input field.
     """
     layers = unpack(params, fs)
-    f = flow_forward(params, z, fs, return_saved=True)
+    R, RF = _rounders(emulate)
+    f = flow_forward(params, z, fs, return_saved=True, emulate=emulate)
     saved = f["saved"]
     B = saved[0].shape[0]
     g_logq = np.broadcast_to(np.asarray(g_logq, dtype=np.float64), (B,))
@@ -264,30 +286,42 @@ def flow_vjp(params, z, fs: FlowShape, g_phi, g_logq):
         x = saved[l]
         mF = frozen_mask(fs, l)
         mA = 1.0 - mF
-        a1, h1, a2, h2, o, s, t = net(x, layers[l], mF, fs)
+        a1, h1, a2, h2, o, s, t = net(x, layers[l], mF, fs, emulate)
         es = np.exp(s)
         g_y = gx
         g_t = mA * g_y
         g_s = mA * (g_y * x * es + g_ld.reshape(shp))
         g_o0 = g_s * (1.0 - s * s) if fs.final_tanh else g_s
         g_o = np.stack([g_o0, g_t], axis=1)
-        dW3, db3 = conv_weight_grad(g_o, h2, fs.dim)
-        g_a2 = conv_transpose(g_o, W3, fs.dim) * leaky_grad(a2)
-        dW2, db2 = conv_weight_grad(g_a2, h1, fs.dim)
-        g_a1 = conv_transpose(g_a2, W2, fs.dim) * leaky_grad(a1)
+        dW3, db3 = _weight_grad(g_o, h2, fs.dim, R)
+        g_a2 = conv_transpose(R(g_o), R(W3), fs.dim) * leaky_grad(a2)
+        dW2, db2 = _weight_grad(g_a2, h1, fs.dim, R)
+        g_a1 = conv_transpose(R(g_a2), R(W2), fs.dim) * leaky_grad(a1)
         h0 = (x * mF)[:, None]
-        dW1, db1 = conv_weight_grad(g_a1, h0, fs.dim)
-        g_h0 = conv_transpose(g_a1, W1, fs.dim)[:, 0]
-        gx = np.where(mA > 0, g_y * es, g_y + mF * g_h0)
+        dW1, db1 = _weight_grad(g_a1, h0, fs.dim, R)
+        g_h0 = conv_transpose(R(g_a1), R(W1), fs.dim)[:, 0]
+        gx = RF(np.where(mA > 0, g_y * es, g_y + mF * g_h0))
         grads[l] = (dW1, db1, dW2, db2, dW3, db3)
     g_z = gx.reshape(B, -1) - g_logq[:, None] * saved[0].reshape(B, -1)   # d log r / dz = -z
     return pack(grads), g_z
 
 
-def loss_gradient(params, z, fs: FlowShape, m2, lam):
+def _weight_grad(g, u, dim: int, R):
+    """conv_weight_grad; when emulating a storage precision, the weight gradient
+    from rounded operands and, like the bias gradient (a plain sum of the
+    unrounded g), accumulated in FP32 by numpy's float32 reductions."""
+    if R is _identity:
+        return conv_weight_grad(g, u, dim)
+    f32 = np.float32
+    dW, _ = conv_weight_grad(R(g).astype(f32), R(u).astype(f32), dim)
+    db = np.asarray(g, f32).sum(axis=tuple(i for i in range(g.ndim) if i != 1))
+    return dW, db.astype(np.float64)
+
+
+def loss_gradient(params, z, fs: FlowShape, m2, lam, emulate=None):
     """Gradient of the batch-mean reverse-KL loss w.r.t. the packed parameters, z fixed."""
-    f = flow_forward(params, z, fs)
+    f = flow_forward(params, z, fs, emulate=emulate)
     B = f["phi"].shape[0]
     g_phi = _force(f["phi"], m2, lam, fs.dim) / B
-    g_params, _ = flow_vjp(params, z, fs, g_phi, 1.0 / B)
+    g_params, _ = flow_vjp(params, z, fs, g_phi, 1.0 / B, emulate=emulate)
     return g_params
