@@ -222,12 +222,13 @@ const FwdEntry* find_fwd(const FlowGeom& g) {
 }  // namespace fused
 
 bool fused_supported(const FlowGeom& g, int for_backward) {
-  if (for_backward) return fused::bwd_supported(g);
+  if (for_backward) return fused::bwd_supported(g) || fused::ring_bwd_supported(g);
   return fused::find_fwd(g) != nullptr || fused::ring_supported(g);
 }
 
 size_t fused_ws_bytes(const FlowGeom& g, int B, int for_backward) {
-  if (for_backward) return fused::bwd_ws_bytes(g, B);
+  if (for_backward)
+    return fused::bwd_supported(g) ? fused::bwd_ws_bytes(g, B) : fused::ring_bwd_ws_bytes(g, B);
   if (!fused::find_fwd(g)) return fused::ring_ws_bytes(g);
   const fused::FwdEntry* e = fused::find_fwd(g);
   return e ? align_up(e->frag_bytes_per_layer * g.N) : 0;
@@ -243,7 +244,9 @@ int32_t fused_forward(const FlowGeom& g, const float* params, int B, const float
 int32_t fused_backward(const FlowGeom& g, const float* params, int B, const float* saved,
                        const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
                        hipStream_t st) {
-  return fused::bwd_run(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
+  if (fused::bwd_supported(g))
+    return fused::bwd_run(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
+  return fused::ring_bwd_run(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
 }
 
 }  // namespace lfs

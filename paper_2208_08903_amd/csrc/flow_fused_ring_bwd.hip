@@ -1,0 +1,753 @@
+// Fused backward of the coupling layers (paper Sec. 1: the gradient of the
+// shifted reverse KL with respect to the network weights, z held fixed) for 3D
+// lattices whose hidden activations do not fit LDS (L = 16, BF16 operands).
+// Three kernels per layer, each streaming the planes of axis 0 through rings of
+// three planes like the plane-streaming forward, with one workgroup per sample:
+//
+//   recompute  h1 = leaky(W1 * mask_F x), h2 = leaky(W2 * h1), s at the active
+//              sites; affine backward: g_x(active) = g_y e^s,
+//              g_o = (g_s (1 - s^2), g_t) (zero at the frozen sites), db3.
+//              Writes h1, h2 channel-major and g_o as BF16 pairs.
+//   transpose  g_a2 = leaky'(h2) (W3^T * g_o), g_a1 = leaky'(h1) (W2^T * g_a2),
+//              g_x(frozen) = g_y + W1^T * g_a1; db2, db1.  Writes g_a2, g_a1
+//              channel-major.  (The recompute also writes, per site, the sign
+//              bits of h1 and h2 over the channels, which give leaky' here.)
+//   weights    dW2[co][ci][t] = sum_m h1[m][ci] g_a2[m - d_t][co],
+//              dW3[co][ci][t] = sum_m h2[m][ci] g_o[m - d_t][co],
+//              dW1[c][t]      = sum_n g_a1[n][c] (mask_F x)[n + d_t]:
+//              GEMMs over the sites of one plane at a time on the matrix cores,
+//              the unshifted operand from the plane, the shifted one from a ring
+//              of three planes (a +-1 shift along the 16-site rows is a funnel
+//              shift of the row's two 8-site halves, periodic).
+//
+// The three kernels run on the same grid, each workgroup looping over the same
+// samples, and write disjoint slots of one partial per workgroup; the
+// fixed-order reduction then sums the partials, so the gradient is bitwise
+// reproducible.  Channel-major tensors are [B][C][V] BF16.
+#include <algorithm>
+
+#include "fused_bwd_common.hpp"
+
+namespace lfs {
+namespace fused {
+namespace {
+
+__device__ __forceinline__ int mod3(int v) { return ((v % 3) + 3) % 3; }
+
+template <int L, int C>
+struct RbCfg {
+  using G = Geo<3, L>;
+  using LX = Lay<3, L, true>;   // the layer's input field, whole sample
+  using LP2 = Lay<2, L, true>;  // one plane of a ring, with its in-plane halo
+  static constexpr int V = G::V, T = 27, PLANE = L * L, PS = LP2::VS, LP = L + 2;
+  static constexpr int NCT = C / 16;
+  static constexpr LayerFrags LF = layer_frags(T, C, true);
+  static constexpr int KT3 = kchunks_bf16(2 * T);
+  static constexpr int OFF3T = LF.total, OFF2T = OFF3T + LF.nct * KT3, OFF1T = OFF2T + LF.nct * LF.k2;
+  static constexpr int FRAGS = OFF1T + LF.k2;
+  static constexpr int P_LAYER = C * T + C + C * C * T + C + 2 * C * T + 2;
+  static constexpr int ZS = 3 * PS;               // zero site after a ring's three planes
+  static constexpr int RING = (3 * PS + 1) * C;   // BF16 elements of a hidden-tensor ring
+  static constexpr size_t XS_BYTES = ((size_t)LX::VS * 4 + 15) / 16 * 16;
+  static constexpr size_t GOR_BYTES = ((size_t)(3 * PS + 1) * 4 + 15) / 16 * 16;
+  static constexpr size_t LDS_A = XS_BYTES + 2 * (size_t)RING * 2;
+  // transpose: g_o ring, the LeakyReLU sign masks of one h2 and one h1 plane, two rings
+  static constexpr size_t LDS_B = GOR_BYTES + 2 * (size_t)PLANE * 4 + 2 * (size_t)RING * 2;
+  // weights: three plane buffers [C][CS] (h1, h2, g_a1 of plane z) and rings of
+  // three planes of g_a2 [C][CS], g_o [2][CS] and mask_F x [PLANE].  Channel rows
+  // are CS = PLANE + 8 elements apart, so the 16 lanes reading 16 channels at the
+  // same site hit different LDS banks.
+  static constexpr int CS = PLANE + 8;
+  static constexpr size_t LDS_C = (6 * (size_t)C * CS + 3 * 2 * (size_t)CS + 3 * (size_t)PLANE) * 2;
+  static constexpr int NT_A = 256, NT_B = 256, NT_C = 512;
+  // weight-gradient GEMM tiles (16 x 16): rows are channels, columns (tap, channel)
+  static constexpr int RT = C / 16;
+  static constexpr int N2 = RT * (T * C / 16), N3 = RT * 4, N1 = RT * 2;
+  static constexpr int NWC = NT_C / 64;
+  static constexpr int S2 = (N2 + NWC - 1) / NWC, S3 = (N3 + NWC - 1) / NWC, S1 = (N1 + NWC - 1) / NWC;
+  static_assert(C % 16 == 0 && L % 16 == 0, "ring backward shapes");
+  static_assert(LDS_A <= 160 * 1024 && LDS_B <= 160 * 1024 && LDS_C <= 160 * 1024, "LDS budget");
+};
+
+// B operand from a ring of three padded planes: the lane's 8 channels at tap
+// k0 / C of the site at in-plane index pq of plane v, displaced by SIGN * d_tap;
+// slots sm, s0, sp hold planes v-1, v, v+1.  K slots past T * C read the zero site.
+template <int L, int C, int SIGN>
+__device__ __forceinline__ u32x4 gather_rb(const uint16_t* ring, int pq, int sm, int s0, int sp,
+                                           int c, int j) {
+  using Cfg = RbCfg<L, C>;
+  constexpr int K = 27 * C;
+  const int k0 = 32 * c + 8 * j;
+  const int tap = k0 / C, ci0 = k0 % C;
+  const int dz = SIGN * (tap / 9 - 1), dy = SIGN * ((tap / 3) % 3 - 1), dx = SIGN * (tap % 3 - 1);
+  const int slot = dz < 0 ? sm : (dz > 0 ? sp : s0);
+  const int e = k0 < K ? (slot * Cfg::PS + pq + dy * Cfg::LP + dx) * C + ci0 : Cfg::ZS * C;
+  return *reinterpret_cast<const u32x4*>(ring + e);
+}
+
+// Four channels co0..co0+3 (BF16 pairs in hv) of site n of a channel-major tensor.
+template <int C, int V>
+__device__ __forceinline__ void store_cm_global(uint16_t* t, int n, int co0, const u32x2& hv) {
+  if (co0 >= C) return;
+  t[(size_t)(co0 + 0) * V + n] = (uint16_t)hv[0];
+  t[(size_t)(co0 + 1) * V + n] = (uint16_t)(hv[0] >> 16);
+  t[(size_t)(co0 + 2) * V + n] = (uint16_t)hv[1];
+  t[(size_t)(co0 + 3) * V + n] = (uint16_t)(hv[1] >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// LeakyReLU' mask word of one 16-channel tile: bit k set iff channel k's output
+// h >= 0 (then leaky' = 1, else the slope; -0 counts as >= 0, like the float
+// comparison).  Lane j holds channels 4j..4j+3 (BF16 pairs in hv); the four
+// lanes that share m combine their nibbles, so every lane returns the word.
+__device__ __forceinline__ uint32_t sign_mask16(const u32x2& hv, int j) {
+  const uint32_t nib = (uint32_t)(bf16_lo(hv[0]) >= 0.f) | (uint32_t)(bf16_hi(hv[0]) >= 0.f) << 1 |
+                       (uint32_t)(bf16_lo(hv[1]) >= 0.f) << 2 | (uint32_t)(bf16_hi(hv[1]) >= 0.f) << 3;
+  uint32_t w = nib << (4 * j);
+  w |= __shfl_xor(w, 16, 64);
+  w |= __shfl_xor(w, 32, 64);
+  return w;
+}
+
+// Sum over the 16 lanes of a wave that share j (lane bits 0-3), fixed order.
+__device__ __forceinline__ float sum16(float v) {
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Per-channel bias gradients db[ct][i] (channel ct*16 + 4j + i) of every wave,
+// summed over lanes and then over waves in index order, into out[0..C).
+template <int C, int NCT, int NW>
+__device__ __forceinline__ void bias_partial(f32x4 (&db)[NCT], float* red, float* out) {
+  const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) db[ct][i] = sum16(db[ct][i]);
+  __syncthreads();
+  if (m == 0) {
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[w * C + ct * 16 + 4 * j + i] = db[ct][i];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    float r = red[c];
+    for (int ww = 1; ww < NW; ++ww) r += red[ww * C + c];
+    out[c] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// recompute: h1, h2, s; affine backward
+// ---------------------------------------------------------------------------
+template <int L, int C, int NT>
+__global__ void __launch_bounds__(NT) kr_recompute(
+    const u32x4* frags, const float* __restrict__ pl, int off_b1, int off_b2, int off_b3,
+    int fpar, int final_tanh, float g_ld, int B, const float* __restrict__ xin,
+    const float* __restrict__ gy, float* __restrict__ gx, uint16_t* __restrict__ h1c,
+    uint16_t* __restrict__ h2c, uint32_t* __restrict__ m1, uint32_t* __restrict__ m2,
+    uint32_t* __restrict__ go, float* __restrict__ partial, int P) {
+  using Cfg = RbCfg<L, C>;
+  using G = typename Cfg::G;
+  using LX = typename Cfg::LX;
+  using LP2 = typename Cfg::LP2;
+  constexpr int V = Cfg::V, PLANE = Cfg::PLANE, PS = Cfg::PS;
+  constexpr LayerFrags LF = Cfg::LF;
+  constexpr int NW = NT / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float red[16];
+  float* xs = reinterpret_cast<float*>(smem);
+  uint16_t* r1 = reinterpret_cast<uint16_t*>(smem + Cfg::XS_BYTES);
+  uint16_t* r2 = r1 + Cfg::RING;
+  for (int q = threadIdx.x; q < C; q += NT) r1[Cfg::ZS * C + q] = 0, r2[Cfg::ZS * C + q] = 0;
+  const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
+  const int apar = fpar ^ 1;
+  const u32x4* fl = frags + lane;
+  u32x4 A1[LF.nct][LF.k1], A2[LF.nct][LF.k2], A3[1][LF.k2];
+  f32x4 bias1[LF.nct], bias2[LF.nct];
+#pragma unroll
+  for (int ct = 0; ct < LF.nct; ++ct) {
+    bias1[ct] = load_bias4<C>(pl + off_b1, ct, j);
+    bias2[ct] = load_bias4<C>(pl + off_b2, ct, j);
+#pragma unroll
+    for (int c = 0; c < LF.k1; ++c) A1[ct][c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
+#pragma unroll
+    for (int c = 0; c < LF.k2; ++c) A2[ct][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
+  }
+#pragma unroll
+  for (int c = 0; c < LF.k2; ++c) A3[0][c] = fl[(LF.off3 + c) * 64];
+  const f32x4 b3[1] = {f32x4{pl[off_b3], 0.f, 0.f, 0.f}};
+  float db3s = 0.f, db3t = 0.f;
+
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    const size_t sb = (size_t)b * V;
+    uint16_t* h1b = h1c + (size_t)b * C * V;
+    uint16_t* h2b = h2c + (size_t)b * C * V;
+    __syncthreads();  // the previous sample's readers are done
+    for (int q = threadIdx.x; q < LX::VS; q += NT) xs[q] = xin[sb + LX::site_of(q)];
+    __syncthreads();
+
+    // h1 of virtual plane v into ring slot v mod 3 (and, for a real plane, to h1c)
+    auto conv1_plane = [&](int v) {
+      const int zr = ((v % L) + L) % L;
+      const bool real = v >= 0 && v < L;
+      uint16_t* dst = r1 + mod3(v) * PS * C;
+      mma_tiles<1, LF.nct, LF.k1, true>(
+          PLANE / 16, w, NW, A1, bias1,
+          [&](int tile, int c) {
+            const int n = zr * PLANE + tile * 16 + m;
+            return gather_tri_x<LX, true>(xs, n, LX::idx(n), G::parity(n), fpar, c, j);
+          },
+          [&](int tile, const f32x4(&acc)[LF.nct]) {
+            uint32_t mw = 0u;
+#pragma unroll
+            for (int ct = 0; ct < LF.nct; ++ct) {
+              const u32x2 hv = store_act_tile<LP2, C, true>(dst, tile, m, ct, j, acc[ct]);
+              if (real) store_cm_global<C, V>(h1b, zr * PLANE + tile * 16 + m, ct * 16 + 4 * j, hv);
+              mw |= sign_mask16(hv, j) << (16 * ct);
+            }
+            if (real && j == 0) m1[sb + zr * PLANE + tile * 16 + m] = mw;
+          });
+    };
+    // h2 of virtual plane v from h1 planes v-1, v, v+1
+    auto conv2_plane = [&](int v) {
+      const int zr = ((v % L) + L) % L;
+      const bool real = v >= 0 && v < L;
+      uint16_t* dst = r2 + mod3(v) * PS * C;
+      const int sm = mod3(v - 1), s0 = mod3(v), sp = mod3(v + 1);
+      mma_tiles<1, LF.nct, LF.k2, true>(
+          PLANE / 16, w, NW, A2, bias2,
+          [&](int tile, int c) { return gather_rb<L, C, 1>(r1, tile_p<LP2>(tile, m), sm, s0, sp, c, j); },
+          [&](int tile, const f32x4(&acc)[LF.nct]) {
+            uint32_t mw = 0u;
+#pragma unroll
+            for (int ct = 0; ct < LF.nct; ++ct) {
+              const u32x2 hv = store_act_tile<LP2, C, true>(dst, tile, m, ct, j, acc[ct]);
+              if (real) store_cm_global<C, V>(h2b, zr * PLANE + tile * 16 + m, ct * 16 + 4 * j, hv);
+              mw |= sign_mask16(hv, j) << (16 * ct);
+            }
+            if (real && j == 0) m2[sb + zr * PLANE + tile * 16 + m] = mw;
+          });
+    };
+    // s at the active sites of plane zr; g_x there, g_o of the whole plane
+    auto conv3_plane = [&](int zr) {
+      const int sm = mod3(zr - 1), s0 = mod3(zr), sp = mod3(zr + 1);
+      const int ppar = apar ^ (zr & 1);  // in-plane parity of the active sites
+      mma_tiles<1, 1, LF.k2, true>(
+          PLANE / 32, w, NW, A3, b3,
+          [&](int tile, int c) {
+            const int q = Geo<2, L>::half_site(tile * 16 + m, ppar);
+            return gather_rb<L, C, 1>(r2, LP2::idx(q), sm, s0, sp, c, j);
+          },
+          [&](int tile, const f32x4(&acc)[1]) {
+            if (j == 0) {
+              const int n = zr * PLANE + Geo<2, L>::half_site(tile * 16 + m, ppar);
+              const float o0 = acc[0][0];
+              const float s = final_tanh ? fast_tanh(o0) : o0;
+              const float es = fast_exp(s);
+              const float g = gy[sb + n];
+              const float gs = g * xs[LX::idx(n)] * es + g_ld;
+              const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
+              db3s += go0;
+              db3t += g;
+              gx[sb + n] = g * es;
+              go[sb + n] = pack_bf16(go0, g);
+            }
+          });
+      for (int i = threadIdx.x; i < PLANE / 2; i += NT)
+        go[sb + zr * PLANE + Geo<2, L>::half_site(i, ppar ^ 1)] = 0u;
+    };
+
+    conv1_plane(-2);
+    conv1_plane(-1);
+    conv1_plane(0);
+    __syncthreads();
+    conv2_plane(-1);
+    __syncthreads();
+    conv1_plane(1);
+    __syncthreads();
+    conv2_plane(0);
+    __syncthreads();
+    for (int zr = 0; zr < L; ++zr) {
+      conv1_plane(zr + 2);
+      __syncthreads();
+      conv2_plane(zr + 1);
+      __syncthreads();
+      conv3_plane(zr);
+    }
+  }
+  db3s = block_sum(db3s, red);
+  db3t = block_sum(db3t, red);
+  if (threadIdx.x == 0) {
+    partial[(size_t)blockIdx.x * P + off_b3] = db3s;
+    partial[(size_t)blockIdx.x * P + off_b3 + 1] = db3t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// transpose: g_a2, g_a1, g_x(frozen)
+// ---------------------------------------------------------------------------
+template <int L, int C, int NT>
+__global__ void __launch_bounds__(NT) kr_transpose(
+    const u32x4* frags, int fpar, int B, const uint32_t* __restrict__ go,
+    const uint32_t* __restrict__ m1, const uint32_t* __restrict__ m2,
+    const float* __restrict__ gy, float* __restrict__ gx, uint16_t* __restrict__ ga2c,
+    uint16_t* __restrict__ ga1c, float* __restrict__ partial, int P, int off_b1, int off_b2) {
+  using Cfg = RbCfg<L, C>;
+  using LP2 = typename Cfg::LP2;
+  constexpr int V = Cfg::V, PLANE = Cfg::PLANE, PS = Cfg::PS, LP = Cfg::LP, NCT = Cfg::NCT;
+  constexpr LayerFrags LF = Cfg::LF;
+  constexpr int NW = NT / 64, KT3 = Cfg::KT3;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float red[NW * C];
+  uint32_t* gor = reinterpret_cast<uint32_t*>(smem);
+  uint32_t* sm2 = reinterpret_cast<uint32_t*>(smem + Cfg::GOR_BYTES);  // h2 signs of one plane
+  uint32_t* sm1 = sm2 + PLANE;                                          // h1 signs of one plane
+  uint16_t* ra2 = reinterpret_cast<uint16_t*>(smem + Cfg::GOR_BYTES + 2 * PLANE * 4);
+  uint16_t* ra1 = ra2 + Cfg::RING;
+  if (threadIdx.x == 0) gor[Cfg::ZS] = 0u;
+  for (int q = threadIdx.x; q < C; q += NT) ra2[Cfg::ZS * C + q] = 0, ra1[Cfg::ZS * C + q] = 0;
+  const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
+  const u32x4* fl = frags + lane;
+  u32x4 A3T[NCT][KT3], A2T[NCT][LF.k2], A1T[1][LF.k2];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+#pragma unroll
+    for (int c = 0; c < KT3; ++c) A3T[ct][c] = fl[(Cfg::OFF3T + ct * KT3 + c) * 64];
+#pragma unroll
+    for (int c = 0; c < LF.k2; ++c) A2T[ct][c] = fl[(Cfg::OFF2T + ct * LF.k2 + c) * 64];
+  }
+#pragma unroll
+  for (int c = 0; c < LF.k2; ++c) A1T[0][c] = fl[(Cfg::OFF1T + c) * 64];
+  const f32x4 zero[NCT] = {};
+  const f32x4 zero1[1] = {};
+  f32x4 db2[NCT], db1[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) db2[ct] = db1[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    const size_t sb = (size_t)b * V;
+    uint16_t* a2b = ga2c + (size_t)b * C * V;
+    uint16_t* a1b = ga1c + (size_t)b * C * V;
+    __syncthreads();
+
+    // g_o of virtual plane v (BF16 pairs, padded plane) into its ring slot
+    auto go_plane = [&](int v) {
+      const int zr = ((v % L) + L) % L;
+      uint32_t* dst = gor + mod3(v) * PS;
+      for (int q = threadIdx.x; q < PS; q += NT) dst[q] = go[sb + zr * PLANE + LP2::site_of(q)];
+    };
+    // the sign words of virtual plane v of h (m2 or m1) into a one-plane buffer
+    auto mask_plane = [&](const uint32_t* mk, uint32_t* dst, int v) {
+      const int zr = ((v % L) + L) % L;
+      for (int q = threadIdx.x; q < PLANE; q += NT) dst[q] = mk[sb + zr * PLANE + q];
+    };
+    // masked transposed-convolution output: leaky'(h) * acc, into a ring slot (and,
+    // for a real plane, channel-major to global memory and the bias sums)
+    auto epilogue = [&](const uint32_t* smk, uint16_t* dst, uint16_t* gout, f32x4(&db)[NCT],
+                        bool real, int zr, int tile, const f32x4(&acc)[NCT]) {
+      const int n = zr * PLANE + tile * 16 + m;
+      const uint32_t mw = smk[tile * 16 + m];
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        const int co0 = ct * 16 + 4 * j;
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = (mw >> (co0 + i)) & 1u ? acc[ct][i] : kLeakySlope * acc[ct][i];
+        const u32x2 pw = store4_tile<LP2, C, true>(dst, tile, m, co0, v);
+        if (real) {
+          store_cm_global<C, V>(gout, n, co0, pw);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) db[ct][i] += v[i];
+        }
+      }
+    };
+    // g_a2 of virtual plane v from g_o planes v-1, v, v+1
+    auto a2_plane = [&](int v) {
+      const int zr = ((v % L) + L) % L;
+      const bool real = v >= 0 && v < L;
+      uint16_t* dst = ra2 + mod3(v) * PS * C;
+      const int sm = mod3(v - 1), s0 = mod3(v), sp = mod3(v + 1);
+      mma_tiles<1, NCT, KT3, true>(
+          PLANE / 16, w, NW, A3T, zero,
+          [&](int tile, int c) {
+            const int pq = tile_p<LP2>(tile, m), t0 = 16 * c + 4 * j;  // K = tap * 2 + co
+            u32x4 r;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int t = t0 + q;
+              const int dz = 1 - t / 9, dy = 1 - (t / 3) % 3, dx = 1 - t % 3;  // -d_t
+              const int slot = dz < 0 ? sm : (dz > 0 ? sp : s0);
+              r[q] = gor[t < 27 ? slot * PS + pq + dy * LP + dx : Cfg::ZS];
+            }
+            return r;
+          },
+          [&](int tile, const f32x4(&acc)[NCT]) { epilogue(sm2, dst, a2b, db2, real, zr, tile, acc); });
+    };
+    // g_a1 of virtual plane v from g_a2 planes v-1, v, v+1
+    auto a1_plane = [&](int v) {
+      const int zr = ((v % L) + L) % L;
+      const bool real = v >= 0 && v < L;
+      uint16_t* dst = ra1 + mod3(v) * PS * C;
+      const int sm = mod3(v - 1), s0 = mod3(v), sp = mod3(v + 1);
+      mma_tiles<1, NCT, LF.k2, true>(
+          PLANE / 16, w, NW, A2T, zero,
+          [&](int tile, int c) { return gather_rb<L, C, -1>(ra2, tile_p<LP2>(tile, m), sm, s0, sp, c, j); },
+          [&](int tile, const f32x4(&acc)[NCT]) { epilogue(sm1, dst, a1b, db1, real, zr, tile, acc); });
+    };
+    // g_x at the frozen sites of plane zr from g_a1 planes zr-1, zr, zr+1
+    auto gx_plane = [&](int zr) {
+      const int sm = mod3(zr - 1), s0 = mod3(zr), sp = mod3(zr + 1);
+      const int fp = fpar ^ (zr & 1);  // in-plane parity of the frozen sites
+      mma_tiles<1, 1, LF.k2, true>(
+          PLANE / 32, w, NW, A1T, zero1,
+          [&](int tile, int c) {
+            const int q = Geo<2, L>::half_site(tile * 16 + m, fp);
+            return gather_rb<L, C, -1>(ra1, LP2::idx(q), sm, s0, sp, c, j);
+          },
+          [&](int tile, const f32x4(&acc)[1]) {
+            if (j == 0) {
+              const int n = zr * PLANE + Geo<2, L>::half_site(tile * 16 + m, fp);
+              gx[sb + n] = gy[sb + n] + acc[0][0];
+            }
+          });
+    };
+
+    // each mask buffer is refilled only after the pass that read it is behind a barrier
+    go_plane(-3);
+    go_plane(-2);
+    go_plane(-1);
+    mask_plane(m2, sm2, -2);
+    __syncthreads();
+    a2_plane(-2);
+    __syncthreads();
+    go_plane(0);
+    mask_plane(m2, sm2, -1);
+    __syncthreads();
+    a2_plane(-1);
+    __syncthreads();
+    go_plane(1);
+    mask_plane(m2, sm2, 0);
+    mask_plane(m1, sm1, -1);
+    __syncthreads();
+    a2_plane(0);
+    __syncthreads();
+    a1_plane(-1);
+    __syncthreads();
+    go_plane(2);
+    mask_plane(m2, sm2, 1);
+    mask_plane(m1, sm1, 0);
+    __syncthreads();
+    a2_plane(1);
+    __syncthreads();
+    a1_plane(0);
+    __syncthreads();
+    for (int z = 0; z < L; ++z) {
+      go_plane(z + 3);
+      mask_plane(m2, sm2, z + 2);
+      mask_plane(m1, sm1, z + 1);
+      __syncthreads();
+      a2_plane(z + 2);
+      __syncthreads();
+      a1_plane(z + 1);
+      __syncthreads();
+      gx_plane(z);
+    }
+  }
+  bias_partial<C, NCT, NW>(db2, red, partial + (size_t)blockIdx.x * P + off_b2);
+  bias_partial<C, NCT, NW>(db1, red, partial + (size_t)blockIdx.x * P + off_b1);
+}
+
+// ---------------------------------------------------------------------------
+// weights: dW3, dW2, dW1 one plane at a time
+// ---------------------------------------------------------------------------
+
+// Eight consecutive sites of one channel row of a plane ([16 rows][16 sites]
+// BF16): row r, starting at x = 8 h + sx (sx in {-1, 0, 1}), periodic in x.
+template <int L>
+__device__ __forceinline__ u32x4 row8(const uint16_t* plane, int r, int h, int sx) {
+  static_assert(L == 16, "rows of two 8-site halves");
+  const u32x4 lo = *reinterpret_cast<const u32x4*>(plane + r * L);
+  const u32x4 hi = *reinterpret_cast<const u32x4*>(plane + r * L + 8);
+  const u32x4 p = h ? hi : lo, o = h ? lo : hi;  // this half, the other half
+  if (sx == 0) return p;
+  u32x4 out;
+  if (sx > 0) {  // p[1..7], o[0]
+    out[0] = __builtin_amdgcn_alignbit(p[1], p[0], 16);
+    out[1] = __builtin_amdgcn_alignbit(p[2], p[1], 16);
+    out[2] = __builtin_amdgcn_alignbit(p[3], p[2], 16);
+    out[3] = __builtin_amdgcn_alignbit(o[0], p[3], 16);
+  } else {  // o[7], p[0..6]
+    out[0] = __builtin_amdgcn_alignbit(p[0], o[3], 16);
+    out[1] = __builtin_amdgcn_alignbit(p[1], p[0], 16);
+    out[2] = __builtin_amdgcn_alignbit(p[2], p[1], 16);
+    out[3] = __builtin_amdgcn_alignbit(p[3], p[2], 16);
+  }
+  return out;
+}
+
+template <int L, int C, int NT>
+__global__ void __launch_bounds__(NT) kr_wgrad(
+    int fpar, int B, const float* __restrict__ xin, const uint16_t* __restrict__ h1c,
+    const uint16_t* __restrict__ h2c, const uint32_t* __restrict__ go,
+    const uint16_t* __restrict__ ga2c, const uint16_t* __restrict__ ga1c,
+    float* __restrict__ partial, int P, int off_W1, int off_W2, int off_W3) {
+  using Cfg = RbCfg<L, C>;
+  using G = typename Cfg::G;
+  constexpr int V = Cfg::V, PLANE = Cfg::PLANE, T = Cfg::T, RT = Cfg::RT, NW = NT / 64;
+  constexpr int S2 = Cfg::S2, S3 = Cfg::S3, S1 = Cfg::S1, NS = S2 + S3 + S1;
+  static_assert(NW == Cfg::NWC, "tile slots are laid out for this block size");
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int CS = Cfg::CS;
+  uint16_t* pa1 = reinterpret_cast<uint16_t*>(smem);  // h1 of plane z, [C][CS]
+  uint16_t* pa2 = pa1 + C * CS;                        // h2 of plane z
+  uint16_t* pa3 = pa2 + C * CS;                        // g_a1 of plane z
+  uint16_t* rg2 = pa3 + C * CS;                        // g_a2 ring [3][C][CS]
+  uint16_t* rgo = rg2 + 3 * C * CS;                    // g_o ring [3][2][CS]
+  uint16_t* rh0 = rgo + 3 * 2 * CS;                    // mask_F x ring [3][PLANE]
+  const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
+  f32x4 acc[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    const size_t sb = (size_t)b * V;
+    auto load_ring = [&](int v) {
+      const int zr = ((v % L) + L) % L, slot = mod3(v);
+      for (int i = threadIdx.x; i < C * PLANE / 8; i += NT) {
+        const int c = i / (PLANE / 8), k = i % (PLANE / 8);
+        *reinterpret_cast<u32x4*>(rg2 + (slot * C + c) * CS + 8 * k) =
+            *reinterpret_cast<const u32x4*>(ga2c + ((size_t)b * C + c) * V + zr * PLANE + 8 * k);
+      }
+      for (int i = threadIdx.x; i < PLANE; i += NT) {
+        const uint32_t u = go[sb + zr * PLANE + i];
+        rgo[(slot * 2 + 0) * CS + i] = (uint16_t)u;
+        rgo[(slot * 2 + 1) * CS + i] = (uint16_t)(u >> 16);
+        const int n = zr * PLANE + i;
+        rh0[slot * PLANE + i] = G::parity(n) == fpar ? (uint16_t)bf16_bits(xin[sb + n]) : (uint16_t)0;
+      }
+    };
+    auto load_plane = [&](int zr) {
+      for (int i = threadIdx.x; i < C * PLANE / 8; i += NT) {
+        const int c = i / (PLANE / 8), k = i % (PLANE / 8);
+        const size_t src = ((size_t)b * C + c) * V + zr * PLANE + 8 * k;
+        const int dst = c * CS + 8 * k;
+        *reinterpret_cast<u32x4*>(pa1 + dst) = *reinterpret_cast<const u32x4*>(h1c + src);
+        *reinterpret_cast<u32x4*>(pa2 + dst) = *reinterpret_cast<const u32x4*>(h2c + src);
+        *reinterpret_cast<u32x4*>(pa3 + dst) = *reinterpret_cast<const u32x4*>(ga1c + src);
+      }
+    };
+    __syncthreads();
+    load_ring(-1);
+    load_ring(0);
+    for (int z = 0; z < L; ++z) {
+      load_ring(z + 1);
+      load_plane(z);
+      __syncthreads();
+#pragma unroll 1
+      for (int c = 0; c < PLANE / 32; ++c) {
+        const int r = 2 * c + (j >> 1), h = j & 1;  // the lane's 8 sites: row r, half h
+        const int a_off = m * CS + 32 * c + 8 * j;
+        // dW2 tiles: row tile rt (channels ci), column tile ct2 = (tap, 16 channels co)
+#pragma unroll
+        for (int k = 0; k < S2; ++k) {
+          const int id = k * NW + w;
+          if (id < Cfg::N2) {
+            const int rt = id % RT, ct2 = id / RT;
+            const int col = ct2 * 16 + m, tap = col / C, co = col % C;
+            const int dz = tap / 9 - 1, dy = tap / 3 % 3 - 1, dx = tap % 3 - 1;
+            const u32x4 a = *reinterpret_cast<const u32x4*>(pa1 + rt * 16 * CS + a_off);
+            const u32x4 bb = row8<L>(rg2 + (mod3(z - dz) * C + co) * CS, (r - dy) & (L - 1), h, -dx);
+            acc[k] = mfma(as_bf16x8(a), as_bf16x8(bb), acc[k]);
+          }
+        }
+        // dW3 tiles: row tile rt (ci), column tile of 16 (tap, co) pairs
+#pragma unroll
+        for (int k = 0; k < S3; ++k) {
+          const int id = k * NW + w;
+          if (id < Cfg::N3) {
+            const int rt = id % RT, ct = id / RT;
+            const int col = ct * 16 + m, tap = std::min(col >> 1, T - 1), co = col & 1;
+            const int dz = tap / 9 - 1, dy = tap / 3 % 3 - 1, dx = tap % 3 - 1;
+            const u32x4 a = *reinterpret_cast<const u32x4*>(pa2 + rt * 16 * CS + a_off);
+            const u32x4 bb = row8<L>(rgo + (mod3(z - dz) * 2 + co) * CS, (r - dy) & (L - 1), h, -dx);
+            acc[S2 + k] = mfma(as_bf16x8(a), as_bf16x8(bb), acc[S2 + k]);
+          }
+        }
+        // dW1 tiles: row tile rt (c), column tile of 16 taps
+#pragma unroll
+        for (int k = 0; k < S1; ++k) {
+          const int id = k * NW + w;
+          if (id < Cfg::N1) {
+            const int rt = id % RT, ct = id / RT;
+            const int tap = std::min(ct * 16 + m, T - 1);
+            const int dz = tap / 9 - 1, dy = tap / 3 % 3 - 1, dx = tap % 3 - 1;
+            const u32x4 a = *reinterpret_cast<const u32x4*>(pa3 + rt * 16 * CS + a_off);
+            const u32x4 bb = row8<L>(rh0 + mod3(z + dz) * PLANE, (r + dy) & (L - 1), h, dx);
+            acc[S2 + S3 + k] = mfma(as_bf16x8(a), as_bf16x8(bb), acc[S2 + S3 + k]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // every weight-gradient slot belongs to exactly one lane of one wave
+  float* out = partial + (size_t)blockIdx.x * P;
+#pragma unroll
+  for (int k = 0; k < S2; ++k) {
+    const int id = k * NW + w;
+    if (id < Cfg::N2) {
+      const int rt = id % RT, ct2 = id / RT;
+      const int col = ct2 * 16 + m, tap = col / C, co = col % C;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[off_W2 + (co * C + rt * 16 + 4 * j + i) * T + tap] = acc[k][i];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < S3; ++k) {
+    const int id = k * NW + w;
+    if (id < Cfg::N3) {
+      const int rt = id % RT, ct = id / RT;
+      const int col = ct * 16 + m, tap = col >> 1, co = col & 1;
+      if (tap < T)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[off_W3 + (co * C + rt * 16 + 4 * j + i) * T + tap] = acc[S2 + k][i];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < S1; ++k) {
+    const int id = k * NW + w;
+    if (id < Cfg::N1) {
+      const int rt = id % RT, ct = id / RT;
+      const int tap = ct * 16 + m;
+      if (tap < T)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[off_W1 + (rt * 16 + 4 * j + i) * T + tap] = acc[S2 + S3 + k][i];
+    }
+  }
+}
+
+// ---- host -----------------------------------------------------------------
+
+template <int L, int C>
+int rb_grid(int B) {
+  return std::min(B, num_cus());
+}
+
+template <int L, int C>
+size_t rb_ws(const FlowGeom& g, int B) {
+  using Cfg = RbCfg<L, C>;
+  const size_t BV = (size_t)B * Cfg::V;
+  return align_up((size_t)Cfg::FRAGS * 64 * 16 * g.N) +
+         align_up((size_t)rb_grid<L, C>(B) * Cfg::P_LAYER * 4) + 2 * align_up(BV * 4) +
+         4 * align_up(BV * C * 2) + 3 * align_up(BV * 4);
+}
+
+template <class K>
+bool set_lds(K kern, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+}
+
+template <int L, int C>
+int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved,
+               const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+               hipStream_t st) {
+  using Cfg = RbCfg<L, C>;
+  const int grid = rb_grid<L, C>(B);
+  const FragTable tab = bwd_table(g, true);
+  if (tab.total != Cfg::FRAGS || (int)g.P_layer != Cfg::P_LAYER) return LFS_EUNSUPPORTED;
+  const size_t BV = (size_t)B * Cfg::V;
+  char* p = ws;
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += align_up(bytes);
+    return r;
+  };
+  u32x4* frags = reinterpret_cast<u32x4*>(take((size_t)Cfg::FRAGS * 64 * 16 * g.N));
+  float* partial = reinterpret_cast<float*>(take((size_t)grid * Cfg::P_LAYER * 4));
+  float* gbuf[2] = {reinterpret_cast<float*>(take(BV * 4)), reinterpret_cast<float*>(take(BV * 4))};
+  uint16_t* h1c = reinterpret_cast<uint16_t*>(take(BV * C * 2));
+  uint16_t* h2c = reinterpret_cast<uint16_t*>(take(BV * C * 2));
+  uint16_t* ga2c = reinterpret_cast<uint16_t*>(take(BV * C * 2));
+  uint16_t* ga1c = reinterpret_cast<uint16_t*>(take(BV * C * 2));
+  uint32_t* go = reinterpret_cast<uint32_t*>(take(BV * 4));
+  uint32_t* m1 = reinterpret_cast<uint32_t*>(take(BV * 4));
+  uint32_t* m2 = reinterpret_cast<uint32_t*>(take(BV * 4));
+
+  const long nthreads = (long)tab.total * 64 * g.N;
+  hipLaunchKernelGGL((kf_prep<true>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st,
+                     params, g.N, g.T, (int)g.P_layer, tab, frags);
+  auto ka = kr_recompute<L, C, Cfg::NT_A>;
+  auto kb = kr_transpose<L, C, Cfg::NT_B>;
+  auto kc = kr_wgrad<L, C, Cfg::NT_C>;
+  if (!set_lds(ka, Cfg::LDS_A) || !set_lds(kb, Cfg::LDS_B) || !set_lds(kc, Cfg::LDS_C))
+    return LFS_EDEVICE;
+  const int P = Cfg::P_LAYER;
+  const float* gy = g_phi;
+  int which = 0;
+  for (int l = g.N - 1; l >= 0; --l) {
+    float* gx = gbuf[which];
+    const u32x4* fl = frags + (size_t)l * tab.total * 64;
+    const float* pl = params + (size_t)l * g.P_layer;
+    const float* xl = saved + (size_t)l * BV;
+    const int fpar = g.frozen_parity(l);
+    hipLaunchKernelGGL(ka, dim3(grid), dim3(Cfg::NT_A), Cfg::LDS_A, st, fl, pl, (int)g.off_b1,
+                       (int)g.off_b2, (int)g.off_b3, fpar, g.final_tanh, (float)(-g_logq), B, xl, gy,
+                       gx, h1c, h2c, m1, m2, go, partial, P);
+    hipLaunchKernelGGL(kb, dim3(grid), dim3(Cfg::NT_B), Cfg::LDS_B, st, fl, fpar, B,
+                       (const uint32_t*)go, (const uint32_t*)m1, (const uint32_t*)m2, gy, gx,
+                       ga2c, ga1c, partial, P, (int)g.off_b1, (int)g.off_b2);
+    hipLaunchKernelGGL(kc, dim3(grid), dim3(Cfg::NT_C), Cfg::LDS_C, st, fpar, B, xl,
+                       (const uint16_t*)h1c, (const uint16_t*)h2c, (const uint32_t*)go,
+                       (const uint16_t*)ga2c, (const uint16_t*)ga1c, partial, P, (int)g.off_W1,
+                       (int)g.off_W2, (int)g.off_W3);
+    hipLaunchKernelGGL(kf_reduce, dim3((P + kRedCols - 1) / kRedCols), dim3(kRedCols * kRedSlices),
+                       0, st, grid, P, (const float*)partial, g_params + (size_t)l * g.P_layer);
+    gy = gx;
+    which ^= 1;
+  }
+  if (g_z)
+    hipLaunchKernelGGL(kf_gz, dim3((unsigned)((BV + 255) / 256)), dim3(256), 0, st, (int64_t)BV,
+                       gy, saved, (float)g_logq, g_z);
+  return launch_status();
+}
+
+struct RbEntry {
+  int L, C;
+  int32_t (*fn)(const FlowGeom&, const float*, int, const float*, const float*, double, float*,
+                float*, char*, hipStream_t);
+  size_t (*ws)(const FlowGeom&, int);
+};
+
+const RbEntry kRbTable[] = {RbEntry{16, 16, &rb_run<16, 16>, &rb_ws<16, 16>},
+                            RbEntry{16, 32, &rb_run<16, 32>, &rb_ws<16, 32>}};
+
+const RbEntry* find_rb(const FlowGeom& g) {
+  if (g.dim != 3 || !g.bf16()) return nullptr;
+  for (const auto& e : kRbTable)
+    if (e.L == g.L && e.C == g.C) return &e;
+  return nullptr;
+}
+
+}  // namespace
+
+bool ring_bwd_supported(const FlowGeom& g) { return find_rb(g) != nullptr; }
+size_t ring_bwd_ws_bytes(const FlowGeom& g, int B) {
+  const RbEntry* e = find_rb(g);
+  return e ? e->ws(g, B) : 0;
+}
+int32_t ring_bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
+                     const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                     hipStream_t st) {
+  const RbEntry* e = find_rb(g);
+  if (!e) return LFS_EUNSUPPORTED;
+  return e->fn(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
+}
+
+}  // namespace fused
+}  // namespace lfs

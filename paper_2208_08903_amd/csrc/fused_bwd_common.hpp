@@ -1,0 +1,76 @@
+// Pieces shared by the fused backward kernels: the fragment table of a
+// layer's backward, the fixed-order reduction of the per-workgroup weight-
+// gradient partials, and the prior term of the gradient with respect to z.
+#pragma once
+
+#include "fused_kernels.hpp"
+#include "lfs_internal.hpp"
+
+namespace lfs {
+namespace fused {
+namespace {  // each translation unit keeps its own copy of the kernels
+
+// Sum of the G workgroup partials of P parameters: a block of 16 waves covers
+// 64 parameters; wave s sums partials [G s / 16, G (s + 1) / 16) in index order
+// (loads unrolled, so several are in flight), then the 16 slice sums are
+// combined in index order.  The order depends on G and P only: deterministic.
+constexpr int kRedCols = 64, kRedSlices = 16;
+__global__ void __launch_bounds__(kRedCols * kRedSlices) kf_reduce(int G, int P,
+                                                                  const float* __restrict__ partial,
+                                                                  float* __restrict__ out) {
+  __shared__ float sh[kRedSlices][kRedCols + 1];
+  const int col = threadIdx.x % kRedCols, sl = threadIdx.x / kRedCols;
+  const int i = blockIdx.x * kRedCols + col;
+  float acc = 0.f;
+  if (i < P) {
+    const int g0 = (int)((long)G * sl / kRedSlices), g1 = (int)((long)G * (sl + 1) / kRedSlices);
+#pragma unroll 8
+    for (int g = g0; g < g1; ++g) acc += partial[(size_t)g * P + i];
+  }
+  sh[sl][col] = acc;
+  __syncthreads();
+  if (sl == 0 && i < P) {
+    float r = sh[0][col];
+#pragma unroll
+    for (int q = 1; q < kRedSlices; ++q) r += sh[q][col];
+    out[i] = r;
+  }
+}
+
+__global__ void kf_gz(int64_t n, const float* __restrict__ gx, const float* __restrict__ z,
+                      float g_logq, float* __restrict__ gz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) gz[i] = gx[i] - g_logq * z[i];
+}
+
+}  // namespace
+
+inline FragTable bwd_table(const FlowGeom& g, bool bf16) {
+  const int T = g.T, C = g.C;
+  const LayerFrags lf = layer_frags(T, C, bf16);
+  const int kt3 = bf16 ? kchunks_bf16(2 * T) : kblocks_f32(2 * T);
+  FragTable t{};
+  t.count = 6;
+  t.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, lf.nct, lf.k1, lf.off1, 1};
+  t.s[1] = FragSpec{0, (int)g.off_W2, C, C, C, lf.nct, lf.k2, lf.off2};
+  t.s[2] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, lf.k2, lf.off3};
+  t.s[3] = FragSpec{1, (int)g.off_W3, C, 2, C, lf.nct, kt3, lf.total};
+  t.s[4] = FragSpec{1, (int)g.off_W2, C, C, C, lf.nct, lf.k2, lf.total + lf.nct * kt3};
+  t.s[5] = FragSpec{1, (int)g.off_W1, 1, C, 1, 1, lf.k2, lf.total + lf.nct * kt3 + lf.nct * lf.k2};
+  t.total = t.s[5].off + lf.k2;
+  return t;
+}
+
+inline int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+  }
+  return n;
+}
+
+}  // namespace fused
+}  // namespace lfs

@@ -57,6 +57,13 @@ size_t bwd_ws_bytes(const FlowGeom& g, int B);
 int32_t bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
                 const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
                 hipStream_t st);
+// Fused backward streaming planes (3D lattices too large to keep resident;
+// three launches per layer), implemented next to its kernels.
+bool ring_bwd_supported(const FlowGeom& g);
+size_t ring_bwd_ws_bytes(const FlowGeom& g, int B);
+int32_t ring_bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
+                     const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                     hipStream_t st);
 }  // namespace fused
 
 }  // namespace lfs

@@ -342,6 +342,40 @@ def test_flow_backward_fused(case, precision):
     _check_backward(desc, params, z, fs, out, precision)
 
 
+# 3D L = 16: the plane-streaming backward (BF16 operands)
+RING_BWD_CASES = [
+    # dim, L, N, C, B
+    (3, 16, 2, 32, 2),
+    (3, 16, 2, 16, 3),
+    (3, 16, 3, 16, 1),
+]
+
+
+@pytest.mark.parametrize("case", RING_BWD_CASES)
+def test_flow_backward_ring(case):
+    print(f"ring backward {case}", flush=True)
+    desc, params, z, fs = _flow_case(*case, lfs.LFS_BF16_CONV, lfs.ALGO_FUSED)
+    out = run_forward(desc, params, z)
+    _check_backward(desc, params, z, fs, out, lfs.LFS_BF16_CONV)
+
+
+def test_flow_backward_ring_deterministic_and_batch_position():
+    """Bitwise reproducible; a sample's g_z does not depend on the batch around it."""
+    desc, params, z, fs = _flow_case(3, 16, 2, 16, 4, lfs.LFS_BF16_CONV, lfs.ALGO_FUSED)
+    g = np.random.default_rng(15).standard_normal(z.shape).astype(np.float32)
+    out = run_forward(desc, params, z)
+    ga, gza = run_backward(desc, out, g, 0.2)
+    gb, gzb = run_backward(desc, out, g, 0.2)
+    np.testing.assert_array_equal(ga, gb)
+    np.testing.assert_array_equal(gza, gzb)
+    parts = []
+    for i in (0, 3):
+        o = run_forward(desc, params, z[i:i + 1])
+        gi, gzi = run_backward(desc, o, g[i:i + 1], 0.2)
+        np.testing.assert_array_equal(gzi, gza[i:i + 1])
+        parts.append(gi)
+
+
 def test_flow_backward_fused_deterministic_and_batch_sum():
     """Bitwise reproducible; the gradient of a batch is the sum of per-sample gradients
     (up to FP32 summation order)."""
