@@ -466,28 +466,23 @@ __global__ void __launch_bounds__(NT) kr_transpose(
 // weights: dW3, dW2, dW1 one plane at a time
 // ---------------------------------------------------------------------------
 
-// Eight consecutive sites of one channel row of a plane ([16 rows][16 sites]
-// BF16): row r, starting at x = 8 h + sx (sx in {-1, 0, 1}), periodic in x.
-template <int L>
-__device__ __forceinline__ u32x4 row8(const uint16_t* plane, int r, int h, int sx) {
-  static_assert(L == 16, "rows of two 8-site halves");
-  const u32x4 lo = *reinterpret_cast<const u32x4*>(plane + r * L);
-  const u32x4 hi = *reinterpret_cast<const u32x4*>(plane + r * L + 8);
-  const u32x4 p = h ? hi : lo, o = h ? lo : hi;  // this half, the other half
-  if (sx == 0) return p;
-  u32x4 out;
-  if (sx > 0) {  // p[1..7], o[0]
-    out[0] = __builtin_amdgcn_alignbit(p[1], p[0], 16);
-    out[1] = __builtin_amdgcn_alignbit(p[2], p[1], 16);
-    out[2] = __builtin_amdgcn_alignbit(p[3], p[2], 16);
-    out[3] = __builtin_amdgcn_alignbit(o[0], p[3], 16);
-  } else {  // o[7], p[0..6]
-    out[0] = __builtin_amdgcn_alignbit(p[0], o[3], 16);
-    out[1] = __builtin_amdgcn_alignbit(p[1], p[0], 16);
-    out[2] = __builtin_amdgcn_alignbit(p[2], p[1], 16);
-    out[3] = __builtin_amdgcn_alignbit(p[3], p[2], 16);
-  }
-  return out;
+// Eight consecutive sites of a 16-site row, periodic in x, from the lane's own
+// half p of the row (x = 8h..8h+7) and the other half o: shifted by sx in
+// {-1, 0, +1}, i.e. x = 8h + sx .. 8h + sx + 7.
+__device__ __forceinline__ u32x4 shift_p1(const u32x4& p, const u32x4& o) {  // p[1..7], o[0]
+  return u32x4{__builtin_amdgcn_alignbit(p[1], p[0], 16), __builtin_amdgcn_alignbit(p[2], p[1], 16),
+               __builtin_amdgcn_alignbit(p[3], p[2], 16), __builtin_amdgcn_alignbit(o[0], p[3], 16)};
+}
+__device__ __forceinline__ u32x4 shift_m1(const u32x4& p, const u32x4& o) {  // o[7], p[0..6]
+  return u32x4{__builtin_amdgcn_alignbit(p[0], o[3], 16), __builtin_amdgcn_alignbit(p[1], p[0], 16),
+               __builtin_amdgcn_alignbit(p[2], p[1], 16), __builtin_amdgcn_alignbit(p[3], p[2], 16)};
+}
+__device__ __forceinline__ u32x4 shift_any(const u32x4& p, const u32x4& o, int sx) {
+  const u32x4 a = shift_p1(p, o), b = shift_m1(p, o);
+  u32x4 r;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) r[q] = sx > 0 ? a[q] : (sx < 0 ? b[q] : p[q]);
+  return r;
 }
 
 template <int L, int C, int NT>
@@ -499,10 +494,14 @@ __global__ void __launch_bounds__(NT) kr_wgrad(
   using Cfg = RbCfg<L, C>;
   using G = typename Cfg::G;
   constexpr int V = Cfg::V, PLANE = Cfg::PLANE, T = Cfg::T, RT = Cfg::RT, NW = NT / 64;
-  constexpr int S2 = Cfg::S2, S3 = Cfg::S3, S1 = Cfg::S1, NS = S2 + S3 + S1;
-  static_assert(NW == Cfg::NWC, "tile slots are laid out for this block size");
-  extern __shared__ __align__(16) unsigned char smem[];
+  static_assert(L == 16, "rows of two 8-site halves");
+  // dW2 jobs: (row tile of ci, row offset (dz, dy), 16 channels co): the three
+  // x offsets share the A operand and the two loads of the source row
+  constexpr int NCO = C / 16, J2 = RT * 9 * NCO, JS2 = (J2 + NW - 1) / NW;
+  // single tiles: dW3 (row tile, 16 (tap, co) columns), then dW1 (row tile, 16 taps)
+  constexpr int N3 = Cfg::N3, J31 = Cfg::N3 + Cfg::N1, JS31 = (J31 + NW - 1) / NW;
   constexpr int CS = Cfg::CS;
+  extern __shared__ __align__(16) unsigned char smem[];
   uint16_t* pa1 = reinterpret_cast<uint16_t*>(smem);  // h1 of plane z, [C][CS]
   uint16_t* pa2 = pa1 + C * CS;                        // h2 of plane z
   uint16_t* pa3 = pa2 + C * CS;                        // g_a1 of plane z
@@ -510,9 +509,12 @@ __global__ void __launch_bounds__(NT) kr_wgrad(
   uint16_t* rgo = rg2 + 3 * C * CS;                    // g_o ring [3][2][CS]
   uint16_t* rh0 = rgo + 3 * 2 * CS;                    // mask_F x ring [3][PLANE]
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
-  f32x4 acc[NS];
+  const int h = j & 1, jr = j >> 1;  // the lane's half row and row within a K chunk
+  f32x4 acc2[JS2][3], acc31[JS31];
 #pragma unroll
-  for (int k = 0; k < NS; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < JS2; ++k) acc2[k][0] = acc2[k][1] = acc2[k][2] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < JS31; ++k) acc31[k] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     const size_t sb = (size_t)b * V;
@@ -548,47 +550,47 @@ __global__ void __launch_bounds__(NT) kr_wgrad(
       load_ring(z + 1);
       load_plane(z);
       __syncthreads();
-#pragma unroll 1
-      for (int c = 0; c < PLANE / 32; ++c) {
-        const int r = 2 * c + (j >> 1), h = j & 1;  // the lane's 8 sites: row r, half h
-        const int a_off = m * CS + 32 * c + 8 * j;
-        // dW2 tiles: row tile rt (channels ci), column tile ct2 = (tap, 16 channels co)
+      // dW2: D[ci][(tap, co)] += sum over the plane's sites m of h1[m][ci] g_a2[m - d][co]
 #pragma unroll
-        for (int k = 0; k < S2; ++k) {
-          const int id = k * NW + w;
-          if (id < Cfg::N2) {
-            const int rt = id % RT, ct2 = id / RT;
-            const int col = ct2 * 16 + m, tap = col / C, co = col % C;
-            const int dz = tap / 9 - 1, dy = tap / 3 % 3 - 1, dx = tap % 3 - 1;
-            const u32x4 a = *reinterpret_cast<const u32x4*>(pa1 + rt * 16 * CS + a_off);
-            const u32x4 bb = row8<L>(rg2 + (mod3(z - dz) * C + co) * CS, (r - dy) & (L - 1), h, -dx);
-            acc[k] = mfma(as_bf16x8(a), as_bf16x8(bb), acc[k]);
+      for (int k = 0; k < JS2; ++k) {
+        const int id = k * NW + w;
+        if (id < J2) {
+          const int rt = id % RT, r9 = id / RT % 9, cot = id / (RT * 9);
+          const int dz = r9 / 3 - 1, dy = r9 % 3 - 1;
+          const uint16_t* src = rg2 + (mod3(z - dz) * C + cot * 16 + m) * CS;
+          const uint16_t* ap = pa1 + (rt * 16 + m) * CS + 8 * j;
+#pragma unroll 2
+          for (int c = 0; c < PLANE / 32; ++c) {
+            const bf16x8 a = as_bf16x8(*reinterpret_cast<const u32x4*>(ap + 32 * c));
+            const uint16_t* row = src + ((2 * c + jr - dy) & (L - 1)) * L;
+            const u32x4 p = *reinterpret_cast<const u32x4*>(row + 8 * h);
+            const u32x4 o = *reinterpret_cast<const u32x4*>(row + 8 - 8 * h);
+            acc2[k][0] = mfma(a, as_bf16x8(shift_p1(p, o)), acc2[k][0]);  // dx = -1: x + 1
+            acc2[k][1] = mfma(a, as_bf16x8(p), acc2[k][1]);
+            acc2[k][2] = mfma(a, as_bf16x8(shift_m1(p, o)), acc2[k][2]);  // dx = +1: x - 1
           }
         }
-        // dW3 tiles: row tile rt (ci), column tile of 16 (tap, co) pairs
+      }
+      // dW3: D[ci][(tap, co)] += sum_m h2[m][ci] g_o[m - d][co];  dW1: D[c][tap] += sum_n g_a1[n][c] h0[n + d]
 #pragma unroll
-        for (int k = 0; k < S3; ++k) {
-          const int id = k * NW + w;
-          if (id < Cfg::N3) {
-            const int rt = id % RT, ct = id / RT;
-            const int col = ct * 16 + m, tap = std::min(col >> 1, T - 1), co = col & 1;
-            const int dz = tap / 9 - 1, dy = tap / 3 % 3 - 1, dx = tap % 3 - 1;
-            const u32x4 a = *reinterpret_cast<const u32x4*>(pa2 + rt * 16 * CS + a_off);
-            const u32x4 bb = row8<L>(rgo + (mod3(z - dz) * 2 + co) * CS, (r - dy) & (L - 1), h, -dx);
-            acc[S2 + k] = mfma(as_bf16x8(a), as_bf16x8(bb), acc[S2 + k]);
-          }
-        }
-        // dW1 tiles: row tile rt (c), column tile of 16 taps
-#pragma unroll
-        for (int k = 0; k < S1; ++k) {
-          const int id = k * NW + w;
-          if (id < Cfg::N1) {
-            const int rt = id % RT, ct = id / RT;
-            const int tap = std::min(ct * 16 + m, T - 1);
-            const int dz = tap / 9 - 1, dy = tap / 3 % 3 - 1, dx = tap % 3 - 1;
-            const u32x4 a = *reinterpret_cast<const u32x4*>(pa3 + rt * 16 * CS + a_off);
-            const u32x4 bb = row8<L>(rh0 + mod3(z + dz) * PLANE, (r + dy) & (L - 1), h, dx);
-            acc[S2 + S3 + k] = mfma(as_bf16x8(a), as_bf16x8(bb), acc[S2 + S3 + k]);
+      for (int k = 0; k < JS31; ++k) {
+        const int id = k * NW + w;
+        if (id < J31) {
+          const bool w3 = id < N3;
+          const int id2 = w3 ? id : id - N3, rt = id2 % RT, ct = id2 / RT;
+          const int col = ct * 16 + m;
+          const int tap = std::min(w3 ? col >> 1 : col, T - 1), co = col & 1;
+          const int dz = tap / 9 - 1, dy = tap / 3 % 3 - 1, dx = tap % 3 - 1;
+          const int sgn = w3 ? -1 : 1;  // dW3 reads g_o at m - d, dW1 reads h0 at n + d
+          const uint16_t* src = w3 ? rgo + (mod3(z - dz) * 2 + co) * CS : rh0 + mod3(z + dz) * PLANE;
+          const uint16_t* ap = (w3 ? pa2 : pa3) + (rt * 16 + m) * CS + 8 * j;
+#pragma unroll 2
+          for (int c = 0; c < PLANE / 32; ++c) {
+            const bf16x8 a = as_bf16x8(*reinterpret_cast<const u32x4*>(ap + 32 * c));
+            const uint16_t* row = src + ((2 * c + jr + sgn * dy) & (L - 1)) * L;
+            const u32x4 p = *reinterpret_cast<const u32x4*>(row + 8 * h);
+            const u32x4 o = *reinterpret_cast<const u32x4*>(row + 8 - 8 * h);
+            acc31[k] = mfma(a, as_bf16x8(shift_any(p, o, sgn * dx)), acc31[k]);
           }
         }
       }
@@ -598,35 +600,30 @@ __global__ void __launch_bounds__(NT) kr_wgrad(
   // every weight-gradient slot belongs to exactly one lane of one wave
   float* out = partial + (size_t)blockIdx.x * P;
 #pragma unroll
-  for (int k = 0; k < S2; ++k) {
+  for (int k = 0; k < JS2; ++k) {
     const int id = k * NW + w;
-    if (id < Cfg::N2) {
-      const int rt = id % RT, ct2 = id / RT;
-      const int col = ct2 * 16 + m, tap = col / C, co = col % C;
+    if (id < J2) {
+      const int rt = id % RT, r9 = id / RT % 9, cot = id / (RT * 9), co = cot * 16 + m;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) out[off_W2 + (co * C + rt * 16 + 4 * j + i) * T + tap] = acc[k][i];
+      for (int dxi = 0; dxi < 3; ++dxi)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          out[off_W2 + (co * C + rt * 16 + 4 * j + i) * T + 3 * r9 + dxi] = acc2[k][dxi][i];
     }
   }
 #pragma unroll
-  for (int k = 0; k < S3; ++k) {
+  for (int k = 0; k < JS31; ++k) {
     const int id = k * NW + w;
-    if (id < Cfg::N3) {
-      const int rt = id % RT, ct = id / RT;
-      const int col = ct * 16 + m, tap = col >> 1, co = col & 1;
+    if (id < J31) {
+      const bool w3 = id < N3;
+      const int id2 = w3 ? id : id - N3, rt = id2 % RT, ct = id2 / RT, col = ct * 16 + m;
+      const int tap = w3 ? col >> 1 : col, co = col & 1;
       if (tap < T)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[off_W3 + (co * C + rt * 16 + 4 * j + i) * T + tap] = acc[S2 + k][i];
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < S1; ++k) {
-    const int id = k * NW + w;
-    if (id < Cfg::N1) {
-      const int rt = id % RT, ct = id / RT;
-      const int tap = ct * 16 + m;
-      if (tap < T)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) out[off_W1 + (rt * 16 + 4 * j + i) * T + tap] = acc[S2 + S3 + k][i];
+        for (int i = 0; i < 4; ++i) {
+          const int c = rt * 16 + 4 * j + i;
+          out[w3 ? off_W3 + (co * C + c) * T + tap : off_W1 + c * T + tap] = acc31[k][i];
+        }
     }
   }
 }
