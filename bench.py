@@ -24,13 +24,21 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = dict(workload="phi4-2d-L32-train", dim=2, L=32, m2=-4.0, lam=8.0, n_layers=16,
-                hidden=16, batch=1024, lr=1e-3)
+WORKLOADS = {
+    # the headline workload (the default)
+    "phi4-2d-L32-train": dict(workload="phi4-2d-L32-train", dim=2, L=32, m2=-4.0, lam=8.0,
+                              n_layers=16, hidden=16, batch=1024, lr=1e-3),
+    # the 3D L = 16 C = 32 training step (for its own profile; BF16 only)
+    "phi4-3d-L16-C32-train": dict(workload="phi4-3d-L16-C32-train", dim=3, L=16, m2=-4.0, lam=5.0,
+                                  n_layers=16, hidden=32, batch=256, lr=1e-3),
+}
+WORKLOAD = WORKLOADS["phi4-2d-L32-train"]
 PEAK = {"bf16_mfma_tflops": 2500.0, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
 KERNEL_SOURCES = ["paper_2208_08903_amd/csrc/flow_fused_bwd.hip",
                   "paper_2208_08903_amd/csrc/fused_kernels.hpp",
                   "paper_2208_08903_amd/csrc/fused_common.hpp",
-                  "paper_2208_08903_amd/csrc/lfs_common.hpp"]
+                  "paper_2208_08903_amd/csrc/lfs_common.hpp",
+                  "paper_2208_08903_amd/csrc/fused_bwd_common.hpp"]
 TRAFFIC_FILE = "profiles/kf_backward_phi4-2d-L32-train_traffic.txt"
 
 
@@ -162,7 +170,8 @@ def hmc_rate(reps=5):
 
 def other_workloads(params_2d):
     """Side figures for the other workloads: the 2D L=8 example shape (latency of one batch of 64,
-    a 2000-proposal chain), the 3D L=8 training step, and 3D L=16 C=32 sampling at batch 4096."""
+    a 2000-proposal chain), the 3D L=8 training step, and 3D L=16 C=32 training at batch 256
+    (with its device-memory footprint) and sampling at batch 4096."""
     import numpy as np
     import torch
     import seeded_inputs as si
@@ -197,8 +206,21 @@ def other_workloads(params_2d):
         tr = fl.Trainer(f3, 512, -4.0, 5.0)
         tt, ph = time_phases(tr, 5, 2)
         out[f"3d_L8_train_{name}_steps_per_s"] = round(5 / tt, 3)
-    # 3D L=16, 16 layers, C=32, BF16: sampling at batch 4096
+    # 3D L=16, 16 layers, C=32, BF16: training at batch 256; the footprint is the peak of
+    # every device allocation the trainer makes (weights, Adam state, saved fields,
+    # workspaces)
     p16 = si.flow_params(3, 16, 32)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    base = torch.cuda.memory_allocated()
+    f16t = fl.Flow(3, 16, 16, 32, lfs.LFS_BF16_CONV, params=p16)
+    tr16 = fl.Trainer(f16t, 256, -4.0, 5.0)
+    tt, ph = time_phases(tr16, 5, 2)
+    out["3d_L16_C32_train_bf16_steps_per_s"] = round(5 / tt, 3)
+    out["3d_L16_C32_train_bf16_phases_ms"] = {k: round(v, 3) for k, v in ph.items()}
+    out["3d_L16_C32_train_hbm_bytes"] = int(torch.cuda.max_memory_allocated() - base)
+    del tr16, f16t
+    # 3D L=16, 16 layers, C=32, BF16: sampling at batch 4096
     f16 = fl.Flow(3, 16, 16, 32, lfs.LFS_BF16_CONV, params=p16)
     out["3d_L16_C32_sampling_bf16"] = sampling_rate(f16, 4096, -4.0, 5.0, batches=2)
     out["3d_L16_C32_forward_ms_b4096"] = round(flow_forward_ms(f16, 4096, reps=2), 3)
@@ -250,7 +272,7 @@ def serving(seconds=5.0):
     return st
 
 
-def cpu_baseline(target_s=15.0):
+def cpu_baseline(w, target_s=15.0):
     """The FP64 oracle's training step, one thread, on a bounded sample of the batch,
     scaled to steps/s of the full batch (cost is linear in the batch: samples are
     independent)."""
@@ -259,7 +281,6 @@ def cpu_baseline(target_s=15.0):
     import seeded_inputs as si
     from oracle import adam as oadam
     from oracle import flow as of
-    w = WORKLOAD
     fs = of.FlowShape(w["dim"], w["L"], w["n_layers"], w["hidden"])
     p = si.flow_params(w["dim"], w["n_layers"], w["hidden"]).astype(np.float64)
 
@@ -271,8 +292,8 @@ def cpu_baseline(target_s=15.0):
         return time.perf_counter() - t
 
     with threadpool_limits(1):
-        t1 = run(4)
-        b = int(max(4, min(128, round(4 * target_s / max(t1, 1e-3)))))
+        t1 = run(2)
+        b = int(max(2, min(128, round(2 * target_s / max(t1, 1e-3)))))
         tb = run(b)
     per_sample = tb / b
     return {"value": 1.0 / (per_sample * w["batch"]), "unit": "train steps/s", "cores": 1,
@@ -288,6 +309,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP32/sampling/HMC side figures")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default=WORKLOAD["workload"],
+                    help="the training step to time (side figures run with the default only)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the timed region, one device-to-device copy of this many MiB "
                          "(the known-size kernel that scales the HBM byte counters)")
@@ -305,7 +328,8 @@ def main():
     from paper_2208_08903_amd import lfs
 
     torch.cuda.set_device(0)
-    w = WORKLOAD
+    w = WORKLOADS[args.workload]
+    headline = w is WORKLOAD
     params = si.flow_params(w["dim"], w["n_layers"], w["hidden"])
     B = w["batch"]
 
@@ -324,7 +348,8 @@ def main():
     fwd_flops = fl_flops * w["n_layers"] * B
     bwd_launches = w["n_layers"]
     if phase["backward"] > fwd_ms:
-        dom_name = "flow_backward (per layer launch)"
+        dom_name = ("flow_backward (per layer launch)" if w["dim"] == 2 else
+                    "flow_backward (per layer: kr_recompute + kr_transpose + kr_wgrad)")
         dom_ms = phase["backward"] / bwd_launches
         dom_flops = 2 * fl_flops * B
     else:
@@ -335,7 +360,7 @@ def main():
     roof = {"kernel": dom_name, "bound": "mfma", "achieved": round(achieved, 3),
             "peak": PEAK["bf16_mfma_tflops"], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK["bf16_mfma_tflops"], 5),
-            "traffic": recorded_traffic() if dom_name.startswith("flow_backward") else None,
+            "traffic": recorded_traffic() if headline and dom_name.startswith("flow_backward") else None,
             "flops_per_launch": dom_flops, "ms_per_launch": round(dom_ms, 5)}
 
     out = {
@@ -353,7 +378,7 @@ def main():
         "loss_last": loss,
         "roofline": roof,
     }
-    if not args.no_extras:
+    if headline and not args.no_extras:
         f32, tr32 = make(lfs.LFS_PLAIN_FP32)
         n32 = max(3, args.steps // 4)
         t32, ph32 = time_phases(tr32, n32, 2)
@@ -379,7 +404,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = nb
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
 
 

@@ -191,7 +191,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
     const u32x4* frags, const float* __restrict__ pl, int off_b1, int off_b2,
     int off_b3, int off_W1, int off_W2, int off_W3, int fpar, int final_tanh, float g_ld, int B,
     const float* __restrict__ xin, const float* __restrict__ gy, float* __restrict__ gx,
-    float* __restrict__ partial) {
+    float* __restrict__ partial, const float* __restrict__ prev_partial, float* __restrict__ prev_out,
+    int n_parts) {
   using Cfg = BwdCfg<DIM, L, C, BF16>;
   using G = Geo<DIM, L>;
   using HT = HElem<BF16>;
@@ -260,6 +261,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
     }
   };
   if constexpr (PF) prefetch(blockIdx.x);
+  // the previous launch's (next layer's) weight gradient, while the prefetch is in flight
+  if (prev_partial) grid_reduce<NT>(prev_partial, prev_out, n_parts, Cfg::P_LAYER);
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     // Weight fragments are reloaded per phase (L1/L2 hits) rather than kept live
@@ -718,7 +721,7 @@ size_t bwd_ws(const FlowGeom& g, int B) {
   const size_t frags = (size_t)Cfg::FRAGS * 64 * 16 * g.N;
   const size_t partial = (size_t)bwd_grid<DIM, L, C, BF16>(B) * Cfg::P_LAYER * 4;
   const size_t gbuf = (size_t)B * Cfg::V * 4;
-  return align_up(frags) + align_up(partial) + 2 * align_up(gbuf);
+  return align_up(frags) + 2 * align_up(partial) + 2 * align_up(gbuf);
 }
 
 template <int DIM, int L, int C, bool BF16>
@@ -731,8 +734,10 @@ int32_t launch_backward(const FlowGeom& g, const float* params, int B, const flo
   char* p = ws;
   u32x4* frags = reinterpret_cast<u32x4*>(p);
   p += align_up((size_t)Cfg::FRAGS * 64 * 16 * g.N);
-  float* partial = reinterpret_cast<float*>(p);
-  p += align_up((size_t)grid * Cfg::P_LAYER * 4);
+  // two partial buffers: a launch reduces the previous launch's while writing its own
+  float* partial[2] = {reinterpret_cast<float*>(p),
+                       reinterpret_cast<float*>(p + align_up((size_t)grid * Cfg::P_LAYER * 4))};
+  p += 2 * align_up((size_t)grid * Cfg::P_LAYER * 4);
   float* gbuf[2] = {reinterpret_cast<float*>(p),
                     reinterpret_cast<float*>(p + align_up((size_t)B * Cfg::V * 4))};
   const long nthreads = (long)tab.total * 64 * g.N;
@@ -748,17 +753,20 @@ int32_t launch_backward(const FlowGeom& g, const float* params, int B, const flo
   int which = 0;
   for (int l = g.N - 1; l >= 0; --l) {
     float* gx = gbuf[which];
+    const bool first = l == g.N - 1;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(Cfg::NT), Cfg::lds_bytes, st,
                        frags + (size_t)l * tab.total * 64, params + (size_t)l * g.P_layer,
                        (int)g.off_b1, (int)g.off_b2, (int)g.off_b3, (int)g.off_W1, (int)g.off_W2,
                        (int)g.off_W3, g.frozen_parity(l), g.final_tanh, (float)(-g_logq), B,
-                       saved + (size_t)l * BV, gy, gx, partial);
-    hipLaunchKernelGGL(kf_reduce, dim3((Cfg::P_LAYER + kRedCols - 1) / kRedCols),
-                       dim3(kRedCols * kRedSlices), 0, st, grid,
-                       Cfg::P_LAYER, partial, g_params + (size_t)l * g.P_layer);
+                       saved + (size_t)l * BV, gy, gx, partial[l & 1],
+                       first ? nullptr : (const float*)partial[(l + 1) & 1],
+                       first ? nullptr : g_params + (size_t)(l + 1) * g.P_layer, grid);
     gy = gx;
     which ^= 1;
   }
+  hipLaunchKernelGGL(kf_reduce, dim3((Cfg::P_LAYER + kRedCols - 1) / kRedCols),
+                     dim3(kRedCols * kRedSlices), 0, st, grid, Cfg::P_LAYER,
+                     (const float*)partial[0], g_params);
   if (g_z)
     hipLaunchKernelGGL(kf_gz, dim3((unsigned)((BV + 255) / 256)), dim3(256), 0, st, (int64_t)BV,
                        gy, saved, (float)g_logq, g_z);
@@ -778,7 +786,10 @@ struct BwdEntry {
 
 template <int DIM, int L, int C, bool BF16>
 constexpr BwdEntry bwd_entry() {
-  static_assert(BwdCfg<DIM, L, C, BF16>::lds_bytes <= 160 * 1024, "LDS budget");
+  using Cfg = BwdCfg<DIM, L, C, BF16>;
+  // dynamic LDS plus the static buffer of the in-kernel partial reduction
+  static_assert(Cfg::lds_bytes + kRedSlices * (Cfg::NT / kRedSlices + 1) * 4 <= 160 * 1024,
+                "LDS budget");
   return BwdEntry{DIM, L, C, BF16, &launch_backward<DIM, L, C, BF16>, &bwd_ws<DIM, L, C, BF16>};
 }
 

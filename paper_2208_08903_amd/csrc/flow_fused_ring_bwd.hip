@@ -66,7 +66,10 @@ struct RbCfg {
   static constexpr int NWC = NT_C / 64;
   static constexpr int S2 = (N2 + NWC - 1) / NWC, S3 = (N3 + NWC - 1) / NWC, S1 = (N1 + NWC - 1) / NWC;
   static_assert(C % 16 == 0 && L % 16 == 0, "ring backward shapes");
-  static_assert(LDS_A <= 160 * 1024 && LDS_B <= 160 * 1024 && LDS_C <= 160 * 1024, "LDS budget");
+  // dynamic LDS plus the kernels' static buffers (partial reduction, bias sums)
+  static_assert(LDS_A + kRedSlices * (NT_A / kRedSlices + 1) * 4 + 64 <= 160 * 1024 &&
+                    LDS_B + (NT_B / 64) * C * 4 <= 160 * 1024 && LDS_C <= 160 * 1024,
+                "LDS budget");
 };
 
 // B operand from a ring of three padded planes: the lane's 8 channels at tap
@@ -150,7 +153,8 @@ __global__ void __launch_bounds__(NT) kr_recompute(
     int fpar, int final_tanh, float g_ld, int B, const float* __restrict__ xin,
     const float* __restrict__ gy, float* __restrict__ gx, uint16_t* __restrict__ h1c,
     uint16_t* __restrict__ h2c, uint32_t* __restrict__ m1, uint32_t* __restrict__ m2,
-    uint32_t* __restrict__ go, float* __restrict__ partial, int P) {
+    uint32_t* __restrict__ go, float* __restrict__ partial, int P,
+    const float* __restrict__ prev_partial, float* __restrict__ prev_out) {
   using Cfg = RbCfg<L, C>;
   using G = typename Cfg::G;
   using LX = typename Cfg::LX;
@@ -182,6 +186,9 @@ __global__ void __launch_bounds__(NT) kr_recompute(
   for (int c = 0; c < LF.k2; ++c) A3[0][c] = fl[(LF.off3 + c) * 64];
   const f32x4 b3[1] = {f32x4{pl[off_b3], 0.f, 0.f, 0.f}};
   float db3s = 0.f, db3t = 0.f;
+  // the previous launch's (next layer's) weight gradient; every kernel of a layer
+  // runs on the same grid, so that is also the number of partials
+  if (prev_partial) grid_reduce<NT>(prev_partial, prev_out, (int)gridDim.x, P);
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     const size_t sb = (size_t)b * V;
@@ -640,7 +647,7 @@ size_t rb_ws(const FlowGeom& g, int B) {
   using Cfg = RbCfg<L, C>;
   const size_t BV = (size_t)B * Cfg::V;
   return align_up((size_t)Cfg::FRAGS * 64 * 16 * g.N) +
-         align_up((size_t)rb_grid<L, C>(B) * Cfg::P_LAYER * 4) + 2 * align_up(BV * 4) +
+         2 * align_up((size_t)rb_grid<L, C>(B) * Cfg::P_LAYER * 4) + 2 * align_up(BV * 4) +
          4 * align_up(BV * C * 2) + 3 * align_up(BV * 4);
 }
 
@@ -666,7 +673,9 @@ int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved
     return r;
   };
   u32x4* frags = reinterpret_cast<u32x4*>(take((size_t)Cfg::FRAGS * 64 * 16 * g.N));
-  float* partial = reinterpret_cast<float*>(take((size_t)grid * Cfg::P_LAYER * 4));
+  // two partial buffers: a layer's recompute reduces the previous layer's partials
+  float* partials[2] = {reinterpret_cast<float*>(take((size_t)grid * Cfg::P_LAYER * 4)),
+                        reinterpret_cast<float*>(take((size_t)grid * Cfg::P_LAYER * 4))};
   float* gbuf[2] = {reinterpret_cast<float*>(take(BV * 4)), reinterpret_cast<float*>(take(BV * 4))};
   uint16_t* h1c = reinterpret_cast<uint16_t*>(take(BV * C * 2));
   uint16_t* h2c = reinterpret_cast<uint16_t*>(take(BV * C * 2));
@@ -693,9 +702,13 @@ int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved
     const float* pl = params + (size_t)l * g.P_layer;
     const float* xl = saved + (size_t)l * BV;
     const int fpar = g.frozen_parity(l);
+    const bool first = l == g.N - 1;
+    float* partial = partials[l & 1];
     hipLaunchKernelGGL(ka, dim3(grid), dim3(Cfg::NT_A), Cfg::LDS_A, st, fl, pl, (int)g.off_b1,
                        (int)g.off_b2, (int)g.off_b3, fpar, g.final_tanh, (float)(-g_logq), B, xl, gy,
-                       gx, h1c, h2c, m1, m2, go, partial, P);
+                       gx, h1c, h2c, m1, m2, go, partial, P,
+                       first ? nullptr : (const float*)partials[(l + 1) & 1],
+                       first ? nullptr : g_params + (size_t)(l + 1) * g.P_layer);
     hipLaunchKernelGGL(kb, dim3(grid), dim3(Cfg::NT_B), Cfg::LDS_B, st, fl, fpar, B,
                        (const uint32_t*)go, (const uint32_t*)m1, (const uint32_t*)m2, gy, gx,
                        ga2c, ga1c, partial, P, (int)g.off_b1, (int)g.off_b2);
@@ -703,11 +716,11 @@ int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved
                        (const uint16_t*)h1c, (const uint16_t*)h2c, (const uint32_t*)go,
                        (const uint16_t*)ga2c, (const uint16_t*)ga1c, partial, P, (int)g.off_W1,
                        (int)g.off_W2, (int)g.off_W3);
-    hipLaunchKernelGGL(kf_reduce, dim3((P + kRedCols - 1) / kRedCols), dim3(kRedCols * kRedSlices),
-                       0, st, grid, P, (const float*)partial, g_params + (size_t)l * g.P_layer);
     gy = gx;
     which ^= 1;
   }
+  hipLaunchKernelGGL(kf_reduce, dim3((P + kRedCols - 1) / kRedCols), dim3(kRedCols * kRedSlices), 0,
+                     st, grid, P, (const float*)partials[0], g_params);
   if (g_z)
     hipLaunchKernelGGL(kf_gz, dim3((unsigned)((BV + 255) / 256)), dim3(256), 0, st, (int64_t)BV,
                        gy, saved, (float)g_logq, g_z);

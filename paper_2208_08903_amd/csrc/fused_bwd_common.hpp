@@ -37,6 +37,38 @@ __global__ void __launch_bounds__(kRedCols * kRedSlices) kf_reduce(int G, int P,
   }
 }
 
+// The same fixed-order sum done inside a backward launch by its whole grid (for
+// the previous layer's partials): blocks of NT / 16 consecutive parameters (a
+// whole cache line of each partial row at 512 threads) go to the workgroups in
+// turn; slice s of a parameter sums partials [G s / 16, G (s + 1) / 16) in index
+// order and the 16 slice sums are combined in index order -- the order of
+// kf_reduce, so results are identical.
+template <int NT>
+__device__ __forceinline__ void grid_reduce(const float* __restrict__ partial, float* __restrict__ out,
+                                            int G, int P) {
+  constexpr int PW = NT / kRedSlices;  // parameters per pass
+  __shared__ float sh[kRedSlices][PW + 1];
+  const int q = threadIdx.x % PW, sl = threadIdx.x / PW;
+  const int g0 = (int)((long)G * sl / kRedSlices), g1 = (int)((long)G * (sl + 1) / kRedSlices);
+  for (int base = blockIdx.x * PW; base < P; base += gridDim.x * PW) {
+    const int i = base + q;
+    float acc = 0.f;
+    if (i < P) {
+#pragma unroll 8
+      for (int g = g0; g < g1; ++g) acc += partial[(size_t)g * P + i];
+    }
+    sh[sl][q] = acc;
+    __syncthreads();
+    if (sl == 0 && i < P) {
+      float r = sh[0][q];
+#pragma unroll
+      for (int k = 1; k < kRedSlices; ++k) r += sh[k][q];
+      out[i] = r;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void kf_gz(int64_t n, const float* __restrict__ gx, const float* __restrict__ z,
                       float g_logq, float* __restrict__ gz) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -30,10 +30,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
-# name: (dim, L, n_layers, hidden, batch, m2, lambda)
+# name: (dim, L, n_layers, hidden, batch, m2, lambda, weight std, FP32 emulation)
+# The 3D L=16 C=32 flow uses N(0, 0.05^2) weights: at the workload's N(0, 0.1^2)
+# its 16 layers amplify rounding beyond any useful comparison (see the tests);
+# it has a BF16 backward only, so no FP32 emulation is stored for it.
 CONFIGS = {
-    "2d_L32_C16_B1024": (2, 32, 16, 16, 1024, -4.0, 8.0),
-    "3d_L8_C16_B512": (3, 8, 12, 16, 512, -4.0, 5.0),
+    "2d_L32_C16_B1024": (2, 32, 16, 16, 1024, -4.0, 8.0, 0.1, True),
+    "3d_L8_C16_B512": (3, 8, 12, 16, 512, -4.0, 5.0, 0.1, True),
+    "3d_L16_C32_B256": (3, 16, 16, 32, 256, -4.0, 5.0, 0.05, False),
 }
 KEY, COUNTER0, WEIGHT_SEED = 12345, 0, 2021
 PROJ_SEED, N_PROJ, PER_BLOCK = 4242, 32, 12
@@ -44,13 +48,13 @@ def _chunk(args):
     import seeded_inputs as si
     from oracle import flow as of
     from oracle import prior as op
-    dim, L, N, C, B, m2, lam, start, n = args
+    dim, L, N, C, B, m2, lam, w_std, emul32, start, n = args
     fs = of.FlowShape(dim, L, N, C)
-    p = si.flow_params(dim, N, C, seed=WEIGHT_SEED).astype(np.float64)
+    p = si.flow_params(dim, N, C, seed=WEIGHT_SEED, w_std=w_std).astype(np.float64)
     z = op.prior_normal(KEY, COUNTER0 + start, n, fs.V)
     from oracle import action as oa
     g = of.loss_gradient(p, z, fs, m2, lam)
-    g32 = of.loss_gradient(p, z, fs, m2, lam, emulate="fp32")
+    g32 = of.loss_gradient(p, z, fs, m2, lam, emulate="fp32") if emul32 else g
     loss = of.kl_loss(p, z, fs, m2, lam)
     # first-order sensitivity of S to per-site field errors e_n <= tol (1 + |phi_n|):
     # sum_n |dS/dphi_n| (1 + |phi_n|), per sample
@@ -87,9 +91,9 @@ def projections(g):
 
 
 def make(name, pool):
-    dim, L, N, C, B, m2, lam = CONFIGS[name]
+    dim, L, N, C, B, m2, lam, w_std, emul32 = CONFIGS[name]
     t = time.time()
-    jobs = [(dim, L, N, C, B, m2, lam, s, min(CHUNK, B - s)) for s in range(0, B, CHUNK)]
+    jobs = [(dim, L, N, C, B, m2, lam, w_std, emul32, s, min(CHUNK, B - s)) for s in range(0, B, CHUNK)]
     res = sorted(pool.map(_chunk, jobs), key=lambda r: r[0])
     g = np.zeros_like(res[0][1])
     g32 = np.zeros_like(g)
@@ -106,6 +110,7 @@ def make(name, pool):
                       for _, _, sl in block_slices(dim, N, C)])
     np.savez(os.path.join(HERE, f"full_size_grad_{name}.npz"),
              config=np.array([dim, L, N, C, B], np.int64), couplings=np.array([m2, lam]),
+             w_std=np.array([w_std]),
              seeds=np.array([KEY, COUNTER0, WEIGHT_SEED, PROJ_SEED], np.int64),
              idx=idx, vals=g[idx], block_norms=norms, proj=projections(g),
              grad_norm=np.array([np.linalg.norm(g)]), loss=np.array([loss]),

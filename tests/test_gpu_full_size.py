@@ -1,7 +1,8 @@
 """The HIP path at the workloads' full sizes, in the launch configuration the
 benchmark times, against the FP64 oracle.
 
-Training steps (2D L=32 C=16 at batch 1024, 3D L=8 C=16 at batch 512): one
+Training steps (2D L=32 C=16 at batch 1024, 3D L=8 C=16 at batch 512, 3D
+L=16 C=32 at batch 256 with N(0, 0.05^2) weights, BF16 only): one
 trainer step's loss and gradient (the trainer's own prior draw, forward and
 backward, i.e. the same kernels, grids and workspace as the timed step) against
 the oracle's gradient of the same step, stored by tests/golden/make_full_size.py
@@ -65,8 +66,10 @@ def _blocks(dim, N, C):
     return out
 
 
-@pytest.mark.parametrize("name", ["2d_L32_C16_B1024", "3d_L8_C16_B512"])
-@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("name,precision", [
+    ("2d_L32_C16_B1024", lfs.LFS_BF16_CONV), ("2d_L32_C16_B1024", lfs.LFS_PLAIN_FP32),
+    ("3d_L8_C16_B512", lfs.LFS_BF16_CONV), ("3d_L8_C16_B512", lfs.LFS_PLAIN_FP32),
+    ("3d_L16_C32_B256", lfs.LFS_BF16_CONV)])
 def test_full_size_training_gradient(name, precision):
     g = np.load(os.path.join(GOLDEN, f"full_size_grad_{name}.npz"), allow_pickle=False)
     dim, L, N, C, B = (int(v) for v in g["config"])
@@ -74,7 +77,8 @@ def test_full_size_training_gradient(name, precision):
     key, c0, wseed, pseed = (int(v) for v in g["seeds"])
     assert c0 == 0  # the trainer's first step draws counters 0 .. B-1
     print(f"full-size training step {name} precision={precision}", flush=True)
-    f = fl.Flow(dim, L, N, C, precision, params=si.flow_params(dim, N, C, seed=wseed))
+    w_std = float(g["w_std"][0])
+    f = fl.Flow(dim, L, N, C, precision, params=si.flow_params(dim, N, C, seed=wseed, w_std=w_std))
     tr = fl.Trainer(f, B, m2, lam, key=key)
     tr.draw()
     tr.forward()
