@@ -106,7 +106,46 @@ __global__ void __launch_bounds__(NT) kf_forward(
       }
       __syncthreads();
       // conv3 at the active sites, affine update and log-det
-      {
+      if constexpr (Cfg::X4) {
+        // four tiles share an accumulator: chunk c of tile u uses the fragments with
+        // the outputs at rows 4u, 4u+1, so lane group j ends with tile j's s and t
+        // and the epilogue runs on all 64 lanes (two chains: tiles 0-1 and 2-3)
+        u32x4 A[4][LF.k2];
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c) {
+          A[0][c] = fl[(LF.off3 + c) * 64];
+#pragma unroll
+          for (int u = 1; u < 4; ++u) A[u][c] = fl[(LF.off3q + (u - 1) * LF.k2 + c) * 64];
+        }
+        const f32x4 b3{pl[off_b3], pl[off_b3 + 1], 0.f, 0.f};
+        const int apar = fpar ^ 1;
+        constexpr int NT3 = V / 32;
+        for (int t0 = w; t0 < NT3; t0 += 4 * NW) {
+          int n4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) n4[u] = G::half_site((t0 + u * NW < NT3 ? t0 + u * NW : t0) * 16 + m, apar);
+          f32x4 a01 = b3, a23{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c = 0; c < LF.k2; ++c) {
+            const u32x4 g0 = gather_h<LY, C, BF16>(h2, n4[0], LY::idx(n4[0]), c, j);
+            const u32x4 g1 = gather_h<LY, C, BF16>(h2, n4[1], LY::idx(n4[1]), c, j);
+            const u32x4 g2 = gather_h<LY, C, BF16>(h2, n4[2], LY::idx(n4[2]), c, j);
+            const u32x4 g3 = gather_h<LY, C, BF16>(h2, n4[3], LY::idx(n4[3]), c, j);
+            a01 = mma<BF16>(A[0][c], g0, a01);
+            a23 = mma<BF16>(A[2][c], g2, a23);
+            a01 = mma<BF16>(A[1][c], g1, a01);
+            a23 = mma<BF16>(A[3][c], g3, a23);
+          }
+          if (t0 + j * NW < NT3) {
+            const int n = G::half_site((t0 + j * NW) * 16 + m, apar), p = LY::idx(n);
+            const float o0 = a01[0] + a23[0], t = a01[1] + a23[1];
+            const float s = final_tanh ? fast_tanh(o0) : o0;
+            const float xn = xs[p] * fast_exp(s) + t;
+            LY::copies(n, [&](int q) { xs[q] = xn; });
+            ld += (R)s;
+          }
+        }
+      } else {
         u32x4 A[1][LF.k2];
 #pragma unroll
         for (int c = 0; c < LF.k2; ++c) A[0][c] = fl[(LF.off3 + c) * 64];
@@ -162,9 +201,12 @@ int32_t launch_forward(const FlowGeom& g, const float* params, int B, const floa
   u32x4* frags = reinterpret_cast<u32x4*>(ws);
   FragTable tab{};
   tab.count = 3;
-  tab.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, LF.nct, LF.k1, LF.off1, 1};
-  tab.s[1] = FragSpec{0, (int)g.off_W2, C, C, C, LF.nct, LF.k2, LF.off2};
-  tab.s[2] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, LF.k2, LF.off3};
+  tab.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, LF.nct, LF.k1, LF.off1, 1, 0};
+  tab.s[1] = FragSpec{0, (int)g.off_W2, C, C, C, LF.nct, LF.k2, LF.off2, 0, 0};
+  tab.s[2] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, LF.k2, LF.off3, 0, 0};
+  if (LF.x4)
+    for (int u = 1; u < 4; ++u)
+      tab.s[tab.count++] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, LF.k2, LF.off3q + (u - 1) * LF.k2, 0, 4 * u};
   tab.total = LF.total;
   const long nthreads = (long)LF.total * 64 * g.N;
   hipLaunchKernelGGL((kf_prep<BF16>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st,

@@ -74,12 +74,7 @@ template <int DIM, int L, int C, bool BF16>
 struct BwdCfg {
   using G = Geo<DIM, L>;
   static constexpr int V = G::V, T = G::T;
-  static constexpr LayerFrags LF = layer_frags(T, C, BF16);
   static constexpr int KT3 = BF16 ? kchunks_bf16(2 * T) : kblocks_f32(2 * T);
-  static constexpr int OFF3T = LF.total;
-  static constexpr int OFF2T = OFF3T + LF.nct * KT3;
-  static constexpr int OFF1T = OFF2T + LF.nct * LF.k2;
-  static constexpr int FRAGS = OFF1T + LF.k2;
   static constexpr int P_LAYER = C * T + C + C * C * T + C + 2 * C * T + 2;
   static constexpr bool PAD = BwdLds<DIM, L, C, BF16, true>::MAIN <= 158 * 1024;
   using M = BwdLds<DIM, L, C, BF16, PAD>;
@@ -92,6 +87,16 @@ struct BwdCfg {
   // Tiles in flight per wave in the tile passes: two where the registers allow
   // (3D shapes, and FP32 C=16 at two waves per SIMD, are already at the limit).
   static constexpr int TU = DIM == 2 && (BF16 || NT == 256 || C < 16) ? 2 : 1;
+  // conv3 recompute: tiles whose affine backward share a pass -- four where the
+  // extra fragments fit the registers, two (one shuffle) otherwise; BF16 with at
+  // least that many active-site tiles per wave, else one
+  static constexpr int TPW3 = V / 32 / NW;
+  static constexpr int QU3 = !(T == 9 && BF16) ? 1 : (NT == 256 && TPW3 >= 4) ? 4 : (TPW3 >= 2 ? 2 : 1);
+  static constexpr LayerFrags LF = layer_frags(T, C, BF16, QU3 == 4);
+  static constexpr int OFF3T = LF.total;
+  static constexpr int OFF2T = OFF3T + LF.nct * KT3;
+  static constexpr int OFF1T = OFF2T + LF.nct * LF.k2;
+  static constexpr int FRAGS = OFF1T + LF.k2;
   static constexpr int MT = (C + 15) / 16;
   static constexpr int NKC = BF16 ? V / 32 : V / 16;  // K chunks (sites) per sample
   // Weight-gradient output tiles; every wave accumulates all of them over its
@@ -358,41 +363,100 @@ __global__ void __launch_bounds__(NT) kf_backward(
     }
     __syncthreads();
     {
-      u32x4 A[1][LF.k2];
-#pragma unroll
-      for (int c = 0; c < LF.k2; ++c) A[0][c] = fr[(LF.off3 + c) * 64];
-      const f32x4 b3[1] = {f32x4{pl[off_b3], 0.f, 0.f, 0.f}};
-      mma_tiles<Cfg::TU, 1, LF.k2, BF16>(
-          V / 32, w, NW, A, b3,
-          [&](int tile, int c) {
-            const int n = G::half_site(tile * 16 + m, apar);
-            return gather_h<LY, C, BF16>(h2s, n, LY::idx(n), c, j);
-          },
-          [&](int tile, const f32x4(&acc3r)[1]) {
-        const int n = G::half_site(tile * 16 + m, apar), p = LY::idx(n);
-        if (j == 0) {
-          const float o0 = acc3r[0][0];
-          const float s = final_tanh ? fast_tanh(o0) : o0;
-          const float es = fast_exp(s);
-          const float g = gys[n];
-          const float gs = g * xs[p] * es + g_ld;
-          const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
-          db3s += go0;
-          db3t += g;
-          gx[sb + n] = g * es;
-          if constexpr (BF16) {
-            const uint32_t pr = pack_bf16(go0, g);
-            LY::copies(n, [&](int pp) { gos_b[pp] = pr; });
-            goc[n] = (uint16_t)pr;
-            goc[CSTR + n] = (uint16_t)(pr >> 16);
-          } else {
-            LY::copies(n, [&](int pp) {
-              gos_f[2 * pp] = go0;
-              gos_f[2 * pp + 1] = g;
-            });
-          }
-        }
+      // affine backward at active site n from conv3's s pre-activation o0
+      auto affine_bwd = [&](int n, float o0) {
+        const int p = LY::idx(n);
+        const float s = final_tanh ? fast_tanh(o0) : o0;
+        const float es = fast_exp(s);
+        const float g = gys[n];
+        const float gs = g * xs[p] * es + g_ld;
+        const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
+        db3s += go0;
+        db3t += g;
+        gx[sb + n] = g * es;
+        if constexpr (BF16) {
+          const uint32_t pr = pack_bf16(go0, g);
+          LY::copies(n, [&](int pp) { gos_b[pp] = pr; });
+          goc[n] = (uint16_t)pr;
+          goc[CSTR + n] = (uint16_t)(pr >> 16);
+        } else {
+          LY::copies(n, [&](int pp) {
+            gos_f[2 * pp] = go0;
+            gos_f[2 * pp + 1] = g;
           });
+        }
+      };
+      const float bs = pl[off_b3];
+      if constexpr (Cfg::QU3 == 2) {
+        // two tiles with the plain fragments; tile 1's s moves from lane group 0 to
+        // lane group 1, so the affine backward runs once on two lane groups
+        u32x4 A[LF.k2];
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c) A[c] = fr[(LF.off3 + c) * 64];
+        constexpr int NT3 = V / 32;
+        for (int t0 = w; t0 < NT3; t0 += 2 * NW) {
+          const int n0 = G::half_site(t0 * 16 + m, apar);
+          const int n1 = G::half_site((t0 + NW < NT3 ? t0 + NW : t0) * 16 + m, apar);
+          f32x4 a0{bs, 0.f, 0.f, 0.f}, a1{bs, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c = 0; c < LF.k2; ++c) {
+            const u32x4 g0 = gather_h<LY, C, BF16>(h2s, n0, LY::idx(n0), c, j);
+            const u32x4 g1 = gather_h<LY, C, BF16>(h2s, n1, LY::idx(n1), c, j);
+            a0 = mma<BF16>(A[c], g0, a0);
+            a1 = mma<BF16>(A[c], g1, a1);
+          }
+          const float o1 = __shfl(a1[0], m, 64);  // row 0 of tile 1, from lane m
+          const float o0 = j == 0 ? a0[0] : o1;
+          if (j < 2 && t0 + j * NW < NT3) affine_bwd(j == 0 ? n0 : n1, o0);
+        }
+      } else if constexpr (Cfg::QU3 == 4) {
+        // four tiles share an accumulator (outputs of tile u at rows 4u, 4u+1), so
+        // the affine backward runs on all 64 lanes, group j for tile j; one chain
+        // per pair of tiles
+        constexpr int QU = 4;
+        u32x4 A[QU][LF.k2];
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c) {
+          A[0][c] = fr[(LF.off3 + c) * 64];
+#pragma unroll
+          for (int u = 1; u < QU; ++u) A[u][c] = fr[(LF.off3q + (u - 1) * LF.k2 + c) * 64];
+        }
+        constexpr int NT3 = V / 32;
+        for (int t0 = w; t0 < NT3; t0 += QU * NW) {
+          int nq[QU];
+#pragma unroll
+          for (int u = 0; u < QU; ++u) nq[u] = G::half_site((t0 + u * NW < NT3 ? t0 + u * NW : t0) * 16 + m, apar);
+          f32x4 acc[QU / 2];
+#pragma unroll
+          for (int h = 0; h < QU / 2; ++h) acc[h] = f32x4{h == 0 ? bs : 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c = 0; c < LF.k2; ++c) {
+            u32x4 gq[QU];
+#pragma unroll
+            for (int u = 0; u < QU; ++u) gq[u] = gather_h<LY, C, BF16>(h2s, nq[u], LY::idx(nq[u]), c, j);
+#pragma unroll
+            for (int u = 0; u < QU; ++u) acc[u / 2] = mma<BF16>(A[u][c], gq[u], acc[u / 2]);
+          }
+          float o0 = acc[0][0];
+#pragma unroll
+          for (int h = 1; h < QU / 2; ++h) o0 += acc[h][0];
+          if (j < QU && t0 + j * NW < NT3) affine_bwd(G::half_site((t0 + j * NW) * 16 + m, apar), o0);
+        }
+      } else {
+        u32x4 A[1][LF.k2];
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c) A[0][c] = fr[(LF.off3 + c) * 64];
+        const f32x4 b3[1] = {f32x4{bs, 0.f, 0.f, 0.f}};
+        mma_tiles<Cfg::TU, 1, LF.k2, BF16>(
+            V / 32, w, NW, A, b3,
+            [&](int tile, int c) {
+              const int n = G::half_site(tile * 16 + m, apar);
+              return gather_h<LY, C, BF16>(h2s, n, LY::idx(n), c, j);
+            },
+            [&](int tile, const f32x4(&acc3r)[1]) {
+              if (j == 0) affine_bwd(G::half_site(tile * 16 + m, apar), acc3r[0][0]);
+            });
+      }
     }
     __syncthreads();
     // ---- dW3[co][ci][tap] += sum_m h2[m][ci] g_o[m - delta_tap][co] ----
@@ -730,7 +794,7 @@ int32_t launch_backward(const FlowGeom& g, const float* params, int B, const flo
                         hipStream_t st) {
   using Cfg = BwdCfg<DIM, L, C, BF16>;
   const int grid = bwd_grid<DIM, L, C, BF16>(B);
-  const FragTable tab = bwd_table(g, BF16);
+  const FragTable tab = bwd_table(g, BF16, Cfg::LF.x4);
   char* p = ws;
   u32x4* frags = reinterpret_cast<u32x4*>(p);
   p += align_up((size_t)Cfg::FRAGS * 64 * 16 * g.N);

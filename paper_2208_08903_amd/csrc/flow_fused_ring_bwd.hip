@@ -663,7 +663,7 @@ int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved
                hipStream_t st) {
   using Cfg = RbCfg<L, C>;
   const int grid = rb_grid<L, C>(B);
-  const FragTable tab = bwd_table(g, true);
+  const FragTable tab = bwd_table(g, true, false);
   if (tab.total != Cfg::FRAGS || (int)g.P_layer != Cfg::P_LAYER) return LFS_EUNSUPPORTED;
   const size_t BV = (size_t)B * Cfg::V;
   char* p = ws;

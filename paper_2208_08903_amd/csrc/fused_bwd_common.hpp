@@ -77,19 +77,24 @@ __global__ void kf_gz(int64_t n, const float* __restrict__ gx, const float* __re
 
 }  // namespace
 
-inline FragTable bwd_table(const FlowGeom& g, bool bf16) {
+// x4: the kernel shares conv3 accumulators between four tiles (extra placements)
+inline FragTable bwd_table(const FlowGeom& g, bool bf16, bool x4) {
   const int T = g.T, C = g.C;
-  const LayerFrags lf = layer_frags(T, C, bf16);
+  const LayerFrags lf = layer_frags(T, C, bf16, x4);
   const int kt3 = bf16 ? kchunks_bf16(2 * T) : kblocks_f32(2 * T);
   FragTable t{};
-  t.count = 6;
-  t.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, lf.nct, lf.k1, lf.off1, 1};
-  t.s[1] = FragSpec{0, (int)g.off_W2, C, C, C, lf.nct, lf.k2, lf.off2};
-  t.s[2] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, lf.k2, lf.off3};
-  t.s[3] = FragSpec{1, (int)g.off_W3, C, 2, C, lf.nct, kt3, lf.total};
-  t.s[4] = FragSpec{1, (int)g.off_W2, C, C, C, lf.nct, lf.k2, lf.total + lf.nct * kt3};
-  t.s[5] = FragSpec{1, (int)g.off_W1, 1, C, 1, 1, lf.k2, lf.total + lf.nct * kt3 + lf.nct * lf.k2};
-  t.total = t.s[5].off + lf.k2;
+  int n = 0;
+  t.s[n++] = FragSpec{0, (int)g.off_W1, 1, C, C, lf.nct, lf.k1, lf.off1, 1, 0};
+  t.s[n++] = FragSpec{0, (int)g.off_W2, C, C, C, lf.nct, lf.k2, lf.off2, 0, 0};
+  t.s[n++] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, lf.k2, lf.off3, 0, 0};
+  if (lf.x4)
+    for (int u = 1; u < 4; ++u)
+      t.s[n++] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, lf.k2, lf.off3q + (u - 1) * lf.k2, 0, 4 * u};
+  t.s[n++] = FragSpec{1, (int)g.off_W3, C, 2, C, lf.nct, kt3, lf.total, 0, 0};
+  t.s[n++] = FragSpec{1, (int)g.off_W2, C, C, C, lf.nct, lf.k2, lf.total + lf.nct * kt3, 0, 0};
+  t.s[n++] = FragSpec{1, (int)g.off_W1, 1, C, 1, 1, lf.k2, lf.total + lf.nct * kt3 + lf.nct * lf.k2, 0, 0};
+  t.count = n;
+  t.total = t.s[n - 1].off + lf.k2;
   return t;
 }
 

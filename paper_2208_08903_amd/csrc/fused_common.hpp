@@ -250,9 +250,14 @@ struct LayerFrags {
   int nct;           // output-channel tiles of conv1/conv2 (16 rows each)
   int k1, k2;        // K chunks (BF16) or blocks (FP32) of conv1 and of conv2/conv3
   int off1, off2, off3, total;  // fragment offsets within the layer
+  // x4: conv3's two output rows also placed at rows 4u, 4u+1 (u = 1, 2, 3; fragments
+  // from off3q, k2 per placement), so four tiles can share one accumulator with
+  // tile u's s and t landing in lane group u
+  bool x4;
+  int off3q;
 };
 
-__host__ __device__ constexpr LayerFrags layer_frags(int T, int C, bool bf16) {
+__host__ __device__ constexpr LayerFrags layer_frags(int T, int C, bool bf16, bool x4 = false) {
   LayerFrags f{};
   f.nct = C >= 16 ? C / 16 : 1;
   f.k1 = bf16 ? kchunks_bf16(k_tri(T)) : kblocks_f32(k_tri(T));
@@ -260,7 +265,9 @@ __host__ __device__ constexpr LayerFrags layer_frags(int T, int C, bool bf16) {
   f.off1 = 0;
   f.off2 = f.nct * f.k1;
   f.off3 = f.off2 + f.nct * f.k2;
-  f.total = f.off3 + f.k2;
+  f.x4 = x4;
+  f.off3q = f.off3 + f.k2;
+  f.total = f.off3q + (f.x4 ? 3 * f.k2 : 0);
   return f;
 }
 

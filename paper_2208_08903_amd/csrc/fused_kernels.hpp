@@ -14,11 +14,12 @@ namespace fused {
 // convolution (rows = output channels, k = tap * cin + ci); 1: its transpose
 // used by the data gradient (rows = input channels, k = tap * cout + co).
 // tri = 1 (single-input-channel forward convolution only): k in row-triple
-// order, k = 4 * (tap / 3) + tap % 3, the slots 4 r + 3 being zero.
+// order, k = 4 * (tap / 3) + tap % 3, the slots 4 r + 3 being zero.  shift:
+// the convolution's output row r is placed at fragment row r + shift.
 struct FragSpec {
-  int transposed, woff, cin, cout, rows, nct, nk, off, tri;
+  int transposed, woff, cin, cout, rows, nct, nk, off, tri, shift;
 };
-constexpr int kMaxSpecs = 6;
+constexpr int kMaxSpecs = 9;
 struct FragTable {
   FragSpec s[kMaxSpecs];
   int count, total;  // fragments per layer
@@ -38,11 +39,12 @@ __global__ void kf_prep(const float* __restrict__ params, int N, int T, int P_la
   int si = 0;
   while (si + 1 < tab.count && f >= tab.s[si + 1].off) ++si;
   const FragSpec sp = tab.s[si];
-  const int fl = f - sp.off, ct = fl / sp.nk, c = fl % sp.nk, row = ct * 16 + m;
+  const int fl = f - sp.off, ct = fl / sp.nk, c = fl % sp.nk, row = ct * 16 + m - sp.shift;
   const float* W = params + (size_t)layer * P_layer + sp.woff;
   const int kdiv = sp.transposed ? sp.cout : sp.cin;
   const int K = T * kdiv;
   auto w_at = [&](int k) -> float {
+    if (row < 0) return 0.f;
     if (sp.tri) {
       const int r = k >> 2, dx = k & 3;
       if (row >= sp.rows || dx == 3 || r >= T / 3) return 0.f;
@@ -277,7 +279,6 @@ template <int DIM, int L, int C, bool BF16>
 struct FwdCfg {
   using G = Geo<DIM, L>;
   static constexpr int V = G::V, T = G::T;
-  static constexpr LayerFrags LF = layer_frags(T, C, BF16);
   static constexpr size_t bytes_for(int vs) {
     return ((size_t)vs * 4 + 15) / 16 * 16 + 2 * (size_t)vs * C * sizeof(HElem<BF16>);
   }
@@ -288,6 +289,10 @@ struct FwdCfg {
   // tiles in flight per wave: conv1 (one K chunk in BF16) and conv2/conv3
   static constexpr int TU1 = BF16 ? 4 : 2;
   static constexpr int TU2 = (DIM == 3 && !BF16) ? 1 : 2;
+  // conv3 four tiles per accumulator (2D BF16: the FP32 and 3D fragments of four
+  // placements do not fit the registers) when every wave has four active-site tiles
+  static constexpr bool X4 = T == 9 && BF16 && V / 32 >= 4 * (NT / 64);
+  static constexpr LayerFrags LF = layer_frags(T, C, BF16, X4);
 };
 
 }  // namespace fused
