@@ -41,7 +41,6 @@ struct BwdLds {
   static constexpr int CSTR = V + 8;  // channel-major row stride in elements (BF16 mode)
   // site-major tensors and g_o carry the layout's extra all-zero site
   static constexpr size_t SA = (size_t)LY::VSZ * C * (BF16 ? 2 : 4);  // site-major tensor
-  static constexpr size_t SC = BF16 ? (size_t)C * CSTR * 2 : 0;  // channel-major tensor
   static constexpr size_t OFF_XS = 0;
   static constexpr size_t OFF_GY = align16((size_t)VS * 4);
   static constexpr size_t OFF_GOS = OFF_GY + align16((size_t)V * 4);
@@ -51,12 +50,18 @@ struct BwdLds {
   static constexpr size_t OFF_H0C = OFF_GOC + align16(GOC_BYTES);
   static constexpr size_t H0C_BYTES = BF16 ? (size_t)CSTR * 2 : 0;
   static constexpr size_t OFF_SLOT = OFF_H0C + align16(H0C_BYTES);
-  // BF16: site-major, channel-major, site-major, channel-major; FP32: two site-major
+  // site-major slots: BF16 three (S0: h1; S1: conv1's row triples, then h2, then
+  // g_a1; S2: g_a2), FP32 two (h1 then g_a1 in place; h2 then g_a2 in place).  The
+  // weight-gradient GEMMs read their site-major operands with transposing LDS
+  // reads; g_o and the masked field keep channel-major rows, and so does g_a2 in
+  // 3D (S3), whose 27 shifted reads in dW2 would otherwise cost more registers
+  // in address arithmetic than the lanes have.
+  static constexpr bool CM2 = BF16 && DIM == 3;
   static constexpr size_t OFF_S0 = OFF_SLOT;
   static constexpr size_t OFF_S1 = OFF_S0 + SA;
-  static constexpr size_t OFF_S2 = OFF_S1 + (BF16 ? SC : SA);
-  static constexpr size_t OFF_S3 = OFF_S2 + (BF16 ? SA : 0);
-  static constexpr size_t MAIN = BF16 ? OFF_S3 + SC : OFF_S2;
+  static constexpr size_t OFF_S2 = OFF_S1 + SA;
+  static constexpr size_t OFF_S3 = OFF_S2 + SA;
+  static constexpr size_t MAIN = !BF16 ? OFF_S2 : CM2 ? OFF_S3 + (size_t)C * CSTR * 2 : OFF_S3;
 };
 
 // Channel-major BF16 copy of four channels co0..co0+3 (packed pairs in hv) of
@@ -218,17 +223,16 @@ __global__ void __launch_bounds__(NT) kf_backward(
   // written afterwards (every later store goes to a lattice site or its mirror).
   {
     HT* z0 = reinterpret_cast<HT*>(smem + M::OFF_S0);
-    HT* z1 = reinterpret_cast<HT*>(smem + (BF16 ? M::OFF_S2 : M::OFF_S1));
-    for (int q = threadIdx.x; q < C; q += NT) z0[LY::ZS * C + q] = HT(0), z1[LY::ZS * C + q] = HT(0);
+    HT* z1 = reinterpret_cast<HT*>(smem + M::OFF_S1);
+    HT* z2 = reinterpret_cast<HT*>(smem + (BF16 ? M::OFF_S2 : M::OFF_S1));
+    for (int q = threadIdx.x; q < C; q += NT)
+      z0[LY::ZS * C + q] = HT(0), z1[LY::ZS * C + q] = HT(0), z2[LY::ZS * C + q] = HT(0);
     if (threadIdx.x < (BF16 ? 1 : 2))
       reinterpret_cast<uint32_t*>(smem + M::OFF_GOS)[LY::ZS * (BF16 ? 1 : 2) + threadIdx.x] = 0u;
   }
-  // site-major activations: BF16 h1s S0, h2s S2; FP32 h1 S0, h2 S1
+  // site-major activations: h1 in S0, h2 in S1
   HT* h1s = reinterpret_cast<HT*>(smem + M::OFF_S0);
-  HT* h2s = reinterpret_cast<HT*>(smem + (BF16 ? M::OFF_S2 : M::OFF_S1));
-  // BF16 channel-major copies and the remaining slots
-  uint16_t* h1c = reinterpret_cast<uint16_t*>(smem + M::OFF_S1);
-  uint16_t* h2c = reinterpret_cast<uint16_t*>(smem + M::OFF_S3);
+  HT* h2s = reinterpret_cast<HT*>(smem + M::OFF_S1);
 
   constexpr int NTL3 = Cfg::NTL3, NTL1 = Cfg::NTL1;
   f32x4 acc3[Cfg::I3], acc2[Cfg::I2], acc1[Cfg::I1];
@@ -313,10 +317,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
           },
           [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
-            for (int ct = 0; ct < LF.nct; ++ct) {
-              const u32x2 hv = store_act_tile<LY, C, BF16>(h1s, tile, m, ct, j, acc[ct]);
-              if constexpr (BF16) store_cm4<C, CSTR>(h1c, tile * 16 + m, ct * 16 + 4 * j, hv);
-            }
+            for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16>(h1s, tile, m, ct, j, acc[ct]);
           });
     }
     __syncthreads();
@@ -337,10 +338,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
           },
           [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
-            for (int ct = 0; ct < LF.nct; ++ct) {
-              const u32x2 hv = store_act_tile<LY, C, BF16>(h2s, tile, m, ct, j, acc[ct]);
-              if constexpr (BF16) store_cm4<C, CSTR>(h2c, tile * 16 + m, ct * 16 + 4 * j, hv);
-            }
+            for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16>(h2s, tile, m, ct, j, acc[ct]);
           });
     }
     // ---- recompute conv3 at active sites; affine backward -> g_o, g_x(active) ----
@@ -467,7 +465,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
         const int ci = mt * 16 + m;
         if constexpr (BF16) {
           const int s0 = kc * 32 + 8 * j;
-          const u32x4 a = ci < C ? *reinterpret_cast<const u32x4*>(h2c + ci * CSTR + s0) : u32x4{0u, 0u, 0u, 0u};
+          const u32x4 a = load_tr8<LY, C, 1>(h2s, s0, mt * 16, -1, m);
 #pragma unroll
           for (int nt = 0; nt < NTL3; ++nt) {
             const int col = nt * 16 + m, tap = col >> 1, co = col & 1;
@@ -491,9 +489,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
     }
     __syncthreads();
     // ---- conv3^T: g_a2 = leaky'(h2) (W3^T * g_o) ----
-    // BF16: site-major into S0 (h1s is dead), channel-major into S3 (h2c is dead);
-    // FP32: in place over h2.
-    HT* ga2s = BF16 ? reinterpret_cast<HT*>(smem + M::OFF_S0) : h2s;
+    // BF16: into S2 (3D also channel-major into S3); FP32: in place over h2.
+    HT* ga2s = BF16 ? reinterpret_cast<HT*>(smem + M::OFF_S2) : h2s;
     uint16_t* ga2c = reinterpret_cast<uint16_t*>(smem + M::OFF_S3);
     {
       u32x4 A[LF.nct][Cfg::KT3];
@@ -536,7 +533,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
                   const float hh[4] = {bf16_lo(hv[0]), bf16_hi(hv[0]), bf16_lo(hv[1]), bf16_hi(hv[1])};
 #pragma unroll
                   for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-                  store_cm4<C, CSTR>(ga2c, n, c0, store4_tile<LY, C, BF16>(ga2s, tile, m, c0, v));
+                  const u32x2 gv = store4_tile<LY, C, BF16>(ga2s, tile, m, c0, v);
+                  if constexpr (M::CM2) store_cm4<C, CSTR>(ga2c, n, c0, gv);
                 } else {
                   const f32x4 hh = *reinterpret_cast<const f32x4*>(h2s + p * C + c0);
 #pragma unroll
@@ -558,16 +556,22 @@ __global__ void __launch_bounds__(NT) kf_backward(
       for (int mt = 0; mt < MT; ++mt) {
         const int ci = mt * 16 + m;
         if constexpr (BF16) {
-          const int s0 = kc * 32 + 8 * j, x0 = s0 % L;
-          const u32x4 a = ci < C ? *reinterpret_cast<const u32x4*>(h1c + ci * CSTR + s0) : u32x4{0u, 0u, 0u, 0u};
+          const int s0 = kc * 32 + 8 * j;
+          const u32x4 a = load_tr8<LY, C, 1>(h1s, s0, mt * 16, -1, m);
+          const int x0 = s0 % L;
           static_for<0, T>([&](auto tc) {
             constexpr int TAP = decltype(tc)::value;
             constexpr int E = -tap_dc<DIM, TAP, DIM - 1>();
             const int rowS = shifted_row_c<DIM, L, TAP, -1>(s0);
 #pragma unroll
             for (int nt = 0; nt < MT; ++nt) {
-              const int co = nt * 16 + m;
-              const u32x4 bb = co < C ? load8_e<L, E>(ga2c + co * CSTR + rowS * L, x0) : u32x4{0u, 0u, 0u, 0u};
+              u32x4 bb;
+              if constexpr (M::CM2) {
+                const int co = nt * 16 + m;
+                bb = co < C ? load8_e<L, E>(ga2c + co * CSTR + rowS * L, x0) : u32x4{0u, 0u, 0u, 0u};
+              } else {
+                bb = load_tr8<LY, C, -1>(ga2s, s0, nt * 16, TAP, m);
+              }
               acc2[(mt * T + TAP) * MT + nt] = mfma(as_bf16x8(a), as_bf16x8(bb), acc2[(mt * T + TAP) * MT + nt]);
             }
           });
@@ -592,10 +596,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
     }
     __syncthreads();
     // ---- conv2^T: g_a1 = leaky'(h1) (W2^T * g_a2) ----
-    // BF16: site-major into S2 (h2s is dead), channel-major into S3 (g_a2c is dead);
-    // FP32: in place over h1.
-    HT* ga1s = BF16 ? reinterpret_cast<HT*>(smem + M::OFF_S2) : h1s;
-    uint16_t* ga1c = reinterpret_cast<uint16_t*>(smem + M::OFF_S3);
+    // BF16: into S1 (h2 is dead); FP32: in place over h1.
+    HT* ga1s = BF16 ? reinterpret_cast<HT*>(smem + M::OFF_S1) : h1s;
     {
       u32x4 A[LF.nct][LF.k2];
 #pragma unroll
@@ -619,12 +621,11 @@ __global__ void __launch_bounds__(NT) kf_backward(
               if (c0 < C) {
                 float v[4];
                 if constexpr (BF16) {
-                  float hh[4];
-#pragma unroll
-                  for (int i = 0; i < 4; ++i) hh[i] = __uint_as_float((uint32_t)h1c[(c0 + i) * CSTR + n] << 16);
+                  const u32x2 hv = *reinterpret_cast<const u32x2*>(h1s + p * C + c0);
+                  const float hh[4] = {bf16_lo(hv[0]), bf16_hi(hv[0]), bf16_lo(hv[1]), bf16_hi(hv[1])};
 #pragma unroll
                   for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-                  store_cm4<C, CSTR>(ga1c, n, c0, store4_tile<LY, C, BF16>(ga1s, tile, m, c0, v));
+                  store4_tile<LY, C, BF16>(ga1s, tile, m, c0, v);
                 } else {
                   const f32x4 hh = *reinterpret_cast<const f32x4*>(h1s + p * C + c0);
 #pragma unroll
@@ -648,7 +649,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
           const int c = mt * 16 + m;
           if constexpr (BF16) {
             const int s0 = kc * 32 + 8 * j;
-            const u32x4 a = c < C ? *reinterpret_cast<const u32x4*>(ga1c + c * CSTR + s0) : u32x4{0u, 0u, 0u, 0u};
+            const u32x4 a = load_tr8<LY, C, 1>(ga1s, s0, mt * 16, -1, m);
 #pragma unroll
             for (int nt = 0; nt < NTL1; ++nt) {
               const int tap = nt * 16 + m;

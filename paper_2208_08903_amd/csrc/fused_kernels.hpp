@@ -162,6 +162,33 @@ __device__ __forceinline__ u32x4 gather_tri_x(const float* xs, int n, int p, int
   }
 }
 
+// MFMA operand whose K slots are 8 consecutive sites: lane (j, m) receives channel
+// ch0 + m of sites s .. s + 7 (s = the lane group's first site), each displaced by
+// SIGN * d_tap (tap < 0: not displaced), from a site-major BF16 tensor (layout LY,
+// C channels).  Two transposing LDS reads (ds_read_b64_tr_b16): within a group of
+// 16 lanes, lane r addresses four elements M[r] and lane i receives M[4k + i/4][i%4]
+// in slot k; lane r = 4k + q addresses channels ch0 + 4q .. ch0 + 4q + 3 of site
+// s + k, so lane i gets channel ch0 + i of sites s .. s + 3 (then s + 4 .. s + 7).
+// Channels at or past C read the next stored site (finite values in rows or
+// columns of the product that are discarded).
+template <class LY, int C, int SIGN>
+__device__ __forceinline__ u32x4 load_tr8(const uint16_t* hs, int s, int ch0, int tap, int m) {
+  typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+  const int k = m >> 2, q = m & 3;
+  const int n1 = s + k, n2 = s + 4 + k;
+  int p1 = LY::idx(n1), p2 = LY::idx(n2);
+  if (tap >= 0) {
+    p1 = LY::nbr(n1, p1, tap, SIGN);
+    p2 = LY::nbr(n2, p2, tap, SIGN);
+  }
+  const bf16x4 v1 = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
+      (lds_bf16x4*)(const_cast<uint16_t*>(hs + p1 * C + ch0 + 4 * q)));
+  const bf16x4 v2 = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
+      (lds_bf16x4*)(const_cast<uint16_t*>(hs + p2 * C + ch0 + 4 * q)));
+  const u32x2 a = __builtin_bit_cast(u32x2, v1), b = __builtin_bit_cast(u32x2, v2);
+  return u32x4{a[0], a[1], b[0], b[1]};
+}
+
 template <bool BF16>
 __device__ __forceinline__ f32x4 mma(const u32x4& a, const u32x4& b, f32x4 acc) {
   if constexpr (BF16) {
