@@ -250,6 +250,18 @@ def trained_example(steps=20000):
             acc, sec = fl.acceptance_rate(f.with_precision(sp), -4.0, 8.0, batches=16, B=4096)
             row[f"acceptance_sampled_{sname}"] = round(acc, 5)
             row[f"accepted_per_s_sampled_{sname}"] = round(acc * 16 * 4096 / sec, 1)
+        if prec == lfs.LFS_BF16_CONV:
+            # chain quality of the trained flow against HMC on the same theory (same GPU)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cq = fl.chain_quality(f, -4.0, 8.0, batches=16, B=4096)
+            torch.cuda.synchronize()
+            cq["seconds"] = round(time.perf_counter() - t0, 3)
+            t0 = time.perf_counter()
+            hq = fl.hmc_chain_quality(2, 8, -4.0, 8.0, n_chains=256, n_traj=2500)
+            torch.cuda.synchronize()
+            hq["seconds"] = round(time.perf_counter() - t0, 3)
+            row["chain_quality"] = {"flow_mh": cq, "hmc": hq}
         out[f"trained_{name}"] = row
     return out
 

@@ -253,6 +253,64 @@ int32_t lfs_hmc_step(int32_t dim, int32_t L, int32_t B, double* phi, const doubl
 int32_t lfs_adam_step(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
                       float b2, float eps, int64_t t, void* stream);
 
+/* ---- chain-quality analysis ----------------------------------------------
+ * Sec. 1: the statistical error of a Monte Carlo average falls as
+ * 1/sqrt(N_indep) with N_indep = N_conf / (2 tau_ac), tau_ac the autocorrelation
+ * time; Sec. 2.2 and the conclusions name the condensate, zero-momentum
+ * two-point functions, the autocorrelation time and the effective sample size
+ * as the analysis quantities, without formulas.  The estimators below are the
+ * standard ones, named in each comment.  All sums are FP64 in a fixed order
+ * (bitwise reproducible). */
+
+/* Per-configuration observables.  Time runs along the first lattice axis:
+ * Phi_b(t) is the sum of phi[b] over the L^(d-1) sites whose first coordinate
+ * is t (a contiguous block in the row-major field layout).
+ *   M[b]    = (1/V) sum_n phi[b][n]                       (condensate)
+ *   C[b][t] = (1/V) sum_{t0} Phi_b(t0) Phi_b((t0 + t) mod L),  t = 0 .. L-1
+ *             (zero-momentum two-point function of one configuration; ensemble
+ *             means and the connected part are formed over configurations)
+ *   phi  [B][V] FP32 (fp64 == 0) or FP64 (fp64 != 0), device
+ *   M    [B] FP64 output or NULL;  C  [B][L] FP64 output or NULL (not both NULL)
+ * B == 0 is a no-op.  Errors: EINVAL (dim not 2 or 3, L < 2, B < 0, phi NULL,
+ * both outputs NULL); EUNSUPPORTED if L > 4096. */
+int32_t lfs_observables(int32_t dim, int32_t L, int32_t B, const void* phi, int32_t fp64, double* M,
+                        double* C, void* stream);
+
+/* Bytes of device workspace lfs_autocorr needs (0 for invalid sizes). */
+size_t lfs_autocorr_workspace_bytes(int32_t n_series, int64_t n, int32_t w_max);
+
+/* Integrated autocorrelation time of n_series series of length n (the windowed
+ * estimator with the automatic window of Madras and Sokal):
+ *   xbar = (1/n) sum_k x_k,  Gamma(t) = (1/(n-t)) sum_{k<n-t} (x_k - xbar)(x_{k+t} - xbar)
+ *   tau(W) = 1/2 + sum_{t=1..W} Gamma(t)/Gamma(0); the window W is the smallest
+ *   W >= 1 with W >= c tau(W), searched up to T = min(w_max, n-1); if none,
+ *   W = T and found = 0.  tau_ac = tau(W), N_indep = n / (2 tau_ac).
+ * Element k of series s is x[s*ldx + k], or x[s*ldx + index[s*n + k]] when
+ * index is given (e.g. an MH chain's current-configuration numbers, so that
+ * repeated configurations are read in place).
+ *   x        FP64 device, series s at x + s*ldx (ldx >= n without index)
+ *   index    [n_series][n] int64 device, or NULL; an entry outside [0, ldx)
+ *            makes that series' gamma, tau and n_indep NaN and its window -1
+ *   gamma    [n_series][w_max+1] FP64 output or NULL (lags beyond T: NaN)
+ *   tau      [n_series] FP64 output (NaN when Gamma(0) == 0: constant series, n == 1)
+ *   window   [n_series] int32 output or NULL (0 when Gamma(0) == 0)
+ *   found    [n_series] uint8 output or NULL;  n_indep [n_series] FP64 output or NULL
+ *   ws       lfs_autocorr_workspace_bytes(n_series, n, w_max) bytes of device memory
+ * Errors: EINVAL (n_series < 1, n < 1, w_max < 0, c <= 0, ldx too small, x,
+ * tau or ws NULL); EWORKSPACE; EUNSUPPORTED if w_max > 8192 or n_series > 65535. */
+int32_t lfs_autocorr(int32_t n_series, int64_t n, const double* x, int64_t ldx, const int64_t* index,
+                     int32_t w_max, double c, double* gamma, double* tau, int32_t* window,
+                     uint8_t* found, double* n_indep, void* ws, size_t ws_bytes, void* stream);
+
+/* Normalised reweighting effective sample size of n_series sets of n
+ * log-weights w = log p - log q (up to a constant, e.g. lfs_log_weights):
+ *   ESS = (sum_k e^{w_k})^2 / (n sum_k e^{2 w_k})  in [1/n, 1],
+ * evaluated with w_k - max_k w_k.  Entries must be finite or -inf; all -inf
+ * gives NaN.
+ *   logw  FP64 device, set s at logw + s*ldw;  ess  [n_series] FP64 output
+ * Errors: EINVAL (n_series < 1, n < 1, ldw < n, NULLs). */
+int32_t lfs_ess(int32_t n_series, int64_t n, const double* logw, int64_t ldw, double* ess, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

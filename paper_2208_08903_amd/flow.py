@@ -10,6 +10,10 @@ one of the library's entry points (see ``lfs``):
 
   sampling (paper Sec. 1, flow proposals + Metropolis-Hastings test)
       prior_normal -> flow_forward -> action -> log_weights -> mh_chain
+
+  chain quality (paper Sec. 1, N_indep = N / (2 tau_ac); Sec. 2.2, HMC "to
+  compare results"): observables of every configuration, then autocorr over
+  the chain (through the MH chain's current-configuration numbers) and ess.
 """
 from __future__ import annotations
 
@@ -176,3 +180,80 @@ def acceptance_rate(flow: Flow, m2: float, lam: float, batches: int, B: int, key
         smp.step(lu[k])
     torch.cuda.synchronize()
     return smp.acceptance()[0], time.perf_counter() - t0
+
+
+def _log_u(rng, shape, device):
+    u = rng.random(shape)
+    return torch.as_tensor(np.log(np.where(u == 0, np.nextafter(0, 1), u)), device=device)
+
+
+def _tau(x, w_max, c, index=None):
+    """tau_ac, window, found, N_indep of each row of x (through index if given)."""
+    S = x.shape[0]
+    o = [torch.empty(S, dtype=torch.float64, device=x.device), torch.empty(S, dtype=torch.int32, device=x.device),
+         torch.empty(S, dtype=torch.uint8, device=x.device), torch.empty(S, dtype=torch.float64, device=x.device)]
+    lfs.autocorr(x, w_max, c, o[0], o[1], o[2], o[3], index=index)
+    return [t.cpu().numpy() for t in o]
+
+
+def chain_quality(flow: Flow, m2: float, lam: float, batches: int, B: int, w_max=2000, c=6.0,
+                  key=4242, u_seed=78):
+    """One independence-MH chain over batches x B flow proposals.  Along the chain:
+    the integrated autocorrelation time (automatic window, factor c) of the
+    condensate M and of the action S, N_indep = N / (2 tau); plus the acceptance
+    and the normalised reweighting ESS of all proposals."""
+    dev, n = flow.device, batches * B
+    f64 = torch.float64
+    M = torch.empty(1, n, dtype=f64, device=dev)
+    S = torch.empty(1, n, dtype=f64, device=dev)
+    logw = torch.empty(1, n, dtype=f64, device=dev)
+    cur = torch.empty(1, n, dtype=torch.int64, device=dev)
+    lu = _log_u(np.random.default_rng(u_seed), (batches, 1, B), dev)
+    smp = Sampler(flow, B, m2, lam, key=key)
+    for k in range(batches):
+        sl = slice(k * B, (k + 1) * B)
+        smp.step(lu[k])
+        lfs.observables(flow.dim, flow.L, smp.phi, M[0, sl], None)
+        S[0, sl].copy_(smp.S)
+        logw[0, sl].copy_(smp.logw)
+        cur[0, sl].copy_(smp.cur[0])
+    tm, wm, fm, nm = _tau(M, w_max, c, index=cur)
+    ts, ws, fs, ns = _tau(S, w_max, c, index=cur)
+    e = torch.empty(1, dtype=f64, device=dev)
+    lfs.ess(logw, e)
+    return {"proposals": n, "acceptance": round(smp.acceptance()[0], 5),
+            "tau_M": float(tm[0]), "window_M": int(wm[0]), "window_found_M": bool(fm[0]),
+            "n_indep_M": float(nm[0]), "tau_S": float(ts[0]), "window_S": int(ws[0]),
+            "window_found_S": bool(fs[0]), "n_indep_S": float(ns[0]), "ess": float(e.item())}
+
+
+def hmc_chain_quality(dim: int, L: int, m2: float, lam: float, n_chains: int, n_traj: int,
+                      n_steps=10, dt=0.1, w_max=2000, c=6.0, seed=91):
+    """n_chains independent HMC chains (FP64, n_steps leapfrog steps of dt per
+    trajectory, fresh momenta each trajectory) from a cold start phi = 0; the
+    first n_traj // 5 trajectories are discarded.  Per chain, the integrated
+    autocorrelation time of M over the remaining trajectories; returns the chain
+    means and the acceptance."""
+    import seeded_inputs as si
+    dev, V, f64 = "cuda", L ** dim, torch.float64
+    phi = torch.zeros(n_chains, V, dtype=f64, device=dev)
+    m2t = torch.tensor([m2], dtype=f64, device=dev)
+    lamt = torch.tensor([lam], dtype=f64, device=dev)
+    dH = torch.empty(n_chains, dtype=f64, device=dev)
+    acc = torch.empty(n_chains, dtype=torch.uint8, device=dev)
+    therm = n_traj // 5
+    n = n_traj - therm
+    Mt = torch.empty(n, n_chains, dtype=f64, device=dev)
+    lu = _log_u(np.random.default_rng(seed), (n_traj, n_chains), dev)
+    n_acc = torch.zeros(n_chains, dtype=torch.int64, device=dev)
+    for k in range(n_traj):
+        pi = torch.as_tensor(si.momenta(seed * 100003 + k, n_chains, V), device=dev)
+        lfs.hmc_step(dim, L, phi, pi, lu[k], m2t, lamt, n_steps, dt, dH, acc)
+        if k >= therm:
+            lfs.observables(dim, L, phi, Mt[k - therm], None)
+            n_acc += acc
+    tm, wm, fm, _ = _tau(Mt.t().contiguous(), w_max, c)
+    return {"chains": n_chains, "trajectories": n, "leapfrog_steps": n_steps, "dt": dt,
+            "acceptance": float(n_acc.sum().item()) / (n * n_chains),
+            "tau_M_mean": float(np.nanmean(tm)), "window_found_M": int(fm.sum()),
+            "n_indep_M_per_chain_mean": float(np.nanmean(n / (2 * tm)))}

@@ -63,6 +63,11 @@ _SIGS = {
                              c_f64, c_vp, c_vp, c_vp]),
     "lfs_adam_step": (c_i32, [c_i64, c_vp, c_vp, c_vp, c_vp, c_f32, c_f32, c_f32, c_f32, c_i64,
                               c_vp]),
+    "lfs_observables": (c_i32, [c_i32, c_i32, c_i32, c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "lfs_autocorr_workspace_bytes": (c_sz, [c_i32, c_i64, c_i32]),
+    "lfs_autocorr": (c_i32, [c_i32, c_i64, c_vp, c_i64, c_vp, c_i32, c_f64, c_vp, c_vp, c_vp, c_vp,
+                             c_vp, c_vp, c_sz, c_vp]),
+    "lfs_ess": (c_i32, [c_i32, c_i64, c_vp, c_i64, c_vp, c_vp]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -233,3 +238,47 @@ def adam_step(p, g, m, v, lr, b1, b2, eps, t):
     _check(load().lfs_adam_step(p.numel(), _p(p, torch.float32, "p"), _p(g, torch.float32, "g"),
                                 _p(m, torch.float32, "m"), _p(v, torch.float32, "v"), lr, b1, b2,
                                 eps, t, _stream()))
+
+
+def observables(dim, L, phi, M=None, C=None):
+    """Condensate M [B] and zero-momentum two-point function C [B, L] (FP64) of phi [B, V]."""
+    if phi.dtype not in (torch.float32, torch.float64):
+        raise LfsError("phi must be float32 or float64")
+    B = phi.shape[0]
+    _check(load().lfs_observables(dim, L, B, _p(phi, None, "phi"), int(phi.dtype == torch.float64),
+                                  _p(M, torch.float64, "M"), _p(C, torch.float64, "C"), _stream()))
+
+
+def autocorr_workspace_bytes(n_series: int, n: int, w_max: int) -> int:
+    return int(load().lfs_autocorr_workspace_bytes(n_series, n, w_max))
+
+
+def autocorr(x, w_max: int, c: float, tau, window=None, found=None, n_indep=None, gamma=None,
+             index=None, n=None, ws=None):
+    """Windowed integrated autocorrelation time of the rows of x [n_series, ldx] (FP64).
+
+    Without index the series are the first n (default: all) entries of each row;
+    with index [n_series, n] (int64) entry k of series s is x[s, index[s, k]]."""
+    n_series, ldx = x.shape
+    if index is not None:
+        n = index.shape[1]
+    elif n is None:
+        n = ldx
+    need = autocorr_workspace_bytes(n_series, n, w_max)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    _check(load().lfs_autocorr(n_series, n, _p(x, torch.float64, "x"), ldx,
+                               _p(index, torch.int64, "index"), w_max, float(c),
+                               _p(gamma, torch.float64, "gamma"), _p(tau, torch.float64, "tau"),
+                               _p(window, torch.int32, "window"), _p(found, torch.uint8, "found"),
+                               _p(n_indep, torch.float64, "n_indep"), _p(ws, torch.uint8, "ws"),
+                               ws.numel(), _stream()))
+
+
+def ess(logw, out):
+    """Normalised reweighting ESS of each row of logw [n_series, n] (FP64) into out [n_series]."""
+    if logw.dim() == 1:
+        logw = logw.reshape(1, -1)
+    n_series, n = logw.shape
+    _check(load().lfs_ess(n_series, n, _p(logw, torch.float64, "logw"), n,
+                          _p(out, torch.float64, "ess"), _stream()))

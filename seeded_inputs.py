@@ -86,6 +86,18 @@ def logw_stream(seed: int, n: int, scale: float = 1.0) -> np.ndarray:
     return scale * np.random.default_rng(seed).standard_normal(n)
 
 
+def correlated_series(seed: int, n_series: int, n: int, a: float) -> np.ndarray:
+    """FP64 [n_series, n] stationary AR(1) series x_k = a x_{k-1} + sqrt(1 - a^2) e_k,
+    inputs with a known autocorrelation for the analysis tests."""
+    e = np.random.default_rng(seed).standard_normal((n_series, n))
+    x = np.empty_like(e)
+    x[:, 0] = e[:, 0]
+    s = math.sqrt(1.0 - a * a)
+    for k in range(1, n):
+        x[:, k] = a * x[:, k - 1] + s * e[:, k]
+    return x
+
+
 # ---------------------------------------------------------------------------
 # Serving workload: Poisson arrivals of sampling requests.
 # ---------------------------------------------------------------------------

@@ -78,6 +78,26 @@ def test_null_and_shape_arguments_rejected_before_any_launch():
     assert lib.lfs_hmc_step(3, 20, 1, 1, 1, 1, 1, 1, 0, 10, 0.1, 1, 1, None) == -2  # V > 4096
     assert lib.lfs_adam_step(0, None, None, None, None, 1e-3, 0.9, 0.999, 1e-8, 1, None) == -1
     assert lib.lfs_adam_step(10, 1, 1, 1, 1, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1  # t < 1
+    assert lib.lfs_observables(4, 8, 2, 1, 0, 1, None, None) == -1           # dim
+    assert lib.lfs_observables(2, 8, 2, 1, 0, None, None, None) == -1        # no output
+    assert lib.lfs_observables(2, 4097, 2, 1, 0, 1, None, None) == -2        # L too large
+    assert lib.lfs_observables(2, 8, 0, 1, 0, 1, None, None) == 0            # empty batch
+    assert lib.lfs_autocorr_workspace_bytes(0, 100, 10) == 0
+    big = 1 << 40
+    assert lib.lfs_autocorr(0, 100, 1, 100, None, 10, 6.0, None, 1, None, None, None, 1, big,
+                            None) == -1                                      # n_series
+    assert lib.lfs_autocorr(1, 100, 1, 50, None, 10, 6.0, None, 1, None, None, None, 1, big,
+                            None) == -1                                      # ldx < n
+    assert lib.lfs_autocorr(1, 100, 1, 100, None, 10, 0.0, None, 1, None, None, None, 1, big,
+                            None) == -1                                      # c <= 0
+    assert lib.lfs_autocorr(1, 100, 1, 100, None, 9000, 6.0, None, 1, None, None, None, 1, big,
+                            None) == -2                                      # w_max
+    need = lib.lfs_autocorr_workspace_bytes(3, 5000, 300)
+    assert need > 0
+    assert lib.lfs_autocorr(3, 5000, 1, 5000, None, 300, 6.0, None, 1, None, None, None, 1,
+                            need - 1, None) == -3                            # workspace
+    assert lib.lfs_ess(1, 10, 1, 9, 1, None) == -1                           # ldw < n
+    assert lib.lfs_ess(1, 0, 1, 9, 1, None) == -1                            # n < 1
 
 
 def test_workspace_too_small_is_reported():
