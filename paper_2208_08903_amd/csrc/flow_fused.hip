@@ -80,9 +80,11 @@ __global__ void __launch_bounds__(NT) kf_forward(
             },
             [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
-              for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16>(h1, tile, m, ct, j, acc[ct]);
+              for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16, false>(h1, tile, m, ct, j, acc[ct]);
             });
       }
+      __syncthreads();
+      fill_halo<LY, C, BF16, NT>(h1);
       __syncthreads();
       // conv2 over all sites
       {
@@ -101,9 +103,11 @@ __global__ void __launch_bounds__(NT) kf_forward(
             },
             [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
-              for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16>(h2, tile, m, ct, j, acc[ct]);
+              for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16, false>(h2, tile, m, ct, j, acc[ct]);
             });
       }
+      __syncthreads();
+      fill_halo<LY, C, BF16, NT>(h2);
       __syncthreads();
       // conv3 at the active sites, affine update and log-det
       if constexpr (Cfg::X4) {

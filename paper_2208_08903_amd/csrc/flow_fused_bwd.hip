@@ -317,9 +317,11 @@ __global__ void __launch_bounds__(NT) kf_backward(
           },
           [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
-            for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16>(h1s, tile, m, ct, j, acc[ct]);
+            for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16, false>(h1s, tile, m, ct, j, acc[ct]);
           });
     }
+    __syncthreads();
+    fill_halo<LY, C, BF16, NT>(h1s);
     __syncthreads();
     // ---- recompute conv2 -> h2 ----
     {
@@ -338,9 +340,11 @@ __global__ void __launch_bounds__(NT) kf_backward(
           },
           [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
-            for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16>(h2s, tile, m, ct, j, acc[ct]);
+            for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16, false>(h2s, tile, m, ct, j, acc[ct]);
           });
     }
+    __syncthreads();
+    fill_halo<LY, C, BF16, NT>(h2s);
     // ---- recompute conv3 at active sites; affine backward -> g_o, g_x(active) ----
     // g_o is zero at the frozen sites.
     uint32_t* gos_b = reinterpret_cast<uint32_t*>(smem + M::OFF_GOS);  // BF16 pairs, layout LY
@@ -533,13 +537,13 @@ __global__ void __launch_bounds__(NT) kf_backward(
                   const float hh[4] = {bf16_lo(hv[0]), bf16_hi(hv[0]), bf16_lo(hv[1]), bf16_hi(hv[1])};
 #pragma unroll
                   for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-                  const u32x2 gv = store4_tile<LY, C, BF16>(ga2s, tile, m, c0, v);
+                  const u32x2 gv = store4_tile<LY, C, BF16, false>(ga2s, tile, m, c0, v);
                   if constexpr (M::CM2) store_cm4<C, CSTR>(ga2c, n, c0, gv);
                 } else {
                   const f32x4 hh = *reinterpret_cast<const f32x4*>(h2s + p * C + c0);
 #pragma unroll
                   for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-                  store4_tile<LY, C, BF16>(ga2s, tile, m, c0, v);
+                  store4_tile<LY, C, BF16, false>(ga2s, tile, m, c0, v);
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) db2[ct][i] += v[i];
@@ -547,6 +551,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
             }
           });
     }
+    __syncthreads();
+    fill_halo<LY, C, BF16, NT>(ga2s);
     __syncthreads();
     // ---- dW2[co][ci][tap] += sum_m h1[m][ci] g_a2[m - delta_tap][co] ----
     // tiles (mt, tap, nt): rows ci = mt*16 + i, columns co = nt*16 + m; the taps are
@@ -625,12 +631,12 @@ __global__ void __launch_bounds__(NT) kf_backward(
                   const float hh[4] = {bf16_lo(hv[0]), bf16_hi(hv[0]), bf16_lo(hv[1]), bf16_hi(hv[1])};
 #pragma unroll
                   for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-                  store4_tile<LY, C, BF16>(ga1s, tile, m, c0, v);
+                  store4_tile<LY, C, BF16, false>(ga1s, tile, m, c0, v);
                 } else {
                   const f32x4 hh = *reinterpret_cast<const f32x4*>(h1s + p * C + c0);
 #pragma unroll
                   for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
-                  store4_tile<LY, C, BF16>(ga1s, tile, m, c0, v);
+                  store4_tile<LY, C, BF16, false>(ga1s, tile, m, c0, v);
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) db1[ct][i] += v[i];
@@ -639,6 +645,9 @@ __global__ void __launch_bounds__(NT) kf_backward(
           });
     }
     __syncthreads();
+    // g_a1's halo (for conv1^T's gathers) is filled alongside dW1, which reads
+    // interior sites only
+    fill_halo<LY, C, BF16, NT>(ga1s);
     // ---- dW1[c][tap] += sum_n g_a1[n][c] h0[n + delta_tap] (h0 = mask_F x) ----
     // tiles (mt, nt): rows c = mt*16 + i, columns tap = nt*16 + m
     {
@@ -676,6 +685,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
         }
       }
     }
+    __syncthreads();
     // ---- conv1^T at the frozen sites: g_x = g_y + W1^T * g_a1 ----
     {
       u32x4 A[LF.k2];

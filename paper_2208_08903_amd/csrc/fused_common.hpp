@@ -153,7 +153,50 @@ struct Lay {
       return (((pz + L - 1) % L) * L + (py + L - 1) % L) * L + (px + L - 1) % L;
     }
   }
-  // Calls f(storage index) for every stored copy of site n.
+  // Halo entries of the padded layout: every storage position with a coordinate
+  // 0 or LP - 1.  halo_entry(h) gives the h-th one (h < NHALO) and the storage
+  // index of the interior position it mirrors (coordinate 0 mirrors L, LP - 1
+  // mirrors 1).  2D: rows 0 and LP - 1 whole, then columns 0 and LP - 1 of the
+  // interior rows.  3D: planes 0 and LP - 1 whole, then each interior plane's
+  // 2D halo.
+  static constexpr int RING2 = 2 * LP + 2 * L;
+  static constexpr int NHALO = DIM == 2 ? RING2 : 2 * LP * LP + L * RING2;
+  __device__ static __forceinline__ int mirror(int c) { return c == 0 ? L : (c == LP - 1 ? 1 : c); }
+  __device__ static __forceinline__ void ring2(int r, int& y, int& x) {
+    if (r < 2 * LP) {
+      y = r < LP ? 0 : LP - 1;
+      x = r < LP ? r : r - LP;
+    } else {
+      y = 1 + ((r - 2 * LP) >> 1);
+      x = (r & 1) ? LP - 1 : 0;
+    }
+  }
+  __device__ static __forceinline__ void halo_entry(int h, int& dst, int& src) {
+    int z = 0, y, x;
+    if constexpr (DIM == 2) {
+      ring2(h, y, x);
+    } else if (h < 2 * LP * LP) {
+      const int r = h < LP * LP ? h : h - LP * LP;
+      z = h < LP * LP ? 0 : LP - 1;
+      y = r / LP;
+      x = r - y * LP;
+    } else {
+      const int r = h - 2 * LP * LP;
+      z = 1 + r / RING2;
+      ring2(r - (z - 1) * RING2, y, x);
+    }
+    if constexpr (DIM == 2) {
+      dst = y * LP + x;
+      src = mirror(y) * LP + mirror(x);
+    } else {
+      dst = (z * LP + y) * LP + x;
+      src = (mirror(z) * LP + mirror(y)) * LP + mirror(x);
+    }
+  }
+  // Calls f(storage index) for every stored copy of site n.  Lanes whose site
+  // has a mirror run every mirror combination without branching: a combination
+  // that needs a mirror the site lacks keeps its own coordinate there, so it
+  // lands on a copy that is stored anyway (f must be an idempotent store).
   template <class F>
   __device__ static __forceinline__ void copies(int n, F&& f) {
     f(idx(n));
@@ -174,46 +217,51 @@ struct Lay {
       if (any) {
 #pragma unroll
         for (int msk = 1; msk < (1 << DIM); ++msk) {
-          bool ok = true;
           int p = 0;
 #pragma unroll
           for (int mu = 0; mu < DIM; ++mu) {
             const bool alt = (msk >> (DIM - 1 - mu)) & 1;
-            const int pc = alt ? a[mu] : c[mu] + 1;
-            ok &= pc >= 0;
-            p = p * LP + pc;
+            p = p * LP + (alt && a[mu] >= 0 ? a[mu] : c[mu] + 1);
           }
-          if (ok) f(p);
+          f(p);
         }
       }
     }
   }
-  // copies(16 tile + m, f) for lane m of a 16-site tile.  When rows hold whole
-  // tiles only the x mirror depends on the lane; the row and plane mirrors
-  // are decided once per tile.  A mirror of coordinate 0 sits L storage
-  // steps above it, one of coordinate L-1 L steps below.
+  // copies(16 tile + m, f) for lane m of a 16-site tile, without divergent
+  // branches: every lane stores its x mirror, and a lane away from the x edges
+  // stores its own site again instead (f must be an idempotent store).  A tile
+  // lies in one plane and spans whole rows or part of one, so whether it meets
+  // a y or z edge is decided once per tile; its lanes then store their y (or z)
+  // mirror, again falling back to their own site.  A mirror of coordinate 0
+  // sits L storage steps above it, one of coordinate L-1 L steps below.
   template <class F>
   __device__ static __forceinline__ void copies_tile(int tile, int m, F&& f) {
-    if constexpr (PAD && L % 16 == 0) {
-      const int n0 = tile * 16, x = n0 % L + m, p = idx(n0) + m;
+    if constexpr (PAD && (L % 16 == 0 || 16 % L == 0)) {
+      constexpr int R = L >= 16 ? 1 : 16 / L;  // rows per tile
+      const int n0 = tile * 16;                // wave-uniform
+      const int x = L >= 16 ? n0 % L + m : m % L;
+      const int p = L >= 16 ? idx(n0) + m : idx(n0 + m);
       const int ax = x == 0 ? L : (x == L - 1 ? -L : 0);
-      const int y = (n0 / L) % L;
-      const int ay = y == 0 ? L * LP : (y == L - 1 ? -L * LP : 0);
       f(p);
-      if (ax) f(p + ax);
-      if (ay) {
+      f(p + ax);
+      const int y0 = (n0 / L) % L;
+      const int y = L >= 16 ? y0 : y0 + m / L;
+      const int ay = y == 0 ? L * LP : (y == L - 1 ? -L * LP : 0);
+      const bool yedge = y0 == 0 || y0 + R - 1 == L - 1;
+      if (yedge) {
         f(p + ay);
-        if (ax) f(p + ay + ax);
+        f(p + ay + ax);
       }
       if constexpr (DIM == 3) {
         const int z = n0 / (L * L);
         const int az = z == 0 ? L * LP * LP : (z == L - 1 ? -L * LP * LP : 0);
         if (az) {
           f(p + az);
-          if (ax) f(p + az + ax);
-          if (ay) {
+          f(p + az + ax);
+          if (yedge) {
             f(p + az + ay);
-            if (ax) f(p + az + ay + ax);
+            f(p + az + ay + ax);
           }
         }
       }

@@ -227,24 +227,50 @@ __device__ __forceinline__ u32x2 store_hidden(HElem<BF16>* h, int n, int ct, int
   return store4<LY, C, BF16>(h, n, co0, v);
 }
 
-// store4 for lane m of a 16-site tile (all stored copies of its site).
-template <class LY, int C, bool BF16>
+// store4 for lane m of a 16-site tile: all stored copies of its site (HALO), or
+// only the interior one, the halo being filled afterwards by fill_halo.
+template <class LY, int C, bool BF16, bool HALO = true>
 __device__ __forceinline__ u32x2 store4_tile(HElem<BF16>* h, int tile, int m, int co0,
                                              const float (&v)[4]) {
   if constexpr (BF16) {
     const u32x2 wv{pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3])};
-    LY::copies_tile(tile, m, [&](int p) { *reinterpret_cast<u32x2*>(h + p * C + co0) = wv; });
+    if constexpr (HALO)
+      LY::copies_tile(tile, m, [&](int p) { *reinterpret_cast<u32x2*>(h + p * C + co0) = wv; });
+    else
+      *reinterpret_cast<u32x2*>(h + tile_p<LY>(tile, m) * C + co0) = wv;
     return wv;
   } else {
     const f32x4 fv{v[0], v[1], v[2], v[3]};
-    LY::copies_tile(tile, m, [&](int p) { *reinterpret_cast<f32x4*>(h + p * C + co0) = fv; });
+    if constexpr (HALO)
+      LY::copies_tile(tile, m, [&](int p) { *reinterpret_cast<f32x4*>(h + p * C + co0) = fv; });
+    else
+      *reinterpret_cast<f32x4*>(h + tile_p<LY>(tile, m) * C + co0) = fv;
     return u32x2{0u, 0u};
+  }
+}
+
+// Copies every halo entry of a site-major tensor (C channels, layout LY) from
+// the interior position it mirrors, 16 bytes per item, all NT threads.  Runs
+// between the barrier that ends the pass storing the interior and the barrier
+// before the first periodic gather.  Unpadded layouts have no halo.
+template <class LY, int C, bool BF16, int NT>
+__device__ __forceinline__ void fill_halo(HElem<BF16>* h) {
+  if constexpr (LY::padded) {
+    constexpr int EL = BF16 ? 8 : 4;  // elements per 16 bytes
+    static_assert(C % EL == 0, "fill_halo copies whole 16-byte chunks");
+    constexpr int CH = C / EL;
+    for (int i = threadIdx.x; i < LY::NHALO * CH; i += NT) {
+      const int e = i / CH, k = i - e * CH;
+      int dst, src;
+      LY::halo_entry(e, dst, src);
+      *reinterpret_cast<u32x4*>(h + dst * C + k * EL) = *reinterpret_cast<const u32x4*>(h + src * C + k * EL);
+    }
   }
 }
 
 // Store leaky(a) for rows 4j..4j+3 of output-channel tile ct at lane m of a
 // tile; a already holds the bias (the MFMA accumulator starts from it).
-template <class LY, int C, bool BF16>
+template <class LY, int C, bool BF16, bool HALO = true>
 __device__ __forceinline__ u32x2 store_act_tile(HElem<BF16>* h, int tile, int m, int ct, int j,
                                                 const f32x4& a) {
   const int co0 = ct * 16 + 4 * j;
@@ -252,7 +278,7 @@ __device__ __forceinline__ u32x2 store_act_tile(HElem<BF16>* h, int tile, int m,
   float v[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) v[i] = leaky(a[i]);
-  return store4_tile<LY, C, BF16>(h, tile, m, co0, v);
+  return store4_tile<LY, C, BF16, HALO>(h, tile, m, co0, v);
 }
 
 template <int C>
