@@ -463,35 +463,42 @@ __global__ void __launch_bounds__(NT) kf_backward(
     __syncthreads();
     // ---- dW3[co][ci][tap] += sum_m h2[m][ci] g_o[m - delta_tap][co] ----
     // tiles (mt, nt): rows ci = mt*16 + i, columns (tap, co) = nt*16 + m
-    for (int kc = kc0; kc < kc1; ++kc) {
+    // FP32 writes g_a2 over h2, which dW3 reads, so dW3 goes first; BF16 keeps
+    // them apart and runs dW3 after conv3^T, next to g_a2's halo fill.
+    auto dw3 = [&]() {
+      for (int kc = kc0; kc < kc1; ++kc) {
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int ci = mt * 16 + m;
-        if constexpr (BF16) {
-          const int s0 = kc * 32 + 8 * j;
-          const u32x4 a = load_tr8<LY, C, 1>(h2s, s0, mt * 16, -1, m);
-#pragma unroll
-          for (int nt = 0; nt < NTL3; ++nt) {
-            const int col = nt * 16 + m, tap = col >> 1, co = col & 1;
-            const u32x4 bb = tap < T ? load8_shift<DIM, L>(goc + co * CSTR, s0, tap, -1) : u32x4{0u, 0u, 0u, 0u};
-            acc3[mt * NTL3 + nt] = mfma(as_bf16x8(a), as_bf16x8(bb), acc3[mt * NTL3 + nt]);
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int sx = kc * 16 + 4 * j + r;
-            const float a = ci < C ? h2s[LY::idx(sx) * C + ci] : 0.f;
+        for (int mt = 0; mt < MT; ++mt) {
+          const int ci = mt * 16 + m;
+          if constexpr (BF16) {
+            const int s0 = kc * 32 + 8 * j;
+            const u32x4 a = load_tr8<LY, C, 1>(h2s, s0, mt * 16, -1, m);
 #pragma unroll
             for (int nt = 0; nt < NTL3; ++nt) {
               const int col = nt * 16 + m, tap = col >> 1, co = col & 1;
-              const float bb = tap < T ? load1_shift<LY, 2>(gos_f, sx, co, tap, -1) : 0.f;
-              acc3[mt * NTL3 + nt] = mfma(a, bb, acc3[mt * NTL3 + nt]);
+              const u32x4 bb = tap < T ? load8_shift<DIM, L>(goc + co * CSTR, s0, tap, -1) : u32x4{0u, 0u, 0u, 0u};
+              acc3[mt * NTL3 + nt] = mfma(as_bf16x8(a), as_bf16x8(bb), acc3[mt * NTL3 + nt]);
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int sx = kc * 16 + 4 * j + r;
+              const float a = ci < C ? h2s[LY::idx(sx) * C + ci] : 0.f;
+#pragma unroll
+              for (int nt = 0; nt < NTL3; ++nt) {
+                const int col = nt * 16 + m, tap = col >> 1, co = col & 1;
+                const float bb = tap < T ? load1_shift<LY, 2>(gos_f, sx, co, tap, -1) : 0.f;
+                acc3[mt * NTL3 + nt] = mfma(a, bb, acc3[mt * NTL3 + nt]);
+              }
             }
           }
         }
       }
+    };
+    if constexpr (!BF16) {
+      dw3();
+      __syncthreads();
     }
-    __syncthreads();
     // ---- conv3^T: g_a2 = leaky'(h2) (W3^T * g_o) ----
     // BF16: into S2 (3D also channel-major into S3); FP32: in place over h2.
     HT* ga2s = BF16 ? reinterpret_cast<HT*>(smem + M::OFF_S2) : h2s;
@@ -553,6 +560,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
     }
     __syncthreads();
     fill_halo<LY, C, BF16, NT>(ga2s);
+    if constexpr (BF16) dw3();
     __syncthreads();
     // ---- dW2[co][ci][tap] += sum_m h1[m][ci] g_a2[m - delta_tap][co] ----
     // tiles (mt, tap, nt): rows ci = mt*16 + i, columns co = nt*16 + m; the taps are
