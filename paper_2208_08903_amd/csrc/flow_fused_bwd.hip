@@ -85,9 +85,10 @@ struct BwdCfg {
   using M = BwdLds<DIM, L, C, BF16, PAD>;
   using LY = typename M::LY;
   static constexpr int CSTR = M::CSTR;
-  static constexpr size_t lds_bytes = cmaxz(M::MAIN, (size_t)P_LAYER * 4);
+  // LDS of the sample state (and, after the sample loop, of the partial sums)
+  static constexpr size_t lds_main = cmaxz(M::MAIN, (size_t)P_LAYER * 4);
   // 3D shapes need more than the 256 registers a lane gets at 2 waves per SIMD.
-  static constexpr int NT = (lds_bytes > 80 * 1024 && DIM == 2) ? 512 : 256;
+  static constexpr int NT = (lds_main > 80 * 1024 && DIM == 2) ? 512 : 256;
   static constexpr int NW = NT / 64;
   // Tiles in flight per wave in the tile passes: two where the registers allow
   // (3D shapes, and FP32 C=16 at two waves per SIMD, are already at the limit).
@@ -102,6 +103,17 @@ struct BwdCfg {
   static constexpr int OFF2T = OFF3T + LF.nct * KT3;
   static constexpr int OFF1T = OFF2T + LF.nct * LF.k2;
   static constexpr int FRAGS = OFF1T + LF.k2;
+  // The layer's weight fragments are the same for every sample of the launch:
+  // where they fit next to the sample state without costing a workgroup per
+  // CU, they are copied to LDS once per launch instead of being fetched from
+  // L2 at the start of every pass of every sample.
+  static constexpr size_t RED_STATIC = (size_t)kRedSlices * (NT / kRedSlices + 1) * 4;
+  static constexpr size_t FRAG_BYTES = (size_t)FRAGS * 64 * 16;
+  static constexpr size_t OFF_FRAG = align16(M::MAIN);
+  static constexpr int per_cu(size_t bytes) { return bytes > 160 * 1024 ? 0 : cmin(8, (int)(160 * 1024 / bytes)); }
+  static constexpr bool FRAG_LDS = OFF_FRAG + FRAG_BYTES + RED_STATIC <= 158 * 1024 &&
+                                   per_cu(OFF_FRAG + FRAG_BYTES + RED_STATIC) == per_cu(lds_main + RED_STATIC);
+  static constexpr size_t lds_bytes = FRAG_LDS ? cmaxz(OFF_FRAG + FRAG_BYTES, (size_t)P_LAYER * 4) : lds_main;
   static constexpr int MT = (C + 15) / 16;
   static constexpr int NKC = BF16 ? V / 32 : V / 16;  // K chunks (sites) per sample
   // Weight-gradient output tiles; every wave accumulates all of them over its
@@ -216,7 +228,14 @@ __global__ void __launch_bounds__(NT) kf_backward(
   float* xs = reinterpret_cast<float*>(smem + M::OFF_XS);
   float* gys = reinterpret_cast<float*>(smem + M::OFF_GY);
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
-  const u32x4* fr = frags + lane;
+  const u32x4* fr;
+  if constexpr (Cfg::FRAG_LDS) {
+    u32x4* sfr = reinterpret_cast<u32x4*>(smem + Cfg::OFF_FRAG);
+    for (int i = threadIdx.x; i < Cfg::FRAGS * 64; i += NT) sfr[i] = frags[i];
+    fr = sfr + lane;  // visible after the first sample's staging barrier
+  } else {
+    fr = frags + lane;
+  }
   const int apar = fpar ^ 1;
 
   // The extra zero site of the site-major slots and of g_o: cleared once, never
@@ -274,8 +293,9 @@ __global__ void __launch_bounds__(NT) kf_backward(
   if (prev_partial) grid_reduce<NT>(prev_partial, prev_out, n_parts, Cfg::P_LAYER);
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
-    // Weight fragments are reloaded per phase (L1/L2 hits) rather than kept live
-    // across the whole sample loop, which would need every phase's registers at once.
+    // Weight fragments are reloaded per phase (from LDS, or L1/L2 hits) rather than
+    // kept live across the whole sample loop, which would need every phase's
+    // registers at once.
     asm volatile("" ::: "memory");
     const size_t sb = (size_t)b * V;
     // stage x and g_y; BF16: masked field channel-major for dW1
