@@ -60,21 +60,47 @@ __global__ void __launch_bounds__(NT) kf_forward(
       const u32x4* fl = frags + (size_t)layer * LF.total * 64 + lane;
       const float* pl = params + (size_t)layer * P_layer;
       __syncthreads();
+      // Weight fragments.  Where the registers allow (Cfg::PFA) each pass's are
+      // fetched one pass ahead, so the L2 latency hides behind the previous
+      // pass: conv1's and conv2's here, conv3's when conv2 starts; otherwise
+      // each pass fetches its own.
+      constexpr int NA3 = Cfg::X4 ? 4 : 1;
+      u32x4 A1[LF.nct][LF.k1], A2[LF.nct][LF.k2], A3[NA3][LF.k2];
+      auto load_a1 = [&]() {
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct)
+#pragma unroll
+          for (int c = 0; c < LF.k1; ++c) A1[ct][c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
+      };
+      auto load_a2 = [&]() {
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct)
+#pragma unroll
+          for (int c = 0; c < LF.k2; ++c) A2[ct][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
+      };
+      auto load_a3 = [&]() {
+#pragma unroll
+        for (int c = 0; c < LF.k2; ++c) {
+          A3[0][c] = fl[(LF.off3 + c) * 64];
+#pragma unroll
+          for (int u = 1; u < NA3; ++u) A3[u][c] = fl[(LF.off3q + (u - 1) * LF.k2 + c) * 64];
+        }
+      };
+      if constexpr (Cfg::PFA) {
+        load_a1();
+        load_a2();
+      }
       // conv1 operands (row triples of the masked field) in the (dead) h2 buffer
       build_tri<LY, BF16, NT>(h2, xs, fpar);
       __syncthreads();
       // conv1 over all sites
       {
-        u32x4 A[LF.nct][LF.k1];
+        if constexpr (!Cfg::PFA) load_a1();
         f32x4 bias[LF.nct];
 #pragma unroll
-        for (int ct = 0; ct < LF.nct; ++ct) {
-          bias[ct] = load_bias4<C>(pl + off_b1, ct, j);
-#pragma unroll
-          for (int c = 0; c < LF.k1; ++c) A[ct][c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
-        }
+        for (int ct = 0; ct < LF.nct; ++ct) bias[ct] = load_bias4<C>(pl + off_b1, ct, j);
         mma_tiles<Cfg::TU1, LF.nct, LF.k1, BF16>(
-            V / 16, w, NW, A, bias,
+            V / 16, w, NW, A1, bias,
             [&](int tile, int c) {
               return gather_tri<LY, BF16>(h2, tile * 16 + m, tile_p<LY>(tile, m), c, j);
             },
@@ -88,16 +114,15 @@ __global__ void __launch_bounds__(NT) kf_forward(
       __syncthreads();
       // conv2 over all sites
       {
-        u32x4 A[LF.nct][LF.k2];
+        if constexpr (Cfg::PFA)
+          load_a3();
+        else
+          load_a2();
         f32x4 bias[LF.nct];
 #pragma unroll
-        for (int ct = 0; ct < LF.nct; ++ct) {
-          bias[ct] = load_bias4<C>(pl + off_b2, ct, j);
-#pragma unroll
-          for (int c = 0; c < LF.k2; ++c) A[ct][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
-        }
+        for (int ct = 0; ct < LF.nct; ++ct) bias[ct] = load_bias4<C>(pl + off_b2, ct, j);
         mma_tiles<Cfg::TU2, LF.nct, LF.k2, BF16>(
-            V / 16, w, NW, A, bias,
+            V / 16, w, NW, A2, bias,
             [&](int tile, int c) {
               return gather_h<LY, C, BF16>(h1, tile * 16 + m, tile_p<LY>(tile, m), c, j);
             },
@@ -110,17 +135,12 @@ __global__ void __launch_bounds__(NT) kf_forward(
       fill_halo<LY, C, BF16, NT>(h2);
       __syncthreads();
       // conv3 at the active sites, affine update and log-det
+      if constexpr (!Cfg::PFA) load_a3();
       if constexpr (Cfg::X4) {
         // four tiles share an accumulator: chunk c of tile u uses the fragments with
         // the outputs at rows 4u, 4u+1, so lane group j ends with tile j's s and t
         // and the epilogue runs on all 64 lanes (two chains: tiles 0-1 and 2-3)
-        u32x4 A[4][LF.k2];
-#pragma unroll
-        for (int c = 0; c < LF.k2; ++c) {
-          A[0][c] = fl[(LF.off3 + c) * 64];
-#pragma unroll
-          for (int u = 1; u < 4; ++u) A[u][c] = fl[(LF.off3q + (u - 1) * LF.k2 + c) * 64];
-        }
+        const auto& A = A3;
         const f32x4 b3{pl[off_b3], pl[off_b3 + 1], 0.f, 0.f};
         const int apar = fpar ^ 1;
         constexpr int NT3 = V / 32;
@@ -150,13 +170,10 @@ __global__ void __launch_bounds__(NT) kf_forward(
           }
         }
       } else {
-        u32x4 A[1][LF.k2];
-#pragma unroll
-        for (int c = 0; c < LF.k2; ++c) A[0][c] = fl[(LF.off3 + c) * 64];
         const f32x4 b3[1] = {f32x4{pl[off_b3], pl[off_b3 + 1], 0.f, 0.f}};
         const int apar = fpar ^ 1;
         mma_tiles<Cfg::TU2, 1, LF.k2, BF16>(
-            V / 32, w, NW, A, b3,
+            V / 32, w, NW, A3, b3,
             [&](int tile, int c) {
               const int n = G::half_site(tile * 16 + m, apar);
               return gather_h<LY, C, BF16>(h2, n, LY::idx(n), c, j);

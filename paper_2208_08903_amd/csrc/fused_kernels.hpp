@@ -346,6 +346,9 @@ struct FwdCfg {
   // placements do not fit the registers) when every wave has four active-site tiles
   static constexpr bool X4 = T == 9 && BF16 && V / 32 >= 4 * (NT / 64);
   static constexpr LayerFrags LF = layer_frags(T, C, BF16, X4);
+  // each pass's weight fragments fetched during the previous pass (2D, C <= 16:
+  // the extra live fragments fit the registers of two waves per SIMD)
+  static constexpr bool PFA = DIM == 2 && C <= 16;
 };
 
 }  // namespace fused
