@@ -42,6 +42,11 @@ KERNEL_SOURCES = ["paper_2208_08903_amd/csrc/flow_fused_bwd.hip",
 TRAFFIC_FILE = "profiles/kf_backward_phi4-2d-L32-train_traffic.txt"
 
 
+def _progress(msg):
+    """One line per finished stage on stderr (the JSON result alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_sha():
     import hashlib
     h = hashlib.sha256()
@@ -404,10 +409,14 @@ def main():
         out["sampling_fp32"] = sampling_rate(fl.Flow(w["dim"], w["L"], w["n_layers"], w["hidden"],
                                                      lfs.LFS_PLAIN_FP32, params=params),
                                              B, w["m2"], w["lam"], batches=4)
+        _progress("headline, FP32 and sampling figures done")
         out["hmc_fp64_3d_L8"] = hmc_rate()
         out["other_workloads"] = other_workloads(params)
+        _progress("other workloads done")
         out["trained_2d_L8_example"] = trained_example()
+        _progress("trained example and chain quality done")
         out["serving"] = serving()
+        _progress("serving done")
     if args.copy_calibration_mb > 0:
         nb = args.copy_calibration_mb * 2 ** 20
         src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
