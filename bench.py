@@ -173,6 +173,51 @@ def hmc_rate(reps=5):
                 acceptance=float(acc.float().mean().item()))
 
 
+def hbm_kernels(reps=20):
+    """Achieved HBM bandwidth of the memory-bound kernels at a bandwidth-bound size: the 3D L=16
+    sampling batch (4096 x 4096 sites) for the prior draw, the action with its force and the
+    observables, and Adam over 16 M parameters.  Bytes are the algorithmic ones (each array read
+    or written once); durations from HIP events on the library's stream."""
+    import torch
+    from paper_2208_08903_amd import lfs
+    B, L, dim = 4096, 16, 3
+    V = L ** dim
+    dev = "cuda"
+    z = torch.empty(B, V, dtype=torch.float32, device=dev)
+    logr = torch.empty(B, dtype=torch.float64, device=dev)
+    S = torch.empty(B, dtype=torch.float64, device=dev)
+    force = torch.empty_like(z)
+    M = torch.empty(B, dtype=torch.float64, device=dev)
+    C = torch.empty(B, L, dtype=torch.float64, device=dev)
+    m2 = torch.tensor([-4.0], dtype=torch.float64, device=dev)
+    lam = torch.tensor([5.0], dtype=torch.float64, device=dev)
+    n = 16 * 2 ** 20
+    p, g = torch.zeros(n, device=dev), torch.full((n,), 1e-3, device=dev)
+    mo, vo = torch.zeros(n, device=dev), torch.zeros(n, device=dev)
+    lfs.prior_normal(5, 0, z, logr)
+    cases = {
+        "prior_normal": (lambda: lfs.prior_normal(5, 0, z, logr), B * V * 4 + B * 8),
+        "action_force_fp64_sums": (lambda: lfs.action(dim, L, z, m2, lam, S, force, 1.0, lfs.LFS_BF16_CONV),
+                                   2 * B * V * 4 + B * 8),
+        "observables": (lambda: lfs.observables(dim, L, z, M, C), B * V * 4 + B * (L + 1) * 8),
+        "adam": (lambda: lfs.adam_step(p, g, mo, vo, 1e-3, 0.9, 0.999, 1e-8, 1), 28 * n),
+    }
+    out = {}
+    for name, (fn, nbytes) in cases.items():
+        for _ in range(3):
+            fn()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        us = 1e3 * s.elapsed_time(e) / reps
+        gbs = nbytes / us / 1e3
+        out[name] = {"bytes": nbytes, "us": round(us, 2), "GB_s": round(gbs, 1), "frac_of_8TB_s": round(gbs / 8000, 3)}
+    return out
+
+
 def other_workloads(params_2d):
     """Side figures for the other workloads: the 2D L=8 example shape (latency of one batch of 64,
     a 2000-proposal chain), the 3D L=8 training step, and 3D L=16 C=32 training at batch 256
@@ -411,6 +456,7 @@ def main():
                                              B, w["m2"], w["lam"], batches=4)
         _progress("headline, FP32 and sampling figures done")
         out["hmc_fp64_3d_L8"] = hmc_rate()
+        out["hbm_kernels"] = hbm_kernels()
         out["other_workloads"] = other_workloads(params)
         _progress("other workloads done")
         out["trained_2d_L8_example"] = trained_example()

@@ -43,18 +43,31 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 
 // One workgroup per configuration.  Time slice t (first coordinate t) is the
 // contiguous block of `slice` = L^(d-1) sites at t * slice; wave w sums slices
-// w, w + 4, ... with its lanes strided over the slice.  Then M = sum_t Phi(t) / V
+// w, w + 4, ... with its lanes strided over the slice, 16 bytes per lane and
+// load when every slice starts 16-byte aligned (vec).  Then M = sum_t Phi(t) / V
 // (slices in order) and C(t) = (1/V) sum_t0 Phi(t0) Phi((t0 + t) mod L) by thread t.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_observables(int L, int slice, const T* __restrict__ phi,
+__global__ void __launch_bounds__(kThreads) k_observables(int L, int slice, int vec, const T* __restrict__ phi,
                                                          double* __restrict__ M, double* __restrict__ C) {
   extern __shared__ double Phi[];  // [L]
+  constexpr int E = 16 / sizeof(T);  // elements per 16 bytes
+  struct alignas(16) Vec { T v[E]; };
   const int b = blockIdx.x, lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const T* f = phi + (size_t)b * L * slice;
   for (int t = w; t < L; t += kWaves) {
     const T* s = f + (size_t)t * slice;
     double acc = 0.0;
-    for (int i = lane; i < slice; i += kWave) acc += (double)s[i];
+    if (vec) {
+      for (int i = lane; i < slice / E; i += kWave) {
+        const Vec x = reinterpret_cast<const Vec*>(s)[i];
+        double part = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) part += (double)x.v[e];
+        acc += part;
+      }
+    } else {
+      for (int i = lane; i < slice; i += kWave) acc += (double)s[i];
+    }
     acc = wave_sum(acc);
     if (lane == 0) Phi[t] = acc;
   }
@@ -227,12 +240,13 @@ extern "C" int32_t lfs_observables(int32_t dim, int32_t L, int32_t B, const void
   if (B == 0) return LFS_OK;
   const int slice = dim == 2 ? L : L * L;
   const size_t shm = (size_t)L * sizeof(double);
+  const int vec = (slice * (fp64 ? 8 : 4)) % 16 == 0 && reinterpret_cast<uintptr_t>(phi) % 16 == 0;
   hipStream_t st = (hipStream_t)stream;
   if (fp64)
-    hipLaunchKernelGGL(lfs::k_observables<double>, dim3(B), dim3(lfs::kThreads), shm, st, L, slice,
+    hipLaunchKernelGGL(lfs::k_observables<double>, dim3(B), dim3(lfs::kThreads), shm, st, L, slice, vec,
                        (const double*)phi, M, C);
   else
-    hipLaunchKernelGGL(lfs::k_observables<float>, dim3(B), dim3(lfs::kThreads), shm, st, L, slice,
+    hipLaunchKernelGGL(lfs::k_observables<float>, dim3(B), dim3(lfs::kThreads), shm, st, L, slice, vec,
                        (const float*)phi, M, C);
   return lfs::launch_status();
 }
