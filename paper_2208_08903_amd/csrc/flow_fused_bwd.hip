@@ -715,7 +715,9 @@ __global__ void __launch_bounds__(NT) kf_backward(
     }
     __syncthreads();
     // ---- conv1^T at the frozen sites: g_x = g_y + W1^T * g_a1 ----
-    {
+    // (3D through the shared tile pass, which also frees registers there; 2D keeps
+    // the plain loop, measured faster at the 2D shapes)
+    if constexpr (DIM == 2) {
       u32x4 A[LF.k2];
 #pragma unroll
       for (int c = 0; c < LF.k2; ++c) A[c] = fr[(Cfg::OFF1T + c) * 64];
@@ -727,6 +729,21 @@ __global__ void __launch_bounds__(NT) kf_backward(
           acc = mma<BF16>(A[c], gather_h<LY, C, BF16, -1>(ga1s, n, p, c, j), acc);
         if (j == 0) gx[sb + n] = gys[n] + acc[0];
       }
+    } else {
+      u32x4 A[1][LF.k2];
+#pragma unroll
+      for (int c = 0; c < LF.k2; ++c) A[0][c] = fr[(Cfg::OFF1T + c) * 64];
+      const f32x4 zero[1] = {};
+      mma_tiles<Cfg::TU, 1, LF.k2, BF16>(
+          V / 32, w, NW, A, zero,
+          [&](int tile, int c) {
+            const int n = G::half_site(tile * 16 + m, fpar);
+            return gather_h<LY, C, BF16, -1>(ga1s, n, LY::idx(n), c, j);
+          },
+          [&](int tile, const f32x4(&acc)[1]) {
+            const int n = G::half_site(tile * 16 + m, fpar);
+            if (j == 0) gx[sb + n] = gys[n] + acc[0][0];
+          });
     }
     __syncthreads();
   }
