@@ -25,12 +25,17 @@ design notes):
     conv(1->C) + LeakyReLU(0.01), conv(C->C) + LeakyReLU(0.01), conv(C->2);
     channel 0 is s (tanh applied when final_tanh), channel 1 is t; kernel 3 per
     axis, periodic padding, cross-correlation with bias; s and t are read at the
-    active sites only.  LeakyReLU'(0) is taken as 1.
+    active sites only.  LeakyReLU'(0) is taken as 1.  The example parameter
+    file's hidden_sizes and kernel_size generalise this: one conv + LeakyReLU
+    per entry of hidden_sizes (default [C, C]), then conv(->2), all with an odd
+    kernel K (default 3) per axis, offsets -K//2 .. K//2.
   * Loss: the batch mean of log q + S with z held fixed (path-wise gradient).
 
 Parameter layout (shared data contract): per layer W1[C][1][T], b1[C],
 W2[C][C][T], b2[C], W3[2][C][T], b3[2]; taps row-major over delta in
-{-1,0,1}^dim, axis 0 slowest.
+{-1,0,1}^dim, axis 0 slowest.  A general network stores, per layer and per
+convolution i in order, W_i[cout_i][cin_i][T] then b_i[cout_i], with T = K^dim
+and taps row-major over {-K//2..K//2}^dim.
 
 Emulated storage precision (emulate = "fp32" or "bf16"; None is plain FP64):
 every convolution's operands -- the input tensor and the weights, in the
@@ -44,7 +49,11 @@ Pinned by: identity and pure-shift flows, a uniform-scale flow whose q is a know
 Gaussian (importance-sampling estimate of a free-field ln Z), invertibility,
 brute-force Jacobian determinants on L <= 4, one-hot convolution orientation,
 hand-computed single-layer values, and central finite differences of the loss
-for the adjoint gradient.
+for the adjoint gradient; for general networks (tests/test_oracle_flow_variants.py)
+the layout, tap order and one-hot orientation for kernels 1, 5 and 7, conv
+adjoints, invertibility, brute-force Jacobians, a hand-computed pointwise layer,
+central finite differences of the loss, and bit-identity of the explicit
+(C, C), kernel-3 network with the default one.
 """
 from __future__ import annotations
 
@@ -68,6 +77,8 @@ class FlowShape:
     hidden: int
     final_tanh: bool = True
     parity0: int = 0
+    kernel: int = 3
+    hidden_sizes: tuple = ()   # empty: (hidden, hidden)
 
     @property
     def V(self) -> int:
@@ -75,22 +86,41 @@ class FlowShape:
 
     @property
     def T(self) -> int:
-        return 3 ** self.dim
+        return self.kernel ** self.dim
+
+    @property
+    def widths(self) -> tuple:
+        return tuple(self.hidden_sizes) if self.hidden_sizes else (self.hidden, self.hidden)
+
+    @property
+    def conv_shapes(self) -> list:
+        """(cout, cin) of every convolution of a layer's network, in order."""
+        w = self.widths
+        return list(zip(w + (2,), (1,) + w))
 
     @property
     def lattice(self) -> tuple:
         return (self.L,) * self.dim
 
 
-def tap_offsets(dim: int):
-    """Offsets delta in {-1,0,1}^dim, row-major (axis 0 slowest)."""
-    return list(itertools.product((-1, 0, 1), repeat=dim))
+def tap_offsets(dim: int, kernel: int = 3):
+    """Offsets delta in {-K//2..K//2}^dim, row-major (axis 0 slowest)."""
+    r = kernel // 2
+    return list(itertools.product(range(-r, r + 1), repeat=dim))
+
+
+def _kernel_of(T: int, dim: int) -> int:
+    K = int(round(T ** (1.0 / dim)))
+    if K ** dim != T:
+        raise ValueError(f"{T} taps is not a cube of an odd kernel in {dim} dimensions")
+    return K
 
 
 def unpack(params, fs: FlowShape):
-    """Split the packed parameter vector into per-layer (W1, b1, W2, b2, W3, b3) in FP64."""
+    """Split the packed parameter vector into per-layer (W1, b1, ..., Wn, bn) in FP64
+    (n = number of convolutions; (W1, b1, W2, b2, W3, b3) for the default network)."""
     p = np.asarray(params, dtype=np.float64).ravel()
-    C, T = fs.hidden, fs.T
+    T = fs.T
     layers, off = [], 0
 
     def take(n, shape):
@@ -100,13 +130,11 @@ def unpack(params, fs: FlowShape):
         return a
 
     for _ in range(fs.n_layers):
-        W1 = take(C * T, (C, 1, T))
-        b1 = take(C, (C,))
-        W2 = take(C * C * T, (C, C, T))
-        b2 = take(C, (C,))
-        W3 = take(2 * C * T, (2, C, T))
-        b3 = take(2, (2,))
-        layers.append((W1, b1, W2, b2, W3, b3))
+        lay = []
+        for co, ci in fs.conv_shapes:
+            lay.append(take(co * ci * T, (co, ci, T)))
+            lay.append(take(co, (co,)))
+        layers.append(tuple(lay))
     if off != p.size:
         raise ValueError(f"parameter vector has {p.size} entries, layout needs {off}")
     return layers
@@ -130,7 +158,7 @@ def conv(u, W, b, dim: int):
     """
     out = np.broadcast_to(b.reshape((1, -1) + (1,) * dim),
                           (u.shape[0], W.shape[0]) + u.shape[2:]).copy()
-    for t, d in enumerate(tap_offsets(dim)):
+    for t, d in enumerate(tap_offsets(dim, _kernel_of(W.shape[2], dim))):
         out += np.einsum("oi,bi...->bo...", W[:, :, t], shifted(u, d, dim))
     return out
 
@@ -138,16 +166,16 @@ def conv(u, W, b, dim: int):
 def conv_transpose(g, W, dim: int):
     """Adjoint of `conv` w.r.t. its input: g_u[b, ci, m] = sum_co sum_t W[co,ci,t] g[b, co, m - delta_t]."""
     out = np.zeros((g.shape[0], W.shape[1]) + g.shape[2:])
-    for t, d in enumerate(tap_offsets(dim)):
+    for t, d in enumerate(tap_offsets(dim, _kernel_of(W.shape[2], dim))):
         out += np.einsum("oi,bo...->bi...", W[:, :, t], shifted(g, tuple(-x for x in d), dim))
     return out
 
 
-def conv_weight_grad(g, u, dim: int):
+def conv_weight_grad(g, u, dim: int, kernel: int = 3):
     """dW[co, ci, t] = sum_b sum_n g[b, co, n] u[b, ci, n + delta_t]; db[co] = sum g."""
-    T = 3 ** dim
+    T = kernel ** dim
     dW = np.zeros((g.shape[1], u.shape[1], T))
-    for t, d in enumerate(tap_offsets(dim)):
+    for t, d in enumerate(tap_offsets(dim, kernel)):
         us = shifted(u, d, dim)
         dW[:, :, t] = np.einsum("bon,bin->oi", g.reshape(g.shape[0], g.shape[1], -1),
                                 us.reshape(us.shape[0], us.shape[1], -1))
@@ -185,18 +213,22 @@ def _rounders(emulate):
 
 
 def net(x, lay, mF, fs: FlowShape, emulate=None):
-    """s/t network of one layer.  Returns (a1, h1, a2, h2, o, s, t)."""
+    """s/t network of one layer.  Returns (acts, hs, o, s, t): the hidden
+    pre-activations a_1 .. a_n, the inputs h_0 = mask_F x, h_i = leaky(a_i) of
+    every convolution, the output o and s, t."""
     R, _ = _rounders(emulate)
-    W1, b1, W2, b2, W3, b3 = lay
-    h0 = (x * mF)[:, None]
-    a1 = conv(R(h0), R(W1), b1, fs.dim)
-    h1 = leaky(a1)
-    a2 = conv(R(h1), R(W2), b2, fs.dim)
-    h2 = leaky(a2)
-    o = conv(R(h2), R(W3), b3, fs.dim)
+    h = (x * mF)[:, None]
+    acts, hs = [], [h]
+    nconv = len(lay) // 2
+    for i in range(nconv - 1):
+        a = conv(R(h), R(lay[2 * i]), lay[2 * i + 1], fs.dim)
+        h = leaky(a)
+        acts.append(a)
+        hs.append(h)
+    o = conv(R(h), R(lay[-2]), lay[-1], fs.dim)
     s = np.tanh(o[:, 0]) if fs.final_tanh else o[:, 0]
     t = o[:, 1]
-    return a1, h1, a2, h2, o, s, t
+    return acts, hs, o, s, t
 
 
 def coupling_forward(x, lay, layer: int, fs: FlowShape, emulate=None):
@@ -282,38 +314,40 @@ def flow_vjp(params, z, fs: FlowShape, g_phi, g_logq, emulate=None):
     gx = np.asarray(g_phi, dtype=np.float64).reshape((B,) + fs.lattice)
     grads = [None] * fs.n_layers
     for l in reversed(range(fs.n_layers)):
-        W1, b1, W2, b2, W3, b3 = layers[l]
+        lay = layers[l]
         x = saved[l]
         mF = frozen_mask(fs, l)
         mA = 1.0 - mF
-        a1, h1, a2, h2, o, s, t = net(x, layers[l], mF, fs, emulate)
+        acts, hs, o, s, t = net(x, lay, mF, fs, emulate)
         es = np.exp(s)
         g_y = gx
         g_t = mA * g_y
         g_s = mA * (g_y * x * es + g_ld.reshape(shp))
         g_o0 = g_s * (1.0 - s * s) if fs.final_tanh else g_s
-        g_o = np.stack([g_o0, g_t], axis=1)
-        dW3, db3 = _weight_grad(g_o, h2, fs.dim, R)
-        g_a2 = conv_transpose(R(g_o), R(W3), fs.dim) * leaky_grad(a2)
-        dW2, db2 = _weight_grad(g_a2, h1, fs.dim, R)
-        g_a1 = conv_transpose(R(g_a2), R(W2), fs.dim) * leaky_grad(a1)
-        h0 = (x * mF)[:, None]
-        dW1, db1 = _weight_grad(g_a1, h0, fs.dim, R)
-        g_h0 = conv_transpose(R(g_a1), R(W1), fs.dim)[:, 0]
+        # back through the convolutions, last to first: g is the gradient of the
+        # current convolution's output (g_o, then g_a_i = g_h_i leaky'(a_i))
+        g = np.stack([g_o0, g_t], axis=1)
+        nconv = len(lay) // 2
+        lay_grads = [None] * (2 * nconv)
+        for i in reversed(range(nconv)):
+            lay_grads[2 * i], lay_grads[2 * i + 1] = _weight_grad(g, hs[i], fs.dim, R, fs.kernel)
+            g_in = conv_transpose(R(g), R(lay[2 * i]), fs.dim)
+            g = g_in * leaky_grad(acts[i - 1]) if i > 0 else g_in
+        g_h0 = g[:, 0]
         gx = RF(np.where(mA > 0, g_y * es, g_y + mF * g_h0))
-        grads[l] = (dW1, db1, dW2, db2, dW3, db3)
+        grads[l] = tuple(lay_grads)
     g_z = gx.reshape(B, -1) - g_logq[:, None] * saved[0].reshape(B, -1)   # d log r / dz = -z
     return pack(grads), g_z
 
 
-def _weight_grad(g, u, dim: int, R):
+def _weight_grad(g, u, dim: int, R, kernel: int = 3):
     """conv_weight_grad; when emulating a storage precision, the weight gradient
     from rounded operands and, like the bias gradient (a plain sum of the
     unrounded g), accumulated in FP32 by numpy's float32 reductions."""
     if R is _identity:
-        return conv_weight_grad(g, u, dim)
+        return conv_weight_grad(g, u, dim, kernel)
     f32 = np.float32
-    dW, _ = conv_weight_grad(R(g).astype(f32), R(u).astype(f32), dim)
+    dW, _ = conv_weight_grad(R(g).astype(f32), R(u).astype(f32), dim, kernel)
     db = np.asarray(g, f32).sum(axis=tuple(i for i in range(g.ndim) if i != 1))
     return dW, db.astype(np.float64)
 

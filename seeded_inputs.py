@@ -27,31 +27,38 @@ from dataclasses import dataclass
 import numpy as np
 
 
-def taps_per_conv(dim: int) -> int:
-    return 3 ** dim
+def taps_per_conv(dim: int, kernel: int = 3) -> int:
+    return kernel ** dim
 
 
-def layer_block_sizes(dim: int, hidden: int) -> list[tuple[str, int]]:
-    T = taps_per_conv(dim)
-    C = hidden
-    return [("W1", C * T), ("b1", C), ("W2", C * C * T), ("b2", C),
-            ("W3", 2 * C * T), ("b3", 2)]
+def layer_block_sizes(dim: int, hidden: int, kernel: int = 3,
+                      hidden_sizes=None) -> list[tuple[str, int]]:
+    """(name, size) of a layer's blocks: W_i[cout][cin][T], b_i[cout] for every
+    convolution, with hidden widths hidden_sizes (default [hidden, hidden])."""
+    T = taps_per_conv(dim, kernel)
+    w = list(hidden_sizes) if hidden_sizes else [hidden, hidden]
+    cin, cout = [1] + w, w + [2]
+    out = []
+    for i, (ci, co) in enumerate(zip(cin, cout), start=1):
+        out += [(f"W{i}", co * ci * T), (f"b{i}", co)]
+    return out
 
 
-def param_count(dim: int, n_layers: int, hidden: int) -> int:
-    return n_layers * sum(n for _, n in layer_block_sizes(dim, hidden))
+def param_count(dim: int, n_layers: int, hidden: int, kernel: int = 3, hidden_sizes=None) -> int:
+    return n_layers * sum(n for _, n in layer_block_sizes(dim, hidden, kernel, hidden_sizes))
 
 
 def flow_params(dim: int, n_layers: int, hidden: int, seed: int = 2021,
-                w_std: float = 0.1, b_std: float = 0.0) -> np.ndarray:
+                w_std: float = 0.1, b_std: float = 0.0, kernel: int = 3,
+                hidden_sizes=None) -> np.ndarray:
     """Packed FP32 flow parameters: weights N(0, w_std), biases N(0, b_std) (0 if b_std == 0)."""
-    n = param_count(dim, n_layers, hidden)
+    n = param_count(dim, n_layers, hidden, kernel, hidden_sizes)
     rng = np.random.default_rng(seed)
     p = rng.normal(0.0, w_std, size=n)
     brng = np.random.default_rng(seed + 7919)
     off = 0
     for _ in range(n_layers):
-        for name, sz in layer_block_sizes(dim, hidden):
+        for name, sz in layer_block_sizes(dim, hidden, kernel, hidden_sizes):
             if name.startswith("b"):
                 p[off:off + sz] = brng.normal(0.0, b_std, size=sz) if b_std > 0 else 0.0
             off += sz
