@@ -63,16 +63,26 @@ typedef enum lfs_precision { LFS_PLAIN_FP32 = 0, LFS_BF16_CONV = 1 } lfs_precisi
 typedef enum lfs_algo { LFS_ALGO_AUTO = 0, LFS_ALGO_GENERIC = 1, LFS_ALGO_FUSED = 2 } lfs_algo;
 
 /* Flow architecture (paper Sec. 1, coupling-layer and composition equations;
- * the example parameter file fixes kernel_size 3, inC 1, outC 2).
+ * the example parameter file: hidden_sizes [8, 8], kernel_size 3, inC 1, outC 2).
  *   dim        lattice dimension, 2 or 3
  *   L          lattice extent, even and >= 2 (the checkerboard needs even L)
  *   n_layers   number of coupling layers N >= 1; layer l freezes the sites of
  *              parity (l + parity0) mod 2 and updates the others
- *   hidden     channels C of the two hidden convolutions: 8, 16 or 32
+ *   hidden     channels C of the two hidden convolutions of the default
+ *              network: 8, 16 or 32 (ignored when n_hidden > 0)
  *   final_tanh 1: s = tanh(o_0); 0: s = o_0
  *   parity0    0 or 1
  *   precision  lfs_precision
- *   algo       lfs_algo */
+ *   algo       lfs_algo
+ * General networks (the parameter file's hidden_sizes and kernel_size):
+ *   kernel     odd kernel size K per axis, 1..7; 0 means 3
+ *   n_hidden   number of hidden convolutions, 1..LFS_MAX_HIDDEN; 0 means two
+ *              of `hidden` channels
+ *   hidden_sizes  their channel counts, 1..64 each (first n_hidden entries)
+ * A network equal to the default (kernel 3, two hidden convolutions of 8, 16
+ * or 32 channels) runs on the fused or generic kernels; any other runs on the
+ * general-network kernels (LFS_ALGO_FUSED then reports EUNSUPPORTED). */
+#define LFS_MAX_HIDDEN 4
 typedef struct lfs_flow_desc {
   int32_t dim;
   int32_t L;
@@ -82,6 +92,9 @@ typedef struct lfs_flow_desc {
   int32_t parity0;
   int32_t precision;
   int32_t algo;
+  int32_t kernel;
+  int32_t n_hidden;
+  int32_t hidden_sizes[LFS_MAX_HIDDEN];
 } lfs_flow_desc;
 
 /* Persistent state of one independence Metropolis-Hastings chain (device POD,
@@ -110,7 +123,10 @@ const char* lfs_version(void);
  * Layout, per layer l = 0..N-1 in order, with C = hidden and T = 3^dim taps:
  *   W1[C][1][T]  b1[C]  W2[C][C][T]  b2[C]  W3[2][C][T]  b3[2]
  * Taps are row-major over delta in {-1,0,1}^dim, axis 0 slowest; channel 0 of
- * the last convolution is s, channel 1 is t.  Returns 0 for an invalid desc. */
+ * the last convolution is s, channel 1 is t.  A general network stores, per
+ * layer, W_i[cout_i][cin_i][T] then b_i[cout_i] for each convolution in order
+ * (cin = 1, w_1, .., w_n; cout = w_1, .., w_n, 2), T = K^dim, taps row-major
+ * over {-K/2..K/2}^dim.  Returns 0 for an invalid desc. */
 size_t lfs_param_count(const lfs_flow_desc* desc);
 
 /* Workspace bytes needed by lfs_flow_forward (for_backward = 0) or

@@ -17,34 +17,79 @@ int32_t make_geom(const lfs_flow_desc* d, FlowGeom* g) {
   if (d->precision != LFS_PLAIN_FP32 && d->precision != LFS_BF16_CONV) return LFS_EINVAL;
   if (d->algo < LFS_ALGO_AUTO || d->algo > LFS_ALGO_FUSED) return LFS_EINVAL;
   if (d->L > 256 || (d->dim == 3 && d->L > 64)) return LFS_EUNSUPPORTED;
-  if (d->hidden != 8 && d->hidden != 16 && d->hidden != 32) return LFS_EUNSUPPORTED;
+  const int K = d->kernel == 0 ? 3 : d->kernel;
+  if (K < 1 || K > 7 || !(K & 1)) return LFS_EINVAL;
+  if (d->n_hidden < 0 || d->n_hidden > LFS_MAX_HIDDEN) return LFS_EINVAL;
+  int widths[LFS_MAX_HIDDEN], nh;
+  if (d->n_hidden == 0) {
+    if (d->hidden != 8 && d->hidden != 16 && d->hidden != 32) return LFS_EUNSUPPORTED;
+    nh = 2;
+    widths[0] = widths[1] = d->hidden;
+  } else {
+    nh = d->n_hidden;
+    for (int i = 0; i < nh; ++i) {
+      if (d->hidden_sizes[i] < 1) return LFS_EINVAL;
+      if (d->hidden_sizes[i] > 64) return LFS_EUNSUPPORTED;
+      widths[i] = d->hidden_sizes[i];
+    }
+  }
   g->dim = d->dim;
   g->L = d->L;
   g->V = d->dim == 2 ? d->L * d->L : d->L * d->L * d->L;
-  g->T = d->dim == 2 ? 9 : 27;
+  g->K = K;
+  g->T = d->dim == 2 ? K * K : K * K * K;
   g->N = d->n_layers;
-  g->C = d->hidden;
+  g->net_default = K == 3 && nh == 2 && widths[0] == widths[1] &&
+                   (widths[0] == 8 || widths[0] == 16 || widths[0] == 32);
+  g->C = g->net_default ? widths[0] : 0;
+  g->n_conv = nh + 1;
+  {
+    size_t off = 0;
+    for (int i = 0; i < g->n_conv; ++i) {
+      g->cin[i] = i == 0 ? 1 : widths[i - 1];
+      g->cout[i] = i == nh ? 2 : widths[i];
+      g->offW[i] = off;
+      off += (size_t)g->cout[i] * g->cin[i] * g->T;
+      g->offb[i] = off;
+      off += g->cout[i];
+    }
+    g->P_layer = off;
+  }
   g->final_tanh = d->final_tanh;
   g->parity0 = d->parity0;
   g->precision = d->precision;
   g->algo = d->algo;
-  const size_t C = g->C, T = g->T;
-  g->off_W1 = 0;
-  g->off_b1 = g->off_W1 + C * T;
-  g->off_W2 = g->off_b1 + C;
-  g->off_b2 = g->off_W2 + C * C * T;
-  g->off_W3 = g->off_b2 + C;
-  g->off_b3 = g->off_W3 + 2 * C * T;
-  g->P_layer = g->off_b3 + 2;
+  // the default network's blocks (same offsets as offW/offb above)
+  g->off_W1 = g->offW[0];
+  g->off_b1 = g->offb[0];
+  g->off_W2 = g->offW[1];
+  g->off_b2 = g->offb[1];
+  g->off_W3 = g->offW[g->n_conv - 1];
+  g->off_b3 = g->offb[g->n_conv - 1];
   g->P_total = g->P_layer * (size_t)g->N;
   return LFS_OK;
 }
 
 namespace {
 
-bool use_fused(const FlowGeom& g, int bwd) {
-  if (g.algo == LFS_ALGO_GENERIC) return false;
-  return fused_supported(g, bwd);
+// Kernel family of a validated geometry: fused (default network, a fused kernel
+// for the shape, algo not GENERIC), generic (default network) or general net.
+enum class Family { Fused, Generic, Net };
+
+bool fused_ok(const FlowGeom& g, int bwd) { return g.net_default && fused_supported(g, bwd); }
+
+Family family(const FlowGeom& g, int bwd) {
+  if (!g.net_default) return Family::Net;
+  if (g.algo != LFS_ALGO_GENERIC && fused_supported(g, bwd)) return Family::Fused;
+  return Family::Generic;
+}
+
+size_t ws_bytes(const FlowGeom& g, int B, int bwd) {
+  switch (family(g, bwd)) {
+    case Family::Fused: return fused_ws_bytes(g, B, bwd);
+    case Family::Generic: return generic_ws_bytes(g, B, bwd);
+    default: return net_ws_bytes(g, B, bwd);
+  }
 }
 
 }  // namespace
@@ -74,10 +119,8 @@ extern "C" int32_t lfs_workspace_bytes(const lfs_flow_desc* desc, int32_t B, int
   const int32_t s = lfs::make_geom(desc, &g);
   if (s != LFS_OK) return s;
   if (B <= 0 || !bytes) return LFS_EINVAL;
-  if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_supported(g, for_backward))
-    return LFS_EUNSUPPORTED;
-  *bytes = lfs::use_fused(g, for_backward) ? lfs::fused_ws_bytes(g, B, for_backward)
-                                           : lfs::generic_ws_bytes(g, B, for_backward);
+  if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_ok(g, for_backward)) return LFS_EUNSUPPORTED;
+  *bytes = lfs::ws_bytes(g, B, for_backward);
   return LFS_OK;
 }
 
@@ -88,13 +131,18 @@ extern "C" int32_t lfs_flow_forward(const lfs_flow_desc* desc, const float* para
   const int32_t s = lfs::make_geom(desc, &g);
   if (s != LFS_OK) return s;
   if (B <= 0 || !params || !z || !phi || !logq) return LFS_EINVAL;
-  if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_supported(g, 0)) return LFS_EUNSUPPORTED;
-  const bool fused = lfs::use_fused(g, 0);
-  const size_t need = fused ? lfs::fused_ws_bytes(g, B, 0) : lfs::generic_ws_bytes(g, B, 0);
+  if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_ok(g, 0)) return LFS_EUNSUPPORTED;
+  const size_t need = lfs::ws_bytes(g, B, 0);
   if (need > 0 && (!ws || ws_bytes < need)) return LFS_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  return fused ? lfs::fused_forward(g, params, B, z, phi, logq, logdet, saved_x, (char*)ws, st)
-               : lfs::generic_forward(g, params, B, z, phi, logq, logdet, saved_x, (char*)ws, st);
+  switch (lfs::family(g, 0)) {
+    case lfs::Family::Fused:
+      return lfs::fused_forward(g, params, B, z, phi, logq, logdet, saved_x, (char*)ws, st);
+    case lfs::Family::Generic:
+      return lfs::generic_forward(g, params, B, z, phi, logq, logdet, saved_x, (char*)ws, st);
+    default:
+      return lfs::net_forward(g, params, B, z, phi, logq, logdet, saved_x, (char*)ws, st);
+  }
 }
 
 extern "C" int32_t lfs_flow_backward(const lfs_flow_desc* desc, const float* params, int32_t B,
@@ -105,13 +153,16 @@ extern "C" int32_t lfs_flow_backward(const lfs_flow_desc* desc, const float* par
   const int32_t s = lfs::make_geom(desc, &g);
   if (s != LFS_OK) return s;
   if (B <= 0 || !params || !saved_x || !g_phi || !g_params) return LFS_EINVAL;
-  if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_supported(g, 1)) return LFS_EUNSUPPORTED;
-  const bool fused = lfs::use_fused(g, 1);
-  const size_t need = fused ? lfs::fused_ws_bytes(g, B, 1) : lfs::generic_ws_bytes(g, B, 1);
+  if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_ok(g, 1)) return LFS_EUNSUPPORTED;
+  const size_t need = lfs::ws_bytes(g, B, 1);
   if (need > 0 && (!ws || ws_bytes < need)) return LFS_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  return fused ? lfs::fused_backward(g, params, B, saved_x, g_phi, g_logq, g_params, g_z,
-                                     (char*)ws, st)
-               : lfs::generic_backward(g, params, B, saved_x, g_phi, g_logq, g_params, g_z,
-                                       (char*)ws, st);
+  switch (lfs::family(g, 1)) {
+    case lfs::Family::Fused:
+      return lfs::fused_backward(g, params, B, saved_x, g_phi, g_logq, g_params, g_z, (char*)ws, st);
+    case lfs::Family::Generic:
+      return lfs::generic_backward(g, params, B, saved_x, g_phi, g_logq, g_params, g_z, (char*)ws, st);
+    default:
+      return lfs::net_backward(g, params, B, saved_x, g_phi, g_logq, g_params, g_z, (char*)ws, st);
+  }
 }

@@ -1,0 +1,400 @@
+// General s/t networks: the example parameter file's hidden_sizes and
+// kernel_size beyond the default two hidden convolutions of C channels with
+// kernel 3.  Per layer the network is conv(1 -> w_1) + LeakyReLU, ...,
+// conv(w_{n-1} -> w_n) + LeakyReLU, conv(w_n -> 2) with an odd kernel K per
+// axis (paper Sec. 1, coupling-layer equation; taps row-major over
+// {-K/2..K/2}^dim, axis 0 slowest).  Direct periodic convolutions with runtime
+// channel counts, one thread per (sample, site, output channel), activations
+// in HBM.  In BF16 mode every convolution operand is rounded to BF16 and
+// products are accumulated in FP32, as in the other kernel families.
+#include "lfs_common.hpp"
+#include "lfs_internal.hpp"
+
+namespace lfs {
+namespace {
+
+inline dim3 grid_for(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+constexpr int kWgChunk = 4096;  // (sample, site) terms per weight-gradient workgroup
+
+// Site n + sign * delta_t, delta_t the offsets of tap t of an odd kernel K.
+template <int DIM>
+__device__ __forceinline__ int nbr_k(int n, int t, int L, int K, int sign) {
+  const int r = K >> 1;
+  int c[DIM], d[DIM];
+#pragma unroll
+  for (int mu = DIM - 1; mu >= 0; --mu) {
+    c[mu] = n % L;
+    n /= L;
+    d[mu] = t % K - r;
+    t /= K;
+  }
+  int out = 0;
+#pragma unroll
+  for (int mu = 0; mu < DIM; ++mu) {
+    int v = (c[mu] + sign * d[mu]) % L;
+    if (v < 0) v += L;
+    out = out * L + v;
+  }
+  return out;
+}
+
+// out[b][n][co] = act(bias[co] + sum_t sum_ci W[co][ci][t] in[b][n + delta_t][ci]).
+// first: the input is the layer's field with the active sites zeroed (cin = 1).
+template <int DIM, bool BF16>
+__global__ void __launch_bounds__(256) kn_conv(int L, int V, int B, int K, int T, int cin, int cout,
+                                               int first, int fpar, int act,
+                                               const float* __restrict__ in,
+                                               const float* __restrict__ W,
+                                               const float* __restrict__ bias,
+                                               float* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)B * V * cout) return;
+  const int co = (int)(idx % cout);
+  const int64_t bn = idx / cout;
+  const int b = (int)(bn / V), n = (int)(bn % V);
+  const float* w = W + (size_t)co * cin * T;
+  float acc = bias[co];
+  for (int t = 0; t < T; ++t) {
+    const int m = nbr_k<DIM>(n, t, L, K, 1);
+    if (first) {
+      const float v = site_parity<DIM>(m, L) == fpar ? in[(size_t)b * V + m] : 0.f;
+      acc += opnd<BF16>(w[t]) * opnd<BF16>(v);
+    } else {
+      const float* h = in + ((size_t)b * V + m) * cin;
+      for (int ci = 0; ci < cin; ++ci) acc += opnd<BF16>(w[(size_t)ci * T + t]) * opnd<BF16>(h[ci]);
+    }
+  }
+  out[idx] = act ? leaky(acc) : acc;
+}
+
+// Affine update of the active sites from o = (o_0, o_1) and per-sample log-det
+// (one block per sample).
+template <int DIM, typename R>
+__global__ void __launch_bounds__(256) kn_couple(int L, int V, int fpar, int final_tanh,
+                                                 const float* __restrict__ xin,
+                                                 const float* __restrict__ o,
+                                                 float* __restrict__ xout,
+                                                 double* __restrict__ logdet_acc) {
+  __shared__ R sh[16];
+  const int b = blockIdx.x;
+  R ssum = 0;
+  for (int n = threadIdx.x; n < V; n += blockDim.x) {
+    const size_t i = (size_t)b * V + n;
+    const float x = xin[i];
+    if (site_parity<DIM>(n, L) == fpar) {
+      xout[i] = x;
+      continue;
+    }
+    const float s = final_tanh ? tanhf(o[2 * i]) : o[2 * i];
+    xout[i] = x * expf(s) + o[2 * i + 1];
+    ssum += (R)s;
+  }
+  ssum = block_sum(ssum, sh);
+  if (threadIdx.x == 0) logdet_acc[b] += (double)ssum;
+}
+
+// log r(z) per sample (one block per sample); zeroes the log-det accumulator.
+template <typename R>
+__global__ void __launch_bounds__(256) kn_logr(int V, const float* __restrict__ z,
+                                               double* __restrict__ logr,
+                                               double* __restrict__ logdet_acc) {
+  __shared__ R sh[16];
+  const int b = blockIdx.x;
+  R acc = 0;
+  for (int n = threadIdx.x; n < V; n += blockDim.x) {
+    const R v = (R)z[(size_t)b * V + n];
+    acc += v * v;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    logr[b] = -0.5 * (double)acc - 0.5 * (double)V * 1.8378770664093454836;
+    logdet_acc[b] = 0.0;
+  }
+}
+
+__global__ void kn_finalize(int B, const double* __restrict__ logr, const double* __restrict__ ld,
+                            double* __restrict__ logq, double* __restrict__ logdet) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  logq[b] = logr[b] - ld[b];
+  if (logdet) logdet[b] = ld[b];
+}
+
+// Backward of the affine update: g_o at the active sites (zero at the frozen
+// ones) and g_x (active: g e^s; frozen: g, the network's path is added later).
+template <int DIM>
+__global__ void __launch_bounds__(256) kn_affine_bwd(int L, int V, int B, int fpar, int final_tanh,
+                                                     const float* __restrict__ x,
+                                                     const float* __restrict__ o,
+                                                     const float* __restrict__ gy, float g_ld,
+                                                     float* __restrict__ go,
+                                                     float* __restrict__ gx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * V) return;
+  const int n = (int)(i % V);
+  const float g = gy[i];
+  if (site_parity<DIM>(n, L) == fpar) {
+    go[2 * i] = 0.f;
+    go[2 * i + 1] = 0.f;
+    gx[i] = g;
+    return;
+  }
+  const float s = final_tanh ? tanhf(o[2 * i]) : o[2 * i];
+  const float es = expf(s);
+  const float gs = g * x[i] * es + g_ld;
+  go[2 * i] = final_tanh ? gs * (1.f - s * s) : gs;
+  go[2 * i + 1] = g;
+  gx[i] = g * es;
+}
+
+// Data gradient of a convolution: gin[b][m][ci] = sum_t sum_co W[co][ci][t]
+// g[b][m - delta_t][co], times LeakyReLU' of the input h (from its sign), or,
+// for the first convolution, added to gx at the frozen sites.
+template <int DIM, bool BF16>
+__global__ void __launch_bounds__(256) kn_conv_t(int L, int V, int B, int K, int T, int cin, int cout,
+                                                 int first, int fpar, const float* __restrict__ g,
+                                                 const float* __restrict__ W,
+                                                 const float* __restrict__ h,
+                                                 float* __restrict__ gin) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)B * V * cin) return;
+  const int ci = (int)(idx % cin);
+  const int64_t bm = idx / cin;
+  const int b = (int)(bm / V), m = (int)(bm % V);
+  float acc = 0.f;
+  for (int t = 0; t < T; ++t) {
+    const float* gr = g + ((size_t)b * V + nbr_k<DIM>(m, t, L, K, -1)) * cout;
+    for (int co = 0; co < cout; ++co)
+      acc += opnd<BF16>(W[((size_t)co * cin + ci) * T + t]) * opnd<BF16>(gr[co]);
+  }
+  if (first) {
+    if (site_parity<DIM>(m, L) == fpar) gin[bm] += acc;
+  } else {
+    gin[idx] = acc * leaky_grad_from_out(h[idx]);
+  }
+}
+
+// Partial weight and bias gradients of one convolution over the (sample, site)
+// terms [chunk * kWgChunk, +kWgChunk): parameter p < cout cin T is W[co][ci][t]
+// (sum of g[.][n][co] u[.][n + delta_t][ci]), the rest b[co] (sum of g).  One
+// workgroup per (parameter, chunk); fixed-order sums.
+template <int DIM, bool BF16>
+__global__ void __launch_bounds__(256) kn_wgrad(int L, int V, int B, int K, int T, int cin, int cout,
+                                                int first, int fpar, const float* __restrict__ g,
+                                                const float* __restrict__ u,
+                                                double* __restrict__ partial, int P) {
+  __shared__ double sh[16];
+  const int p = blockIdx.x, chunk = blockIdx.y;
+  const int64_t BV = (int64_t)B * V;
+  const int64_t t0 = (int64_t)chunk * kWgChunk, t1 = t0 + kWgChunk < BV ? t0 + kWgChunk : BV;
+  const int nW = cout * cin * T;
+  double acc = 0.0;
+  if (p < nW) {
+    const int co = p / (cin * T), ci = (p / T) % cin, t = p % T;
+    for (int64_t bn = t0 + threadIdx.x; bn < t1; bn += blockDim.x) {
+      const int b = (int)(bn / V), n = (int)(bn % V);
+      const int m = nbr_k<DIM>(n, t, L, K, 1);
+      float uv;
+      if (first)
+        uv = site_parity<DIM>(m, L) == fpar ? u[(size_t)b * V + m] : 0.f;
+      else
+        uv = u[((size_t)b * V + m) * cin + ci];
+      acc += (double)(opnd<BF16>(g[bn * cout + co]) * opnd<BF16>(uv));
+    }
+  } else {
+    const int co = p - nW;
+    for (int64_t bn = t0 + threadIdx.x; bn < t1; bn += blockDim.x) acc += (double)g[bn * cout + co];
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[(size_t)chunk * P + p] = acc;
+}
+
+// out[p] = sum over chunks of partial[chunk][p], in chunk order.
+__global__ void __launch_bounds__(256) kn_reduce(int G, int P, const double* __restrict__ partial,
+                                                 float* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double acc = 0.0;
+  for (int c = 0; c < G; ++c) acc += partial[(size_t)c * P + p];
+  out[p] = (float)acc;
+}
+
+// g_z = g_x - g_logq z (d log r / dz = -z).
+__global__ void kn_gz(int64_t n, const float* __restrict__ gx, const float* __restrict__ z,
+                      float g_logq, float* __restrict__ gz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) gz[i] = gx[i] - g_logq * z[i];
+}
+
+struct NetWs {
+  double *logdet, *logr, *partial;
+  float* h[LFS_MAX_HIDDEN];
+  float *o, *go, *gA, *gB, *gxA, *gxB;
+};
+
+int max_width(const FlowGeom& g) {
+  int w = 2;
+  for (int i = 0; i < g.n_conv; ++i) w = w > g.cout[i] ? w : g.cout[i];
+  return w;
+}
+
+size_t max_conv_params(const FlowGeom& g) {
+  size_t m = 0;
+  for (int i = 0; i < g.n_conv; ++i) {
+    const size_t p = (size_t)g.cout[i] * g.cin[i] * g.T + g.cout[i];
+    m = m > p ? m : p;
+  }
+  return m;
+}
+
+int wg_chunks(int B, int V) { return (int)(((int64_t)B * V + kWgChunk - 1) / kWgChunk); }
+
+NetWs carve(const FlowGeom& g, int B, char* base, size_t* total) {
+  NetWs w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  const size_t BV = (size_t)B * g.V;
+  w.logdet = (double*)take(sizeof(double) * B);
+  w.logr = (double*)take(sizeof(double) * B);
+  for (int i = 0; i + 1 < g.n_conv; ++i) w.h[i] = (float*)take(sizeof(float) * BV * g.cout[i]);
+  w.o = (float*)take(sizeof(float) * BV * 2);
+  const size_t fwd = off;
+  const int mw = max_width(g);
+  w.go = (float*)take(sizeof(float) * BV * 2);
+  w.gA = (float*)take(sizeof(float) * BV * mw);
+  w.gB = (float*)take(sizeof(float) * BV * mw);
+  w.gxA = (float*)take(sizeof(float) * BV);
+  w.gxB = (float*)take(sizeof(float) * BV);
+  w.partial = (double*)take(sizeof(double) * (size_t)wg_chunks(B, g.V) * max_conv_params(g));
+  total[0] = fwd;
+  total[1] = off;
+  return w;
+}
+
+// The layer's network from its input field x: hidden activations into w.h, output into w.o.
+template <int DIM, bool BF16>
+void run_net(const FlowGeom& g, const float* p, int B, const float* x, int fpar, const NetWs& w,
+             hipStream_t st) {
+  const int64_t BV = (int64_t)B * g.V;
+  for (int i = 0; i < g.n_conv; ++i) {
+    const bool last = i + 1 == g.n_conv;
+    float* out = last ? w.o : w.h[i];
+    const float* in = i == 0 ? x : w.h[i - 1];
+    hipLaunchKernelGGL((kn_conv<DIM, BF16>), grid_for(BV * g.cout[i]), dim3(256), 0, st, g.L, g.V, B,
+                       g.K, g.T, g.cin[i], g.cout[i], i == 0, fpar, !last, in, p + g.offW[i],
+                       p + g.offb[i], out);
+  }
+}
+
+template <int DIM, bool BF16>
+int32_t forward_impl(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
+                     double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
+  size_t tot[2];
+  NetWs w = carve(g, B, ws, tot);
+  const size_t BV = (size_t)B * g.V;
+  // log r first: phi may alias z
+  if (BF16)
+    hipLaunchKernelGGL(kn_logr<double>, dim3(B), dim3(256), 0, st, g.V, z, w.logr, w.logdet);
+  else
+    hipLaunchKernelGGL(kn_logr<float>, dim3(B), dim3(256), 0, st, g.V, z, w.logr, w.logdet);
+  float* cur = saved ? saved : phi;
+  if (cur != z && hipMemcpyAsync(cur, z, sizeof(float) * BV, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return LFS_EDEVICE;
+  for (int l = 0; l < g.N; ++l) {
+    const float* p = params + (size_t)l * g.P_layer;
+    const float* xin = saved ? saved + (size_t)l * BV : phi;
+    float* xout = saved ? saved + (size_t)(l + 1) * BV : phi;
+    const int fpar = g.frozen_parity(l);
+    run_net<DIM, BF16>(g, p, B, xin, fpar, w, st);
+    if (BF16)
+      hipLaunchKernelGGL((kn_couple<DIM, double>), dim3(B), dim3(256), 0, st, g.L, g.V, fpar,
+                         g.final_tanh, xin, w.o, xout, w.logdet);
+    else
+      hipLaunchKernelGGL((kn_couple<DIM, float>), dim3(B), dim3(256), 0, st, g.L, g.V, fpar,
+                         g.final_tanh, xin, w.o, xout, w.logdet);
+  }
+  if (saved && phi &&
+      hipMemcpyAsync(phi, saved + (size_t)g.N * BV, sizeof(float) * BV, hipMemcpyDeviceToDevice, st) !=
+          hipSuccess)
+    return LFS_EDEVICE;
+  hipLaunchKernelGGL(kn_finalize, grid_for(B), dim3(256), 0, st, B, w.logr, w.logdet, logq, logdet);
+  return launch_status();
+}
+
+template <int DIM, bool BF16>
+int32_t backward_impl(const FlowGeom& g, const float* params, int B, const float* saved,
+                      const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                      hipStream_t st) {
+  size_t tot[2];
+  NetWs w = carve(g, B, ws, tot);
+  const int64_t BV = (int64_t)B * g.V;
+  const int G = wg_chunks(B, g.V);
+  const float* gy = g_phi;
+  float* gxs[2] = {w.gxA, w.gxB};
+  float* gbuf[2] = {w.gA, w.gB};
+  int which = 0;
+  for (int l = g.N - 1; l >= 0; --l) {
+    const float* p = params + (size_t)l * g.P_layer;
+    float* gp = g_params + (size_t)l * g.P_layer;
+    const float* x = saved + (size_t)l * BV;
+    const int fpar = g.frozen_parity(l);
+    float* gx = gxs[which];
+    run_net<DIM, BF16>(g, p, B, x, fpar, w, st);
+    hipLaunchKernelGGL((kn_affine_bwd<DIM>), grid_for(BV), dim3(256), 0, st, g.L, g.V, B, fpar,
+                       g.final_tanh, x, w.o, gy, (float)(-g_logq), w.go, gx);
+    // back through the convolutions, last to first; gcur is the gradient of
+    // convolution i's output
+    const float* gcur = w.go;
+    for (int i = g.n_conv - 1; i >= 0; --i) {
+      const int P = g.cout[i] * g.cin[i] * g.T + g.cout[i];
+      const float* u = i == 0 ? x : w.h[i - 1];
+      hipLaunchKernelGGL((kn_wgrad<DIM, BF16>), dim3(P, G), dim3(256), 0, st, g.L, g.V, B, g.K, g.T,
+                         g.cin[i], g.cout[i], i == 0, fpar, gcur, u, w.partial, P);
+      hipLaunchKernelGGL(kn_reduce, grid_for(P), dim3(256), 0, st, G, P, w.partial, gp + g.offW[i]);
+      float* gin = i == 0 ? gx : gbuf[i & 1];
+      hipLaunchKernelGGL((kn_conv_t<DIM, BF16>), grid_for(BV * g.cin[i]), dim3(256), 0, st, g.L, g.V, B,
+                         g.K, g.T, g.cin[i], g.cout[i], i == 0, fpar, gcur, p + g.offW[i],
+                         i == 0 ? nullptr : w.h[i - 1], gin);
+      gcur = gin;
+    }
+    gy = gx;
+    which ^= 1;
+  }
+  if (g_z)
+    hipLaunchKernelGGL(kn_gz, grid_for(BV), dim3(256), 0, st, BV, gy, saved, (float)g_logq, g_z);
+  return launch_status();
+}
+
+}  // namespace
+
+size_t net_ws_bytes(const FlowGeom& g, int B, int for_backward) {
+  size_t tot[2];
+  carve(g, B, nullptr, tot);
+  return tot[for_backward ? 1 : 0];
+}
+
+int32_t net_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
+                    double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
+  if (g.dim == 2)
+    return g.bf16() ? forward_impl<2, true>(g, params, B, z, phi, logq, logdet, saved, ws, st)
+                    : forward_impl<2, false>(g, params, B, z, phi, logq, logdet, saved, ws, st);
+  return g.bf16() ? forward_impl<3, true>(g, params, B, z, phi, logq, logdet, saved, ws, st)
+                  : forward_impl<3, false>(g, params, B, z, phi, logq, logdet, saved, ws, st);
+}
+
+int32_t net_backward(const FlowGeom& g, const float* params, int B, const float* saved,
+                     const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                     hipStream_t st) {
+  if (g.dim == 2)
+    return g.bf16() ? backward_impl<2, true>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st)
+                    : backward_impl<2, false>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
+  return g.bf16() ? backward_impl<3, true>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st)
+                  : backward_impl<3, false>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
+}
+
+}  // namespace lfs

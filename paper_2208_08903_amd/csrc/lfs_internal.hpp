@@ -15,8 +15,15 @@ namespace lfs {
 struct FlowGeom {
   int dim, L, V, T, N, C;
   int final_tanh, parity0, precision, algo;
-  size_t off_W1, off_b1, off_W2, off_b2, off_W3, off_b3;  // within a layer
+  size_t off_W1, off_b1, off_W2, off_b2, off_W3, off_b3;  // within a layer (default network)
   size_t P_layer, P_total;
+  // every network: kernel size, convolutions with their channel counts and
+  // offsets within a layer; net_default: the default network (kernel 3, two
+  // hidden convolutions of C = 8, 16 or 32 channels)
+  int K, n_conv;
+  int cin[LFS_MAX_HIDDEN + 1], cout[LFS_MAX_HIDDEN + 1];
+  size_t offW[LFS_MAX_HIDDEN + 1], offb[LFS_MAX_HIDDEN + 1];
+  bool net_default;
 
   int frozen_parity(int layer) const { return (layer + parity0) & 1; }
   bool bf16() const { return precision == LFS_BF16_CONV; }
@@ -34,6 +41,14 @@ int32_t generic_forward(const FlowGeom& g, const float* params, int B, const flo
 int32_t generic_backward(const FlowGeom& g, const float* params, int B, const float* saved,
                          const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
                          hipStream_t st);
+
+// General-network kernels: any hidden_sizes / odd kernel, activations in HBM.
+size_t net_ws_bytes(const FlowGeom& g, int B, int for_backward);
+int32_t net_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
+                    double* logq, double* logdet, float* saved, char* ws, hipStream_t st);
+int32_t net_backward(const FlowGeom& g, const float* params, int B, const float* saved,
+                     const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                     hipStream_t st);
 
 // Fused kernels: LDS-resident per-sample lattices, matrix-core convolutions.
 bool fused_supported(const FlowGeom& g, int for_backward);

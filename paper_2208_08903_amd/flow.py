@@ -27,11 +27,13 @@ class Flow:
     """A flow architecture, its packed FP32 parameters on the device, and workspaces."""
 
     def __init__(self, dim, L, n_layers, hidden, precision=lfs.LFS_BF16_CONV, algo=lfs.ALGO_AUTO,
-                 final_tanh=True, parity0=0, params=None, device="cuda"):
+                 final_tanh=True, parity0=0, params=None, device="cuda", kernel=0, hidden_sizes=None):
         self.dim, self.L, self.n_layers, self.hidden = dim, L, n_layers, hidden
+        self.kernel, self.hidden_sizes = kernel, hidden_sizes
         self.V = L ** dim
         self.precision = precision
-        self.desc = lfs.make_desc(dim, L, n_layers, hidden, final_tanh, parity0, precision, algo)
+        self.desc = lfs.make_desc(dim, L, n_layers, hidden, final_tanh, parity0, precision, algo,
+                                  kernel, hidden_sizes)
         self.P = lfs.param_count(self.desc)
         if self.P == 0:
             raise lfs.LfsError("invalid flow description")
@@ -53,7 +55,8 @@ class Flow:
 
     def with_precision(self, precision):
         f = Flow(self.dim, self.L, self.n_layers, self.hidden, precision, self.desc.algo,
-                 bool(self.desc.final_tanh), self.desc.parity0, device=self.device)
+                 bool(self.desc.final_tanh), self.desc.parity0, device=self.device,
+                 kernel=self.kernel, hidden_sizes=self.hidden_sizes)
         f.params = self.params
         return f
 

@@ -28,12 +28,17 @@ class LfsError(RuntimeError):
     pass
 
 
+MAX_HIDDEN = 4
+
+
 class FlowDesc(ctypes.Structure):
     _fields_ = [("dim", c_i32), ("L", c_i32), ("n_layers", c_i32), ("hidden", c_i32),
-                ("final_tanh", c_i32), ("parity0", c_i32), ("precision", c_i32), ("algo", c_i32)]
+                ("final_tanh", c_i32), ("parity0", c_i32), ("precision", c_i32), ("algo", c_i32),
+                ("kernel", c_i32), ("n_hidden", c_i32), ("hidden_sizes", c_i32 * MAX_HIDDEN)]
 
     def key(self):
-        return tuple(getattr(self, f) for f, _ in self._fields_)
+        return tuple(tuple(v) if f == "hidden_sizes" else getattr(self, f)
+                     for f, _ in self._fields_ for v in [getattr(self, f)])
 
 
 class ChainState(ctypes.Structure):
@@ -118,8 +123,15 @@ def _p(t, dtype=None, name="tensor"):
 
 
 def make_desc(dim, L, n_layers, hidden, final_tanh=True, parity0=0,
-              precision=LFS_PLAIN_FP32, algo=ALGO_AUTO) -> FlowDesc:
-    return FlowDesc(dim, L, n_layers, hidden, int(final_tanh), parity0, precision, algo)
+              precision=LFS_PLAIN_FP32, algo=ALGO_AUTO, kernel=0, hidden_sizes=None) -> FlowDesc:
+    """hidden_sizes: the widths of the hidden convolutions (None: two of `hidden`);
+    kernel: odd kernel size per axis (0: 3)."""
+    hs = list(hidden_sizes or [])
+    if len(hs) > MAX_HIDDEN:
+        raise LfsError(f"at most {MAX_HIDDEN} hidden convolutions")
+    arr = (c_i32 * MAX_HIDDEN)(*(hs + [0] * (MAX_HIDDEN - len(hs))))
+    return FlowDesc(dim, L, n_layers, hidden, int(final_tanh), parity0, precision, algo, kernel,
+                    len(hs), arr)
 
 
 def param_count(desc: FlowDesc) -> int:

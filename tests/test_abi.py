@@ -27,8 +27,32 @@ def test_library_exports_every_header_function():
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(lfs.FlowDesc) == 32
+    assert ctypes.sizeof(lfs.FlowDesc) == 56   # 10 int32 fields + hidden_sizes[4]
     assert lfs.CHAIN_STATE_BYTES == 40
+
+
+@pytest.mark.parametrize("dim,N,K,hs", [(2, 16, 5, (8, 8)), (2, 3, 3, (3, 5, 4)), (3, 2, 5, (2,)),
+                                        (2, 4, 1, (16, 16, 16, 16)), (3, 12, 3, (16, 16))])
+def test_param_count_general_networks(dim, N, K, hs):
+    d = lfs.make_desc(dim, 8, N, 0, kernel=K, hidden_sizes=hs)
+    assert lfs.param_count(d) == si.param_count(dim, N, 0, K, hs)
+
+
+def test_general_network_validation():
+    lib = lfs.load()
+    out = ctypes.c_size_t(0)
+    for kw, code in [(dict(kernel=4), -1), (dict(kernel=9), -1), (dict(kernel=-1), -1),
+                     (dict(hidden_sizes=(8, 0)), -1), (dict(hidden_sizes=(8, 65)), -2)]:
+        d = lfs.make_desc(2, 8, 2, 8, **kw)
+        assert lib.lfs_workspace_bytes(ctypes.byref(d), 4, 0, ctypes.byref(out)) == code, kw
+    d = lfs.make_desc(2, 8, 2, 8)
+    d.n_hidden = 5
+    assert lib.lfs_workspace_bytes(ctypes.byref(d), 4, 0, ctypes.byref(out)) == -1
+    # a non-default network has no fused kernel; the explicit default one does
+    fused = lfs.make_desc(2, 8, 2, 8, kernel=5, algo=lfs.ALGO_FUSED)
+    assert lib.lfs_workspace_bytes(ctypes.byref(fused), 4, 0, ctypes.byref(out)) == -2
+    dflt = lfs.make_desc(2, 8, 2, 0, kernel=3, hidden_sizes=(8, 8), algo=lfs.ALGO_FUSED)
+    assert lib.lfs_workspace_bytes(ctypes.byref(dflt), 4, 0, ctypes.byref(out)) == 0
 
 
 @pytest.mark.parametrize("dim,N,C", [(2, 16, 8), (2, 16, 16), (3, 12, 16), (3, 16, 32)])
