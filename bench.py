@@ -218,6 +218,31 @@ def hbm_kernels(reps=20):
     return out
 
 
+def general_networks(steps=200):
+    """Training steps/s of the example shape (2D L=8, 16 layers, batch 64, BF16) with other
+    s/t networks from the parameter file's hidden_sizes / kernel_size, on the
+    general-network kernels, beside the default network (hidden [8, 8], kernel 3)."""
+    import torch
+    import seeded_inputs as si
+    from paper_2208_08903_amd import flow as fl
+    from paper_2208_08903_amd import lfs
+    out = {}
+    for name, K, hs in (("default_8x8_k3", 0, None), ("hidden_8x8_k5", 5, (8, 8)),
+                        ("hidden_16x16x16_k3", 3, (16, 16, 16)), ("hidden_8_k3", 3, (8,))):
+        f = fl.Flow(2, 8, 16, 8, lfs.LFS_BF16_CONV, kernel=K, hidden_sizes=hs,
+                    params=si.flow_params(2, 16, 8, kernel=K or 3, hidden_sizes=hs))
+        tr = fl.Trainer(f, 64, -4.0, 8.0)
+        for _ in range(5):
+            tr.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            tr.step()
+        torch.cuda.synchronize()
+        out[name] = {"params": f.P, "train_steps_per_s": round(steps / (time.perf_counter() - t0), 1)}
+    return out
+
+
 def other_workloads(params_2d):
     """Side figures for the other workloads: the 2D L=8 example shape (latency of one batch of 64,
     a 2000-proposal chain), the 3D L=8 training step, and 3D L=16 C=32 training at batch 256
@@ -459,6 +484,7 @@ def main():
         out["hbm_kernels"] = hbm_kernels()
         out["other_workloads"] = other_workloads(params)
         _progress("other workloads done")
+        out["general_networks_2d_L8"] = general_networks()
         out["trained_2d_L8_example"] = trained_example()
         _progress("trained example and chain quality done")
         out["serving"] = serving()

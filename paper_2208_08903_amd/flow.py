@@ -61,16 +61,32 @@ class Flow:
         return f
 
 
+def step_lr(gamma: float, every: int):
+    """Step-decay schedule: lr_t = lr gamma^floor((t - 1) / every) for Adam step t >= 1."""
+    return lambda lr, t: lr * gamma ** ((t - 1) // every)
+
+
+def exp_lr(gamma: float):
+    """Exponential schedule: lr_t = lr gamma^(t - 1)."""
+    return lambda lr, t: lr * gamma ** (t - 1)
+
+
 class Trainer:
-    """Reverse-KL training on fresh prior batches; all buffers allocated once."""
+    """Reverse-KL training on fresh prior batches; all buffers allocated once.
+
+    lr_schedule (the example parameter file's lr_scheduler, empty there: a constant
+    rate): None, or a function (base_lr, t) -> learning rate of Adam step t >= 1,
+    e.g. step_lr or exp_lr.  It runs on the host and only sets the rate passed to
+    the Adam kernel."""
 
     def __init__(self, flow: Flow, B: int, m2: float, lam: float, lr=1e-3, key=12345,
-                 betas=(0.9, 0.999), eps=1e-8):
+                 betas=(0.9, 0.999), eps=1e-8, lr_schedule=None):
         self.flow, self.B = flow, B
         dev, V, N = flow.device, flow.V, flow.n_layers
         self.m2 = torch.tensor([m2], dtype=torch.float64, device=dev)
         self.lam = torch.tensor([lam], dtype=torch.float64, device=dev)
         self.lr, self.betas, self.eps, self.key = lr, betas, eps, key
+        self.lr_schedule = lr_schedule
         f32, f64 = torch.float32, torch.float64
         self.z = torch.empty(B, V, dtype=f32, device=dev)
         self.phi = torch.empty(B, V, dtype=f32, device=dev)
@@ -103,10 +119,14 @@ class Trainer:
         lfs.flow_backward(f.desc, f.params, self.saved, self.gphi, 1.0 / self.B, self.gparams, None,
                           self.ws_b)
 
+    def current_lr(self, t=None):
+        t = self.t if t is None else t
+        return self.lr if self.lr_schedule is None else float(self.lr_schedule(self.lr, t))
+
     def update(self):
         self.t += 1
-        lfs.adam_step(self.flow.params, self.gparams, self.m, self.v, self.lr, self.betas[0],
-                      self.betas[1], self.eps, self.t)
+        lfs.adam_step(self.flow.params, self.gparams, self.m, self.v, self.current_lr(),
+                      self.betas[0], self.betas[1], self.eps, self.t)
 
     def step(self):
         self.draw()

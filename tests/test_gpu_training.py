@@ -28,3 +28,25 @@ def test_training_is_bitwise_reproducible():
         fl.train(f, 50, 64, -4.0, 8.0)
         runs.append(f.params.cpu().numpy())
     np.testing.assert_array_equal(runs[0], runs[1])
+
+
+def test_lr_schedule_sets_the_adam_rate():
+    """A schedule only changes the rate handed to the Adam kernel: a constant schedule
+    trains bit-identically to none, and a rate of 0 after the first step freezes the
+    parameters (Adam moves p by lr times its update)."""
+    def run(schedule, steps):
+        f = fl.Flow(2, 8, 4, 8, lfs.LFS_BF16_CONV, params=si.flow_params(2, 4, 8))
+        tr = fl.Trainer(f, 64, -4.0, 8.0, lr=1e-3, lr_schedule=schedule)
+        out = []
+        for _ in range(steps):
+            tr.step()
+            out.append(f.params.cpu().numpy().copy())
+        return out
+    plain = run(None, 4)
+    const = run(lambda lr, t: lr, 4)
+    np.testing.assert_array_equal(plain[-1], const[-1])
+    frozen = run(lambda lr, t: lr if t == 1 else 0.0, 4)
+    np.testing.assert_array_equal(frozen[0], plain[0])
+    for p in frozen[1:]:
+        np.testing.assert_array_equal(p, frozen[0])
+    assert not np.array_equal(plain[-1], plain[0])
