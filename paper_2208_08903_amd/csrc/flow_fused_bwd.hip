@@ -14,10 +14,14 @@
 // Every convolution is an implicit GEMM on the matrix cores.  The weight
 // gradients are GEMMs whose reduction runs over the sites; their operands are
 // 8 (BF16) or 4 (FP32) consecutive sites of one channel.  In BF16 mode the
-// activations are therefore also kept channel-major, so each operand is one
-// 16-byte LDS read (a +-1 offset along the fast axis is a funnel shift with one
-// extra element); FP32 operands are single values read from the site-major
-// copy.  Weight-gradient tiles accumulate in registers over all of a
+// activations stay site-major and those operands come from two transposing LDS
+// reads (ds_read_b64_tr_b16); g_o, the masked field and, in 3D, g_a2 also keep
+// channel-major rows, read 16 bytes at a time (a +-1 offset along the fast
+// axis is a funnel shift with one extra element).  FP32 operands are single
+// values read from the site-major tensors.  Halo copies of the site-major
+// tensors are filled in one cooperative pass after each producing pass, and
+// the layer's weight fragments are staged in LDS once per launch where they
+// fit.  Weight-gradient tiles accumulate in registers over all of a
 // workgroup's samples, are summed across waves in a fixed order, and written
 // as one partial per workgroup; a fixed-order reduction over workgroups gives
 // the gradient, so results are bitwise reproducible.
