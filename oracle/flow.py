@@ -30,12 +30,25 @@ design notes):
     per entry of hidden_sizes (default [C, C]), then conv(->2), all with an odd
     kernel K (default 3) per axis, offsets -K//2 .. K//2.
   * Loss: the batch mean of log q + S with z held fixed (path-wise gradient).
+  * Batch norm (the example parameter file's use_bn, false there and otherwise
+    undefined): with batch_norm, every hidden convolution's output a is
+    normalised per channel before its LeakyReLU, y = gamma (a - mean) /
+    sqrt(var + 1e-5) + beta, with learnable gamma, beta.  Training (batch
+    statistics) takes the mean and the biased variance over the batch and all
+    sites; sampling takes running statistics, updated after each training
+    forward as r <- (1 - m) r + m s with momentum m (default 0.1) and the
+    unbiased variance n/(n - 1) var, n = B V.  The network reads only the
+    frozen sites, so the statistics do too and the log-det is still the sum of
+    s over the active sites.
 
 Parameter layout (shared data contract): per layer W1[C][1][T], b1[C],
 W2[C][C][T], b2[C], W3[2][C][T], b3[2]; taps row-major over delta in
 {-1,0,1}^dim, axis 0 slowest.  A general network stores, per layer and per
 convolution i in order, W_i[cout_i][cin_i][T] then b_i[cout_i], with T = K^dim
-and taps row-major over {-K//2..K//2}^dim.
+and taps row-major over {-K//2..K//2}^dim.  With batch norm a hidden
+convolution's b_i is followed by gamma_i[cout_i] then beta_i[cout_i]; the
+statistics (not parameters) are stored per layer and hidden convolution as
+mean[cout_i] then var[cout_i].
 
 Emulated storage precision (emulate = "fp32" or "bf16"; None is plain FP64):
 every convolution's operands -- the input tensor and the weights, in the
@@ -53,7 +66,13 @@ for the adjoint gradient; for general networks (tests/test_oracle_flow_variants.
 the layout, tap order and one-hot orientation for kernels 1, 5 and 7, conv
 adjoints, invertibility, brute-force Jacobians, a hand-computed pointwise layer,
 central finite differences of the loss, and bit-identity of the explicit
-(C, C), kernel-3 network with the default one.
+(C, C), kernel-3 network with the default one; for batch norm
+(tests/test_oracle_flow_bn.py) the layout, unit statistics of the normalised
+activations, the bias dropping out under batch statistics, running statistics
+equal to the batch's reproducing batch mode, running mode equal to a plain
+network with the normalisation folded into the convolutions, invertibility, the
+brute-force Jacobian of a whole batch, the running average against numpy's
+unbiased variance, and central finite differences of the loss in both modes.
 """
 from __future__ import annotations
 
@@ -67,6 +86,8 @@ from .prior import log_prior
 from .rounding import ROUNDERS, to_fp32
 
 LEAKY_SLOPE = 0.01
+BN_EPS = 1e-5
+BN_MOMENTUM = 0.1
 
 
 @dataclass(frozen=True)
@@ -79,6 +100,7 @@ class FlowShape:
     parity0: int = 0
     kernel: int = 3
     hidden_sizes: tuple = ()   # empty: (hidden, hidden)
+    batch_norm: bool = False
 
     @property
     def V(self) -> int:
@@ -129,11 +151,15 @@ def unpack(params, fs: FlowShape):
         off += n
         return a
 
+    n_conv = len(fs.conv_shapes)
     for _ in range(fs.n_layers):
         lay = []
-        for co, ci in fs.conv_shapes:
+        for i, (co, ci) in enumerate(fs.conv_shapes):
             lay.append(take(co * ci * T, (co, ci, T)))
             lay.append(take(co, (co,)))
+            if fs.batch_norm and i < n_conv - 1:
+                lay.append(take(co, (co,)))      # gamma
+                lay.append(take(co, (co,)))      # beta
         layers.append(tuple(lay))
     if off != p.size:
         raise ValueError(f"parameter vector has {p.size} entries, layout needs {off}")
@@ -142,6 +168,92 @@ def unpack(params, fs: FlowShape):
 
 def pack(layers) -> np.ndarray:
     return np.concatenate([np.concatenate([a.ravel() for a in lay]) for lay in layers])
+
+
+def split_convs(lay, fs: FlowShape):
+    """Per convolution of a layer's tuple: (W, b, gamma, beta); gamma and beta are
+    None without batch norm and for the last convolution."""
+    out, k = [], 0
+    n_conv = len(fs.conv_shapes)
+    for i in range(n_conv):
+        W, b = lay[k], lay[k + 1]
+        k += 2
+        g = be = None
+        if fs.batch_norm and i < n_conv - 1:
+            g, be = lay[k], lay[k + 1]
+            k += 2
+        out.append((W, b, g, be))
+    return out
+
+
+def initial_bn_stats(fs: FlowShape):
+    """Running statistics before training: mean 0, variance 1, per layer and hidden convolution."""
+    return [[(np.zeros(w), np.ones(w)) for w in fs.widths] for _ in range(fs.n_layers)]
+
+
+def pack_bn_stats(stats) -> np.ndarray:
+    return np.concatenate([np.concatenate([np.concatenate([m, v]) for m, v in lay]) for lay in stats])
+
+
+def unpack_bn_stats(vec, fs: FlowShape):
+    v = np.asarray(vec, dtype=np.float64).ravel()
+    out, off = [], 0
+    for _ in range(fs.n_layers):
+        lay = []
+        for w in fs.widths:
+            lay.append((v[off:off + w], v[off + w:off + 2 * w]))
+            off += 2 * w
+        out.append(lay)
+    if off != v.size:
+        raise ValueError(f"statistics vector has {v.size} entries, layout needs {off}")
+    return out
+
+
+def _per_channel(v, ndim):
+    return np.asarray(v).reshape((1, -1) + (1,) * (ndim - 2))
+
+
+def batch_norm(a, gamma, beta, stats=None):
+    """Per-channel normalisation of a [B, c, *lattice] over the batch and all sites.
+
+    stats None: the batch's own mean and biased variance; else the given (mean, var).
+    Returns y = gamma (a - mean) / sqrt(var + eps) + beta, the normalised xhat, the
+    reciprocal deviation r = 1 / sqrt(var + eps), and the (mean, var) used."""
+    ax = (0,) + tuple(range(2, a.ndim))
+    if stats is None:
+        mean = a.mean(axis=ax)
+        var = ((a - _per_channel(mean, a.ndim)) ** 2).mean(axis=ax)
+    else:
+        mean, var = (np.asarray(x, dtype=np.float64) for x in stats)
+    r = 1.0 / np.sqrt(var + BN_EPS)
+    xh = (a - _per_channel(mean, a.ndim)) * _per_channel(r, a.ndim)
+    y = _per_channel(gamma, a.ndim) * xh + _per_channel(beta, a.ndim)
+    return y, xh, r, (mean, var)
+
+
+def batch_norm_vjp(g_y, xh, r, gamma, batch_stats: bool):
+    """Adjoint of `batch_norm`: (g_a, g_gamma, g_beta).  With batch statistics the
+    mean and variance depend on every entry of a:
+    g_a = gamma r (g_y - mean(g_y) - xhat mean(g_y xhat)), means per channel."""
+    ax = (0,) + tuple(range(2, g_y.ndim))
+    g_gamma = (g_y * xh).sum(axis=ax)
+    g_beta = g_y.sum(axis=ax)
+    scale = _per_channel(gamma * r, g_y.ndim)
+    if not batch_stats:
+        return scale * g_y, g_gamma, g_beta
+    n = g_y.size // g_y.shape[1]
+    return (scale * (g_y - _per_channel(g_beta / n, g_y.ndim) - xh * _per_channel(g_gamma / n, g_y.ndim)),
+            g_gamma, g_beta)
+
+
+def bn_running_update(running, batch, n: int, momentum: float = BN_MOMENTUM):
+    """Running statistics after one training batch of n = B V terms per channel:
+    r <- (1 - m) r + m s, with the unbiased variance n / (n - 1) var."""
+    out = []
+    for lay_r, lay_b in zip(running, batch):
+        out.append([((1 - momentum) * rm + momentum * bm, (1 - momentum) * rv + momentum * bv * n / (n - 1))
+                    for (rm, rv), (bm, bv) in zip(lay_r, lay_b)])
+    return out
 
 
 def shifted(u, delta, dim: int):
@@ -212,40 +324,49 @@ def _rounders(emulate):
     return ROUNDERS[emulate], to_fp32
 
 
-def net(x, lay, mF, fs: FlowShape, emulate=None):
-    """s/t network of one layer.  Returns (acts, hs, o, s, t): the hidden
-    pre-activations a_1 .. a_n, the inputs h_0 = mask_F x, h_i = leaky(a_i) of
-    every convolution, the output o and s, t."""
+def net(x, lay, mF, fs: FlowShape, emulate=None, bn_stats=None, bn_cache=None):
+    """s/t network of one layer.  Returns (acts, hs, o, s, t): the inputs of every
+    LeakyReLU a_1 .. a_n (the normalised y_i with batch norm), the inputs h_0 =
+    mask_F x, h_i = leaky(a_i) of every convolution, the output o and s, t.
+
+    Batch norm: bn_stats is None for batch statistics or this layer's running
+    (mean, var) per hidden convolution; bn_cache, a list, receives per hidden
+    convolution (xhat, r, gamma, (mean, var) used)."""
     R, _ = _rounders(emulate)
     h = (x * mF)[:, None]
     acts, hs = [], [h]
-    nconv = len(lay) // 2
-    for i in range(nconv - 1):
-        a = conv(R(h), R(lay[2 * i]), lay[2 * i + 1], fs.dim)
+    convs = split_convs(lay, fs)
+    for i, (W, b, gamma, beta) in enumerate(convs[:-1]):
+        a = conv(R(h), R(W), b, fs.dim)
+        if gamma is not None:
+            a, xh, r, st = batch_norm(a, gamma, beta, None if bn_stats is None else bn_stats[i])
+            if bn_cache is not None:
+                bn_cache.append((xh, r, gamma, st))
         h = leaky(a)
         acts.append(a)
         hs.append(h)
-    o = conv(R(h), R(lay[-2]), lay[-1], fs.dim)
+    o = conv(R(h), R(convs[-1][0]), convs[-1][1], fs.dim)
     s = np.tanh(o[:, 0]) if fs.final_tanh else o[:, 0]
     t = o[:, 1]
     return acts, hs, o, s, t
 
 
-def coupling_forward(x, lay, layer: int, fs: FlowShape, emulate=None):
+def coupling_forward(x, lay, layer: int, fs: FlowShape, emulate=None, bn_stats=None, bn_cache=None):
     """One layer in the sampling direction.  Returns (y, sum_A s per sample)."""
     mF = frozen_mask(fs, layer)
     mA = 1.0 - mF
-    *_, s, t = net(x, lay, mF, fs, emulate)
+    *_, s, t = net(x, lay, mF, fs, emulate, bn_stats, bn_cache)
     y = _rounders(emulate)[1](np.where(mA > 0, x * np.exp(s) + t, x))
     ax = tuple(range(1, x.ndim))
     return y, np.sum(mA * s, axis=ax)
 
 
-def coupling_inverse(y, lay, layer: int, fs: FlowShape):
-    """Inverse of `coupling_forward`: s, t depend only on the frozen sites, which are unchanged."""
+def coupling_inverse(y, lay, layer: int, fs: FlowShape, bn_stats=None):
+    """Inverse of `coupling_forward`: s, t depend only on the frozen sites, which are
+    unchanged (and so are batch statistics over the same batch)."""
     mF = frozen_mask(fs, layer)
     mA = 1.0 - mF
-    *_, s, t = net(y, lay, mF, fs)
+    *_, s, t = net(y, lay, mF, fs, bn_stats=bn_stats)
     x = np.where(mA > 0, (y - t) * np.exp(-s), y)
     ax = tuple(range(1, y.ndim))
     return x, np.sum(mA * s, axis=ax)
@@ -256,30 +377,44 @@ def as_lattice(z, fs: FlowShape):
     return z.reshape((z.shape[0],) + fs.lattice)
 
 
-def flow_forward(params, z, fs: FlowShape, return_saved: bool = False, emulate=None):
-    """phi = F^{-1}(z) with log q.  Returns dict(phi, logdet, logr, logq[, saved])."""
+def _layer_stats(bn_stats, l):
+    return None if bn_stats is None else bn_stats[l]
+
+
+def flow_forward(params, z, fs: FlowShape, return_saved: bool = False, emulate=None, bn_stats=None):
+    """phi = F^{-1}(z) with log q.  Returns dict(phi, logdet, logr, logq[, saved]).
+
+    Batch norm: bn_stats None normalises with batch statistics, else with the given
+    running statistics (per layer, per hidden convolution (mean, var)); the result
+    then also holds bn_used, the (mean, var) each hidden convolution used (the
+    batch's mean and biased variance under batch statistics)."""
     layers = unpack(params, fs)
     x = as_lattice(z, fs)
     logdet = np.zeros(x.shape[0])
     saved = [x]
+    used = []
     for l, lay in enumerate(layers):
-        x, ld = coupling_forward(x, lay, l, fs, emulate)
+        cache = []
+        x, ld = coupling_forward(x, lay, l, fs, emulate, _layer_stats(bn_stats, l), cache)
+        used.append([c[3] for c in cache])
         logdet = logdet + ld
         saved.append(x)
     logr = log_prior(z)
     out = dict(phi=x, logdet=logdet, logr=logr, logq=logr - logdet)
+    if fs.batch_norm:
+        out["bn_used"] = used
     if return_saved:
         out["saved"] = saved
     return out
 
 
-def flow_inverse(params, phi, fs: FlowShape):
+def flow_inverse(params, phi, fs: FlowShape, bn_stats=None):
     """z = F(phi) and the log-determinant of F^{-1} at z (for tests)."""
     layers = unpack(params, fs)
     x = as_lattice(phi, fs)
     logdet = np.zeros(x.shape[0])
     for l in reversed(range(fs.n_layers)):
-        x, ld = coupling_inverse(x, layers[l], l, fs)
+        x, ld = coupling_inverse(x, layers[l], l, fs, _layer_stats(bn_stats, l))
         logdet = logdet + ld
     return x, logdet
 
@@ -289,23 +424,24 @@ def log_weights(S, logq):
     return -np.asarray(S, dtype=np.float64) - np.asarray(logq, dtype=np.float64)
 
 
-def kl_loss(params, z, fs: FlowShape, m2, lam) -> float:
+def kl_loss(params, z, fs: FlowShape, m2, lam, bn_stats=None) -> float:
     """Shifted reverse KL, batch mean of log q + S, with z fixed."""
-    f = flow_forward(params, z, fs)
+    f = flow_forward(params, z, fs, bn_stats=bn_stats)
     S = _action(f["phi"], m2, lam, fs.dim)
     return float(np.mean(f["logq"] + S))
 
 
-def flow_vjp(params, z, fs: FlowShape, g_phi, g_logq, emulate=None):
+def flow_vjp(params, z, fs: FlowShape, g_phi, g_logq, emulate=None, bn_stats=None):
     """Vector-Jacobian product of (phi, log q) = flow_forward(params, z) w.r.t. (params, z).
 
     g_phi: [B, *lattice] or [B, V]; g_logq: [B] or scalar.  Returns (g_params packed, g_z [B, V]).
     Hand-derived adjoint, layer by layer in reverse, recomputing each layer's network
-    from the layer's input field.
+    from the layer's input field.  bn_stats as in flow_forward; batch statistics are
+    differentiated as functions of the whole batch.
     """
     layers = unpack(params, fs)
     R, RF = _rounders(emulate)
-    f = flow_forward(params, z, fs, return_saved=True, emulate=emulate)
+    f = flow_forward(params, z, fs, return_saved=True, emulate=emulate, bn_stats=bn_stats)
     saved = f["saved"]
     B = saved[0].shape[0]
     g_logq = np.broadcast_to(np.asarray(g_logq, dtype=np.float64), (B,))
@@ -318,21 +454,31 @@ def flow_vjp(params, z, fs: FlowShape, g_phi, g_logq, emulate=None):
         x = saved[l]
         mF = frozen_mask(fs, l)
         mA = 1.0 - mF
-        acts, hs, o, s, t = net(x, lay, mF, fs, emulate)
+        cache = []
+        acts, hs, o, s, t = net(x, lay, mF, fs, emulate, _layer_stats(bn_stats, l), cache)
         es = np.exp(s)
         g_y = gx
         g_t = mA * g_y
         g_s = mA * (g_y * x * es + g_ld.reshape(shp))
         g_o0 = g_s * (1.0 - s * s) if fs.final_tanh else g_s
         # back through the convolutions, last to first: g is the gradient of the
-        # current convolution's output (g_o, then g_a_i = g_h_i leaky'(a_i))
+        # current convolution's output (g_o, then g_a_i = g_h_i leaky'(a_i), taken
+        # back through the normalisation with batch norm)
         g = np.stack([g_o0, g_t], axis=1)
-        nconv = len(lay) // 2
-        lay_grads = [None] * (2 * nconv)
-        for i in reversed(range(nconv)):
-            lay_grads[2 * i], lay_grads[2 * i + 1] = _weight_grad(g, hs[i], fs.dim, R, fs.kernel)
-            g_in = conv_transpose(R(g), R(lay[2 * i]), fs.dim)
-            g = g_in * leaky_grad(acts[i - 1]) if i > 0 else g_in
+        convs = split_convs(lay, fs)
+        conv_grads = [None] * len(convs)
+        bn_grads = [()] * len(convs)
+        for i in reversed(range(len(convs))):
+            conv_grads[i] = _weight_grad(g, hs[i], fs.dim, R, fs.kernel)
+            g = conv_transpose(R(g), R(convs[i][0]), fs.dim)
+            if i == 0:
+                break
+            g = g * leaky_grad(acts[i - 1])
+            if convs[i - 1][2] is not None:
+                xh, r, gamma, _ = cache[i - 1]
+                g, d_gamma, d_beta = batch_norm_vjp(g, xh, r, gamma, bn_stats is None)
+                bn_grads[i - 1] = (d_gamma, d_beta)
+        lay_grads = [a for cg, bg in zip(conv_grads, bn_grads) for a in (*cg, *bg)]
         g_h0 = g[:, 0]
         gx = RF(np.where(mA > 0, g_y * es, g_y + mF * g_h0))
         grads[l] = tuple(lay_grads)
@@ -352,10 +498,10 @@ def _weight_grad(g, u, dim: int, R, kernel: int = 3):
     return dW, db.astype(np.float64)
 
 
-def loss_gradient(params, z, fs: FlowShape, m2, lam, emulate=None):
+def loss_gradient(params, z, fs: FlowShape, m2, lam, emulate=None, bn_stats=None):
     """Gradient of the batch-mean reverse-KL loss w.r.t. the packed parameters, z fixed."""
-    f = flow_forward(params, z, fs, emulate=emulate)
+    f = flow_forward(params, z, fs, emulate=emulate, bn_stats=bn_stats)
     B = f["phi"].shape[0]
     g_phi = _force(f["phi"], m2, lam, fs.dim) / B
-    g_params, _ = flow_vjp(params, z, fs, g_phi, 1.0 / B, emulate=emulate)
+    g_params, _ = flow_vjp(params, z, fs, g_phi, 1.0 / B, emulate=emulate, bn_stats=bn_stats)
     return g_params

@@ -12,7 +12,10 @@ order, with C hidden channels and T = 3**dim stencil taps:
     W1[C][1][T]  b1[C]  W2[C][C][T]  b2[C]  W3[2][C][T]  b3[2]
 
 Taps are row-major over the offset delta in {-1,0,1}**dim, axis 0 slowest.
-Channel 0 of the last convolution is s, channel 1 is t.
+Channel 0 of the last convolution is s, channel 1 is t.  With batch norm every
+hidden convolution's bias is followed by its gamma[cout] and beta[cout]; the
+normalisation statistics are a separate vector, per layer and hidden
+convolution mean[cout] then var[cout].
 
 The default initialisation follows the paper's example parameter file (model
 seed 2021) with the weight law N(0, 0.1) read as standard deviation 0.1 and the
@@ -32,37 +35,56 @@ def taps_per_conv(dim: int, kernel: int = 3) -> int:
 
 
 def layer_block_sizes(dim: int, hidden: int, kernel: int = 3,
-                      hidden_sizes=None) -> list[tuple[str, int]]:
+                      hidden_sizes=None, batch_norm: bool = False) -> list[tuple[str, int]]:
     """(name, size) of a layer's blocks: W_i[cout][cin][T], b_i[cout] for every
-    convolution, with hidden widths hidden_sizes (default [hidden, hidden])."""
+    convolution (then gamma_i[cout], beta_i[cout] for a hidden one with batch
+    norm), with hidden widths hidden_sizes (default [hidden, hidden])."""
     T = taps_per_conv(dim, kernel)
     w = list(hidden_sizes) if hidden_sizes else [hidden, hidden]
     cin, cout = [1] + w, w + [2]
     out = []
     for i, (ci, co) in enumerate(zip(cin, cout), start=1):
         out += [(f"W{i}", co * ci * T), (f"b{i}", co)]
+        if batch_norm and i <= len(w):
+            out += [(f"gamma{i}", co), (f"beta{i}", co)]
     return out
 
 
-def param_count(dim: int, n_layers: int, hidden: int, kernel: int = 3, hidden_sizes=None) -> int:
-    return n_layers * sum(n for _, n in layer_block_sizes(dim, hidden, kernel, hidden_sizes))
+def param_count(dim: int, n_layers: int, hidden: int, kernel: int = 3, hidden_sizes=None,
+                batch_norm: bool = False) -> int:
+    return n_layers * sum(n for _, n in layer_block_sizes(dim, hidden, kernel, hidden_sizes, batch_norm))
 
 
 def flow_params(dim: int, n_layers: int, hidden: int, seed: int = 2021,
                 w_std: float = 0.1, b_std: float = 0.0, kernel: int = 3,
-                hidden_sizes=None) -> np.ndarray:
-    """Packed FP32 flow parameters: weights N(0, w_std), biases N(0, b_std) (0 if b_std == 0)."""
-    n = param_count(dim, n_layers, hidden, kernel, hidden_sizes)
+                hidden_sizes=None, batch_norm: bool = False, gamma_std: float = 0.0) -> np.ndarray:
+    """Packed FP32 flow parameters: weights N(0, w_std), biases and batch-norm betas
+    N(0, b_std) (0 if b_std == 0), batch-norm gammas 1 + N(0, gamma_std)."""
+    n = param_count(dim, n_layers, hidden, kernel, hidden_sizes, batch_norm)
     rng = np.random.default_rng(seed)
     p = rng.normal(0.0, w_std, size=n)
     brng = np.random.default_rng(seed + 7919)
+    grng = np.random.default_rng(seed + 104729)
     off = 0
     for _ in range(n_layers):
-        for name, sz in layer_block_sizes(dim, hidden, kernel, hidden_sizes):
-            if name.startswith("b"):
+        for name, sz in layer_block_sizes(dim, hidden, kernel, hidden_sizes, batch_norm):
+            if name.startswith("gamma"):
+                p[off:off + sz] = 1.0 + (grng.normal(0.0, gamma_std, size=sz) if gamma_std > 0 else 0.0)
+            elif name.startswith("b"):
                 p[off:off + sz] = brng.normal(0.0, b_std, size=sz) if b_std > 0 else 0.0
             off += sz
     return p.astype(np.float32)
+
+
+def bn_stats(seed: int, n_layers: int, widths, mean_std: float = 0.3, var_range=(0.5, 2.0)) -> np.ndarray:
+    """FP32 running statistics, per layer and hidden convolution of width w:
+    mean[w] ~ N(0, mean_std) then var[w] ~ U(var_range)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_layers):
+        for w in widths:
+            out += [rng.normal(0.0, mean_std, size=w), rng.uniform(*var_range, size=w)]
+    return np.concatenate(out).astype(np.float32)
 
 
 def normal_fields(seed: int, B: int, V: int) -> np.ndarray:
