@@ -79,9 +79,15 @@ typedef enum lfs_algo { LFS_ALGO_AUTO = 0, LFS_ALGO_GENERIC = 1, LFS_ALGO_FUSED 
  *   n_hidden   number of hidden convolutions, 1..LFS_MAX_HIDDEN; 0 means two
  *              of `hidden` channels
  *   hidden_sizes  their channel counts, 1..64 each (first n_hidden entries)
+ *   batch_norm 0 or 1 (the parameter file's use_bn): 1 normalises every hidden
+ *              convolution's output per channel before its LeakyReLU,
+ *              y = gamma (a - mean) / sqrt(var + 1e-5) + beta, with batch or
+ *              running statistics (lfs_flow_forward_bn); such a flow runs only
+ *              through the _bn entry points
  * A network equal to the default (kernel 3, two hidden convolutions of 8, 16
- * or 32 channels) runs on the fused or generic kernels; any other runs on the
- * general-network kernels (LFS_ALGO_FUSED then reports EUNSUPPORTED). */
+ * or 32 channels, no batch norm) runs on the fused or generic kernels; any
+ * other runs on the general-network kernels (LFS_ALGO_FUSED then reports
+ * EUNSUPPORTED). */
 #define LFS_MAX_HIDDEN 4
 typedef struct lfs_flow_desc {
   int32_t dim;
@@ -95,7 +101,11 @@ typedef struct lfs_flow_desc {
   int32_t kernel;
   int32_t n_hidden;
   int32_t hidden_sizes[LFS_MAX_HIDDEN];
+  int32_t batch_norm;
 } lfs_flow_desc;
+
+/* Statistics a batch-norm flow normalises with. */
+typedef enum lfs_bn_mode { LFS_BN_BATCH = 0, LFS_BN_RUNNING = 1 } lfs_bn_mode;
 
 /* Persistent state of one independence Metropolis-Hastings chain (device POD,
  * caller-owned; zero-initialise a new chain).
@@ -126,8 +136,15 @@ const char* lfs_version(void);
  * the last convolution is s, channel 1 is t.  A general network stores, per
  * layer, W_i[cout_i][cin_i][T] then b_i[cout_i] for each convolution in order
  * (cin = 1, w_1, .., w_n; cout = w_1, .., w_n, 2), T = K^dim, taps row-major
- * over {-K/2..K/2}^dim.  Returns 0 for an invalid desc. */
+ * over {-K/2..K/2}^dim; with batch norm a hidden convolution's b_i is followed
+ * by gamma_i[cout_i] then beta_i[cout_i].  Returns 0 for an invalid desc. */
 size_t lfs_param_count(const lfs_flow_desc* desc);
+
+/* Number of FP32 entries of a batch-norm flow's statistics vector: per layer,
+ * per hidden convolution i in order, mean[w_i] then var[w_i].  Returns 0
+ * without batch norm or for an invalid desc.  Before training the running
+ * statistics are mean 0, var 1. */
+size_t lfs_bn_stats_count(const lfs_flow_desc* desc);
 
 /* Workspace bytes needed by lfs_flow_forward (for_backward = 0) or
  * lfs_flow_backward (for_backward = 1) at batch size B.  Writes *bytes. */
@@ -173,7 +190,8 @@ int32_t lfs_prior_normal_streams(int32_t B, int32_t V, const uint64_t* keys,
  *   saved_x   [(N+1)][B][V] FP32 output or NULL: the field entering each
  *             layer, then phi; required later by lfs_flow_backward
  *   ws        workspace of at least lfs_workspace_bytes(desc, B, 0) bytes
- * Errors: EINVAL (desc, B, nulls), EUNSUPPORTED (hidden), EWORKSPACE. */
+ * Errors: EINVAL (desc, B, nulls, a desc with batch norm), EUNSUPPORTED
+ * (hidden), EWORKSPACE. */
 int32_t lfs_flow_forward(const lfs_flow_desc* desc, const float* params, int32_t B,
                          const float* z, float* phi, double* logq, double* logdet,
                          float* saved_x, void* ws, size_t ws_bytes, void* stream);
@@ -195,6 +213,43 @@ int32_t lfs_flow_forward(const lfs_flow_desc* desc, const float* params, int32_t
 int32_t lfs_flow_backward(const lfs_flow_desc* desc, const float* params, int32_t B,
                           const float* saved_x, const float* g_phi, double g_logq,
                           float* g_params, float* g_z, void* ws, size_t ws_bytes, void* stream);
+
+/* lfs_flow_forward for flows with batch norm (the example parameter file's
+ * use_bn, otherwise undefined by the paper).  Each hidden convolution's output
+ * a is normalised per channel, over the batch and all sites, before its
+ * LeakyReLU.  The network reads only the frozen sites, so the statistics do
+ * too and the log-determinant is still the sum of s over the active sites.
+ *   bn_mode   LFS_BN_BATCH (training): mean and biased variance of this batch
+ *             (FP64 sums in a fixed order); the samples of a batch are coupled
+ *             through them.  If bn_stats is not NULL it holds running
+ *             statistics, updated in place after each layer's network as
+ *             r = (1 - momentum) r + momentum s with the unbiased variance
+ *             n/(n-1) var, n = B V.
+ *             LFS_BN_RUNNING (sampling): normalise with bn_stats (read only);
+ *             samples are independent.
+ *   bn_stats  [lfs_bn_stats_count] FP32 device, or NULL in batch mode
+ *   momentum  in [0, 1] (0.1 is customary); ignored in running mode
+ * Other arguments as lfs_flow_forward.  A desc without batch norm ignores the
+ * bn arguments and computes what lfs_flow_forward does.
+ * Errors: as lfs_flow_forward; EINVAL also for a bn_mode other than the two,
+ * running mode with bn_stats NULL, or momentum outside [0, 1]. */
+int32_t lfs_flow_forward_bn(const lfs_flow_desc* desc, const float* params, int32_t B,
+                            const float* z, float* phi, double* logq, double* logdet,
+                            float* saved_x, int32_t bn_mode, float* bn_stats, double momentum,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* lfs_flow_backward for flows with batch norm.  In batch mode the statistics
+ * are recomputed from saved_x and differentiated as functions of the whole
+ * batch (g_a = gamma r (g_y - mean(g_y) - xhat mean(g_y xhat)) per channel,
+ * r = 1/sqrt(var + 1e-5), xhat = (a - mean) r); bn_stats is not read and may
+ * be NULL.  In running mode bn_stats (required) holds the statistics the
+ * forward used and g_a = gamma r g_y.  The gamma and beta gradients are the
+ * sums of g_y xhat and g_y.  Other arguments and errors as lfs_flow_backward
+ * and lfs_flow_forward_bn. */
+int32_t lfs_flow_backward_bn(const lfs_flow_desc* desc, const float* params, int32_t B,
+                             const float* saved_x, const float* g_phi, double g_logq,
+                             int32_t bn_mode, const float* bn_stats, float* g_params, float* g_z,
+                             void* ws, size_t ws_bytes, void* stream);
 
 /* Lattice action (paper Sec. 1, action, Laplacian and potential equations):
  *   S = sum_n [ -phi(n) sum_mu (phi(n+mu) + phi(n-mu) - 2 phi(n))

@@ -20,6 +20,7 @@ int32_t make_geom(const lfs_flow_desc* d, FlowGeom* g) {
   const int K = d->kernel == 0 ? 3 : d->kernel;
   if (K < 1 || K > 7 || !(K & 1)) return LFS_EINVAL;
   if (d->n_hidden < 0 || d->n_hidden > LFS_MAX_HIDDEN) return LFS_EINVAL;
+  if (d->batch_norm != 0 && d->batch_norm != 1) return LFS_EINVAL;
   int widths[LFS_MAX_HIDDEN], nh;
   if (d->n_hidden == 0) {
     if (d->hidden != 8 && d->hidden != 16 && d->hidden != 32) return LFS_EUNSUPPORTED;
@@ -39,12 +40,13 @@ int32_t make_geom(const lfs_flow_desc* d, FlowGeom* g) {
   g->K = K;
   g->T = d->dim == 2 ? K * K : K * K * K;
   g->N = d->n_layers;
-  g->net_default = K == 3 && nh == 2 && widths[0] == widths[1] &&
+  g->bn = d->batch_norm == 1;
+  g->net_default = !g->bn && K == 3 && nh == 2 && widths[0] == widths[1] &&
                    (widths[0] == 8 || widths[0] == 16 || widths[0] == 32);
   g->C = g->net_default ? widths[0] : 0;
   g->n_conv = nh + 1;
   {
-    size_t off = 0;
+    size_t off = 0, soff = 0;
     for (int i = 0; i < g->n_conv; ++i) {
       g->cin[i] = i == 0 ? 1 : widths[i - 1];
       g->cout[i] = i == nh ? 2 : widths[i];
@@ -52,8 +54,15 @@ int32_t make_geom(const lfs_flow_desc* d, FlowGeom* g) {
       off += (size_t)g->cout[i] * g->cin[i] * g->T;
       g->offb[i] = off;
       off += g->cout[i];
+      if (g->bn && i < nh) {
+        g->offg[i] = off;
+        off += 2 * (size_t)g->cout[i];
+        g->offS[i] = soff;
+        soff += 2 * (size_t)g->cout[i];
+      }
     }
     g->P_layer = off;
+    g->S_layer = soff;
   }
   g->final_tanh = d->final_tanh;
   g->parity0 = d->parity0;
@@ -67,6 +76,7 @@ int32_t make_geom(const lfs_flow_desc* d, FlowGeom* g) {
   g->off_W3 = g->offW[g->n_conv - 1];
   g->off_b3 = g->offb[g->n_conv - 1];
   g->P_total = g->P_layer * (size_t)g->N;
+  g->S_total = g->S_layer * (size_t)g->N;
   return LFS_OK;
 }
 
@@ -113,6 +123,11 @@ extern "C" size_t lfs_param_count(const lfs_flow_desc* desc) {
   return lfs::make_geom(desc, &g) == LFS_OK ? g.P_total : 0;
 }
 
+extern "C" size_t lfs_bn_stats_count(const lfs_flow_desc* desc) {
+  lfs::FlowGeom g;
+  return lfs::make_geom(desc, &g) == LFS_OK ? g.S_total : 0;
+}
+
 extern "C" int32_t lfs_workspace_bytes(const lfs_flow_desc* desc, int32_t B, int32_t for_backward,
                                        size_t* bytes) {
   lfs::FlowGeom g;
@@ -130,7 +145,7 @@ extern "C" int32_t lfs_flow_forward(const lfs_flow_desc* desc, const float* para
   lfs::FlowGeom g;
   const int32_t s = lfs::make_geom(desc, &g);
   if (s != LFS_OK) return s;
-  if (B <= 0 || !params || !z || !phi || !logq) return LFS_EINVAL;
+  if (B <= 0 || !params || !z || !phi || !logq || g.bn) return LFS_EINVAL;
   if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_ok(g, 0)) return LFS_EUNSUPPORTED;
   const size_t need = lfs::ws_bytes(g, B, 0);
   if (need > 0 && (!ws || ws_bytes < need)) return LFS_EWORKSPACE;
@@ -152,7 +167,7 @@ extern "C" int32_t lfs_flow_backward(const lfs_flow_desc* desc, const float* par
   lfs::FlowGeom g;
   const int32_t s = lfs::make_geom(desc, &g);
   if (s != LFS_OK) return s;
-  if (B <= 0 || !params || !saved_x || !g_phi || !g_params) return LFS_EINVAL;
+  if (B <= 0 || !params || !saved_x || !g_phi || !g_params || g.bn) return LFS_EINVAL;
   if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_ok(g, 1)) return LFS_EUNSUPPORTED;
   const size_t need = lfs::ws_bytes(g, B, 1);
   if (need > 0 && (!ws || ws_bytes < need)) return LFS_EWORKSPACE;
@@ -165,4 +180,50 @@ extern "C" int32_t lfs_flow_backward(const lfs_flow_desc* desc, const float* par
     default:
       return lfs::net_backward(g, params, B, saved_x, g_phi, g_logq, g_params, g_z, (char*)ws, st);
   }
+}
+
+extern "C" int32_t lfs_flow_forward_bn(const lfs_flow_desc* desc, const float* params, int32_t B,
+                                       const float* z, float* phi, double* logq, double* logdet,
+                                       float* saved_x, int32_t bn_mode, float* bn_stats,
+                                       double momentum, void* ws, size_t ws_bytes, void* stream) {
+  lfs::FlowGeom g;
+  const int32_t s = lfs::make_geom(desc, &g);
+  if (s != LFS_OK) return s;
+  if (!g.bn) {
+    lfs_flow_desc plain = *desc;
+    plain.batch_norm = 0;
+    return lfs_flow_forward(&plain, params, B, z, phi, logq, logdet, saved_x, ws, ws_bytes, stream);
+  }
+  if (B <= 0 || !params || !z || !phi || !logq) return LFS_EINVAL;
+  if (bn_mode != LFS_BN_BATCH && bn_mode != LFS_BN_RUNNING) return LFS_EINVAL;
+  if (bn_mode == LFS_BN_RUNNING && !bn_stats) return LFS_EINVAL;
+  if (!(momentum >= 0.0 && momentum <= 1.0)) return LFS_EINVAL;
+  if (desc->algo == LFS_ALGO_FUSED) return LFS_EUNSUPPORTED;
+  const size_t need = lfs::net_ws_bytes(g, B, 0);
+  if (!ws || ws_bytes < need) return LFS_EWORKSPACE;
+  return lfs::net_forward_bn(g, params, B, z, phi, logq, logdet, saved_x, bn_mode, bn_stats,
+                             (float)momentum, (char*)ws, (hipStream_t)stream);
+}
+
+extern "C" int32_t lfs_flow_backward_bn(const lfs_flow_desc* desc, const float* params, int32_t B,
+                                        const float* saved_x, const float* g_phi, double g_logq,
+                                        int32_t bn_mode, const float* bn_stats, float* g_params,
+                                        float* g_z, void* ws, size_t ws_bytes, void* stream) {
+  lfs::FlowGeom g;
+  const int32_t s = lfs::make_geom(desc, &g);
+  if (s != LFS_OK) return s;
+  if (!g.bn) {
+    lfs_flow_desc plain = *desc;
+    plain.batch_norm = 0;
+    return lfs_flow_backward(&plain, params, B, saved_x, g_phi, g_logq, g_params, g_z, ws, ws_bytes,
+                             stream);
+  }
+  if (B <= 0 || !params || !saved_x || !g_phi || !g_params) return LFS_EINVAL;
+  if (bn_mode != LFS_BN_BATCH && bn_mode != LFS_BN_RUNNING) return LFS_EINVAL;
+  if (bn_mode == LFS_BN_RUNNING && !bn_stats) return LFS_EINVAL;
+  if (desc->algo == LFS_ALGO_FUSED) return LFS_EUNSUPPORTED;
+  const size_t need = lfs::net_ws_bytes(g, B, 1);
+  if (!ws || ws_bytes < need) return LFS_EWORKSPACE;
+  return lfs::net_backward_bn(g, params, B, saved_x, g_phi, g_logq, bn_mode, bn_stats, g_params, g_z,
+                              (char*)ws, (hipStream_t)stream);
 }

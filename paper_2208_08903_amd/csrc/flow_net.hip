@@ -7,6 +7,13 @@
 // channel counts, one thread per (sample, site, output channel), activations
 // in HBM.  In BF16 mode every convolution operand is rounded to BF16 and
 // products are accumulated in FP32, as in the other kernel families.
+//
+// Batch norm (the parameter file's use_bn): a hidden convolution's output a is
+// kept, its per-channel statistics are reduced over the batch and all sites in
+// FP64 with a fixed chunk order (two passes: the mean, then the squared
+// deviations), and h = leaky(gamma (a - mean) r + beta), r = 1/sqrt(var + eps),
+// is written next to it.  The backward turns g_y = g_h leaky'(y) into g_a with
+// the per-channel sums of g_y xhat and g_y.
 #include "lfs_common.hpp"
 #include "lfs_internal.hpp"
 
@@ -16,6 +23,8 @@ namespace {
 inline dim3 grid_for(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
 constexpr int kWgChunk = 4096;  // (sample, site) terms per weight-gradient workgroup
+constexpr double kBnEps = 1e-5;
+constexpr int kMaxWidth = 64;   // hidden_sizes entries are at most 64
 
 // Site n + sign * delta_t, delta_t the offsets of tap t of an odd kernel K.
 template <int DIM>
@@ -227,10 +236,145 @@ __global__ void kn_gz(int64_t n, const float* __restrict__ gx, const float* __re
   if (i < n) gz[i] = gx[i] - g_logq * z[i];
 }
 
+// ---- batch norm ------------------------------------------------------------
+
+__device__ __forceinline__ float bn_xhat(float a, double mean, double r) {
+  return (float)(((double)a - mean) * r);
+}
+
+// Per-channel partial sums of a [B V][c] tensor over the (sample, site) terms of
+// chunk blockIdx.y, channel blockIdx.x:
+//   OP 0: sum a                      -> partial[chunk][ch]
+//   OP 1: sum (a - mean)^2           -> partial[chunk][ch], mean = sums[ch] / n
+//   OP 2: sum g xhat and sum g       -> partial[chunk][ch] and partial[chunk][c + ch]
+template <int OP>
+__global__ void __launch_bounds__(256) kn_bn_partial(int64_t BV, int c, const float* __restrict__ a,
+                                                     const float* __restrict__ g,
+                                                     const double* __restrict__ sums,
+                                                     const double* __restrict__ mean,
+                                                     const double* __restrict__ rstd,
+                                                     double* __restrict__ partial, int P) {
+  __shared__ double sh[16];
+  const int ch = blockIdx.x, chunk = blockIdx.y;
+  const int64_t t0 = (int64_t)chunk * kWgChunk, t1 = t0 + kWgChunk < BV ? t0 + kWgChunk : BV;
+  double s0 = 0.0, s1 = 0.0;
+  const double mu = OP == 1 ? sums[ch] / (double)BV : OP == 2 ? mean[ch] : 0.0;
+  const double r = OP == 2 ? rstd[ch] : 0.0;
+  for (int64_t bn = t0 + threadIdx.x; bn < t1; bn += blockDim.x) {
+    const float v = a[bn * c + ch];
+    if (OP == 0) {
+      s0 += (double)v;
+    } else if (OP == 1) {
+      const double d = (double)v - mu;
+      s0 += d * d;
+    } else {
+      const float gv = g[bn * c + ch];
+      s0 += (double)gv * (double)bn_xhat(v, mu, r);
+      s1 += (double)gv;
+    }
+  }
+  s0 = block_sum(s0, sh);
+  if (OP == 2) s1 = block_sum(s1, sh);
+  if (threadIdx.x == 0) {
+    partial[(size_t)chunk * P + ch] = s0;
+    if (OP == 2) partial[(size_t)chunk * P + c + ch] = s1;
+  }
+}
+
+// out[p] = sum over chunks of partial[chunk][p], in chunk order (FP64).
+__global__ void __launch_bounds__(256) kn_reduce_d(int G, int P, const double* __restrict__ partial,
+                                                   double* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double acc = 0.0;
+  for (int k = 0; k < G; ++k) acc += partial[(size_t)k * P + p];
+  out[p] = acc;
+}
+
+// Batch statistics of channel ch from sums[ch] = sum a and the partials of
+// sum (a - mean)^2; optionally the running-statistics update.
+__global__ void kn_bn_batch_stats(int c, int G, int64_t BV, const double* __restrict__ sums,
+                                  const double* __restrict__ partial, double* __restrict__ mean,
+                                  double* __restrict__ rstd, float* __restrict__ running,
+                                  float momentum) {
+  const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ch >= c) return;
+  double sq = 0.0;
+  for (int k = 0; k < G; ++k) sq += partial[(size_t)k * c + ch];
+  const double n = (double)BV;
+  const double mu = sums[ch] / n, var = sq / n;
+  mean[ch] = mu;
+  rstd[ch] = 1.0 / sqrt(var + kBnEps);
+  if (running) {
+    const double m = (double)momentum;
+    running[ch] = (float)((1.0 - m) * (double)running[ch] + m * mu);
+    running[c + ch] = (float)((1.0 - m) * (double)running[c + ch] + m * var * (n / (n - 1.0)));
+  }
+}
+
+// Running statistics (mean[c] then var[c]) into mean and r.
+__global__ void kn_bn_running_stats(int c, const float* __restrict__ stats, double* __restrict__ mean,
+                                    double* __restrict__ rstd) {
+  const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ch >= c) return;
+  mean[ch] = (double)stats[ch];
+  rstd[ch] = 1.0 / sqrt((double)stats[c + ch] + kBnEps);
+}
+
+// h = leaky(gamma xhat + beta) over [B V][c].
+__global__ void __launch_bounds__(256) kn_bn_apply(int64_t n, int c, const float* __restrict__ a,
+                                                   const double* __restrict__ mean,
+                                                   const double* __restrict__ rstd,
+                                                   const float* __restrict__ gamma,
+                                                   const float* __restrict__ beta,
+                                                   float* __restrict__ h) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int ch = (int)(i % c);
+  h[i] = leaky(gamma[ch] * bn_xhat(a[i], mean[ch], rstd[ch]) + beta[ch]);
+}
+
+// g_y -> g_a in place (batch statistics: gamma r (g_y - sg / n - xhat sgx / n);
+// running: gamma r g_y), sums = (sgx[c], sg[c]); the first 2c threads also
+// write the gamma and beta gradients (sgx, then sg; B V >= 4 so the grid of
+// B V c threads covers them).
+__global__ void __launch_bounds__(256) kn_bn_bwd(int64_t BV, int c, int batch, const float* __restrict__ a,
+                                                 const double* __restrict__ mean,
+                                                 const double* __restrict__ rstd,
+                                                 const float* __restrict__ gamma,
+                                                 const double* __restrict__ sums, float* __restrict__ g,
+                                                 float* __restrict__ g_gamma_beta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 2 * c) g_gamma_beta[i] = (float)sums[i];
+  if (i >= BV * c) return;
+  const int ch = (int)(i % c);
+  const double k = (double)gamma[ch] * rstd[ch];
+  double ga = (double)g[i];
+  if (batch) {
+    const double n = (double)BV;
+    ga -= sums[c + ch] / n + (double)bn_xhat(a[i], mean[ch], rstd[ch]) * (sums[ch] / n);
+  }
+  g[i] = (float)(k * ga);
+}
+
+// ---------------------------------------------------------------------------
+
 struct NetWs {
   double *logdet, *logr, *partial;
   float* h[LFS_MAX_HIDDEN];
   float *o, *go, *gA, *gB, *gxA, *gxB;
+  // batch norm: pre-normalisation outputs, per-channel mean and r of every
+  // hidden convolution, and per-channel sums
+  float* a[LFS_MAX_HIDDEN];
+  double *bn_mean, *bn_rstd, *bn_sum;
+};
+
+// How a layer's network normalises (batch norm only).
+struct BnRun {
+  int mode;              // LFS_BN_BATCH or LFS_BN_RUNNING
+  const float* stats;    // running mode: the layer's statistics block
+  float* running;        // batch mode: the layer's running statistics to update, or null
+  float momentum;
 };
 
 int max_width(const FlowGeom& g) {
@@ -240,7 +384,7 @@ int max_width(const FlowGeom& g) {
 }
 
 size_t max_conv_params(const FlowGeom& g) {
-  size_t m = 0;
+  size_t m = 2 * kMaxWidth;  // batch-norm partials: two sums per channel
   for (int i = 0; i < g.n_conv; ++i) {
     const size_t p = (size_t)g.cout[i] * g.cin[i] * g.T + g.cout[i];
     m = m > p ? m : p;
@@ -263,6 +407,14 @@ NetWs carve(const FlowGeom& g, int B, char* base, size_t* total) {
   w.logr = (double*)take(sizeof(double) * B);
   for (int i = 0; i + 1 < g.n_conv; ++i) w.h[i] = (float*)take(sizeof(float) * BV * g.cout[i]);
   w.o = (float*)take(sizeof(float) * BV * 2);
+  const size_t partial_bytes = sizeof(double) * (size_t)wg_chunks(B, g.V) * max_conv_params(g);
+  if (g.bn) {
+    for (int i = 0; i + 1 < g.n_conv; ++i) w.a[i] = (float*)take(sizeof(float) * BV * g.cout[i]);
+    w.bn_mean = (double*)take(sizeof(double) * LFS_MAX_HIDDEN * kMaxWidth);
+    w.bn_rstd = (double*)take(sizeof(double) * LFS_MAX_HIDDEN * kMaxWidth);
+    w.bn_sum = (double*)take(sizeof(double) * 2 * kMaxWidth);
+    w.partial = (double*)take(partial_bytes);
+  }
   const size_t fwd = off;
   const int mw = max_width(g);
   w.go = (float*)take(sizeof(float) * BV * 2);
@@ -270,30 +422,57 @@ NetWs carve(const FlowGeom& g, int B, char* base, size_t* total) {
   w.gB = (float*)take(sizeof(float) * BV * mw);
   w.gxA = (float*)take(sizeof(float) * BV);
   w.gxB = (float*)take(sizeof(float) * BV);
-  w.partial = (double*)take(sizeof(double) * (size_t)wg_chunks(B, g.V) * max_conv_params(g));
+  if (!g.bn) w.partial = (double*)take(partial_bytes);
   total[0] = fwd;
   total[1] = off;
   return w;
 }
 
+// Batch norm of hidden convolution i from w.a[i] into w.h[i] (statistics into
+// w.bn_mean / w.bn_rstd + i * kMaxWidth).
+void run_bn(const FlowGeom& g, const float* p, int B, int i, const BnRun& bn, const NetWs& w,
+            hipStream_t st) {
+  const int64_t BV = (int64_t)B * g.V;
+  const int c = g.cout[i], G = wg_chunks(B, g.V);
+  double* mean = w.bn_mean + i * kMaxWidth;
+  double* rstd = w.bn_rstd + i * kMaxWidth;
+  if (bn.mode == LFS_BN_BATCH) {
+    hipLaunchKernelGGL(kn_bn_partial<0>, dim3(c, G), dim3(256), 0, st, BV, c, w.a[i], nullptr, nullptr,
+                       nullptr, nullptr, w.partial, c);
+    hipLaunchKernelGGL(kn_reduce_d, dim3(1), dim3(kMaxWidth), 0, st, G, c, w.partial, w.bn_sum);
+    hipLaunchKernelGGL(kn_bn_partial<1>, dim3(c, G), dim3(256), 0, st, BV, c, w.a[i], nullptr, w.bn_sum,
+                       nullptr, nullptr, w.partial, c);
+    hipLaunchKernelGGL(kn_bn_batch_stats, dim3(1), dim3(kMaxWidth), 0, st, c, G, BV, w.bn_sum, w.partial,
+                       mean, rstd, bn.running ? bn.running + g.offS[i] : nullptr, bn.momentum);
+  } else {
+    hipLaunchKernelGGL(kn_bn_running_stats, dim3(1), dim3(kMaxWidth), 0, st, c, bn.stats + g.offS[i],
+                       mean, rstd);
+  }
+  hipLaunchKernelGGL(kn_bn_apply, grid_for(BV * c), dim3(256), 0, st, BV * c, c, w.a[i], mean, rstd,
+                     p + g.offg[i], p + g.offg[i] + c, w.h[i]);
+}
+
 // The layer's network from its input field x: hidden activations into w.h, output into w.o.
 template <int DIM, bool BF16>
 void run_net(const FlowGeom& g, const float* p, int B, const float* x, int fpar, const NetWs& w,
-             hipStream_t st) {
+             const BnRun& bn, hipStream_t st) {
   const int64_t BV = (int64_t)B * g.V;
   for (int i = 0; i < g.n_conv; ++i) {
     const bool last = i + 1 == g.n_conv;
-    float* out = last ? w.o : w.h[i];
+    const bool norm = g.bn && !last;
+    float* out = last ? w.o : norm ? w.a[i] : w.h[i];
     const float* in = i == 0 ? x : w.h[i - 1];
     hipLaunchKernelGGL((kn_conv<DIM, BF16>), grid_for(BV * g.cout[i]), dim3(256), 0, st, g.L, g.V, B,
-                       g.K, g.T, g.cin[i], g.cout[i], i == 0, fpar, !last, in, p + g.offW[i],
+                       g.K, g.T, g.cin[i], g.cout[i], i == 0, fpar, !last && !norm, in, p + g.offW[i],
                        p + g.offb[i], out);
+    if (norm) run_bn(g, p, B, i, bn, w, st);
   }
 }
 
 template <int DIM, bool BF16>
 int32_t forward_impl(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
-                     double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
+                     double* logq, double* logdet, float* saved, int bn_mode, float* stats,
+                     float momentum, char* ws, hipStream_t st) {
   size_t tot[2];
   NetWs w = carve(g, B, ws, tot);
   const size_t BV = (size_t)B * g.V;
@@ -310,7 +489,14 @@ int32_t forward_impl(const FlowGeom& g, const float* params, int B, const float*
     const float* xin = saved ? saved + (size_t)l * BV : phi;
     float* xout = saved ? saved + (size_t)(l + 1) * BV : phi;
     const int fpar = g.frozen_parity(l);
-    run_net<DIM, BF16>(g, p, B, xin, fpar, w, st);
+    BnRun bn{bn_mode, nullptr, nullptr, momentum};
+    if (g.bn && stats) {
+      if (bn_mode == LFS_BN_RUNNING)
+        bn.stats = stats + (size_t)l * g.S_layer;
+      else
+        bn.running = stats + (size_t)l * g.S_layer;
+    }
+    run_net<DIM, BF16>(g, p, B, xin, fpar, w, bn, st);
     if (BF16)
       hipLaunchKernelGGL((kn_couple<DIM, double>), dim3(B), dim3(256), 0, st, g.L, g.V, fpar,
                          g.final_tanh, xin, w.o, xout, w.logdet);
@@ -328,8 +514,8 @@ int32_t forward_impl(const FlowGeom& g, const float* params, int B, const float*
 
 template <int DIM, bool BF16>
 int32_t backward_impl(const FlowGeom& g, const float* params, int B, const float* saved,
-                      const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
-                      hipStream_t st) {
+                      const float* g_phi, double g_logq, int bn_mode, const float* stats,
+                      float* g_params, float* g_z, char* ws, hipStream_t st) {
   size_t tot[2];
   NetWs w = carve(g, B, ws, tot);
   const int64_t BV = (int64_t)B * g.V;
@@ -344,7 +530,10 @@ int32_t backward_impl(const FlowGeom& g, const float* params, int B, const float
     const float* x = saved + (size_t)l * BV;
     const int fpar = g.frozen_parity(l);
     float* gx = gxs[which];
-    run_net<DIM, BF16>(g, p, B, x, fpar, w, st);
+    // batch statistics are recomputed (no running update); running ones are read
+    const BnRun bn{bn_mode, g.bn && bn_mode == LFS_BN_RUNNING ? stats + (size_t)l * g.S_layer : nullptr,
+                   nullptr, 0.f};
+    run_net<DIM, BF16>(g, p, B, x, fpar, w, bn, st);
     hipLaunchKernelGGL((kn_affine_bwd<DIM>), grid_for(BV), dim3(256), 0, st, g.L, g.V, B, fpar,
                        g.final_tanh, x, w.o, gy, (float)(-g_logq), w.go, gx);
     // back through the convolutions, last to first; gcur is the gradient of
@@ -360,6 +549,19 @@ int32_t backward_impl(const FlowGeom& g, const float* params, int B, const float
       hipLaunchKernelGGL((kn_conv_t<DIM, BF16>), grid_for(BV * g.cin[i]), dim3(256), 0, st, g.L, g.V, B,
                          g.K, g.T, g.cin[i], g.cout[i], i == 0, fpar, gcur, p + g.offW[i],
                          i == 0 ? nullptr : w.h[i - 1], gin);
+      if (g.bn && i > 0) {
+        // gin holds g_y of hidden convolution j = i - 1: back through its normalisation
+        const int j = i - 1, c = g.cout[j];
+        const double* mean = w.bn_mean + j * kMaxWidth;
+        const double* rstd = w.bn_rstd + j * kMaxWidth;
+        hipLaunchKernelGGL(kn_bn_partial<2>, dim3(c, G), dim3(256), 0, st, BV, c, w.a[j], gin, nullptr,
+                           mean, rstd, w.partial, 2 * c);
+        hipLaunchKernelGGL(kn_reduce_d, dim3(1), dim3(2 * kMaxWidth), 0, st, G, 2 * c, w.partial,
+                           w.bn_sum);
+        hipLaunchKernelGGL(kn_bn_bwd, grid_for(BV * c), dim3(256), 0, st, BV, c,
+                           bn_mode == LFS_BN_BATCH, w.a[j], mean, rstd, p + g.offg[j], w.bn_sum, gin,
+                           gp + g.offg[j]);
+      }
       gcur = gin;
     }
     gy = gx;
@@ -378,23 +580,43 @@ size_t net_ws_bytes(const FlowGeom& g, int B, int for_backward) {
   return tot[for_backward ? 1 : 0];
 }
 
+int32_t net_forward_bn(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
+                       double* logq, double* logdet, float* saved, int bn_mode, float* stats,
+                       float momentum, char* ws, hipStream_t st) {
+  if (g.dim == 2)
+    return g.bf16() ? forward_impl<2, true>(g, params, B, z, phi, logq, logdet, saved, bn_mode, stats,
+                                            momentum, ws, st)
+                    : forward_impl<2, false>(g, params, B, z, phi, logq, logdet, saved, bn_mode, stats,
+                                             momentum, ws, st);
+  return g.bf16() ? forward_impl<3, true>(g, params, B, z, phi, logq, logdet, saved, bn_mode, stats,
+                                          momentum, ws, st)
+                  : forward_impl<3, false>(g, params, B, z, phi, logq, logdet, saved, bn_mode, stats,
+                                           momentum, ws, st);
+}
+
+int32_t net_backward_bn(const FlowGeom& g, const float* params, int B, const float* saved,
+                        const float* g_phi, double g_logq, int bn_mode, const float* stats,
+                        float* g_params, float* g_z, char* ws, hipStream_t st) {
+  if (g.dim == 2)
+    return g.bf16() ? backward_impl<2, true>(g, params, B, saved, g_phi, g_logq, bn_mode, stats, g_params,
+                                             g_z, ws, st)
+                    : backward_impl<2, false>(g, params, B, saved, g_phi, g_logq, bn_mode, stats,
+                                              g_params, g_z, ws, st);
+  return g.bf16() ? backward_impl<3, true>(g, params, B, saved, g_phi, g_logq, bn_mode, stats, g_params,
+                                           g_z, ws, st)
+                  : backward_impl<3, false>(g, params, B, saved, g_phi, g_logq, bn_mode, stats, g_params,
+                                            g_z, ws, st);
+}
+
 int32_t net_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
                     double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
-  if (g.dim == 2)
-    return g.bf16() ? forward_impl<2, true>(g, params, B, z, phi, logq, logdet, saved, ws, st)
-                    : forward_impl<2, false>(g, params, B, z, phi, logq, logdet, saved, ws, st);
-  return g.bf16() ? forward_impl<3, true>(g, params, B, z, phi, logq, logdet, saved, ws, st)
-                  : forward_impl<3, false>(g, params, B, z, phi, logq, logdet, saved, ws, st);
+  return net_forward_bn(g, params, B, z, phi, logq, logdet, saved, LFS_BN_BATCH, nullptr, 0.f, ws, st);
 }
 
 int32_t net_backward(const FlowGeom& g, const float* params, int B, const float* saved,
                      const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
                      hipStream_t st) {
-  if (g.dim == 2)
-    return g.bf16() ? backward_impl<2, true>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st)
-                    : backward_impl<2, false>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
-  return g.bf16() ? backward_impl<3, true>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st)
-                  : backward_impl<3, false>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
+  return net_backward_bn(g, params, B, saved, g_phi, g_logq, LFS_BN_BATCH, nullptr, g_params, g_z, ws, st);
 }
 
 }  // namespace lfs

@@ -24,6 +24,12 @@ struct FlowGeom {
   int cin[LFS_MAX_HIDDEN + 1], cout[LFS_MAX_HIDDEN + 1];
   size_t offW[LFS_MAX_HIDDEN + 1], offb[LFS_MAX_HIDDEN + 1];
   bool net_default;
+  // batch norm: gamma (beta follows at + cout) of hidden convolution i within a
+  // layer; its statistics (mean, then var at + cout) within a layer's block of
+  // S_layer entries of the statistics vector
+  bool bn;
+  size_t offg[LFS_MAX_HIDDEN], offS[LFS_MAX_HIDDEN];
+  size_t S_layer, S_total;
 
   int frozen_parity(int layer) const { return (layer + parity0) & 1; }
   bool bf16() const { return precision == LFS_BF16_CONV; }
@@ -49,6 +55,14 @@ int32_t net_forward(const FlowGeom& g, const float* params, int B, const float* 
 int32_t net_backward(const FlowGeom& g, const float* params, int B, const float* saved,
                      const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
                      hipStream_t st);
+// Batch-norm variants (g.bn): bn_mode lfs_bn_mode; stats per the statistics
+// layout (running statistics, updated in batch mode if not null).
+int32_t net_forward_bn(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
+                       double* logq, double* logdet, float* saved, int bn_mode, float* stats,
+                       float momentum, char* ws, hipStream_t st);
+int32_t net_backward_bn(const FlowGeom& g, const float* params, int B, const float* saved,
+                        const float* g_phi, double g_logq, int bn_mode, const float* stats,
+                        float* g_params, float* g_z, char* ws, hipStream_t st);
 
 // Fused kernels: LDS-resident per-sample lattices, matrix-core convolutions.
 bool fused_supported(const FlowGeom& g, int for_backward);

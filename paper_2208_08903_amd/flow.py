@@ -14,6 +14,10 @@ one of the library's entry points (see ``lfs``):
   chain quality (paper Sec. 1, N_indep = N / (2 tau_ac); Sec. 2.2, HMC "to
   compare results"): observables of every configuration, then autocorr over
   the chain (through the MH chain's current-configuration numbers) and ess.
+
+A flow with batch norm (the example parameter file's use_bn) trains with batch
+statistics, updating its running statistics (momentum 0.1) on every training
+forward, and samples with the running statistics.
 """
 from __future__ import annotations
 
@@ -27,16 +31,28 @@ class Flow:
     """A flow architecture, its packed FP32 parameters on the device, and workspaces."""
 
     def __init__(self, dim, L, n_layers, hidden, precision=lfs.LFS_BF16_CONV, algo=lfs.ALGO_AUTO,
-                 final_tanh=True, parity0=0, params=None, device="cuda", kernel=0, hidden_sizes=None):
+                 final_tanh=True, parity0=0, params=None, device="cuda", kernel=0, hidden_sizes=None,
+                 batch_norm=False, bn_stats=None, bn_momentum=0.1):
         self.dim, self.L, self.n_layers, self.hidden = dim, L, n_layers, hidden
         self.kernel, self.hidden_sizes = kernel, hidden_sizes
         self.V = L ** dim
         self.precision = precision
+        self.batch_norm, self.bn_momentum = bool(batch_norm), bn_momentum
         self.desc = lfs.make_desc(dim, L, n_layers, hidden, final_tanh, parity0, precision, algo,
-                                  kernel, hidden_sizes)
+                                  kernel, hidden_sizes, batch_norm)
         self.P = lfs.param_count(self.desc)
         if self.P == 0:
             raise lfs.LfsError("invalid flow description")
+        self.bn_stats = None
+        if self.batch_norm:
+            # running statistics, per layer and hidden convolution mean[w] then var[w]
+            widths = list(hidden_sizes) if hidden_sizes else [hidden, hidden]
+            init = np.concatenate([np.concatenate([np.zeros(w), np.ones(w)]) for w in widths] * n_layers)
+            if bn_stats is not None:
+                init = np.asarray(bn_stats, np.float64).ravel()
+            if init.size != lfs.bn_stats_count(self.desc):
+                raise lfs.LfsError(f"expected {lfs.bn_stats_count(self.desc)} statistics, got {init.size}")
+            self.bn_stats = torch.as_tensor(init.astype(np.float32)).to(device).contiguous()
         self.device = device
         if params is None:
             params = np.zeros(self.P, np.float32)
@@ -56,9 +72,31 @@ class Flow:
     def with_precision(self, precision):
         f = Flow(self.dim, self.L, self.n_layers, self.hidden, precision, self.desc.algo,
                  bool(self.desc.final_tanh), self.desc.parity0, device=self.device,
-                 kernel=self.kernel, hidden_sizes=self.hidden_sizes)
+                 kernel=self.kernel, hidden_sizes=self.hidden_sizes, batch_norm=self.batch_norm,
+                 bn_momentum=self.bn_momentum)
         f.params = self.params
+        f.bn_stats = self.bn_stats
         return f
+
+    def forward(self, z, phi, logq, logdet=None, saved_x=None, ws=None, train=False):
+        """phi = F^{-1}(z) and log q.  Batch norm: train=True normalises with the batch's
+        statistics and updates the running ones; otherwise the running ones are used."""
+        if not self.batch_norm:
+            lfs.flow_forward(self.desc, self.params, z, phi, logq, logdet, saved_x, ws)
+        elif train:
+            lfs.flow_forward_bn(self.desc, self.params, z, phi, logq, lfs.BN_BATCH, self.bn_stats,
+                                self.bn_momentum, logdet, saved_x, ws)
+        else:
+            lfs.flow_forward_bn(self.desc, self.params, z, phi, logq, lfs.BN_RUNNING, self.bn_stats,
+                                0.0, logdet, saved_x, ws)
+
+    def backward(self, saved_x, g_phi, g_logq, g_params, g_z=None, ws=None, train=True):
+        """Vector-Jacobian product of `forward` (batch statistics when train=True)."""
+        if not self.batch_norm:
+            lfs.flow_backward(self.desc, self.params, saved_x, g_phi, g_logq, g_params, g_z, ws)
+        else:
+            lfs.flow_backward_bn(self.desc, self.params, saved_x, g_phi, g_logq, g_params,
+                                 lfs.BN_BATCH if train else lfs.BN_RUNNING, self.bn_stats, g_z, ws)
 
 
 def step_lr(gamma: float, every: int):
@@ -109,15 +147,13 @@ class Trainer:
 
     def forward(self):
         f = self.flow
-        lfs.flow_forward(f.desc, f.params, self.z, self.phi, self.logq, None, self.saved, self.ws_f)
+        f.forward(self.z, self.phi, self.logq, None, self.saved, self.ws_f, train=True)
         lfs.action(f.dim, f.L, self.phi, self.m2, self.lam, self.S, self.gphi, 1.0 / self.B,
                    f.precision)
         lfs.log_weights(self.S, self.logq, self.logw, self.loss)
 
     def backward(self):
-        f = self.flow
-        lfs.flow_backward(f.desc, f.params, self.saved, self.gphi, 1.0 / self.B, self.gparams, None,
-                          self.ws_b)
+        self.flow.backward(self.saved, self.gphi, 1.0 / self.B, self.gparams, None, self.ws_b)
 
     def current_lr(self, t=None):
         t = self.t if t is None else t
@@ -163,7 +199,7 @@ class Sampler:
         """One batch of B proposals; log_u is a [n_chains, B/n_chains] FP64 device tensor."""
         f = self.flow
         lfs.prior_normal(self.key, self.batch * self.B, self.z)
-        lfs.flow_forward(f.desc, f.params, self.z, self.phi, self.logq, None, None, self.ws)
+        f.forward(self.z, self.phi, self.logq, None, None, self.ws)
         lfs.action(f.dim, f.L, self.phi, self.m2, self.lam, self.S, None, 1.0, f.precision)
         lfs.log_weights(self.S, self.logq, self.logw)
         lfs.mh_chain(self.logw.view(self.n_chains, -1), log_u, self.state, self.cur, self.acc)

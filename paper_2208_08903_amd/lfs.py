@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblfs.so")
 LFS_PLAIN_FP32 = 0
 LFS_BF16_CONV = 1
 ALGO_AUTO, ALGO_GENERIC, ALGO_FUSED = 0, 1, 2
+BN_BATCH, BN_RUNNING = 0, 1
 
 c_i32, c_i64, c_u64, c_f32, c_f64, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                                  ctypes.c_float, ctypes.c_double, ctypes.c_void_p,
@@ -34,7 +35,8 @@ MAX_HIDDEN = 4
 class FlowDesc(ctypes.Structure):
     _fields_ = [("dim", c_i32), ("L", c_i32), ("n_layers", c_i32), ("hidden", c_i32),
                 ("final_tanh", c_i32), ("parity0", c_i32), ("precision", c_i32), ("algo", c_i32),
-                ("kernel", c_i32), ("n_hidden", c_i32), ("hidden_sizes", c_i32 * MAX_HIDDEN)]
+                ("kernel", c_i32), ("n_hidden", c_i32), ("hidden_sizes", c_i32 * MAX_HIDDEN),
+                ("batch_norm", c_i32)]
 
     def key(self):
         return tuple(tuple(v) if f == "hidden_sizes" else getattr(self, f)
@@ -60,6 +62,11 @@ _SIGS = {
                                  c_vp, c_vp, c_sz, c_vp]),
     "lfs_flow_backward": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_f64, c_vp,
                                   c_vp, c_vp, c_sz, c_vp]),
+    "lfs_bn_stats_count": (c_sz, [ctypes.POINTER(FlowDesc)]),
+    "lfs_flow_forward_bn": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
+                                    c_vp, c_i32, c_vp, c_f64, c_vp, c_sz, c_vp]),
+    "lfs_flow_backward_bn": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_f64, c_i32,
+                                     c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "lfs_action": (c_i32, [c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_f64,
                            c_vp]),
     "lfs_log_weights": (c_i32, [c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -123,19 +130,25 @@ def _p(t, dtype=None, name="tensor"):
 
 
 def make_desc(dim, L, n_layers, hidden, final_tanh=True, parity0=0,
-              precision=LFS_PLAIN_FP32, algo=ALGO_AUTO, kernel=0, hidden_sizes=None) -> FlowDesc:
+              precision=LFS_PLAIN_FP32, algo=ALGO_AUTO, kernel=0, hidden_sizes=None,
+              batch_norm=False) -> FlowDesc:
     """hidden_sizes: the widths of the hidden convolutions (None: two of `hidden`);
-    kernel: odd kernel size per axis (0: 3)."""
+    kernel: odd kernel size per axis (0: 3); batch_norm: normalise every hidden
+    convolution's output (the _bn entry points)."""
     hs = list(hidden_sizes or [])
     if len(hs) > MAX_HIDDEN:
         raise LfsError(f"at most {MAX_HIDDEN} hidden convolutions")
     arr = (c_i32 * MAX_HIDDEN)(*(hs + [0] * (MAX_HIDDEN - len(hs))))
     return FlowDesc(dim, L, n_layers, hidden, int(final_tanh), parity0, precision, algo, kernel,
-                    len(hs), arr)
+                    len(hs), arr, int(batch_norm))
 
 
 def param_count(desc: FlowDesc) -> int:
     return int(load().lfs_param_count(ctypes.byref(desc)))
+
+
+def bn_stats_count(desc: FlowDesc) -> int:
+    return int(load().lfs_bn_stats_count(ctypes.byref(desc)))
 
 
 def workspace_bytes(desc: FlowDesc, B: int, for_backward: bool) -> int:
@@ -180,6 +193,34 @@ def flow_backward(desc, params, saved_x, g_phi, g_logq: float, g_params, g_z=Non
                                     _p(g_params, torch.float32, "g_params"),
                                     _p(g_z, torch.float32, "g_z"), _p(ws, torch.uint8, "ws"),
                                     nbytes, _stream()))
+
+
+def flow_forward_bn(desc, params, z, phi, logq, bn_mode, bn_stats=None, momentum=0.1, logdet=None,
+                    saved_x=None, ws=None):
+    """bn_mode BN_BATCH (bn_stats: running statistics updated in place, or None) or
+    BN_RUNNING (bn_stats read)."""
+    B = z.shape[0]
+    nbytes = ws.numel() if ws is not None else 0
+    _check(load().lfs_flow_forward_bn(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
+                                      _p(z, torch.float32, "z"), _p(phi, torch.float32, "phi"),
+                                      _p(logq, torch.float64, "logq"),
+                                      _p(logdet, torch.float64, "logdet"),
+                                      _p(saved_x, torch.float32, "saved_x"), int(bn_mode),
+                                      _p(bn_stats, torch.float32, "bn_stats"), float(momentum),
+                                      _p(ws, torch.uint8, "ws"), nbytes, _stream()))
+
+
+def flow_backward_bn(desc, params, saved_x, g_phi, g_logq: float, g_params, bn_mode, bn_stats=None,
+                     g_z=None, ws=None):
+    B = g_phi.shape[0]
+    nbytes = ws.numel() if ws is not None else 0
+    _check(load().lfs_flow_backward_bn(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
+                                       _p(saved_x, torch.float32, "saved_x"),
+                                       _p(g_phi, torch.float32, "g_phi"), float(g_logq), int(bn_mode),
+                                       _p(bn_stats, torch.float32, "bn_stats"),
+                                       _p(g_params, torch.float32, "g_params"),
+                                       _p(g_z, torch.float32, "g_z"), _p(ws, torch.uint8, "ws"),
+                                       nbytes, _stream()))
 
 
 def action(dim, L, phi, m2, lam, S, force=None, force_scale=1.0, precision=LFS_BF16_CONV):

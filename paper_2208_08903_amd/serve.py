@@ -231,7 +231,7 @@ class Server:
             z, phi, logq, S, logw = (g["z"][:B], g["phi"][:B], g["logq"][:B], g["S"][:B],
                                      g["logw"][:B])
             lfs.prior_normal_streams(t_keys, t_ctrs, z)
-            lfs.flow_forward(flow.desc, flow.params, z, phi, logq, None, None, g["ws"])
+            flow.forward(z, phi, logq, None, None, g["ws"])
             lfs.action(dim, L, phi, t_m2, t_lam, S, None, 1.0, self.precision)
             lfs.log_weights(S, logq, logw)
             lfs.mh_chain_ragged(t_off, logw, t_lu, self.states, t_sidx, g["cur"][:B], g["acc"][:B])

@@ -27,7 +27,7 @@ def test_library_exports_every_header_function():
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(lfs.FlowDesc) == 56   # 10 int32 fields + hidden_sizes[4]
+    assert ctypes.sizeof(lfs.FlowDesc) == 60   # 10 int32 fields + hidden_sizes[4] + batch_norm
     assert lfs.CHAIN_STATE_BYTES == 40
 
 
@@ -53,6 +53,40 @@ def test_general_network_validation():
     assert lib.lfs_workspace_bytes(ctypes.byref(fused), 4, 0, ctypes.byref(out)) == -2
     dflt = lfs.make_desc(2, 8, 2, 0, kernel=3, hidden_sizes=(8, 8), algo=lfs.ALGO_FUSED)
     assert lib.lfs_workspace_bytes(ctypes.byref(dflt), 4, 0, ctypes.byref(out)) == 0
+
+
+@pytest.mark.parametrize("dim,N,K,hs", [(2, 3, 3, (3, 5, 4)), (3, 2, 5, (2,)), (2, 4, 3, (8, 8))])
+def test_batch_norm_layout_and_validation(dim, N, K, hs):
+    lib = lfs.load()
+    d = lfs.make_desc(dim, 8, N, 0, kernel=K, hidden_sizes=hs, batch_norm=True)
+    assert lfs.param_count(d) == si.param_count(dim, N, 0, K, hs, batch_norm=True)
+    assert lfs.bn_stats_count(d) == N * 2 * sum(hs) == si.bn_stats(0, N, hs).size
+    assert lfs.bn_stats_count(lfs.make_desc(dim, 8, N, 0, kernel=K, hidden_sizes=hs)) == 0
+    out = ctypes.c_size_t(0)
+    assert lib.lfs_workspace_bytes(ctypes.byref(d), 4, 0, ctypes.byref(out)) == 0 and out.value > 0
+    need_f = out.value
+    assert lib.lfs_workspace_bytes(ctypes.byref(d), 4, 1, ctypes.byref(out)) == 0 and out.value > need_f
+    need_b = out.value
+    # the plain entry points refuse a batch-norm flow; the _bn ones validate mode,
+    # statistics, momentum and workspace before any launch (non-null dummies)
+    assert lib.lfs_flow_forward(ctypes.byref(d), 1, 4, 1, 1, 1, None, None, 1, 1 << 40, None) == -1
+    assert lib.lfs_flow_backward(ctypes.byref(d), 1, 4, 1, 1, 0.25, 1, None, 1, 1 << 40, None) == -1
+    fwd = lib.lfs_flow_forward_bn
+    assert fwd(ctypes.byref(d), 1, 4, 1, 1, 1, None, None, 2, 1, 0.1, 1, 1 << 40, None) == -1  # mode
+    assert fwd(ctypes.byref(d), 1, 4, 1, 1, 1, None, None, 1, None, 0.1, 1, 1 << 40, None) == -1  # stats
+    assert fwd(ctypes.byref(d), 1, 4, 1, 1, 1, None, None, 0, None, 1.5, 1, 1 << 40, None) == -1  # momentum
+    assert fwd(ctypes.byref(d), 1, 4, 1, 1, 1, None, None, 0, None, float("nan"), 1, 1 << 40, None) == -1
+    assert fwd(ctypes.byref(d), 1, 4, 1, 1, 1, None, None, 0, None, 0.1, 1, need_f - 1, None) == -3
+    bwd = lib.lfs_flow_backward_bn
+    assert bwd(ctypes.byref(d), 1, 4, 1, 1, 0.25, 1, None, 1, None, 1, 1 << 40, None) == -1    # stats
+    assert bwd(ctypes.byref(d), 1, 4, 1, 1, 0.25, 3, 1, 1, None, 1, 1 << 40, None) == -1       # mode
+    assert bwd(ctypes.byref(d), 1, 4, 1, 1, 0.25, 0, None, 1, None, 1, need_b - 1, None) == -3
+    fused = lfs.make_desc(dim, 8, N, 0, kernel=K, hidden_sizes=hs, batch_norm=True, algo=lfs.ALGO_FUSED)
+    assert lib.lfs_workspace_bytes(ctypes.byref(fused), 4, 0, ctypes.byref(out)) == -2
+    assert fwd(ctypes.byref(fused), 1, 4, 1, 1, 1, None, None, 0, None, 0.1, 1, 1 << 40, None) == -2
+    d.batch_norm = 2
+    assert lib.lfs_workspace_bytes(ctypes.byref(d), 4, 0, ctypes.byref(out)) == -1
+    assert lfs.param_count(d) == 0
 
 
 @pytest.mark.parametrize("dim,N,C", [(2, 16, 8), (2, 16, 16), (3, 12, 16), (3, 16, 32)])
