@@ -214,6 +214,16 @@ int32_t lfs_flow_backward(const lfs_flow_desc* desc, const float* params, int32_
                           const float* saved_x, const float* g_phi, double g_logq,
                           float* g_params, float* g_z, void* ws, size_t ws_bytes, void* stream);
 
+/* lfs_flow_backward with a cotangent of log q per sample (what an autograd
+ * engine hands over for a [B] output):
+ *   g_logq    [B] FP64 device, required
+ * g_z then includes -g_logq[b] z[b].  Everything else as lfs_flow_backward;
+ * equal entries give the same bits as lfs_flow_backward with that scalar.
+ * Errors: as lfs_flow_backward; EINVAL also for g_logq NULL. */
+int32_t lfs_flow_backward_vec(const lfs_flow_desc* desc, const float* params, int32_t B,
+                              const float* saved_x, const float* g_phi, const double* g_logq,
+                              float* g_params, float* g_z, void* ws, size_t ws_bytes, void* stream);
+
 /* lfs_flow_forward for flows with batch norm (the example parameter file's
  * use_bn, otherwise undefined by the paper).  Each hidden convolution's output
  * a is normalised per channel, over the batch and all sites, before its
@@ -244,12 +254,14 @@ int32_t lfs_flow_forward_bn(const lfs_flow_desc* desc, const float* params, int3
  * r = 1/sqrt(var + 1e-5), xhat = (a - mean) r); bn_stats is not read and may
  * be NULL.  In running mode bn_stats (required) holds the statistics the
  * forward used and g_a = gamma r g_y.  The gamma and beta gradients are the
- * sums of g_y xhat and g_y.  Other arguments and errors as lfs_flow_backward
- * and lfs_flow_forward_bn. */
+ * sums of g_y xhat and g_y.
+ *   g_logq_vec  [B] FP64 device cotangents of log q, or NULL to use g_logq for
+ *               every sample (as lfs_flow_backward_vec / lfs_flow_backward)
+ * Other arguments and errors as lfs_flow_backward and lfs_flow_forward_bn. */
 int32_t lfs_flow_backward_bn(const lfs_flow_desc* desc, const float* params, int32_t B,
                              const float* saved_x, const float* g_phi, double g_logq,
-                             int32_t bn_mode, const float* bn_stats, float* g_params, float* g_z,
-                             void* ws, size_t ws_bytes, void* stream);
+                             const double* g_logq_vec, int32_t bn_mode, const float* bn_stats,
+                             float* g_params, float* g_z, void* ws, size_t ws_bytes, void* stream);
 
 /* Lattice action (paper Sec. 1, action, Laplacian and potential equations):
  *   S = sum_n [ -phi(n) sum_mu (phi(n+mu) + phi(n-mu) - 2 phi(n))

@@ -94,7 +94,7 @@ Family family(const FlowGeom& g, int bwd) {
   return Family::Generic;
 }
 
-size_t ws_bytes(const FlowGeom& g, int B, int bwd) {
+size_t ws_bytes_of(const FlowGeom& g, int B, int bwd) {
   switch (family(g, bwd)) {
     case Family::Fused: return fused_ws_bytes(g, B, bwd);
     case Family::Generic: return generic_ws_bytes(g, B, bwd);
@@ -135,7 +135,7 @@ extern "C" int32_t lfs_workspace_bytes(const lfs_flow_desc* desc, int32_t B, int
   if (s != LFS_OK) return s;
   if (B <= 0 || !bytes) return LFS_EINVAL;
   if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_ok(g, for_backward)) return LFS_EUNSUPPORTED;
-  *bytes = lfs::ws_bytes(g, B, for_backward);
+  *bytes = lfs::ws_bytes_of(g, B, for_backward);
   return LFS_OK;
 }
 
@@ -147,7 +147,7 @@ extern "C" int32_t lfs_flow_forward(const lfs_flow_desc* desc, const float* para
   if (s != LFS_OK) return s;
   if (B <= 0 || !params || !z || !phi || !logq || g.bn) return LFS_EINVAL;
   if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_ok(g, 0)) return LFS_EUNSUPPORTED;
-  const size_t need = lfs::ws_bytes(g, B, 0);
+  const size_t need = lfs::ws_bytes_of(g, B, 0);
   if (need > 0 && (!ws || ws_bytes < need)) return LFS_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   switch (lfs::family(g, 0)) {
@@ -160,6 +160,36 @@ extern "C" int32_t lfs_flow_forward(const lfs_flow_desc* desc, const float* para
   }
 }
 
+namespace lfs {
+namespace {
+
+// Backward of a validated flow without batch norm; g_logq_vec (nullable) gives
+// each sample its own cotangent of log q.
+int32_t backward_plain(const lfs_flow_desc* desc, const FlowGeom& g, const float* params, int32_t B,
+                       const float* saved_x, const float* g_phi, double g_logq,
+                       const double* g_logq_vec, float* g_params, float* g_z, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (B <= 0 || !params || !saved_x || !g_phi || !g_params || g.bn) return LFS_EINVAL;
+  if (desc->algo == LFS_ALGO_FUSED && !fused_ok(g, 1)) return LFS_EUNSUPPORTED;
+  const size_t need = ws_bytes_of(g, B, 1);
+  if (need > 0 && (!ws || ws_bytes < need)) return LFS_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  switch (family(g, 1)) {
+    case Family::Fused:
+      return fused_backward(g, params, B, saved_x, g_phi, g_logq, g_logq_vec, g_params, g_z,
+                            (char*)ws, st);
+    case Family::Generic:
+      return generic_backward(g, params, B, saved_x, g_phi, g_logq, g_logq_vec, g_params, g_z,
+                              (char*)ws, st);
+    default:
+      return net_backward(g, params, B, saved_x, g_phi, g_logq, g_logq_vec, g_params, g_z,
+                          (char*)ws, st);
+  }
+}
+
+}  // namespace
+}  // namespace lfs
+
 extern "C" int32_t lfs_flow_backward(const lfs_flow_desc* desc, const float* params, int32_t B,
                                      const float* saved_x, const float* g_phi, double g_logq,
                                      float* g_params, float* g_z, void* ws, size_t ws_bytes,
@@ -167,19 +197,20 @@ extern "C" int32_t lfs_flow_backward(const lfs_flow_desc* desc, const float* par
   lfs::FlowGeom g;
   const int32_t s = lfs::make_geom(desc, &g);
   if (s != LFS_OK) return s;
-  if (B <= 0 || !params || !saved_x || !g_phi || !g_params || g.bn) return LFS_EINVAL;
-  if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_ok(g, 1)) return LFS_EUNSUPPORTED;
-  const size_t need = lfs::ws_bytes(g, B, 1);
-  if (need > 0 && (!ws || ws_bytes < need)) return LFS_EWORKSPACE;
-  hipStream_t st = (hipStream_t)stream;
-  switch (lfs::family(g, 1)) {
-    case lfs::Family::Fused:
-      return lfs::fused_backward(g, params, B, saved_x, g_phi, g_logq, g_params, g_z, (char*)ws, st);
-    case lfs::Family::Generic:
-      return lfs::generic_backward(g, params, B, saved_x, g_phi, g_logq, g_params, g_z, (char*)ws, st);
-    default:
-      return lfs::net_backward(g, params, B, saved_x, g_phi, g_logq, g_params, g_z, (char*)ws, st);
-  }
+  return lfs::backward_plain(desc, g, params, B, saved_x, g_phi, g_logq, nullptr, g_params, g_z, ws,
+                             ws_bytes, stream);
+}
+
+extern "C" int32_t lfs_flow_backward_vec(const lfs_flow_desc* desc, const float* params, int32_t B,
+                                         const float* saved_x, const float* g_phi,
+                                         const double* g_logq, float* g_params, float* g_z, void* ws,
+                                         size_t ws_bytes, void* stream) {
+  lfs::FlowGeom g;
+  const int32_t s = lfs::make_geom(desc, &g);
+  if (s != LFS_OK) return s;
+  if (!g_logq) return LFS_EINVAL;
+  return lfs::backward_plain(desc, g, params, B, saved_x, g_phi, 0.0, g_logq, g_params, g_z, ws,
+                             ws_bytes, stream);
 }
 
 extern "C" int32_t lfs_flow_forward_bn(const lfs_flow_desc* desc, const float* params, int32_t B,
@@ -189,11 +220,7 @@ extern "C" int32_t lfs_flow_forward_bn(const lfs_flow_desc* desc, const float* p
   lfs::FlowGeom g;
   const int32_t s = lfs::make_geom(desc, &g);
   if (s != LFS_OK) return s;
-  if (!g.bn) {
-    lfs_flow_desc plain = *desc;
-    plain.batch_norm = 0;
-    return lfs_flow_forward(&plain, params, B, z, phi, logq, logdet, saved_x, ws, ws_bytes, stream);
-  }
+  if (!g.bn) return lfs_flow_forward(desc, params, B, z, phi, logq, logdet, saved_x, ws, ws_bytes, stream);
   if (B <= 0 || !params || !z || !phi || !logq) return LFS_EINVAL;
   if (bn_mode != LFS_BN_BATCH && bn_mode != LFS_BN_RUNNING) return LFS_EINVAL;
   if (bn_mode == LFS_BN_RUNNING && !bn_stats) return LFS_EINVAL;
@@ -207,23 +234,21 @@ extern "C" int32_t lfs_flow_forward_bn(const lfs_flow_desc* desc, const float* p
 
 extern "C" int32_t lfs_flow_backward_bn(const lfs_flow_desc* desc, const float* params, int32_t B,
                                         const float* saved_x, const float* g_phi, double g_logq,
-                                        int32_t bn_mode, const float* bn_stats, float* g_params,
-                                        float* g_z, void* ws, size_t ws_bytes, void* stream) {
+                                        const double* g_logq_vec, int32_t bn_mode,
+                                        const float* bn_stats, float* g_params, float* g_z, void* ws,
+                                        size_t ws_bytes, void* stream) {
   lfs::FlowGeom g;
   const int32_t s = lfs::make_geom(desc, &g);
   if (s != LFS_OK) return s;
-  if (!g.bn) {
-    lfs_flow_desc plain = *desc;
-    plain.batch_norm = 0;
-    return lfs_flow_backward(&plain, params, B, saved_x, g_phi, g_logq, g_params, g_z, ws, ws_bytes,
-                             stream);
-  }
+  if (!g.bn)
+    return lfs::backward_plain(desc, g, params, B, saved_x, g_phi, g_logq, g_logq_vec, g_params, g_z,
+                               ws, ws_bytes, stream);
   if (B <= 0 || !params || !saved_x || !g_phi || !g_params) return LFS_EINVAL;
   if (bn_mode != LFS_BN_BATCH && bn_mode != LFS_BN_RUNNING) return LFS_EINVAL;
   if (bn_mode == LFS_BN_RUNNING && !bn_stats) return LFS_EINVAL;
   if (desc->algo == LFS_ALGO_FUSED) return LFS_EUNSUPPORTED;
   const size_t need = lfs::net_ws_bytes(g, B, 1);
   if (!ws || ws_bytes < need) return LFS_EWORKSPACE;
-  return lfs::net_backward_bn(g, params, B, saved_x, g_phi, g_logq, bn_mode, bn_stats, g_params, g_z,
-                              (char*)ws, (hipStream_t)stream);
+  return lfs::net_backward_bn(g, params, B, saved_x, g_phi, g_logq, g_logq_vec, bn_mode, bn_stats,
+                              g_params, g_z, (char*)ws, (hipStream_t)stream);
 }

@@ -305,11 +305,12 @@ int32_t fused_forward(const FlowGeom& g, const float* params, int B, const float
 }
 
 int32_t fused_backward(const FlowGeom& g, const float* params, int B, const float* saved,
-                       const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                       const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
+                       float* g_z, char* ws,
                        hipStream_t st) {
   if (fused::bwd_supported(g))
-    return fused::bwd_run(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
-  return fused::ring_bwd_run(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
+    return fused::bwd_run(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
+  return fused::ring_bwd_run(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
 }
 
 }  // namespace lfs

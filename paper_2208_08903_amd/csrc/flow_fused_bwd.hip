@@ -215,7 +215,8 @@ __device__ __forceinline__ u32x4 load8_e(const uint16_t* rp, int x0) {
 template <int DIM, int L, int C, bool BF16, int NT>
 __global__ void __launch_bounds__(NT) kf_backward(
     const u32x4* frags, const float* __restrict__ pl, int off_b1, int off_b2,
-    int off_b3, int off_W1, int off_W2, int off_W3, int fpar, int final_tanh, float g_ld, int B,
+    int off_b3, int off_W1, int off_W2, int off_W3, int fpar, int final_tanh, float g_ld,
+    const double* __restrict__ g_ld_vec, int B,
     const float* __restrict__ xin, const float* __restrict__ gy, float* __restrict__ gx,
     float* __restrict__ partial, const float* __restrict__ prev_partial, float* __restrict__ prev_out,
     int n_parts) {
@@ -302,6 +303,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
     // registers at once.
     asm volatile("" ::: "memory");
     const size_t sb = (size_t)b * V;
+    // cotangent of the log-det: one for all samples, or this sample's
+    const float gld = g_ld_vec ? (float)(-g_ld_vec[b]) : g_ld;
     // stage x and g_y; BF16: masked field channel-major for dW1
     if constexpr (PF) {
 #pragma unroll
@@ -395,7 +398,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
         const float s = final_tanh ? fast_tanh(o0) : o0;
         const float es = fast_exp(s);
         const float g = gys[n];
-        const float gs = g * xs[p] * es + g_ld;
+        const float gs = g * xs[p] * es + gld;
         const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
         db3s += go0;
         db3t += g;
@@ -850,7 +853,8 @@ size_t bwd_ws(const FlowGeom& g, int B) {
 
 template <int DIM, int L, int C, bool BF16>
 int32_t launch_backward(const FlowGeom& g, const float* params, int B, const float* saved,
-                        const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                        const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
+                        float* g_z, char* ws,
                         hipStream_t st) {
   using Cfg = BwdCfg<DIM, L, C, BF16>;
   const int grid = bwd_grid<DIM, L, C, BF16>(B);
@@ -881,7 +885,7 @@ int32_t launch_backward(const FlowGeom& g, const float* params, int B, const flo
     hipLaunchKernelGGL(kern, dim3(grid), dim3(Cfg::NT), Cfg::lds_bytes, st,
                        frags + (size_t)l * tab.total * 64, params + (size_t)l * g.P_layer,
                        (int)g.off_b1, (int)g.off_b2, (int)g.off_b3, (int)g.off_W1, (int)g.off_W2,
-                       (int)g.off_W3, g.frozen_parity(l), g.final_tanh, (float)(-g_logq), B,
+                       (int)g.off_W3, g.frozen_parity(l), g.final_tanh, (float)(-g_logq), g_logq_vec, B,
                        saved + (size_t)l * BV, gy, gx, partial[l & 1],
                        first ? nullptr : (const float*)partial[(l + 1) & 1],
                        first ? nullptr : g_params + (size_t)(l + 1) * g.P_layer, grid);
@@ -893,12 +897,12 @@ int32_t launch_backward(const FlowGeom& g, const float* params, int B, const flo
                      (const float*)partial[0], g_params);
   if (g_z)
     hipLaunchKernelGGL(kf_gz, dim3((unsigned)((BV + 255) / 256)), dim3(256), 0, st, (int64_t)BV,
-                       gy, saved, (float)g_logq, g_z);
+                       gy, saved, (float)g_logq, g_logq_vec, (int64_t)Cfg::V, g_z);
   return launch_status();
 }
 
 using BwdFn = int32_t (*)(const FlowGeom&, const float*, int, const float*, const float*, double,
-                          float*, float*, char*, hipStream_t);
+                          const double*, float*, float*, char*, hipStream_t);
 using BwdWsFn = size_t (*)(const FlowGeom&, int);
 
 struct BwdEntry {
@@ -938,11 +942,12 @@ size_t bwd_ws_bytes(const FlowGeom& g, int B) {
   return e ? e->ws(g, B) : 0;
 }
 int32_t bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
-                const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params, float* g_z,
+                char* ws,
                 hipStream_t st) {
   const BwdEntry* e = find_bwd(g);
   if (!e) return LFS_EUNSUPPORTED;
-  return e->fn(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
+  return e->fn(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
 }
 
 }  // namespace fused

@@ -150,7 +150,8 @@ __device__ __forceinline__ void bias_partial(f32x4 (&db)[NCT], float* red, float
 template <int L, int C, int NT>
 __global__ void __launch_bounds__(NT) kr_recompute(
     const u32x4* frags, const float* __restrict__ pl, int off_b1, int off_b2, int off_b3,
-    int fpar, int final_tanh, float g_ld, int B, const float* __restrict__ xin,
+    int fpar, int final_tanh, float g_ld, const double* __restrict__ g_ld_vec, int B,
+    const float* __restrict__ xin,
     const float* __restrict__ gy, float* __restrict__ gx, uint16_t* __restrict__ h1c,
     uint16_t* __restrict__ h2c, uint32_t* __restrict__ m1, uint32_t* __restrict__ m2,
     uint32_t* __restrict__ go, float* __restrict__ partial, int P,
@@ -192,6 +193,8 @@ __global__ void __launch_bounds__(NT) kr_recompute(
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     const size_t sb = (size_t)b * V;
+    // cotangent of the log-det: one for all samples, or this sample's
+    const float gld = g_ld_vec ? (float)(-g_ld_vec[b]) : g_ld;
     uint16_t* h1b = h1c + (size_t)b * C * V;
     uint16_t* h2b = h2c + (size_t)b * C * V;
     __syncthreads();  // the previous sample's readers are done
@@ -257,7 +260,7 @@ __global__ void __launch_bounds__(NT) kr_recompute(
               const float s = final_tanh ? fast_tanh(o0) : o0;
               const float es = fast_exp(s);
               const float g = gy[sb + n];
-              const float gs = g * xs[LX::idx(n)] * es + g_ld;
+              const float gs = g * xs[LX::idx(n)] * es + gld;
               const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
               db3s += go0;
               db3t += g;
@@ -659,7 +662,8 @@ bool set_lds(K kern, size_t bytes) {
 
 template <int L, int C>
 int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved,
-               const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+               const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params, float* g_z,
+               char* ws,
                hipStream_t st) {
   using Cfg = RbCfg<L, C>;
   const int grid = rb_grid<L, C>(B);
@@ -705,7 +709,8 @@ int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved
     const bool first = l == g.N - 1;
     float* partial = partials[l & 1];
     hipLaunchKernelGGL(ka, dim3(grid), dim3(Cfg::NT_A), Cfg::LDS_A, st, fl, pl, (int)g.off_b1,
-                       (int)g.off_b2, (int)g.off_b3, fpar, g.final_tanh, (float)(-g_logq), B, xl, gy,
+                       (int)g.off_b2, (int)g.off_b3, fpar, g.final_tanh, (float)(-g_logq), g_logq_vec, B, xl,
+                        gy,
                        gx, h1c, h2c, m1, m2, go, partial, P,
                        first ? nullptr : (const float*)partials[(l + 1) & 1],
                        first ? nullptr : g_params + (size_t)(l + 1) * g.P_layer);
@@ -723,14 +728,14 @@ int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved
                      st, grid, P, (const float*)partials[0], g_params);
   if (g_z)
     hipLaunchKernelGGL(kf_gz, dim3((unsigned)((BV + 255) / 256)), dim3(256), 0, st, (int64_t)BV,
-                       gy, saved, (float)g_logq, g_z);
+                       gy, saved, (float)g_logq, g_logq_vec, (int64_t)g.V, g_z);
   return launch_status();
 }
 
 struct RbEntry {
   int L, C;
-  int32_t (*fn)(const FlowGeom&, const float*, int, const float*, const float*, double, float*,
-                float*, char*, hipStream_t);
+  int32_t (*fn)(const FlowGeom&, const float*, int, const float*, const float*, double,
+                const double*, float*, float*, char*, hipStream_t);
   size_t (*ws)(const FlowGeom&, int);
 };
 
@@ -752,11 +757,12 @@ size_t ring_bwd_ws_bytes(const FlowGeom& g, int B) {
   return e ? e->ws(g, B) : 0;
 }
 int32_t ring_bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
-                     const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                     const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
+                     float* g_z, char* ws,
                      hipStream_t st) {
   const RbEntry* e = find_rb(g);
   if (!e) return LFS_EUNSUPPORTED;
-  return e->fn(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
+  return e->fn(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
 }
 
 }  // namespace fused

@@ -157,6 +157,7 @@ __global__ void __launch_bounds__(256) kg_couple_bwd(int L, int V, int B, int fp
                                                      const float* __restrict__ W3,
                                                      const float* __restrict__ b3,
                                                      const float* __restrict__ gy, float g_ld,
+                                                     const double* __restrict__ g_ld_vec,
                                                      float* __restrict__ g_o,
                                                      float* __restrict__ gx) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -173,7 +174,7 @@ __global__ void __launch_bounds__(256) kg_couple_bwd(int L, int V, int B, int fp
   conv3_at<DIM, C, BF16>(L, V, b, n, h2, W3, b3, o0, o1);
   const float s = final_tanh ? tanhf(o0) : o0;
   const float es = expf(s);
-  const float gs = g * x[idx] * es + g_ld;
+  const float gs = g * x[idx] * es + (g_ld_vec ? (float)(-g_ld_vec[b]) : g_ld);
   g_o[2 * idx] = final_tanh ? gs * (1.f - s * s) : gs;
   g_o[2 * idx + 1] = g;
   gx[idx] = g * es;
@@ -293,11 +294,14 @@ __global__ void __launch_bounds__(256) kg_reduce(int B, int P, const float* __re
   out[i] = (float)acc;
 }
 
-// g_z = g_x - g_logq z (d log r / dz = -z).
+// g_z = g_x - g_logq z (d log r / dz = -z); g_logq per sample if g_logq_vec is given.
 __global__ void kg_gz(int64_t n, const float* __restrict__ gx, const float* __restrict__ z,
-                      float g_logq, float* __restrict__ gz) {
+                      float g_logq, const double* __restrict__ g_logq_vec, int64_t V,
+                      float* __restrict__ gz) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) gz[i] = gx[i] - g_logq * z[i];
+  if (i >= n) return;
+  const float gl = g_logq_vec ? (float)g_logq_vec[i / V] : g_logq;
+  gz[i] = gx[i] - gl * z[i];
 }
 
 struct GenericWs {
@@ -368,7 +372,8 @@ int32_t forward_impl(const FlowGeom& g, const float* params, int B, const float*
 
 template <int DIM, int C, bool BF16>
 int32_t backward_impl(const FlowGeom& g, const float* params, int B, const float* saved,
-                      const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                      const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
+                      float* g_z, char* ws,
                       hipStream_t st) {
   constexpr int T = taps<DIM>();
   size_t tot[2];
@@ -390,7 +395,7 @@ int32_t backward_impl(const FlowGeom& g, const float* params, int B, const float
                        p + g.off_W2, p + g.off_b2, w.h2);
     hipLaunchKernelGGL((kg_couple_bwd<DIM, C, BF16>), grid1(BV), dim3(256), 0, st, L, V, B, fpar,
                        g.final_tanh, x, w.h2, p + g.off_W3, p + g.off_b3, gy, (float)(-g_logq),
-                       w.g_o, gx);
+                       g_logq_vec, w.g_o, gx);
     hipLaunchKernelGGL((kg_conv3T<DIM, C, BF16>), grid1(BV), dim3(256), 0, st, L, V, B, w.g_o,
                        p + g.off_W3, w.h2, w.g_a2);
     hipLaunchKernelGGL((kg_conv2T<DIM, C, BF16>), grid1(BV), dim3(256), 0, st, L, V, B, w.g_a2,
@@ -412,7 +417,7 @@ int32_t backward_impl(const FlowGeom& g, const float* params, int B, const float
   }
   if (g_z)
     hipLaunchKernelGGL(kg_gz, grid1(BV), dim3(256), 0, st, (int64_t)BV, gy, saved,
-                       (float)g_logq, g_z);
+                       (float)g_logq, g_logq_vec, (int64_t)V, g_z);
   return launch_status();
 }
 
@@ -429,16 +434,18 @@ int32_t fwd_c(const FlowGeom& g, const float* params, int B, const float* z, flo
 
 template <int DIM, bool BF16>
 int32_t bwd_c(const FlowGeom& g, const float* params, int B, const float* saved,
-              const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+              const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params, float* g_z,
+              char* ws,
               hipStream_t st) {
   switch (g.C) {
     case 8:
-      return backward_impl<DIM, 8, BF16>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
+      return backward_impl<DIM, 8, BF16>(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws,
+                                         st);
     case 16:
-      return backward_impl<DIM, 16, BF16>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws,
+      return backward_impl<DIM, 16, BF16>(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws,
                                           st);
     case 32:
-      return backward_impl<DIM, 32, BF16>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws,
+      return backward_impl<DIM, 32, BF16>(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws,
                                           st);
   }
   return LFS_EUNSUPPORTED;
@@ -462,13 +469,14 @@ int32_t generic_forward(const FlowGeom& g, const float* params, int B, const flo
 }
 
 int32_t generic_backward(const FlowGeom& g, const float* params, int B, const float* saved,
-                         const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                         const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
+                         float* g_z, char* ws,
                          hipStream_t st) {
   if (g.dim == 2)
-    return g.bf16() ? bwd_c<2, true>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st)
-                    : bwd_c<2, false>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
-  return g.bf16() ? bwd_c<3, true>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st)
-                  : bwd_c<3, false>(g, params, B, saved, g_phi, g_logq, g_params, g_z, ws, st);
+    return g.bf16() ? bwd_c<2, true>(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st)
+                    : bwd_c<2, false>(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
+  return g.bf16() ? bwd_c<3, true>(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st)
+                  : bwd_c<3, false>(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
 }
 
 }  // namespace lfs

@@ -137,6 +137,7 @@ __global__ void __launch_bounds__(256) kn_affine_bwd(int L, int V, int B, int fp
                                                      const float* __restrict__ x,
                                                      const float* __restrict__ o,
                                                      const float* __restrict__ gy, float g_ld,
+                                                     const double* __restrict__ g_ld_vec,
                                                      float* __restrict__ go,
                                                      float* __restrict__ gx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -151,7 +152,7 @@ __global__ void __launch_bounds__(256) kn_affine_bwd(int L, int V, int B, int fp
   }
   const float s = final_tanh ? tanhf(o[2 * i]) : o[2 * i];
   const float es = expf(s);
-  const float gs = g * x[i] * es + g_ld;
+  const float gs = g * x[i] * es + (g_ld_vec ? (float)(-g_ld_vec[i / V]) : g_ld);
   go[2 * i] = final_tanh ? gs * (1.f - s * s) : gs;
   go[2 * i + 1] = g;
   gx[i] = g * es;
@@ -229,11 +230,14 @@ __global__ void __launch_bounds__(256) kn_reduce(int G, int P, const double* __r
   out[p] = (float)acc;
 }
 
-// g_z = g_x - g_logq z (d log r / dz = -z).
+// g_z = g_x - g_logq z (d log r / dz = -z); g_logq per sample if g_logq_vec is given.
 __global__ void kn_gz(int64_t n, const float* __restrict__ gx, const float* __restrict__ z,
-                      float g_logq, float* __restrict__ gz) {
+                      float g_logq, const double* __restrict__ g_logq_vec, int64_t V,
+                      float* __restrict__ gz) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) gz[i] = gx[i] - g_logq * z[i];
+  if (i >= n) return;
+  const float gl = g_logq_vec ? (float)g_logq_vec[i / V] : g_logq;
+  gz[i] = gx[i] - gl * z[i];
 }
 
 // ---- batch norm ------------------------------------------------------------
@@ -514,7 +518,8 @@ int32_t forward_impl(const FlowGeom& g, const float* params, int B, const float*
 
 template <int DIM, bool BF16>
 int32_t backward_impl(const FlowGeom& g, const float* params, int B, const float* saved,
-                      const float* g_phi, double g_logq, int bn_mode, const float* stats,
+                      const float* g_phi, double g_logq, const double* g_logq_vec, int bn_mode,
+                      const float* stats,
                       float* g_params, float* g_z, char* ws, hipStream_t st) {
   size_t tot[2];
   NetWs w = carve(g, B, ws, tot);
@@ -535,7 +540,7 @@ int32_t backward_impl(const FlowGeom& g, const float* params, int B, const float
                    nullptr, 0.f};
     run_net<DIM, BF16>(g, p, B, x, fpar, w, bn, st);
     hipLaunchKernelGGL((kn_affine_bwd<DIM>), grid_for(BV), dim3(256), 0, st, g.L, g.V, B, fpar,
-                       g.final_tanh, x, w.o, gy, (float)(-g_logq), w.go, gx);
+                       g.final_tanh, x, w.o, gy, (float)(-g_logq), g_logq_vec, w.go, gx);
     // back through the convolutions, last to first; gcur is the gradient of
     // convolution i's output
     const float* gcur = w.go;
@@ -568,7 +573,8 @@ int32_t backward_impl(const FlowGeom& g, const float* params, int B, const float
     which ^= 1;
   }
   if (g_z)
-    hipLaunchKernelGGL(kn_gz, grid_for(BV), dim3(256), 0, st, BV, gy, saved, (float)g_logq, g_z);
+    hipLaunchKernelGGL(kn_gz, grid_for(BV), dim3(256), 0, st, BV, gy, saved, (float)g_logq, g_logq_vec,
+                       (int64_t)g.V, g_z);
   return launch_status();
 }
 
@@ -595,16 +601,20 @@ int32_t net_forward_bn(const FlowGeom& g, const float* params, int B, const floa
 }
 
 int32_t net_backward_bn(const FlowGeom& g, const float* params, int B, const float* saved,
-                        const float* g_phi, double g_logq, int bn_mode, const float* stats,
+                        const float* g_phi, double g_logq, const double* g_logq_vec, int bn_mode,
+                        const float* stats,
                         float* g_params, float* g_z, char* ws, hipStream_t st) {
   if (g.dim == 2)
-    return g.bf16() ? backward_impl<2, true>(g, params, B, saved, g_phi, g_logq, bn_mode, stats, g_params,
+    return g.bf16() ? backward_impl<2, true>(g, params, B, saved, g_phi, g_logq, g_logq_vec, bn_mode, stats,
+                  g_params,
                                              g_z, ws, st)
-                    : backward_impl<2, false>(g, params, B, saved, g_phi, g_logq, bn_mode, stats,
+                    : backward_impl<2, false>(g, params, B, saved, g_phi, g_logq, g_logq_vec, bn_mode, stats,
                                               g_params, g_z, ws, st);
-  return g.bf16() ? backward_impl<3, true>(g, params, B, saved, g_phi, g_logq, bn_mode, stats, g_params,
+  return g.bf16() ? backward_impl<3, true>(g, params, B, saved, g_phi, g_logq, g_logq_vec, bn_mode, stats,
+                g_params,
                                            g_z, ws, st)
-                  : backward_impl<3, false>(g, params, B, saved, g_phi, g_logq, bn_mode, stats, g_params,
+                  : backward_impl<3, false>(g, params, B, saved, g_phi, g_logq, g_logq_vec, bn_mode, stats,
+                                            g_params,
                                             g_z, ws, st);
 }
 
@@ -614,9 +624,11 @@ int32_t net_forward(const FlowGeom& g, const float* params, int B, const float* 
 }
 
 int32_t net_backward(const FlowGeom& g, const float* params, int B, const float* saved,
-                     const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                     const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
+                     float* g_z, char* ws,
                      hipStream_t st) {
-  return net_backward_bn(g, params, B, saved, g_phi, g_logq, LFS_BN_BATCH, nullptr, g_params, g_z, ws, st);
+  return net_backward_bn(g, params, B, saved, g_phi, g_logq, g_logq_vec, LFS_BN_BATCH, nullptr, g_params,
+                         g_z, ws, st);
 }
 
 }  // namespace lfs

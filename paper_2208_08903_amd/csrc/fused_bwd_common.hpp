@@ -69,10 +69,14 @@ __device__ __forceinline__ void grid_reduce(const float* __restrict__ partial, f
   }
 }
 
+// g_z = g_x - g_logq z (d log r / dz = -z); g_logq per sample if g_logq_vec is given.
 __global__ void kf_gz(int64_t n, const float* __restrict__ gx, const float* __restrict__ z,
-                      float g_logq, float* __restrict__ gz) {
+                      float g_logq, const double* __restrict__ g_logq_vec, int64_t V,
+                      float* __restrict__ gz) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) gz[i] = gx[i] - g_logq * z[i];
+  if (i >= n) return;
+  const float gl = g_logq_vec ? (float)g_logq_vec[i / V] : g_logq;
+  gz[i] = gx[i] - gl * z[i];
 }
 
 }  // namespace

@@ -45,7 +45,8 @@ size_t generic_ws_bytes(const FlowGeom& g, int B, int for_backward);
 int32_t generic_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
                         double* logq, double* logdet, float* saved, char* ws, hipStream_t st);
 int32_t generic_backward(const FlowGeom& g, const float* params, int B, const float* saved,
-                         const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                         const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
+                         float* g_z, char* ws,
                          hipStream_t st);
 
 // General-network kernels: any hidden_sizes / odd kernel, activations in HBM.
@@ -53,7 +54,8 @@ size_t net_ws_bytes(const FlowGeom& g, int B, int for_backward);
 int32_t net_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
                     double* logq, double* logdet, float* saved, char* ws, hipStream_t st);
 int32_t net_backward(const FlowGeom& g, const float* params, int B, const float* saved,
-                     const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                     const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
+                     float* g_z, char* ws,
                      hipStream_t st);
 // Batch-norm variants (g.bn): bn_mode lfs_bn_mode; stats per the statistics
 // layout (running statistics, updated in batch mode if not null).
@@ -61,7 +63,8 @@ int32_t net_forward_bn(const FlowGeom& g, const float* params, int B, const floa
                        double* logq, double* logdet, float* saved, int bn_mode, float* stats,
                        float momentum, char* ws, hipStream_t st);
 int32_t net_backward_bn(const FlowGeom& g, const float* params, int B, const float* saved,
-                        const float* g_phi, double g_logq, int bn_mode, const float* stats,
+                        const float* g_phi, double g_logq, const double* g_logq_vec, int bn_mode,
+                        const float* stats,
                         float* g_params, float* g_z, char* ws, hipStream_t st);
 
 // Fused kernels: LDS-resident per-sample lattices, matrix-core convolutions.
@@ -70,7 +73,8 @@ size_t fused_ws_bytes(const FlowGeom& g, int B, int for_backward);
 int32_t fused_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
                       double* logq, double* logdet, float* saved, char* ws, hipStream_t st);
 int32_t fused_backward(const FlowGeom& g, const float* params, int B, const float* saved,
-                       const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                       const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
+                       float* g_z, char* ws,
                        hipStream_t st);
 
 namespace fused {
@@ -84,14 +88,16 @@ int32_t ring_forward(const FlowGeom& g, const float* params, int B, const float*
 bool bwd_supported(const FlowGeom& g);
 size_t bwd_ws_bytes(const FlowGeom& g, int B);
 int32_t bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
-                const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params, float* g_z,
+                char* ws,
                 hipStream_t st);
 // Fused backward streaming planes (3D lattices too large to keep resident;
 // three launches per layer), implemented next to its kernels.
 bool ring_bwd_supported(const FlowGeom& g);
 size_t ring_bwd_ws_bytes(const FlowGeom& g, int B);
 int32_t ring_bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
-                     const float* g_phi, double g_logq, float* g_params, float* g_z, char* ws,
+                     const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
+                     float* g_z, char* ws,
                      hipStream_t st);
 }  // namespace fused
 

@@ -65,8 +65,10 @@ _SIGS = {
     "lfs_bn_stats_count": (c_sz, [ctypes.POINTER(FlowDesc)]),
     "lfs_flow_forward_bn": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
                                     c_vp, c_i32, c_vp, c_f64, c_vp, c_sz, c_vp]),
-    "lfs_flow_backward_bn": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_f64, c_i32,
-                                     c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "lfs_flow_backward_bn": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_f64, c_vp,
+                                     c_i32, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "lfs_flow_backward_vec": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
+                                      c_vp, c_vp, c_sz, c_vp]),
     "lfs_action": (c_i32, [c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_f64,
                            c_vp]),
     "lfs_log_weights": (c_i32, [c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -210,13 +212,34 @@ def flow_forward_bn(desc, params, z, phi, logq, bn_mode, bn_stats=None, momentum
                                       _p(ws, torch.uint8, "ws"), nbytes, _stream()))
 
 
-def flow_backward_bn(desc, params, saved_x, g_phi, g_logq: float, g_params, bn_mode, bn_stats=None,
+def flow_backward_vec(desc, params, saved_x, g_phi, g_logq, g_params, g_z=None, ws=None):
+    """flow_backward with a per-sample cotangent of log q: g_logq is a [B] FP64 device tensor."""
+    B = g_phi.shape[0]
+    if g_logq.numel() != B:
+        raise LfsError("g_logq needs one entry per sample")
+    nbytes = ws.numel() if ws is not None else 0
+    _check(load().lfs_flow_backward_vec(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
+                                        _p(saved_x, torch.float32, "saved_x"),
+                                        _p(g_phi, torch.float32, "g_phi"),
+                                        _p(g_logq, torch.float64, "g_logq"),
+                                        _p(g_params, torch.float32, "g_params"),
+                                        _p(g_z, torch.float32, "g_z"), _p(ws, torch.uint8, "ws"),
+                                        nbytes, _stream()))
+
+
+def flow_backward_bn(desc, params, saved_x, g_phi, g_logq, g_params, bn_mode, bn_stats=None,
                      g_z=None, ws=None):
+    """g_logq: a float (the same cotangent for every sample) or a [B] FP64 device tensor."""
     B = g_phi.shape[0]
     nbytes = ws.numel() if ws is not None else 0
+    vec = g_logq if isinstance(g_logq, torch.Tensor) else None
+    if vec is not None and vec.numel() != B:
+        raise LfsError("g_logq needs one entry per sample")
+    scalar = 0.0 if vec is not None else float(g_logq)
     _check(load().lfs_flow_backward_bn(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
                                        _p(saved_x, torch.float32, "saved_x"),
-                                       _p(g_phi, torch.float32, "g_phi"), float(g_logq), int(bn_mode),
+                                       _p(g_phi, torch.float32, "g_phi"), scalar,
+                                       _p(vec, torch.float64, "g_logq"), int(bn_mode),
                                        _p(bn_stats, torch.float32, "bn_stats"),
                                        _p(g_params, torch.float32, "g_params"),
                                        _p(g_z, torch.float32, "g_z"), _p(ws, torch.uint8, "ws"),

@@ -78,9 +78,11 @@ def test_batch_norm_layout_and_validation(dim, N, K, hs):
     assert fwd(ctypes.byref(d), 1, 4, 1, 1, 1, None, None, 0, None, float("nan"), 1, 1 << 40, None) == -1
     assert fwd(ctypes.byref(d), 1, 4, 1, 1, 1, None, None, 0, None, 0.1, 1, need_f - 1, None) == -3
     bwd = lib.lfs_flow_backward_bn
-    assert bwd(ctypes.byref(d), 1, 4, 1, 1, 0.25, 1, None, 1, None, 1, 1 << 40, None) == -1    # stats
-    assert bwd(ctypes.byref(d), 1, 4, 1, 1, 0.25, 3, 1, 1, None, 1, 1 << 40, None) == -1       # mode
-    assert bwd(ctypes.byref(d), 1, 4, 1, 1, 0.25, 0, None, 1, None, 1, need_b - 1, None) == -3
+    assert bwd(ctypes.byref(d), 1, 4, 1, 1, 0.25, None, 1, None, 1, None, 1, 1 << 40, None) == -1  # stats
+    assert bwd(ctypes.byref(d), 1, 4, 1, 1, 0.25, None, 3, 1, 1, None, 1, 1 << 40, None) == -1     # mode
+    assert bwd(ctypes.byref(d), 1, 4, 1, 1, 0.25, 1, 0, None, 1, None, 1, need_b - 1, None) == -3
+    # the per-sample entry point takes no batch-norm flow either
+    assert lib.lfs_flow_backward_vec(ctypes.byref(d), 1, 4, 1, 1, 1, 1, None, 1, 1 << 40, None) == -1
     fused = lfs.make_desc(dim, 8, N, 0, kernel=K, hidden_sizes=hs, batch_norm=True, algo=lfs.ALGO_FUSED)
     assert lib.lfs_workspace_bytes(ctypes.byref(fused), 4, 0, ctypes.byref(out)) == -2
     assert fwd(ctypes.byref(fused), 1, 4, 1, 1, 1, None, None, 0, None, 0.1, 1, 1 << 40, None) == -2
@@ -126,6 +128,11 @@ def test_null_and_shape_arguments_rejected_before_any_launch():
                                 None) == -1
     assert lib.lfs_flow_backward(ctypes.byref(d), None, 4, None, None, 0.25, None, None, None, 0,
                                  None) == -1
+    assert lib.lfs_flow_backward_vec(ctypes.byref(d), 1, 4, 1, 1, None, 1, None, 1, 1 << 40,
+                                     None) == -1                              # g_logq NULL
+    need = lfs.workspace_bytes(d, 4, True)
+    assert lib.lfs_flow_backward_vec(ctypes.byref(d), 1, 4, 1, 1, 1, 1, None, 1, need - 1,
+                                     None) == -3
     assert lib.lfs_prior_normal(1, 0, 4, 6, None, None, None) == -1          # V % 4
     assert lib.lfs_action(4, 8, 4, None, None, None, 0, 1, None, None, 1.0, None) == -1
     assert lib.lfs_action(2, 256, 4, 1, 1, 1, 0, 1, 1, None, 1.0, None) == -2  # V too large
