@@ -40,6 +40,15 @@ KERNEL_SOURCES = ["paper_2208_08903_amd/csrc/flow_fused_bwd.hip",
                   "paper_2208_08903_amd/csrc/lfs_common.hpp",
                   "paper_2208_08903_amd/csrc/fused_bwd_common.hpp"]
 TRAFFIC_FILE = "profiles/kf_backward_phi4-2d-L32-train_traffic.txt"
+# VALU instructions of the prior draw at the 4096 x 4096-site sampling shape
+# (rocprofv3 SQ_INSTS_VALU); the prior is bound by its Philox and Box-Muller
+# arithmetic, not by HBM
+PRIOR_SOURCES = ["paper_2208_08903_amd/csrc/prior.hip", "paper_2208_08903_amd/csrc/lfs_common.hpp"]
+PRIOR_VALU_FILE = "profiles/k_prior_phi4-3d-L16-sample_valu.txt"
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per SIMD every 4 cycles
+# (16 lanes per SIMD); reduced-rate instructions (64-bit integer multiply-add, transcendentals)
+# take longer, so a fraction of this peak is a lower bound on the VALU's busy fraction
+VALU_PEAK_G_WAVE_INSTR = 256 * 4 * 2.4 / 4
 
 
 def _progress(msg):
@@ -47,19 +56,19 @@ def _progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_sha():
+def kernel_source_sha(sources=None):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per backward launch from the committed rocprofv3 --pmc summary, if the
-    kernel sources are unchanged since the counters were taken; else None."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
+def _recorded(path, key, sources=None):
+    """A figure from a committed rocprofv3 summary, if the kernel sources are unchanged
+    since the counters were taken; else None."""
+    path = os.path.join(ROOT, path)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -67,12 +76,22 @@ def recorded_traffic():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha256_16") != kernel_source_sha():
+    if kv.get("source_sha256_16") != kernel_source_sha(sources):
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def recorded_traffic():
+    """HBM bytes per backward launch (rocprofv3 FETCH_SIZE / WRITE_SIZE summary)."""
+    return _recorded(TRAFFIC_FILE, "traffic_bytes_per_launch")
+
+
+def recorded_prior_valu():
+    """VALU wave instructions per prior launch at the sampling shape (SQ_INSTS_VALU summary)."""
+    return _recorded(PRIOR_VALU_FILE, "valu_wave_instructions_per_launch", PRIOR_SOURCES)
 
 
 def algorithmic_flops_per_sample_layer(dim, L, C):
@@ -215,6 +234,13 @@ def hbm_kernels(reps=20):
         us = 1e3 * s.elapsed_time(e) / reps
         gbs = nbytes / us / 1e3
         out[name] = {"bytes": nbytes, "us": round(us, 2), "GB_s": round(gbs, 1), "frac_of_8TB_s": round(gbs / 8000, 3)}
+    valu = recorded_prior_valu()
+    if valu:
+        g = valu / out["prior_normal"]["us"] / 1e3
+        out["prior_normal"]["alu"] = {"bound": "alu", "achieved": round(g, 1), "peak": VALU_PEAK_G_WAVE_INSTR,
+                                      "unit": "G VALU wave-instructions/s",
+                                      "frac": round(g / VALU_PEAK_G_WAVE_INSTR, 3),
+                                      "valu_wave_instructions_per_launch": valu}
     return out
 
 
