@@ -368,14 +368,16 @@ def trained_example(steps=20000):
     return out
 
 
-def serving(seconds=5.0):
-    """Poisson(200/s) sampling requests for `seconds` through the continuous-batching server."""
+def serving(seconds=5.0, precision=None):
+    """Poisson(200/s) sampling requests for `seconds` through the continuous-batching server
+    (BF16 convolutions unless `precision` says otherwise)."""
     import seeded_inputs as si
     from paper_2208_08903_amd import lfs
     from paper_2208_08903_amd.serve import DEFAULT_ARCH, Server, run_workload
     params = {d: si.flow_params(d, n, c, seed=2021 + d) for d, (n, c) in DEFAULT_ARCH.items()}
     reqs = si.serving_requests(seed=2208, rate=200.0, duration=seconds)
-    srv = Server(params, precision=lfs.LFS_BF16_CONV, hbm_budget=512 << 20)
+    prec = lfs.LFS_BF16_CONV if precision is None else precision
+    srv = Server(params, precision=prec, hbm_budget=512 << 20)
     warm = si.serving_requests(seed=1, rate=200.0, duration=0.3)
     run_workload(srv, warm)
     srv.peak_used = 0
@@ -416,6 +418,68 @@ def cpu_baseline(w, target_s=15.0):
                       f"({tb:.1f} s, FP64 NumPy, 1 thread), scaled linearly to the full batch"}
 
 
+def host_description():
+    """CPU model, logical CPUs the process may use, and numpy's BLAS."""
+    import numpy as np
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        blas = np.show_config(mode="dicts")["Build Dependencies"]["blas"]["name"]
+    except Exception:
+        blas = "unknown"
+    return {"cpu_model": model, "cpus_available": len(os.sched_getaffinity(0)), "numpy_blas": blas}
+
+
+def oracle_timings():
+    """The FP64 oracle, one thread, on the other workloads: the 2D L=8 example batch (forward,
+    action, log-weights), a 2000-proposal MH chain, one HMC trajectory for 512 3D L=8 chains,
+    and the 3D L=8 training step on a sample of its batch (scaled linearly)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import seeded_inputs as si
+    from oracle import action as oa
+    from oracle import flow as of
+    from oracle import hmc as oh
+    from oracle import mh as om
+    out = {"host": host_description(), "threads": 1}
+    with threadpool_limits(1):
+        fs = of.FlowShape(2, 8, 16, 8)
+        p = si.flow_params(2, 16, 8).astype(np.float64)
+        z = si.normal_fields(3, 64, 64)
+        t = time.perf_counter()
+        f = of.flow_forward(p, z, fs)
+        S = oa.action(f["phi"], -4.0, 8.0, 2)
+        of.log_weights(S, f["logq"])
+        out["2d_L8_batch64_forward_action_ms"] = round(1e3 * (time.perf_counter() - t), 2)
+        lw, lu = si.logw_stream(4, 2000), si.log_uniforms(5, 2000)
+        t = time.perf_counter()
+        om.mh_chain(lw, lu)
+        out["mh_chain_2000_ms"] = round(1e3 * (time.perf_counter() - t), 2)
+        # the same start as the GPU figure (hmc_rate)
+        phi = 0.5 * si.normal_fields(3, 512, 512).astype(np.float64).reshape(512, 8, 8, 8)
+        pi = si.momenta(4, 512, 512)
+        t = time.perf_counter()
+        oh.hmc_step(phi, pi, si.log_uniforms(5, 512), -4.0, 5.0, 3, 10, 0.1)
+        dt = time.perf_counter() - t
+        out["hmc_3d_L8_512_chains_trajectories_per_s"] = round(512 / dt, 1)
+        fs3 = of.FlowShape(3, 8, 12, 16)
+        p3 = si.flow_params(3, 12, 16).astype(np.float64)
+        b = 4
+        z3 = si.normal_fields(9, b, 512)
+        t = time.perf_counter()
+        of.loss_gradient(p3, z3, fs3, -4.0, 5.0)
+        dt = time.perf_counter() - t
+        out["3d_L8_train_steps_per_s"] = round(b / (dt * 512), 5)
+        out["3d_L8_train_sample"] = f"loss gradient on {b} of the 512 samples ({dt:.1f} s), scaled linearly"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,6 +489,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip FP32/sampling/HMC side figures")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default=WORKLOAD["workload"],
                     help="the training step to time (side figures run with the default only)")
+    ap.add_argument("--serving-seconds", type=float, default=5.0,
+                    help="length of the Poisson arrival window of the serving figures")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the timed region, one device-to-device copy of this many MiB "
                          "(the known-size kernel that scales the HBM byte counters)")
@@ -514,8 +580,10 @@ def main():
         out["general_networks_2d_L8"] = general_networks()
         out["trained_2d_L8_example"] = trained_example()
         _progress("trained example and chain quality done")
-        out["serving"] = serving()
-        _progress("serving done")
+        out["serving"] = serving(args.serving_seconds)
+        _progress("serving (BF16) done")
+        out["serving_fp32"] = serving(args.serving_seconds, lfs.LFS_PLAIN_FP32)
+        _progress("serving (FP32) done")
     if args.copy_calibration_mb > 0:
         nb = args.copy_calibration_mb * 2 ** 20
         src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
@@ -525,6 +593,9 @@ def main():
         out["copy_calibration_bytes"] = nb
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
+        _progress("oracle baseline done")
+        if headline and not args.no_extras:
+            out["oracle_timings"] = oracle_timings()
     print(json.dumps(out), flush=True)
 
 
