@@ -14,6 +14,8 @@
 // deviations), and h = leaky(gamma (a - mean) r + beta), r = 1/sqrt(var + eps),
 // is written next to it.  The backward turns g_y = g_h leaky'(y) into g_a with
 // the per-channel sums of g_y xhat and g_y.
+#include <type_traits>
+
 #include "lfs_common.hpp"
 #include "lfs_internal.hpp"
 
@@ -22,59 +24,126 @@ namespace {
 
 inline dim3 grid_for(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
+constexpr int ipow(int k, int d) { return d == 0 ? 1 : k * ipow(k, d - 1); }
+
 constexpr int kWgChunk = 4096;  // (sample, site) terms per weight-gradient workgroup
+// Lanes that share one convolution output: lane s of a group takes the (tap,
+// channel) pairs q = t cin + ci with q = s mod kSplit, and the group's partial
+// sums are combined by a fixed xor-shuffle tree (deterministic).
+constexpr int kSplit = 8;
+
+__device__ __forceinline__ float split_sum(float v) {
+#pragma unroll
+  for (int o = kSplit / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kSplit);
+  return v;
+}
+
+// First channel c of the pairs (t, c), c = c0, c0 + kSplit, ..., that lane s takes.
+__device__ __forceinline__ int split_first(int s, int t, int nc) { return (s - t * nc) & (kSplit - 1); }
 constexpr double kBnEps = 1e-5;
 constexpr int kMaxWidth = 64;   // hidden_sizes entries are at most 64
 
-// Site n + sign * delta_t, delta_t the offsets of tap t of an odd kernel K.
+// Site arithmetic of the periodic L^DIM lattice (row-major, axis 0 slowest):
+// coordinates by shift and mask when L is a power of two (lg = log2 L), by
+// division otherwise, and (c + d) mod L for kernel offsets |d| <= 3 by two
+// conditional corrections each way (L >= 2).
 template <int DIM>
-__device__ __forceinline__ int nbr_k(int n, int t, int L, int K, int sign) {
-  const int r = K >> 1;
-  int c[DIM], d[DIM];
+struct SiteMath {
+  int L, lg;
+  __device__ __forceinline__ void coords(int n, int (&c)[DIM]) const {
 #pragma unroll
-  for (int mu = DIM - 1; mu >= 0; --mu) {
-    c[mu] = n % L;
-    n /= L;
-    d[mu] = t % K - r;
-    t /= K;
+    for (int mu = DIM - 1; mu >= 0; --mu) {
+      if (lg >= 0) {
+        c[mu] = n & (L - 1);
+        n >>= lg;
+      } else {
+        c[mu] = n % L;
+        n /= L;
+      }
+    }
   }
-  int out = 0;
+  __device__ __forceinline__ int wrap(int v) const {
+    v = v < 0 ? v + L : v;
+    v = v < 0 ? v + L : v;
+    v = v >= L ? v - L : v;
+    return v >= L ? v - L : v;
+  }
+  // sample and site of the (sample, site) term bn
+  __device__ __forceinline__ void split(int64_t bn, int V, int& b, int& n) const {
+    if (lg >= 0) {
+      b = (int)(bn >> (lg * DIM));
+      n = (int)(bn & (V - 1));
+    } else {
+      b = (int)(bn / V);
+      n = (int)(bn % V);
+    }
+  }
+};
+
+// f(t, m) for every tap t of an odd kernel K, m = the site at coordinates
+// c + sign * delta_t; taps row-major over {-K/2..K/2}^DIM, axis 0 slowest.  K is
+// a compile-time constant so that a row of taps unrolls and its loads overlap.
+template <int DIM, int K, typename F>
+__device__ __forceinline__ void for_taps(const SiteMath<DIM>& sm, const int (&c)[DIM], int sign, F&& f) {
+  constexpr int r = K >> 1;
+  int t = 0;
+  if constexpr (DIM == 2) {
+    for (int d0 = -r; d0 <= r; ++d0) {
+      const int row = sm.wrap(c[0] + sign * d0) * sm.L;
 #pragma unroll
-  for (int mu = 0; mu < DIM; ++mu) {
-    int v = (c[mu] + sign * d[mu]) % L;
-    if (v < 0) v += L;
-    out = out * L + v;
+      for (int d1 = -r; d1 <= r; ++d1, ++t) f(t, row + sm.wrap(c[1] + sign * d1));
+    }
+  } else {
+    for (int d0 = -r; d0 <= r; ++d0) {
+      const int pl = sm.wrap(c[0] + sign * d0) * sm.L;
+      for (int d1 = -r; d1 <= r; ++d1) {
+        const int row = (pl + sm.wrap(c[1] + sign * d1)) * sm.L;
+#pragma unroll
+        for (int d2 = -r; d2 <= r; ++d2, ++t) f(t, row + sm.wrap(c[2] + sign * d2));
+      }
+    }
   }
-  return out;
 }
 
-// out[b][n][co] = act(bias[co] + sum_t sum_ci W[co][ci][t] in[b][n + delta_t][ci]).
-// first: the input is the layer's field with the active sites zeroed (cin = 1).
-template <int DIM, bool BF16>
-__global__ void __launch_bounds__(256) kn_conv(int L, int V, int B, int K, int T, int cin, int cout,
+// out[b][n][co] = act(bias[co] + sum_t sum_ci W[co][ci][t] in[b][n + delta_t][ci]),
+// kSplit lanes per output.  first: the input is the layer's field with the
+// active sites zeroed (cin = 1).
+template <int DIM, int K, bool BF16>
+__global__ void __launch_bounds__(256) kn_conv(int L, int lg, int V, int B, int cin, int cout,
                                                int first, int fpar, int act,
                                                const float* __restrict__ in,
                                                const float* __restrict__ W,
                                                const float* __restrict__ bias,
                                                float* __restrict__ out) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)B * V * cout) return;
+  constexpr int T = ipow(K, DIM);
+  const int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // groups of kSplit lanes never straddle the end (the grid is a multiple of kSplit)
+  if (gidx >= (int64_t)B * V * cout * kSplit) return;
+  const int s = (int)(gidx & (kSplit - 1));
+  const int64_t idx = gidx / kSplit;
   const int co = (int)(idx % cout);
   const int64_t bn = idx / cout;
-  const int b = (int)(bn / V), n = (int)(bn % V);
+  const SiteMath<DIM> sm{L, lg};
+  int b, n, c[DIM];
+  sm.split(bn, V, b, n);
+  sm.coords(n, c);
   const float* w = W + (size_t)co * cin * T;
-  float acc = bias[co];
-  for (int t = 0; t < T; ++t) {
-    const int m = nbr_k<DIM>(n, t, L, K, 1);
+  const float* ib = in + (size_t)b * V * (first ? 1 : cin);
+  float acc = 0.f;
+  for_taps<DIM, K>(sm, c, 1, [&](int t, int m) {
     if (first) {
-      const float v = site_parity<DIM>(m, L) == fpar ? in[(size_t)b * V + m] : 0.f;
-      acc += opnd<BF16>(w[t]) * opnd<BF16>(v);
+      if (((t - s) & (kSplit - 1)) == 0) {
+        const float v = site_parity<DIM>(m, L) == fpar ? ib[m] : 0.f;
+        acc += opnd<BF16>(w[t]) * opnd<BF16>(v);
+      }
     } else {
-      const float* h = in + ((size_t)b * V + m) * cin;
-      for (int ci = 0; ci < cin; ++ci) acc += opnd<BF16>(w[(size_t)ci * T + t]) * opnd<BF16>(h[ci]);
+      const float* h = ib + (size_t)m * cin;
+      for (int ci = split_first(s, t, cin); ci < cin; ci += kSplit)
+        acc += opnd<BF16>(w[(size_t)ci * T + t]) * opnd<BF16>(h[ci]);
     }
-  }
-  out[idx] = act ? leaky(acc) : acc;
+  });
+  acc = split_sum(acc) + bias[co];
+  if (s == 0) out[idx] = act ? leaky(acc) : acc;
 }
 
 // Affine update of the active sites from o = (o_0, o_1) and per-sample log-det
@@ -160,24 +229,34 @@ __global__ void __launch_bounds__(256) kn_affine_bwd(int L, int V, int B, int fp
 
 // Data gradient of a convolution: gin[b][m][ci] = sum_t sum_co W[co][ci][t]
 // g[b][m - delta_t][co], times LeakyReLU' of the input h (from its sign), or,
-// for the first convolution, added to gx at the frozen sites.
-template <int DIM, bool BF16>
-__global__ void __launch_bounds__(256) kn_conv_t(int L, int V, int B, int K, int T, int cin, int cout,
+// for the first convolution, added to gx at the frozen sites; kSplit lanes per
+// output.
+template <int DIM, int K, bool BF16>
+__global__ void __launch_bounds__(256) kn_conv_t(int L, int lg, int V, int B, int cin, int cout,
                                                  int first, int fpar, const float* __restrict__ g,
                                                  const float* __restrict__ W,
                                                  const float* __restrict__ h,
                                                  float* __restrict__ gin) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)B * V * cin) return;
+  constexpr int T = ipow(K, DIM);
+  const int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gidx >= (int64_t)B * V * cin * kSplit) return;   // whole groups of kSplit lanes
+  const int s = (int)(gidx & (kSplit - 1));
+  const int64_t idx = gidx / kSplit;
   const int ci = (int)(idx % cin);
   const int64_t bm = idx / cin;
-  const int b = (int)(bm / V), m = (int)(bm % V);
+  const SiteMath<DIM> sm{L, lg};
+  int b, m, c[DIM];
+  sm.split(bm, V, b, m);
+  sm.coords(m, c);
+  const float* gb = g + (size_t)b * V * cout;
   float acc = 0.f;
-  for (int t = 0; t < T; ++t) {
-    const float* gr = g + ((size_t)b * V + nbr_k<DIM>(m, t, L, K, -1)) * cout;
-    for (int co = 0; co < cout; ++co)
+  for_taps<DIM, K>(sm, c, -1, [&](int t, int nb) {
+    const float* gr = gb + (size_t)nb * cout;
+    for (int co = split_first(s, t, cout); co < cout; co += kSplit)
       acc += opnd<BF16>(W[((size_t)co * cin + ci) * T + t]) * opnd<BF16>(gr[co]);
-  }
+  });
+  acc = split_sum(acc);
+  if (s != 0) return;
   if (first) {
     if (site_parity<DIM>(m, L) == fpar) gin[bm] += acc;
   } else {
@@ -188,12 +267,14 @@ __global__ void __launch_bounds__(256) kn_conv_t(int L, int V, int B, int K, int
 // Partial weight and bias gradients of one convolution over the (sample, site)
 // terms [chunk * kWgChunk, +kWgChunk): parameter p < cout cin T is W[co][ci][t]
 // (sum of g[.][n][co] u[.][n + delta_t][ci]), the rest b[co] (sum of g).  One
-// workgroup per (parameter, chunk); fixed-order sums.
+// workgroup per (parameter, chunk); fixed-order sums.  With a single chunk the
+// sum is the gradient and goes straight to `direct`.
 template <int DIM, bool BF16>
-__global__ void __launch_bounds__(256) kn_wgrad(int L, int V, int B, int K, int T, int cin, int cout,
+__global__ void __launch_bounds__(256) kn_wgrad(int L, int lg, int V, int B, int K, int T, int cin, int cout,
                                                 int first, int fpar, const float* __restrict__ g,
                                                 const float* __restrict__ u,
-                                                double* __restrict__ partial, int P) {
+                                                double* __restrict__ partial, int P,
+                                                float* __restrict__ direct) {
   __shared__ double sh[16];
   const int p = blockIdx.x, chunk = blockIdx.y;
   const int64_t BV = (int64_t)B * V;
@@ -201,23 +282,54 @@ __global__ void __launch_bounds__(256) kn_wgrad(int L, int V, int B, int K, int 
   const int nW = cout * cin * T;
   double acc = 0.0;
   if (p < nW) {
-    const int co = p / (cin * T), ci = (p / T) % cin, t = p % T;
-    for (int64_t bn = t0 + threadIdx.x; bn < t1; bn += blockDim.x) {
-      const int b = (int)(bn / V), n = (int)(bn % V);
-      const int m = nbr_k<DIM>(n, t, L, K, 1);
+    const int co = p / (cin * T), ci = (p / T) % cin;
+    // this parameter's tap offsets
+    const SiteMath<DIM> sm{L, lg};
+    int d[DIM];
+    {
+      int t = p % T;
+#pragma unroll
+      for (int mu = DIM - 1; mu >= 0; --mu) {
+        d[mu] = t % K - (K >> 1);
+        t /= K;
+      }
+    }
+    // four terms' loads in flight at a time, summed in term order
+    auto term = [&](int64_t bn) {
+      int b, n, c[DIM];
+      sm.split(bn, V, b, n);
+      sm.coords(n, c);
+      int m = 0;
+#pragma unroll
+      for (int mu = 0; mu < DIM; ++mu) m = m * L + sm.wrap(c[mu] + d[mu]);
       float uv;
       if (first)
         uv = site_parity<DIM>(m, L) == fpar ? u[(size_t)b * V + m] : 0.f;
       else
         uv = u[((size_t)b * V + m) * cin + ci];
-      acc += (double)(opnd<BF16>(g[bn * cout + co]) * opnd<BF16>(uv));
+      return opnd<BF16>(g[bn * cout + co]) * opnd<BF16>(uv);
+    };
+    const int64_t step = blockDim.x;
+    int64_t bn = t0 + threadIdx.x;
+    for (; bn + 3 * step < t1; bn += 4 * step) {
+      const float q0 = term(bn), q1 = term(bn + step), q2 = term(bn + 2 * step), q3 = term(bn + 3 * step);
+      acc += (double)q0;
+      acc += (double)q1;
+      acc += (double)q2;
+      acc += (double)q3;
     }
+    for (; bn < t1; bn += step) acc += (double)term(bn);
   } else {
     const int co = p - nW;
     for (int64_t bn = t0 + threadIdx.x; bn < t1; bn += blockDim.x) acc += (double)g[bn * cout + co];
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[(size_t)chunk * P + p] = acc;
+  if (threadIdx.x == 0) {
+    if (direct)
+      direct[p] = (float)acc;
+    else
+      partial[(size_t)chunk * P + p] = acc;
+  }
 }
 
 // out[p] = sum over chunks of partial[chunk][p], in chunk order.
@@ -363,6 +475,20 @@ __global__ void __launch_bounds__(256) kn_bn_bwd(int64_t BV, int c, int batch, c
 
 // ---------------------------------------------------------------------------
 
+// log2 L for a power of two, else -1 (the kernels then divide)
+int log2_or_neg(int L) { return (L & (L - 1)) == 0 ? __builtin_ctz((unsigned)L) : -1; }
+
+// f(std::integral_constant<int, K>) for the odd kernel sizes 1..7 (validated by make_geom)
+template <typename F>
+void with_kernel_size(int K, F&& f) {
+  switch (K) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    default: f(std::integral_constant<int, 7>{}); break;
+  }
+}
+
 struct NetWs {
   double *logdet, *logr, *partial;
   float* h[LFS_MAX_HIDDEN];
@@ -466,9 +592,11 @@ void run_net(const FlowGeom& g, const float* p, int B, const float* x, int fpar,
     const bool norm = g.bn && !last;
     float* out = last ? w.o : norm ? w.a[i] : w.h[i];
     const float* in = i == 0 ? x : w.h[i - 1];
-    hipLaunchKernelGGL((kn_conv<DIM, BF16>), grid_for(BV * g.cout[i]), dim3(256), 0, st, g.L, g.V, B,
-                       g.K, g.T, g.cin[i], g.cout[i], i == 0, fpar, !last && !norm, in, p + g.offW[i],
-                       p + g.offb[i], out);
+    with_kernel_size(g.K, [&](auto kc) {
+      hipLaunchKernelGGL((kn_conv<DIM, decltype(kc)::value, BF16>), grid_for(BV * g.cout[i] * kSplit),
+                         dim3(256), 0, st, g.L, log2_or_neg(g.L), g.V, B, g.cin[i], g.cout[i], i == 0, fpar,
+                         !last && !norm, in, p + g.offW[i], p + g.offb[i], out);
+    });
     if (norm) run_bn(g, p, B, i, bn, w, st);
   }
 }
@@ -547,13 +675,17 @@ int32_t backward_impl(const FlowGeom& g, const float* params, int B, const float
     for (int i = g.n_conv - 1; i >= 0; --i) {
       const int P = g.cout[i] * g.cin[i] * g.T + g.cout[i];
       const float* u = i == 0 ? x : w.h[i - 1];
-      hipLaunchKernelGGL((kn_wgrad<DIM, BF16>), dim3(P, G), dim3(256), 0, st, g.L, g.V, B, g.K, g.T,
-                         g.cin[i], g.cout[i], i == 0, fpar, gcur, u, w.partial, P);
-      hipLaunchKernelGGL(kn_reduce, grid_for(P), dim3(256), 0, st, G, P, w.partial, gp + g.offW[i]);
+      hipLaunchKernelGGL((kn_wgrad<DIM, BF16>), dim3(P, G), dim3(256), 0, st, g.L, log2_or_neg(g.L), g.V,
+                         B, g.K, g.T, g.cin[i], g.cout[i], i == 0, fpar, gcur, u, w.partial, P,
+                         G == 1 ? gp + g.offW[i] : nullptr);
+      if (G > 1)
+        hipLaunchKernelGGL(kn_reduce, grid_for(P), dim3(256), 0, st, G, P, w.partial, gp + g.offW[i]);
       float* gin = i == 0 ? gx : gbuf[i & 1];
-      hipLaunchKernelGGL((kn_conv_t<DIM, BF16>), grid_for(BV * g.cin[i]), dim3(256), 0, st, g.L, g.V, B,
-                         g.K, g.T, g.cin[i], g.cout[i], i == 0, fpar, gcur, p + g.offW[i],
-                         i == 0 ? nullptr : w.h[i - 1], gin);
+      with_kernel_size(g.K, [&](auto kc) {
+        hipLaunchKernelGGL((kn_conv_t<DIM, decltype(kc)::value, BF16>), grid_for(BV * g.cin[i] * kSplit),
+                           dim3(256), 0, st, g.L, log2_or_neg(g.L), g.V, B, g.cin[i], g.cout[i], i == 0,
+                           fpar, gcur, p + g.offW[i], i == 0 ? nullptr : w.h[i - 1], gin);
+      });
       if (g.bn && i > 0) {
         // gin holds g_y of hidden convolution j = i - 1: back through its normalisation
         const int j = i - 1, c = g.cout[j];
