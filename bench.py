@@ -247,7 +247,8 @@ def hbm_kernels(reps=20):
 def general_networks(steps=200):
     """Training steps/s of the example shape (2D L=8, 16 layers, batch 64, BF16) with other
     s/t networks from the parameter file's hidden_sizes / kernel_size / use_bn, on the
-    general-network kernels, beside the default network (hidden [8, 8], kernel 3)."""
+    general-network kernels, beside the default network (hidden [8, 8], kernel 3); each
+    eagerly and with forward + backward replayed from a captured HIP graph."""
     import torch
     import seeded_inputs as si
     from paper_2208_08903_amd import flow as fl
@@ -256,17 +257,22 @@ def general_networks(steps=200):
     for name, K, hs, bn in (("default_8x8_k3", 0, None, False), ("hidden_8x8_k5", 5, (8, 8), False),
                             ("hidden_16x16x16_k3", 3, (16, 16, 16), False), ("hidden_8_k3", 3, (8,), False),
                             ("hidden_8x8_k3_batch_norm", 3, (8, 8), True)):
-        f = fl.Flow(2, 8, 16, 8, lfs.LFS_BF16_CONV, kernel=K, hidden_sizes=hs, batch_norm=bn,
-                    params=si.flow_params(2, 16, 8, kernel=K or 3, hidden_sizes=hs, batch_norm=bn))
-        tr = fl.Trainer(f, 64, -4.0, 8.0)
-        for _ in range(5):
-            tr.step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            tr.step()
-        torch.cuda.synchronize()
-        out[name] = {"params": f.P, "train_steps_per_s": round(steps / (time.perf_counter() - t0), 1)}
+        row = {}
+        for graph in (False, True):
+            f = fl.Flow(2, 8, 16, 8, lfs.LFS_BF16_CONV, kernel=K, hidden_sizes=hs, batch_norm=bn,
+                        params=si.flow_params(2, 16, 8, kernel=K or 3, hidden_sizes=hs, batch_norm=bn))
+            tr = fl.Trainer(f, 64, -4.0, 8.0, graph=graph)
+            for _ in range(5):
+                tr.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                tr.step()
+            torch.cuda.synchronize()
+            row["params"] = f.P
+            row["train_steps_per_s_graph" if graph else "train_steps_per_s"] = \
+                round(steps / (time.perf_counter() - t0), 1)
+        out[name] = row
     return out
 
 

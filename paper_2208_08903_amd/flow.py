@@ -115,10 +115,16 @@ class Trainer:
     lr_schedule (the example parameter file's lr_scheduler, empty there: a constant
     rate): None, or a function (base_lr, t) -> learning rate of Adam step t >= 1,
     e.g. step_lr or exp_lr.  It runs on the host and only sets the rate passed to
-    the Adam kernel."""
+    the Adam kernel.
+
+    graph: replay forward + action + loss + backward (every launch but the prior
+    draw and the Adam step, whose counters change each step) as one captured HIP
+    graph.  The first step runs them eagerly and captures them; buffers are fixed,
+    so later steps replay the same launches on fresh prior draws.  For small
+    shapes, where a step is launch-bound."""
 
     def __init__(self, flow: Flow, B: int, m2: float, lam: float, lr=1e-3, key=12345,
-                 betas=(0.9, 0.999), eps=1e-8, lr_schedule=None):
+                 betas=(0.9, 0.999), eps=1e-8, lr_schedule=None, graph=False):
         self.flow, self.B = flow, B
         dev, V, N = flow.device, flow.V, flow.n_layers
         self.m2 = torch.tensor([m2], dtype=torch.float64, device=dev)
@@ -140,6 +146,8 @@ class Trainer:
         self.ws_f = flow.workspace(B, False)
         self.ws_b = flow.workspace(B, True)
         self.t = 0
+        self.graph = graph
+        self._graph = None
 
     # The four phases, separately callable so a caller can time them.
     def draw(self):
@@ -164,10 +172,24 @@ class Trainer:
         lfs.adam_step(self.flow.params, self.gparams, self.m, self.v, self.current_lr(),
                       self.betas[0], self.betas[1], self.eps, self.t)
 
+    def _forward_backward(self):
+        if not self.graph:
+            self.forward()
+            self.backward()
+        elif self._graph is None:
+            self.forward()
+            self.backward()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                self.forward()
+                self.backward()
+            self._graph = g
+        else:
+            self._graph.replay()
+
     def step(self):
         self.draw()
-        self.forward()
-        self.backward()
+        self._forward_backward()
         self.update()
 
 
