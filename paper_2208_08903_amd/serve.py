@@ -16,7 +16,10 @@ exact).  The server
     groups overlap on the device: prior draw with per-request Philox streams ->
     fused flow forward -> action with per-sample couplings -> log-weights ->
     ragged MH over the requests' persistent chain states;
-  * returns a request and frees its memory as soon as its last chunk is done.
+  * returns a request and frees its memory as soon as its last chunk is done;
+  * cancels a request on demand between scheduling rounds (nothing of it is on
+    the device then): a waiting one is dropped, a live one retired early with
+    its memory and chain-state slot freed.
 
 A sample's computation never depends on which batch it is in (per-sample
 kernels, per-request random streams, per-request chains whose state persists
@@ -135,6 +138,7 @@ class Server:
         self.live: list[_Live] = []
         self.results: list[Result] = []
         self.rejected: list = []
+        self.cancelled: list = []   # (rid, proposals decided before the cancellation)
         self.used = 0
         self.peak_used = 0
         self._groups = {}
@@ -283,6 +287,23 @@ class Server:
         self.live = still
         self.rounds += 1
         return done_n
+
+    def cancel(self, rid) -> bool:
+        """Withdraw request `rid` (call between steps; step() has finished all device
+        work by the time it returns).  Returns False if it is not waiting or live."""
+        for r in self.waiting:
+            if r.rid == rid:
+                self.waiting.remove(r)
+                self.cancelled.append((rid, 0))
+                return True
+        for lv in self.live:
+            if lv.req.rid == rid:
+                self.live.remove(lv)
+                self.used -= lv.nbytes
+                self.free_slots.append(lv.slot)
+                self.cancelled.append((rid, lv.done))
+                return True
+        return False
 
     def idle(self) -> bool:
         return not self.live and not self.waiting

@@ -93,3 +93,29 @@ def test_poisson_workload_runs():
     stats = run_workload(srv, reqs)
     assert stats["requests"] == len(reqs) and stats["rejected"] == 0
     assert stats["p99_latency_s"] >= stats["p50_latency_s"] > 0
+
+
+def test_cancellation_frees_memory_and_slot():
+    """A waiting and a live request are cancelled between rounds: neither returns a
+    result, their memory and chain slot come back, and a request that then takes the
+    freed slot gives the same result as alone (its chain state starts from zero)."""
+    late = req(9, 2, 16, 400, seed=31, m2=-3.9, lam=6.5)
+    _, alone = serve_all([late], quantum=128)
+    srv = Server(params(), arch=ARCH, quantum=128, max_live=2,
+                 hbm_budget=request_bytes(2, 16, 900) + request_bytes(2, 8, 600))
+    for r in (req(0, 2, 16, 900, 1), req(1, 2, 8, 600, 2), req(2, 3, 8, 50, 3)):
+        srv.submit(r)
+    srv.step()                                       # 0 and 1 live (two slots), 2 waiting
+    assert [lv.req.rid for lv in srv.live] == [0, 1] and len(srv.waiting) == 1
+    assert srv.cancel(2) and srv.cancel(0) and not srv.cancel(42)
+    assert srv.used == request_bytes(2, 8, 600) and len(srv.free_slots) == 1
+    srv.submit(late)                                 # takes the cancelled request's slot
+    while not srv.idle():
+        srv.step()
+    torch.cuda.synchronize()
+    res = {r.rid: r for r in srv.results}
+    assert sorted(res) == [1, 9]
+    assert [c[0] for c in srv.cancelled] == [2, 0] and srv.cancelled[1][1] == 128
+    assert srv.used == 0 and sorted(srv.free_slots) == [0, 1]
+    for f in ("proposals", "logw", "cur_idx", "accepted"):
+        np.testing.assert_array_equal(getattr(res[9], f).cpu().numpy(), getattr(alone[9], f).cpu().numpy())
