@@ -87,7 +87,8 @@ def test_log_weights_and_loss():
     np.testing.assert_allclose(host(loss)[0], np.mean(lq + S), rtol=1e-13)
 
 
-@pytest.mark.parametrize("n_chains,n_prop,scale", [(1, 2000, 1.0), (7, 333, 3.0), (64, 130, 0.3)])
+@pytest.mark.parametrize("n_chains,n_prop,scale", [(1, 2000, 1.0), (1, 10_000, 2.0), (7, 333, 3.0),
+                                                   (64, 130, 0.3)])
 def test_mh_chain_bit_exact(n_chains, n_prop, scale):
     w = si.logw_stream(5, n_chains * n_prop, scale).reshape(n_chains, n_prop)
     lu = si.log_uniforms(6, (n_chains, n_prop))
