@@ -192,6 +192,43 @@ class Trainer:
         self._forward_backward()
         self.update()
 
+    # Checkpoints: with counter-based prior draws and the Adam step count in the
+    # state, a resumed run continues bit for bit.
+    def state(self) -> dict:
+        """Host copies of everything a resume needs: parameters, Adam moments, the step
+        count, the prior key (and batch-norm running statistics)."""
+        st = {"params": self.flow.params.cpu().numpy(), "adam_m": self.m.cpu().numpy(),
+              "adam_v": self.v.cpu().numpy(), "step": np.int64(self.t), "key": np.int64(self.key),
+              "batch": np.int64(self.B)}
+        if self.flow.batch_norm:
+            st["bn_stats"] = self.flow.bn_stats.cpu().numpy()
+        return st
+
+    def load_state(self, st: dict):
+        """Restore a state() into this trainer's buffers (in place, so a captured graph
+        stays valid)."""
+        for name, dst in (("params", self.flow.params), ("adam_m", self.m), ("adam_v", self.v)):
+            a = np.asarray(st[name], np.float32)
+            if a.size != dst.numel():
+                raise lfs.LfsError(f"checkpoint {name} has {a.size} entries, the flow needs {dst.numel()}")
+            dst.copy_(torch.as_tensor(a.reshape(dst.shape)))
+        if self.flow.batch_norm:
+            if "bn_stats" not in st:
+                raise lfs.LfsError("checkpoint has no batch-norm statistics")
+            self.flow.bn_stats.copy_(torch.as_tensor(np.asarray(st["bn_stats"], np.float32)))
+        if int(st["key"]) != self.key or int(st["batch"]) != self.B:
+            raise lfs.LfsError("checkpoint was written with another prior key or batch size")
+        self.t = int(st["step"])
+
+
+def save_checkpoint(path: str, trainer: Trainer):
+    np.savez(path, **trainer.state())
+
+
+def load_checkpoint(path: str) -> dict:
+    with np.load(path, allow_pickle=False) as f:
+        return {k: f[k] for k in f.files}
+
 
 class Sampler:
     """Flow proposals and one persistent independence-MH chain per sampler."""

@@ -1,0 +1,85 @@
+"""The run configuration in the paper's parameter-file layout (Sec. 2.1, the
+example2d.toml listing): parsing of the paper's own file, validation, the
+packed-parameter layout against the library's count, and the learning-rate
+schedules.  Host-only."""
+import os
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from paper_2208_08903_amd import config as cf
+from paper_2208_08903_amd import lfs
+
+EXAMPLE = os.path.join(os.path.dirname(__file__), "golden", "example2d.toml")
+
+
+def test_paper_example_file():
+    # the listing trains on the CPU (device_id = -1), which this build does not
+    with pytest.raises(cf.ConfigError, match="CPU"):
+        cf.load(EXAMPLE)
+    c = cf.load(EXAMPLE, device_id=0)
+    assert (c.training.seed, c.training.batchsize, c.training.epochs, c.training.iterations) == (12345, 64, 200, 100)
+    assert c.training.base_lr == 1e-3 and c.training.opt == "Adam" and c.training.lr_scheduler == ""
+    assert (c.physical.L, c.physical.Nd, c.physical.M2, c.physical.lam) == (8, 2, -4.0, 8.0)
+    m = c.model
+    assert (m.seed, m.n_layers, list(m.hidden_sizes), m.kernel_size, m.inC, m.outC) == (2021, 16, [8, 8], 3, 1, 2)
+    assert m.use_final_tanh and not m.use_bn
+    # the example network is the default one: 12960 parameters
+    assert cf.init_params(c).size == 12960 == si.param_count(2, 16, 8)
+
+
+@pytest.mark.parametrize("group,key,value,match", [
+    ("training", "opt", "SGD", "Adam"),
+    ("training", "prior", "Uniform(0, 1)", "standard normal"),
+    ("training", "lr_scheduler", "cosine", "lr_scheduler"),
+    ("training", "batchsize", 0, "batchsize"),
+    ("physical", "Nd", 4, "Nd"),
+    ("physical", "L", 7, "even"),
+    ("model", "inC", 2, "1 input"),
+    ("model", "hidden_sizes", [8, 8, 8, 8, 8], "hidden_sizes"),
+    ("model", "hidden_sizes", [8, 65], "hidden_sizes"),
+    ("model", "kernel_size", 4, "odd"),
+    ("model", "precision", "fp8", "precision"),
+    ("model", "colour", 1, "unknown key"),
+    ("optics", "x", 1, "unknown group"),
+])
+def test_validation(group, key, value, match):
+    d = {"device": {"device_id": 0}, group: {key: value}}
+    with pytest.raises(cf.ConfigError, match=match):
+        cf.from_dict(d)
+
+
+def test_accepted_prior_spellings_and_schedules():
+    for prior in ("Normal{Float32}(0.f0, 1.f0)", "Normal(0, 1)", "Normal{Float64}(0.0, 1.0)"):
+        cf.from_dict({"training": {"prior": prior}})
+    f = cf.lr_schedule("step:0.5:10")
+    assert f(1e-3, 1) == 1e-3 and f(1e-3, 11) == 5e-4 and f(1e-3, 21) == 2.5e-4
+    g = cf.lr_schedule("exp:0.9")
+    assert g(1.0, 1) == 1.0 and abs(g(1.0, 3) - 0.81) < 1e-15
+    assert cf.lr_schedule("") is None
+
+
+@pytest.mark.parametrize("Nd,hs,K,bn", [(2, [8, 8], 3, False), (3, [3, 5, 4], 5, False), (2, [6], 1, True),
+                                        (3, [16, 16], 3, True)])
+def test_layout_matches_library_and_generator(Nd, hs, K, bn):
+    c = cf.from_dict({"physical": {"Nd": Nd, "L": 4}, "model": {"hidden_sizes": hs, "kernel_size": K,
+                                                                "use_bn": bn, "n_layers": 3}})
+    p = cf.init_params(c)
+    d = lfs.make_desc(Nd, 4, 3, 0, kernel=K, hidden_sizes=hs, batch_norm=bn)
+    assert p.size == lfs.param_count(d) == si.param_count(Nd, 3, 0, K, hs, batch_norm=bn)
+    names = [k for k, _ in cf.layer_blocks(c)]
+    gen = [n.rstrip("0123456789") for n, _ in si.layer_block_sizes(Nd, 0, K, hs, bn)]
+    assert names == gen
+    # biases and betas start at 0, gammas at 1, weights N(0, 0.1^2)
+    lay = p[:p.size // 3]
+    off = 0
+    for kind, shape in cf.layer_blocks(c):
+        n = int(np.prod(shape))
+        blk = lay[off:off + n]
+        off += n
+        if kind == "gamma":
+            assert np.all(blk == 1)
+        elif kind in ("b", "beta"):
+            assert np.all(blk == 0)
+    assert abs(np.std(p[np.abs(p) != 0][np.abs(p[np.abs(p) != 0]) != 1]) - 0.1) < 0.02
