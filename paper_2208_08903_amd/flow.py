@@ -318,8 +318,9 @@ def chain_quality(flow: Flow, m2: float, lam: float, batches: int, B: int, w_max
                   key=4242, u_seed=78):
     """One independence-MH chain over batches x B flow proposals.  Along the chain:
     the integrated autocorrelation time (automatic window, factor c) of the
-    condensate M and of the action S, N_indep = N / (2 tau); plus the acceptance
-    and the normalised reweighting ESS of all proposals."""
+    condensate M and of the action S, N_indep = N / (2 tau); the chain average of
+    M^2 with its error sqrt(2 tau var / N) (tau of the M^2 series); plus the
+    acceptance and the normalised reweighting ESS of all proposals."""
     dev, n = flow.device, batches * B
     f64 = torch.float64
     M = torch.empty(1, n, dtype=f64, device=dev)
@@ -337,12 +338,17 @@ def chain_quality(flow: Flow, m2: float, lam: float, batches: int, B: int, w_max
         cur[0, sl].copy_(smp.cur[0])
     tm, wm, fm, nm = _tau(M, w_max, c, index=cur)
     ts, ws, fs, ns = _tau(S, w_max, c, index=cur)
+    # M^2 along the chain (the squares formed on the host), its mean and error
+    m2_chain = M.cpu().numpy()[0][cur.cpu().numpy()[0]] ** 2
+    t2, _, _, _ = _tau(torch.as_tensor(m2_chain.reshape(1, -1), device=dev), w_max, c)
     e = torch.empty(1, dtype=f64, device=dev)
     lfs.ess(logw, e)
     return {"proposals": n, "acceptance": round(smp.acceptance()[0], 5),
             "tau_M": float(tm[0]), "window_M": int(wm[0]), "window_found_M": bool(fm[0]),
             "n_indep_M": float(nm[0]), "tau_S": float(ts[0]), "window_S": int(ws[0]),
-            "window_found_S": bool(fs[0]), "n_indep_S": float(ns[0]), "ess": float(e.item())}
+            "window_found_S": bool(fs[0]), "n_indep_S": float(ns[0]), "ess": float(e.item()),
+            "M2_mean": float(m2_chain.mean()),
+            "M2_err": float(np.sqrt(2.0 * max(float(t2[0]), 0.5) * m2_chain.var() / n))}
 
 
 def hmc_chain_quality(dim: int, L: int, m2: float, lam: float, n_chains: int, n_traj: int,
@@ -351,7 +357,8 @@ def hmc_chain_quality(dim: int, L: int, m2: float, lam: float, n_chains: int, n_
     trajectory, fresh momenta each trajectory) from a cold start phi = 0; the
     first n_traj // 5 trajectories are discarded.  Per chain, the integrated
     autocorrelation time of M over the remaining trajectories; returns the chain
-    means and the acceptance."""
+    means, the acceptance, and the average of M^2 with its error from the spread of
+    the per-chain averages."""
     import seeded_inputs as si
     dev, V, f64 = "cuda", L ** dim, torch.float64
     phi = torch.zeros(n_chains, V, dtype=f64, device=dev)
@@ -371,7 +378,9 @@ def hmc_chain_quality(dim: int, L: int, m2: float, lam: float, n_chains: int, n_
             lfs.observables(dim, L, phi, Mt[k - therm], None)
             n_acc += acc
     tm, wm, fm, _ = _tau(Mt.t().contiguous(), w_max, c)
+    per_chain = (Mt.cpu().numpy() ** 2).mean(axis=0)
     return {"chains": n_chains, "trajectories": n, "leapfrog_steps": n_steps, "dt": dt,
             "acceptance": float(n_acc.sum().item()) / (n * n_chains),
             "tau_M_mean": float(np.nanmean(tm)), "window_found_M": int(fm.sum()),
-            "n_indep_M_per_chain_mean": float(np.nanmean(n / (2 * tm)))}
+            "n_indep_M_per_chain_mean": float(np.nanmean(n / (2 * tm))),
+            "M2_mean": float(per_chain.mean()), "M2_err": float(per_chain.std(ddof=1) / np.sqrt(n_chains))}
