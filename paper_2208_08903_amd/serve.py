@@ -19,7 +19,8 @@ exact).  The server
   * returns a request and frees its memory as soon as its last chunk is done;
   * cancels a request on demand between scheduling rounds (nothing of it is on
     the device then): a waiting one is dropped, a live one retired early with
-    its memory and chain-state slot freed.
+    its memory and chain-state slot freed;
+  * refuses new requests while max_waiting are queued (overload).
 
 A sample's computation never depends on which batch it is in (per-sample
 kernels, per-request random streams, per-request chains whose state persists
@@ -124,10 +125,11 @@ class Server:
     def __init__(self, params_by_dim: dict, arch: dict | None = None,
                  precision=lfs.LFS_BF16_CONV, hbm_budget: int = 512 << 20, quantum: int = 2048,
                  max_batch: int = 8192, max_batch_sites: int = 8 << 20, max_live: int = 256,
-                 device="cuda", clock=time.perf_counter):
+                 max_waiting: int = 1 << 16, device="cuda", clock=time.perf_counter):
         self.arch = dict(DEFAULT_ARCH if arch is None else arch)
         self.precision = precision
         self.budget, self.quantum, self.max_batch, self.max_live = hbm_budget, quantum, max_batch, max_live
+        self.max_waiting = max_waiting
         self.max_batch_sites = max_batch_sites
         self.device, self.clock = device, clock
         self.params = {d: torch.as_tensor(np.asarray(p, np.float32)).to(device)
@@ -167,8 +169,14 @@ class Server:
         return self._groups[key]
 
     # -- request flow ---------------------------------------------------------------
-    def submit(self, req):
+    def submit(self, req) -> bool:
+        """Queue a request; False (and the request is counted as rejected) when the
+        waiting queue already holds max_waiting requests."""
+        if len(self.waiting) >= self.max_waiting:
+            self.rejected.append(req)
+            return False
         self.waiting.append(req)
+        return True
 
     def _admit(self):
         admit, reject = plan_admission(list(self.waiting), self.used, self.budget, len(self.free_slots))

@@ -119,3 +119,14 @@ def test_cancellation_frees_memory_and_slot():
     assert srv.used == 0 and sorted(srv.free_slots) == [0, 1]
     for f in ("proposals", "logw", "cur_idx", "accepted"):
         np.testing.assert_array_equal(getattr(res[9], f).cpu().numpy(), getattr(alone[9], f).cpu().numpy())
+
+
+def test_queue_overflow_rejects():
+    srv = Server(params(), arch=ARCH, max_waiting=2)
+    assert srv.submit(req(0, 2, 8, 10, 1)) and srv.submit(req(1, 2, 8, 10, 2))
+    assert not srv.submit(req(2, 2, 8, 10, 3))
+    assert [r.rid for r in srv.rejected] == [2]
+    while not srv.idle():
+        srv.step()
+    assert sorted(r.rid for r in srv.results) == [0, 1]
+    assert srv.submit(req(3, 2, 8, 10, 4))           # room again once the queue drained
