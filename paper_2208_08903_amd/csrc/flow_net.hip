@@ -4,9 +4,10 @@
 // conv(w_{n-1} -> w_n) + LeakyReLU, conv(w_n -> 2) with an odd kernel K per
 // axis (paper Sec. 1, coupling-layer equation; taps row-major over
 // {-K/2..K/2}^dim, axis 0 slowest).  Direct periodic convolutions with runtime
-// channel counts, one thread per (sample, site, output channel), activations
-// in HBM.  In BF16 mode every convolution operand is rounded to BF16 and
-// products are accumulated in FP32, as in the other kernel families.
+// channel counts and the kernel size as a template parameter, kSplit lanes per
+// (sample, site, output channel), activations in HBM.  In BF16 mode every
+// convolution operand is rounded to BF16 and products are accumulated in FP32,
+// as in the other kernel families.
 //
 // Batch norm (the parameter file's use_bn): a hidden convolution's output a is
 // kept, its per-channel statistics are reduced over the batch and all sites in
@@ -26,7 +27,7 @@ inline dim3 grid_for(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs -
 
 constexpr int ipow(int k, int d) { return d == 0 ? 1 : k * ipow(k, d - 1); }
 
-constexpr int kWgChunk = 4096;  // (sample, site) terms per weight-gradient workgroup
+constexpr int kWgChunk = 4096;  // (sample, site) terms per weight-gradient or batch-norm partial sum
 // Lanes that share one convolution output: lane s of a group takes the (tap,
 // channel) pairs q = t cin + ci with q = s mod kSplit, and the group's partial
 // sums are combined by a fixed xor-shuffle tree (deterministic).
@@ -40,6 +41,7 @@ __device__ __forceinline__ float split_sum(float v) {
 
 // First channel c of the pairs (t, c), c = c0, c0 + kSplit, ..., that lane s takes.
 __device__ __forceinline__ int split_first(int s, int t, int nc) { return (s - t * nc) & (kSplit - 1); }
+
 constexpr double kBnEps = 1e-5;
 constexpr int kMaxWidth = 64;   // hidden_sizes entries are at most 64
 
@@ -201,6 +203,7 @@ __global__ void kn_finalize(int B, const double* __restrict__ logr, const double
 
 // Backward of the affine update: g_o at the active sites (zero at the frozen
 // ones) and g_x (active: g e^s; frozen: g, the network's path is added later).
+// The log-det's cotangent is g_ld, or -g_ld_vec[b] per sample when given.
 template <int DIM>
 __global__ void __launch_bounds__(256) kn_affine_bwd(int L, int V, int B, int fpar, int final_tanh,
                                                      const float* __restrict__ x,
