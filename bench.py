@@ -7,10 +7,16 @@ batch 1024, Adam lr 1e-3: prior draw -> flow forward with log q (saving the
 layer inputs) -> action and force -> log-weights and loss -> hand-written flow
 backward -> Adam.  Inputs are synthetic: seeded N(0, 0.1) weights (biases 0),
 Philox prior draws.  `value` is BF16-conv (FP32 accumulate, FP64 sums) training
-steps per second; the plain FP32 path, flow+MH sampling and the FP64 HMC
-baseline are reported beside it.
+steps per second, with `roofline` (the per-layer backward launch against the
+BF16 MFMA peak, and its HBM traffic from the committed rocprofv3 summary) and
+`cpu_baseline` (the FP64 oracle on a bounded sample of the batch).  Beside it:
+the plain FP32 path, flow+MH sampling, the FP64 HMC baseline, the memory-side
+kernels against HBM (the prior also against the VALU issue peak), the other
+workloads (2D L=8, 3D L=8, 3D L=16 C=32), other s/t networks, the example
+schedule trained to convergence with chain quality against HMC, serving in
+both precisions, and the oracle on the other workloads.
 
-Prints ONE JSON line.  Only one GPU is supported.
+Prints ONE JSON line (progress lines go to stderr).  Only one GPU is supported.
 """
 from __future__ import annotations
 
