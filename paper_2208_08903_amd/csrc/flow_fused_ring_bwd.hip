@@ -511,6 +511,8 @@ __global__ void __launch_bounds__(NT) kr_wgrad(
   // single tiles: dW3 (row tile, 16 (tap, co) columns), then dW1 (row tile, 16 taps)
   constexpr int N3 = Cfg::N3, J31 = Cfg::N3 + Cfg::N1, JS31 = (J31 + NW - 1) / NW;
   constexpr int CS = Cfg::CS;
+  constexpr int PPT = (C * PLANE / 8 + NT - 1) / NT;  // 16-byte plane pieces per thread
+  static_assert(PLANE <= NT, "one ring site per thread");
   extern __shared__ __align__(16) unsigned char smem[];
   uint16_t* pa1 = reinterpret_cast<uint16_t*>(smem);  // h1 of plane z, [C][CS]
   uint16_t* pa2 = pa1 + C * CS;                        // h2 of plane z
@@ -543,23 +545,61 @@ __global__ void __launch_bounds__(NT) kr_wgrad(
         rh0[slot * PLANE + i] = G::parity(n) == fpar ? (uint16_t)bf16_bits(xin[sb + n]) : (uint16_t)0;
       }
     };
-    auto load_plane = [&](int zr) {
-      for (int i = threadIdx.x; i < C * PLANE / 8; i += NT) {
-        const int c = i / (PLANE / 8), k = i % (PLANE / 8);
-        const size_t src = ((size_t)b * C + c) * V + zr * PLANE + 8 * k;
-        const int dst = c * CS + 8 * k;
-        *reinterpret_cast<u32x4*>(pa1 + dst) = *reinterpret_cast<const u32x4*>(h1c + src);
-        *reinterpret_cast<u32x4*>(pa2 + dst) = *reinterpret_cast<const u32x4*>(h2c + src);
-        *reinterpret_cast<u32x4*>(pa3 + dst) = *reinterpret_cast<const u32x4*>(ga1c + src);
+    // Software pipelining: the operands of the next step (plane z + 1 of h1, h2,
+    // g_a1 and ring plane z + 2 of g_a2, g_o, mask_F x) are fetched into registers
+    // while plane z is computed, and written to LDS after the step's closing
+    // barrier, so the HBM latency hides behind the matrix work.
+    u32x4 f1[PPT], f2[PPT], f3[PPT], fr[PPT];
+    uint32_t fgo = 0u;
+    float fx = 0.f;
+    auto fetch = [&](int zp, int vr) {
+      const int zr = ((vr % L) + L) % L;
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int i = threadIdx.x + q * NT;
+        if (i < C * PLANE / 8) {
+          const int c = i / (PLANE / 8), k = i % (PLANE / 8);
+          const size_t src = ((size_t)b * C + c) * V + zp * PLANE + 8 * k;
+          f1[q] = *reinterpret_cast<const u32x4*>(h1c + src);
+          f2[q] = *reinterpret_cast<const u32x4*>(h2c + src);
+          f3[q] = *reinterpret_cast<const u32x4*>(ga1c + src);
+          fr[q] = *reinterpret_cast<const u32x4*>(ga2c + ((size_t)b * C + c) * V + zr * PLANE + 8 * k);
+        }
+      }
+      if (threadIdx.x < PLANE) {
+        fgo = go[sb + zr * PLANE + threadIdx.x];
+        fx = xin[sb + zr * PLANE + threadIdx.x];
+      }
+    };
+    auto commit = [&](int vr) {
+      const int zr = ((vr % L) + L) % L, slot = mod3(vr);
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int i = threadIdx.x + q * NT;
+        if (i < C * PLANE / 8) {
+          const int c = i / (PLANE / 8), k = i % (PLANE / 8);
+          const int dst = c * CS + 8 * k;
+          *reinterpret_cast<u32x4*>(pa1 + dst) = f1[q];
+          *reinterpret_cast<u32x4*>(pa2 + dst) = f2[q];
+          *reinterpret_cast<u32x4*>(pa3 + dst) = f3[q];
+          *reinterpret_cast<u32x4*>(rg2 + (slot * C + c) * CS + 8 * k) = fr[q];
+        }
+      }
+      if (threadIdx.x < PLANE) {
+        const int i = threadIdx.x, n = zr * PLANE + i;
+        rgo[(slot * 2 + 0) * CS + i] = (uint16_t)fgo;
+        rgo[(slot * 2 + 1) * CS + i] = (uint16_t)(fgo >> 16);
+        rh0[slot * PLANE + i] = G::parity(n) == fpar ? (uint16_t)bf16_bits(fx) : (uint16_t)0;
       }
     };
     __syncthreads();
     load_ring(-1);
     load_ring(0);
+    fetch(0, 1);
     for (int z = 0; z < L; ++z) {
-      load_ring(z + 1);
-      load_plane(z);
+      commit(z + 1);        // plane z and ring plane z + 1 (their previous readers passed the last barrier)
       __syncthreads();
+      if (z + 1 < L) fetch(z + 1, z + 2);
       // dW2: D[ci][(tap, co)] += sum over the plane's sites m of h1[m][ci] g_a2[m - d][co]
 #pragma unroll
       for (int k = 0; k < JS2; ++k) {
