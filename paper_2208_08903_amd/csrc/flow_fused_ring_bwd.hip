@@ -67,7 +67,7 @@ struct RbCfg {
   static constexpr int S2 = (N2 + NWC - 1) / NWC, S3 = (N3 + NWC - 1) / NWC, S1 = (N1 + NWC - 1) / NWC;
   static_assert(C % 16 == 0 && L % 16 == 0, "ring backward shapes");
   // dynamic LDS plus the kernels' static buffers (partial reduction, bias sums)
-  static_assert(LDS_A + kRedSlices * (NT_A / kRedSlices + 1) * 4 + 64 <= 160 * 1024 &&
+  static_assert(LDS_A + kRedSlices * (NT_A / kRedSlices + 1) * 4 + 64 + 2 * PLANE * 4 <= 160 * 1024 &&
                     LDS_B + (NT_B / 64) * C * 4 <= 160 * 1024 && LDS_C <= 160 * 1024,
                 "LDS budget");
 };
@@ -165,6 +165,10 @@ __global__ void __launch_bounds__(NT) kr_recompute(
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float red[16];
+  // g_y of the plane conv3 works on, two buffers: plane zr's is stored while conv3
+  // of plane zr - 1 may still read the other
+  static_assert(PLANE <= NT, "one g_y value per thread and plane");
+  __shared__ float gys[2][PLANE];
   float* xs = reinterpret_cast<float*>(smem);
   uint16_t* r1 = reinterpret_cast<uint16_t*>(smem + Cfg::XS_BYTES);
   uint16_t* r2 = r1 + Cfg::RING;
@@ -259,7 +263,7 @@ __global__ void __launch_bounds__(NT) kr_recompute(
               const float o0 = acc[0][0];
               const float s = final_tanh ? fast_tanh(o0) : o0;
               const float es = fast_exp(s);
-              const float g = gy[sb + n];
+              const float g = gys[zr & 1][n - zr * PLANE];
               const float gs = g * xs[LX::idx(n)] * es + gld;
               const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
               db3s += go0;
@@ -283,7 +287,11 @@ __global__ void __launch_bounds__(NT) kr_recompute(
     conv2_plane(0);
     __syncthreads();
     for (int zr = 0; zr < L; ++zr) {
+      // plane zr's g_y is read here and held in a register through conv1, so its
+      // HBM latency hides behind that pass instead of stalling conv3's epilogue
+      const float gpre = threadIdx.x < PLANE ? gy[sb + zr * PLANE + threadIdx.x] : 0.f;
       conv1_plane(zr + 2);
+      if (threadIdx.x < PLANE) gys[zr & 1][threadIdx.x] = gpre;
       __syncthreads();
       conv2_plane(zr + 1);
       __syncthreads();
