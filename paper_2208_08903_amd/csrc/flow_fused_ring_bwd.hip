@@ -68,7 +68,7 @@ struct RbCfg {
   static_assert(C % 16 == 0 && L % 16 == 0, "ring backward shapes");
   // dynamic LDS plus the kernels' static buffers (partial reduction, bias sums)
   static_assert(LDS_A + kRedSlices * (NT_A / kRedSlices + 1) * 4 + 64 + 2 * PLANE * 4 <= 160 * 1024 &&
-                    LDS_B + (NT_B / 64) * C * 4 <= 160 * 1024 && LDS_C <= 160 * 1024,
+                    LDS_B + (NT_B / 64) * C * 4 + 2 * PLANE * 4 <= 160 * 1024 && LDS_C <= 160 * 1024,
                 "LDS budget");
 };
 
@@ -322,6 +322,9 @@ __global__ void __launch_bounds__(NT) kr_transpose(
   constexpr int NW = NT / 64, KT3 = Cfg::KT3;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float red[NW * C];
+  // g_y of the plane the g_x pass works on, two buffers (see the plane loop)
+  static_assert(PLANE <= NT, "one g_y value per thread and plane");
+  __shared__ float gys[2][PLANE];
   uint32_t* gor = reinterpret_cast<uint32_t*>(smem);
   uint32_t* sm2 = reinterpret_cast<uint32_t*>(smem + Cfg::GOR_BYTES);  // h2 signs of one plane
   uint32_t* sm1 = sm2 + PLANE;                                          // h1 signs of one plane
@@ -429,8 +432,8 @@ __global__ void __launch_bounds__(NT) kr_transpose(
           },
           [&](int tile, const f32x4(&acc)[1]) {
             if (j == 0) {
-              const int n = zr * PLANE + Geo<2, L>::half_site(tile * 16 + m, fp);
-              gx[sb + n] = gy[sb + n] + acc[0][0];
+              const int q = Geo<2, L>::half_site(tile * 16 + m, fp), n = zr * PLANE + q;
+              gx[sb + n] = gys[zr & 1][q] + acc[0][0];
             }
           });
     };
@@ -464,15 +467,49 @@ __global__ void __launch_bounds__(NT) kr_transpose(
     __syncthreads();
     a1_plane(0);
     __syncthreads();
+    // Software pipelining: the next step's g_o plane, sign words and g_y are read
+    // into registers before the g_x pass and written to LDS at the top of the next
+    // step (their previous readers, the a2 and a1 passes, are behind its barriers;
+    // g_y alternates between two rows because the g_x pass may still read the
+    // other), so the HBM latency hides behind the g_x pass.
+    constexpr int GPT = (PS + NT - 1) / NT;
+    uint32_t fgo[GPT], fm2 = 0u, fm1 = 0u;
+    float fgy = 0.f;
+    auto fetch = [&](int z) {
+      const int zg = (((z + 3) % L) + L) % L, z2 = (((z + 2) % L) + L) % L, z1 = (((z + 1) % L) + L) % L;
+#pragma unroll
+      for (int r = 0; r < GPT; ++r) {
+        const int q = threadIdx.x + r * NT;
+        if (q < PS) fgo[r] = go[sb + zg * PLANE + LP2::site_of(q)];
+      }
+      if (threadIdx.x < PLANE) {
+        fm2 = m2[sb + z2 * PLANE + threadIdx.x];
+        fm1 = m1[sb + z1 * PLANE + threadIdx.x];
+        fgy = gy[sb + z * PLANE + threadIdx.x];
+      }
+    };
+    auto commit = [&](int z) {
+      uint32_t* dst = gor + mod3(z + 3) * PS;
+#pragma unroll
+      for (int r = 0; r < GPT; ++r) {
+        const int q = threadIdx.x + r * NT;
+        if (q < PS) dst[q] = fgo[r];
+      }
+      if (threadIdx.x < PLANE) {
+        sm2[threadIdx.x] = fm2;
+        sm1[threadIdx.x] = fm1;
+        gys[z & 1][threadIdx.x] = fgy;
+      }
+    };
+    fetch(0);
     for (int z = 0; z < L; ++z) {
-      go_plane(z + 3);
-      mask_plane(m2, sm2, z + 2);
-      mask_plane(m1, sm1, z + 1);
+      commit(z);
       __syncthreads();
       a2_plane(z + 2);
       __syncthreads();
       a1_plane(z + 1);
       __syncthreads();
+      if (z + 1 < L) fetch(z + 1);
       gx_plane(z);
     }
   }
