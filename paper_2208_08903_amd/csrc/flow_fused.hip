@@ -90,9 +90,12 @@ __global__ void __launch_bounds__(NT) kf_forward(
         load_a1();
         load_a2();
       }
-      // conv1 operands (row triples of the masked field) in the (dead) h2 buffer
-      build_tri<LY, BF16, NT>(h2, xs, fpar);
-      __syncthreads();
+      // conv1 operands: row triples of the masked field, built in the (dead) h2
+      // buffer, or (Cfg::TRIX) gathered straight from the field by each tile
+      if constexpr (!Cfg::TRIX) {
+        build_tri<LY, BF16, NT>(h2, xs, fpar);
+        __syncthreads();
+      }
       // conv1 over all sites
       {
         if constexpr (!Cfg::PFA) load_a1();
@@ -102,7 +105,12 @@ __global__ void __launch_bounds__(NT) kf_forward(
         mma_tiles<Cfg::TU1, LF.nct, LF.k1, BF16>(
             V / 16, w, NW, A1, bias,
             [&](int tile, int c) {
-              return gather_tri<LY, BF16>(h2, tile * 16 + m, tile_p<LY>(tile, m), c, j);
+              if constexpr (Cfg::TRIX) {
+                const int n = tile * 16 + m;
+                return gather_tri_x<LY, BF16>(xs, n, LY::idx(n), G::parity(n), fpar, c, j);
+              } else {
+                return gather_tri<LY, BF16>(h2, tile * 16 + m, tile_p<LY>(tile, m), c, j);
+              }
             },
             [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll

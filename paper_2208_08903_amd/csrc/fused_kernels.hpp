@@ -349,6 +349,12 @@ struct FwdCfg {
   // each pass's weight fragments fetched during the previous pass (2D, C <= 16:
   // the extra live fragments fit the registers of two waves per SIMD)
   static constexpr bool PFA = DIM == 2 && C <= 16;
+  // conv1 gathers its operands straight from the field instead of from row
+  // triples built in a pass of their own: faster where the pass and its barrier
+  // weigh more than the costlier gathers (2D FP32, and small 2D lattices whose
+  // four tiles per sample leave the barrier exposed); the 2D L = 32 and 3D BF16
+  // forwards are faster with the built triples
+  static constexpr bool TRIX = DIM == 2 && (!BF16 || L <= 8);
 };
 
 }  // namespace fused
