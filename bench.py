@@ -510,7 +510,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the multi-GPU data-parallel design is described in DESIGN.md", file=sys.stderr)
+              "every workload here is measured on a single GPU, and no multi-GPU figure is produced",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -15,7 +15,7 @@ EXAMPLE = os.path.join(os.path.dirname(__file__), "golden", "example2d.toml")
 
 
 def test_paper_example_file():
-    # the listing trains on the CPU (device_id = -1), which this build does not
+    # the listing trains on the CPU (device_id = -1), which this GPU implementation rejects
     with pytest.raises(cf.ConfigError, match="CPU"):
         cf.load(EXAMPLE)
     c = cf.load(EXAMPLE, device_id=0)
