@@ -240,15 +240,8 @@ int32_t launch_forward(const FlowGeom& g, const float* params, int B, const floa
   const long nthreads = (long)LF.total * 64 * g.N;
   hipLaunchKernelGGL((kf_prep<BF16>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st,
                      params, g.N, g.T, (int)g.P_layer, tab, frags);
-  auto kern = kf_forward<DIM, L, C, BF16, Cfg::NT>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)Cfg::lds_bytes) != hipSuccess)
-      return LFS_EDEVICE;
-    attr_set = true;
-  }
+  constexpr auto kern = kf_forward<DIM, L, C, BF16, Cfg::NT>;
+  if (!set_lds_limit<kern>(Cfg::lds_bytes)) return LFS_EDEVICE;
   hipLaunchKernelGGL(kern, dim3(B), dim3(Cfg::NT), Cfg::lds_bytes, st, frags, params,
                      (int)g.P_layer, (int)g.off_b1, (int)g.off_b2, (int)g.off_b3, g.N, g.parity0,
                      g.final_tanh, B, z, phi, saved, logq, logdet);

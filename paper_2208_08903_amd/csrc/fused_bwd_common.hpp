@@ -102,16 +102,5 @@ inline FragTable bwd_table(const FlowGeom& g, bool bf16, bool x4) {
   return t;
 }
 
-inline int num_cus() {
-  static int n = 0;
-  if (n == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
-      n = 256;
-  }
-  return n;
-}
-
 }  // namespace fused
 }  // namespace lfs

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "lfs.h"
 
 #define LFS_RETURN_IF(cond, code) \
@@ -18,6 +20,38 @@ constexpr int kWave = 64;
 
 inline int32_t launch_status() {
   return hipGetLastError() == hipSuccess ? LFS_OK : LFS_EDEVICE;
+}
+
+// Host-side facts cached per device (ordinals below kCachedDevices; others are
+// looked up on every call).  Safe to call from several host threads.
+constexpr int kCachedDevices = 64;
+
+// Raises kernel KERN's dynamic LDS limit to `bytes` on the current device, once
+// per device.
+template <auto KERN>
+inline bool set_lds_limit(size_t bytes) {
+  static std::atomic<uint64_t> done{0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  const uint64_t bit = (dev >= 0 && dev < kCachedDevices) ? (1ull << dev) : 0;
+  if (bit && (done.load(std::memory_order_acquire) & bit)) return true;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(KERN), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)bytes) != hipSuccess)
+    return false;
+  if (bit) done.fetch_or(bit, std::memory_order_acq_rel);
+  return true;
+}
+
+// Compute units of the current device (256 if the query fails).
+inline int num_cus() {
+  static std::atomic<int> cache[kCachedDevices];
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  const bool cached = dev >= 0 && dev < kCachedDevices;
+  if (cached && (n = cache[dev].load(std::memory_order_relaxed)) > 0) return n;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+  if (cached) cache[dev].store(n, std::memory_order_relaxed);
+  return n;
 }
 
 inline int ipow(int b, int e) {
