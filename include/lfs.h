@@ -25,6 +25,11 @@
  *    fastest), one sample after another: index b*V + site, V = L^dim.  The
  *    lattice is periodic in every direction.
  *  - Site parity is p(n) = (sum_mu n_mu) mod 2 with 0-based coordinates.
+ *  - An empty batch (B == 0, n_chains == 0) is a no-op for the per-sample
+ *    entry points (prior draws, flow forward, action, MH chains, HMC,
+ *    observables): they return LFS_OK after checking the shape arguments and
+ *    read no pointer.  Reductions over the batch (flow backward, the
+ *    log-weights loss, batch-norm batch statistics) reject it with EINVAL.
  *  - Results for sample b depend only on sample b's inputs (never on the batch
  *    size or the sample's position in the batch), except for reductions over
  *    the batch (g_params, loss), which use a fixed order.  All results are
@@ -147,7 +152,10 @@ size_t lfs_param_count(const lfs_flow_desc* desc);
 size_t lfs_bn_stats_count(const lfs_flow_desc* desc);
 
 /* Workspace bytes needed by lfs_flow_forward (for_backward = 0) or
- * lfs_flow_backward (for_backward = 1) at batch size B.  Writes *bytes. */
+ * lfs_flow_backward (for_backward = 1) at batch size B.  Writes *bytes (0 for
+ * B == 0).  The size depends on the current device's compute-unit count.
+ * Errors: EINVAL (desc, B < 0, bytes NULL), EUNSUPPORTED (ALGO_FUSED on a shape
+ * without fused kernels). */
 int32_t lfs_workspace_bytes(const lfs_flow_desc* desc, int32_t B, int32_t for_backward,
                             size_t* bytes);
 
@@ -160,7 +168,7 @@ int32_t lfs_workspace_bytes(const lfs_flow_desc* desc, int32_t B, int32_t for_ba
  * counter (j, lo32(counter0+b), hi32(counter0+b), 0); each output word x maps
  * to u = (floor(x/2^9) + 1/2) 2^-23; words (u0,u1) and (u2,u3) give two
  * Box-Muller pairs r cos(2 pi u_b), r sin(2 pi u_b), r = sqrt(-2 ln u_a).
- * Errors: EINVAL if B <= 0, V <= 0, V % 4 != 0, z == NULL or z not 16-byte
+ * Errors: EINVAL if B < 0, V <= 0, V % 4 != 0, z == NULL or z not 16-byte
  * aligned. */
 int32_t lfs_prior_normal(uint64_t key, uint64_t counter0, int32_t B, int32_t V, float* z,
                          double* logr, void* stream);
@@ -171,7 +179,7 @@ int32_t lfs_prior_normal(uint64_t key, uint64_t counter0, int32_t B, int32_t V, 
  * keys[b] = key, counters[b] = c0 + b).
  *   keys, counters  [B] uint64, device memory
  *   z               [B][V] FP32 output, 16-byte aligned;  logr [B] FP64 or NULL
- * Errors: EINVAL (B <= 0, V <= 0, V % 4 != 0, nulls, misaligned z). */
+ * Errors: EINVAL (B < 0, V <= 0, V % 4 != 0, nulls, misaligned z). */
 int32_t lfs_prior_normal_streams(int32_t B, int32_t V, const uint64_t* keys,
                                  const uint64_t* counters, float* z, double* logr, void* stream);
 
@@ -190,7 +198,7 @@ int32_t lfs_prior_normal_streams(int32_t B, int32_t V, const uint64_t* keys,
  *   saved_x   [(N+1)][B][V] FP32 output or NULL: the field entering each
  *             layer, then phi; required later by lfs_flow_backward
  *   ws        workspace of at least lfs_workspace_bytes(desc, B, 0) bytes
- * Errors: EINVAL (desc, B, nulls, a desc with batch norm), EUNSUPPORTED
+ * Errors: EINVAL (desc, B < 0, nulls, a desc with batch norm), EUNSUPPORTED
  * (hidden), EWORKSPACE. */
 int32_t lfs_flow_forward(const lfs_flow_desc* desc, const float* params, int32_t B,
                          const float* z, float* phi, double* logq, double* logdet,
@@ -209,7 +217,7 @@ int32_t lfs_flow_forward(const lfs_flow_desc* desc, const float* params, int32_t
  *             in a fixed order)
  *   g_z       [B][V] FP32 output or NULL (includes d log r / dz = -z)
  *   ws        workspace of at least lfs_workspace_bytes(desc, B, 1) bytes
- * Errors: as lfs_flow_forward. */
+ * Errors: as lfs_flow_forward, and EINVAL for B == 0 (a batch reduction). */
 int32_t lfs_flow_backward(const lfs_flow_desc* desc, const float* params, int32_t B,
                           const float* saved_x, const float* g_phi, double g_logq,
                           float* g_params, float* g_z, void* ws, size_t ws_bytes, void* stream);
@@ -242,7 +250,8 @@ int32_t lfs_flow_backward_vec(const lfs_flow_desc* desc, const float* params, in
  * Other arguments as lfs_flow_forward.  A desc without batch norm ignores the
  * bn arguments and computes what lfs_flow_forward does.
  * Errors: as lfs_flow_forward; EINVAL also for a bn_mode other than the two,
- * running mode with bn_stats NULL, or momentum outside [0, 1]. */
+ * running mode with bn_stats NULL, momentum outside [0, 1], or B == 0 in batch
+ * mode (B == 0 in running mode is a no-op). */
 int32_t lfs_flow_forward_bn(const lfs_flow_desc* desc, const float* params, int32_t B,
                             const float* z, float* phi, double* logq, double* logdet,
                             float* saved_x, int32_t bn_mode, float* bn_stats, double momentum,
@@ -274,7 +283,7 @@ int32_t lfs_flow_backward_bn(const lfs_flow_desc* desc, const float* params, int
  *              LFS_PLAIN_FP32: in FP32 (stored widened)
  *   S          [B] FP64 output
  *   force      [B][V] FP32 output or NULL
- * Errors: EINVAL (dim not 2/3, L < 2, B <= 0, nulls). */
+ * Errors: EINVAL (dim not 2/3, L < 2, B < 0, nulls). */
 int32_t lfs_action(int32_t dim, int32_t L, int32_t B, const float* phi, const double* m2,
                    const double* lam, int32_t per_sample, int32_t precision, double* S,
                    float* force, double force_scale, void* stream);
@@ -298,7 +307,8 @@ int32_t lfs_log_weights(int32_t B, const double* S, const double* logq, double* 
  *   cur_idx   [n_chains][n_prop] int64 output: global proposal number of the
  *             chain's configuration after each proposal
  *   accepted  [n_chains][n_prop] uint8 output, or NULL
- * Errors: EINVAL (n_chains <= 0, n_prop <= 0, nulls). */
+ * n_chains == 0 or n_prop == 0 is a no-op.
+ * Errors: EINVAL (n_chains < 0, n_prop < 0, nulls). */
 int32_t lfs_mh_chain(int32_t n_chains, int32_t n_prop, const double* logw, const double* log_u,
                      lfs_chain_state* state, int64_t* cur_idx, uint8_t* accepted, void* stream);
 
@@ -309,7 +319,7 @@ int32_t lfs_mh_chain(int32_t n_chains, int32_t n_prop, const double* logw, const
  * Used by the server, where one batch holds chunks of several requests.
  *   offsets      [n_chains + 1] int64, non-decreasing, offsets[0] >= 0
  *   state_index  [n_chains] int32, distinct
- * Errors: EINVAL (n_chains <= 0, nulls). */
+ * Errors: EINVAL (n_chains < 0, nulls). */
 int32_t lfs_mh_chain_ragged(int32_t n_chains, const int64_t* offsets, const double* logw,
                             const double* log_u, lfs_chain_state* states,
                             const int32_t* state_index, int64_t* cur_idx, uint8_t* accepted,
@@ -324,7 +334,7 @@ int32_t lfs_mh_chain_ragged(int32_t n_chains, const int64_t* offsets, const doub
  *   log_u     [B] FP64
  *   m2, lam   FP64, [B] if per_sample else [1]
  *   dH        [B] FP64 output;  accepted [B] uint8 output
- * Errors: EINVAL (shape, n_steps < 0, nulls); EUNSUPPORTED if V > 4096. */
+ * Errors: EINVAL (shape, B < 0, n_steps < 0, nulls); EUNSUPPORTED if V > 4096. */
 int32_t lfs_hmc_step(int32_t dim, int32_t L, int32_t B, double* phi, const double* pi0,
                      const double* log_u, const double* m2, const double* lam, int32_t per_sample,
                      int32_t n_steps, double dt, double* dH, uint8_t* accepted, void* stream);

@@ -149,10 +149,12 @@ extern "C" int32_t lfs_action(int32_t dim, int32_t L, int32_t B, const float* ph
                               const double* lam, int32_t per_sample, int32_t precision, double* S,
                               float* force, double force_scale, void* stream) {
   LFS_RETURN_IF(dim != 2 && dim != 3, LFS_EINVAL);
-  LFS_RETURN_IF(L < 2 || B <= 0 || !phi || !m2 || !lam || !S, LFS_EINVAL);
+  LFS_RETURN_IF(L < 2 || B < 0, LFS_EINVAL);
   LFS_RETURN_IF(precision != LFS_PLAIN_FP32 && precision != LFS_BF16_CONV, LFS_EINVAL);
   const long V = dim == 2 ? (long)L * L : (long)L * L * L;
   LFS_RETURN_IF(V > 16384, LFS_EUNSUPPORTED);
+  if (B == 0) return LFS_OK;
+  LFS_RETURN_IF(!phi || !m2 || !lam || !S, LFS_EINVAL);
   const size_t shm = (size_t)V * sizeof(float);
   hipStream_t st = (hipStream_t)stream;
   const bool f64 = precision == LFS_BF16_CONV;

@@ -170,7 +170,9 @@ __global__ void k_adam(int64_t n, float* __restrict__ p, const float* __restrict
 extern "C" int32_t lfs_mh_chain(int32_t n_chains, int32_t n_prop, const double* logw,
                                 const double* log_u, lfs_chain_state* state, int64_t* cur_idx,
                                 uint8_t* accepted, void* stream) {
-  LFS_RETURN_IF(n_chains <= 0 || n_prop <= 0 || !logw || !log_u || !state || !cur_idx, LFS_EINVAL);
+  LFS_RETURN_IF(n_chains < 0 || n_prop < 0, LFS_EINVAL);
+  if (n_chains == 0 || n_prop == 0) return LFS_OK;
+  LFS_RETURN_IF(!logw || !log_u || !state || !cur_idx, LFS_EINVAL);
   hipLaunchKernelGGL(lfs::k_mh_chain, dim3(n_chains), dim3(lfs::kWave), 0, (hipStream_t)stream,
                      n_prop, nullptr, logw, log_u, state, nullptr, cur_idx, accepted);
   return lfs::launch_status();
@@ -180,8 +182,9 @@ extern "C" int32_t lfs_mh_chain_ragged(int32_t n_chains, const int64_t* offsets,
                                        const double* log_u, lfs_chain_state* states,
                                        const int32_t* state_index, int64_t* cur_idx,
                                        uint8_t* accepted, void* stream) {
-  LFS_RETURN_IF(n_chains <= 0 || !offsets || !logw || !log_u || !states || !state_index || !cur_idx,
-                LFS_EINVAL);
+  LFS_RETURN_IF(n_chains < 0, LFS_EINVAL);
+  if (n_chains == 0) return LFS_OK;
+  LFS_RETURN_IF(!offsets || !logw || !log_u || !states || !state_index || !cur_idx, LFS_EINVAL);
   hipLaunchKernelGGL(lfs::k_mh_chain, dim3(n_chains), dim3(lfs::kWave), 0, (hipStream_t)stream, 0,
                      offsets, logw, log_u, states, state_index, cur_idx, accepted);
   return lfs::launch_status();
@@ -192,10 +195,11 @@ extern "C" int32_t lfs_hmc_step(int32_t dim, int32_t L, int32_t B, double* phi, 
                                 int32_t per_sample, int32_t n_steps, double dt, double* dH,
                                 uint8_t* accepted, void* stream) {
   LFS_RETURN_IF(dim != 2 && dim != 3, LFS_EINVAL);
-  LFS_RETURN_IF(L < 2 || B <= 0 || n_steps < 0, LFS_EINVAL);
-  LFS_RETURN_IF(!phi || !pi0 || !log_u || !m2 || !lam || !dH || !accepted, LFS_EINVAL);
+  LFS_RETURN_IF(L < 2 || B < 0 || n_steps < 0, LFS_EINVAL);
   const long V = dim == 2 ? (long)L * L : (long)L * L * L;
   LFS_RETURN_IF(V > 4096, LFS_EUNSUPPORTED);  // phi and pi in at most 64 KB of LDS
+  if (B == 0) return LFS_OK;
+  LFS_RETURN_IF(!phi || !pi0 || !log_u || !m2 || !lam || !dH || !accepted, LFS_EINVAL);
   const size_t shm = 2 * (size_t)V * sizeof(double);
   hipStream_t st = (hipStream_t)stream;
   if (dim == 2)

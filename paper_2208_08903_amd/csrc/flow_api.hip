@@ -133,9 +133,9 @@ extern "C" int32_t lfs_workspace_bytes(const lfs_flow_desc* desc, int32_t B, int
   lfs::FlowGeom g;
   const int32_t s = lfs::make_geom(desc, &g);
   if (s != LFS_OK) return s;
-  if (B <= 0 || !bytes) return LFS_EINVAL;
+  if (B < 0 || !bytes) return LFS_EINVAL;
   if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_ok(g, for_backward)) return LFS_EUNSUPPORTED;
-  *bytes = lfs::ws_bytes_of(g, B, for_backward);
+  *bytes = B == 0 ? 0 : lfs::ws_bytes_of(g, B, for_backward);
   return LFS_OK;
 }
 
@@ -145,8 +145,10 @@ extern "C" int32_t lfs_flow_forward(const lfs_flow_desc* desc, const float* para
   lfs::FlowGeom g;
   const int32_t s = lfs::make_geom(desc, &g);
   if (s != LFS_OK) return s;
-  if (B <= 0 || !params || !z || !phi || !logq || g.bn) return LFS_EINVAL;
+  if (B < 0 || g.bn) return LFS_EINVAL;
   if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_ok(g, 0)) return LFS_EUNSUPPORTED;
+  if (B == 0) return LFS_OK;
+  if (!params || !z || !phi || !logq) return LFS_EINVAL;
   const size_t need = lfs::ws_bytes_of(g, B, 0);
   if (need > 0 && (!ws || ws_bytes < need)) return LFS_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
@@ -221,11 +223,13 @@ extern "C" int32_t lfs_flow_forward_bn(const lfs_flow_desc* desc, const float* p
   const int32_t s = lfs::make_geom(desc, &g);
   if (s != LFS_OK) return s;
   if (!g.bn) return lfs_flow_forward(desc, params, B, z, phi, logq, logdet, saved_x, ws, ws_bytes, stream);
-  if (B <= 0 || !params || !z || !phi || !logq) return LFS_EINVAL;
+  if (B < 0 || (B == 0 && bn_mode == LFS_BN_BATCH)) return LFS_EINVAL;  // no statistics of nothing
   if (bn_mode != LFS_BN_BATCH && bn_mode != LFS_BN_RUNNING) return LFS_EINVAL;
-  if (bn_mode == LFS_BN_RUNNING && !bn_stats) return LFS_EINVAL;
   if (!(momentum >= 0.0 && momentum <= 1.0)) return LFS_EINVAL;
   if (desc->algo == LFS_ALGO_FUSED) return LFS_EUNSUPPORTED;
+  if (B == 0) return LFS_OK;
+  if (!params || !z || !phi || !logq) return LFS_EINVAL;
+  if (bn_mode == LFS_BN_RUNNING && !bn_stats) return LFS_EINVAL;
   const size_t need = lfs::net_ws_bytes(g, B, 0);
   if (!ws || ws_bytes < need) return LFS_EWORKSPACE;
   return lfs::net_forward_bn(g, params, B, z, phi, logq, logdet, saved_x, bn_mode, bn_stats,

@@ -73,8 +73,9 @@ __global__ void __launch_bounds__(256) k_prior(uint32_t key0_, uint32_t key1_, u
 
 extern "C" int32_t lfs_prior_normal(uint64_t key, uint64_t counter0, int32_t B, int32_t V, float* z,
                                     double* logr, void* stream) {
-  LFS_RETURN_IF(B <= 0 || V <= 0 || (V % 4) != 0 || z == nullptr, LFS_EINVAL);
-  LFS_RETURN_IF(((uintptr_t)z & 15u) != 0, LFS_EINVAL);  // float4 stores
+  LFS_RETURN_IF(B < 0 || V <= 0 || (V % 4) != 0, LFS_EINVAL);
+  if (B == 0) return LFS_OK;
+  LFS_RETURN_IF(z == nullptr || ((uintptr_t)z & 15u) != 0, LFS_EINVAL);  // float4 stores
   hipLaunchKernelGGL(lfs::k_prior, dim3(B), dim3(256), 0, (hipStream_t)stream, (uint32_t)key,
                      (uint32_t)(key >> 32), counter0, nullptr, nullptr, V, z, logr);
   return lfs::launch_status();
@@ -83,8 +84,9 @@ extern "C" int32_t lfs_prior_normal(uint64_t key, uint64_t counter0, int32_t B, 
 extern "C" int32_t lfs_prior_normal_streams(int32_t B, int32_t V, const uint64_t* keys,
                                             const uint64_t* counters, float* z, double* logr,
                                             void* stream) {
-  LFS_RETURN_IF(B <= 0 || V <= 0 || (V % 4) != 0 || !z || !keys || !counters, LFS_EINVAL);
-  LFS_RETURN_IF(((uintptr_t)z & 15u) != 0, LFS_EINVAL);
+  LFS_RETURN_IF(B < 0 || V <= 0 || (V % 4) != 0, LFS_EINVAL);
+  if (B == 0) return LFS_OK;
+  LFS_RETURN_IF(!z || !keys || !counters || ((uintptr_t)z & 15u) != 0, LFS_EINVAL);
   hipLaunchKernelGGL(lfs::k_prior, dim3(B), dim3(256), 0, (hipStream_t)stream, 0u, 0u, 0ull, keys,
                      counters, V, z, logr);
   return lfs::launch_status();

@@ -120,6 +120,49 @@ def test_descriptor_validation(kw, code):
     assert lfs.param_count(d) == 0
 
 
+def test_empty_batches():
+    """B == 0 is a no-op (LFS_OK, no pointer read) for the per-sample entry points and an
+    error for the reductions over the batch; negative sizes are errors everywhere."""
+    lib = lfs.load()
+    d = lfs.make_desc(2, 8, 4, 8)
+    out = ctypes.c_size_t(7)
+    assert lib.lfs_workspace_bytes(ctypes.byref(d), 0, 0, ctypes.byref(out)) == 0 and out.value == 0
+    assert lib.lfs_workspace_bytes(ctypes.byref(d), -1, 0, ctypes.byref(out)) == -1
+    assert lib.lfs_prior_normal(1, 0, 0, 64, None, None, None) == 0
+    assert lib.lfs_prior_normal(1, 0, -1, 64, None, None, None) == -1
+    assert lib.lfs_prior_normal(1, 0, 0, 6, None, None, None) == -1           # V % 4 still checked
+    assert lib.lfs_prior_normal_streams(0, 64, None, None, None, None, None) == 0
+    assert lib.lfs_flow_forward(ctypes.byref(d), None, 0, None, None, None, None, None, None, 0,
+                                None) == 0
+    assert lib.lfs_flow_forward(ctypes.byref(d), None, -1, None, None, None, None, None, None, 0,
+                                None) == -1
+    bad = lfs.make_desc(2, 8, 4, 8)
+    bad.L = 7
+    assert lib.lfs_flow_forward(ctypes.byref(bad), None, 0, None, None, None, None, None, None, 0,
+                                None) == -1                                   # desc still checked
+    assert lib.lfs_flow_backward(ctypes.byref(d), None, 0, None, None, 0.25, None, None, None, 0,
+                                 None) == -1                                  # batch reduction
+    bn = lfs.make_desc(2, 8, 2, 0, kernel=3, hidden_sizes=(8, 8), batch_norm=True)
+    fwd = lib.lfs_flow_forward_bn
+    assert fwd(ctypes.byref(bn), None, 0, None, None, None, None, None, lfs.BN_RUNNING, None, 0.0,
+               None, 0, None) == 0
+    assert fwd(ctypes.byref(bn), None, 0, None, None, None, None, None, lfs.BN_BATCH, None, 0.1,
+               None, 0, None) == -1                                           # no statistics
+    assert lib.lfs_action(2, 8, 0, None, None, None, 0, 1, None, None, 1.0, None) == 0
+    assert lib.lfs_action(2, 8, -2, None, None, None, 0, 1, None, None, 1.0, None) == -1
+    assert lib.lfs_action(2, 256, 0, None, None, None, 0, 1, None, None, 1.0, None) == -2  # V
+    assert lib.lfs_log_weights(0, None, None, None, None, None) == -1
+    assert lib.lfs_mh_chain(0, 10, None, None, None, None, None, None) == 0
+    assert lib.lfs_mh_chain(3, 0, None, None, None, None, None, None) == 0
+    assert lib.lfs_mh_chain(-1, 10, None, None, None, None, None, None) == -1
+    assert lib.lfs_mh_chain_ragged(0, None, None, None, None, None, None, None, None) == 0
+    assert lib.lfs_mh_chain_ragged(-1, None, None, None, None, None, None, None, None) == -1
+    assert lib.lfs_hmc_step(2, 8, 0, None, None, None, None, None, 0, 10, 0.1, None, None,
+                            None) == 0
+    assert lib.lfs_hmc_step(3, 20, 0, None, None, None, None, None, 0, 10, 0.1, None, None,
+                            None) == -2                                       # V > 4096
+
+
 def test_null_and_shape_arguments_rejected_before_any_launch():
     lib = lfs.load()
     d = lfs.make_desc(2, 8, 4, 8)
@@ -137,7 +180,7 @@ def test_null_and_shape_arguments_rejected_before_any_launch():
     assert lib.lfs_action(4, 8, 4, None, None, None, 0, 1, None, None, 1.0, None) == -1
     assert lib.lfs_action(2, 256, 4, 1, 1, 1, 0, 1, 1, None, 1.0, None) == -2  # V too large
     assert lib.lfs_log_weights(0, None, None, None, None, None) == -1
-    assert lib.lfs_mh_chain(1, 0, None, None, None, None, None, None) == -1
+    assert lib.lfs_mh_chain(1, 5, None, None, None, None, None, None) == -1   # nulls
     assert lib.lfs_hmc_step(2, 8, 4, None, None, None, None, None, 0, -1, 0.1, None, None,
                             None) == -1
     assert lib.lfs_hmc_step(3, 20, 1, 1, 1, 1, 1, 1, 0, 10, 0.1, 1, 1, None) == -2  # V > 4096
