@@ -38,7 +38,11 @@ struct RingCfg {
   static constexpr int ZS = 3 * PS;  // all-zero site after the three planes
   static constexpr size_t RING = (3 * (size_t)PS + 1) * C * sizeof(HElem<BF16>);
   static constexpr size_t lds_bytes = XS_BYTES + 2 * RING;
-  static constexpr int NT = 256;
+  // Two output-channel tiles (C = 32): eight waves, four per tile, so that a
+  // wave holds one tile's conv1/conv2 fragments and conv3's are fetched per
+  // chunk; the registers then admit two waves per SIMD instead of one.
+  static constexpr int NT = LF.nct == 2 ? 512 : 256;
+  static constexpr bool A3_HELD = LF.nct == 1;
 };
 
 __device__ __forceinline__ int mod3(int v) { return ((v % 3) + 3) % 3; }
@@ -73,6 +77,8 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
   constexpr int V = Cfg::V, PLANE = L * L, PS = Cfg::PS;
   constexpr LayerFrags LF = Cfg::LF;
   constexpr int NW = NT / 64;
+  constexpr int WPC = NW / LF.nct;  // waves per output-channel tile
+  static_assert(NW % LF.nct == 0, "waves split evenly over the channel tiles");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ R red[16];
   float* xs = reinterpret_cast<float*>(smem);
@@ -80,6 +86,8 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
   HT* r2 = r1 + (3 * PS + 1) * C;
   for (int q = threadIdx.x; q < C; q += NT) r1[Cfg::ZS * C + q] = HT(0), r2[Cfg::ZS * C + q] = HT(0);
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
+  // this wave's channel tile and its index among that tile's waves
+  const int ct = LF.nct == 1 ? 0 : w / WPC, wc = LF.nct == 1 ? w : w % WPC;
   const size_t BV = (size_t)B * V;
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
@@ -98,58 +106,41 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
       const int fpar = (layer + parity0) & 1, apar = fpar ^ 1;
       const u32x4* fl = frags + (size_t)layer * LF.total * 64 + lane;
       const float* pl = params + (size_t)layer * P_layer;
-      u32x4 A1[LF.nct][LF.k1], A2[LF.nct][LF.k2], A3[LF.k2];
-      f32x4 bias1[LF.nct], bias2[LF.nct];
+      u32x4 A1[LF.k1], A2[LF.k2], A3[Cfg::A3_HELD ? LF.k2 : 1];
+      const f32x4 bias1 = load_bias4<C>(pl + off_b1, ct, j), bias2 = load_bias4<C>(pl + off_b2, ct, j);
 #pragma unroll
-      for (int ct = 0; ct < LF.nct; ++ct) {
-        bias1[ct] = load_bias4<C>(pl + off_b1, ct, j);
-        bias2[ct] = load_bias4<C>(pl + off_b2, ct, j);
+      for (int c = 0; c < LF.k1; ++c) A1[c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
 #pragma unroll
-        for (int c = 0; c < LF.k1; ++c) A1[ct][c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
+      for (int c = 0; c < LF.k2; ++c) A2[c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
+      if constexpr (Cfg::A3_HELD) {
 #pragma unroll
-        for (int c = 0; c < LF.k2; ++c) A2[ct][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
+        for (int c = 0; c < LF.k2; ++c) A3[c] = fl[(LF.off3 + c) * 64];
       }
-#pragma unroll
-      for (int c = 0; c < LF.k2; ++c) A3[c] = fl[(LF.off3 + c) * 64];
       const float bs = pl[off_b3], bt = pl[off_b3 + 1];
 
       // h1 of virtual plane v into ring slot v mod 3
       auto conv1_plane = [&](int v) {
         const int zr = ((v % L) + L) % L;
         HT* dst = r1 + mod3(v) * PS * C;
-        for (int tile = w; tile < PLANE / 16; tile += NW) {
+        for (int tile = wc; tile < PLANE / 16; tile += WPC) {
           const int q = tile * 16 + m, n = zr * PLANE + q;
           const int p = LX::idx(n), pn = G::parity(n);
-          f32x4 acc[LF.nct];
+          f32x4 acc{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int c = 0; c < LF.k1; ++c) {
-            const u32x4 bop = gather_tri_x<LX, BF16>(xs, n, p, pn, fpar, c, j);
-#pragma unroll
-            for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A1[ct][c], bop, acc[ct]);
-          }
-#pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) store_hidden<LP2, C, BF16>(dst, q, ct, j, acc[ct], bias1[ct]);
+          for (int c = 0; c < LF.k1; ++c) acc = mma<BF16>(A1[c], gather_tri_x<LX, BF16>(xs, n, p, pn, fpar, c, j), acc);
+          store_hidden<LP2, C, BF16>(dst, q, ct, j, acc, bias1);
         }
       };
       // h2 of virtual plane v from h1 planes v-1, v, v+1
       auto conv2_plane = [&](int v) {
         HT* dst = r2 + mod3(v) * PS * C;
         const int sm = mod3(v - 1), s0 = mod3(v), sp = mod3(v + 1);
-        for (int tile = w; tile < PLANE / 16; tile += NW) {
+        for (int tile = wc; tile < PLANE / 16; tile += WPC) {
           const int q = tile * 16 + m, pq = tile_p<LP2>(tile, m);
-          f32x4 acc[LF.nct];
+          f32x4 acc{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int c = 0; c < LF.k2; ++c) {
-            const u32x4 bop = gather_ring<L, C, BF16>(r1, pq, sm, s0, sp, c, j);
-#pragma unroll
-            for (int ct = 0; ct < LF.nct; ++ct) acc[ct] = mma<BF16>(A2[ct][c], bop, acc[ct]);
-          }
-#pragma unroll
-          for (int ct = 0; ct < LF.nct; ++ct) store_hidden<LP2, C, BF16>(dst, q, ct, j, acc[ct], bias2[ct]);
+          for (int c = 0; c < LF.k2; ++c) acc = mma<BF16>(A2[c], gather_ring<L, C, BF16>(r1, pq, sm, s0, sp, c, j), acc);
+          store_hidden<LP2, C, BF16>(dst, q, ct, j, acc, bias2);
         }
       };
       // conv3 of h2 planes z-1, z, z+1 at the active sites of plane z; affine update
@@ -159,9 +150,16 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
         for (int tile = w; tile < PLANE / 32; tile += NW) {
           const int q = Geo<2, L>::half_site(tile * 16 + m, ppar), pq = LP2::idx(q);
           f32x4 acc{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int c = 0; c < LF.k2; ++c)
-            acc = mma<BF16>(A3[c], gather_ring<L, C, BF16>(r2, pq, sm, s0, sp, c, j), acc);
+          // fetched fragments: a few chunks in flight at a time, not all 27
+#pragma unroll Cfg::A3_HELD ? LF.k2 : 3
+          for (int c = 0; c < LF.k2; ++c) {
+            u32x4 a3;
+            if constexpr (Cfg::A3_HELD)
+              a3 = A3[c];
+            else
+              a3 = fl[(LF.off3 + c) * 64];  // L2-resident, shared by every workgroup
+            acc = mma<BF16>(a3, gather_ring<L, C, BF16>(r2, pq, sm, s0, sp, c, j), acc);
+          }
           if (j == 0) {
             const int n = zr * PLANE + q;
             const float o0 = acc[0] + bs, t = acc[1] + bt;
