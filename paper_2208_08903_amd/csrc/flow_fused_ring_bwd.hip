@@ -59,7 +59,11 @@ struct RbCfg {
   // same site hit different LDS banks.
   static constexpr int CS = PLANE + 8;
   static constexpr size_t LDS_C = (6 * (size_t)C * CS + 3 * 2 * (size_t)CS + 3 * (size_t)PLANE) * 2;
-  static constexpr int NT_A = 256, NT_B = 256, NT_C = 512;
+  // recompute with two output-channel tiles (C = 32): eight waves, four per tile,
+  // each holding one tile's conv1/conv2 fragments, conv3's fetched per chunk, so
+  // that two waves fit per SIMD
+  static constexpr int NT_A = LF.nct == 2 ? 512 : 256, NT_B = 256, NT_C = 512;
+  static constexpr bool A3_HELD = LF.nct == 1;
   // weight-gradient GEMM tiles (16 x 16): rows are channels, columns (tap, channel)
   static constexpr int RT = C / 16;
   static constexpr int N2 = RT * (T * C / 16), N3 = RT * 4, N1 = RT * 2;
@@ -174,22 +178,29 @@ __global__ void __launch_bounds__(NT) kr_recompute(
   uint16_t* r2 = r1 + Cfg::RING;
   for (int q = threadIdx.x; q < C; q += NT) r1[Cfg::ZS * C + q] = 0, r2[Cfg::ZS * C + q] = 0;
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
+  constexpr int WPC = NW / LF.nct;  // waves per output-channel tile
+  static_assert(NW % LF.nct == 0, "waves split evenly over the channel tiles");
+  // this wave's channel tile and its index among that tile's waves
+  const int ct = LF.nct == 1 ? 0 : w / WPC, wc = LF.nct == 1 ? w : w % WPC;
   const int apar = fpar ^ 1;
   const u32x4* fl = frags + lane;
-  u32x4 A1[LF.nct][LF.k1], A2[LF.nct][LF.k2], A3[1][LF.k2];
-  f32x4 bias1[LF.nct], bias2[LF.nct];
+  u32x4 A1[1][LF.k1], A2[1][LF.k2], A3[Cfg::A3_HELD ? LF.k2 : 1];
+  const f32x4 bias1[1] = {load_bias4<C>(pl + off_b1, ct, j)}, bias2[1] = {load_bias4<C>(pl + off_b2, ct, j)};
 #pragma unroll
-  for (int ct = 0; ct < LF.nct; ++ct) {
-    bias1[ct] = load_bias4<C>(pl + off_b1, ct, j);
-    bias2[ct] = load_bias4<C>(pl + off_b2, ct, j);
+  for (int c = 0; c < LF.k1; ++c) A1[0][c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
 #pragma unroll
-    for (int c = 0; c < LF.k1; ++c) A1[ct][c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
+  for (int c = 0; c < LF.k2; ++c) A2[0][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
+  if constexpr (Cfg::A3_HELD) {
 #pragma unroll
-    for (int c = 0; c < LF.k2; ++c) A2[ct][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
+    for (int c = 0; c < LF.k2; ++c) A3[c] = fl[(LF.off3 + c) * 64];
   }
-#pragma unroll
-  for (int c = 0; c < LF.k2; ++c) A3[0][c] = fl[(LF.off3 + c) * 64];
-  const f32x4 b3[1] = {f32x4{pl[off_b3], 0.f, 0.f, 0.f}};
+  // one channel tile's sign bits of a site: the whole mask word, or its half
+  auto store_mask = [&](uint32_t* mk, size_t n, uint32_t mw) {
+    if constexpr (LF.nct == 1)
+      mk[n] = mw;
+    else
+      reinterpret_cast<uint16_t*>(mk)[2 * n + ct] = (uint16_t)mw;  // little-endian: tile ct's 16 bits
+  };
   float db3s = 0.f, db3t = 0.f;
   // the previous launch's (next layer's) weight gradient; every kernel of a layer
   // runs on the same grid, so that is also the number of partials
@@ -210,21 +221,17 @@ __global__ void __launch_bounds__(NT) kr_recompute(
       const int zr = ((v % L) + L) % L;
       const bool real = v >= 0 && v < L;
       uint16_t* dst = r1 + mod3(v) * PS * C;
-      mma_tiles<1, LF.nct, LF.k1, true>(
-          PLANE / 16, w, NW, A1, bias1,
+      mma_tiles<1, 1, LF.k1, true>(
+          PLANE / 16, wc, WPC, A1, bias1,
           [&](int tile, int c) {
             const int n = zr * PLANE + tile * 16 + m;
             return gather_tri_x<LX, true>(xs, n, LX::idx(n), G::parity(n), fpar, c, j);
           },
-          [&](int tile, const f32x4(&acc)[LF.nct]) {
-            uint32_t mw = 0u;
-#pragma unroll
-            for (int ct = 0; ct < LF.nct; ++ct) {
-              const u32x2 hv = store_act_tile<LP2, C, true>(dst, tile, m, ct, j, acc[ct]);
-              if (real) store_cm_global<C, V>(h1b, zr * PLANE + tile * 16 + m, ct * 16 + 4 * j, hv);
-              mw |= sign_mask16(hv, j) << (16 * ct);
-            }
-            if (real && j == 0) m1[sb + zr * PLANE + tile * 16 + m] = mw;
+          [&](int tile, const f32x4(&acc)[1]) {
+            const u32x2 hv = store_act_tile<LP2, C, true>(dst, tile, m, ct, j, acc[0]);
+            if (real) store_cm_global<C, V>(h1b, zr * PLANE + tile * 16 + m, ct * 16 + 4 * j, hv);
+            const uint32_t mw = sign_mask16(hv, j);
+            if (real && j == 0) store_mask(m1, sb + zr * PLANE + tile * 16 + m, mw);
           });
     };
     // h2 of virtual plane v from h1 planes v-1, v, v+1
@@ -233,45 +240,47 @@ __global__ void __launch_bounds__(NT) kr_recompute(
       const bool real = v >= 0 && v < L;
       uint16_t* dst = r2 + mod3(v) * PS * C;
       const int sm = mod3(v - 1), s0 = mod3(v), sp = mod3(v + 1);
-      mma_tiles<1, LF.nct, LF.k2, true>(
-          PLANE / 16, w, NW, A2, bias2,
+      mma_tiles<1, 1, LF.k2, true>(
+          PLANE / 16, wc, WPC, A2, bias2,
           [&](int tile, int c) { return gather_rb<L, C, 1>(r1, tile_p<LP2>(tile, m), sm, s0, sp, c, j); },
-          [&](int tile, const f32x4(&acc)[LF.nct]) {
-            uint32_t mw = 0u;
-#pragma unroll
-            for (int ct = 0; ct < LF.nct; ++ct) {
-              const u32x2 hv = store_act_tile<LP2, C, true>(dst, tile, m, ct, j, acc[ct]);
-              if (real) store_cm_global<C, V>(h2b, zr * PLANE + tile * 16 + m, ct * 16 + 4 * j, hv);
-              mw |= sign_mask16(hv, j) << (16 * ct);
-            }
-            if (real && j == 0) m2[sb + zr * PLANE + tile * 16 + m] = mw;
+          [&](int tile, const f32x4(&acc)[1]) {
+            const u32x2 hv = store_act_tile<LP2, C, true>(dst, tile, m, ct, j, acc[0]);
+            if (real) store_cm_global<C, V>(h2b, zr * PLANE + tile * 16 + m, ct * 16 + 4 * j, hv);
+            const uint32_t mw = sign_mask16(hv, j);
+            if (real && j == 0) store_mask(m2, sb + zr * PLANE + tile * 16 + m, mw);
           });
     };
     // s at the active sites of plane zr; g_x there, g_o of the whole plane
     auto conv3_plane = [&](int zr) {
       const int sm = mod3(zr - 1), s0 = mod3(zr), sp = mod3(zr + 1);
       const int ppar = apar ^ (zr & 1);  // in-plane parity of the active sites
-      mma_tiles<1, 1, LF.k2, true>(
-          PLANE / 32, w, NW, A3, b3,
-          [&](int tile, int c) {
-            const int q = Geo<2, L>::half_site(tile * 16 + m, ppar);
-            return gather_rb<L, C, 1>(r2, LP2::idx(q), sm, s0, sp, c, j);
-          },
-          [&](int tile, const f32x4(&acc)[1]) {
-            if (j == 0) {
-              const int n = zr * PLANE + Geo<2, L>::half_site(tile * 16 + m, ppar);
-              const float o0 = acc[0][0];
-              const float s = final_tanh ? fast_tanh(o0) : o0;
-              const float es = fast_exp(s);
-              const float g = gys[zr & 1][n - zr * PLANE];
-              const float gs = g * xs[LX::idx(n)] * es + gld;
-              const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
-              db3s += go0;
-              db3t += g;
-              gx[sb + n] = g * es;
-              go[sb + n] = pack_bf16(go0, g);
-            }
-          });
+      for (int tile = w; tile < PLANE / 32; tile += NW) {
+        const int q3 = LP2::idx(Geo<2, L>::half_site(tile * 16 + m, ppar));
+        f32x4 acc[1] = {f32x4{pl[off_b3], 0.f, 0.f, 0.f}};
+        // fetched fragments: a few chunks in flight at a time, not all 27
+#pragma unroll Cfg::A3_HELD ? LF.k2 : 3
+        for (int c = 0; c < LF.k2; ++c) {
+          u32x4 a3;
+          if constexpr (Cfg::A3_HELD)
+            a3 = A3[c];
+          else
+            a3 = fl[(LF.off3 + c) * 64];  // L2-resident, shared by every workgroup
+          acc[0] = mma<true>(a3, gather_rb<L, C, 1>(r2, q3, sm, s0, sp, c, j), acc[0]);
+        }
+        if (j == 0) {
+          const int n = zr * PLANE + Geo<2, L>::half_site(tile * 16 + m, ppar);
+          const float o0 = acc[0][0];
+          const float s = final_tanh ? fast_tanh(o0) : o0;
+          const float es = fast_exp(s);
+          const float g = gys[zr & 1][n - zr * PLANE];
+          const float gs = g * xs[LX::idx(n)] * es + gld;
+          const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
+          db3s += go0;
+          db3t += g;
+          gx[sb + n] = g * es;
+          go[sb + n] = pack_bf16(go0, g);
+        }
+      }
       for (int i = threadIdx.x; i < PLANE / 2; i += NT)
         go[sb + zr * PLANE + Geo<2, L>::half_site(i, ppar ^ 1)] = 0u;
     };
