@@ -59,11 +59,13 @@ struct RbCfg {
   // same site hit different LDS banks.
   static constexpr int CS = PLANE + 8;
   static constexpr size_t LDS_C = (6 * (size_t)C * CS + 3 * 2 * (size_t)CS + 3 * (size_t)PLANE) * 2;
-  // recompute with two output-channel tiles (C = 32): eight waves, four per tile,
-  // each holding one tile's conv1/conv2 fragments, conv3's fetched per chunk, so
-  // that two waves fit per SIMD
-  static constexpr int NT_A = LF.nct == 2 ? 512 : 256, NT_B = 256, NT_C = 512;
-  static constexpr bool A3_HELD = LF.nct == 1;
+  // recompute and transpose with two output-channel tiles (C = 32): eight waves,
+  // four per tile, each holding one tile's fragments of the C-output
+  // convolutions; the narrow one (conv3, or conv1 transposed: 2 or 1 outputs)
+  // fetches its fragments per chunk instead of holding them, so that two waves
+  // fit per SIMD
+  static constexpr int NT_A = LF.nct == 2 ? 512 : 256, NT_B = NT_A, NT_C = 512;
+  static constexpr bool NARROW_HELD = LF.nct == 1;
   // weight-gradient GEMM tiles (16 x 16): rows are channels, columns (tap, channel)
   static constexpr int RT = C / 16;
   static constexpr int N2 = RT * (T * C / 16), N3 = RT * 4, N1 = RT * 2;
@@ -184,13 +186,13 @@ __global__ void __launch_bounds__(NT) kr_recompute(
   const int ct = LF.nct == 1 ? 0 : w / WPC, wc = LF.nct == 1 ? w : w % WPC;
   const int apar = fpar ^ 1;
   const u32x4* fl = frags + lane;
-  u32x4 A1[1][LF.k1], A2[1][LF.k2], A3[Cfg::A3_HELD ? LF.k2 : 1];
+  u32x4 A1[1][LF.k1], A2[1][LF.k2], A3[Cfg::NARROW_HELD ? LF.k2 : 1];
   const f32x4 bias1[1] = {load_bias4<C>(pl + off_b1, ct, j)}, bias2[1] = {load_bias4<C>(pl + off_b2, ct, j)};
 #pragma unroll
   for (int c = 0; c < LF.k1; ++c) A1[0][c] = fl[(LF.off1 + ct * LF.k1 + c) * 64];
 #pragma unroll
   for (int c = 0; c < LF.k2; ++c) A2[0][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
-  if constexpr (Cfg::A3_HELD) {
+  if constexpr (Cfg::NARROW_HELD) {
 #pragma unroll
     for (int c = 0; c < LF.k2; ++c) A3[c] = fl[(LF.off3 + c) * 64];
   }
@@ -258,10 +260,10 @@ __global__ void __launch_bounds__(NT) kr_recompute(
         const int q3 = LP2::idx(Geo<2, L>::half_site(tile * 16 + m, ppar));
         f32x4 acc[1] = {f32x4{pl[off_b3], 0.f, 0.f, 0.f}};
         // fetched fragments: a few chunks in flight at a time, not all 27
-#pragma unroll Cfg::A3_HELD ? LF.k2 : 3
+#pragma unroll Cfg::NARROW_HELD ? LF.k2 : 3
         for (int c = 0; c < LF.k2; ++c) {
           u32x4 a3;
-          if constexpr (Cfg::A3_HELD)
+          if constexpr (Cfg::NARROW_HELD)
             a3 = A3[c];
           else
             a3 = fl[(LF.off3 + c) * 64];  // L2-resident, shared by every workgroup
@@ -342,22 +344,22 @@ __global__ void __launch_bounds__(NT) kr_transpose(
   if (threadIdx.x == 0) gor[Cfg::ZS] = 0u;
   for (int q = threadIdx.x; q < C; q += NT) ra2[Cfg::ZS * C + q] = 0, ra1[Cfg::ZS * C + q] = 0;
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
+  constexpr int WPC = NW / NCT;  // waves per output-channel tile
+  static_assert(NW % NCT == 0, "waves split evenly over the channel tiles");
+  // this wave's channel tile and its index among that tile's waves
+  const int ct = NCT == 1 ? 0 : w / WPC, wc = NCT == 1 ? w : w % WPC;
   const u32x4* fl = frags + lane;
-  u32x4 A3T[NCT][KT3], A2T[NCT][LF.k2], A1T[1][LF.k2];
+  u32x4 A3T[1][KT3], A2T[1][LF.k2], A1T[Cfg::NARROW_HELD ? LF.k2 : 1];
 #pragma unroll
-  for (int ct = 0; ct < NCT; ++ct) {
+  for (int c = 0; c < KT3; ++c) A3T[0][c] = fl[(Cfg::OFF3T + ct * KT3 + c) * 64];
 #pragma unroll
-    for (int c = 0; c < KT3; ++c) A3T[ct][c] = fl[(Cfg::OFF3T + ct * KT3 + c) * 64];
+  for (int c = 0; c < LF.k2; ++c) A2T[0][c] = fl[(Cfg::OFF2T + ct * LF.k2 + c) * 64];
+  if constexpr (Cfg::NARROW_HELD) {
 #pragma unroll
-    for (int c = 0; c < LF.k2; ++c) A2T[ct][c] = fl[(Cfg::OFF2T + ct * LF.k2 + c) * 64];
+    for (int c = 0; c < LF.k2; ++c) A1T[c] = fl[(Cfg::OFF1T + c) * 64];
   }
-#pragma unroll
-  for (int c = 0; c < LF.k2; ++c) A1T[0][c] = fl[(Cfg::OFF1T + c) * 64];
-  const f32x4 zero[NCT] = {};
   const f32x4 zero1[1] = {};
-  f32x4 db2[NCT], db1[NCT];
-#pragma unroll
-  for (int ct = 0; ct < NCT; ++ct) db2[ct] = db1[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+  f32x4 db2{0.f, 0.f, 0.f, 0.f}, db1{0.f, 0.f, 0.f, 0.f};  // channels ct * 16 + 4 j + i
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     const size_t sb = (size_t)b * V;
@@ -378,22 +380,19 @@ __global__ void __launch_bounds__(NT) kr_transpose(
     };
     // masked transposed-convolution output: leaky'(h) * acc, into a ring slot (and,
     // for a real plane, channel-major to global memory and the bias sums)
-    auto epilogue = [&](const uint32_t* smk, uint16_t* dst, uint16_t* gout, f32x4(&db)[NCT],
-                        bool real, int zr, int tile, const f32x4(&acc)[NCT]) {
+    auto epilogue = [&](const uint32_t* smk, uint16_t* dst, uint16_t* gout, f32x4& db, bool real,
+                        int zr, int tile, const f32x4(&acc)[1]) {
       const int n = zr * PLANE + tile * 16 + m;
       const uint32_t mw = smk[tile * 16 + m];
+      const int co0 = ct * 16 + 4 * j;
+      float v[4];
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) {
-        const int co0 = ct * 16 + 4 * j;
-        float v[4];
+      for (int i = 0; i < 4; ++i) v[i] = (mw >> (co0 + i)) & 1u ? acc[0][i] : kLeakySlope * acc[0][i];
+      const u32x2 pw = store4_tile<LP2, C, true>(dst, tile, m, co0, v);
+      if (real) {
+        store_cm_global<C, V>(gout, n, co0, pw);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = (mw >> (co0 + i)) & 1u ? acc[ct][i] : kLeakySlope * acc[ct][i];
-        const u32x2 pw = store4_tile<LP2, C, true>(dst, tile, m, co0, v);
-        if (real) {
-          store_cm_global<C, V>(gout, n, co0, pw);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) db[ct][i] += v[i];
-        }
+        for (int i = 0; i < 4; ++i) db[i] += v[i];
       }
     };
     // g_a2 of virtual plane v from g_o planes v-1, v, v+1
@@ -402,8 +401,8 @@ __global__ void __launch_bounds__(NT) kr_transpose(
       const bool real = v >= 0 && v < L;
       uint16_t* dst = ra2 + mod3(v) * PS * C;
       const int sm = mod3(v - 1), s0 = mod3(v), sp = mod3(v + 1);
-      mma_tiles<1, NCT, KT3, true>(
-          PLANE / 16, w, NW, A3T, zero,
+      mma_tiles<1, 1, KT3, true>(
+          PLANE / 16, wc, WPC, A3T, zero1,
           [&](int tile, int c) {
             const int pq = tile_p<LP2>(tile, m), t0 = 16 * c + 4 * j;  // K = tap * 2 + co
             u32x4 r;
@@ -416,7 +415,7 @@ __global__ void __launch_bounds__(NT) kr_transpose(
             }
             return r;
           },
-          [&](int tile, const f32x4(&acc)[NCT]) { epilogue(sm2, dst, a2b, db2, real, zr, tile, acc); });
+          [&](int tile, const f32x4(&acc)[1]) { epilogue(sm2, dst, a2b, db2, real, zr, tile, acc); });
     };
     // g_a1 of virtual plane v from g_a2 planes v-1, v, v+1
     auto a1_plane = [&](int v) {
@@ -424,27 +423,30 @@ __global__ void __launch_bounds__(NT) kr_transpose(
       const bool real = v >= 0 && v < L;
       uint16_t* dst = ra1 + mod3(v) * PS * C;
       const int sm = mod3(v - 1), s0 = mod3(v), sp = mod3(v + 1);
-      mma_tiles<1, NCT, LF.k2, true>(
-          PLANE / 16, w, NW, A2T, zero,
+      mma_tiles<1, 1, LF.k2, true>(
+          PLANE / 16, wc, WPC, A2T, zero1,
           [&](int tile, int c) { return gather_rb<L, C, -1>(ra2, tile_p<LP2>(tile, m), sm, s0, sp, c, j); },
-          [&](int tile, const f32x4(&acc)[NCT]) { epilogue(sm1, dst, a1b, db1, real, zr, tile, acc); });
+          [&](int tile, const f32x4(&acc)[1]) { epilogue(sm1, dst, a1b, db1, real, zr, tile, acc); });
     };
     // g_x at the frozen sites of plane zr from g_a1 planes zr-1, zr, zr+1
     auto gx_plane = [&](int zr) {
       const int sm = mod3(zr - 1), s0 = mod3(zr), sp = mod3(zr + 1);
       const int fp = fpar ^ (zr & 1);  // in-plane parity of the frozen sites
-      mma_tiles<1, 1, LF.k2, true>(
-          PLANE / 32, w, NW, A1T, zero1,
-          [&](int tile, int c) {
-            const int q = Geo<2, L>::half_site(tile * 16 + m, fp);
-            return gather_rb<L, C, -1>(ra1, LP2::idx(q), sm, s0, sp, c, j);
-          },
-          [&](int tile, const f32x4(&acc)[1]) {
-            if (j == 0) {
-              const int q = Geo<2, L>::half_site(tile * 16 + m, fp), n = zr * PLANE + q;
-              gx[sb + n] = gys[zr & 1][q] + acc[0][0];
-            }
-          });
+      for (int tile = w; tile < PLANE / 32; tile += NW) {
+        const int q = Geo<2, L>::half_site(tile * 16 + m, fp), pq = LP2::idx(q);
+        f32x4 acc{0.f, 0.f, 0.f, 0.f};
+        // fetched fragments: a few chunks in flight at a time, not all 27
+#pragma unroll Cfg::NARROW_HELD ? LF.k2 : 3
+        for (int c = 0; c < LF.k2; ++c) {
+          u32x4 a1;
+          if constexpr (Cfg::NARROW_HELD)
+            a1 = A1T[c];
+          else
+            a1 = fl[(Cfg::OFF1T + c) * 64];  // L2-resident, shared by every workgroup
+          acc = mma<true>(a1, gather_rb<L, C, -1>(ra1, pq, sm, s0, sp, c, j), acc);
+        }
+        if (j == 0) gx[sb + zr * PLANE + q] = gys[zr & 1][q] + acc[0];
+      }
     };
 
     // each mask buffer is refilled only after the pass that read it is behind a barrier
@@ -522,8 +524,15 @@ __global__ void __launch_bounds__(NT) kr_transpose(
       gx_plane(z);
     }
   }
-  bias_partial<C, NCT, NW>(db2, red, partial + (size_t)blockIdx.x * P + off_b2);
-  bias_partial<C, NCT, NW>(db1, red, partial + (size_t)blockIdx.x * P + off_b1);
+  // every wave's sums for all channel tiles, zero for the tiles it did not compute
+  f32x4 d2[NCT], d1[NCT];
+#pragma unroll
+  for (int t = 0; t < NCT; ++t) {
+    d2[t] = t == ct ? db2 : f32x4{0.f, 0.f, 0.f, 0.f};
+    d1[t] = t == ct ? db1 : f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  bias_partial<C, NCT, NW>(d2, red, partial + (size_t)blockIdx.x * P + off_b2);
+  bias_partial<C, NCT, NW>(d1, red, partial + (size_t)blockIdx.x * P + off_b1);
 }
 
 // ---------------------------------------------------------------------------
