@@ -150,8 +150,8 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
         for (int tile = w; tile < PLANE / 32; tile += NW) {
           const int q = Geo<2, L>::half_site(tile * 16 + m, ppar), pq = LP2::idx(q);
           f32x4 acc{0.f, 0.f, 0.f, 0.f};
-          // fetched fragments: a few chunks in flight at a time, not all 27
-#pragma unroll Cfg::A3_HELD ? LF.k2 : 3
+          // fetched fragments: nine chunks in flight at a time (three: 2 % slower), not all 27
+#pragma unroll Cfg::A3_HELD ? LF.k2 : 9
           for (int c = 0; c < LF.k2; ++c) {
             u32x4 a3;
             if constexpr (Cfg::A3_HELD)
