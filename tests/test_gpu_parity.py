@@ -360,9 +360,12 @@ def test_flow_backward_ring(case):
     _check_backward(desc, params, z, fs, out, lfs.LFS_BF16_CONV)
 
 
-def test_flow_backward_ring_deterministic_and_batch_position():
-    """Bitwise reproducible; a sample's g_z does not depend on the batch around it."""
-    desc, params, z, fs = _flow_case(3, 16, 2, 16, 4, lfs.LFS_BF16_CONV, lfs.ALGO_FUSED)
+@pytest.mark.parametrize("C", [16, 32])
+def test_flow_backward_ring_deterministic_and_batch_position(C):
+    """Bitwise reproducible; a sample's g_z does not depend on the batch around it
+    (C = 32: eight waves over two channel tiles, each writing half of a mask word)."""
+    print(f"ring backward determinism C={C}", flush=True)
+    desc, params, z, fs = _flow_case(3, 16, 2, C, 4, lfs.LFS_BF16_CONV, lfs.ALGO_FUSED)
     g = np.random.default_rng(15).standard_normal(z.shape).astype(np.float32)
     out = run_forward(desc, params, z)
     ga, gza = run_backward(desc, out, g, 0.2)
@@ -372,6 +375,8 @@ def test_flow_backward_ring_deterministic_and_batch_position():
     parts = []
     for i in (0, 3):
         o = run_forward(desc, params, z[i:i + 1])
+        np.testing.assert_array_equal(host(o["phi"]), host(out["phi"])[i:i + 1])
+        np.testing.assert_array_equal(host(o["logq"]), host(out["logq"])[i:i + 1])
         gi, gzi = run_backward(desc, o, g[i:i + 1], 0.2)
         np.testing.assert_array_equal(gzi, gza[i:i + 1])
         parts.append(gi)
