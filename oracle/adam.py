@@ -9,7 +9,9 @@ beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and optimizer state kept across steps.
     p <- p - lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)
 
 Pinned by: the first step from zero state moves every parameter by
--lr g/(|g| + eps), and a constant gradient keeps the step at lr.
+-lr g/(|g| + eps), a constant gradient keeps the step at lr, and the second and
+third steps with varying gradients match the closed forms of the bias-corrected
+moments as weighted means of the gradients (which fix beta1 and beta2).
 """
 from __future__ import annotations
 

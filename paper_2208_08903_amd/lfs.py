@@ -1,8 +1,11 @@
 """ctypes binding of liblfs.so: one Python function per C entry point, same names.
 
-Argument marshalling only: tensors are checked for device, dtype and
-contiguity, their data pointers and torch's current HIP stream are passed
-through, and a negative status raises LfsError.  Every step of the computation
+Argument marshalling only: tensors are checked for their sizes against the
+shapes the call implies (batch B, sites V = L^dim, layers N from the flow
+descriptor), then for device, dtype and contiguity; their data pointers and
+torch's current HIP stream are passed through, and a negative status raises
+LfsError.  A mis-sized buffer is an LfsError here, never an out-of-bounds
+access in a kernel.  Every step of the computation
 runs in the library's HIP kernels; there is no fallback of any kind.
 """
 from __future__ import annotations
@@ -131,6 +134,41 @@ def _p(t, dtype=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t, n, name, exact=True):
+    """t (if given) holds exactly n entries (at least n if not exact)."""
+    if t is None:
+        return
+    k = t.numel()
+    if (k != n) if exact else (k < n):
+        raise LfsError(f"{name} has {k} entries, the call needs {'' if exact else 'at least '}{n}")
+
+
+def _field(t, V, name):
+    """A [B, V] field: returns B."""
+    if t is None or t.dim() != 2 or t.shape[1] != V:
+        shape = None if t is None else tuple(t.shape)
+        raise LfsError(f"{name} must be a [B, {V}] tensor, got {shape}")
+    return int(t.shape[0])
+
+
+def _sites(desc) -> int:
+    if desc.dim not in (2, 3) or desc.L < 2:
+        raise LfsError(f"invalid lattice dim={desc.dim} L={desc.L}")
+    return desc.L ** desc.dim
+
+
+def _flow_sizes(desc, params, B, saved_x, bn_stats=None):
+    V = _sites(desc)
+    P = param_count(desc)
+    if P == 0:
+        raise LfsError("invalid flow descriptor")
+    _need(params, P, "params")
+    _need(saved_x, (desc.n_layers + 1) * B * V, "saved_x", exact=False)
+    if bn_stats is not None:
+        _need(bn_stats, bn_stats_count(desc), "bn_stats")
+    return V, P
+
+
 def make_desc(dim, L, n_layers, hidden, final_tanh=True, parity0=0,
               precision=LFS_PLAIN_FP32, algo=ALGO_AUTO, kernel=0, hidden_sizes=None,
               batch_norm=False) -> FlowDesc:
@@ -160,15 +198,21 @@ def workspace_bytes(desc: FlowDesc, B: int, for_backward: bool) -> int:
 
 
 def prior_normal(key: int, counter0: int, z, logr=None):
+    if z is None or z.dim() != 2:
+        raise LfsError("z must be a [B, V] tensor")
     B, V = z.shape
+    _need(logr, B, "logr")
     _check(load().lfs_prior_normal(key, counter0, B, V, _p(z, torch.float32, "z"),
                                    _p(logr, torch.float64, "logr"), _stream()))
 
 
 def prior_normal_streams(keys, counters, z, logr=None):
+    if z is None or z.dim() != 2:
+        raise LfsError("z must be a [B, V] tensor")
     B, V = z.shape
     if keys.numel() != B or counters.numel() != B:
         raise LfsError("keys and counters need one entry per sample")
+    _need(logr, B, "logr")
     _check(load().lfs_prior_normal_streams(B, V, _p(keys, torch.int64, "keys"),
                                            _p(counters, torch.int64, "counters"),
                                            _p(z, torch.float32, "z"),
@@ -176,7 +220,11 @@ def prior_normal_streams(keys, counters, z, logr=None):
 
 
 def flow_forward(desc, params, z, phi, logq, logdet=None, saved_x=None, ws=None):
-    B = z.shape[0]
+    B = _field(z, _sites(desc), "z")
+    V, _ = _flow_sizes(desc, params, B, saved_x)
+    _need(phi, B * V, "phi")
+    _need(logq, B, "logq")
+    _need(logdet, B, "logdet")
     nbytes = ws.numel() if ws is not None else 0
     _check(load().lfs_flow_forward(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
                                    _p(z, torch.float32, "z"), _p(phi, torch.float32, "phi"),
@@ -187,7 +235,11 @@ def flow_forward(desc, params, z, phi, logq, logdet=None, saved_x=None, ws=None)
 
 
 def flow_backward(desc, params, saved_x, g_phi, g_logq: float, g_params, g_z=None, ws=None):
-    B = g_phi.shape[0]
+    B = _field(g_phi, _sites(desc), "g_phi")
+    V, P = _flow_sizes(desc, params, B, saved_x)
+    _need(saved_x, (desc.n_layers + 1) * B * V, "saved_x", exact=False)
+    _need(g_params, P, "g_params")
+    _need(g_z, B * V, "g_z")
     nbytes = ws.numel() if ws is not None else 0
     _check(load().lfs_flow_backward(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
                                     _p(saved_x, torch.float32, "saved_x"),
@@ -201,7 +253,11 @@ def flow_forward_bn(desc, params, z, phi, logq, bn_mode, bn_stats=None, momentum
                     saved_x=None, ws=None):
     """bn_mode BN_BATCH (bn_stats: running statistics updated in place, or None) or
     BN_RUNNING (bn_stats read)."""
-    B = z.shape[0]
+    B = _field(z, _sites(desc), "z")
+    V, _ = _flow_sizes(desc, params, B, saved_x, bn_stats)
+    _need(phi, B * V, "phi")
+    _need(logq, B, "logq")
+    _need(logdet, B, "logdet")
     nbytes = ws.numel() if ws is not None else 0
     _check(load().lfs_flow_forward_bn(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
                                       _p(z, torch.float32, "z"), _p(phi, torch.float32, "phi"),
@@ -214,9 +270,13 @@ def flow_forward_bn(desc, params, z, phi, logq, bn_mode, bn_stats=None, momentum
 
 def flow_backward_vec(desc, params, saved_x, g_phi, g_logq, g_params, g_z=None, ws=None):
     """flow_backward with a per-sample cotangent of log q: g_logq is a [B] FP64 device tensor."""
-    B = g_phi.shape[0]
-    if g_logq.numel() != B:
+    B = _field(g_phi, _sites(desc), "g_phi")
+    if g_logq is None or g_logq.numel() != B:
         raise LfsError("g_logq needs one entry per sample")
+    V, P = _flow_sizes(desc, params, B, saved_x)
+    _need(saved_x, (desc.n_layers + 1) * B * V, "saved_x", exact=False)
+    _need(g_params, P, "g_params")
+    _need(g_z, B * V, "g_z")
     nbytes = ws.numel() if ws is not None else 0
     _check(load().lfs_flow_backward_vec(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
                                         _p(saved_x, torch.float32, "saved_x"),
@@ -230,7 +290,11 @@ def flow_backward_vec(desc, params, saved_x, g_phi, g_logq, g_params, g_z=None, 
 def flow_backward_bn(desc, params, saved_x, g_phi, g_logq, g_params, bn_mode, bn_stats=None,
                      g_z=None, ws=None):
     """g_logq: a float (the same cotangent for every sample) or a [B] FP64 device tensor."""
-    B = g_phi.shape[0]
+    B = _field(g_phi, _sites(desc), "g_phi")
+    V, P = _flow_sizes(desc, params, B, saved_x, bn_stats)
+    _need(saved_x, (desc.n_layers + 1) * B * V, "saved_x", exact=False)
+    _need(g_params, P, "g_params")
+    _need(g_z, B * V, "g_z")
     nbytes = ws.numel() if ws is not None else 0
     vec = g_logq if isinstance(g_logq, torch.Tensor) else None
     if vec is not None and vec.numel() != B:
@@ -247,7 +311,11 @@ def flow_backward_bn(desc, params, saved_x, g_phi, g_logq, g_params, bn_mode, bn
 
 
 def action(dim, L, phi, m2, lam, S, force=None, force_scale=1.0, precision=LFS_BF16_CONV):
-    B = phi.shape[0]
+    if dim not in (2, 3) or L < 2:
+        raise LfsError(f"invalid lattice dim={dim} L={L}")
+    B = _field(phi, L ** dim, "phi")
+    _need(S, B, "S")
+    _need(force, B * L ** dim, "force")
     per_sample = int(m2.numel() > 1)
     if m2.numel() not in (1, B) or lam.numel() != m2.numel():
         raise LfsError("m2 and lam must both have 1 or B entries")
@@ -258,6 +326,10 @@ def action(dim, L, phi, m2, lam, S, force=None, force_scale=1.0, precision=LFS_B
 
 
 def log_weights(S, logq, logw, loss=None):
+    B = S.numel()
+    _need(logq, B, "logq")
+    _need(logw, B, "logw")
+    _need(loss, 1, "loss")
     _check(load().lfs_log_weights(S.shape[0], _p(S, torch.float64, "S"),
                                   _p(logq, torch.float64, "logq"), _p(logw, torch.float64, "logw"),
                                   _p(loss, torch.float64, "loss"), _stream()))
@@ -279,7 +351,12 @@ def decode_chain_state(buf):
 
 
 def mh_chain(logw, log_u, state, cur_idx, accepted=None):
+    if logw is None or logw.dim() != 2:
+        raise LfsError("logw must be an [n_chains, n_prop] tensor")
     n_chains, n_prop = logw.shape
+    _need(log_u, n_chains * n_prop, "log_u")
+    _need(cur_idx, n_chains * n_prop, "cur_idx")
+    _need(accepted, n_chains * n_prop, "accepted")
     if state.numel() < n_chains * CHAIN_STATE_BYTES:
         raise LfsError("chain state buffer too small")
     _check(load().lfs_mh_chain(n_chains, n_prop, _p(logw, torch.float64, "logw"),
@@ -289,8 +366,21 @@ def mh_chain(logw, log_u, state, cur_idx, accepted=None):
 
 
 def mh_chain_ragged(offsets, logw, log_u, states, state_index, cur_idx, accepted=None):
-    """offsets: int64 [n_chains+1] device tensor; states: byte buffer of chain states."""
+    """offsets: int64 [n_chains+1] device tensor; states: byte buffer of chain states.
+
+    The offsets stay on the device, so what is checked here is that logw, log_u,
+    cur_idx and accepted are equally long, that there is one state index per chain and
+    room for that many states; the caller keeps offsets[-1] <= len(logw) and the state
+    indices below the number of states."""
     n_chains = offsets.numel() - 1
+    if n_chains < 0:
+        raise LfsError("offsets needs n_chains + 1 entries")
+    n = logw.numel()
+    _need(log_u, n, "log_u")
+    _need(cur_idx, n, "cur_idx")
+    _need(accepted, n, "accepted")
+    _need(state_index, n_chains, "state_index")
+    _need(states, n_chains * CHAIN_STATE_BYTES, "states", exact=False)
     _check(load().lfs_mh_chain_ragged(n_chains, _p(offsets, torch.int64, "offsets"),
                                       _p(logw, torch.float64, "logw"),
                                       _p(log_u, torch.float64, "log_u"),
@@ -301,7 +391,15 @@ def mh_chain_ragged(offsets, logw, log_u, states, state_index, cur_idx, accepted
 
 
 def hmc_step(dim, L, phi, pi0, log_u, m2, lam, n_steps, dt, dH, accepted):
-    B = phi.shape[0]
+    if dim not in (2, 3) or L < 2:
+        raise LfsError(f"invalid lattice dim={dim} L={L}")
+    B = _field(phi, L ** dim, "phi")
+    _need(pi0, B * L ** dim, "pi0")
+    _need(log_u, B, "log_u")
+    _need(dH, B, "dH")
+    _need(accepted, B, "accepted")
+    if m2.numel() not in (1, B) or lam.numel() != m2.numel():
+        raise LfsError("m2 and lam must both have 1 or B entries")
     per_sample = int(m2.numel() > 1)
     _check(load().lfs_hmc_step(dim, L, B, _p(phi, torch.float64, "phi"),
                                _p(pi0, torch.float64, "pi0"), _p(log_u, torch.float64, "log_u"),
@@ -311,6 +409,8 @@ def hmc_step(dim, L, phi, pi0, log_u, m2, lam, n_steps, dt, dH, accepted):
 
 
 def adam_step(p, g, m, v, lr, b1, b2, eps, t):
+    for t_, name in ((g, "g"), (m, "m"), (v, "v")):
+        _need(t_, p.numel(), name)
     _check(load().lfs_adam_step(p.numel(), _p(p, torch.float32, "p"), _p(g, torch.float32, "g"),
                                 _p(m, torch.float32, "m"), _p(v, torch.float32, "v"), lr, b1, b2,
                                 eps, t, _stream()))
@@ -320,7 +420,11 @@ def observables(dim, L, phi, M=None, C=None):
     """Condensate M [B] and zero-momentum two-point function C [B, L] (FP64) of phi [B, V]."""
     if phi.dtype not in (torch.float32, torch.float64):
         raise LfsError("phi must be float32 or float64")
-    B = phi.shape[0]
+    if dim not in (2, 3) or L < 2:
+        raise LfsError(f"invalid lattice dim={dim} L={L}")
+    B = _field(phi, L ** dim, "phi")
+    _need(M, B, "M")
+    _need(C, B * L, "C")
     _check(load().lfs_observables(dim, L, B, _p(phi, None, "phi"), int(phi.dtype == torch.float64),
                                   _p(M, torch.float64, "M"), _p(C, torch.float64, "C"), _stream()))
 
@@ -340,6 +444,14 @@ def autocorr(x, w_max: int, c: float, tau, window=None, found=None, n_indep=None
         n = index.shape[1]
     elif n is None:
         n = ldx
+    if index is not None:
+        _need(index, n_series * n, "index")
+    elif n > ldx:
+        raise LfsError(f"series of {n} entries do not fit rows of {ldx}")
+    _need(gamma, n_series * (w_max + 1), "gamma")
+    _need(tau, n_series, "tau")
+    for t_, name in ((window, "window"), (found, "found"), (n_indep, "n_indep")):
+        _need(t_, n_series, name)
     need = autocorr_workspace_bytes(n_series, n, w_max)
     if ws is None:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
@@ -356,5 +468,6 @@ def ess(logw, out):
     if logw.dim() == 1:
         logw = logw.reshape(1, -1)
     n_series, n = logw.shape
+    _need(out, n_series, "ess")
     _check(load().lfs_ess(n_series, n, _p(logw, torch.float64, "logw"), n,
                           _p(out, torch.float64, "ess"), _stream()))

@@ -3,6 +3,15 @@ FP64 oracle: forward outputs, log q, and the backward's parameter and z
 gradients, with the tolerances of the default network's generic-path tests
 (the field bound scales with the taps per convolution, T / 9).
 
+BF16 forward: against the oracle's BF16 emulation as for the default network,
+except the share of the distance from FP64 that the emulation must explain
+(2-norm of phi, largest log q difference): 0.6 instead of 0.2 and 5 %.  A wide
+kernel on a small lattice (5 x 5 taps on 8 x 8 sites) spreads one activation
+whose BF16 rounding the FP32-versus-FP64 sums flip over the whole sample, and
+such flips are the only difference left: on operands that make every sum exact
+the general-network kernels match the emulation to FP32 rounding
+(tests/test_gpu_rounding.py), so they round at the same points.
+
 BF16 gradients: small networks with wide kernels (125 taps of 3 channels in
 3D) amplify the BF16 rounding of the operands well past the default network's
 0.4 per-block bound (one 3D case moves a bias block by 0.8 relative).  There the
@@ -47,7 +56,7 @@ def _net_case(dim, L, N, K, hs, B, precision, tanh=True):
 def test_net_forward_backward(case, precision):
     print(f"general network {case} precision={precision}", flush=True)
     desc, params, z, fs = _net_case(*case, precision)
-    out, _ = _check_forward(desc, params, z, fs, precision)
+    out, _ = _check_forward(desc, params, z, fs, precision, rho=0.6, qfrac=0.6)
     if precision == lfs.LFS_PLAIN_FP32:
         _check_backward(desc, params, z, fs, out, precision)
     else:

@@ -5,13 +5,29 @@ Tolerances (derived in the design notes):
   action FP64 mode |dS| <= 1e-12 |S| + 1e-9     per-site FP64 on FP32 inputs
   action FP32 mode |dS| <= 1e-4 V               (plain FP32 sums)
   flow FP32        |dphi| <= 1e-5 (T/9) (1 + |phi|), |dlogq| <= 1e-4 V
-  flow BF16        |dphi| <= 0.02 (T/9) (1 + |phi|), |dlogq| <= 0.05 sqrt(V N) + 1e-4 V
-  gradient FP32    per-block relative 2-norm <= 1e-4
-  gradient BF16    whole-vector relative 2-norm <= 0.1, per block <= 0.4, g_z <= 0.1
-                   (BF16 unit roundoff 2^-9 times the conditioning of short sums on
-                   small lattices; 5e-3 at the 2D L=32 training shape)
-  (T = 3^dim taps: the fan-in of every convolution grows with T.)
+  gradient FP32    per parameter block: relative 2-norm <= 1e-4 and max |g - g_64| <=
+                   1e-5 max |g_64| (element-wise against the block's scale); g_z likewise
   MH, HMC decisions bit-exact given equal inputs
+  (T = 3^dim taps: the fan-in of every convolution grows with T.)
+
+BF16 convolutions are held to the oracle's emulate="bf16" mode, which rounds
+every convolution operand (input and weights, forward and adjoint) to BF16 at
+the points where the kernels round them, keeps the field in FP32 between layers
+and accumulates weight gradients in FP32.  Kernel and emulation then differ only
+by FP32-versus-FP64 accumulation and the FP32 tanh/exp, plus the rare BF16
+rounding those differences flip (one stored activation moved by one BF16 ulp);
+the emulation differs from FP64 by the rounding of every operand.  So:
+  flow BF16        |phi - phi_emu| <= 1e-2 (T/9)(1 + |phi_emu|) element-wise;
+                   ||phi - phi_emu|| <= RHO_PHI ||phi_emu - phi_64|| (2-norm over the
+                   batch: most of the kernel's distance from FP64 is the emulated
+                   rounding; measured <= 0.07, RHO_PHI = 0.2); |logq - logq_emu| <= 5 % of the emulation's largest
+                   distance from FP64 (+ 1e-6 V N); against FP64 directly, phi and log q
+                   within twice the emulation's own largest distance
+  gradient BF16    per parameter block: max |g - g_emu| <= 2e-2 max |g_emu| and
+                   relative 2-norm <= 1e-2; relative 2-norm against FP64 <= 3 times the
+                   emulation's; whole vector: relative 2-norm to the emulation <= 5e-3
+                   and <= 15 % of the emulation's own distance from FP64; g_z likewise
+                   (element-wise 5e-2 of its largest entry, 2-norm 1e-2)
 """
 import numpy as np
 import pytest
@@ -171,7 +187,10 @@ def _flow_case(dim, L, N, C, B, precision, algo, tanh=True, parity0=0):
     return desc, params, z, fs
 
 
-def _check_forward(desc, params, z, fs, precision):
+RHO_PHI = 0.2
+
+
+def _check_forward(desc, params, z, fs, precision, rho=RHO_PHI, qfrac=0.05):
     B, V = z.shape
     out = run_forward(desc, params, z)
     ref = of.flow_forward(params, z, fs, return_saved=True)
@@ -181,15 +200,36 @@ def _check_forward(desc, params, z, fs, precision):
     if precision == lfs.LFS_PLAIN_FP32:
         assert np.all(np.abs(phi - phio) <= 1e-5 * tf * (1 + np.abs(phio)))
         assert np.all(np.abs(logq - ref["logq"]) <= 1e-4 * V)
+        np.testing.assert_allclose(host(out["logdet"]), ref["logdet"], atol=1e-4 * V)
     else:
-        assert np.all(np.abs(phi - phio) <= 0.02 * tf * (1 + np.abs(phio)))
-        assert np.all(np.abs(logq - ref["logq"]) <= 0.05 * np.sqrt(V * fs.n_layers) + 1e-4 * V)
+        _check_forward_bf16(params, z, fs, phi, logq, host(out["logdet"]), ref, rho, qfrac)
     saved = host(out["saved"]).reshape(fs.n_layers + 1, B, V)
     np.testing.assert_array_equal(saved[0], z)
     np.testing.assert_array_equal(saved[-1], host(out["phi"]))
-    np.testing.assert_allclose(host(out["logdet"]), ref["logdet"],
-                               atol=1e-4 * V if precision == 0 else 0.05 * np.sqrt(V * fs.n_layers) + 1e-4 * V)
     return out, ref
+
+
+def _check_forward_bf16(params, z, fs, phi, logq, logdet, ref, rho=RHO_PHI, qfrac=0.05):
+    """phi, log q, log-det of a BF16 forward against the emulation and against FP64."""
+    B, V = z.shape
+    emu = of.flow_forward(params, z, fs, emulate="bf16")
+    pe, p64 = emu["phi"].reshape(B, V), ref["phi"].reshape(B, V)
+    tf = fs.T / 9
+    el = np.max(np.abs(phi - pe) / (1 + np.abs(pe)))
+    dev64 = np.max(np.abs(pe - p64) / (1 + np.abs(p64)))
+    ratio = np.linalg.norm(phi - pe) / max(np.linalg.norm(pe - p64), 1e-300)
+    q_dev64 = np.max(np.abs(emu["logq"] - ref["logq"]))
+    q_emu = np.max(np.abs(logq - emu["logq"]))
+    floor = 1e-6 * V * fs.n_layers
+    print(f"  bf16 forward: phi vs emulation {el:.2e} (2-norm ratio {ratio:.3f}), emulation vs FP64 "
+          f"{dev64:.2e}; log q vs emulation {q_emu:.2e}, emulation vs FP64 {q_dev64:.2e}", flush=True)
+    assert el <= 1e-2 * tf, el
+    assert ratio <= rho or np.linalg.norm(phi - pe) <= 1e-6 * np.linalg.norm(pe), ratio
+    assert q_emu <= qfrac * q_dev64 + floor, (q_emu, q_dev64)
+    if logdet is not None:
+        assert np.max(np.abs(logdet - emu["logdet"])) <= qfrac * q_dev64 + floor
+    assert np.max(np.abs(phi - p64) / (1 + np.abs(p64))) <= 2 * dev64 + 1e-6
+    assert np.max(np.abs(logq - ref["logq"])) <= 2 * q_dev64 + floor
 
 
 @pytest.mark.parametrize("case", FLOW_CASES)
@@ -224,14 +264,38 @@ def _check_backward(desc, params, z, fs, out, precision):
     g_logq = 0.37
     gp, gz = run_backward(desc, out, g_phi, g_logq)
     gpo, gzo = of.flow_vjp(params, z, fs, g_phi.astype(np.float64), g_logq)
-    fp32 = precision == lfs.LFS_PLAIN_FP32
-    tol_block = 1e-4 if fp32 else 0.4
-    for lay_g, lay_o in zip(of.unpack(gp, fs), of.unpack(gpo, fs)):
-        for a, b in zip(lay_g, lay_o):
-            assert rel_norm(a, b) <= tol_block, (rel_norm(a, b), a.shape)
-    assert rel_norm(gp, gpo) <= (1e-4 if fp32 else 0.1)
-    assert rel_norm(gz, gzo) <= (1e-4 if fp32 else 0.1)
+    if precision == lfs.LFS_PLAIN_FP32:
+        for lay_g, lay_o in zip(of.unpack(gp, fs), of.unpack(gpo, fs)):
+            for a, b in zip(lay_g, lay_o):
+                assert rel_norm(a, b) <= 1e-4, (rel_norm(a, b), a.shape)
+                assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(b)), a.shape
+        assert rel_norm(gp, gpo) <= 1e-4
+        assert rel_norm(gz, gzo) <= 1e-4
+        assert np.max(np.abs(gz - gzo)) <= 1e-5 * np.max(np.abs(gzo))
+    else:
+        _check_backward_bf16(params, z, fs, g_phi, g_logq, gp, gz, gpo, gzo)
     return gp, gpo
+
+
+def _check_backward_bf16(params, z, fs, g_phi, g_logq, gp, gz, g64, z64):
+    """A BF16 backward's parameter and z gradients against the emulation and FP64."""
+    g16, z16 = of.flow_vjp(params, z, fs, g_phi.astype(np.float64), g_logq, emulate="bf16")
+    worst_el = worst_rn = 0.0
+    for lay_g, lay_e, lay_r in zip(of.unpack(gp, fs), of.unpack(g16, fs), of.unpack(g64, fs)):
+        for a, e, r in zip(lay_g, lay_e, lay_r):
+            el = np.max(np.abs(a - e)) / max(np.max(np.abs(e)), 1e-300)
+            rn = rel_norm(a, e)
+            worst_el, worst_rn = max(worst_el, el), max(worst_rn, rn)
+            assert el <= 2e-2, (el, a.shape)
+            assert rn <= 1e-2, (rn, a.shape)
+            assert rel_norm(a, r) <= 3 * rel_norm(e, r) + 1e-6, (rel_norm(a, r), rel_norm(e, r), a.shape)
+    whole, whole64 = rel_norm(gp, g16), rel_norm(g16, g64)
+    print(f"  bf16 backward: worst block vs emulation: element {worst_el:.2e}, 2-norm {worst_rn:.2e}; "
+          f"whole {whole:.2e} (emulation vs FP64 {whole64:.2e})", flush=True)
+    assert whole <= 5e-3 and whole <= 0.15 * whole64 + 1e-7, (whole, whole64)
+    assert np.max(np.abs(gz - z16)) <= 5e-2 * np.max(np.abs(z16))
+    assert rel_norm(gz, z16) <= 1e-2
+    assert rel_norm(gz, z64) <= 3 * rel_norm(z16, z64) + 1e-6
 
 
 @pytest.mark.parametrize("case", FLOW_CASES[:6])
@@ -373,13 +437,19 @@ def test_flow_backward_ring_deterministic_and_batch_position(C):
     np.testing.assert_array_equal(ga, gb)
     np.testing.assert_array_equal(gza, gzb)
     parts = []
-    for i in (0, 3):
+    for i in range(4):
         o = run_forward(desc, params, z[i:i + 1])
         np.testing.assert_array_equal(host(o["phi"]), host(out["phi"])[i:i + 1])
         np.testing.assert_array_equal(host(o["logq"]), host(out["logq"])[i:i + 1])
         gi, gzi = run_backward(desc, o, g[i:i + 1], 0.2)
         np.testing.assert_array_equal(gzi, gza[i:i + 1])
         parts.append(gi)
+    # the batch gradient is the sum of the per-sample gradients, up to FP32 summation order
+    # (at C = 32 the bias sums go through both channel tiles' zero-filled partials)
+    assert rel_norm(ga, np.sum(parts, axis=0)) < 1e-5
+    for lay_a, lay_s in zip(of.unpack(ga, fs), of.unpack(np.sum(parts, axis=0), fs)):
+        for a, b in zip(lay_a, lay_s):
+            assert rel_norm(a, b) < 1e-4, (rel_norm(a, b), a.shape)
 
 
 def test_flow_backward_fused_deterministic_and_batch_sum():

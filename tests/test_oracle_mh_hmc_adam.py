@@ -151,6 +151,33 @@ def test_hmc_accept_rule_and_restore():
     np.testing.assert_array_equal(out_acc, p1)
 
 
+def test_adam_second_step_pins_betas():
+    """Two steps from zero state with different gradients.  After two updates
+    m = (1 - b1)(b1 g1 + g2) and 1 - b1^2 = (1 - b1)(1 + b1), so the bias-corrected
+    moments are weighted means, m_hat = (b1 g1 + g2)/(1 + b1) and
+    v_hat = (b2 g1^2 + g2^2)/(1 + b2).  g = (1, -1) gives v_hat = 1 and
+    m_hat = -(1 - b1)/(1 + b1) = -0.1/1.9, which fixes b1; g = (1, 0) gives
+    m_hat = 0.9/1.9 and v_hat = 0.999/1.999, which then fixes b2 (the decimal values
+    are those of b1 = 0.9, b2 = 0.999 written out)."""
+    lr, eps = 1e-3, 1e-8
+    for g1, g2, step in ((1.0, -1.0, lr * 0.052631578947368425 / (1 + eps)),
+                         (1.0, 0.0, -lr * 0.4736842105263158 / (0.706929893933952 + eps)),
+                         (-2.0, 0.5, -lr * (-1.8 + 0.5) / 1.9 / (np.sqrt((0.999 * 4 + 0.25) / 1.999) + eps))):
+        p0 = np.array([0.25])
+        p1, m, v = adam_step(p0, np.array([g1]), np.zeros(1), np.zeros(1), 1, lr=lr)
+        p2, _, _ = adam_step(p1, np.array([g2]), m, v, 2, lr=lr)
+        np.testing.assert_allclose(p2 - p1, [step], rtol=1e-12, atol=0)
+    # a third step: m_hat = (b1^2 g1 + b1 g2 + g3)/(1 + b1 + b1^2), likewise v_hat with b2
+    g = (0.5, -1.5, 3.0)
+    p, m, v = np.array([0.0]), np.zeros(1), np.zeros(1)
+    for t, gt in enumerate(g, start=1):
+        q, m, v = adam_step(p, np.array([gt]), m, v, t, lr=lr)
+        last, p = q - p, q
+    mh = (0.81 * 0.5 + 0.9 * -1.5 + 3.0) / (1 + 0.9 + 0.81)
+    vh = (0.998001 * 0.25 + 0.999 * 2.25 + 9.0) / (1 + 0.999 + 0.998001)
+    np.testing.assert_allclose(last, [-lr * mh / (np.sqrt(vh) + eps)], rtol=1e-12)
+
+
 def test_adam_first_step_and_constant_gradient():
     rng = np.random.default_rng(10)
     g = rng.standard_normal(100)
