@@ -13,7 +13,8 @@
  *  - Every pointer argument is a DEVICE pointer to contiguous memory, unless
  *    the argument is documented as host memory.  The caller owns every buffer,
  *    including the workspace; the library never allocates or frees device
- *    memory inside these calls and keeps no mutable global state.
+ *    memory inside these calls.  Its only global state is the static device
+ *    scratch of lfs_flow_forward_noalloc and that array's per-device address.
  *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
  *    Calls are asynchronous on that stream: inputs must stay unchanged and
  *    outputs must not be read until the stream reaches the call.
@@ -203,6 +204,25 @@ int32_t lfs_prior_normal_streams(int32_t B, int32_t V, const uint64_t* keys,
 int32_t lfs_flow_forward(const lfs_flow_desc* desc, const float* params, int32_t B,
                          const float* z, float* phi, double* logq, double* logdet,
                          float* saved_x, void* ws, size_t ws_bytes, void* stream);
+
+/* lfs_flow_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and results, bit for bit, with the workspace taken from a
+ * static device array of LFS_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends (its address is looked up once
+ * per device, on the first call with that device current).  The call allocates
+ * and frees nothing.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (different streams, or host threads) race and must
+ * be serialised by the caller.  Nothing in the array needs to start at zero.
+ * Arguments as lfs_flow_forward, without ws and ws_bytes.
+ * Errors: as lfs_flow_forward; LFS_EWORKSPACE when the workspace this flow and
+ * batch need (lfs_workspace_bytes(desc, B, 0)) exceeds LFS_NOALLOC_SCRATCH_BYTES
+ * (the fused forwards need only their weight fragments, at most 85 KB per
+ * layer, at any batch; the generic kernels' hidden activations grow with B). */
+#define LFS_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+int32_t lfs_flow_forward_noalloc(const lfs_flow_desc* desc, const float* params, int32_t B,
+                                 const float* z, float* phi, double* logq, double* logdet,
+                                 float* saved_x, void* stream);
 
 /* Vector-Jacobian product of lfs_flow_forward's outputs (phi, log q) with
  * respect to its inputs (params, z): the hand-written backward of the

@@ -2,6 +2,8 @@
 // sizing and dispatch between the fused and the generic kernel families.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "lfs_common.hpp"
 #include "lfs_internal.hpp"
 
@@ -255,4 +257,51 @@ extern "C" int32_t lfs_flow_backward_bn(const lfs_flow_desc* desc, const float* 
   if (!ws || ws_bytes < need) return LFS_EWORKSPACE;
   return lfs::net_backward_bn(g, params, B, saved_x, g_phi, g_logq, g_logq_vec, bn_mode, bn_stats,
                               g_params, g_z, (char*)ws, (hipStream_t)stream);
+}
+
+// ---- allocation-free forward ------------------------------------------------
+// The forward's workspace (weight fragments, or the generic kernels' hidden
+// activations) lives in one file-scope device array instead of caller memory.
+// Its device address differs per GPU and is looked up once per device with
+// that device current; host code never passes the array's name to a kernel.
+namespace lfs {
+namespace {
+
+__device__ __align__(256) unsigned char scratch[LFS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int32_t scratch_of_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LFS_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LFS_EDEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LFS_OK;
+}
+
+}  // namespace
+}  // namespace lfs
+
+extern "C" int32_t lfs_flow_forward_noalloc(const lfs_flow_desc* desc, const float* params, int32_t B,
+                                            const float* z, float* phi, double* logq, double* logdet,
+                                            float* saved_x, void* stream) {
+  lfs::FlowGeom g;
+  const int32_t s = lfs::make_geom(desc, &g);
+  if (s != LFS_OK) return s;
+  if (B < 0 || g.bn) return LFS_EINVAL;
+  if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_ok(g, 0)) return LFS_EUNSUPPORTED;
+  if (B == 0) return LFS_OK;
+  if (lfs::ws_bytes_of(g, B, 0) > LFS_NOALLOC_SCRATCH_BYTES) return LFS_EWORKSPACE;
+  void* ws = nullptr;
+  const int32_t sp = lfs::scratch_of_current_device(&ws);
+  if (sp != LFS_OK) return sp;
+  return lfs_flow_forward(desc, params, B, z, phi, logq, logdet, saved_x, ws,
+                          LFS_NOALLOC_SCRATCH_BYTES, stream);
 }

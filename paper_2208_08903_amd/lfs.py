@@ -65,6 +65,8 @@ _SIGS = {
                                  c_vp, c_vp, c_sz, c_vp]),
     "lfs_flow_backward": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_f64, c_vp,
                                   c_vp, c_vp, c_sz, c_vp]),
+    "lfs_flow_forward_noalloc": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
+                                         c_vp, c_vp]),
     "lfs_bn_stats_count": (c_sz, [ctypes.POINTER(FlowDesc)]),
     "lfs_flow_forward_bn": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
                                     c_vp, c_i32, c_vp, c_f64, c_vp, c_sz, c_vp]),
@@ -232,6 +234,28 @@ def flow_forward(desc, params, z, phi, logq, logdet=None, saved_x=None, ws=None)
                                    _p(logdet, torch.float64, "logdet"),
                                    _p(saved_x, torch.float32, "saved_x"),
                                    _p(ws, torch.uint8, "ws"), nbytes, _stream()))
+
+
+NOALLOC_SCRATCH_BYTES = 8 << 20   # LFS_NOALLOC_SCRATCH_BYTES
+
+
+def flow_forward_noalloc(desc, params, z, phi, logq, logdet=None, saved_x=None):
+    """flow_forward with the library's static device scratch as workspace (no allocation
+    anywhere in the call).  Calls that overlap on one GPU share the scratch and race."""
+    B = _field(z, _sites(desc), "z")
+    V, _ = _flow_sizes(desc, params, B, saved_x)
+    _need(phi, B * V, "phi")
+    _need(logq, B, "logq")
+    _need(logdet, B, "logdet")
+    st = load().lfs_flow_forward_noalloc(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
+                                         _p(z, torch.float32, "z"), _p(phi, torch.float32, "phi"),
+                                         _p(logq, torch.float64, "logq"),
+                                         _p(logdet, torch.float64, "logdet"),
+                                         _p(saved_x, torch.float32, "saved_x"), _stream())
+    if st == -3:
+        raise LfsError(f"flow_forward_noalloc: this flow at batch {B} needs more workspace than the "
+                       f"{NOALLOC_SCRATCH_BYTES} bytes of static scratch (LFS_EWORKSPACE)")
+    _check(st)
 
 
 def flow_backward(desc, params, saved_x, g_phi, g_logq: float, g_params, g_z=None, ws=None):
