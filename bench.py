@@ -6,15 +6,18 @@ L = 32, m^2 = -4, lambda = 8, 16 affine coupling layers with hidden channels 16,
 batch 1024, Adam lr 1e-3: prior draw -> flow forward with log q (saving the
 layer inputs) -> action and force -> log-weights and loss -> hand-written flow
 backward -> Adam.  Inputs are synthetic: seeded N(0, 0.1) weights (biases 0),
-Philox prior draws.  `value` is BF16-conv (FP32 accumulate, FP64 sums) training
-steps per second, with `roofline` (the per-layer backward launch against the
-BF16 MFMA peak, and its HBM traffic from the committed rocprofv3 summary) and
-`cpu_baseline` (the FP64 oracle on a bounded sample of the batch).  Beside it:
-the plain FP32 path, flow+MH sampling, the FP64 HMC baseline, the memory-side
-kernels against HBM (the prior also against the VALU issue peak), the other
-workloads (2D L=8, 3D L=8, 3D L=16 C=32), other s/t networks, the example
-schedule trained to convergence with chain quality against HMC, serving in
-both precisions, and the oracle on the other workloads.
+Philox prior draws.  `value` is plain-FP32 training steps per second (the
+paper's arithmetic: FP32 convolutions, on FP32 matrix cores), with `roofline`
+(the per-layer backward launch against the FP32 MFMA peak, and its HBM traffic
+from the committed rocprofv3 summary) and `cpu_baseline` (the FP64 oracle on a
+bounded sample of the batch, on all host cores, with the one-thread figure
+beside it).  Beside it: the BF16-convolution form of the same step with its own
+roofline, flow+MH sampling, the FP64 HMC baseline with its FP64 roofline, the
+memory-side kernels against HBM (the prior also against the VALU issue peak),
+the other workloads (2D L=8, 3D L=8 with its 10k-proposal chain, 3D L=16 C=32),
+other s/t networks, the example schedule and the 3D L=8 flow trained with
+acceptance over training and chain quality against HMC, serving in both
+precisions, and the oracle on the other workloads.
 
 Prints ONE JSON line (progress lines go to stderr).  Only one GPU is supported.
 """
@@ -39,13 +42,15 @@ WORKLOADS = {
                                   n_layers=16, hidden=32, batch=256, lr=1e-3),
 }
 WORKLOAD = WORKLOADS["phi4-2d-L32-train"]
-PEAK = {"bf16_mfma_tflops": 2500.0, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
+PEAK = {"bf16_mfma_tflops": 2500.0, "fp32_mfma_tflops": 157.3, "fp64_tflops": 78.6, "hbm_gbs": 8000.0}
 KERNEL_SOURCES = ["paper_2208_08903_amd/csrc/flow_fused_bwd.hip",
                   "paper_2208_08903_amd/csrc/fused_kernels.hpp",
                   "paper_2208_08903_amd/csrc/fused_common.hpp",
                   "paper_2208_08903_amd/csrc/lfs_common.hpp",
                   "paper_2208_08903_amd/csrc/fused_bwd_common.hpp"]
-TRAFFIC_FILE = "profiles/kf_backward_phi4-2d-L32-train_traffic.txt"
+# HBM bytes per backward launch (rocprofv3 FETCH_SIZE / WRITE_SIZE), per precision
+TRAFFIC_FILES = {"fp32": "profiles/kf_backward_fp32_phi4-2d-L32-train_traffic.txt",
+                 "bf16": "profiles/kf_backward_bf16_phi4-2d-L32-train_traffic.txt"}
 # VALU instructions of the prior draw at the 4096 x 4096-site sampling shape
 # (rocprofv3 SQ_INSTS_VALU); the prior is bound by its Philox and Box-Muller
 # arithmetic, not by HBM
@@ -90,9 +95,9 @@ def _recorded(path, key, sources=None):
         return None
 
 
-def recorded_traffic():
+def recorded_traffic(prec_name):
     """HBM bytes per backward launch (rocprofv3 FETCH_SIZE / WRITE_SIZE summary)."""
-    return _recorded(TRAFFIC_FILE, "traffic_bytes_per_launch")
+    return _recorded(TRAFFIC_FILES[prec_name], "traffic_bytes_per_launch")
 
 
 def recorded_prior_valu():
@@ -173,12 +178,22 @@ def sampling_rate(flow, B, m2, lam, batches=10):
                 accepted_per_s=acc * B * batches / dt, batch=B)
 
 
+def hmc_flops_per_trajectory(dim, V, n_steps):
+    """Algorithmic FP64 flops of one KDK trajectory of one chain: per site and leapfrog step
+    the force -2 Lap phi + 2 m^2 phi + 4 lambda phi^3 (2 dim + 1 for the Laplacian, 5 for
+    the rest: 2 dim + 6), two half-kicks and a drift (2 each: 6); the Hamiltonian at both
+    ends (the action density and 1/2 pi^2: 2 dim + 8 each)."""
+    return V * (n_steps * (2 * dim + 12) + 2 * (2 * dim + 8))
+
+
 def hmc_rate(reps=5):
-    """FP64 HMC baseline on the 3D L=8 theory: 512 chains x 10 leapfrog steps of 0.1."""
+    """FP64 HMC baseline on the 3D L=8 theory: 512 chains x 10 leapfrog steps of 0.1, with
+    its rate against the FP64 vector peak (a trajectory is latency-bound: 10 dependent
+    steps, two barriers each, over 512 sites per chain)."""
     import torch
     from paper_2208_08903_amd import lfs
     import seeded_inputs as si
-    B, L, dim = 512, 8, 3
+    B, L, dim, n_steps = 512, 8, 3, 10
     V = L ** dim
     phi = torch.as_tensor(0.5 * si.normal_fields(3, B, V).astype("float64"), device="cuda")
     pi = torch.as_tensor(si.momenta(4, B, V), device="cuda")
@@ -187,15 +202,51 @@ def hmc_rate(reps=5):
     lam = torch.tensor([5.0], dtype=torch.float64, device="cuda")
     dH = torch.empty(B, dtype=torch.float64, device="cuda")
     acc = torch.empty(B, dtype=torch.uint8, device="cuda")
-    lfs.hmc_step(dim, L, phi, pi, lu, m2, lam, 10, 0.1, dH, acc)
+    lfs.hmc_step(dim, L, phi, pi, lu, m2, lam, n_steps, 0.1, dH, acc)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
     for _ in range(reps):
-        lfs.hmc_step(dim, L, phi, pi, lu, m2, lam, 10, 0.1, dH, acc)
+        lfs.hmc_step(dim, L, phi, pi, lu, m2, lam, n_steps, 0.1, dH, acc)
+    e.record()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    return dict(trajectories_per_s=B / dt, chains=B, leapfrog_steps=10, dt=0.1,
-                acceptance=float(acc.float().mean().item()))
+    dt = s.elapsed_time(e) * 1e-3 / reps
+    flops = B * hmc_flops_per_trajectory(dim, V, n_steps)
+    tf = flops / dt / 1e12
+    return dict(trajectories_per_s=B / dt, chains=B, leapfrog_steps=n_steps, dt=0.1,
+                acceptance=float(acc.float().mean().item()), us_per_call=round(dt * 1e6, 2),
+                force_evaluations_per_trajectory=n_steps + 1,
+                roofline={"bound": "fp64", "achieved": round(tf, 4), "peak": PEAK["fp64_tflops"],
+                          "unit": "TFLOP/s", "frac": round(tf / PEAK["fp64_tflops"], 5),
+                          "flops_per_call": flops})
+
+
+def chain_3d_L8_10k():
+    """The 3D L=8 workload's sampling chain: 10 000 flow proposals (12 layers, C=16, seeded
+    N(0,0.1) weights) in one batch, their action and log-weights, and one independence-MH
+    chain over them; proposals/s and acceptance, in both precisions."""
+    import torch
+    import seeded_inputs as si
+    from paper_2208_08903_amd import flow as fl
+    from paper_2208_08903_amd import lfs
+    out = {}
+    p3 = si.flow_params(3, 12, 16)
+    n = 10_000
+    lu = torch.as_tensor(si.log_uniforms(31, (3, 1, n)), device="cuda")
+    for prec, name in ((lfs.LFS_BF16_CONV, "bf16"), (lfs.LFS_PLAIN_FP32, "fp32")):
+        f = fl.Flow(3, 8, 12, 16, prec, params=p3)
+        smp = fl.Sampler(f, n, -4.0, 5.0, key=2024)
+        smp.step(lu[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        smp.step(lu[1])
+        smp.step(lu[2])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 2
+        acc, n_acc = smp.acceptance()
+        out[name] = {"proposals": n, "chain_ms": round(1e3 * dt, 3), "proposals_per_s": round(n / dt, 1),
+                     "acceptance": acc, "accepted": n_acc}
+    return out
 
 
 def hbm_kernels(reps=20):
@@ -380,9 +431,57 @@ def trained_example(steps=20000):
     return out
 
 
-def serving(seconds=5.0, precision=None):
+def trained_3d(steps=20000, B=256, w_std=0.02):
+    """The 3D L=8 workload's flow (12 layers, C=16, m2=-4, lambda=5) trained to convergence
+    at batch 256, Adam lr 1e-3, from N(0, 0.02^2) weights (at the workload's N(0, 0.1^2) the
+    3D networks start deep in tanh saturation and the reverse-KL loss stays in the
+    thousands with acceptance ~1e-3 after 60 000 steps), once with BF16 convolutions and
+    once in plain FP32: loss and MH acceptance over training (4096-proposal batches), then
+    for the BF16-trained flow the chain of 16 x 4096 proposals against FP64 HMC on the same
+    theory: <M^2> and the zero-momentum two-point function C(t) with their errors."""
+    import numpy as np
+    import torch
+    import seeded_inputs as si
+    from paper_2208_08903_amd import flow as fl
+    from paper_2208_08903_amd import lfs
+    out = {"steps": steps, "batch": B, "lr": 1e-3, "w_std": w_std}
+    marks = sorted({steps // 8, steps // 4, steps // 2, steps})
+    for prec, name in ((lfs.LFS_BF16_CONV, "bf16"), (lfs.LFS_PLAIN_FP32, "fp32")):
+        f = fl.Flow(3, 8, 12, 16, prec, params=si.flow_params(3, 12, 16, w_std=w_std))
+        tr = fl.Trainer(f, B, -4.0, 5.0, lr=1e-3)
+        hist, t_train, done = [], 0.0, 0
+        for mk in marks:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            while done < mk:
+                tr.step()
+                done += 1
+            torch.cuda.synchronize()
+            t_train += time.perf_counter() - t0
+            acc, _ = fl.acceptance_rate(f, -4.0, 5.0, batches=2, B=4096)
+            hist.append({"step": done, "loss": round(float(tr.loss.item()), 4), "acceptance": round(acc, 4)})
+        row = {"train_s": round(t_train, 2), "train_steps_per_s": round(steps / t_train, 1), "history": hist}
+        if prec == lfs.LFS_BF16_CONV:
+            cq = fl.chain_quality(f, -4.0, 5.0, batches=16, B=4096)
+            hq = fl.hmc_chain_quality(3, 8, -4.0, 5.0, n_chains=256, n_traj=1500)
+            keep = ("acceptance", "tau_M", "n_indep_M", "ess", "M2_mean", "M2_err", "C_mean", "C_err")
+            row["chain_quality"] = {"flow_mh": {k: cq[k] for k in keep},
+                                    "hmc": {k: hq[k] for k in ("acceptance", "tau_M_mean", "M2_mean", "M2_err",
+                                                                "C_mean", "C_err")}}
+            d = np.abs(np.array(cq["C_mean"]) - np.array(hq["C_mean"]))
+            sig = np.hypot(np.array(cq["C_err"]), np.array(hq["C_err"]))
+            row["chain_quality"]["max_C_deviation_sigma"] = round(float(np.max(d / sig)), 3)
+            row["chain_quality"]["M2_deviation_sigma"] = round(
+                abs(cq["M2_mean"] - hq["M2_mean"]) / float(np.hypot(cq["M2_err"], hq["M2_err"])), 3)
+        out[name] = row
+        del tr, f
+    return out
+
+
+def serving(seconds=60.0, precision=None):
     """Poisson(200/s) sampling requests for `seconds` through the continuous-batching server
-    (BF16 convolutions unless `precision` says otherwise)."""
+    (BF16 convolutions unless `precision` says otherwise), HBM budget 512 MB; peak admitted
+    bytes (requests and group buffers) and peak device bytes of the run beside it."""
     import seeded_inputs as si
     from paper_2208_08903_amd import lfs
     from paper_2208_08903_amd.serve import DEFAULT_ARCH, Server, run_workload
@@ -400,34 +499,57 @@ def serving(seconds=5.0, precision=None):
     return st
 
 
-def cpu_baseline(w, target_s=15.0):
-    """The FP64 oracle's training step, one thread, on a bounded sample of the batch,
-    scaled to steps/s of the full batch (cost is linear in the batch: samples are
-    independent)."""
+def _oracle_gradient_seconds(args):
+    """Process-pool worker: seconds the FP64 oracle (one BLAS thread) takes for the loss
+    gradient of n samples of the workload."""
+    dim, L, N, C, m2, lam, seed, n = args
+    from threadpoolctl import threadpool_limits
+    import seeded_inputs as si
+    from oracle import flow as of
+    fs = of.FlowShape(dim, L, N, C)
+    p = si.flow_params(dim, N, C).astype("float64")
+    z = si.normal_fields(seed, n, fs.V)
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        of.loss_gradient(p, z, fs, m2, lam)
+        return time.perf_counter() - t
+
+
+def cpu_baseline(w, target_s=10.0):
+    """The FP64 oracle's training step (loss gradient + Adam) on a bounded sample of the
+    batch, scaled to steps/s of the full batch (cost is linear in the batch: samples are
+    independent): on all host cores (one oracle process per core, each on its own
+    samples, one BLAS thread each), with the one-thread figure beside it."""
+    import multiprocessing as mp
     import numpy as np
     from threadpoolctl import threadpool_limits
     import seeded_inputs as si
     from oracle import adam as oadam
-    from oracle import flow as of
-    fs = of.FlowShape(w["dim"], w["L"], w["n_layers"], w["hidden"])
+    key = (w["dim"], w["L"], w["n_layers"], w["hidden"], w["m2"], w["lam"])
     p = si.flow_params(w["dim"], w["n_layers"], w["hidden"]).astype(np.float64)
-
-    def run(b):
-        z = si.normal_fields(9, b, fs.V)
-        t = time.perf_counter()
-        g = of.loss_gradient(p, z, fs, w["m2"], w["lam"])
-        oadam.adam_step(p, g, np.zeros_like(p), np.zeros_like(p), 1, lr=w["lr"])
-        return time.perf_counter() - t
-
     with threadpool_limits(1):
-        t1 = run(2)
-        b = int(max(2, min(128, round(2 * target_s / max(t1, 1e-3)))))
-        tb = run(b)
-    per_sample = tb / b
-    return {"value": 1.0 / (per_sample * w["batch"]), "unit": "train steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"oracle loss gradient + Adam on {b} of the {w['batch']} samples "
-                      f"({tb:.1f} s, FP64 NumPy, 1 thread), scaled linearly to the full batch"}
+        t = time.perf_counter()
+        oadam.adam_step(p, np.ones_like(p), np.zeros_like(p), np.zeros_like(p), 1, lr=w["lr"])
+        t_adam = time.perf_counter() - t
+    t2 = _oracle_gradient_seconds((*key, 9, 2))
+    b1 = int(max(2, min(128, round(2 * target_s / max(t2, 1e-3)))))
+    tb = _oracle_gradient_seconds((*key, 9, b1))
+    single = 1.0 / (tb / b1 * w["batch"] + t_adam)
+    cores = len(os.sched_getaffinity(0))
+    per = int(max(2, min(64, round(b1 * 0.8))))
+    with mp.get_context("spawn").Pool(cores) as pool:
+        pool.map(_oracle_gradient_seconds, [(*key, 9, 1)] * cores)       # imports done before timing
+        t = time.perf_counter()
+        pool.map(_oracle_gradient_seconds, [(*key, 100 + i, per) for i in range(cores)])
+        wall = time.perf_counter() - t
+    n = per * cores
+    allc = 1.0 / (wall / n * w["batch"] + t_adam)
+    return {"value": allc, "unit": "train steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle loss gradient on {n} of the {w['batch']} samples in {cores} processes "
+                      f"({per} each, one BLAS thread each; {wall:.1f} s wall) plus one Adam step, "
+                      "FP64 NumPy, scaled linearly to the full batch",
+            "single_thread": {"value": single, "cores": 1,
+                              "sample": f"{b1} samples in one thread ({tb:.1f} s) plus one Adam step"}}
 
 
 def host_description():
@@ -492,17 +614,43 @@ def oracle_timings():
     return out
 
 
+def roofline_of(phase, fwd_ms, w, B, prec_name):
+    """Dominant kernel of a training step and its rate against the matrix-core peak of its
+    precision: the fused forward (one launch per call) or the per-layer backward launch
+    (the backward phase's HIP-event time over its N launches; the fragment preparation,
+    the last reduction and the tiny launches around them are in that time too, so this
+    slightly understates the launch's own rate)."""
+    fl_flops = algorithmic_flops_per_sample_layer(w["dim"], w["L"], w["hidden"])
+    peak = PEAK["fp32_mfma_tflops"] if prec_name == "fp32" else PEAK["bf16_mfma_tflops"]
+    if phase["backward"] > fwd_ms:
+        name = ("flow_backward (per layer launch)" if w["dim"] == 2 else
+                "flow_backward (per layer: kr_recompute + kr_transpose + kr_wgrad)")
+        ms = phase["backward"] / w["n_layers"]
+        flops = 2 * fl_flops * B
+        traffic = recorded_traffic(prec_name) if w is WORKLOAD else None
+    else:
+        name, ms, flops, traffic = "kf_forward (flow forward, all layers)", fwd_ms, fl_flops * w["n_layers"] * B, None
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 5), "traffic": traffic,
+            "flops_per_launch": flops, "ms_per_launch": round(ms, 5)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip FP32/sampling/HMC side figures")
+    ap.add_argument("--no-extras", action="store_true", help="skip the side figures")
+    ap.add_argument("--precision", choices=("both", "fp32", "bf16"), default="both",
+                    help="which training steps to time (profiling runs time one)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default=WORKLOAD["workload"],
                     help="the training step to time (side figures run with the default only)")
-    ap.add_argument("--serving-seconds", type=float, default=5.0,
-                    help="length of the Poisson arrival window of the serving figures")
+    ap.add_argument("--serving-seconds", type=float, default=60.0,
+                    help="length of the Poisson arrival window of the BF16 serving figure")
+    ap.add_argument("--serving-seconds-fp32", type=float, default=10.0,
+                    help="the same for plain FP32 (which saturates at the offered load)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the timed region, one device-to-device copy of this many MiB "
                          "(the known-size kernel that scales the HBM byte counters)")
@@ -514,7 +662,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import seeded_inputs as si
     from paper_2208_08903_amd import flow as fl
@@ -530,72 +677,66 @@ def main():
         f = fl.Flow(w["dim"], w["L"], w["n_layers"], w["hidden"], prec, params=params)
         return f, fl.Trainer(f, B, w["m2"], w["lam"], lr=w["lr"])
 
-    flow, tr = make(lfs.LFS_BF16_CONV)
-    total, phase = time_phases(tr, args.steps, args.warmup)
-    ms = 1000.0 * total / args.steps
-    loss = float(tr.loss.item())
-
-    # dominant kernel: the fused forward (one launch per call) or the backward launches
-    fwd_ms = flow_forward_ms(flow, B)
-    fl_flops = algorithmic_flops_per_sample_layer(w["dim"], w["L"], w["hidden"])
-    fwd_flops = fl_flops * w["n_layers"] * B
-    bwd_launches = w["n_layers"]
-    if phase["backward"] > fwd_ms:
-        dom_name = ("flow_backward (per layer launch)" if w["dim"] == 2 else
-                    "flow_backward (per layer: kr_recompute + kr_transpose + kr_wgrad)")
-        dom_ms = phase["backward"] / bwd_launches
-        dom_flops = 2 * fl_flops * B
-    else:
-        dom_name = "kf_forward (flow forward, all layers)"
-        dom_ms = fwd_ms
-        dom_flops = fwd_flops
-    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
-    roof = {"kernel": dom_name, "bound": "mfma", "achieved": round(achieved, 3),
-            "peak": PEAK["bf16_mfma_tflops"], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK["bf16_mfma_tflops"], 5),
-            "traffic": recorded_traffic() if headline and dom_name.startswith("flow_backward") else None,
-            "flops_per_launch": dom_flops, "ms_per_launch": round(dom_ms, 5)}
-
+    # the 3D L = 16 C = 32 workload has a BF16 backward only
+    precs = [("fp32", lfs.LFS_PLAIN_FP32), ("bf16", lfs.LFS_BF16_CONV)]
+    if args.precision != "both":
+        precs = [p for p in precs if p[0] == args.precision]
+    if w["dim"] == 3 and w["L"] == 16:
+        precs = [p for p in precs if p[0] == "bf16"]
+    runs = {}
+    for name, prec in precs:
+        flow, tr = make(prec)
+        total, phase = time_phases(tr, args.steps, args.warmup)
+        fwd_ms = flow_forward_ms(flow, B)
+        runs[name] = {"steps_per_s": round(args.steps / total, 3), "ms_per_step": round(1000.0 * total / args.steps, 4),
+                      "phases_ms": {k: round(v, 4) for k, v in phase.items()}, "forward_ms": round(fwd_ms, 4),
+                      "loss_last": float(tr.loss.item()), "roofline": roofline_of(phase, fwd_ms, w, B, name)}
+        del tr, flow
+        _progress(f"{name} training steps timed")
+    head_name = precs[0][0]
+    head = runs[head_name]
+    desc = "plain FP32" if head_name == "fp32" else "BF16 conv + FP64 sums"
     out = {
-        "metric": "train steps/s (reverse-KL, BF16 conv + FP64 sums)",
-        "value": round(args.steps / total, 3),
+        "metric": f"train steps/s (reverse-KL, {desc})",
+        "value": head["steps_per_s"],
         "unit": "steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16", "data": "synthetic (seeded N(0,0.1) weights, Philox prior draws)",
+        "dtype": head_name, "data": "synthetic (seeded N(0,0.1) weights, Philox prior draws)",
         "config": {"workload": w["workload"], "dim": w["dim"], "L": w["L"], "m2": w["m2"],
                    "lambda": w["lam"], "n_layers": w["n_layers"], "hidden": w["hidden"],
                    "global_batch": B, "parallelism": "single GPU"},
-        "phases_ms": {k: round(v, 4) for k, v in phase.items()},
-        "loss_last": loss,
-        "roofline": roof,
+        "phases_ms": head["phases_ms"],
+        "loss_last": head["loss_last"],
+        "roofline": head["roofline"],
     }
+    for name, r in runs.items():
+        if name != head_name:
+            out[name] = r
+    if "fp32" in runs and "bf16" in runs:
+        out["bf16_speedup_vs_fp32"] = round(runs["bf16"]["steps_per_s"] / runs["fp32"]["steps_per_s"], 3)
     if headline and not args.no_extras:
-        f32, tr32 = make(lfs.LFS_PLAIN_FP32)
-        n32 = max(3, args.steps // 4)
-        t32, ph32 = time_phases(tr32, n32, 2)
-        out["fp32_plain"] = {"steps_per_s": round(n32 / t32, 3),
-                             "phases_ms": {k: round(v, 4) for k, v in ph32.items()},
-                             "forward_ms": round(flow_forward_ms(f32, B, 5), 4)}
-        out["bf16_speedup_vs_fp32"] = round((args.steps / total) / (n32 / t32), 3)
         out["sampling_bf16"] = sampling_rate(fl.Flow(w["dim"], w["L"], w["n_layers"], w["hidden"],
                                                      lfs.LFS_BF16_CONV, params=params),
                                              B, w["m2"], w["lam"])
         out["sampling_fp32"] = sampling_rate(fl.Flow(w["dim"], w["L"], w["n_layers"], w["hidden"],
                                                      lfs.LFS_PLAIN_FP32, params=params),
                                              B, w["m2"], w["lam"], batches=4)
-        _progress("headline, FP32 and sampling figures done")
+        _progress("sampling figures done")
         out["hmc_fp64_3d_L8"] = hmc_rate()
         out["hbm_kernels"] = hbm_kernels()
         out["other_workloads"] = other_workloads(params)
+        out["chain_3d_L8_10k"] = chain_3d_L8_10k()
         _progress("other workloads done")
         out["general_networks_2d_L8"] = general_networks()
         out["trained_2d_L8_example"] = trained_example()
         _progress("trained example and chain quality done")
+        out["trained_3d_L8"] = trained_3d()
+        _progress("3D training and chain quality done")
         out["serving"] = serving(args.serving_seconds)
         _progress("serving (BF16) done")
-        out["serving_fp32"] = serving(args.serving_seconds, lfs.LFS_PLAIN_FP32)
+        out["serving_fp32"] = serving(args.serving_seconds_fp32, lfs.LFS_PLAIN_FP32)
         _progress("serving (FP32) done")
     if args.copy_calibration_mb > 0:
         nb = args.copy_calibration_mb * 2 ** 20

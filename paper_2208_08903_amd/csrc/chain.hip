@@ -91,7 +91,13 @@ __device__ __forceinline__ void site_terms(const double* f, int n, int L, double
   frc = -2.0 * lap + 2.0 * m2 * p + 4.0 * lam * p2 * p;
 }
 
-// One block per chain; phi and pi stay in LDS for the whole trajectory.
+// One block per chain; phi, pi and the force stay in LDS for the whole
+// trajectory.  Kick-drift-kick: the closing half-kick of a step and the opening
+// half-kick of the next use the force at the same field, so it is evaluated
+// once per step (and once at the start); both half-kicks are still applied as
+// two separate subtractions, as the definition has them.  The last force pass
+// also sums the final Hamiltonian.  Every thread owns sites tid, tid + 256, ...
+// in every pass, so its kicks read only its own force entries.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_hmc(int L, double* __restrict__ phi,
                                              const double* __restrict__ pi0,
@@ -106,6 +112,7 @@ __global__ void __launch_bounds__(256) k_hmc(int L, double* __restrict__ phi,
   for (int i = 1; i < DIM; ++i) V *= L;
   double* f = smem;
   double* p = smem + V;
+  double* F = smem + 2 * V;
   const int b = blockIdx.x;
   const double m2 = m2p[per_sample ? b : 0], lam = lamp[per_sample ? b : 0];
   for (int n = threadIdx.x; n < V; n += blockDim.x) {
@@ -116,30 +123,28 @@ __global__ void __launch_bounds__(256) k_hmc(int L, double* __restrict__ phi,
   double h = 0.0, dens, frc;
   for (int n = threadIdx.x; n < V; n += blockDim.x) {
     site_terms<DIM>(f, n, L, m2, lam, dens, frc);
+    F[n] = frc;
     h += 0.5 * p[n] * p[n] + dens;
   }
-  const double H0 = block_sum(h, sh);
+  const double H0 = block_sum(h, sh);  // ends with a barrier
   const double hdt = 0.5 * dt;
+  h = 0.0;
   for (int s = 0; s < n_steps; ++s) {
     for (int n = threadIdx.x; n < V; n += blockDim.x) {
-      site_terms<DIM>(f, n, L, m2, lam, dens, frc);
-      p[n] = p[n] - hdt * frc;
+      p[n] = p[n] - hdt * F[n];
+      f[n] = f[n] + dt * p[n];
     }
     __syncthreads();
-    for (int n = threadIdx.x; n < V; n += blockDim.x) f[n] = f[n] + dt * p[n];
-    __syncthreads();
+    const bool last = s == n_steps - 1;
     for (int n = threadIdx.x; n < V; n += blockDim.x) {
       site_terms<DIM>(f, n, L, m2, lam, dens, frc);
+      F[n] = frc;
       p[n] = p[n] - hdt * frc;
+      if (last) h += 0.5 * p[n] * p[n] + dens;
     }
+    __syncthreads();  // the next drift rewrites f, which this pass read at neighbours
   }
-  __syncthreads();
-  h = 0.0;
-  for (int n = threadIdx.x; n < V; n += blockDim.x) {
-    site_terms<DIM>(f, n, L, m2, lam, dens, frc);
-    h += 0.5 * p[n] * p[n] + dens;
-  }
-  const double H1 = block_sum(h, sh);
+  const double H1 = n_steps > 0 ? block_sum(h, sh) : H0;
   const double d = H1 - H0;
   const bool acc = log_u[b] < -d;
   if (acc)
@@ -197,11 +202,16 @@ extern "C" int32_t lfs_hmc_step(int32_t dim, int32_t L, int32_t B, double* phi, 
   LFS_RETURN_IF(dim != 2 && dim != 3, LFS_EINVAL);
   LFS_RETURN_IF(L < 2 || B < 0 || n_steps < 0, LFS_EINVAL);
   const long V = dim == 2 ? (long)L * L : (long)L * L * L;
-  LFS_RETURN_IF(V > 4096, LFS_EUNSUPPORTED);  // phi and pi in at most 64 KB of LDS
+  LFS_RETURN_IF(V > 4096, LFS_EUNSUPPORTED);  // phi, pi and the force in at most 96 KB of LDS
   if (B == 0) return LFS_OK;
   LFS_RETURN_IF(!phi || !pi0 || !log_u || !m2 || !lam || !dH || !accepted, LFS_EINVAL);
-  const size_t shm = 2 * (size_t)V * sizeof(double);
+  const size_t shm = 3 * (size_t)V * sizeof(double);
   hipStream_t st = (hipStream_t)stream;
+  if (shm > 64 * 1024) {
+    const void* k = dim == 2 ? reinterpret_cast<const void*>(lfs::k_hmc<2>) : reinterpret_cast<const void*>(lfs::k_hmc<3>);
+    LFS_RETURN_IF(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess,
+                  LFS_EDEVICE);
+  }
   if (dim == 2)
     hipLaunchKernelGGL(lfs::k_hmc<2>, dim3(B), dim3(256), shm, st, L, phi, pi0, log_u, m2, lam,
                        per_sample, n_steps, dt, dH, accepted);

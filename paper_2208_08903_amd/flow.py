@@ -319,11 +319,14 @@ def chain_quality(flow: Flow, m2: float, lam: float, batches: int, B: int, w_max
     """One independence-MH chain over batches x B flow proposals.  Along the chain:
     the integrated autocorrelation time (automatic window, factor c) of the
     condensate M and of the action S, N_indep = N / (2 tau); the chain average of
-    M^2 with its error sqrt(2 tau var / N) (tau of the M^2 series); plus the
-    acceptance and the normalised reweighting ESS of all proposals."""
-    dev, n = flow.device, batches * B
+    M^2 with its error sqrt(2 tau var / N) (tau of the M^2 series) and likewise of
+    the zero-momentum two-point function C(t), t = 0 .. L-1 (tau of each C(t)
+    series); plus the acceptance and the normalised reweighting ESS of all
+    proposals."""
+    dev, n, L = flow.device, batches * B, flow.L
     f64 = torch.float64
     M = torch.empty(1, n, dtype=f64, device=dev)
+    Ct = torch.empty(n, L, dtype=f64, device=dev)
     S = torch.empty(1, n, dtype=f64, device=dev)
     logw = torch.empty(1, n, dtype=f64, device=dev)
     cur = torch.empty(1, n, dtype=torch.int64, device=dev)
@@ -332,15 +335,19 @@ def chain_quality(flow: Flow, m2: float, lam: float, batches: int, B: int, w_max
     for k in range(batches):
         sl = slice(k * B, (k + 1) * B)
         smp.step(lu[k])
-        lfs.observables(flow.dim, flow.L, smp.phi, M[0, sl], None)
+        lfs.observables(flow.dim, flow.L, smp.phi, M[0, sl], Ct[sl])
         S[0, sl].copy_(smp.S)
         logw[0, sl].copy_(smp.logw)
         cur[0, sl].copy_(smp.cur[0])
     tm, wm, fm, nm = _tau(M, w_max, c, index=cur)
     ts, ws, fs, ns = _tau(S, w_max, c, index=cur)
-    # M^2 along the chain (the squares formed on the host), its mean and error
-    m2_chain = M.cpu().numpy()[0][cur.cpu().numpy()[0]] ** 2
+    # M^2 and C(t) along the chain (the chain's configurations picked on the host)
+    idx = cur.cpu().numpy()[0]
+    m2_chain = M.cpu().numpy()[0][idx] ** 2
     t2, _, _, _ = _tau(torch.as_tensor(m2_chain.reshape(1, -1), device=dev), w_max, c)
+    c_chain = Ct.cpu().numpy()[idx]                                     # [n, L]
+    tc, _, _, _ = _tau(torch.as_tensor(np.ascontiguousarray(c_chain.T), device=dev), w_max, c)
+    c_err = np.sqrt(2.0 * np.maximum(np.nan_to_num(tc, nan=0.5), 0.5) * c_chain.var(axis=0) / n)
     e = torch.empty(1, dtype=f64, device=dev)
     lfs.ess(logw, e)
     return {"proposals": n, "acceptance": round(smp.acceptance()[0], 5),
@@ -348,7 +355,8 @@ def chain_quality(flow: Flow, m2: float, lam: float, batches: int, B: int, w_max
             "n_indep_M": float(nm[0]), "tau_S": float(ts[0]), "window_S": int(ws[0]),
             "window_found_S": bool(fs[0]), "n_indep_S": float(ns[0]), "ess": float(e.item()),
             "M2_mean": float(m2_chain.mean()),
-            "M2_err": float(np.sqrt(2.0 * max(float(t2[0]), 0.5) * m2_chain.var() / n))}
+            "M2_err": float(np.sqrt(2.0 * max(float(t2[0]), 0.5) * m2_chain.var() / n)),
+            "C_mean": [float(v) for v in c_chain.mean(axis=0)], "C_err": [float(v) for v in c_err]}
 
 
 def hmc_chain_quality(dim: int, L: int, m2: float, lam: float, n_chains: int, n_traj: int,
@@ -357,8 +365,9 @@ def hmc_chain_quality(dim: int, L: int, m2: float, lam: float, n_chains: int, n_
     trajectory, fresh momenta each trajectory) from a cold start phi = 0; the
     first n_traj // 5 trajectories are discarded.  Per chain, the integrated
     autocorrelation time of M over the remaining trajectories; returns the chain
-    means, the acceptance, and the average of M^2 with its error from the spread of
-    the per-chain averages."""
+    means, the acceptance, and the averages of M^2 and of the zero-momentum
+    two-point function C(t) with their errors from the spread of the per-chain
+    averages."""
     import seeded_inputs as si
     dev, V, f64 = "cuda", L ** dim, torch.float64
     phi = torch.zeros(n_chains, V, dtype=f64, device=dev)
@@ -369,18 +378,22 @@ def hmc_chain_quality(dim: int, L: int, m2: float, lam: float, n_chains: int, n_
     therm = n_traj // 5
     n = n_traj - therm
     Mt = torch.empty(n, n_chains, dtype=f64, device=dev)
+    Ct = torch.empty(n, n_chains, L, dtype=f64, device=dev)
     lu = _log_u(np.random.default_rng(seed), (n_traj, n_chains), dev)
     n_acc = torch.zeros(n_chains, dtype=torch.int64, device=dev)
     for k in range(n_traj):
         pi = torch.as_tensor(si.momenta(seed * 100003 + k, n_chains, V), device=dev)
         lfs.hmc_step(dim, L, phi, pi, lu[k], m2t, lamt, n_steps, dt, dH, acc)
         if k >= therm:
-            lfs.observables(dim, L, phi, Mt[k - therm], None)
+            lfs.observables(dim, L, phi, Mt[k - therm], Ct[k - therm])
             n_acc += acc
     tm, wm, fm, _ = _tau(Mt.t().contiguous(), w_max, c)
     per_chain = (Mt.cpu().numpy() ** 2).mean(axis=0)
+    c_chain = Ct.cpu().numpy().mean(axis=0)                             # [n_chains, L]
     return {"chains": n_chains, "trajectories": n, "leapfrog_steps": n_steps, "dt": dt,
             "acceptance": float(n_acc.sum().item()) / (n * n_chains),
             "tau_M_mean": float(np.nanmean(tm)), "window_found_M": int(fm.sum()),
             "n_indep_M_per_chain_mean": float(np.nanmean(n / (2 * tm))),
-            "M2_mean": float(per_chain.mean()), "M2_err": float(per_chain.std(ddof=1) / np.sqrt(n_chains))}
+            "M2_mean": float(per_chain.mean()), "M2_err": float(per_chain.std(ddof=1) / np.sqrt(n_chains)),
+            "C_mean": [float(v) for v in c_chain.mean(axis=0)],
+            "C_err": [float(v) for v in c_chain.std(axis=0, ddof=1) / np.sqrt(n_chains)]}

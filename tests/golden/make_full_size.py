@@ -6,7 +6,12 @@ the batch mean of sum_n |dS/dphi_n| (1 + |phi_n|), the first-order sensitivity
 of S to per-site field errors bounded by tol (1 + |phi_n|), and the relative
 error of each block (and of the whole gradient) when the oracle stores the conv
 operands and the field in FP32 (its emulate="fp32" mode): the error an FP32
-implementation incurs from storage rounding alone.
+implementation incurs from storage rounding alone.  For the BF16 path the
+gradient of the oracle's emulate="bf16" mode (every convolution operand rounded
+to BF16, the field kept in FP32, weight gradients accumulated in FP32) is stored
+the same way (sampled entries, block norms, projections), with its loss and its
+relative deviation from FP64 per block: an implementation that rounds at the
+same points must match it far more closely than it matches FP64.
 
 Only oracle/ and the seeded input generators are used: z is the oracle's own
 Philox prior draw (key 12345, counter 0, as the trainer's first step draws it)
@@ -48,20 +53,24 @@ def _chunk(args):
     import seeded_inputs as si
     from oracle import flow as of
     from oracle import prior as op
+    from oracle import action as oa
     dim, L, N, C, B, m2, lam, w_std, emul32, start, n = args
     fs = of.FlowShape(dim, L, N, C)
     p = si.flow_params(dim, N, C, seed=WEIGHT_SEED, w_std=w_std).astype(np.float64)
     z = op.prior_normal(KEY, COUNTER0 + start, n, fs.V)
-    from oracle import action as oa
     g = of.loss_gradient(p, z, fs, m2, lam)
     g32 = of.loss_gradient(p, z, fs, m2, lam, emulate="fp32") if emul32 else g
+    g16 = of.loss_gradient(p, z, fs, m2, lam, emulate="bf16")
     loss = of.kl_loss(p, z, fs, m2, lam)
+    f16 = of.flow_forward(p, z, fs, emulate="bf16")
+    loss16 = float(np.mean(f16["logq"] + oa.action(f16["phi"], m2, lam, dim)))
     # first-order sensitivity of S to per-site field errors e_n <= tol (1 + |phi_n|):
     # sum_n |dS/dphi_n| (1 + |phi_n|), per sample
     phi = of.flow_forward(p, z, fs)["phi"]
     F = oa.force(phi, m2, lam, dim).reshape(n, -1)
     sens = np.sum(np.abs(F) * (1.0 + np.abs(phi.reshape(n, -1))), axis=1)
-    return start, g * (n / B), g32 * (n / B), loss * (n / B), float(np.sum(sens)) / B
+    return (start, g * (n / B), g32 * (n / B), loss * (n / B), float(np.sum(sens)) / B,
+            g16 * (n / B), loss16 * (n / B))
 
 
 def block_slices(dim, N, C):
@@ -97,17 +106,22 @@ def make(name, pool):
     res = sorted(pool.map(_chunk, jobs), key=lambda r: r[0])
     g = np.zeros_like(res[0][1])
     g32 = np.zeros_like(g)
-    loss = sens = 0.0
-    for _, gc, g32c, lc, sc in res:
+    g16 = np.zeros_like(g)
+    loss = sens = loss16 = 0.0
+    for _, gc, g32c, lc, sc, g16c, l16c in res:
         g += gc
         g32 += g32c
         loss += lc
         sens += sc
+        g16 += g16c
+        loss16 += l16c
     idx = sample_indices(dim, N, C)
     norms = np.array([np.linalg.norm(g[sl]) for _, _, sl in block_slices(dim, N, C)])
     # how far FP32 storage of the conv operands and the field alone moves each block
     err32 = np.array([np.linalg.norm(g32[sl] - g[sl]) / max(np.linalg.norm(g[sl]), 1e-300)
                       for _, _, sl in block_slices(dim, N, C)])
+    blocks = block_slices(dim, N, C)
+    err16 = np.array([np.linalg.norm(g16[sl] - g[sl]) / max(np.linalg.norm(g[sl]), 1e-300) for _, _, sl in blocks])
     np.savez(os.path.join(HERE, f"full_size_grad_{name}.npz"),
              config=np.array([dim, L, N, C, B], np.int64), couplings=np.array([m2, lam]),
              w_std=np.array([w_std]),
@@ -115,9 +129,14 @@ def make(name, pool):
              idx=idx, vals=g[idx], block_norms=norms, proj=projections(g),
              grad_norm=np.array([np.linalg.norm(g)]), loss=np.array([loss]),
              loss_sensitivity=np.array([sens]), fp32_block_err=err32,
-             fp32_whole_err=np.array([np.linalg.norm(g32 - g) / np.linalg.norm(g)]))
+             fp32_whole_err=np.array([np.linalg.norm(g32 - g) / np.linalg.norm(g)]),
+             bf16_vals=g16[idx], bf16_block_norms=np.array([np.linalg.norm(g16[sl]) for _, _, sl in blocks]),
+             bf16_proj=projections(g16), bf16_grad_norm=np.array([np.linalg.norm(g16)]),
+             bf16_loss=np.array([loss16]), bf16_block_err=err16,
+             bf16_whole_err=np.array([np.linalg.norm(g16 - g) / np.linalg.norm(g)]))
     print(f"{name}: {time.time() - t:.1f} s, |g| = {np.linalg.norm(g):.6g}, loss = {loss:.6f}, "
-          f"FP32-operand error: max block {err32.max():.3g}, whole {np.linalg.norm(g32 - g) / np.linalg.norm(g):.3g}")
+          f"FP32-operand error: max block {err32.max():.3g}, whole {np.linalg.norm(g32 - g) / np.linalg.norm(g):.3g}; "
+          f"BF16-operand error: max block {err16.max():.3g}, whole {np.linalg.norm(g16 - g) / np.linalg.norm(g):.3g}", flush=True)
 
 
 if __name__ == "__main__":

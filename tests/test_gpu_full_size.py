@@ -25,11 +25,17 @@ Tolerances are those of the small-size parity tests:
   signs; numpy's float32 sums are pairwise (about 18 additions deep), the
   kernels' chains (per-lane sums over a workgroup's tiles, lane and wave trees,
   the partials reduction) about 56, hence 3x, times a margin of 4.
-  BF16: whole 0.1, per block 0.4.  Flow outputs: FP32 |dphi| <= 1e-5 (T/9)(1+|phi|),
-  |dlogq| <= 1e-4 V; BF16 |dphi| <= 0.02 (T/9)(1+|phi|),
-  |dlogq| <= 0.05 sqrt(V N) + 1e-4 V.  Loss (a batch mean of log q + S): the
-  log q bound plus the field bound propagated to S to first order, i.e. the
-  phi tolerance times the oracle's batch mean of sum_n |dS/dphi_n| (1 + |phi_n|).
+  BF16 gradient: against the oracle's emulate="bf16" gradient of the same step
+  (stored beside the FP64 one), per block 1e-2 relative (norms and sampled
+  entries) and whole vector 5e-3, or a quarter of the emulation's own relative
+  distance from FP64 where that is larger; against FP64, each block's norm within
+  3 times the emulation's own relative distance.  Flow outputs: FP32 |dphi| <= 1e-5
+  (T/9)(1+|phi|), |dlogq| <= 1e-4 V; BF16 as the small-size tests, against the
+  emulation of the same samples.  Loss (a batch mean of log q + S): FP32 the
+  log q bound plus the field bound propagated to S to first order, i.e. the phi
+  tolerance times the oracle's batch mean of sum_n |dS/dphi_n| (1 + |phi_n|);
+  BF16 against the emulation's loss: the element-wise field bound 1e-2 (T/9)
+  (1+|phi|) propagated the same way, plus the emulation's own distance from FP64.
 """
 import os
 
@@ -44,6 +50,7 @@ from paper_2208_08903_amd import flow as fl
 from paper_2208_08903_amd import lfs
 
 from .gpu_util import host
+from .test_gpu_parity import _check_forward_bf16
 
 pytestmark = pytest.mark.gpu
 
@@ -51,10 +58,9 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 PRECISIONS = [lfs.LFS_BF16_CONV, lfs.LFS_PLAIN_FP32]
 
 
-def _tol(precision, T, V, N):
-    if precision == lfs.LFS_PLAIN_FP32:
-        return dict(phi=1e-5 * T / 9, logq=1e-4 * V, g_block=1e-4, g_whole=1e-4)
-    return dict(phi=0.02 * T / 9, logq=0.05 * np.sqrt(V * N) + 1e-4 * V, g_block=0.4, g_whole=0.1)
+def _tol(T, V):
+    """FP32 bounds (BF16 results are held to the emulation instead)."""
+    return dict(phi=1e-5 * T / 9, logq=1e-4 * V, g_block=1e-4, g_whole=1e-4)
 
 
 def _blocks(dim, N, C):
@@ -86,39 +92,77 @@ def test_full_size_training_gradient(name, precision):
     torch.cuda.synchronize()
     grad = host(tr.gparams).astype(np.float64)
     loss = float(tr.loss.item())
-    tol = _tol(precision, 3 ** dim, L ** dim, N)
+    if precision == lfs.LFS_BF16_CONV:
+        _check_bf16_gradient(g, grad, loss, dim, N, C)
+        return
+    tol = _tol(3 ** dim, L ** dim)
     blk_tol = np.full(len(g["block_norms"]), tol["g_block"])
     whole_tol = tol["g_whole"]
-    if precision == lfs.LFS_PLAIN_FP32:
-        # 12x the oracle's own error under FP32 storage and accumulation (see the header)
-        blk_tol = np.maximum(blk_tol, 12 * g["fp32_block_err"])
-        whole_tol = max(whole_tol, 12 * float(g["fp32_whole_err"][0]))
+    # 12x the oracle's own error under FP32 storage and accumulation (see the header)
+    blk_tol = np.maximum(blk_tol, 12 * g["fp32_block_err"])
+    whole_tol = max(whole_tol, 12 * float(g["fp32_whole_err"][0]))
 
     # log q's bound plus S's first-order response to the field bound
     assert abs(loss - float(g["loss"][0])) <= tol["logq"] + tol["phi"] * float(g["loss_sensitivity"][0])
-    # every block's norm; the sampled entries of each block against its norm
-    idx, vals = g["idx"], g["vals"]
+    _check_stored_gradient(grad, dim, N, C, g["idx"], g["vals"], g["block_norms"], blk_tol, g["proj"],
+                           int(g["seeds"][3]), whole_tol, float(g["grad_norm"][0]))
+
+
+def _check_stored_gradient(grad, dim, N, C, idx, vals, norms, blk_tol, proj, pseed, whole_tol, gnorm):
+    """Every block's norm and its sampled entries against the stored ones, and the whole
+    vector through the stored seeded projections."""
     for k, sl in enumerate(_blocks(dim, N, C)):
-        ref = float(g["block_norms"][k])
+        ref = float(norms[k])
         got = np.linalg.norm(grad[sl])
         assert abs(got - ref) <= blk_tol[k] * ref + 1e-30, (k, got, ref)
         sel = (idx >= sl.start) & (idx < sl.stop)
         d = np.linalg.norm(grad[idx[sel]] - vals[sel])
         assert d <= blk_tol[k] * ref + 1e-30, (k, d, ref)
-    # whole vector: R (grad - g_oracle) = R grad - stored projections
-    R = np.random.default_rng(pseed).standard_normal((g["proj"].size, grad.size))
-    dproj = R @ grad - g["proj"]
-    assert np.max(np.abs(dproj)) <= 5 * whole_tol * float(g["grad_norm"][0])
+    # whole vector: R (grad - g_ref) = R grad - stored projections
+    R = np.random.default_rng(pseed).standard_normal((proj.size, grad.size))
+    dproj = R @ grad - proj
+    assert np.max(np.abs(dproj)) <= 5 * whole_tol * gnorm
 
 
-def _sampled_forward_check(f, params, z_host_key, c0, phi, logq, samples, precision):
+def _check_bf16_gradient(g, grad, loss, dim, N, C):
+    """A BF16 step against the stored emulate="bf16" gradient and loss, and its block norms
+    against FP64 within 3 times the emulation's own distance."""
+    loss16, loss64 = float(g["bf16_loss"][0]), float(g["loss"][0])
+    norms16 = g["bf16_block_norms"]
+    print(f"  bf16 full-size step: loss {loss:.6f}, emulation {loss16:.6f}, FP64 {loss64:.6f}; "
+          f"largest block error of the emulation vs FP64 {float(np.max(g['bf16_block_err'])):.3e}", flush=True)
+    # the element-wise field bound against the emulation propagated to S to first order,
+    # plus the log q bound (the emulation's own distance from FP64)
+    T, V = 3 ** dim, g["config"][1] ** dim
+    bound = 1e-2 * T / 9 * float(g["loss_sensitivity"][0]) + abs(loss16 - loss64) + 1e-6 * V * N
+    assert abs(loss - loss16) <= bound, (loss, loss16, loss64, bound)
+    # 1e-2 per block and 5e-3 whole, or a quarter of the emulation's own distance from FP64
+    # where the flow amplifies rounding more (the 3D L=8 random-init flow: 25 % on its first
+    # block; the kernel is then still four times closer to the emulation than to FP64)
+    blk = np.maximum(1e-2, 0.25 * g["bf16_block_err"])
+    whole = max(5e-3, 0.25 * float(g["bf16_whole_err"][0]))
+    _check_stored_gradient(grad, dim, N, C, g["idx"], g["bf16_vals"], norms16, blk,
+                           g["bf16_proj"], int(g["seeds"][3]), whole, float(g["bf16_grad_norm"][0]))
+    for k, sl in enumerate(_blocks(dim, N, C)):
+        ref = float(g["block_norms"][k])
+        got = np.linalg.norm(grad[sl])
+        assert abs(got - ref) <= (3 * float(g["bf16_block_err"][k]) + 1e-6) * ref, (k, got, ref)
+
+
+def _sampled_forward_check(f, params, z_host_key, c0, phi, logq, samples, precision, rho=None):
     dim, L, N, C = f.dim, f.L, f.n_layers, f.hidden
     fs = of.FlowShape(dim, L, N, C)
-    tol = _tol(precision, 3 ** dim, fs.V, N)
     p = params.astype(np.float64)
-    for b in samples:
-        z = op.prior_normal(z_host_key, c0 + int(b), 1, fs.V)
-        o = of.flow_forward(p, z, fs)
+    samples = list(samples)
+    z = np.concatenate([op.prior_normal(z_host_key, c0 + int(b), 1, fs.V) for b in samples])
+    if precision == lfs.LFS_BF16_CONV:
+        ref = of.flow_forward(p, z, fs)
+        _check_forward_bf16(p, z, fs, phi[samples].astype(np.float64), logq[samples], None, ref,
+                            **({} if rho is None else {"rho": rho}))
+        return
+    tol = _tol(3 ** dim, fs.V)
+    for k, b in enumerate(samples):
+        o = of.flow_forward(p, z[k:k + 1], fs)
         po = o["phi"].reshape(-1)
         pg = phi[b].astype(np.float64)
         assert np.all(np.abs(pg - po) <= tol["phi"] * (1 + np.abs(po))), b
@@ -156,8 +200,11 @@ def test_full_size_3d_L16_C32_sampling_sampled():
     lu = torch.as_tensor(si.log_uniforms(5, (1, B)), device="cuda")
     smp.step(lu)
     torch.cuda.synchronize()
+    # 16 layers of fan-in 864 spread the few BF16 roundings the FP32 sums flip over whole
+    # samples: the share of the distance from FP64 not explained by the emulation is up to
+    # ~0.8 here (the rounding points themselves are pinned exactly by the exact-operand tests)
     _sampled_forward_check(f, params, 4242, 0, host(smp.phi), host(smp.logq), [0, 2049, 4095],
-                           lfs.LFS_BF16_CONV)
+                           lfs.LFS_BF16_CONV, rho=1.0)
 
 
 def test_full_size_3d_L16_C32_batch_position_independent():
@@ -194,10 +241,13 @@ def test_full_size_2d_L8_chain_batch(precision):
     smp.step(lu)
     torch.cuda.synchronize()
     fs = of.FlowShape(2, 8, 16, 8)
-    tol = _tol(precision, 9, 64, 16)
+    tol = _tol(9, 64)
     z = op.prior_normal(12, 0, B, fs.V)
     o = of.flow_forward(params.astype(np.float64), z, fs)
-    po = o["phi"].reshape(B, -1)
     pg = host(smp.phi).astype(np.float64)
+    if precision == lfs.LFS_BF16_CONV:
+        _check_forward_bf16(params.astype(np.float64), z, fs, pg, host(smp.logq), None, o)
+        return
+    po = o["phi"].reshape(B, -1)
     assert np.all(np.abs(pg - po) <= tol["phi"] * (1 + np.abs(po)))
     assert np.all(np.abs(host(smp.logq) - o["logq"]) <= tol["logq"])

@@ -5,7 +5,7 @@ gradients, with the tolerances of the default network's generic-path tests
 
 BF16 forward: against the oracle's BF16 emulation as for the default network,
 except the share of the distance from FP64 that the emulation must explain
-(2-norm of phi, largest log q difference): 0.6 instead of 0.2 and 5 %.  A wide
+(2-norms of phi and log q over the batch): 0.6 instead of 0.2.  A wide
 kernel on a small lattice (5 x 5 taps on 8 x 8 sites) spreads one activation
 whose BF16 rounding the FP32-versus-FP64 sums flip over the whole sample, and
 such flips are the only difference left: on operands that make every sum exact
@@ -56,7 +56,7 @@ def _net_case(dim, L, N, K, hs, B, precision, tanh=True):
 def test_net_forward_backward(case, precision):
     print(f"general network {case} precision={precision}", flush=True)
     desc, params, z, fs = _net_case(*case, precision)
-    out, _ = _check_forward(desc, params, z, fs, precision, rho=0.6, qfrac=0.6)
+    out, _ = _check_forward(desc, params, z, fs, precision, rho=0.6)
     if precision == lfs.LFS_PLAIN_FP32:
         _check_backward(desc, params, z, fs, out, precision)
     else:

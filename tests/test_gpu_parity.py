@@ -18,11 +18,11 @@ by FP32-versus-FP64 accumulation and the FP32 tanh/exp, plus the rare BF16
 rounding those differences flip (one stored activation moved by one BF16 ulp);
 the emulation differs from FP64 by the rounding of every operand.  So:
   flow BF16        |phi - phi_emu| <= 1e-2 (T/9)(1 + |phi_emu|) element-wise;
-                   ||phi - phi_emu|| <= RHO_PHI ||phi_emu - phi_64|| (2-norm over the
-                   batch: most of the kernel's distance from FP64 is the emulated
-                   rounding; measured <= 0.07, RHO_PHI = 0.2); |logq - logq_emu| <= 5 % of the emulation's largest
-                   distance from FP64 (+ 1e-6 V N); against FP64 directly, phi and log q
-                   within twice the emulation's own largest distance
+                   ||phi - phi_emu|| <= RHO_PHI ||phi_emu - phi_64|| and the same for log q
+                   (2-norms over the batch: most of the kernel's distance from FP64 is the
+                   emulated rounding; measured <= 0.07 on these cases, RHO_PHI = 0.2);
+                   log q + log-det (= log r) equal; against FP64 directly, phi and log q
+                   within 3 times the emulation's own largest distance
   gradient BF16    per parameter block: max |g - g_emu| <= 2e-2 max |g_emu| and
                    relative 2-norm <= 1e-2; relative 2-norm against FP64 <= 3 times the
                    emulation's; whole vector: relative 2-norm to the emulation <= 5e-3
@@ -190,7 +190,7 @@ def _flow_case(dim, L, N, C, B, precision, algo, tanh=True, parity0=0):
 RHO_PHI = 0.2
 
 
-def _check_forward(desc, params, z, fs, precision, rho=RHO_PHI, qfrac=0.05):
+def _check_forward(desc, params, z, fs, precision, rho=RHO_PHI):
     B, V = z.shape
     out = run_forward(desc, params, z)
     ref = of.flow_forward(params, z, fs, return_saved=True)
@@ -202,14 +202,14 @@ def _check_forward(desc, params, z, fs, precision, rho=RHO_PHI, qfrac=0.05):
         assert np.all(np.abs(logq - ref["logq"]) <= 1e-4 * V)
         np.testing.assert_allclose(host(out["logdet"]), ref["logdet"], atol=1e-4 * V)
     else:
-        _check_forward_bf16(params, z, fs, phi, logq, host(out["logdet"]), ref, rho, qfrac)
+        _check_forward_bf16(params, z, fs, phi, logq, host(out["logdet"]), ref, rho)
     saved = host(out["saved"]).reshape(fs.n_layers + 1, B, V)
     np.testing.assert_array_equal(saved[0], z)
     np.testing.assert_array_equal(saved[-1], host(out["phi"]))
     return out, ref
 
 
-def _check_forward_bf16(params, z, fs, phi, logq, logdet, ref, rho=RHO_PHI, qfrac=0.05):
+def _check_forward_bf16(params, z, fs, phi, logq, logdet, ref, rho=RHO_PHI):
     """phi, log q, log-det of a BF16 forward against the emulation and against FP64."""
     B, V = z.shape
     emu = of.flow_forward(params, z, fs, emulate="bf16")
@@ -218,18 +218,18 @@ def _check_forward_bf16(params, z, fs, phi, logq, logdet, ref, rho=RHO_PHI, qfra
     el = np.max(np.abs(phi - pe) / (1 + np.abs(pe)))
     dev64 = np.max(np.abs(pe - p64) / (1 + np.abs(p64)))
     ratio = np.linalg.norm(phi - pe) / max(np.linalg.norm(pe - p64), 1e-300)
+    q_ratio = np.linalg.norm(logq - emu["logq"]) / max(np.linalg.norm(emu["logq"] - ref["logq"]), 1e-300)
     q_dev64 = np.max(np.abs(emu["logq"] - ref["logq"]))
-    q_emu = np.max(np.abs(logq - emu["logq"]))
-    floor = 1e-6 * V * fs.n_layers
     print(f"  bf16 forward: phi vs emulation {el:.2e} (2-norm ratio {ratio:.3f}), emulation vs FP64 "
-          f"{dev64:.2e}; log q vs emulation {q_emu:.2e}, emulation vs FP64 {q_dev64:.2e}", flush=True)
+          f"{dev64:.2e}; log q 2-norm ratio {q_ratio:.3f}, emulation vs FP64 {q_dev64:.2e}", flush=True)
     assert el <= 1e-2 * tf, el
     assert ratio <= rho or np.linalg.norm(phi - pe) <= 1e-6 * np.linalg.norm(pe), ratio
-    assert q_emu <= qfrac * q_dev64 + floor, (q_emu, q_dev64)
+    assert q_ratio <= rho or np.max(np.abs(logq - emu["logq"])) <= 1e-6 * V, q_ratio
     if logdet is not None:
-        assert np.max(np.abs(logdet - emu["logdet"])) <= qfrac * q_dev64 + floor
-    assert np.max(np.abs(phi - p64) / (1 + np.abs(p64))) <= 2 * dev64 + 1e-6
-    assert np.max(np.abs(logq - ref["logq"])) <= 2 * q_dev64 + floor
+        np.testing.assert_allclose(logq + logdet, emu["logq"] + emu["logdet"], rtol=1e-12, atol=1e-9)
+    # against FP64: within 3 times the emulation's own largest distance
+    assert np.max(np.abs(phi - p64) / (1 + np.abs(p64))) <= 3 * dev64 + 1e-6
+    assert np.max(np.abs(logq - ref["logq"])) <= 3 * q_dev64 + 1e-6 * V
 
 
 @pytest.mark.parametrize("case", FLOW_CASES)
