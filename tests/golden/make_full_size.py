@@ -43,6 +43,10 @@ CONFIGS = {
     "2d_L32_C16_B1024": (2, 32, 16, 16, 1024, -4.0, 8.0, 0.1, True),
     "3d_L8_C16_B512": (3, 8, 12, 16, 512, -4.0, 5.0, 0.1, True),
     "3d_L16_C32_B256": (3, 16, 16, 32, 256, -4.0, 5.0, 0.05, False),
+    # the 3D L=8 step again at N(0, 0.05^2) weights: at N(0, 0.1^2) the flow's loss is ~1e10
+    # and BF16 rounding moves its gradient blocks by up to 25 %, too ill-conditioned for
+    # tight bounds; here the same kernels are held to the tight ones
+    "3d_L8_C16_B512_w05": (3, 8, 12, 16, 512, -4.0, 5.0, 0.05, True),
 }
 KEY, COUNTER0, WEIGHT_SEED = 12345, 0, 2021
 PROJ_SEED, N_PROJ, PER_BLOCK = 4242, 32, 12

@@ -1,8 +1,9 @@
 """The HIP path at the workloads' full sizes, in the launch configuration the
 benchmark times, against the FP64 oracle.
 
-Training steps (2D L=32 C=16 at batch 1024, 3D L=8 C=16 at batch 512, 3D
-L=16 C=32 at batch 256 with N(0, 0.05^2) weights, BF16 only): one
+Training steps (2D L=32 C=16 at batch 1024, 3D L=8 C=16 at batch 512 with
+N(0, 0.1^2) and with N(0, 0.05^2) weights, 3D L=16 C=32 at batch 256 with
+N(0, 0.05^2) weights, BF16 only): one
 trainer step's loss and gradient (the trainer's own prior draw, forward and
 backward, i.e. the same kernels, grids and workspace as the timed step) against
 the oracle's gradient of the same step, stored by tests/golden/make_full_size.py
@@ -27,8 +28,10 @@ Tolerances are those of the small-size parity tests:
   the partials reduction) about 56, hence 3x, times a margin of 4.
   BF16 gradient: against the oracle's emulate="bf16" gradient of the same step
   (stored beside the FP64 one), per block 1e-2 relative (norms and sampled
-  entries) and whole vector 5e-3, or a quarter of the emulation's own relative
-  distance from FP64 where that is larger; against FP64, each block's norm within
+  entries) and whole vector 5e-3 (for the 3D L=8 flow at N(0, 0.1^2) weights,
+  whose loss is ~1e10: 2 % per block or the emulation's own relative distance
+  from FP64 where that is larger, half of it whole; the same step at N(0, 0.05^2)
+  has the tight bounds); against FP64, each block's norm within
   3 times the emulation's own relative distance.  Flow outputs: FP32 |dphi| <= 1e-5
   (T/9)(1+|phi|), |dlogq| <= 1e-4 V; BF16 as the small-size tests, against the
   emulation of the same samples.  Loss (a batch mean of log q + S): FP32 the
@@ -75,6 +78,7 @@ def _blocks(dim, N, C):
 @pytest.mark.parametrize("name,precision", [
     ("2d_L32_C16_B1024", lfs.LFS_BF16_CONV), ("2d_L32_C16_B1024", lfs.LFS_PLAIN_FP32),
     ("3d_L8_C16_B512", lfs.LFS_BF16_CONV), ("3d_L8_C16_B512", lfs.LFS_PLAIN_FP32),
+    ("3d_L8_C16_B512_w05", lfs.LFS_BF16_CONV), ("3d_L8_C16_B512_w05", lfs.LFS_PLAIN_FP32),
     ("3d_L16_C32_B256", lfs.LFS_BF16_CONV)])
 def test_full_size_training_gradient(name, precision):
     g = np.load(os.path.join(GOLDEN, f"full_size_grad_{name}.npz"), allow_pickle=False)
@@ -93,7 +97,7 @@ def test_full_size_training_gradient(name, precision):
     grad = host(tr.gparams).astype(np.float64)
     loss = float(tr.loss.item())
     if precision == lfs.LFS_BF16_CONV:
-        _check_bf16_gradient(g, grad, loss, dim, N, C)
+        _check_bf16_gradient(g, grad, loss, dim, N, C, ill_conditioned=w_std >= 0.1 and dim == 3)
         return
     tol = _tol(3 ** dim, L ** dim)
     blk_tol = np.full(len(g["block_norms"]), tol["g_block"])
@@ -124,7 +128,7 @@ def _check_stored_gradient(grad, dim, N, C, idx, vals, norms, blk_tol, proj, pse
     assert np.max(np.abs(dproj)) <= 5 * whole_tol * gnorm
 
 
-def _check_bf16_gradient(g, grad, loss, dim, N, C):
+def _check_bf16_gradient(g, grad, loss, dim, N, C, ill_conditioned=False):
     """A BF16 step against the stored emulate="bf16" gradient and loss, and its block norms
     against FP64 within 3 times the emulation's own distance."""
     loss16, loss64 = float(g["bf16_loss"][0]), float(g["loss"][0])
@@ -136,11 +140,17 @@ def _check_bf16_gradient(g, grad, loss, dim, N, C):
     T, V = 3 ** dim, g["config"][1] ** dim
     bound = 1e-2 * T / 9 * float(g["loss_sensitivity"][0]) + abs(loss16 - loss64) + 1e-6 * V * N
     assert abs(loss - loss16) <= bound, (loss, loss16, loss64, bound)
-    # 1e-2 per block and 5e-3 whole, or a quarter of the emulation's own distance from FP64
-    # where the flow amplifies rounding more (the 3D L=8 random-init flow: 25 % on its first
-    # block; the kernel is then still four times closer to the emulation than to FP64)
-    blk = np.maximum(1e-2, 0.25 * g["bf16_block_err"])
-    whole = max(5e-3, 0.25 * float(g["bf16_whole_err"][0]))
+    # 1e-2 per block and 5e-3 whole.  The 3D L=8 flow at the workload's N(0, 0.1^2) weights
+    # (loss ~1e10) amplifies rounding so much that the emulation itself is 1-25 % from FP64
+    # per block and the BF16 roundings that FP32-versus-FP64 sums flip move the kernel by
+    # 1-4 %: there a block must be within 2 % of the emulation or no further from it than
+    # the emulation is from FP64, the whole vector within half the emulation's distance;
+    # the same step at N(0, 0.05^2) weights is held to the tight bounds
+    if ill_conditioned:
+        blk = np.maximum(2e-2, g["bf16_block_err"])
+        whole = max(5e-3, 0.5 * float(g["bf16_whole_err"][0]))
+    else:
+        blk, whole = np.full(len(norms16), 1e-2), 5e-3
     _check_stored_gradient(grad, dim, N, C, g["idx"], g["bf16_vals"], norms16, blk,
                            g["bf16_proj"], int(g["seeds"][3]), whole, float(g["bf16_grad_norm"][0]))
     for k, sl in enumerate(_blocks(dim, N, C)):
