@@ -6,7 +6,8 @@
 // Per layer l (frozen parity f = (l + parity0) mod 2, active parity 1 - f):
 //   conv1: h1 = leaky(W1 * mask_F x + b1)   over all V sites   (K = T taps)
 //   conv2: h2 = leaky(W2 * h1 + b2)         over all V sites   (K = T C)
-//   conv3: (o0, o1) = W3 * h2 + b3          at the V/2 active sites only
+//   conv3: (o0, o1) = W3 * h2 + b3          at the V/2 active sites only (FP32: on the
+//          4x4 matrix-core blocks, see quad_conv)
 //          x <- x exp(s) + t, s = tanh(o0) (or o0), t = o1; logdet += sum s
 // Three workgroup barriers per layer separate the phases.
 #include <type_traits>
@@ -65,7 +66,8 @@ __global__ void __launch_bounds__(NT) kf_forward(
       // pass: conv1's and conv2's here, conv3's when conv2 starts; otherwise
       // each pass fetches its own.
       constexpr int NA3 = Cfg::X4 ? 4 : 1;
-      u32x4 A1[LF.nct][LF.k1], A2[LF.nct][LF.k2], A3[NA3][LF.k2];
+      constexpr int KA3 = Cfg::Q3 ? 1 : LF.k2;  // quad conv3 fetches its fragments per chunk
+      u32x4 A1[LF.nct][LF.k1], A2[LF.nct][LF.k2], A3[NA3][KA3];
       auto load_a1 = [&]() {
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct)
@@ -79,11 +81,13 @@ __global__ void __launch_bounds__(NT) kf_forward(
           for (int c = 0; c < LF.k2; ++c) A2[ct][c] = fl[(LF.off2 + ct * LF.k2 + c) * 64];
       };
       auto load_a3 = [&]() {
+        if constexpr (!Cfg::Q3) {
 #pragma unroll
-        for (int c = 0; c < LF.k2; ++c) {
-          A3[0][c] = fl[(LF.off3 + c) * 64];
+          for (int c = 0; c < LF.k2; ++c) {
+            A3[0][c] = fl[(LF.off3 + c) * 64];
 #pragma unroll
-          for (int u = 1; u < NA3; ++u) A3[u][c] = fl[(LF.off3q + (u - 1) * LF.k2 + c) * 64];
+            for (int u = 1; u < NA3; ++u) A3[u][c] = fl[(LF.off3q + (u - 1) * LF.k2 + c) * 64];
+          }
         }
       };
       if constexpr (Cfg::PFA) {
@@ -144,7 +148,26 @@ __global__ void __launch_bounds__(NT) kf_forward(
       __syncthreads();
       // conv3 at the active sites, affine update and log-det
       if constexpr (!Cfg::PFA) load_a3();
-      if constexpr (Cfg::X4) {
+      if constexpr (Cfg::Q3) {
+        // FP32: 64 active sites per wave pass, one per lane, on the 4x4 blocks; every
+        // lane updates its own site
+        const int apar = fpar ^ 1;
+        constexpr int NG = (V / 2 + 63) / 64;
+        const f32x4 b3{pl[off_b3], pl[off_b3 + 1], 0.f, 0.f};
+        for (int gi = w; gi < NG; gi += NW) {
+          const int a = gi * 64 + lane;
+          const bool valid = a < V / 2;
+          const int n = G::half_site(valid ? a : 0, apar), p = LY::idx(n);
+          const f32x4 o = quad_conv<LF.k3>(fl + LF.off3 * 64, b3,
+                                           [&](int q) { return gather_q<LY, C>(h2, n, p, q); });
+          if (valid) {
+            const float s = final_tanh ? fast_tanh(o[0]) : o[0];
+            const float xn = xs[p] * fast_exp(s) + o[1];
+            LY::copies(n, [&](int q) { xs[q] = xn; });
+            ld += (R)s;
+          }
+        }
+      } else if constexpr (Cfg::X4) {
         // four tiles share an accumulator: chunk c of tile u uses the fragments with
         // the outputs at rows 4u, 4u+1, so lane group j ends with tile j's s and t
         // and the epilogue runs on all 64 lanes (two chains: tiles 0-1 and 2-3)
@@ -232,7 +255,7 @@ int32_t launch_forward(const FlowGeom& g, const float* params, int B, const floa
   tab.count = 3;
   tab.s[0] = FragSpec{0, (int)g.off_W1, 1, C, C, LF.nct, LF.k1, LF.off1, 1, 0};
   tab.s[1] = FragSpec{0, (int)g.off_W2, C, C, C, LF.nct, LF.k2, LF.off2, 0, 0};
-  tab.s[2] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, LF.k2, LF.off3, 0, 0};
+  tab.s[2] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, LF.k3, LF.off3, 0, 0, LF.quad ? 1 : 0};
   if (LF.x4)
     for (int u = 1; u < 4; ++u)
       tab.s[tab.count++] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, LF.k2, LF.off3q + (u - 1) * LF.k2, 0, 4 * u};

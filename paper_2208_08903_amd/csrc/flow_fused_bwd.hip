@@ -5,6 +5,7 @@
 //
 //   recompute  h1 = leaky(W1 * mask_F x + b1), h2 = leaky(W2 * h1 + b2),
 //              (o0, o1) = W3 * h2 + b3 at the active sites, s = tanh(o0), t = o1
+//              (FP32: conv3 and conv1^T on the 4x4 matrix-core blocks, quad_conv)
 //   affine     g_t = g_y, g_s = g_y x e^s + g_logdet, g_o0 = g_s (1 - s^2),
 //              g_x(active) = g_y e^s
 //   conv3^T    g_a2 = leaky'(h2) (W3^T * g_o)        dW3 += g_o (x) h2
@@ -102,11 +103,14 @@ struct BwdCfg {
   // least that many active-site tiles per wave, else one
   static constexpr int TPW3 = V / 32 / NW;
   static constexpr int QU3 = !(T == 9 && BF16) ? 1 : (NT == 256 && TPW3 >= 4) ? 4 : (TPW3 >= 2 ? 2 : 1);
-  static constexpr LayerFrags LF = layer_frags(T, C, BF16, QU3 == 4);
+  // FP32: conv3 (recompute) and conv1^T (one output channel) on the 4x4 matrix-core
+  // blocks (quad fragments), every lane with its own site's result
+  static constexpr LayerFrags LF = layer_frags(T, C, BF16, QU3 == 4, !BF16);
+  static constexpr int K1T = BF16 ? LF.k2 : T * C / 4;  // conv1^T fragments
   static constexpr int OFF3T = LF.total;
   static constexpr int OFF2T = OFF3T + LF.nct * KT3;
   static constexpr int OFF1T = OFF2T + LF.nct * LF.k2;
-  static constexpr int FRAGS = OFF1T + LF.k2;
+  static constexpr int FRAGS = OFF1T + K1T;
   // The layer's weight fragments are the same for every sample of the launch:
   // where they fit next to the sample state without costing a workgroup per
   // CU, they are copied to LDS once per launch instead of being fetched from
@@ -416,7 +420,19 @@ __global__ void __launch_bounds__(NT) kf_backward(
         }
       };
       const float bs = pl[off_b3];
-      if constexpr (Cfg::QU3 == 2) {
+      if constexpr (!BF16) {
+        // 64 active sites per wave pass, one per lane (4x4 blocks: o0 in register 0)
+        constexpr int NG = (V / 2 + 63) / 64;
+        const f32x4 b3{bs, 0.f, 0.f, 0.f};
+        for (int gi = w; gi < NG; gi += NW) {
+          const int a = gi * 64 + lane;
+          const bool valid = a < V / 2;
+          const int n = G::half_site(valid ? a : 0, apar), p = LY::idx(n);
+          const f32x4 o = quad_conv<LF.k3>(fr + LF.off3 * 64, b3,
+                                           [&](int q) { return gather_q<LY, C>(h2s, n, p, q); });
+          if (valid) affine_bwd(n, o[0]);
+        }
+      } else if constexpr (Cfg::QU3 == 2) {
         // two tiles with the plain fragments; tile 1's s moves from lane group 0 to
         // lane group 1, so the affine backward runs once on two lane groups
         u32x4 A[LF.k2];
@@ -724,7 +740,19 @@ __global__ void __launch_bounds__(NT) kf_backward(
     // ---- conv1^T at the frozen sites: g_x = g_y + W1^T * g_a1 ----
     // (3D through the shared tile pass, which also frees registers there; 2D keeps
     // the plain loop, measured faster at the 2D shapes)
-    if constexpr (DIM == 2) {
+    if constexpr (!BF16) {
+      // FP32: 64 frozen sites per wave pass on the 4x4 blocks (g_h0 in register 0)
+      constexpr int NG = (V / 2 + 63) / 64;
+      const f32x4 zero{0.f, 0.f, 0.f, 0.f};
+      for (int gi = w; gi < NG; gi += NW) {
+        const int a = gi * 64 + lane;
+        const bool valid = a < V / 2;
+        const int n = G::half_site(valid ? a : 0, fpar), p = LY::idx(n);
+        const f32x4 o = quad_conv<Cfg::K1T>(fr + Cfg::OFF1T * 64, zero,
+                                            [&](int q) { return gather_q<LY, C, -1>(ga1s, n, p, q); });
+        if (valid) gx[sb + n] = gys[n] + o[0];
+      }
+    } else if constexpr (DIM == 2) {
       u32x4 A[LF.k2];
 #pragma unroll
       for (int c = 0; c < LF.k2; ++c) A[c] = fr[(Cfg::OFF1T + c) * 64];
@@ -858,7 +886,8 @@ int32_t launch_backward(const FlowGeom& g, const float* params, int B, const flo
                         hipStream_t st) {
   using Cfg = BwdCfg<DIM, L, C, BF16>;
   const int grid = bwd_grid<DIM, L, C, BF16>(B);
-  const FragTable tab = bwd_table(g, BF16, Cfg::LF.x4);
+  const FragTable tab = bwd_table(g, BF16, Cfg::LF.x4, Cfg::LF.quad);
+  if (tab.total != Cfg::FRAGS) return LFS_EDEVICE;  // the table and the kernel's offsets agree
   char* p = ws;
   u32x4* frags = reinterpret_cast<u32x4*>(p);
   p += align_up((size_t)Cfg::FRAGS * 64 * 16 * g.N);

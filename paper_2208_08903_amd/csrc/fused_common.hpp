@@ -297,25 +297,32 @@ __host__ __device__ constexpr int kblocks_f32(int K) { return (K + 15) / 16; }
 // Fragment bookkeeping for one layer (counts of 1 KB fragments = 64 lanes x 16 B).
 struct LayerFrags {
   int nct;           // output-channel tiles of conv1/conv2 (16 rows each)
-  int k1, k2;        // K chunks (BF16) or blocks (FP32) of conv1 and of conv2/conv3
+  int k1, k2;        // K chunks (BF16) or blocks (FP32) of conv1 and of conv2
+  int k3;            // fragments of conv3: k2, or T C / 4 in quad layout
   int off1, off2, off3, total;  // fragment offsets within the layer
   // x4: conv3's two output rows also placed at rows 4u, 4u+1 (u = 1, 2, 3; fragments
   // from off3q, k2 per placement), so four tiles can share one accumulator with
   // tile u's s and t landing in lane group u
   bool x4;
+  // quad (FP32): conv3 on v_mfma_f32_4x4x1f32, 16 blocks of 4 output rows x 4 sites;
+  // fragment q holds k = 4q .. 4q + 3 of row (lane & 3)
+  bool quad;
   int off3q;
 };
 
-__host__ __device__ constexpr LayerFrags layer_frags(int T, int C, bool bf16, bool x4 = false) {
+__host__ __device__ constexpr LayerFrags layer_frags(int T, int C, bool bf16, bool x4 = false,
+                                                     bool quad = false) {
   LayerFrags f{};
   f.nct = C >= 16 ? C / 16 : 1;
   f.k1 = bf16 ? kchunks_bf16(k_tri(T)) : kblocks_f32(k_tri(T));
   f.k2 = bf16 ? kchunks_bf16(T * C) : kblocks_f32(T * C);
+  f.quad = quad;
+  f.k3 = quad ? T * C / 4 : f.k2;
   f.off1 = 0;
   f.off2 = f.nct * f.k1;
   f.off3 = f.off2 + f.nct * f.k2;
   f.x4 = x4;
-  f.off3q = f.off3 + f.k2;
+  f.off3q = f.off3 + f.k3;
   f.total = f.off3q + (f.x4 ? 3 * f.k2 : 0);
   return f;
 }

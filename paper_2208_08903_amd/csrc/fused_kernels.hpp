@@ -15,9 +15,11 @@ namespace fused {
 // used by the data gradient (rows = input channels, k = tap * cout + co).
 // tri = 1 (single-input-channel forward convolution only): k in row-triple
 // order, k = 4 * (tap / 3) + tap % 3, the slots 4 r + 3 being zero.  shift:
-// the convolution's output row r is placed at fragment row r + shift.
+// the convolution's output row r is placed at fragment row r + shift.  quad = 1
+// (FP32, v_mfma_f32_4x4x1f32): fragment c holds, in every lane l, row (l & 3) at
+// k = 4c .. 4c + 3 (each of the 16 blocks of 4 lanes has the same A).
 struct FragSpec {
-  int transposed, woff, cin, cout, rows, nct, nk, off, tri, shift;
+  int transposed, woff, cin, cout, rows, nct, nk, off, tri, shift, quad;
 };
 constexpr int kMaxSpecs = 9;
 struct FragTable {
@@ -39,7 +41,8 @@ __global__ void kf_prep(const float* __restrict__ params, int N, int T, int P_la
   int si = 0;
   while (si + 1 < tab.count && f >= tab.s[si + 1].off) ++si;
   const FragSpec sp = tab.s[si];
-  const int fl = f - sp.off, ct = fl / sp.nk, c = fl % sp.nk, row = ct * 16 + m - sp.shift;
+  const int fl = f - sp.off, ct = fl / sp.nk, c = fl % sp.nk;
+  const int row = sp.quad ? (l & 3) - sp.shift : ct * 16 + m - sp.shift;
   const float* W = params + (size_t)layer * P_layer + sp.woff;
   const int kdiv = sp.transposed ? sp.cout : sp.cin;
   const int K = T * kdiv;
@@ -59,7 +62,7 @@ __global__ void kf_prep(const float* __restrict__ params, int N, int T, int P_la
     const int k0 = 32 * c + 8 * j;
     for (int q = 0; q < 4; ++q) out[q] = pack_bf16(w_at(k0 + 2 * q), w_at(k0 + 2 * q + 1));
   } else {
-    const int k0 = 16 * c + 4 * j;
+    const int k0 = sp.quad ? 4 * c : 16 * c + 4 * j;
     for (int q = 0; q < 4; ++q) out[q] = __float_as_uint(w_at(k0 + q));
   }
   frags[gid] = out;
@@ -187,6 +190,44 @@ __device__ __forceinline__ u32x4 load_tr8(const uint16_t* hs, int s, int ch0, in
       (lds_bf16x4*)(const_cast<uint16_t*>(hs + p2 * C + ch0 + 4 * q)));
   const u32x2 a = __builtin_bit_cast(u32x2, v1), b = __builtin_bit_cast(u32x2, v2);
   return u32x4{a[0], a[1], b[0], b[1]};
+}
+
+// FP32 convolutions with one or two output channels (conv3, and conv1 transposed)
+// on v_mfma_f32_4x4x1f32: 16 blocks of 4 lanes, block b = l / 4; lane l gives
+// A[l & 3][k] (the block's output row l & 3) and B[k][l & 3] (the input at its own
+// site), and receives D[r][l & 3] in register r: every lane ends with all output
+// channels of its own site.  Against the 16 x 16 tile the padding to 16 output
+// rows is gone (4 rows of which 2 or 1 are used).
+__device__ __forceinline__ f32x4 mfma4(float a, float b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+// The lane's 4 consecutive input channels of K chunk q (k = 4q .. 4q + 3, tap-major,
+// channel fastest) at site n + SIGN delta_tap (storage index p of n), FP32 storage.
+template <class LY, int C, int SIGN = 1>
+__device__ __forceinline__ u32x4 gather_q(const float* h, int n, int p, int q) {
+  const int k0 = 4 * q, tap = k0 / C, ci0 = k0 % C;
+  return *reinterpret_cast<const u32x4*>(h + LY::nbr(n, p, tap, SIGN) * C + ci0);
+}
+
+// sum_k A[r][k] B[k] over KQ chunks of 4 k for the lane's site: fq points at the lane's
+// entry of the first quad fragment (fragments 64 entries apart); two accumulator
+// chains (even and odd chunks) summed at the end.  init: the first chain's start.
+template <int KQ, class Gather>
+__device__ __forceinline__ f32x4 quad_conv(const u32x4* fq, const f32x4& init, Gather&& gather) {
+  static_assert(KQ % 2 == 0, "chunks come in pairs");
+  f32x4 a0 = init, a1{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 3
+  for (int q = 0; q < KQ; q += 2) {
+    const u32x4 w0 = fq[q * 64], w1 = fq[(q + 1) * 64];
+    const u32x4 b0 = gather(q), b1 = gather(q + 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a0 = mfma4(__uint_as_float(w0[r]), __uint_as_float(b0[r]), a0);
+      a1 = mfma4(__uint_as_float(w1[r]), __uint_as_float(b1[r]), a1);
+    }
+  }
+  return a0 + a1;
 }
 
 template <bool BF16>
@@ -345,7 +386,10 @@ struct FwdCfg {
   // conv3 four tiles per accumulator (2D BF16: the FP32 and 3D fragments of four
   // placements do not fit the registers) when every wave has four active-site tiles
   static constexpr bool X4 = T == 9 && BF16 && V / 32 >= 4 * (NT / 64);
-  static constexpr LayerFrags LF = layer_frags(T, C, BF16, X4);
+  // FP32 conv3 on the 4x4 matrix-core blocks (two of every four output rows used
+  // instead of two of sixteen), every lane ending with its own site's s and t
+  static constexpr bool Q3 = !BF16;
+  static constexpr LayerFrags LF = layer_frags(T, C, BF16, X4, Q3);
   // each pass's weight fragments fetched during the previous pass (2D, C <= 16:
   // the extra live fragments fit the registers of two waves per SIMD)
   static constexpr bool PFA = DIM == 2 && C <= 16;
