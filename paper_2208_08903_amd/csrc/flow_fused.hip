@@ -40,6 +40,7 @@ __global__ void __launch_bounds__(NT) kf_forward(
   float* xs = reinterpret_cast<float*>(smem);
   HT* h1 = reinterpret_cast<HT*>(smem + ((LY::VSZ * 4 + 15) / 16) * 16);
   HT* h2 = h1 + LY::VSZ * C;
+  u32x4* qt = reinterpret_cast<u32x4*>(h2 + LY::VSZ * C);  // FP32: the layer's conv3 A table
   for (int q = threadIdx.x; q < C; q += NT) h1[LY::ZS * C + q] = 0, h2[LY::ZS * C + q] = 0;
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
   const size_t BV = (size_t)B * V;
@@ -61,6 +62,12 @@ __global__ void __launch_bounds__(NT) kf_forward(
       const u32x4* fl = frags + (size_t)layer * LF.total * 64 + lane;
       const float* pl = params + (size_t)layer * P_layer;
       __syncthreads();
+      if constexpr (Cfg::Q3) {
+        // conv3's quad A entries (rows 0..3 of every chunk) into LDS: read by every
+        // conv3 chunk of every wave, visible after the next barrier
+        const u32x4* f3 = frags + ((size_t)layer * LF.total + LF.off3) * 64;
+        for (int i = threadIdx.x; i < LF.k3 * 4; i += NT) qt[i] = f3[(i >> 2) * 64 + (i & 3)];
+      }
       // Weight fragments.  Where the registers allow (Cfg::PFA) each pass's are
       // fetched one pass ahead, so the L2 latency hides behind the previous
       // pass: conv1's and conv2's here, conv3's when conv2 starts; otherwise
@@ -158,8 +165,8 @@ __global__ void __launch_bounds__(NT) kf_forward(
           const int a = gi * 64 + lane;
           const bool valid = a < V / 2;
           const int n = G::half_site(valid ? a : 0, apar), p = LY::idx(n);
-          const f32x4 o = quad_conv<LF.k3>(fl + LF.off3 * 64, b3,
-                                           [&](int q) { return gather_q<LY, C>(h2, n, p, q); });
+          const f32x4 o = quad_conv<LF.k3, 4>(qt + (lane & 3), b3,
+                                              [&](int q) { return gather_q<LY, C>(h2, n, p, q); });
           if (valid) {
             const float s = final_tanh ? fast_tanh(o[0]) : o[0];
             const float xn = xs[p] * fast_exp(s) + o[1];

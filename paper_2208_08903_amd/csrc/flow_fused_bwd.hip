@@ -91,7 +91,8 @@ struct BwdCfg {
   using LY = typename M::LY;
   static constexpr int CSTR = M::CSTR;
   // LDS of the sample state (and, after the sample loop, of the partial sums)
-  static constexpr size_t lds_main = cmaxz(M::MAIN, (size_t)P_LAYER * 4);
+  static constexpr size_t lds_main = cmaxz(M::MAIN + (BF16 ? 0 : 16 + (size_t)(T * C / 4) * 2 * 4 * 16),
+                                           (size_t)P_LAYER * 4);
   // 3D shapes need more than the 256 registers a lane gets at 2 waves per SIMD.
   static constexpr int NT = (lds_main > 80 * 1024 && DIM == 2) ? 512 : 256;
   static constexpr int NW = NT / 64;
@@ -117,7 +118,11 @@ struct BwdCfg {
   // L2 at the start of every pass of every sample.
   static constexpr size_t RED_STATIC = (size_t)kRedSlices * (NT / kRedSlices + 1) * 4;
   static constexpr size_t FRAG_BYTES = (size_t)FRAGS * 64 * 16;
-  static constexpr size_t OFF_FRAG = align16(M::MAIN);
+  // FP32: the quad A tables of conv3 and conv1^T, compact (4 rows of 16 bytes per
+  // chunk), staged in LDS once per launch after the sample state
+  static constexpr size_t OFF_QT = align16(M::MAIN);
+  static constexpr size_t QT_BYTES = BF16 ? 0 : (size_t)(LF.k3 + K1T) * 4 * 16;
+  static constexpr size_t OFF_FRAG = align16(OFF_QT + QT_BYTES);
   static constexpr int per_cu(size_t bytes) { return bytes > 160 * 1024 ? 0 : cmin(8, (int)(160 * 1024 / bytes)); }
   static constexpr bool FRAG_LDS = OFF_FRAG + FRAG_BYTES + RED_STATIC <= 158 * 1024 &&
                                    per_cu(OFF_FRAG + FRAG_BYTES + RED_STATIC) == per_cu(lds_main + RED_STATIC);
@@ -246,6 +251,16 @@ __global__ void __launch_bounds__(NT) kf_backward(
     fr = frags + lane;
   }
   const int apar = fpar ^ 1;
+  const u32x4* qt = reinterpret_cast<const u32x4*>(smem + Cfg::OFF_QT);
+  if constexpr (!BF16) {
+    // quad A entries (rows 0..3 of every chunk) of conv3 and conv1^T; visible after
+    // the first sample's staging barrier
+    u32x4* q = reinterpret_cast<u32x4*>(smem + Cfg::OFF_QT);
+    for (int i = threadIdx.x; i < (LF.k3 + Cfg::K1T) * 4; i += NT) {
+      const int c = i >> 2;
+      q[i] = frags[(c < LF.k3 ? LF.off3 + c : Cfg::OFF1T + c - LF.k3) * 64 + (i & 3)];
+    }
+  }
 
   // The extra zero site of the site-major slots and of g_o: cleared once, never
   // written afterwards (every later store goes to a lattice site or its mirror).
@@ -428,8 +443,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
           const int a = gi * 64 + lane;
           const bool valid = a < V / 2;
           const int n = G::half_site(valid ? a : 0, apar), p = LY::idx(n);
-          const f32x4 o = quad_conv<LF.k3>(fr + LF.off3 * 64, b3,
-                                           [&](int q) { return gather_q<LY, C>(h2s, n, p, q); });
+          const f32x4 o = quad_conv<LF.k3, 4>(qt + (lane & 3), b3,
+                                              [&](int q) { return gather_q<LY, C>(h2s, n, p, q); });
           if (valid) affine_bwd(n, o[0]);
         }
       } else if constexpr (Cfg::QU3 == 2) {
@@ -748,8 +763,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
         const int a = gi * 64 + lane;
         const bool valid = a < V / 2;
         const int n = G::half_site(valid ? a : 0, fpar), p = LY::idx(n);
-        const f32x4 o = quad_conv<Cfg::K1T>(fr + Cfg::OFF1T * 64, zero,
-                                            [&](int q) { return gather_q<LY, C, -1>(ga1s, n, p, q); });
+        const f32x4 o = quad_conv<Cfg::K1T, 4>(qt + LF.k3 * 4 + (lane & 3), zero,
+                                               [&](int q) { return gather_q<LY, C, -1>(ga1s, n, p, q); });
         if (valid) gx[sb + n] = gys[n] + o[0];
       }
     } else if constexpr (DIM == 2) {

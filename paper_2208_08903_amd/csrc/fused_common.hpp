@@ -78,9 +78,20 @@ struct Geo {
     return (mu == 0 ? t / 9 : (mu == 1 ? (t / 3) % 3 : t % 3)) - 1;
   }
 
-  // Site n + sign * delta_t, periodic.
+  // Site n + sign * delta_t, periodic (power-of-two L: coordinates by shift and
+  // mask, the wrap by a mask, which also holds for the -1 offset).
   __device__ static __forceinline__ int nbr(int n, int t, int sign = 1) {
-    if constexpr (DIM == 2) {
+    if constexpr ((L & (L - 1)) == 0) {
+      constexpr int LG = L <= 1 ? 0 : 31 - __builtin_clz(L), MK = L - 1;
+      if constexpr (DIM == 2) {
+        const int y = n >> LG, x = n & MK;
+        return (((y + sign * tap_d(t, 0)) & MK) << LG) | ((x + sign * tap_d(t, 1)) & MK);
+      } else {
+        const int z = n >> (2 * LG), y = (n >> LG) & MK, x = n & MK;
+        return (((((z + sign * tap_d(t, 0)) & MK) << LG) | ((y + sign * tap_d(t, 1)) & MK)) << LG) |
+               ((x + sign * tap_d(t, 2)) & MK);
+      }
+    } else if constexpr (DIM == 2) {
       const int y = n / L, x = n - (n / L) * L;
       return wrapc(y + sign * tap_d(t, 0)) * L + wrapc(x + sign * tap_d(t, 1));
     } else {

@@ -211,15 +211,16 @@ __device__ __forceinline__ u32x4 gather_q(const float* h, int n, int p, int q) {
 }
 
 // sum_k A[r][k] B[k] over KQ chunks of 4 k for the lane's site: fq points at the lane's
-// entry of the first quad fragment (fragments 64 entries apart); two accumulator
-// chains (even and odd chunks) summed at the end.  init: the first chain's start.
-template <int KQ, class Gather>
+// A entry of the first chunk, chunks STRIDE entries apart (64 in the fragment layout,
+// 4 in a compact table of 4 rows per chunk); two accumulator chains (even and odd
+// chunks) summed at the end.  init: the first chain's start.
+template <int KQ, int STRIDE = 64, class Gather>
 __device__ __forceinline__ f32x4 quad_conv(const u32x4* fq, const f32x4& init, Gather&& gather) {
   static_assert(KQ % 2 == 0, "chunks come in pairs");
   f32x4 a0 = init, a1{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 3
   for (int q = 0; q < KQ; q += 2) {
-    const u32x4 w0 = fq[q * 64], w1 = fq[(q + 1) * 64];
+    const u32x4 w0 = fq[q * STRIDE], w1 = fq[(q + 1) * STRIDE];
     const u32x4 b0 = gather(q), b1 = gather(q + 1);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -373,8 +374,10 @@ template <int DIM, int L, int C, bool BF16>
 struct FwdCfg {
   using G = Geo<DIM, L>;
   static constexpr int V = G::V, T = G::T;
+  // FP32: conv3's quad A table, compact (4 rows of 16 bytes per chunk), after h2
+  static constexpr size_t QT_BYTES = BF16 ? 0 : (size_t)(T * C / 4) * 4 * 16;
   static constexpr size_t bytes_for(int vs) {
-    return ((size_t)vs * 4 + 15) / 16 * 16 + 2 * (size_t)vs * C * sizeof(HElem<BF16>);
+    return ((size_t)vs * 4 + 15) / 16 * 16 + 2 * (size_t)vs * C * sizeof(HElem<BF16>) + QT_BYTES;
   }
   static constexpr bool PAD = bytes_for(Lay<DIM, L, true>::VSZ) <= 156 * 1024;
   using LY = Lay<DIM, L, PAD>;
