@@ -129,8 +129,10 @@ __global__ void __launch_bounds__(NT) kf_forward(
             });
       }
       __syncthreads();
-      fill_halo<LY, C, BF16, NT>(h1);
-      __syncthreads();
+      if constexpr (LY::padded) {
+        fill_halo<LY, C, BF16, NT>(h1);
+        __syncthreads();
+      }
       // conv2 over all sites
       {
         if constexpr (Cfg::PFA)
@@ -151,8 +153,10 @@ __global__ void __launch_bounds__(NT) kf_forward(
             });
       }
       __syncthreads();
-      fill_halo<LY, C, BF16, NT>(h2);
-      __syncthreads();
+      if constexpr (LY::padded) {
+        fill_halo<LY, C, BF16, NT>(h2);
+        __syncthreads();
+      }
       // conv3 at the active sites, affine update and log-det
       if constexpr (!Cfg::PFA) load_a3();
       if constexpr (Cfg::Q3) {

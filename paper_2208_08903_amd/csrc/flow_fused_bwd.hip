@@ -39,7 +39,10 @@ constexpr size_t align16(size_t x) { return (x + 15) / 16 * 16; }
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr size_t cmaxz(size_t a, size_t b) { return a > b ? a : b; }
 
-template <int DIM, int L, int C, bool BF16, bool PAD>
+// SPLIT (2D BF16 at L = 32): the sample state of a 4-wave workgroup kept under
+// half the LDS so that two workgroups share a CU: no g_y copy (read from L2),
+// the masked field's channel-major row over g_o's (built after dW3), two slots.
+template <int DIM, int L, int C, bool BF16, bool PAD, bool SPLIT = false>
 struct BwdLds {
   using LY = Lay<DIM, L, PAD>;
   static constexpr int V = Geo<DIM, L>::V, VS = LY::VS;
@@ -48,25 +51,26 @@ struct BwdLds {
   static constexpr size_t SA = (size_t)LY::VSZ * C * (BF16 ? 2 : 4);  // site-major tensor
   static constexpr size_t OFF_XS = 0;
   static constexpr size_t OFF_GY = align16((size_t)VS * 4);
-  static constexpr size_t OFF_GOS = OFF_GY + align16((size_t)V * 4);
+  static constexpr size_t OFF_GOS = OFF_GY + (SPLIT ? 0 : align16((size_t)V * 4));
   static constexpr size_t GOS_BYTES = (size_t)LY::VSZ * (BF16 ? 4 : 8);
   static constexpr size_t OFF_GOC = OFF_GOS + align16(GOS_BYTES);
   static constexpr size_t GOC_BYTES = BF16 ? 2 * (size_t)CSTR * 2 : 0;
-  static constexpr size_t OFF_H0C = OFF_GOC + align16(GOC_BYTES);
+  static constexpr size_t OFF_H0C = SPLIT ? OFF_GOC : OFF_GOC + align16(GOC_BYTES);
   static constexpr size_t H0C_BYTES = BF16 ? (size_t)CSTR * 2 : 0;
-  static constexpr size_t OFF_SLOT = OFF_H0C + align16(H0C_BYTES);
+  static constexpr size_t OFF_SLOT = SPLIT ? OFF_GOC + align16(GOC_BYTES) : OFF_H0C + align16(H0C_BYTES);
   // site-major slots: BF16 three (S0: h1; S1: conv1's row triples, then h2, then
-  // g_a1; S2: g_a2), FP32 two (h1 then g_a1 in place; h2 then g_a2 in place).  The
-  // weight-gradient GEMMs read their site-major operands with transposing LDS
-  // reads; g_o and the masked field keep channel-major rows, and so does g_a2 in
-  // 3D (S3), whose 27 shifted reads in dW2 would otherwise cost more registers
-  // in address arithmetic than the lanes have.
+  // g_a1; S2: g_a2), FP32 and SPLIT two (h1 then g_a1 in place; conv1's row
+  // triples (BF16), then h2, then g_a2 in place).  The weight-gradient GEMMs read
+  // their site-major operands with transposing LDS reads; g_o and the masked
+  // field keep channel-major rows, and so does g_a2 in 3D (S3), whose 27 shifted
+  // reads in dW2 would otherwise cost more registers in address arithmetic than
+  // the lanes have.
   static constexpr bool CM2 = BF16 && DIM == 3;
   static constexpr size_t OFF_S0 = OFF_SLOT;
   static constexpr size_t OFF_S1 = OFF_S0 + SA;
   static constexpr size_t OFF_S2 = OFF_S1 + SA;
   static constexpr size_t OFF_S3 = OFF_S2 + SA;
-  static constexpr size_t MAIN = !BF16 ? OFF_S2 : CM2 ? OFF_S3 + (size_t)C * CSTR * 2 : OFF_S3;
+  static constexpr size_t MAIN = (!BF16 || SPLIT) ? OFF_S2 : CM2 ? OFF_S3 + (size_t)C * CSTR * 2 : OFF_S3;
 };
 
 // Channel-major BF16 copy of four channels co0..co0+3 (packed pairs in hv) of
@@ -86,8 +90,16 @@ struct BwdCfg {
   static constexpr int V = G::V, T = G::T;
   static constexpr int KT3 = BF16 ? kchunks_bf16(2 * T) : kblocks_f32(2 * T);
   static constexpr int P_LAYER = C * T + C + C * C * T + C + 2 * C * T + 2;
-  static constexpr bool PAD = BwdLds<DIM, L, C, BF16, true>::MAIN <= 158 * 1024;
-  using M = BwdLds<DIM, L, C, BF16, PAD>;
+  // 2D BF16 at L = 32, C = 16: two 4-wave workgroups per CU, each on its own
+  // sample, so that one workgroup's barriers and pass-start latencies overlap the
+  // other's work (the passes are latency-bound: a few MFMAs per tile between LDS
+  // round trips).  The sample state then has to fit half the LDS: unpadded layout
+  // (periodic neighbours by shift and mask), g_a2 and g_a1 in place over h2 and h1
+  // (dW3 runs before conv3^T overwrites h2), g_y read from L2 where it is used, and
+  // the layer's weight fragments read from L2 instead of an LDS copy.
+  static constexpr bool SPLIT = BF16 && DIM == 2 && L == 32 && C == 16;
+  static constexpr bool PAD = !SPLIT && BwdLds<DIM, L, C, BF16, true>::MAIN <= 158 * 1024;
+  using M = BwdLds<DIM, L, C, BF16, PAD, SPLIT>;
   using LY = typename M::LY;
   static constexpr int CSTR = M::CSTR;
   // LDS of the sample state (and, after the sample loop, of the partial sums)
@@ -95,15 +107,17 @@ struct BwdCfg {
                                            (size_t)P_LAYER * 4);
   // 3D shapes need more than the 256 registers a lane gets at 2 waves per SIMD.
   static constexpr int NT = (lds_main > 80 * 1024 && DIM == 2) ? 512 : 256;
+  // waves per SIMD the register allocation has to allow (SPLIT: two workgroups)
+  static constexpr int MINW = SPLIT ? 2 : 1;
   static constexpr int NW = NT / 64;
   // Tiles in flight per wave in the tile passes: two where the registers allow
   // (3D shapes, and FP32 C=16 at two waves per SIMD, are already at the limit).
   static constexpr int TU = DIM == 2 && (BF16 || NT == 256 || C < 16) ? 2 : 1;
   // conv3 recompute: tiles whose affine backward share a pass -- four where the
   // extra fragments fit the registers, two (one shuffle) otherwise; BF16 with at
-  // least that many active-site tiles per wave, else one
+  // least that many active-site tiles per wave, else one (SPLIT: two, for registers)
   static constexpr int TPW3 = V / 32 / NW;
-  static constexpr int QU3 = !(T == 9 && BF16) ? 1 : (NT == 256 && TPW3 >= 4) ? 4 : (TPW3 >= 2 ? 2 : 1);
+  static constexpr int QU3 = !(T == 9 && BF16) ? 1 : (NT == 256 && !SPLIT && TPW3 >= 4) ? 4 : (TPW3 >= 2 ? 2 : 1);
   // FP32: conv3 (recompute) and conv1^T (one output channel) on the 4x4 matrix-core
   // blocks (quad fragments), every lane with its own site's result
   static constexpr LayerFrags LF = layer_frags(T, C, BF16, QU3 == 4, !BF16);
@@ -222,7 +236,7 @@ __device__ __forceinline__ u32x4 load8_e(const uint16_t* rp, int x0) {
 // ---- the kernel -------------------------------------------------------------
 
 template <int DIM, int L, int C, bool BF16, int NT>
-__global__ void __launch_bounds__(NT) kf_backward(
+__global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backward(
     const u32x4* frags, const float* __restrict__ pl, int off_b1, int off_b2,
     int off_b3, int off_W1, int off_W2, int off_W3, int fpar, int final_tanh, float g_ld,
     const double* __restrict__ g_ld_vec, int B,
@@ -295,7 +309,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
   // previous sample is still being processed, so staging them is LDS writes
   // only.  3D shapes have no registers to spare and load them when staging.
   constexpr bool PF = DIM == 2;
-  constexpr int NPX = PF ? (VS + NT - 1) / NT : 1, NPG = PF ? (V / 4 + NT - 1) / NT : 1;
+  constexpr bool GYL = !Cfg::SPLIT;  // g_y staged in LDS (SPLIT: read from L2 where used)
+  constexpr int NPX = PF ? (VS + NT - 1) / NT : 1, NPG = PF && GYL ? (V / 4 + NT - 1) / NT : 1;
   float pfx[NPX];
   f32x4 pfg[NPG];
   auto prefetch = [&](int bb) {
@@ -306,13 +321,24 @@ __global__ void __launch_bounds__(NT) kf_backward(
       const int q = threadIdx.x + i * NT;
       pfx[i] = q < VS ? xin[s0 + LY::site_of(q)] : 0.f;
     }
+    if constexpr (GYL) {
 #pragma unroll
-    for (int i = 0; i < NPG; ++i) {
-      const int q = threadIdx.x + i * NT;
-      pfg[i] = q < V / 4 ? reinterpret_cast<const f32x4*>(gy + s0)[q] : f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int i = 0; i < NPG; ++i) {
+        const int q = threadIdx.x + i * NT;
+        pfg[i] = q < V / 4 ? reinterpret_cast<const f32x4*>(gy + s0)[q] : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
     }
   };
   if constexpr (PF) prefetch(blockIdx.x);
+  // the hidden convolutions' biases, the same for every sample of the launch: held
+  // in registers (2D; the 3D shapes have none to spare and reload them per pass)
+  constexpr bool HB = DIM == 2;
+  f32x4 hb1[LF.nct], hb2[LF.nct];
+#pragma unroll
+  for (int ct = 0; ct < LF.nct; ++ct) {
+    hb1[ct] = HB ? load_bias4<C>(pl + off_b1, ct, j) : f32x4{};
+    hb2[ct] = HB ? load_bias4<C>(pl + off_b2, ct, j) : f32x4{};
+  }
   // the previous launch's (next layer's) weight gradient, while the prefetch is in flight
   if (prev_partial) grid_reduce<NT>(prev_partial, prev_out, n_parts, Cfg::P_LAYER);
 
@@ -329,35 +355,39 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
       for (int i = 0; i < NPX; ++i)
         if (threadIdx.x + i * NT < VS) xs[threadIdx.x + i * NT] = pfx[i];
+      if constexpr (GYL) {
 #pragma unroll
-      for (int i = 0; i < NPG; ++i)
-        if (threadIdx.x + i * NT < V / 4) reinterpret_cast<f32x4*>(gys)[threadIdx.x + i * NT] = pfg[i];
+        for (int i = 0; i < NPG; ++i)
+          if (threadIdx.x + i * NT < V / 4) reinterpret_cast<f32x4*>(gys)[threadIdx.x + i * NT] = pfg[i];
+      }
     } else {
       for (int q = threadIdx.x; q < VS; q += NT) xs[q] = xin[sb + LY::site_of(q)];
       for (int q = threadIdx.x; q < V / 4; q += NT)
         reinterpret_cast<f32x4*>(gys)[q] = reinterpret_cast<const f32x4*>(gy + sb)[q];
     }
     __syncthreads();
-    if constexpr (BF16) {
+    // masked field, channel-major, for dW1 (SPLIT: built after dW3, over g_o's rows)
+    auto build_h0c = [&]() {
       uint16_t* h0c = reinterpret_cast<uint16_t*>(smem + M::OFF_H0C);
       for (int n = threadIdx.x; n < V; n += NT)
         h0c[n] = (uint16_t)bf16_bits(G::parity(n) == fpar ? xs[LY::idx(n)] : 0.f);
-    }
+    };
+    if constexpr (BF16 && !Cfg::SPLIT) build_h0c();
     // conv1 operands (row triples of the masked field) in the (not yet written) h2 slot
     build_tri<LY, BF16, NT>(h2s, xs, fpar);
     __syncthreads();
     // ---- recompute conv1 -> h1 ----
     {
       u32x4 A[LF.nct][LF.k1];
-      f32x4 bias[LF.nct];
+      f32x4 bias1[LF.nct];
 #pragma unroll
       for (int ct = 0; ct < LF.nct; ++ct) {
-        bias[ct] = load_bias4<C>(pl + off_b1, ct, j);
+        bias1[ct] = HB ? hb1[ct] : load_bias4<C>(pl + off_b1, ct, j);
 #pragma unroll
         for (int c = 0; c < LF.k1; ++c) A[ct][c] = fr[(LF.off1 + ct * LF.k1 + c) * 64];
       }
       mma_tiles<Cfg::TU, LF.nct, LF.k1, BF16>(
-          V / 16, w, NW, A, bias,
+          V / 16, w, NW, A, bias1,
           [&](int tile, int c) {
             return gather_tri<LY, BF16>(h2s, tile * 16 + m, tile_p<LY>(tile, m), c, j);
           },
@@ -367,20 +397,22 @@ __global__ void __launch_bounds__(NT) kf_backward(
           });
     }
     __syncthreads();
-    fill_halo<LY, C, BF16, NT>(h1s);
-    __syncthreads();
+    if constexpr (LY::padded) {
+      fill_halo<LY, C, BF16, NT>(h1s);
+      __syncthreads();
+    }
     // ---- recompute conv2 -> h2 ----
     {
       u32x4 A[LF.nct][LF.k2];
-      f32x4 bias[LF.nct];
+      f32x4 bias2[LF.nct];
 #pragma unroll
       for (int ct = 0; ct < LF.nct; ++ct) {
-        bias[ct] = load_bias4<C>(pl + off_b2, ct, j);
+        bias2[ct] = HB ? hb2[ct] : load_bias4<C>(pl + off_b2, ct, j);
 #pragma unroll
         for (int c = 0; c < LF.k2; ++c) A[ct][c] = fr[(LF.off2 + ct * LF.k2 + c) * 64];
       }
       mma_tiles<Cfg::TU, LF.nct, LF.k2, BF16>(
-          V / 16, w, NW, A, bias,
+          V / 16, w, NW, A, bias2,
           [&](int tile, int c) {
             return gather_h<LY, C, BF16>(h1s, tile * 16 + m, tile_p<LY>(tile, m), c, j);
           },
@@ -409,14 +441,16 @@ __global__ void __launch_bounds__(NT) kf_backward(
         });
       }
     }
-    __syncthreads();
+    // (the zeros go to frozen sites, the affine backward below writes active ones;
+    // the barrier publishes h2's halo)
+    if constexpr (LY::padded) __syncthreads();
     {
       // affine backward at active site n from conv3's s pre-activation o0
       auto affine_bwd = [&](int n, float o0) {
         const int p = LY::idx(n);
         const float s = final_tanh ? fast_tanh(o0) : o0;
         const float es = fast_exp(s);
-        const float g = gys[n];
+        const float g = GYL ? gys[n] : gy[sb + n];
         const float gs = g * xs[p] * es + gld;
         const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
         db3s += go0;
@@ -553,14 +587,15 @@ __global__ void __launch_bounds__(NT) kf_backward(
         }
       }
     };
-    if constexpr (!BF16) {
+    if constexpr (!BF16 || Cfg::SPLIT) {
       dw3();
       __syncthreads();
     }
     // ---- conv3^T: g_a2 = leaky'(h2) (W3^T * g_o) ----
-    // BF16: into S2 (3D also channel-major into S3); FP32: in place over h2.
-    HT* ga2s = BF16 ? reinterpret_cast<HT*>(smem + M::OFF_S2) : h2s;
+    // BF16: into S2 (3D also channel-major into S3); FP32 and SPLIT: in place over h2.
+    HT* ga2s = BF16 && !Cfg::SPLIT ? reinterpret_cast<HT*>(smem + M::OFF_S2) : h2s;
     uint16_t* ga2c = reinterpret_cast<uint16_t*>(smem + M::OFF_S3);
+    if constexpr (Cfg::SPLIT) build_h0c();  // over g_o's channel-major rows, dead after dW3
     {
       u32x4 A[LF.nct][Cfg::KT3];
 #pragma unroll
@@ -617,9 +652,12 @@ __global__ void __launch_bounds__(NT) kf_backward(
           });
     }
     __syncthreads();
-    fill_halo<LY, C, BF16, NT>(ga2s);
-    if constexpr (BF16) dw3();
-    __syncthreads();
+    // g_a2's halo, and BF16 (but SPLIT) dW3; nothing to do for unpadded FP32 and SPLIT
+    if constexpr (LY::padded || (BF16 && !Cfg::SPLIT)) {
+      fill_halo<LY, C, BF16, NT>(ga2s);
+      if constexpr (BF16 && !Cfg::SPLIT) dw3();
+      __syncthreads();
+    }
     // ---- dW2[co][ci][tap] += sum_m h1[m][ci] g_a2[m - delta_tap][co] ----
     // tiles (mt, tap, nt): rows ci = mt*16 + i, columns co = nt*16 + m; the taps are
     // unrolled so each shift is known at compile time.
@@ -668,8 +706,8 @@ __global__ void __launch_bounds__(NT) kf_backward(
     }
     __syncthreads();
     // ---- conv2^T: g_a1 = leaky'(h1) (W2^T * g_a2) ----
-    // BF16: into S1 (h2 is dead); FP32: in place over h1.
-    HT* ga1s = BF16 ? reinterpret_cast<HT*>(smem + M::OFF_S1) : h1s;
+    // BF16: into S1 (h2 is dead); FP32 and SPLIT: in place over h1.
+    HT* ga1s = BF16 && !Cfg::SPLIT ? reinterpret_cast<HT*>(smem + M::OFF_S1) : h1s;
     {
       u32x4 A[LF.nct][LF.k2];
 #pragma unroll
@@ -777,7 +815,7 @@ __global__ void __launch_bounds__(NT) kf_backward(
 #pragma unroll
         for (int c = 0; c < LF.k2; ++c)
           acc = mma<BF16>(A[c], gather_h<LY, C, BF16, -1>(ga1s, n, p, c, j), acc);
-        if (j == 0) gx[sb + n] = gys[n] + acc[0];
+        if (j == 0) gx[sb + n] = (GYL ? gys[n] : gy[sb + n]) + acc[0];
       }
     } else {
       u32x4 A[1][LF.k2];
