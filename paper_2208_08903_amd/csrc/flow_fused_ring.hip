@@ -37,12 +37,17 @@ struct RingCfg {
   static constexpr size_t XS_BYTES = ((size_t)LX::VS * 4 + 15) / 16 * 16;
   static constexpr int ZS = 3 * PS;  // all-zero site after the three planes
   static constexpr size_t RING = (3 * (size_t)PS + 1) * C * sizeof(HElem<BF16>);
-  static constexpr size_t lds_bytes = XS_BYTES + 2 * RING;
   // Two output-channel tiles (C = 32): eight waves, four per tile, so that a
-  // wave holds one tile's conv1/conv2 fragments and conv3's are fetched per
-  // chunk; the registers then admit two waves per SIMD instead of one.
+  // wave holds one tile's conv1/conv2 fragments and conv3's come from LDS; the
+  // registers then admit two waves per SIMD instead of one.
   static constexpr int NT = LF.nct == 2 ? 512 : 256;
   static constexpr bool A3_HELD = LF.nct == 1;
+  // conv3's A operand has two live rows (s and t): lanes 16 j + m with m < 2.  A
+  // compact LDS table holds those 8 lanes' entries per chunk (copied once per
+  // layer), and every lane reads entry 2 j + (m & 1), so rows 2..15 repeat rows 0
+  // and 1; those rows of the product are never read.
+  static constexpr size_t T3_BYTES = A3_HELD ? 0 : (size_t)LF.k2 * 8 * 16;
+  static constexpr size_t lds_bytes = XS_BYTES + 2 * RING + T3_BYTES;
 };
 
 __device__ __forceinline__ int mod3(int v) { return ((v % 3) + 3) % 3; }
@@ -84,6 +89,7 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
   float* xs = reinterpret_cast<float*>(smem);
   HT* r1 = reinterpret_cast<HT*>(smem + Cfg::XS_BYTES);
   HT* r2 = r1 + (3 * PS + 1) * C;
+  u32x4* t3 = reinterpret_cast<u32x4*>(smem + Cfg::XS_BYTES + 2 * Cfg::RING);
   for (int q = threadIdx.x; q < C; q += NT) r1[Cfg::ZS * C + q] = HT(0), r2[Cfg::ZS * C + q] = HT(0);
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
   // this wave's channel tile and its index among that tile's waves
@@ -150,14 +156,13 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
         for (int tile = w; tile < PLANE / 32; tile += NW) {
           const int q = Geo<2, L>::half_site(tile * 16 + m, ppar), pq = LP2::idx(q);
           f32x4 acc{0.f, 0.f, 0.f, 0.f};
-          // fetched fragments: nine chunks in flight at a time (three: 2 % slower), not all 27
 #pragma unroll Cfg::A3_HELD ? LF.k2 : 9
           for (int c = 0; c < LF.k2; ++c) {
             u32x4 a3;
             if constexpr (Cfg::A3_HELD)
               a3 = A3[c];
             else
-              a3 = fl[(LF.off3 + c) * 64];  // L2-resident, shared by every workgroup
+              a3 = t3[c * 8 + 2 * j + (m & 1)];
             acc = mma<BF16>(a3, gather_ring<L, C, BF16>(r2, pq, sm, s0, sp, c, j), acc);
           }
           if (j == 0) {
@@ -172,6 +177,11 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
       };
 
       __syncthreads();  // field of the previous layer complete
+      if constexpr (!Cfg::A3_HELD) {
+        // conv3's live A rows into the compact table (read after the next barriers)
+        const u32x4* f3 = frags + ((size_t)layer * LF.total + LF.off3) * 64;
+        for (int i = threadIdx.x; i < LF.k2 * 8; i += NT) t3[i] = f3[(i >> 3) * 64 + 16 * ((i & 7) >> 1) + (i & 1)];
+      }
       conv1_plane(-2);
       conv1_plane(-1);
       conv1_plane(0);

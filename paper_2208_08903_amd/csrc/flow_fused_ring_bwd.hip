@@ -50,9 +50,16 @@ struct RbCfg {
   static constexpr int RING = (3 * PS + 1) * C;   // BF16 elements of a hidden-tensor ring
   static constexpr size_t XS_BYTES = ((size_t)LX::VS * 4 + 15) / 16 * 16;
   static constexpr size_t GOR_BYTES = ((size_t)(3 * PS + 1) * 4 + 15) / 16 * 16;
-  static constexpr size_t LDS_A = XS_BYTES + 2 * (size_t)RING * 2;
+  static constexpr bool NARROW_HELD = LF.nct == 1;
+  // The narrow convolutions' A operands (conv3: rows s and t, lanes 16 j + m with
+  // m < 2; conv1 transposed: row 0, lanes 16 j) in compact LDS tables copied once
+  // per launch; every lane reads its row group's entry, so the other rows of the
+  // product repeat the live ones and are never read.
+  static constexpr size_t T3_BYTES = NARROW_HELD ? 0 : (size_t)LF.k2 * 8 * 16;
+  static constexpr size_t T1_BYTES = NARROW_HELD ? 0 : (size_t)LF.k2 * 4 * 16;
+  static constexpr size_t LDS_A = XS_BYTES + 2 * (size_t)RING * 2 + T3_BYTES;
   // transpose: g_o ring, the LeakyReLU sign masks of one h2 and one h1 plane, two rings
-  static constexpr size_t LDS_B = GOR_BYTES + 2 * (size_t)PLANE * 4 + 2 * (size_t)RING * 2;
+  static constexpr size_t LDS_B = GOR_BYTES + 2 * (size_t)PLANE * 4 + 2 * (size_t)RING * 2 + T1_BYTES;
   // weights: three plane buffers [C][CS] (h1, h2, g_a1 of plane z) and rings of
   // three planes of g_a2 [C][CS], g_o [2][CS] and mask_F x [PLANE].  Channel rows
   // are CS = PLANE + 8 elements apart, so the 16 lanes reading 16 channels at the
@@ -62,10 +69,9 @@ struct RbCfg {
   // recompute and transpose with two output-channel tiles (C = 32): eight waves,
   // four per tile, each holding one tile's fragments of the C-output
   // convolutions; the narrow one (conv3, or conv1 transposed: 2 or 1 outputs)
-  // fetches its fragments per chunk instead of holding them, so that two waves
-  // fit per SIMD
+  // reads its A operand from the compact LDS table instead of holding it, so that
+  // two waves fit per SIMD
   static constexpr int NT_A = LF.nct == 2 ? 512 : 256, NT_B = NT_A, NT_C = 512;
-  static constexpr bool NARROW_HELD = LF.nct == 1;
   // weight-gradient GEMM tiles (16 x 16): rows are channels, columns (tap, channel)
   static constexpr int RT = C / 16;
   static constexpr int N2 = RT * (T * C / 16), N3 = RT * 4, N1 = RT * 2;
@@ -178,6 +184,10 @@ __global__ void __launch_bounds__(NT) kr_recompute(
   float* xs = reinterpret_cast<float*>(smem);
   uint16_t* r1 = reinterpret_cast<uint16_t*>(smem + Cfg::XS_BYTES);
   uint16_t* r2 = r1 + Cfg::RING;
+  u32x4* t3 = reinterpret_cast<u32x4*>(r2 + Cfg::RING);  // visible after the sample loop's first barrier
+  if constexpr (!Cfg::NARROW_HELD)
+    for (int i = threadIdx.x; i < LF.k2 * 8; i += NT)
+      t3[i] = frags[(LF.off3 + (i >> 3)) * 64 + 16 * ((i & 7) >> 1) + (i & 1)];
   for (int q = threadIdx.x; q < C; q += NT) r1[Cfg::ZS * C + q] = 0, r2[Cfg::ZS * C + q] = 0;
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
   constexpr int WPC = NW / LF.nct;  // waves per output-channel tile
@@ -259,14 +269,13 @@ __global__ void __launch_bounds__(NT) kr_recompute(
       for (int tile = w; tile < PLANE / 32; tile += NW) {
         const int q3 = LP2::idx(Geo<2, L>::half_site(tile * 16 + m, ppar));
         f32x4 acc[1] = {f32x4{pl[off_b3], 0.f, 0.f, 0.f}};
-        // fetched fragments: a few chunks in flight at a time, not all 27
 #pragma unroll Cfg::NARROW_HELD ? LF.k2 : 3
         for (int c = 0; c < LF.k2; ++c) {
           u32x4 a3;
           if constexpr (Cfg::NARROW_HELD)
             a3 = A3[c];
           else
-            a3 = fl[(LF.off3 + c) * 64];  // L2-resident, shared by every workgroup
+            a3 = t3[c * 8 + 2 * j + (m & 1)];
           acc[0] = mma<true>(a3, gather_rb<L, C, 1>(r2, q3, sm, s0, sp, c, j), acc[0]);
         }
         if (j == 0) {
@@ -341,6 +350,9 @@ __global__ void __launch_bounds__(NT) kr_transpose(
   uint32_t* sm1 = sm2 + PLANE;                                          // h1 signs of one plane
   uint16_t* ra2 = reinterpret_cast<uint16_t*>(smem + Cfg::GOR_BYTES + 2 * PLANE * 4);
   uint16_t* ra1 = ra2 + Cfg::RING;
+  u32x4* t1 = reinterpret_cast<u32x4*>(ra1 + Cfg::RING);  // visible after the sample loop's first barrier
+  if constexpr (!Cfg::NARROW_HELD)
+    for (int i = threadIdx.x; i < LF.k2 * 4; i += NT) t1[i] = frags[(Cfg::OFF1T + (i >> 2)) * 64 + 16 * (i & 3)];
   if (threadIdx.x == 0) gor[Cfg::ZS] = 0u;
   for (int q = threadIdx.x; q < C; q += NT) ra2[Cfg::ZS * C + q] = 0, ra1[Cfg::ZS * C + q] = 0;
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
@@ -435,14 +447,13 @@ __global__ void __launch_bounds__(NT) kr_transpose(
       for (int tile = w; tile < PLANE / 32; tile += NW) {
         const int q = Geo<2, L>::half_site(tile * 16 + m, fp), pq = LP2::idx(q);
         f32x4 acc{0.f, 0.f, 0.f, 0.f};
-        // fetched fragments: a few chunks in flight at a time, not all 27
 #pragma unroll Cfg::NARROW_HELD ? LF.k2 : 3
         for (int c = 0; c < LF.k2; ++c) {
           u32x4 a1;
           if constexpr (Cfg::NARROW_HELD)
             a1 = A1T[c];
           else
-            a1 = fl[(Cfg::OFF1T + c) * 64];  // L2-resident, shared by every workgroup
+            a1 = t1[c * 4 + j];
           acc = mma<true>(a1, gather_rb<L, C, -1>(ra1, pq, sm, s0, sp, c, j), acc);
         }
         if (j == 0) gx[sb + zr * PLANE + q] = gys[zr & 1][q] + acc[0];
