@@ -789,7 +789,8 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
         }
       }
     }
-    __syncthreads();
+    // dW1 and conv1^T only read LDS (conv1^T needs g_a1's halo where there is one)
+    if constexpr (LY::padded) __syncthreads();
     // ---- conv1^T at the frozen sites: g_x = g_y + W1^T * g_a1 ----
     // (3D through the shared tile pass, which also frees registers there; 2D keeps
     // the plain loop, measured faster at the 2D shapes)
@@ -833,8 +834,11 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
             if (j == 0) gx[sb + n] = gys[n] + acc[0][0];
           });
     }
-    __syncthreads();
+    // SPLIT: the next sample's staging writes only the field, which the tail passes
+    // (dW1, conv1^T) do not read; its first barrier comes before any other write
+    if constexpr (!Cfg::SPLIT) __syncthreads();
   }
+  if constexpr (Cfg::SPLIT) __syncthreads();  // the partial sums below overwrite the sample state
 
   // ---- sum the waves' weight-gradient tiles in a fixed order, write the partial ----
   float* red = reinterpret_cast<float*>(smem);
