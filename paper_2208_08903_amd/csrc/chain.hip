@@ -70,10 +70,13 @@ __global__ void __launch_bounds__(64) k_mh_chain(int n_prop_rect, const int64_t*
   }
 }
 
-// Per-site action density and force from an LDS-resident FP64 field.
-template <int DIM>
-__device__ __forceinline__ void site_terms(const double* f, int n, int L, double m2, double lam,
+// Per-site action density and force from an LDS-resident FP64 field.  L is the
+// compile-time LT where LT > 0 (a power of two: the coordinate arithmetic is shifts
+// and masks), else the runtime value.
+template <int DIM, int LT>
+__device__ __forceinline__ void site_terms(const double* f, int n, int Lrt, double m2, double lam,
                                            double& dens, double& frc) {
+  const int L = LT > 0 ? LT : Lrt;
   const double p = f[n];
   double nb = 0.0;
   int stride = 1;
@@ -96,10 +99,10 @@ __device__ __forceinline__ void site_terms(const double* f, int n, int L, double
 // half-kick of the next use the force at the same field, so it is evaluated
 // once per step (and once at the start); both half-kicks are still applied as
 // two separate subtractions, as the definition has them.  The last force pass
-// also sums the final Hamiltonian.  Every thread owns sites tid, tid + 256, ...
+// also sums the final Hamiltonian.  Every thread owns sites tid, tid + blockDim, ...
 // in every pass, so its kicks read only its own force entries.
-template <int DIM>
-__global__ void __launch_bounds__(256) k_hmc(int L, double* __restrict__ phi,
+template <int DIM, int LT>
+__global__ void __launch_bounds__(256) k_hmc(int Lrt, double* __restrict__ phi,
                                              const double* __restrict__ pi0,
                                              const double* __restrict__ log_u,
                                              const double* __restrict__ m2p,
@@ -108,6 +111,7 @@ __global__ void __launch_bounds__(256) k_hmc(int L, double* __restrict__ phi,
                                              uint8_t* __restrict__ accepted) {
   extern __shared__ double smem[];
   __shared__ double sh[16];
+  const int L = LT > 0 ? LT : Lrt;
   int V = L;
   for (int i = 1; i < DIM; ++i) V *= L;
   double* f = smem;
@@ -122,7 +126,7 @@ __global__ void __launch_bounds__(256) k_hmc(int L, double* __restrict__ phi,
   __syncthreads();
   double h = 0.0, dens, frc;
   for (int n = threadIdx.x; n < V; n += blockDim.x) {
-    site_terms<DIM>(f, n, L, m2, lam, dens, frc);
+    site_terms<DIM, LT>(f, n, L, m2, lam, dens, frc);
     F[n] = frc;
     h += 0.5 * p[n] * p[n] + dens;
   }
@@ -137,7 +141,7 @@ __global__ void __launch_bounds__(256) k_hmc(int L, double* __restrict__ phi,
     __syncthreads();
     const bool last = s == n_steps - 1;
     for (int n = threadIdx.x; n < V; n += blockDim.x) {
-      site_terms<DIM>(f, n, L, m2, lam, dens, frc);
+      site_terms<DIM, LT>(f, n, L, m2, lam, dens, frc);
       F[n] = frc;
       p[n] = p[n] - hdt * frc;
       if (last) h += 0.5 * p[n] * p[n] + dens;
@@ -207,17 +211,19 @@ extern "C" int32_t lfs_hmc_step(int32_t dim, int32_t L, int32_t B, double* phi, 
   LFS_RETURN_IF(!phi || !pi0 || !log_u || !m2 || !lam || !dH || !accepted, LFS_EINVAL);
   const size_t shm = 3 * (size_t)V * sizeof(double);
   hipStream_t st = (hipStream_t)stream;
-  if (shm > 64 * 1024) {
-    const void* k = dim == 2 ? reinterpret_cast<const void*>(lfs::k_hmc<2>) : reinterpret_cast<const void*>(lfs::k_hmc<3>);
-    LFS_RETURN_IF(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess,
+  // compile-time lattice sizes for the common powers of two, the runtime L otherwise
+  using Kern = void (*)(int, double*, const double*, const double*, const double*, const double*, int, int,
+                        double, double*, uint8_t*);
+  const int li = L == 4 ? 1 : L == 8 ? 2 : L == 16 ? 3 : 0;
+  static const Kern k2[4] = {lfs::k_hmc<2, 0>, lfs::k_hmc<2, 4>, lfs::k_hmc<2, 8>, lfs::k_hmc<2, 16>};
+  static const Kern k3[4] = {lfs::k_hmc<3, 0>, lfs::k_hmc<3, 4>, lfs::k_hmc<3, 8>, lfs::k_hmc<3, 16>};
+  const Kern k = dim == 2 ? k2[li] : k3[li];
+  if (shm > 64 * 1024)
+    LFS_RETURN_IF(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)shm) != hipSuccess,
                   LFS_EDEVICE);
-  }
-  if (dim == 2)
-    hipLaunchKernelGGL(lfs::k_hmc<2>, dim3(B), dim3(256), shm, st, L, phi, pi0, log_u, m2, lam,
-                       per_sample, n_steps, dt, dH, accepted);
-  else
-    hipLaunchKernelGGL(lfs::k_hmc<3>, dim3(B), dim3(256), shm, st, L, phi, pi0, log_u, m2, lam,
-                       per_sample, n_steps, dt, dH, accepted);
+  hipLaunchKernelGGL(k, dim3(B), dim3(256), shm, st, L, phi, pi0, log_u, m2, lam, per_sample, n_steps, dt, dH,
+                     accepted);
   return lfs::launch_status();
 }
 
