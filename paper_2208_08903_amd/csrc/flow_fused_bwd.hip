@@ -555,8 +555,9 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
     __syncthreads();
     // ---- dW3[co][ci][tap] += sum_m h2[m][ci] g_o[m - delta_tap][co] ----
     // tiles (mt, nt): rows ci = mt*16 + i, columns (tap, co) = nt*16 + m
-    // FP32 writes g_a2 over h2, which dW3 reads, so dW3 goes first; BF16 keeps
-    // them apart and runs dW3 after conv3^T, next to g_a2's halo fill.
+    // FP32 and SPLIT write g_a2 over h2, which dW3 reads, so dW3 goes first; the
+    // other BF16 layouts keep them apart and run dW3 after conv3^T, next to g_a2's
+    // halo fill.
     auto dw3 = [&]() {
       for (int kc = kc0; kc < kc1; ++kc) {
 #pragma unroll
