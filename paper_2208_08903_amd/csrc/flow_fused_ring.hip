@@ -47,10 +47,16 @@ struct RingCfg {
   // layer), and every lane reads entry 2 j + (m & 1), so rows 2..15 repeat rows 0
   // and 1; those rows of the product are never read.
   static constexpr size_t T3_BYTES = A3_HELD ? 0 : (size_t)LF.k2 * 8 * 16;
-  static constexpr size_t lds_bytes = XS_BYTES + 2 * RING + T3_BYTES;
+  // BF16: conv1's operands as row triples of the masked field (x-1, x, x+1, 0 per
+  // site, 8 bytes) in a ring of five planes, each built one step ahead of the
+  // conv1 passes that read it (three planes per pass, five in the prologue)
+  static constexpr bool TRIR = BF16;
+  static constexpr size_t TRI_BYTES = TRIR ? 5 * (size_t)L * L * 8 : 0;
+  static constexpr size_t lds_bytes = XS_BYTES + 2 * RING + T3_BYTES + TRI_BYTES;
 };
 
 __device__ __forceinline__ int mod3(int v) { return ((v % 3) + 3) % 3; }
+__device__ __forceinline__ int mod5(int v) { return ((v % 5) + 5) % 5; }
 
 // B operand of a C-input convolution on a ring: in-plane storage index pq of the
 // output site, the ring slots of planes v-1, v, v+1.
@@ -90,11 +96,21 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
   HT* r1 = reinterpret_cast<HT*>(smem + Cfg::XS_BYTES);
   HT* r2 = r1 + (3 * PS + 1) * C;
   u32x4* t3 = reinterpret_cast<u32x4*>(smem + Cfg::XS_BYTES + 2 * Cfg::RING);
+  uint16_t* tr = reinterpret_cast<uint16_t*>(smem + Cfg::XS_BYTES + 2 * Cfg::RING + Cfg::T3_BYTES);
   for (int q = threadIdx.x; q < C; q += NT) r1[Cfg::ZS * C + q] = HT(0), r2[Cfg::ZS * C + q] = HT(0);
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
   // this wave's channel tile and its index among that tile's waves
   const int ct = LF.nct == 1 ? 0 : w / WPC, wc = LF.nct == 1 ? w : w % WPC;
   const size_t BV = (size_t)B * V;
+  // the lane's four triple rows (chunk c, slot u: row r = 8 c + 2 j + u, past the nine
+  // rows (dz, dy) = (r / 3 - 1, r % 3 - 1) the centre row, which meets zero weights)
+  int tdz[4], tdy[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r0 = 8 * (i >> 1) + 2 * j + (i & 1), r = r0 < 9 ? r0 : 4;
+    tdz[i] = r / 3 - 1;
+    tdy[i] = r % 3 - 1;
+  }
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     R zz = 0;
@@ -124,16 +140,45 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
       }
       const float bs = pl[off_b3], bt = pl[off_b3 + 1];
 
+      // row triples of the masked field of virtual plane v into triple-ring slot v mod 5
+      // (only frozen sites' values enter, which conv3 never changes)
+      auto build_tri_plane = [&](int v) {
+        const int zr = ((v % L) + L) % L;
+        uint16_t* dst = tr + mod5(v) * PLANE * 4;
+        for (int q = threadIdx.x; q < PLANE; q += NT) {
+          const int n = zr * PLANE + q, p = LX::idx(n);
+          const bool frozen = G::parity(n) == fpar;  // the x neighbours have the other parity
+          const float v0 = frozen ? 0.f : xs[p - 1], v1 = frozen ? xs[p] : 0.f, v2 = frozen ? 0.f : xs[p + 1];
+          *reinterpret_cast<u32x2*>(dst + 4 * q) = u32x2{pack_bf16(v0, v1), pack_bf16(v2, 0.f)};
+        }
+      };
       // h1 of virtual plane v into ring slot v mod 3
       auto conv1_plane = [&](int v) {
         const int zr = ((v % L) + L) % L;
         HT* dst = r1 + mod3(v) * PS * C;
+        int tbase[4];  // the lane's triple rows: ring slot of plane v + dz, as an element offset
+        if constexpr (Cfg::TRIR) {
+          const int sm = mod5(v - 1) * PLANE, s0 = mod5(v) * PLANE, sp = mod5(v + 1) * PLANE;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) tbase[i] = tdz[i] < 0 ? sm : (tdz[i] > 0 ? sp : s0);
+        }
         for (int tile = wc; tile < PLANE / 16; tile += WPC) {
           const int q = tile * 16 + m, n = zr * PLANE + q;
-          const int p = LX::idx(n), pn = G::parity(n);
           f32x4 acc{0.f, 0.f, 0.f, 0.f};
+          if constexpr (Cfg::TRIR) {
+            // tile = in-plane row y, m = x
 #pragma unroll
-          for (int c = 0; c < LF.k1; ++c) acc = mma<BF16>(A1[c], gather_tri_x<LX, BF16>(xs, n, p, pn, fpar, c, j), acc);
+            for (int c = 0; c < LF.k1; ++c) {
+              const int e0 = (tbase[2 * c] + ((tile + tdy[2 * c]) & (L - 1)) * L + m) * 4;
+              const int e1 = (tbase[2 * c + 1] + ((tile + tdy[2 * c + 1]) & (L - 1)) * L + m) * 4;
+              const u32x2 a = *reinterpret_cast<const u32x2*>(tr + e0), b = *reinterpret_cast<const u32x2*>(tr + e1);
+              acc = mma<BF16>(A1[c], u32x4{a[0], a[1], b[0], b[1]}, acc);
+            }
+          } else {
+            const int p = LX::idx(n), pn = G::parity(n);
+#pragma unroll
+            for (int c = 0; c < LF.k1; ++c) acc = mma<BF16>(A1[c], gather_tri_x<LX, BF16>(xs, n, p, pn, fpar, c, j), acc);
+          }
           store_hidden<LP2, C, BF16>(dst, q, ct, j, acc, bias1);
         }
       };
@@ -182,20 +227,28 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
         const u32x4* f3 = frags + ((size_t)layer * LF.total + LF.off3) * 64;
         for (int i = threadIdx.x; i < LF.k2 * 8; i += NT) t3[i] = f3[(i >> 3) * 64 + 16 * ((i & 7) >> 1) + (i & 1)];
       }
+      if constexpr (Cfg::TRIR) {
+        for (int v = -3; v <= 1; ++v) build_tri_plane(v);
+        __syncthreads();
+      }
       conv1_plane(-2);
       conv1_plane(-1);
       conv1_plane(0);
       __syncthreads();
       conv2_plane(-1);
+      if constexpr (Cfg::TRIR) build_tri_plane(2);  // over plane -3's triples, last read by conv1(-2)
       __syncthreads();
       conv1_plane(1);
       __syncthreads();
       conv2_plane(0);
+      if constexpr (Cfg::TRIR) build_tri_plane(3);
       __syncthreads();
       for (int zr = 0; zr < L; ++zr) {
-        conv1_plane(zr + 2);
+        conv1_plane(zr + 2);  // triples of planes zr + 1 .. zr + 3
         __syncthreads();
         conv2_plane(zr + 1);
+        // plane zr + 4's triples (for the next conv1) over plane zr - 1's, last read by conv1(zr)
+        if constexpr (Cfg::TRIR) build_tri_plane(zr + 4);
         __syncthreads();
         conv3_plane(zr);
       }
