@@ -57,7 +57,11 @@ struct RbCfg {
   // product repeat the live ones and are never read.
   static constexpr size_t T3_BYTES = NARROW_HELD ? 0 : (size_t)LF.k2 * 8 * 16;
   static constexpr size_t T1_BYTES = NARROW_HELD ? 0 : (size_t)LF.k2 * 4 * 16;
-  static constexpr size_t LDS_A = XS_BYTES + 2 * (size_t)RING * 2 + T3_BYTES;
+  // recompute: conv1's operands as row triples of the masked field (x-1, x, x+1, 0
+  // per site, 8 bytes) in a ring of four planes, built one step ahead of the conv1
+  // passes that read them (three planes per pass)
+  static constexpr size_t TRI_BYTES = 4 * (size_t)PLANE * 8;
+  static constexpr size_t LDS_A = XS_BYTES + 2 * (size_t)RING * 2 + T3_BYTES + TRI_BYTES;
   // transpose: g_o ring, the LeakyReLU sign masks of one h2 and one h1 plane, two rings
   static constexpr size_t LDS_B = GOR_BYTES + 2 * (size_t)PLANE * 4 + 2 * (size_t)RING * 2 + T1_BYTES;
   // weights: three plane buffers [C][CS] (h1, h2, g_a1 of plane z) and rings of
@@ -185,6 +189,7 @@ __global__ void __launch_bounds__(NT) kr_recompute(
   uint16_t* r1 = reinterpret_cast<uint16_t*>(smem + Cfg::XS_BYTES);
   uint16_t* r2 = r1 + Cfg::RING;
   u32x4* t3 = reinterpret_cast<u32x4*>(r2 + Cfg::RING);  // visible after the sample loop's first barrier
+  uint16_t* tr = reinterpret_cast<uint16_t*>(smem + Cfg::XS_BYTES + 2 * (size_t)Cfg::RING * 2 + Cfg::T3_BYTES);
   if constexpr (!Cfg::NARROW_HELD)
     for (int i = threadIdx.x; i < LF.k2 * 8; i += NT)
       t3[i] = frags[(LF.off3 + (i >> 3)) * 64 + 16 * ((i & 7) >> 1) + (i & 1)];
@@ -195,6 +200,15 @@ __global__ void __launch_bounds__(NT) kr_recompute(
   // this wave's channel tile and its index among that tile's waves
   const int ct = LF.nct == 1 ? 0 : w / WPC, wc = LF.nct == 1 ? w : w % WPC;
   const int apar = fpar ^ 1;
+  // the lane's four triple rows (chunk c, slot u: row r = 8 c + 2 j + u, past the nine
+  // rows (dz, dy) = (r / 3 - 1, r % 3 - 1) the centre row, which meets zero weights)
+  int tdz[4], tdy[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r0 = 8 * (i >> 1) + 2 * j + (i & 1), r = r0 < 9 ? r0 : 4;
+    tdz[i] = r / 3 - 1;
+    tdy[i] = r % 3 - 1;
+  }
   const u32x4* fl = frags + lane;
   u32x4 A1[1][LF.k1], A2[1][LF.k2], A3[Cfg::NARROW_HELD ? LF.k2 : 1];
   const f32x4 bias1[1] = {load_bias4<C>(pl + off_b1, ct, j)}, bias2[1] = {load_bias4<C>(pl + off_b2, ct, j)};
@@ -228,16 +242,33 @@ __global__ void __launch_bounds__(NT) kr_recompute(
     for (int q = threadIdx.x; q < LX::VS; q += NT) xs[q] = xin[sb + LX::site_of(q)];
     __syncthreads();
 
+    // row triples of the masked field of virtual plane v into triple-ring slot v mod 4
+    // (only frozen sites' values enter)
+    auto build_tri_plane = [&](int v) {
+      const int zr = ((v % L) + L) % L;
+      uint16_t* dst = tr + (v & 3) * PLANE * 4;
+      for (int q = threadIdx.x; q < PLANE; q += NT) {
+        const int n = zr * PLANE + q, p = LX::idx(n);
+        const bool frozen = G::parity(n) == fpar;  // the x neighbours have the other parity
+        const float v0 = frozen ? 0.f : xs[p - 1], v1 = frozen ? xs[p] : 0.f, v2 = frozen ? 0.f : xs[p + 1];
+        *reinterpret_cast<u32x2*>(dst + 4 * q) = u32x2{pack_bf16(v0, v1), pack_bf16(v2, 0.f)};
+      }
+    };
     // h1 of virtual plane v into ring slot v mod 3 (and, for a real plane, to h1c)
     auto conv1_plane = [&](int v) {
       const int zr = ((v % L) + L) % L;
       const bool real = v >= 0 && v < L;
       uint16_t* dst = r1 + mod3(v) * PS * C;
+      int tbase[4];  // the lane's triple rows: ring slot of plane v + dz, as an element offset
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tbase[i] = ((v + tdz[i]) & 3) * PLANE;
       mma_tiles<1, 1, LF.k1, true>(
           PLANE / 16, wc, WPC, A1, bias1,
-          [&](int tile, int c) {
-            const int n = zr * PLANE + tile * 16 + m;
-            return gather_tri_x<LX, true>(xs, n, LX::idx(n), G::parity(n), fpar, c, j);
+          [&](int tile, int c) {  // tile = in-plane row y, m = x
+            const int e0 = (tbase[2 * c] + ((tile + tdy[2 * c]) & (L - 1)) * L + m) * 4;
+            const int e1 = (tbase[2 * c + 1] + ((tile + tdy[2 * c + 1]) & (L - 1)) * L + m) * 4;
+            const u32x2 a = *reinterpret_cast<const u32x2*>(tr + e0), b = *reinterpret_cast<const u32x2*>(tr + e1);
+            return u32x4{a[0], a[1], b[0], b[1]};
           },
           [&](int tile, const f32x4(&acc)[1]) {
             const u32x2 hv = store_act_tile<LP2, C, true>(dst, tile, m, ct, j, acc[0]);
@@ -296,24 +327,34 @@ __global__ void __launch_bounds__(NT) kr_recompute(
         go[sb + zr * PLANE + Geo<2, L>::half_site(i, ppar ^ 1)] = 0u;
     };
 
-    conv1_plane(-2);
-    conv1_plane(-1);
+    // triple ring slot (v & 3): each plane's triples are built after the last conv1
+    // pass that read the plane four back in the same slot
+    for (int v = -3; v <= 0; ++v) build_tri_plane(v);
+    __syncthreads();
+    conv1_plane(-2);  // triples of planes -3 .. -1
+    conv1_plane(-1);  // -2 .. 0
+    __syncthreads();
+    build_tri_plane(1);  // over plane -3's
+    __syncthreads();
     conv1_plane(0);
     __syncthreads();
     conv2_plane(-1);
+    build_tri_plane(2);  // over plane -2's, last read by conv1(-1)
     __syncthreads();
     conv1_plane(1);
     __syncthreads();
     conv2_plane(0);
+    build_tri_plane(3);  // over plane -1's, last read by conv1(0)
     __syncthreads();
     for (int zr = 0; zr < L; ++zr) {
       // plane zr's g_y is read here and held in a register through conv1, so its
       // HBM latency hides behind that pass instead of stalling conv3's epilogue
       const float gpre = threadIdx.x < PLANE ? gy[sb + zr * PLANE + threadIdx.x] : 0.f;
-      conv1_plane(zr + 2);
+      conv1_plane(zr + 2);  // triples of planes zr + 1 .. zr + 3
       if (threadIdx.x < PLANE) gys[zr & 1][threadIdx.x] = gpre;
       __syncthreads();
       conv2_plane(zr + 1);
+      build_tri_plane(zr + 4);  // over plane zr's, last read by conv1(zr + 1)
       __syncthreads();
       conv3_plane(zr);
     }
