@@ -200,16 +200,21 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
         const int ppar = apar ^ (zr & 1);  // in-plane parity of the active sites
         for (int tile = w; tile < PLANE / 32; tile += NW) {
           const int q = Geo<2, L>::half_site(tile * 16 + m, ppar), pq = LP2::idx(q);
-          f32x4 acc{0.f, 0.f, 0.f, 0.f};
-#pragma unroll Cfg::A3_HELD ? LF.k2 : 9
-          for (int c = 0; c < LF.k2; ++c) {
-            u32x4 a3;
+          // two accumulator chains (even and odd chunks), summed at the end
+          auto a3_of = [&](int c) -> u32x4 {
             if constexpr (Cfg::A3_HELD)
-              a3 = A3[c];
+              return A3[c];
             else
-              a3 = t3[c * 8 + 2 * j + (m & 1)];
-            acc = mma<BF16>(a3, gather_ring<L, C, BF16>(r2, pq, sm, s0, sp, c, j), acc);
+              return t3[c * 8 + 2 * j + (m & 1)];
+          };
+          f32x4 ae{0.f, 0.f, 0.f, 0.f}, ao{0.f, 0.f, 0.f, 0.f};
+#pragma unroll Cfg::A3_HELD ? LF.k2 / 2 : 4
+          for (int c = 0; c + 1 < LF.k2; c += 2) {
+            ae = mma<BF16>(a3_of(c), gather_ring<L, C, BF16>(r2, pq, sm, s0, sp, c, j), ae);
+            ao = mma<BF16>(a3_of(c + 1), gather_ring<L, C, BF16>(r2, pq, sm, s0, sp, c + 1, j), ao);
           }
+          if constexpr (LF.k2 % 2) ae = mma<BF16>(a3_of(LF.k2 - 1), gather_ring<L, C, BF16>(r2, pq, sm, s0, sp, LF.k2 - 1, j), ae);
+          const f32x4 acc = ae + ao;
           if (j == 0) {
             const int n = zr * PLANE + q;
             const float o0 = acc[0] + bs, t = acc[1] + bt;

@@ -299,16 +299,21 @@ __global__ void __launch_bounds__(NT) kr_recompute(
       const int ppar = apar ^ (zr & 1);  // in-plane parity of the active sites
       for (int tile = w; tile < PLANE / 32; tile += NW) {
         const int q3 = LP2::idx(Geo<2, L>::half_site(tile * 16 + m, ppar));
-        f32x4 acc[1] = {f32x4{pl[off_b3], 0.f, 0.f, 0.f}};
-#pragma unroll Cfg::NARROW_HELD ? LF.k2 : 3
-        for (int c = 0; c < LF.k2; ++c) {
-          u32x4 a3;
+        // two accumulator chains (even and odd chunks), summed at the end
+        auto a3_of = [&](int c) -> u32x4 {
           if constexpr (Cfg::NARROW_HELD)
-            a3 = A3[c];
+            return A3[c];
           else
-            a3 = t3[c * 8 + 2 * j + (m & 1)];
-          acc[0] = mma<true>(a3, gather_rb<L, C, 1>(r2, q3, sm, s0, sp, c, j), acc[0]);
+            return t3[c * 8 + 2 * j + (m & 1)];
+        };
+        f32x4 ae{pl[off_b3], 0.f, 0.f, 0.f}, ao{0.f, 0.f, 0.f, 0.f};
+#pragma unroll Cfg::NARROW_HELD ? LF.k2 / 2 : 2
+        for (int c = 0; c + 1 < LF.k2; c += 2) {
+          ae = mma<true>(a3_of(c), gather_rb<L, C, 1>(r2, q3, sm, s0, sp, c, j), ae);
+          ao = mma<true>(a3_of(c + 1), gather_rb<L, C, 1>(r2, q3, sm, s0, sp, c + 1, j), ao);
         }
+        if constexpr (LF.k2 % 2) ae = mma<true>(a3_of(LF.k2 - 1), gather_rb<L, C, 1>(r2, q3, sm, s0, sp, LF.k2 - 1, j), ae);
+        const f32x4 acc[1] = {ae + ao};
         if (j == 0) {
           const int n = zr * PLANE + Geo<2, L>::half_site(tile * 16 + m, ppar);
           const float o0 = acc[0][0];
@@ -487,16 +492,21 @@ __global__ void __launch_bounds__(NT) kr_transpose(
       const int fp = fpar ^ (zr & 1);  // in-plane parity of the frozen sites
       for (int tile = w; tile < PLANE / 32; tile += NW) {
         const int q = Geo<2, L>::half_site(tile * 16 + m, fp), pq = LP2::idx(q);
-        f32x4 acc{0.f, 0.f, 0.f, 0.f};
-#pragma unroll Cfg::NARROW_HELD ? LF.k2 : 3
-        for (int c = 0; c < LF.k2; ++c) {
-          u32x4 a1;
+        // two accumulator chains (even and odd chunks), summed at the end
+        auto a1_of = [&](int c) -> u32x4 {
           if constexpr (Cfg::NARROW_HELD)
-            a1 = A1T[c];
+            return A1T[c];
           else
-            a1 = t1[c * 4 + j];
-          acc = mma<true>(a1, gather_rb<L, C, -1>(ra1, pq, sm, s0, sp, c, j), acc);
+            return t1[c * 4 + j];
+        };
+        f32x4 ae{0.f, 0.f, 0.f, 0.f}, ao{0.f, 0.f, 0.f, 0.f};
+#pragma unroll Cfg::NARROW_HELD ? LF.k2 / 2 : 2
+        for (int c = 0; c + 1 < LF.k2; c += 2) {
+          ae = mma<true>(a1_of(c), gather_rb<L, C, -1>(ra1, pq, sm, s0, sp, c, j), ae);
+          ao = mma<true>(a1_of(c + 1), gather_rb<L, C, -1>(ra1, pq, sm, s0, sp, c + 1, j), ao);
         }
+        if constexpr (LF.k2 % 2) ae = mma<true>(a1_of(LF.k2 - 1), gather_rb<L, C, -1>(ra1, pq, sm, s0, sp, LF.k2 - 1, j), ae);
+        const f32x4 acc = ae + ao;
         if (j == 0) gx[sb + zr * PLANE + q] = gys[zr & 1][q] + acc[0];
       }
     };
