@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(NT) kf_forward(
         f32x4 bias[LF.nct];
 #pragma unroll
         for (int ct = 0; ct < LF.nct; ++ct) bias[ct] = load_bias4<C>(pl + off_b1, ct, j);
-        mma_tiles<Cfg::TU1, LF.nct, LF.k1, BF16>(
+        mma_tiles<Cfg::TU1, LF.nct, LF.k1, BF16, k_tri(Cfg::T), true>(
             V / 16, w, NW, A1, bias,
             [&](int tile, int c) {
               if constexpr (Cfg::TRIX) {

@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
 #pragma unroll
         for (int c = 0; c < LF.k1; ++c) A[ct][c] = fr[(LF.off1 + ct * LF.k1 + c) * 64];
       }
-      mma_tiles<Cfg::TU, LF.nct, LF.k1, BF16>(
+      mma_tiles<Cfg::TU, LF.nct, LF.k1, BF16, k_tri(T), true>(
           V / 16, w, NW, A, bias1,
           [&](int tile, int c) {
             return gather_tri<LY, BF16>(h2s, tile * 16 + m, tile_p<LY>(tile, m), c, j);
@@ -604,7 +604,7 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
 #pragma unroll
         for (int c = 0; c < Cfg::KT3; ++c) A[ct][c] = fr[(Cfg::OFF3T + ct * Cfg::KT3 + c) * 64];
       const f32x4 zero[LF.nct] = {};
-      mma_tiles<Cfg::TU, LF.nct, Cfg::KT3, BF16>(
+      mma_tiles<Cfg::TU, LF.nct, Cfg::KT3, BF16, 2 * T>(
           V / 16, w, NW, A, zero,
           [&](int tile, int c) {
             const int n = tile * 16 + m, p = tile_p<LY>(tile, m);

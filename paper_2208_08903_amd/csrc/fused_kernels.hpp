@@ -342,7 +342,12 @@ __device__ __forceinline__ f32x4 load_bias4(const float* b, int ct, int j) {
 // arrange by itself (it cannot prove the epilogue's stores miss the next
 // tile's loads).  Accumulators start from init (a bias, or zeros).
 // gather(tile, c) -> u32x4; epi(tile, f32x4 (&acc)[NCT]).
-template <int TU, int NCT, int KC, bool BF16, class Gather, class Epi>
+//
+// FP32: chunk c is four MFMAs, MFMA r taking k = 16 c + 4 j + r from lane group j;
+// those whose k are all padding (k >= KLIM, or the zero slot 3 of every row
+// triple when TRI) are not issued.
+template <int TU, int NCT, int KC, bool BF16, int KLIM = (1 << 30), bool TRI = false, class Gather,
+          class Epi>
 __device__ __forceinline__ void mma_tiles(int ntiles, int w, int nw, const u32x4 (&A)[NCT][KC],
                                           const f32x4 (&init)[NCT], Gather&& gather, Epi&& epi) {
   for (int t0 = w; t0 < ntiles; t0 += TU * nw) {
@@ -362,7 +367,16 @@ __device__ __forceinline__ void mma_tiles(int ntiles, int w, int nw, const u32x4
 #pragma unroll
       for (int u = 0; u < TU; ++u)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = mma<BF16>(A[ct][c], bop[u], acc[u][ct]);
+        for (int ct = 0; ct < NCT; ++ct) {
+          if constexpr (BF16) {
+            acc[u][ct] = mma<true>(A[ct][c], bop[u], acc[u][ct]);
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (16 * c + r < KLIM && !(TRI && r == 3))
+                acc[u][ct] = mfma(__uint_as_float(A[ct][c][r]), __uint_as_float(bop[u][r]), acc[u][ct]);
+          }
+        }
     }
 #pragma unroll
     for (int u = 0; u < TU; ++u)
