@@ -472,6 +472,28 @@ def test_flow_backward_fused_deterministic_and_batch_sum():
 
 
 @pytest.mark.parametrize("precision", [lfs.LFS_PLAIN_FP32, lfs.LFS_BF16_CONV])
+def test_flow_backward_fused_ragged_grid(precision):
+    """2D L = 32, C = 16 at a batch that leaves the backward's workgroups unevenly loaded:
+    515 samples give the BF16 grid of 512 (two workgroups per CU) three workgroups with two
+    samples, and the FP32 grid of 256 three with three.  The batch gradient is the sum of
+    the gradients of the two sub-batches (run on grids of 257 and 256: one and two samples
+    per workgroup), up to FP32 summation order, and every sample's g_z is bitwise its
+    sub-batch's."""
+    desc, params, z, fs = _flow_case(2, 32, 2, 16, 515, precision, lfs.ALGO_FUSED)
+    g = np.random.default_rng(25).standard_normal(z.shape).astype(np.float32)
+    ga, gza = run_backward(desc, run_forward(desc, params, z), g, 0.2)
+    parts = []
+    for sl in (slice(0, 257), slice(257, 515)):
+        gi, gzi = run_backward(desc, run_forward(desc, params, z[sl]), g[sl], 0.2)
+        np.testing.assert_array_equal(gzi, gza[sl])
+        parts.append(gi)
+    assert rel_norm(ga, parts[0] + parts[1]) < 1e-5
+    for lay_a, lay_s in zip(of.unpack(ga, fs), of.unpack(parts[0] + parts[1], fs)):
+        for a, b in zip(lay_a, lay_s):
+            assert rel_norm(a, b) < 1e-4, (rel_norm(a, b), a.shape)
+
+
+@pytest.mark.parametrize("precision", [lfs.LFS_PLAIN_FP32, lfs.LFS_BF16_CONV])
 def test_fused_backward_matches_generic(precision):
     desc_f, params, z, fs = _flow_case(2, 8, 4, 8, 8, precision, lfs.ALGO_FUSED)
     desc_g, *_ = _flow_case(2, 8, 4, 8, 8, precision, lfs.ALGO_GENERIC)
