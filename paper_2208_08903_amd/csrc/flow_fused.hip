@@ -39,9 +39,9 @@ __global__ void __launch_bounds__(NT) kf_forward(
   __shared__ R red[16];
   float* xs = reinterpret_cast<float*>(smem);
   HT* h1 = reinterpret_cast<HT*>(smem + ((LY::VSZ * 4 + 15) / 16) * 16);
-  HT* h2 = h1 + LY::VSZ * C;
-  u32x4* qt = reinterpret_cast<u32x4*>(h2 + LY::VSZ * C);  // FP32: the layer's conv3 A table
-  for (int q = threadIdx.x; q < C; q += NT) h1[LY::ZS * C + q] = 0, h2[LY::ZS * C + q] = 0;
+  HT* h2 = h1 + LY::template elems<C>();
+  u32x4* qt = reinterpret_cast<u32x4*>(h2 + LY::template elems<C>());  // FP32: the layer's conv3 A table
+  for (int q = threadIdx.x; q < C; q += NT) h1[LY::template off<C>(LY::ZS, q)] = 0, h2[LY::template off<C>(LY::ZS, q)] = 0;
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
   const size_t BV = (size_t)B * V;
 

@@ -42,13 +42,13 @@ constexpr size_t cmaxz(size_t a, size_t b) { return a > b ? a : b; }
 // SPLIT (2D BF16 at L = 32): the sample state of a 4-wave workgroup kept under
 // half the LDS so that two workgroups share a CU: no g_y copy (read from L2),
 // the masked field's channel-major row over g_o's (built after dW3), two slots.
-template <int DIM, int L, int C, bool BF16, bool PAD, bool SPLIT = false>
+template <int DIM, int L, int C, bool BF16, bool PAD, bool SPLIT = false, bool QM = false>
 struct BwdLds {
-  using LY = Lay<DIM, L, PAD>;
+  using LY = Lay<DIM, L, PAD, QM>;
   static constexpr int V = Geo<DIM, L>::V, VS = LY::VS;
   static constexpr int CSTR = V + 8;  // channel-major row stride in elements (BF16 mode)
   // site-major tensors and g_o carry the layout's extra all-zero site
-  static constexpr size_t SA = (size_t)LY::VSZ * C * (BF16 ? 2 : 4);  // site-major tensor
+  static constexpr size_t SA = (size_t)LY::template elems<C>() * (BF16 ? 2 : 4);  // activation tensor
   static constexpr size_t OFF_XS = 0;
   static constexpr size_t OFF_GY = align16((size_t)VS * 4);
   static constexpr size_t OFF_GOS = OFF_GY + (SPLIT ? 0 : align16((size_t)V * 4));
@@ -99,7 +99,9 @@ struct BwdCfg {
   // the layer's weight fragments read from L2 instead of an LDS copy.
   static constexpr bool SPLIT = BF16 && DIM == 2 && L == 32 && C == 16;
   static constexpr bool PAD = !SPLIT && BwdLds<DIM, L, C, BF16, true>::MAIN <= 158 * 1024;
-  using M = BwdLds<DIM, L, C, BF16, PAD, SPLIT>;
+  // FP32 2D L = 32: activations quad-major (conflict-free gathers and stores)
+  static constexpr bool QM = !BF16 && DIM == 2 && !PAD;
+  using M = BwdLds<DIM, L, C, BF16, PAD, SPLIT, QM>;
   using LY = typename M::LY;
   static constexpr int CSTR = M::CSTR;
   // LDS of the sample state (and, after the sample loop, of the partial sums)
@@ -283,7 +285,8 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
     HT* z1 = reinterpret_cast<HT*>(smem + M::OFF_S1);
     HT* z2 = reinterpret_cast<HT*>(smem + (BF16 ? M::OFF_S2 : M::OFF_S1));
     for (int q = threadIdx.x; q < C; q += NT)
-      z0[LY::ZS * C + q] = HT(0), z1[LY::ZS * C + q] = HT(0), z2[LY::ZS * C + q] = HT(0);
+      z0[LY::template off<C>(LY::ZS, q)] = HT(0), z1[LY::template off<C>(LY::ZS, q)] = HT(0),
+      z2[LY::template off<C>(LY::ZS, q)] = HT(0);
     if (threadIdx.x < (BF16 ? 1 : 2))
       reinterpret_cast<uint32_t*>(smem + M::OFF_GOS)[LY::ZS * (BF16 ? 1 : 2) + threadIdx.x] = 0u;
   }
@@ -576,7 +579,7 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int sx = kc * 16 + 4 * j + r;
-              const float a = ci < C ? h2s[LY::idx(sx) * C + ci] : 0.f;
+              const float a = ci < C ? h2s[LY::template off<C>(LY::idx(sx), ci)] : 0.f;
 #pragma unroll
               for (int nt = 0; nt < NTL3; ++nt) {
                 const int col = nt * 16 + m, tap = col >> 1, co = col & 1;
@@ -641,7 +644,7 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
                   const u32x2 gv = store4_tile<LY, C, BF16, false>(ga2s, tile, m, c0, v);
                   if constexpr (M::CM2) store_cm4<C, CSTR>(ga2c, n, c0, gv);
                 } else {
-                  const f32x4 hh = *reinterpret_cast<const f32x4*>(h2s + p * C + c0);
+                  const f32x4 hh = *reinterpret_cast<const f32x4*>(h2s + LY::template off<C>(p, c0));
 #pragma unroll
                   for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
                   store4_tile<LY, C, BF16, false>(ga2s, tile, m, c0, v);
@@ -690,14 +693,14 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int sx = kc * 16 + 4 * j + r, px = LY::idx(sx);
-            const float a = ci < C ? h1s[px * C + ci] : 0.f;
+            const float a = ci < C ? h1s[LY::template off<C>(px, ci)] : 0.f;
             static_for<0, T>([&](auto tc) {
               constexpr int TAP = decltype(tc)::value;
               const int nb = LY::nbr(sx, px, TAP, -1);
 #pragma unroll
               for (int nt = 0; nt < MT; ++nt) {
                 const int co = nt * 16 + m;
-                const float bb = co < C ? ga2s[nb * C + co] : 0.f;
+                const float bb = co < C ? ga2s[LY::template off<C>(nb, co)] : 0.f;
                 acc2[(mt * T + TAP) * MT + nt] = mfma(a, bb, acc2[(mt * T + TAP) * MT + nt]);
               }
             });
@@ -738,7 +741,7 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
                   for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
                   store4_tile<LY, C, BF16, false>(ga1s, tile, m, c0, v);
                 } else {
-                  const f32x4 hh = *reinterpret_cast<const f32x4*>(h1s + p * C + c0);
+                  const f32x4 hh = *reinterpret_cast<const f32x4*>(h1s + LY::template off<C>(p, c0));
 #pragma unroll
                   for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
                   store4_tile<LY, C, BF16, false>(ga1s, tile, m, c0, v);
@@ -774,7 +777,7 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int sx = kc * 16 + 4 * j + r, px = LY::idx(sx);
-              const float a = c < C ? ga1s[px * C + c] : 0.f;
+              const float a = c < C ? ga1s[LY::template off<C>(px, c)] : 0.f;
 #pragma unroll
               for (int nt = 0; nt < NTL1; ++nt) {
                 const int tap = nt * 16 + m;

@@ -119,10 +119,17 @@ struct Geo {
 // constant per tap, and producers also write the halo copies of boundary sites.
 // Without PAD the storage index is the site index and neighbours come from
 // periodic wrap arithmetic (for shapes whose padded lattice does not fit LDS).
-template <int DIM, int L, bool PAD>
+// QM (FP32, unpadded): channels stored quad-major, [C / 4][site][4] with the quad
+// planes QSZ elements apart (QSZ * 4 bytes = 64 mod 256), instead of site-major
+// [site][C].  Sixteen lanes reading the same channel quad of sixteen consecutive
+// sites then touch 256 contiguous bytes (site-major: 64 bytes apart, four lanes per
+// bank group), and sixteen lanes reading the sixteen channels of one site still hit
+// sixteen different banks.
+template <int DIM, int L, bool PAD, bool QM = false>
 struct Lay {
   using G = Geo<DIM, L>;
   static constexpr bool padded = PAD;
+  static constexpr bool quad_major = QM;
   static constexpr int Ls = L;
   static constexpr int LP = PAD ? L + 2 : L;
   static constexpr int VS = DIM == 2 ? LP * LP : LP * LP * LP;  // storage sites
@@ -130,6 +137,21 @@ struct Lay {
   // convolution's K read it instead of branching.
   static constexpr int ZS = VS;
   static constexpr int VSZ = VS + 1;  // sites to allocate
+  // quad-plane stride (QM, 4-byte elements): at least 4 VSZ, and 16 mod 64
+  static constexpr int QSZ = (4 * VSZ + 47) / 64 * 64 + 16;
+  // element offset of channel ch of storage site p in a tensor of C channels
+  template <int C>
+  __host__ __device__ static constexpr int off(int p, int ch) {
+    if constexpr (QM)
+      return (ch >> 2) * QSZ + p * 4 + (ch & 3);
+    else
+      return p * C + ch;
+  }
+  // elements to allocate for a tensor of C channels
+  template <int C>
+  __host__ __device__ static constexpr int elems() {
+    return QM ? C / 4 * QSZ : VSZ * C;
+  }
 
   __device__ static __forceinline__ int idx(int n) {
     if constexpr (!PAD) return n;

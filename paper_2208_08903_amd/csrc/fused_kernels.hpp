@@ -79,7 +79,8 @@ __device__ __forceinline__ u32x4 gather_h(const HElem<BF16>* h, int n, int p, in
   constexpr int K = LY::G::T * C;
   const int k0 = BF16 ? 32 * c + 8 * j : 16 * c + 4 * j;
   const int tap = k0 / C, ci0 = k0 % C;
-  const int e = k0 < K ? LY::nbr(n, p, tap < LY::G::T ? tap : 0, SIGN) * C + ci0 : LY::ZS * C;
+  const int e = k0 < K ? LY::template off<C>(LY::nbr(n, p, tap < LY::G::T ? tap : 0, SIGN), ci0)
+                        : LY::template off<C>(LY::ZS, 0);
   return *reinterpret_cast<const u32x4*>(h + e);
 }
 
@@ -207,7 +208,7 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, const f32x4& c) {
 template <class LY, int C, int SIGN = 1>
 __device__ __forceinline__ u32x4 gather_q(const float* h, int n, int p, int q) {
   const int k0 = 4 * q, tap = k0 / C, ci0 = k0 % C;
-  return *reinterpret_cast<const u32x4*>(h + LY::nbr(n, p, tap, SIGN) * C + ci0);
+  return *reinterpret_cast<const u32x4*>(h + LY::template off<C>(LY::nbr(n, p, tap, SIGN), ci0));
 }
 
 // sum_k A[r][k] B[k] over KQ chunks of 4 k for the lane's site: fq points at the lane's
@@ -252,7 +253,7 @@ __device__ __forceinline__ u32x2 store4(HElem<BF16>* h, int n, int co0, const fl
     return wv;
   } else {
     const f32x4 fv{v[0], v[1], v[2], v[3]};
-    LY::copies(n, [&](int p) { *reinterpret_cast<f32x4*>(h + p * C + co0) = fv; });
+    LY::copies(n, [&](int p) { *reinterpret_cast<f32x4*>(h + LY::template off<C>(p, co0)) = fv; });
     return u32x2{0u, 0u};
   }
 }
@@ -284,9 +285,9 @@ __device__ __forceinline__ u32x2 store4_tile(HElem<BF16>* h, int tile, int m, in
   } else {
     const f32x4 fv{v[0], v[1], v[2], v[3]};
     if constexpr (HALO)
-      LY::copies_tile(tile, m, [&](int p) { *reinterpret_cast<f32x4*>(h + p * C + co0) = fv; });
+      LY::copies_tile(tile, m, [&](int p) { *reinterpret_cast<f32x4*>(h + LY::template off<C>(p, co0)) = fv; });
     else
-      *reinterpret_cast<f32x4*>(h + tile_p<LY>(tile, m) * C + co0) = fv;
+      *reinterpret_cast<f32x4*>(h + LY::template off<C>(tile_p<LY>(tile, m), co0)) = fv;
     return u32x2{0u, 0u};
   }
 }
@@ -305,7 +306,8 @@ __device__ __forceinline__ void fill_halo(HElem<BF16>* h) {
       const int e = i / CH, k = i - e * CH;
       int dst, src;
       LY::halo_entry(e, dst, src);
-      *reinterpret_cast<u32x4*>(h + dst * C + k * EL) = *reinterpret_cast<const u32x4*>(h + src * C + k * EL);
+      *reinterpret_cast<u32x4*>(h + LY::template off<C>(dst, k * EL)) =
+          *reinterpret_cast<const u32x4*>(h + LY::template off<C>(src, k * EL));
     }
   }
 }
@@ -390,12 +392,16 @@ struct FwdCfg {
   static constexpr int V = G::V, T = G::T;
   // FP32: conv3's quad A table, compact (4 rows of 16 bytes per chunk), after h2
   static constexpr size_t QT_BYTES = BF16 ? 0 : (size_t)(T * C / 4) * 4 * 16;
-  static constexpr size_t bytes_for(int vs) {
-    return ((size_t)vs * 4 + 15) / 16 * 16 + 2 * (size_t)vs * C * sizeof(HElem<BF16>) + QT_BYTES;
+  // FP32 2D L = 32: activations quad-major (conflict-free gathers and stores)
+  static constexpr bool QM = !BF16 && DIM == 2 && L == 32;
+  template <class LYX>
+  static constexpr size_t bytes_of() {
+    return ((size_t)LYX::VSZ * 4 + 15) / 16 * 16 + 2 * (size_t)LYX::template elems<C>() * sizeof(HElem<BF16>) +
+           QT_BYTES;
   }
-  static constexpr bool PAD = bytes_for(Lay<DIM, L, true>::VSZ) <= 156 * 1024;
-  using LY = Lay<DIM, L, PAD>;
-  static constexpr size_t lds_bytes = bytes_for(LY::VSZ);
+  static constexpr bool PAD = bytes_of<Lay<DIM, L, true, QM>>() <= 156 * 1024;
+  using LY = Lay<DIM, L, PAD, QM>;
+  static constexpr size_t lds_bytes = bytes_of<LY>();
   static constexpr int NT = lds_bytes > 80 * 1024 ? 512 : 256;
   // tiles in flight per wave: conv1 (one K chunk in BF16) and conv2/conv3
   static constexpr int TU1 = BF16 ? 4 : 2;
