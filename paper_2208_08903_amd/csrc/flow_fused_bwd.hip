@@ -147,7 +147,10 @@ struct BwdCfg {
   static constexpr int NKC = BF16 ? V / 32 : V / 16;  // K chunks (sites) per sample
   // Weight-gradient output tiles; every wave accumulates all of them over its
   // contiguous range of K chunks, and the waves are summed in a fixed order.
-  static constexpr int NTL3 = (2 * T + 15) / 16, NTL1 = (T + 15) / 16;
+  // FP32 2D: dW3's last tap (columns 16 and 17 of 18) on the 4x4 blocks (Q8), so its
+  // 16x16x4 tiles cover the first sixteen columns only
+  static constexpr bool Q8 = !BF16 && DIM == 2 && 2 * T == 18 && C % 4 == 0;
+  static constexpr int NTL3 = Q8 ? 1 : (2 * T + 15) / 16, NTL1 = (T + 15) / 16;
   static constexpr int I3 = MT * NTL3;
   static constexpr int I2 = MT * T * MT;
   static constexpr int I1 = MT * NTL1;
@@ -296,6 +299,13 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
 
   constexpr int NTL3 = Cfg::NTL3, NTL1 = Cfg::NTL1;
   f32x4 acc3[Cfg::I3], acc2[Cfg::I2], acc1[Cfg::I1];
+  // Q8: block b (lanes 4b .. 4b + 3) of a 4x4 MFMA takes site 16 kc + b; lane 4b + r gives
+  // h2 channel 4g + r (A) and lane 4b + c the last tap's g_o channel c (B, c < 2), and lane
+  // 4b + c receives D[4g + r][c] in register r: block-wise partial sums, added over the
+  // blocks after the sample loop
+  f32x4 acc8[Cfg::Q8 ? C / 4 : 1];
+#pragma unroll
+  for (int g = 0; g < (Cfg::Q8 ? C / 4 : 1); ++g) acc8[g] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < Cfg::I3; ++i) acc3[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -589,6 +599,12 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
             }
           }
         }
+        if constexpr (Cfg::Q8) {
+          const int sq = kc * 16 + (lane >> 2), pq = LY::idx(sq), c4 = lane & 3;
+          const float bq = c4 < 2 ? gos_f[2 * LY::nbr(sq, pq, T - 1, -1) + c4] : 0.f;
+#pragma unroll
+          for (int g = 0; g < C / 4; ++g) acc8[g] = mfma4(h2s[LY::template off<C>(pq, 4 * g + c4)], bq, acc8[g]);
+        }
       }
     };
     if constexpr (!BF16 || Cfg::SPLIT) {
@@ -859,6 +875,15 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
       }
   db3s = wave_sum(db3s);
   db3t = wave_sum(db3t);
+  if constexpr (Cfg::Q8) {
+    // the 16 blocks' partial sums of the last tap's columns, fixed xor order
+#pragma unroll
+    for (int g = 0; g < C / 4; ++g)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int o = 4; o < 64; o <<= 1) acc8[g][i] += __shfl_xor(acc8[g][i], o, 64);
+  }
   __syncthreads();
   for (int ww = 0; ww < NW; ++ww) {
     if (w == ww) {
@@ -913,6 +938,14 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
       if (lane == 0) {
         red[off_b3] += db3s;
         red[off_b3 + 1] += db3t;
+      }
+      if constexpr (Cfg::Q8) {
+        if (lane < 2) {
+#pragma unroll
+          for (int g = 0; g < C / 4; ++g)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[off_W3 + (lane * C + 4 * g + i) * T + (T - 1)] += acc8[g][i];
+        }
       }
     }
     __syncthreads();
