@@ -219,7 +219,10 @@ template <int KQ, int STRIDE = 64, class Gather>
 __device__ __forceinline__ f32x4 quad_conv(const u32x4* fq, const f32x4& init, Gather&& gather) {
   static_assert(KQ % 2 == 0, "chunks come in pairs");
   f32x4 a0 = init, a1{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 3
+  // fully unrolled where K is short (2D: 36 chunks), so every table read and gather
+  // can be issued ahead of its MFMAs; the 3D shapes (108 chunks) have no registers
+  // for that
+#pragma unroll(KQ <= 36 ? KQ / 2 : 3)
   for (int q = 0; q < KQ; q += 2) {
     const u32x4 w0 = fq[q * STRIDE], w1 = fq[(q + 1) * STRIDE];
     const u32x4 b0 = gather(q), b1 = gather(q + 1);
