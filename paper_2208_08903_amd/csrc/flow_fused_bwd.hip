@@ -149,9 +149,11 @@ struct BwdCfg {
   // compile-time trip count lets the weight-gradient loops unroll)
   static constexpr bool KEXACT = NKC % NW == 0;
   static constexpr int KPW = NKC / NW;
-  // unroll of the dW3 and dW1 chunk loops: 4 for the 2D L=32 C=16 shape
-  // (measured about 1 % faster), 1 elsewhere (more registers, spills in 3D)
-  static constexpr int DWU = DIM == 2 && L == 32 && C == 16 ? 4 : 1;
+  // unroll of the dW3 and dW1 chunk loops, 2D L=32 C=16 only (measured about
+  // 1 % faster; elsewhere unrolling costs registers, spills in 3D): dW1 by 4,
+  // dW3 by 4 in BF16 and not in FP32, where it would spill
+  static constexpr bool DWX = DIM == 2 && L == 32 && C == 16;
+  static constexpr int DWU3 = DWX && BF16 ? 4 : 1, DWU1 = DWX ? 4 : 1;
   // Weight-gradient output tiles; every wave accumulates all of them over its
   // contiguous range of K chunks, and the waves are summed in a fixed order.
   // FP32 2D: dW3's last tap (columns 16 and 17 of 18) on the 4x4 blocks (Q8), so its
@@ -579,7 +581,7 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
     // other BF16 layouts keep them apart and run dW3 after conv3^T, next to g_a2's
     // halo fill.
     auto dw3 = [&]() {
-#pragma unroll(Cfg::DWU)
+#pragma unroll(Cfg::DWU3)
       for (int kc = kc0, kk_ = 0; kk_ < (Cfg::KEXACT ? Cfg::KPW : kc1 - kc0); ++kk_, ++kc) {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -785,7 +787,7 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
     // tiles (mt, nt): rows c = mt*16 + i, columns tap = nt*16 + m
     {
       const uint16_t* h0c = reinterpret_cast<const uint16_t*>(smem + M::OFF_H0C);
-#pragma unroll(Cfg::DWU)
+#pragma unroll(Cfg::DWU1)
       for (int kc = kc0, kk_ = 0; kk_ < (Cfg::KEXACT ? Cfg::KPW : kc1 - kc0); ++kk_, ++kc) {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
