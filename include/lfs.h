@@ -252,6 +252,43 @@ int32_t lfs_flow_backward_vec(const lfs_flow_desc* desc, const float* params, in
                               const float* saved_x, const float* g_phi, const double* g_logq,
                               float* g_params, float* g_z, void* ws, size_t ws_bytes, void* stream);
 
+/* Training pair that keeps each layer's second hidden activation instead of
+ * recomputing it in the backward (the coupling networks of paper Sec. 1: the
+ * backward needs h2 = LeakyReLU(W2 * h1 + b2) at every site of every layer).
+ * Saving costs device memory and write bandwidth in the forward; recomputing
+ * costs the second hidden convolution again in the backward.
+ *
+ * lfs_saved_h_bytes: bytes of the saved activations at batch size B, written
+ * to *bytes: N B C V x 4 for the shapes whose fused backward reads them (2D
+ * L = 32, hidden 16, plain FP32), 0 for every other flow (its backward
+ * recomputes; saved_h below is then ignored and may be NULL).
+ * Errors: EINVAL (desc, B < 0, bytes NULL). */
+int32_t lfs_saved_h_bytes(const lfs_flow_desc* desc, int32_t B, size_t* bytes);
+
+/* lfs_flow_forward that also writes saved_h (device, lfs_saved_h_bytes bytes,
+ * a layout private to the library, read only by lfs_flow_backward_saved with
+ * the same desc, params and B).  saved_x is required.  Every output is
+ * bitwise what lfs_flow_forward writes.
+ * Errors: as lfs_flow_forward; EINVAL also for saved_x NULL (B > 0), or
+ * saved_h NULL where lfs_saved_h_bytes is not 0. */
+int32_t lfs_flow_forward_train(const lfs_flow_desc* desc, const float* params, int32_t B,
+                               const float* z, float* phi, double* logq, double* logdet,
+                               float* saved_x, float* saved_h, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* lfs_flow_backward reading the activations lfs_flow_forward_train saved
+ * instead of recomputing them.  g_logq_vec: [B] FP64 device cotangents of
+ * log q, or NULL to use g_logq for every sample.  The results equal those of
+ * lfs_flow_backward / lfs_flow_backward_vec up to the rounding of the second
+ * hidden convolution (the forward's and the backward's tilings may sum in a
+ * different order).  Workspace: lfs_workspace_bytes(desc, B, 1).
+ * Errors: as lfs_flow_backward; EINVAL also for saved_h NULL where
+ * lfs_saved_h_bytes is not 0. */
+int32_t lfs_flow_backward_saved(const lfs_flow_desc* desc, const float* params, int32_t B,
+                                const float* saved_x, const float* saved_h, const float* g_phi,
+                                double g_logq, const double* g_logq_vec, float* g_params,
+                                float* g_z, void* ws, size_t ws_bytes, void* stream);
+
 /* lfs_flow_forward for flows with batch norm (the example parameter file's
  * use_bn, otherwise undefined by the paper).  Each hidden convolution's output
  * a is normalised per channel, over the batch and all sites, before its

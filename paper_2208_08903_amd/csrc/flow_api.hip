@@ -156,7 +156,7 @@ extern "C" int32_t lfs_flow_forward(const lfs_flow_desc* desc, const float* para
   hipStream_t st = (hipStream_t)stream;
   switch (lfs::family(g, 0)) {
     case lfs::Family::Fused:
-      return lfs::fused_forward(g, params, B, z, phi, logq, logdet, saved_x, (char*)ws, st);
+      return lfs::fused_forward(g, params, B, z, phi, logq, logdet, saved_x, nullptr, (char*)ws, st);
     case lfs::Family::Generic:
       return lfs::generic_forward(g, params, B, z, phi, logq, logdet, saved_x, (char*)ws, st);
     default:
@@ -172,7 +172,7 @@ namespace {
 int32_t backward_plain(const lfs_flow_desc* desc, const FlowGeom& g, const float* params, int32_t B,
                        const float* saved_x, const float* g_phi, double g_logq,
                        const double* g_logq_vec, float* g_params, float* g_z, void* ws,
-                       size_t ws_bytes, void* stream) {
+                       size_t ws_bytes, void* stream, const float* saved_h = nullptr) {
   if (B <= 0 || !params || !saved_x || !g_phi || !g_params || g.bn) return LFS_EINVAL;
   if (desc->algo == LFS_ALGO_FUSED && !fused_ok(g, 1)) return LFS_EUNSUPPORTED;
   const size_t need = ws_bytes_of(g, B, 1);
@@ -180,8 +180,8 @@ int32_t backward_plain(const lfs_flow_desc* desc, const FlowGeom& g, const float
   hipStream_t st = (hipStream_t)stream;
   switch (family(g, 1)) {
     case Family::Fused:
-      return fused_backward(g, params, B, saved_x, g_phi, g_logq, g_logq_vec, g_params, g_z,
-                            (char*)ws, st);
+      return fused_backward(g, params, B, saved_x, saved_h, g_phi, g_logq, g_logq_vec, g_params,
+                            g_z, (char*)ws, st);
     case Family::Generic:
       return generic_backward(g, params, B, saved_x, g_phi, g_logq, g_logq_vec, g_params, g_z,
                               (char*)ws, st);
@@ -215,6 +215,59 @@ extern "C" int32_t lfs_flow_backward_vec(const lfs_flow_desc* desc, const float*
   if (!g_logq) return LFS_EINVAL;
   return lfs::backward_plain(desc, g, params, B, saved_x, g_phi, 0.0, g_logq, g_params, g_z, ws,
                              ws_bytes, stream);
+}
+
+namespace lfs {
+namespace {
+// bytes of the saved h2 of a validated flow at batch B (0: its backward recomputes)
+size_t saved_h_bytes_of(const FlowGeom& g, int B) {
+  if (B <= 0 || family(g, 0) != Family::Fused || family(g, 1) != Family::Fused) return 0;
+  return fused_hsave_bytes(g, B);
+}
+}  // namespace
+}  // namespace lfs
+
+extern "C" int32_t lfs_saved_h_bytes(const lfs_flow_desc* desc, int32_t B, size_t* bytes) {
+  lfs::FlowGeom g;
+  const int32_t s = lfs::make_geom(desc, &g);
+  if (s != LFS_OK) return s;
+  if (B < 0 || !bytes) return LFS_EINVAL;
+  *bytes = g.bn ? 0 : lfs::saved_h_bytes_of(g, B);
+  return LFS_OK;
+}
+
+extern "C" int32_t lfs_flow_forward_train(const lfs_flow_desc* desc, const float* params, int32_t B,
+                                          const float* z, float* phi, double* logq, double* logdet,
+                                          float* saved_x, float* saved_h, void* ws, size_t ws_bytes,
+                                          void* stream) {
+  lfs::FlowGeom g;
+  const int32_t s = lfs::make_geom(desc, &g);
+  if (s != LFS_OK) return s;
+  if (B < 0 || g.bn) return LFS_EINVAL;
+  if (B > 0 && !saved_x) return LFS_EINVAL;
+  const size_t hb = lfs::saved_h_bytes_of(g, B);
+  if (hb == 0) return lfs_flow_forward(desc, params, B, z, phi, logq, logdet, saved_x, ws, ws_bytes, stream);
+  if (desc->algo == LFS_ALGO_FUSED && !lfs::fused_ok(g, 0)) return LFS_EUNSUPPORTED;
+  if (!params || !z || !phi || !logq || !saved_h) return LFS_EINVAL;
+  const size_t need = lfs::ws_bytes_of(g, B, 0);
+  if (need > 0 && (!ws || ws_bytes < need)) return LFS_EWORKSPACE;
+  return lfs::fused_forward(g, params, B, z, phi, logq, logdet, saved_x, saved_h, (char*)ws,
+                            (hipStream_t)stream);
+}
+
+extern "C" int32_t lfs_flow_backward_saved(const lfs_flow_desc* desc, const float* params, int32_t B,
+                                           const float* saved_x, const float* saved_h,
+                                           const float* g_phi, double g_logq, const double* g_logq_vec,
+                                           float* g_params, float* g_z, void* ws, size_t ws_bytes,
+                                           void* stream) {
+  lfs::FlowGeom g;
+  const int32_t s = lfs::make_geom(desc, &g);
+  if (s != LFS_OK) return s;
+  if (g.bn) return LFS_EINVAL;
+  const size_t hb = lfs::saved_h_bytes_of(g, B);
+  if (hb > 0 && !saved_h) return LFS_EINVAL;
+  return lfs::backward_plain(desc, g, params, B, saved_x, g_phi, g_logq, g_logq_vec, g_params, g_z, ws,
+                             ws_bytes, stream, hb > 0 ? saved_h : nullptr);
 }
 
 extern "C" int32_t lfs_flow_forward_bn(const lfs_flow_desc* desc, const float* params, int32_t B,

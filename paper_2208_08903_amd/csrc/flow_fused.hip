@@ -26,12 +26,13 @@ __global__ void __launch_bounds__(NT) kf_forward(
     const u32x4* __restrict__ frags, const float* __restrict__ params, int P_layer, int off_b1,
     int off_b2, int off_b3, int N, int parity0, int final_tanh, int B, const float* __restrict__ z,
     float* __restrict__ phi, float* __restrict__ saved, double* __restrict__ logq,
-    double* __restrict__ logdet) {
+    double* __restrict__ logdet, float* __restrict__ hsave) {
   using Cfg = FwdCfg<DIM, L, C, BF16>;
   using G = Geo<DIM, L>;
   using LY = typename Cfg::LY;
   using HT = HElem<BF16>;
   using R = std::conditional_t<BF16, double, float>;
+  using HS = HSave<DIM, L, C, BF16>;
   constexpr int V = Cfg::V, VS = LY::VS;
   constexpr LayerFrags LF = Cfg::LF;
   constexpr int NW = NT / 64;
@@ -150,6 +151,19 @@ __global__ void __launch_bounds__(NT) kf_forward(
             [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
               for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16, false>(h2, tile, m, ct, j, acc[ct]);
+              if constexpr (HS::ok) {
+                // training: h2 saved for the backward (the same values as in LDS)
+                if (hsave) {
+                  float* hb = hsave + ((size_t)layer * B + b) * (HS::sample_bytes / 4);
+#pragma unroll
+                  for (int ct = 0; ct < LF.nct; ++ct) {
+                    const int co0 = ct * 16 + 4 * j;
+                    if (co0 < C)
+                      *reinterpret_cast<f32x4*>(hb + HS::off4(tile * 16 + m, co0)) =
+                          f32x4{leaky(acc[ct][0]), leaky(acc[ct][1]), leaky(acc[ct][2]), leaky(acc[ct][3])};
+                  }
+                }
+              }
             });
       }
       __syncthreads();
@@ -257,7 +271,8 @@ __global__ void __launch_bounds__(NT) kf_forward(
 
 template <int DIM, int L, int C, bool BF16>
 int32_t launch_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
-                       double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
+                       double* logq, double* logdet, float* saved, float* hsave, char* ws,
+                       hipStream_t st) {
   using Cfg = FwdCfg<DIM, L, C, BF16>;
   static_assert(Cfg::lds_bytes + 16 * 8 <= 160 * 1024, "LDS budget");
   constexpr LayerFrags LF = Cfg::LF;
@@ -278,24 +293,27 @@ int32_t launch_forward(const FlowGeom& g, const float* params, int B, const floa
   if (!set_lds_limit<kern>(Cfg::lds_bytes)) return LFS_EDEVICE;
   hipLaunchKernelGGL(kern, dim3(B), dim3(Cfg::NT), Cfg::lds_bytes, st, frags, params,
                      (int)g.P_layer, (int)g.off_b1, (int)g.off_b2, (int)g.off_b3, g.N, g.parity0,
-                     g.final_tanh, B, z, phi, saved, logq, logdet);
+                     g.final_tanh, B, z, phi, saved, logq, logdet,
+                     HSave<DIM, L, C, BF16>::ok ? hsave : nullptr);
   return launch_status();
 }
 
 using FwdFn = int32_t (*)(const FlowGeom&, const float*, int, const float*, float*, double*,
-                          double*, float*, char*, hipStream_t);
+                          double*, float*, float*, char*, hipStream_t);
 
 struct FwdEntry {
   int dim, L, C;
   bool bf16;
   FwdFn fn;
   size_t frag_bytes_per_layer;
+  size_t hsave_bytes_per_sample;  // 0: the backward recomputes h2
 };
 
 template <int DIM, int L, int C, bool BF16>
 constexpr FwdEntry fwd_entry() {
+  using HS = HSave<DIM, L, C, BF16>;
   return FwdEntry{DIM, L, C, BF16, &launch_forward<DIM, L, C, BF16>,
-                  (size_t)FwdCfg<DIM, L, C, BF16>::LF.total * 64 * 16};
+                  (size_t)FwdCfg<DIM, L, C, BF16>::LF.total * 64 * 16, HS::ok ? HS::sample_bytes : 0};
 }
 
 // Shapes with a fused forward: the whole sample (field + two hidden tensors)
@@ -333,18 +351,25 @@ size_t fused_ws_bytes(const FlowGeom& g, int B, int for_backward) {
 }
 
 int32_t fused_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
-                      double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
+                      double* logq, double* logdet, float* saved, float* hsave, char* ws,
+                      hipStream_t st) {
   const fused::FwdEntry* e = fused::find_fwd(g);
   if (!e) return fused::ring_forward(g, params, B, z, phi, logq, logdet, saved, ws, st);
-  return e->fn(g, params, B, z, phi, logq, logdet, saved, ws, st);
+  return e->fn(g, params, B, z, phi, logq, logdet, saved, hsave, ws, st);
+}
+
+size_t fused_hsave_bytes(const FlowGeom& g, int B) {
+  const fused::FwdEntry* e = fused::find_fwd(g);
+  if (!e || !e->hsave_bytes_per_sample || !fused::bwd_supported(g)) return 0;
+  return e->hsave_bytes_per_sample * (size_t)B * g.N;
 }
 
 int32_t fused_backward(const FlowGeom& g, const float* params, int B, const float* saved,
-                       const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
-                       float* g_z, char* ws,
+                       const float* hsave, const float* g_phi, double g_logq,
+                       const double* g_logq_vec, float* g_params, float* g_z, char* ws,
                        hipStream_t st) {
   if (fused::bwd_supported(g))
-    return fused::bwd_run(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
+    return fused::bwd_run(g, params, B, saved, hsave, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
   return fused::ring_bwd_run(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
 }
 

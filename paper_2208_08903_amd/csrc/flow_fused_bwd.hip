@@ -247,16 +247,39 @@ __device__ __forceinline__ u32x4 load8_e(const uint16_t* rp, int x0) {
   }
 }
 
+// ---- saved h2 ----------------------------------------------------------------
+// Asynchronous copy of one sample's saved h2 (HSave image at src) into the LDS
+// slot dst, segment s at dst + s * seg_stride bytes: wave w copies chunks w,
+// w + NW, ..., every lane 16 bytes (global_load_lds_dwordx4: lane i's bytes land
+// at the chunk's LDS address + 16 i).  No registers hold the data; the copy
+// counts as outstanding vector-memory loads until s_waitcnt vmcnt(0), after
+// which a barrier publishes it to the workgroup.
+template <class HS, int NW>
+__device__ __forceinline__ void load_h2_async(const unsigned char* src, unsigned char* dst, int seg_stride,
+                                              int w, int lane) {
+  typedef __attribute__((address_space(1))) void* gptr;
+  typedef __attribute__((address_space(3))) void* lptr;
+  constexpr int CPS = HS::SEG_BYTES / 1024;
+#pragma unroll
+  for (int k = w; k < HS::CHUNKS; k += NW) {
+    const int sg = k / CPS, o = (k - sg * CPS) * 1024;
+    __builtin_amdgcn_global_load_lds((gptr)(src + (size_t)k * 1024 + lane * 16), (lptr)(dst + sg * seg_stride + o),
+                                     16, 0, 0);
+  }
+}
+
 // ---- the kernel -------------------------------------------------------------
 
-template <int DIM, int L, int C, bool BF16, int NT>
+// HS: h2 is read from the training forward's saved copy (hsv, this layer's
+// [B] HSave images) instead of being recomputed.
+template <int DIM, int L, int C, bool BF16, int NT, bool HS = false>
 __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backward(
     const u32x4* frags, const float* __restrict__ pl, int off_b1, int off_b2,
     int off_b3, int off_W1, int off_W2, int off_W3, int fpar, int final_tanh, float g_ld,
     const double* __restrict__ g_ld_vec, int B,
     const float* __restrict__ xin, const float* __restrict__ gy, float* __restrict__ gx,
     float* __restrict__ partial, const float* __restrict__ prev_partial, float* __restrict__ prev_out,
-    int n_parts) {
+    int n_parts, const unsigned char* __restrict__ hsv) {
   using Cfg = BwdCfg<DIM, L, C, BF16>;
   using G = Geo<DIM, L>;
   using HT = HElem<BF16>;
@@ -305,6 +328,19 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
   // site-major activations: h1 in S0, h2 in S1
   HT* h1s = reinterpret_cast<HT*>(smem + M::OFF_S0);
   HT* h2s = reinterpret_cast<HT*>(smem + M::OFF_S1);
+  // HS: sample bb's saved h2 copied into S1 while the previous sample's tail
+  // passes (dW1, conv1^T), the staging and conv1 run; S1 is free from the end of
+  // conv2^T until conv1's barrier (conv1 gathers its operands from the field)
+  using HSv = HSave<DIM, L, C, BF16>;
+  static_assert(!HS || (HSv::ok && !LY::padded && LY::quad_major == !BF16), "saved h2 image = LDS slot");
+  auto load_h2 = [&](int bb) {
+    if constexpr (HS) {
+      if (bb < B)
+        load_h2_async<HSv, NW>(hsv + (size_t)bb * HSv::sample_bytes, smem + M::OFF_S1,
+                               LY::quad_major ? LY::QSZ * 4 : 0, w, lane);
+    }
+  };
+  load_h2(blockIdx.x);
 
   constexpr int NTL3 = Cfg::NTL3, NTL1 = Cfg::NTL1;
   f32x4 acc3[Cfg::I3], acc2[Cfg::I2], acc1[Cfg::I1];
@@ -395,9 +431,12 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
         h0c[n] = (uint16_t)bf16_bits(G::parity(n) == fpar ? xs[LY::idx(n)] : 0.f);
     };
     if constexpr (BF16 && !Cfg::SPLIT) build_h0c();
-    // conv1 operands (row triples of the masked field) in the (not yet written) h2 slot
-    build_tri<LY, BF16, NT>(h2s, xs, fpar);
-    __syncthreads();
+    // conv1 operands (row triples of the masked field) in the (not yet written) h2
+    // slot; HS: gathered from the field by every tile
+    if constexpr (!HS) {
+      build_tri<LY, BF16, NT>(h2s, xs, fpar);
+      __syncthreads();
+    }
     // ---- recompute conv1 -> h1 ----
     {
       u32x4 A[LF.nct][LF.k1];
@@ -411,20 +450,27 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
       mma_tiles<Cfg::TU, LF.nct, LF.k1, BF16, k_tri(T), true>(
           V / 16, w, NW, A, bias1,
           [&](int tile, int c) {
-            return gather_tri<LY, BF16>(h2s, tile * 16 + m, tile_p<LY>(tile, m), c, j);
+            if constexpr (HS) {
+              const int n = tile * 16 + m;
+              return gather_tri_x<LY, BF16>(xs, n, LY::idx(n), G::parity(n), fpar, c, j);
+            } else {
+              return gather_tri<LY, BF16>(h2s, tile * 16 + m, tile_p<LY>(tile, m), c, j);
+            }
           },
           [&](int tile, const f32x4(&acc)[LF.nct]) {
 #pragma unroll
             for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16, false>(h1s, tile, m, ct, j, acc[ct]);
           });
     }
+    // HS: the saved h2 has landed in S1 (the barrier publishes it)
+    if constexpr (HS) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if constexpr (LY::padded) {
       fill_halo<LY, C, BF16, NT>(h1s);
       __syncthreads();
     }
-    // ---- recompute conv2 -> h2 ----
-    {
+    // ---- recompute conv2 -> h2 (HS: saved) ----
+    if constexpr (!HS) {
       u32x4 A[LF.nct][LF.k2];
       f32x4 bias2[LF.nct];
 #pragma unroll
@@ -442,8 +488,8 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
 #pragma unroll
             for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16, false>(h2s, tile, m, ct, j, acc[ct]);
           });
+      __syncthreads();
     }
-    __syncthreads();
     fill_halo<LY, C, BF16, NT>(h2s);
     // ---- recompute conv3 at active sites; affine backward -> g_o, g_x(active) ----
     // g_o is zero at the frozen sites.
@@ -780,6 +826,7 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
           });
     }
     __syncthreads();
+    load_h2(b + gridDim.x);  // S1 (g_a2) is dead from here on
     // g_a1's halo (for conv1^T's gathers) is filled alongside dW1, which reads
     // interior sites only
     fill_halo<LY, C, BF16, NT>(ga1s);
@@ -987,8 +1034,8 @@ size_t bwd_ws(const FlowGeom& g, int B) {
 
 template <int DIM, int L, int C, bool BF16>
 int32_t launch_backward(const FlowGeom& g, const float* params, int B, const float* saved,
-                        const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
-                        float* g_z, char* ws,
+                        const float* hsave, const float* g_phi, double g_logq,
+                        const double* g_logq_vec, float* g_params, float* g_z, char* ws,
                         hipStream_t st) {
   using Cfg = BwdCfg<DIM, L, C, BF16>;
   const int grid = bwd_grid<DIM, L, C, BF16>(B);
@@ -1006,7 +1053,11 @@ int32_t launch_backward(const FlowGeom& g, const float* params, int B, const flo
   const long nthreads = (long)tab.total * 64 * g.N;
   hipLaunchKernelGGL((kf_prep<BF16>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st,
                      params, g.N, g.T, (int)g.P_layer, tab, frags);
-  auto kern = kf_backward<DIM, L, C, BF16, Cfg::NT>;
+  using HSv = HSave<DIM, L, C, BF16>;
+  if (!HSv::ok) hsave = nullptr;
+  auto kern = kf_backward<DIM, L, C, BF16, Cfg::NT, false>;
+  if constexpr (HSv::ok)
+    if (hsave) kern = kf_backward<DIM, L, C, BF16, Cfg::NT, true>;
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::lds_bytes) !=
       hipSuccess)
@@ -1023,7 +1074,9 @@ int32_t launch_backward(const FlowGeom& g, const float* params, int B, const flo
                        (int)g.off_W3, g.frozen_parity(l), g.final_tanh, (float)(-g_logq), g_logq_vec, B,
                        saved + (size_t)l * BV, gy, gx, partial[l & 1],
                        first ? nullptr : (const float*)partial[(l + 1) & 1],
-                       first ? nullptr : g_params + (size_t)(l + 1) * g.P_layer, grid);
+                       first ? nullptr : g_params + (size_t)(l + 1) * g.P_layer, grid,
+                       hsave ? reinterpret_cast<const unsigned char*>(hsave) + (size_t)l * B * HSv::sample_bytes
+                             : nullptr);
     gy = gx;
     which ^= 1;
   }
@@ -1036,8 +1089,8 @@ int32_t launch_backward(const FlowGeom& g, const float* params, int B, const flo
   return launch_status();
 }
 
-using BwdFn = int32_t (*)(const FlowGeom&, const float*, int, const float*, const float*, double,
-                          const double*, float*, float*, char*, hipStream_t);
+using BwdFn = int32_t (*)(const FlowGeom&, const float*, int, const float*, const float*,
+                          const float*, double, const double*, float*, float*, char*, hipStream_t);
 using BwdWsFn = size_t (*)(const FlowGeom&, int);
 
 struct BwdEntry {
@@ -1077,12 +1130,11 @@ size_t bwd_ws_bytes(const FlowGeom& g, int B) {
   return e ? e->ws(g, B) : 0;
 }
 int32_t bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
-                const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params, float* g_z,
-                char* ws,
-                hipStream_t st) {
+                const float* hsave, const float* g_phi, double g_logq, const double* g_logq_vec,
+                float* g_params, float* g_z, char* ws, hipStream_t st) {
   const BwdEntry* e = find_bwd(g);
   if (!e) return LFS_EUNSUPPORTED;
-  return e->fn(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
+  return e->fn(g, params, B, saved, hsave, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
 }
 
 }  // namespace fused

@@ -70,11 +70,16 @@ int32_t net_backward_bn(const FlowGeom& g, const float* params, int B, const flo
 // Fused kernels: LDS-resident per-sample lattices, matrix-core convolutions.
 bool fused_supported(const FlowGeom& g, int for_backward);
 size_t fused_ws_bytes(const FlowGeom& g, int B, int for_backward);
+// hsave (nullable): the training forward's saved h2 of every layer, in the
+// shape's HSave image ([N][B] samples); fused_hsave_bytes gives its size (0:
+// the shape's backward recomputes h2, and hsave is ignored)
 int32_t fused_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
-                      double* logq, double* logdet, float* saved, char* ws, hipStream_t st);
+                      double* logq, double* logdet, float* saved, float* hsave, char* ws,
+                      hipStream_t st);
+size_t fused_hsave_bytes(const FlowGeom& g, int B);
 int32_t fused_backward(const FlowGeom& g, const float* params, int B, const float* saved,
-                       const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
-                       float* g_z, char* ws,
+                       const float* hsave, const float* g_phi, double g_logq,
+                       const double* g_logq_vec, float* g_params, float* g_z, char* ws,
                        hipStream_t st);
 
 namespace fused {
@@ -88,9 +93,8 @@ int32_t ring_forward(const FlowGeom& g, const float* params, int B, const float*
 bool bwd_supported(const FlowGeom& g);
 size_t bwd_ws_bytes(const FlowGeom& g, int B);
 int32_t bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
-                const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params, float* g_z,
-                char* ws,
-                hipStream_t st);
+                const float* hsave, const float* g_phi, double g_logq, const double* g_logq_vec,
+                float* g_params, float* g_z, char* ws, hipStream_t st);
 // Fused backward streaming planes (3D lattices too large to keep resident;
 // three launches per layer), implemented next to its kernels.
 bool ring_bwd_supported(const FlowGeom& g);

@@ -5,8 +5,9 @@ one of the library's entry points (see ``lfs``):
 
   train step (paper Sec. 1, reverse-KL training; example parameter file:
   Adam, lr 1e-3, fresh prior batch per iteration)
-      prior_normal -> flow_forward (saving layer inputs) -> action (+force/B)
-      -> log_weights (loss) -> flow_backward -> adam_step
+      prior_normal -> flow_forward (saving layer inputs; flow_forward_train also
+      the second hidden activations) -> action (+force/B) -> log_weights (loss)
+      -> flow_backward (flow_backward_saved) -> adam_step
 
   sampling (paper Sec. 1, flow proposals + Metropolis-Hastings test)
       prior_normal -> flow_forward -> action -> log_weights -> mh_chain
@@ -121,10 +122,15 @@ class Trainer:
     draw and the Adam step, whose counters change each step) as one captured HIP
     graph.  The first step runs them eagerly and captures them; buffers are fixed,
     so later steps replay the same launches on fresh prior draws.  For small
-    shapes, where a step is launch-bound."""
+    shapes, where a step is launch-bound.
+
+    save_h: the forward keeps every layer's second hidden activation for the
+    backward, which then skips recomputing it (lfs.flow_forward_train and
+    lfs.flow_backward_saved), on the shapes where lfs.saved_h_bytes is not 0;
+    elsewhere, and with save_h=False, the backward recomputes it."""
 
     def __init__(self, flow: Flow, B: int, m2: float, lam: float, lr=1e-3, key=12345,
-                 betas=(0.9, 0.999), eps=1e-8, lr_schedule=None, graph=False):
+                 betas=(0.9, 0.999), eps=1e-8, lr_schedule=None, graph=False, save_h=True):
         self.flow, self.B = flow, B
         dev, V, N = flow.device, flow.V, flow.n_layers
         self.m2 = torch.tensor([m2], dtype=torch.float64, device=dev)
@@ -145,6 +151,8 @@ class Trainer:
         self.v = torch.zeros(flow.P, dtype=f32, device=dev)
         self.ws_f = flow.workspace(B, False)
         self.ws_b = flow.workspace(B, True)
+        hb = lfs.saved_h_bytes(flow.desc, B) if save_h and not flow.batch_norm else 0
+        self.saved_h = torch.empty(hb, dtype=torch.uint8, device=dev) if hb else None
         self.t = 0
         self.graph = graph
         self._graph = None
@@ -155,13 +163,22 @@ class Trainer:
 
     def forward(self):
         f = self.flow
-        f.forward(self.z, self.phi, self.logq, None, self.saved, self.ws_f, train=True)
+        if self.saved_h is not None:
+            lfs.flow_forward_train(f.desc, f.params, self.z, self.phi, self.logq, self.saved,
+                                   self.saved_h, None, self.ws_f)
+        else:
+            f.forward(self.z, self.phi, self.logq, None, self.saved, self.ws_f, train=True)
         lfs.action(f.dim, f.L, self.phi, self.m2, self.lam, self.S, self.gphi, 1.0 / self.B,
                    f.precision)
         lfs.log_weights(self.S, self.logq, self.logw, self.loss)
 
     def backward(self):
-        self.flow.backward(self.saved, self.gphi, 1.0 / self.B, self.gparams, None, self.ws_b)
+        f = self.flow
+        if self.saved_h is not None:
+            lfs.flow_backward_saved(f.desc, f.params, self.saved, self.saved_h, self.gphi, 1.0 / self.B,
+                                    self.gparams, None, self.ws_b)
+        else:
+            f.backward(self.saved, self.gphi, 1.0 / self.B, self.gparams, None, self.ws_b)
 
     def current_lr(self, t=None):
         t = self.t if t is None else t

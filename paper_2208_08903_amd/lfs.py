@@ -68,6 +68,11 @@ _SIGS = {
     "lfs_flow_forward_noalloc": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
                                          c_vp, c_vp]),
     "lfs_bn_stats_count": (c_sz, [ctypes.POINTER(FlowDesc)]),
+    "lfs_saved_h_bytes": (c_i32, [ctypes.POINTER(FlowDesc), c_i32, ctypes.POINTER(c_sz)]),
+    "lfs_flow_forward_train": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
+                                       c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "lfs_flow_backward_saved": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_vp, c_f64,
+                                        c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "lfs_flow_forward_bn": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
                                     c_vp, c_i32, c_vp, c_f64, c_vp, c_sz, c_vp]),
     "lfs_flow_backward_bn": (c_i32, [ctypes.POINTER(FlowDesc), c_vp, c_i32, c_vp, c_vp, c_f64, c_vp,
@@ -271,6 +276,61 @@ def flow_backward(desc, params, saved_x, g_phi, g_logq: float, g_params, g_z=Non
                                     _p(g_params, torch.float32, "g_params"),
                                     _p(g_z, torch.float32, "g_z"), _p(ws, torch.uint8, "ws"),
                                     nbytes, _stream()))
+
+
+def saved_h_bytes(desc: FlowDesc, B: int) -> int:
+    """Bytes of the activations flow_forward_train saves (0: the backward recomputes them)."""
+    out = c_sz(0)
+    _check(load().lfs_saved_h_bytes(ctypes.byref(desc), B, ctypes.byref(out)))
+    return int(out.value)
+
+
+def flow_forward_train(desc, params, z, phi, logq, saved_x, saved_h, logdet=None, ws=None):
+    """flow_forward that also saves the second hidden activation of every layer in saved_h
+    (a uint8 device tensor of saved_h_bytes(desc, B) bytes, or None when that is 0)."""
+    B = _field(z, _sites(desc), "z")
+    if saved_x is None:
+        raise LfsError("flow_forward_train needs saved_x")
+    V, _ = _flow_sizes(desc, params, B, saved_x)
+    _need(phi, B * V, "phi")
+    _need(logq, B, "logq")
+    _need(logdet, B, "logdet")
+    hb = saved_h_bytes(desc, B)
+    if hb and (saved_h is None or saved_h.numel() * saved_h.element_size() < hb):
+        raise LfsError(f"saved_h needs {hb} bytes")
+    nbytes = ws.numel() if ws is not None else 0
+    _check(load().lfs_flow_forward_train(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
+                                         _p(z, torch.float32, "z"), _p(phi, torch.float32, "phi"),
+                                         _p(logq, torch.float64, "logq"),
+                                         _p(logdet, torch.float64, "logdet"),
+                                         _p(saved_x, torch.float32, "saved_x"),
+                                         _p(saved_h if hb else None, None, "saved_h"),
+                                         _p(ws, torch.uint8, "ws"), nbytes, _stream()))
+
+
+def flow_backward_saved(desc, params, saved_x, saved_h, g_phi, g_logq, g_params, g_z=None, ws=None):
+    """flow_backward (g_logq a float) or flow_backward_vec (g_logq a [B] FP64 device tensor)
+    reading the activations flow_forward_train saved."""
+    B = _field(g_phi, _sites(desc), "g_phi")
+    V, P = _flow_sizes(desc, params, B, saved_x)
+    _need(g_params, P, "g_params")
+    _need(g_z, B * V, "g_z")
+    hb = saved_h_bytes(desc, B)
+    if hb and (saved_h is None or saved_h.numel() * saved_h.element_size() < hb):
+        raise LfsError(f"saved_h needs {hb} bytes")
+    vec = g_logq if isinstance(g_logq, torch.Tensor) else None
+    if vec is not None and vec.numel() != B:
+        raise LfsError("g_logq needs one entry per sample")
+    scalar = 0.0 if vec is not None else float(g_logq)
+    nbytes = ws.numel() if ws is not None else 0
+    _check(load().lfs_flow_backward_saved(ctypes.byref(desc), _p(params, torch.float32, "params"), B,
+                                          _p(saved_x, torch.float32, "saved_x"),
+                                          _p(saved_h if hb else None, None, "saved_h"),
+                                          _p(g_phi, torch.float32, "g_phi"), scalar,
+                                          _p(vec, torch.float64, "g_logq"),
+                                          _p(g_params, torch.float32, "g_params"),
+                                          _p(g_z, torch.float32, "g_z"), _p(ws, torch.uint8, "ws"),
+                                          nbytes, _stream()))
 
 
 def flow_forward_bn(desc, params, z, phi, logq, bn_mode, bn_stats=None, momentum=0.1, logdet=None,

@@ -208,6 +208,37 @@ def test_null_and_shape_arguments_rejected_before_any_launch():
     assert lib.lfs_ess(1, 0, 1, 9, 1, None) == -1                            # n < 1
 
 
+def test_saved_h_bytes_and_validation():
+    """The training pair's saved activations: N B C V FP32 values on 2D L = 32, hidden 16,
+    plain FP32; none elsewhere; missing buffers are rejected before any launch."""
+    lib = lfs.load()
+    d = lfs.make_desc(2, 32, 3, 16)
+    assert lfs.saved_h_bytes(d, 5) == 3 * 5 * 16 * 1024 * 4
+    assert lfs.saved_h_bytes(d, 0) == 0
+    for other in (lfs.make_desc(2, 8, 2, 16), lfs.make_desc(2, 32, 2, 8),
+                  lfs.make_desc(2, 32, 2, 16, precision=lfs.LFS_BF16_CONV),
+                  lfs.make_desc(3, 16, 2, 32, precision=lfs.LFS_BF16_CONV),
+                  lfs.make_desc(2, 32, 2, 16, algo=lfs.ALGO_GENERIC)):
+        assert lfs.saved_h_bytes(other, 4) == 0
+    out = ctypes.c_size_t(0)
+    assert lib.lfs_saved_h_bytes(ctypes.byref(d), -1, ctypes.byref(out)) == -1
+    assert lib.lfs_saved_h_bytes(ctypes.byref(d), 4, None) == -1
+    need = lfs.workspace_bytes(d, 4, False)
+    # saved_x NULL, saved_h NULL
+    assert lib.lfs_flow_forward_train(ctypes.byref(d), 1, 4, 1, 1, 1, None, None, 1, 1, need, None) == -1
+    assert lib.lfs_flow_forward_train(ctypes.byref(d), 1, 4, 1, 1, 1, None, 1, None, 1, need, None) == -1
+    assert lib.lfs_flow_forward_train(ctypes.byref(d), None, 0, None, None, None, None, None, None, None,
+                                      0, None) == 0                                    # empty batch
+    need_b = lfs.workspace_bytes(d, 4, True)
+    assert lib.lfs_flow_backward_saved(ctypes.byref(d), 1, 4, 1, None, 1, 0.25, None, 1, None, 1, need_b,
+                                       None) == -1                                     # saved_h NULL
+    assert lib.lfs_flow_backward_saved(ctypes.byref(d), 1, 4, 1, 1, 1, 0.25, None, 1, None, 1, need_b - 1,
+                                       None) == -3                                     # workspace
+    bn = lfs.make_desc(2, 8, 2, 8, batch_norm=True)
+    assert lib.lfs_flow_backward_saved(ctypes.byref(bn), 1, 4, 1, 1, 1, 0.25, None, 1, None, 1, 1 << 40,
+                                       None) == -1                                     # batch norm
+
+
 def test_workspace_too_small_is_reported():
     lib = lfs.load()
     d = lfs.make_desc(2, 8, 4, 8)

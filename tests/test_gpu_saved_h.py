@@ -1,0 +1,157 @@
+"""The training pair that saves the second hidden activation (lfs_flow_forward_train,
+lfs_flow_backward_saved) against the plain pair and the oracle.
+
+The backward of a coupling layer needs h2 = LeakyReLU(W2 h1 + b2) at every site (paper
+Sec. 1, the s/t networks of the coupling layers); the saved pair keeps it from the
+forward instead of recomputing it.  Checked here, on 2D L = 32, hidden 16, plain FP32
+(the shape the pair saves for) at batches that leave some workgroups two samples:
+  - the forward's outputs are bitwise those of lfs_flow_forward;
+  - the saved h2 of every layer and sample equals the oracle's h2 of that layer's
+    saved input field (FP32 bounds of the forward, T = 9 taps of fan-in 16);
+  - the backward equals the recomputing backward (both within the FP32 gradient
+    bounds of the oracle), scalar and per-sample log q cotangents;
+  - on a shape without a saved layout the pair reports 0 bytes and falls back to
+    the plain entry points' results.
+"""
+import numpy as np
+import pytest
+import torch
+
+import seeded_inputs as si
+from oracle import flow as of
+from paper_2208_08903_amd import lfs
+
+from .gpu_util import DEV, dev, flow_buffers, host, rel_norm, run_backward, run_forward
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(B, N=2, L=32, C=16, precision=lfs.LFS_PLAIN_FP32):
+    desc = lfs.make_desc(2, L, N, C, precision=precision, algo=lfs.ALGO_FUSED)
+    params = si.flow_params(2, N, C, seed=140 + L, w_std=0.1, b_std=0.05)
+    z = si.normal_fields(240 + L, B, L * L)
+    fs = of.FlowShape(2, L, N, C)
+    return desc, params, z, fs
+
+
+def _forward_train(desc, params_np, z_np):
+    B = z_np.shape[0]
+    b = flow_buffers(desc, B, True)
+    hb = lfs.saved_h_bytes(desc, B)
+    b["saved_h"] = torch.empty(max(hb, 1), device=DEV, dtype=torch.uint8) if hb else None
+    b["params"], b["z"] = dev(params_np, torch.float32), dev(z_np, torch.float32)
+    lfs.flow_forward_train(desc, b["params"], b["z"], b["phi"], b["logq"], b["saved"], b["saved_h"],
+                           b["logdet"], b["ws"])
+    torch.cuda.synchronize()
+    return b
+
+
+def _backward_saved(desc, fwd, g_phi_np, g_logq):
+    B = g_phi_np.shape[0]
+    ws = torch.empty(max(lfs.workspace_bytes(desc, B, True), 1), device=DEV, dtype=torch.uint8)
+    gp = torch.empty_like(fwd["params"])
+    gz = torch.empty(B, desc.L ** desc.dim, device=DEV, dtype=torch.float32)
+    lfs.flow_backward_saved(desc, fwd["params"], fwd["saved"], fwd["saved_h"], dev(g_phi_np, torch.float32),
+                            g_logq, gp, gz, ws)
+    torch.cuda.synchronize()
+    return host(gp), host(gz)
+
+
+def test_saved_bytes():
+    desc, *_ = _case(4, N=3)
+    assert lfs.saved_h_bytes(desc, 5) == 3 * 5 * 16 * 1024 * 4
+    assert lfs.saved_h_bytes(desc, 0) == 0
+    for other in (lfs.make_desc(2, 8, 2, 16), lfs.make_desc(2, 32, 2, 8),
+                  lfs.make_desc(3, 16, 2, 32, precision=lfs.LFS_BF16_CONV)):
+        assert lfs.saved_h_bytes(other, 4) == 0
+
+
+def test_forward_train_outputs_and_saved_h():
+    """Outputs bitwise those of the plain forward; saved h2 = the oracle's h2 per layer."""
+    B = 300
+    print(f"forward_train 2D L=32 C=16 FP32 B={B}", flush=True)
+    desc, params, z, fs = _case(B)
+    a = run_forward(desc, params, z)
+    t = _forward_train(desc, params, z)
+    for k in ("phi", "logq", "logdet", "saved"):
+        assert torch.equal(a[k], t[k]), k
+    N, C, V = fs.n_layers, fs.hidden, 1024
+    # [N][B][C/4][V][4] -> [N][B][C][V]
+    hs = host(t["saved_h"]).view(np.float32).reshape(N, B, C // 4, V, 4).transpose(0, 1, 2, 4, 3)
+    hs = hs.reshape(N, B, C, V).astype(np.float64)
+    rows = [0, 1, 255, 256, 299]
+    saved = host(t["saved"]).reshape(N + 1, B, V).astype(np.float64)
+    layers = of.unpack(params, fs)
+    for l in range(N):
+        # the oracle's network on the kernel's own layer input (FP32 values, exact in FP64)
+        x = of.as_lattice(saved[l, rows], fs)
+        _, hl, *_ = of.net(x, layers[l], of.frozen_mask(fs, l), fs)
+        h2 = hl[2].reshape(len(rows), C, V)
+        got = hs[l, rows]
+        # FP32 sums of 9 and 144 terms: well inside the forward's 1e-5 (1 + |phi|)
+        err = np.max(np.abs(got - h2) / (1 + np.abs(h2)))
+        print(f"  layer {l}: saved h2 vs oracle {err:.2e}", flush=True)
+        assert err <= 1e-5, (l, err)
+
+
+@pytest.mark.parametrize("B", [300, 4])
+def test_backward_saved_matches_recompute_and_oracle(B):
+    """B = 300: the grid of 256 gives 44 workgroups a second sample, whose saved h2 is
+    copied in while the first one's tail passes run."""
+    print(f"backward_saved 2D L=32 C=16 FP32 B={B}", flush=True)
+    desc, params, z, fs = _case(B)
+    rng = np.random.default_rng(310)
+    g_phi = rng.standard_normal(z.shape).astype(np.float32)
+    t = _forward_train(desc, params, z)
+    gs, gzs = _backward_saved(desc, t, g_phi, 0.37)
+    gr, gzr = run_backward(desc, t, g_phi, 0.37)
+    d = np.max(np.abs(gs - gr)) / np.max(np.abs(gr))
+    dz = np.max(np.abs(gzs - gzr)) / np.max(np.abs(gzr))
+    print(f"  saved vs recomputed: params {d:.2e}, g_z {dz:.2e}", flush=True)
+    assert rel_norm(gs, gr) <= 1e-6 and d <= 1e-6
+    assert rel_norm(gzs, gzr) <= 1e-6 and dz <= 1e-6
+    if B <= 8:
+        gpo, gzo = of.flow_vjp(params, z, fs, g_phi.astype(np.float64), 0.37)
+        for lay_g, lay_o in zip(of.unpack(gs, fs), of.unpack(gpo, fs)):
+            for a, b in zip(lay_g, lay_o):
+                assert rel_norm(a, b) <= 1e-4, (rel_norm(a, b), a.shape)
+                assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(b)), a.shape
+        assert rel_norm(gzs, gzo) <= 1e-4
+        assert np.max(np.abs(gzs - gzo)) <= 1e-5 * np.max(np.abs(gzo))
+
+
+def test_backward_saved_vector_cotangent_and_determinism():
+    B = 260
+    desc, params, z, fs = _case(B)
+    g_phi = np.random.default_rng(311).standard_normal(z.shape).astype(np.float32)
+    t = _forward_train(desc, params, z)
+    g1, gz1 = _backward_saved(desc, t, g_phi, 0.25)
+    g2, gz2 = _backward_saved(desc, t, g_phi, 0.25)
+    np.testing.assert_array_equal(g1, g2)
+    np.testing.assert_array_equal(gz1, gz2)
+    ws = torch.empty(lfs.workspace_bytes(desc, B, True), device=DEV, dtype=torch.uint8)
+    gp = torch.empty_like(t["params"])
+    gz = torch.empty(B, 1024, device=DEV, dtype=torch.float32)
+    vec = torch.full((B,), 0.25, device=DEV, dtype=torch.float64)
+    lfs.flow_backward_saved(desc, t["params"], t["saved"], t["saved_h"], dev(g_phi, torch.float32), vec,
+                            gp, gz, ws)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(gp), g1)
+    np.testing.assert_array_equal(host(gz), gz1)
+
+
+def test_shapes_without_saved_layout_fall_back():
+    """2D L = 8 (padded backward layout) and BF16: 0 saved bytes, the plain results."""
+    for L, prec in ((8, lfs.LFS_PLAIN_FP32), (32, lfs.LFS_BF16_CONV)):
+        desc, params, z, fs = _case(6, L=L, precision=prec)
+        assert lfs.saved_h_bytes(desc, 6) == 0
+        g_phi = np.random.default_rng(312).standard_normal(z.shape).astype(np.float32)
+        a = run_forward(desc, params, z)
+        t = _forward_train(desc, params, z)
+        assert t["saved_h"] is None
+        for k in ("phi", "logq", "saved"):
+            assert torch.equal(a[k], t[k]), k
+        gs, gzs = _backward_saved(desc, t, g_phi, 0.3)
+        gr, gzr = run_backward(desc, a, g_phi, 0.3)
+        np.testing.assert_array_equal(gs, gr)
+        np.testing.assert_array_equal(gzs, gzr)
