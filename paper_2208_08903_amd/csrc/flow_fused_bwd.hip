@@ -332,12 +332,10 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
   // passes (dW1, conv1^T), the staging and conv1 run; S1 is free from the end of
   // conv2^T until conv1's barrier (conv1 gathers its operands from the field)
   using HSv = HSave<DIM, L, C, BF16>;
-  static_assert(!HS || (HSv::ok && !LY::padded && LY::quad_major == !BF16), "saved h2 image = LDS slot");
+  static_assert(!HS || (HSv::ok && !LY::padded && LY::quad_major), "saved h2 image = LDS slot");
   auto load_h2 = [&](int bb) {
     if constexpr (HS) {
-      if (bb < B)
-        load_h2_async<HSv, NW>(hsv + (size_t)bb * HSv::sample_bytes, smem + M::OFF_S1,
-                               LY::quad_major ? LY::QSZ * 4 : 0, w, lane);
+      if (bb < B) load_h2_async<HSv, NW>(hsv + (size_t)bb * HSv::sample_bytes, smem + M::OFF_S1, LY::QSZ * 4, w, lane);
     }
   };
   load_h2(blockIdx.x);

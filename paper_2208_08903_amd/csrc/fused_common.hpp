@@ -314,23 +314,24 @@ __device__ __forceinline__ int tile_p(int tile, int m) {
 
 // The second hidden activation h2 = leaky(W2 * h1 + b2) of every site, saved by
 // the training forward so that the backward reads it instead of recomputing
-// conv2 (shapes whose backward holds h2 unpadded).  A sample's entry is the
-// image of the backward's h2 slot restricted to the lattice sites: SEGS
-// contiguous segments of SEG_BYTES each, which the backward copies into LDS as
-// 1 KB chunks (64 lanes x 16 bytes).  FP32 (quad-major): segment q holds
-// channels 4q .. 4q + 3 of site n at 4 n; BF16 (site-major): one segment, the
-// C channels of site n at C n.
+// conv2: FP32 2D L = 32, C = 16, whose backward holds h2 unpadded and
+// quad-major.  A sample's entry is the image of the backward's h2 slot
+// restricted to the lattice sites: C / 4 contiguous segments (segment q holds
+// channels 4q .. 4q + 3 of site n at 4 n), which the backward copies into LDS
+// as 1 KB chunks (64 lanes x 16 bytes).  (The BF16 2D L = 32 step was slower
+// this way: without conv2 its backward still waits on the copy, and its conv1
+// loses the row triples built in the h2 slot.)
 template <int DIM, int L, int C, bool BF16>
 struct HSave {
   static constexpr int V = DIM == 2 ? L * L : L * L * L;
   static constexpr bool ok = !BF16 && DIM == 2 && L == 32 && C == 16;
-  static constexpr int SEGS = BF16 ? 1 : C / 4;
-  static constexpr int SEG_BYTES = BF16 ? 2 * C * V : 16 * V;
+  static constexpr int SEGS = C / 4;
+  static constexpr int SEG_BYTES = 16 * V;
   static constexpr int CHUNKS = SEGS * SEG_BYTES / 1024;
   static constexpr size_t sample_bytes = (size_t)SEGS * SEG_BYTES;
   static_assert(SEG_BYTES % 1024 == 0, "whole 1 KB chunks per segment");
-  // element offset of channels ch0 .. ch0 + 3 (ch0 % 4 == 0) of site n in a sample
-  __host__ __device__ static constexpr int off4(int n, int ch0) { return BF16 ? n * C + ch0 : ((ch0 >> 2) * V + n) * 4; }
+  // float offset of channels ch0 .. ch0 + 3 (ch0 % 4 == 0) of site n in a sample
+  __host__ __device__ static constexpr int off4(int n, int ch0) { return ((ch0 >> 2) * V + n) * 4; }
 };
 
 // Parity of |delta_t|_1: a neighbour at tap t has parity p(n) ^ todd(t).

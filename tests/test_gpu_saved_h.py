@@ -4,12 +4,15 @@ lfs_flow_backward_saved) against the plain pair and the oracle.
 The backward of a coupling layer needs h2 = LeakyReLU(W2 h1 + b2) at every site (paper
 Sec. 1, the s/t networks of the coupling layers); the saved pair keeps it from the
 forward instead of recomputing it.  Checked here, on 2D L = 32, hidden 16, plain FP32
-(the shape the pair saves for) at batches that leave some workgroups two samples:
+(the shape the pair saves for), at batches that leave some workgroups two or three
+samples:
   - the forward's outputs are bitwise those of lfs_flow_forward;
   - the saved h2 of every layer and sample equals the oracle's h2 of that layer's
-    saved input field (FP32 bounds of the forward, T = 9 taps of fan-in 16);
-  - the backward equals the recomputing backward (both within the FP32 gradient
-    bounds of the oracle), scalar and per-sample log q cotangents;
+    input field within 1e-5 (1 + |h2|) (FP32 sums of 9 and 144 terms);
+  - the backward equals the recomputing backward within 1e-6 relative (measured:
+    bitwise), and at a small batch the oracle within the FP32 bounds of the parity
+    tests;
+  - scalar and per-sample log q cotangents give the same bits;
   - on a shape without a saved layout the pair reports 0 bytes and falls back to
     the plain entry points' results.
 """
@@ -62,13 +65,14 @@ def test_saved_bytes():
     assert lfs.saved_h_bytes(desc, 5) == 3 * 5 * 16 * 1024 * 4
     assert lfs.saved_h_bytes(desc, 0) == 0
     for other in (lfs.make_desc(2, 8, 2, 16), lfs.make_desc(2, 32, 2, 8),
+                  lfs.make_desc(2, 32, 2, 16, precision=lfs.LFS_BF16_CONV),
                   lfs.make_desc(3, 16, 2, 32, precision=lfs.LFS_BF16_CONV)):
         assert lfs.saved_h_bytes(other, 4) == 0
 
 
 def test_forward_train_outputs_and_saved_h():
     """Outputs bitwise those of the plain forward; saved h2 = the oracle's h2 per layer."""
-    B = 300
+    B = 520
     print(f"forward_train 2D L=32 C=16 FP32 B={B}", flush=True)
     desc, params, z, fs = _case(B)
     a = run_forward(desc, params, z)
@@ -79,7 +83,7 @@ def test_forward_train_outputs_and_saved_h():
     # [N][B][C/4][V][4] -> [N][B][C][V]
     hs = host(t["saved_h"]).view(np.float32).reshape(N, B, C // 4, V, 4).transpose(0, 1, 2, 4, 3)
     hs = hs.reshape(N, B, C, V).astype(np.float64)
-    rows = [0, 1, 255, 256, 299]
+    rows = [0, 1, 255, 256, 511, 519]
     saved = host(t["saved"]).reshape(N + 1, B, V).astype(np.float64)
     layers = of.unpack(params, fs)
     for l in range(N):
@@ -94,10 +98,10 @@ def test_forward_train_outputs_and_saved_h():
         assert err <= 1e-5, (l, err)
 
 
-@pytest.mark.parametrize("B", [300, 4])
+@pytest.mark.parametrize("B", [520, 4])
 def test_backward_saved_matches_recompute_and_oracle(B):
-    """B = 300: the grid of 256 gives 44 workgroups a second sample, whose saved h2 is
-    copied in while the first one's tail passes run."""
+    """B = 520: the grid of 256 workgroups gives eight of them a third sample, whose
+    saved h2 is copied in while the previous one's tail passes run."""
     print(f"backward_saved 2D L=32 C=16 FP32 B={B}", flush=True)
     desc, params, z, fs = _case(B)
     rng = np.random.default_rng(310)
@@ -121,7 +125,7 @@ def test_backward_saved_matches_recompute_and_oracle(B):
 
 
 def test_backward_saved_vector_cotangent_and_determinism():
-    B = 260
+    B = 600
     desc, params, z, fs = _case(B)
     g_phi = np.random.default_rng(311).standard_normal(z.shape).astype(np.float32)
     t = _forward_train(desc, params, z)
