@@ -152,15 +152,17 @@ __global__ void __launch_bounds__(NT) kf_forward(
 #pragma unroll
               for (int ct = 0; ct < LF.nct; ++ct) store_act_tile<LY, C, BF16, false>(h2, tile, m, ct, j, acc[ct]);
               if constexpr (HS::ok) {
-                // training: h2 saved for the backward (the same values as in LDS)
+                // training: h2 saved for the backward (the same values as in LDS),
+                // nontemporal: read back only by the backward, after every layer
                 if (hsave) {
                   float* hb = hsave + ((size_t)layer * B + b) * (HS::sample_bytes / 4);
 #pragma unroll
                   for (int ct = 0; ct < LF.nct; ++ct) {
                     const int co0 = ct * 16 + 4 * j;
                     if (co0 < C)
-                      *reinterpret_cast<f32x4*>(hb + HS::off4(tile * 16 + m, co0)) =
-                          f32x4{leaky(acc[ct][0]), leaky(acc[ct][1]), leaky(acc[ct][2]), leaky(acc[ct][3])};
+                      __builtin_nontemporal_store(
+                          f32x4{leaky(acc[ct][0]), leaky(acc[ct][1]), leaky(acc[ct][2]), leaky(acc[ct][3])},
+                          reinterpret_cast<f32x4*>(hb + HS::off4(tile * 16 + m, co0)));
                   }
                 }
               }
