@@ -356,13 +356,16 @@ int32_t fused_forward(const FlowGeom& g, const float* params, int B, const float
                       double* logq, double* logdet, float* saved, float* hsave, char* ws,
                       hipStream_t st) {
   const fused::FwdEntry* e = fused::find_fwd(g);
-  if (!e) return fused::ring_forward(g, params, B, z, phi, logq, logdet, saved, ws, st);
+  if (!e)
+    return fused::ring_forward(g, params, B, z, phi, logq, logdet, saved,
+                               reinterpret_cast<unsigned char*>(hsave), ws, st);
   return e->fn(g, params, B, z, phi, logq, logdet, saved, hsave, ws, st);
 }
 
 size_t fused_hsave_bytes(const FlowGeom& g, int B) {
   const fused::FwdEntry* e = fused::find_fwd(g);
-  if (!e || !e->hsave_bytes_per_sample || !fused::bwd_supported(g)) return 0;
+  if (!e) return fused::ring_bwd_supported(g) ? fused::ring_hsave_bytes(g, B) : 0;
+  if (!e->hsave_bytes_per_sample || !fused::bwd_supported(g)) return 0;
   return e->hsave_bytes_per_sample * (size_t)B * g.N;
 }
 
@@ -372,7 +375,8 @@ int32_t fused_backward(const FlowGeom& g, const float* params, int B, const floa
                        hipStream_t st) {
   if (fused::bwd_supported(g))
     return fused::bwd_run(g, params, B, saved, hsave, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
-  return fused::ring_bwd_run(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
+  return fused::ring_bwd_run(g, params, B, saved, reinterpret_cast<const unsigned char*>(hsave), g_phi,
+                             g_logq, g_logq_vec, g_params, g_z, ws, st);
 }
 
 }  // namespace lfs

@@ -73,12 +73,20 @@ __device__ __forceinline__ u32x4 gather_ring(const HElem<BF16>* ring, int pq, in
   return *reinterpret_cast<const u32x4*>(ring + e);
 }
 
-template <int L, int C, bool BF16, int NT>
+// shapes whose plane-streaming backward reads saved activations
+template <int L, int C, bool BF16>
+constexpr bool ring_saves() {
+  return BF16 && L == 16 && (C == 16 || C == 32);
+}
+
+// SV (training, BF16): every layer's h1, h2, their sign words and s are also
+// written to hsave (RingSave layout) for the backward.
+template <int L, int C, bool BF16, int NT, bool SV = false>
 __global__ void __launch_bounds__(NT) kf_forward_ring(
     const u32x4* __restrict__ frags, const float* __restrict__ params, int P_layer, int off_b1,
     int off_b2, int off_b3, int N, int parity0, int final_tanh, int B, const float* __restrict__ z,
     float* __restrict__ phi, float* __restrict__ saved, double* __restrict__ logq,
-    double* __restrict__ logdet) {
+    double* __restrict__ logdet, unsigned char* __restrict__ hsave) {
   using Cfg = RingCfg<L, C, BF16>;
   using G = typename Cfg::G;
   using LX = typename Cfg::LX;
@@ -139,6 +147,51 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
         for (int c = 0; c < LF.k2; ++c) A3[c] = fl[(LF.off3 + c) * 64];
       }
       const float bs = pl[off_b3], bt = pl[off_b3 + 1];
+      // SV: this layer's and sample's saved tensors
+      uint16_t *sh1 = nullptr, *sh2 = nullptr;
+      uint32_t *sm1 = nullptr, *sm2 = nullptr;
+      float* ssv = nullptr;
+      if constexpr (SV) {
+        const RingSave rs((size_t)B, C, V);
+        unsigned char* hl = hsave + (size_t)layer * rs.layer;
+        sh1 = reinterpret_cast<uint16_t*>(hl + rs.h1) + (size_t)b * C * V;
+        sh2 = reinterpret_cast<uint16_t*>(hl + rs.h2) + (size_t)b * C * V;
+        sm1 = reinterpret_cast<uint32_t*>(hl + rs.m1) + (size_t)b * V;
+        sm2 = reinterpret_cast<uint32_t*>(hl + rs.m2) + (size_t)b * V;
+        ssv = reinterpret_cast<float*>(hl + rs.s) + (size_t)b * V;
+      }
+      // SV: real plane zr of a ring (its slot) to the channel-major copy hc and the sign
+      // words mk, by all threads while the plane is only read (between the barrier after
+      // the pass that wrote it and the pass that overwrites its slot): item (g, q) takes
+      // channels 8g .. 8g + 7 of in-plane site q, consecutive threads consecutive sites
+      auto save_plane = [&](const HT* ring, int slot, int zr, uint16_t* hc, uint32_t* mk) {
+        if constexpr (SV) {
+          constexpr int NG = C / 8;
+          // the thread index made opaque here, so that the items' offsets are computed
+          // at each call instead of being hoisted out of the plane loop and held in
+          // registers across the convolutions
+          int t0 = threadIdx.x;
+          asm volatile("" : "+v"(t0));
+#pragma unroll 1
+          for (int i = t0; i < NG * PLANE; i += NT) {
+            const int g = i / PLANE, q = i - g * PLANE;
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(ring + (slot * PS + LP2::idx(q)) * C + 8 * g);
+            const int n = zr * PLANE + q;  // 32-bit offsets from the uniform base hc
+            uint32_t bits = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const uint32_t hw = src[k];
+              hc[(8 * g + 2 * k) * V + n] = (uint16_t)hw;
+              hc[(8 * g + 2 * k + 1) * V + n] = (uint16_t)(hw >> 16);
+              bits |= (uint32_t)(bf16_lo(hw) >= 0.f) << (2 * k) | (uint32_t)(bf16_hi(hw) >= 0.f) << (2 * k + 1);
+            }
+            // byte g of site n's word holds channels 8g .. 8g + 7 (bit c: channel c)
+            uint8_t* mb = reinterpret_cast<uint8_t*>(mk + n);
+            mb[g] = (uint8_t)bits;
+            if constexpr (C == 16) mb[g + 2] = 0;
+          }
+        }
+      };
 
       // row triples of the masked field of virtual plane v into triple-ring slot v mod 5
       // (only frozen sites' values enter, which conv3 never changes)
@@ -222,6 +275,7 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
             const float xn = xs[LX::idx(n)] * fast_exp(s) + t;
             LX::copies(n, [&](int qq) { xs[qq] = xn; });
             ld += (R)s;
+            if constexpr (SV) ssv[n] = s;
           }
         }
       };
@@ -241,20 +295,25 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
       conv1_plane(0);
       __syncthreads();
       conv2_plane(-1);
+      save_plane(r1, mod3(0), 0, sh1, sm1);
       if constexpr (Cfg::TRIR) build_tri_plane(2);  // over plane -3's triples, last read by conv1(-2)
       __syncthreads();
       conv1_plane(1);
       __syncthreads();
       conv2_plane(0);
+      save_plane(r1, mod3(1), 1, sh1, sm1);
       if constexpr (Cfg::TRIR) build_tri_plane(3);
       __syncthreads();
+      save_plane(r2, mod3(0), 0, sh2, sm2);
       for (int zr = 0; zr < L; ++zr) {
         conv1_plane(zr + 2);  // triples of planes zr + 1 .. zr + 3
         __syncthreads();
         conv2_plane(zr + 1);
+        if (zr + 2 < L) save_plane(r1, mod3(zr + 2), zr + 2, sh1, sm1);
         // plane zr + 4's triples (for the next conv1) over plane zr - 1's, last read by conv1(zr)
         if constexpr (Cfg::TRIR) build_tri_plane(zr + 4);
         __syncthreads();
+        if (zr + 1 < L) save_plane(r2, mod3(zr + 1), zr + 1, sh2, sm2);
         conv3_plane(zr);
       }
       __syncthreads();
@@ -279,7 +338,8 @@ __global__ void __launch_bounds__(NT) kf_forward_ring(
 
 template <int L, int C, bool BF16>
 int32_t launch_ring(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
-                    double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
+                    double* logq, double* logdet, float* saved, unsigned char* hsave, char* ws,
+                    hipStream_t st) {
   using Cfg = RingCfg<L, C, BF16>;
   constexpr LayerFrags LF = Cfg::LF;
   static_assert(Cfg::lds_bytes <= 160 * 1024, "LDS budget");
@@ -293,14 +353,17 @@ int32_t launch_ring(const FlowGeom& g, const float* params, int B, const float* 
   const long nthreads = (long)LF.total * 64 * g.N;
   hipLaunchKernelGGL((kf_prep<BF16>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st,
                      params, g.N, g.T, (int)g.P_layer, tab, frags);
-  auto kern = kf_forward_ring<L, C, BF16, Cfg::NT>;
+  auto kern = kf_forward_ring<L, C, BF16, Cfg::NT, false>;
+  if constexpr (ring_saves<L, C, BF16>())
+    if (hsave) kern = kf_forward_ring<L, C, BF16, Cfg::NT, true>;
+  if (!ring_saves<L, C, BF16>()) hsave = nullptr;
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)Cfg::lds_bytes) !=
       hipSuccess)
     return LFS_EDEVICE;
   hipLaunchKernelGGL(kern, dim3(B), dim3(Cfg::NT), Cfg::lds_bytes, st, frags, params,
                      (int)g.P_layer, (int)g.off_b1, (int)g.off_b2, (int)g.off_b3, g.N, g.parity0,
-                     g.final_tanh, B, z, phi, saved, logq, logdet);
+                     g.final_tanh, B, z, phi, saved, logq, logdet, hsave);
   return launch_status();
 }
 
@@ -308,14 +371,15 @@ struct RingEntry {
   int L, C;
   bool bf16;
   int32_t (*fn)(const FlowGeom&, const float*, int, const float*, float*, double*, double*, float*,
-                char*, hipStream_t);
+                unsigned char*, char*, hipStream_t);
   size_t frag_bytes_per_layer;
+  bool saves;  // the training forward saves the activations (RingSave) for the backward
 };
 
 template <int L, int C, bool BF16>
 constexpr RingEntry ring_entry() {
   return RingEntry{L, C, BF16, &launch_ring<L, C, BF16>,
-                   (size_t)RingCfg<L, C, BF16>::LF.total * 64 * 16};
+                   (size_t)RingCfg<L, C, BF16>::LF.total * 64 * 16, ring_saves<L, C, BF16>()};
 }
 
 const RingEntry kRingTable[] = {ring_entry<16, 8, false>(), ring_entry<16, 8, true>(),
@@ -337,10 +401,16 @@ size_t ring_ws_bytes(const FlowGeom& g) {
   return e ? align_up(e->frag_bytes_per_layer * g.N) : 0;
 }
 int32_t ring_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
-                     double* logq, double* logdet, float* saved, char* ws, hipStream_t st) {
+                     double* logq, double* logdet, float* saved, unsigned char* hsave, char* ws,
+                     hipStream_t st) {
   const RingEntry* e = find_ring(g);
   if (!e) return LFS_EUNSUPPORTED;
-  return e->fn(g, params, B, z, phi, logq, logdet, saved, ws, st);
+  return e->fn(g, params, B, z, phi, logq, logdet, saved, hsave, ws, st);
+}
+size_t ring_hsave_bytes(const FlowGeom& g, int B) {
+  const RingEntry* e = find_ring(g);
+  if (!e || !e->saves) return 0;
+  return RingSave((size_t)B, g.C, g.V).layer * g.N;
 }
 
 }  // namespace fused

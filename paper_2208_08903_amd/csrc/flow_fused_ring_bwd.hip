@@ -104,30 +104,7 @@ __device__ __forceinline__ u32x4 gather_rb(const uint16_t* ring, int pq, int sm,
   return *reinterpret_cast<const u32x4*>(ring + e);
 }
 
-// Four channels co0..co0+3 (BF16 pairs in hv) of site n of a channel-major tensor.
-template <int C, int V>
-__device__ __forceinline__ void store_cm_global(uint16_t* t, int n, int co0, const u32x2& hv) {
-  if (co0 >= C) return;
-  t[(size_t)(co0 + 0) * V + n] = (uint16_t)hv[0];
-  t[(size_t)(co0 + 1) * V + n] = (uint16_t)(hv[0] >> 16);
-  t[(size_t)(co0 + 2) * V + n] = (uint16_t)hv[1];
-  t[(size_t)(co0 + 3) * V + n] = (uint16_t)(hv[1] >> 16);
-}
-
 __device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// LeakyReLU' mask word of one 16-channel tile: bit k set iff channel k's output
-// h >= 0 (then leaky' = 1, else the slope; -0 counts as >= 0, like the float
-// comparison).  Lane j holds channels 4j..4j+3 (BF16 pairs in hv); the four
-// lanes that share m combine their nibbles, so every lane returns the word.
-__device__ __forceinline__ uint32_t sign_mask16(const u32x2& hv, int j) {
-  const uint32_t nib = (uint32_t)(bf16_lo(hv[0]) >= 0.f) | (uint32_t)(bf16_hi(hv[0]) >= 0.f) << 1 |
-                       (uint32_t)(bf16_lo(hv[1]) >= 0.f) << 2 | (uint32_t)(bf16_hi(hv[1]) >= 0.f) << 3;
-  uint32_t w = nib << (4 * j);
-  w |= __shfl_xor(w, 16, 64);
-  w |= __shfl_xor(w, 32, 64);
-  return w;
-}
 
 // Sum over the 16 lanes of a wave that share j (lane bits 0-3), fixed order.
 __device__ __forceinline__ float sum16(float v) {
@@ -362,6 +339,67 @@ __global__ void __launch_bounds__(NT) kr_recompute(
       build_tri_plane(zr + 4);  // over plane zr's, last read by conv1(zr + 1)
       __syncthreads();
       conv3_plane(zr);
+    }
+  }
+  db3s = block_sum(db3s, red);
+  db3t = block_sum(db3t, red);
+  if (threadIdx.x == 0) {
+    partial[(size_t)blockIdx.x * P + off_b3] = db3s;
+    partial[(size_t)blockIdx.x * P + off_b3 + 1] = db3t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// affine backward from the training forward's saved s (in place of recompute)
+// ---------------------------------------------------------------------------
+// At the active sites: g_x = g_y e^s, g_o = (g_s (1 - s^2), g_t) with g_s = g_y x e^s
+// + g_ld (the log-det's cotangent) and g_t = g_y; zero g_o at the frozen sites; db3.
+// (paper Sec. 1, coupling-layer equation).  Element-wise: four consecutive sites per
+// thread and step.
+template <int L, int NT>
+__global__ void __launch_bounds__(NT) kr_affine(
+    int fpar, int final_tanh, float g_ld, const double* __restrict__ g_ld_vec, int B,
+    const float* __restrict__ xin, const float* __restrict__ gy, const float* __restrict__ ss,
+    float* __restrict__ gx, uint32_t* __restrict__ go, float* __restrict__ partial, int P, int off_b3,
+    const float* __restrict__ prev_partial, float* __restrict__ prev_out) {
+  using G = Geo<3, L>;
+  constexpr int V = G::V;
+  static_assert(L % 4 == 0, "four sites of one row per thread");
+  __shared__ float red[16];
+  float db3s = 0.f, db3t = 0.f;
+  // the previous launch's (next layer's) weight gradient (same grid as every kernel
+  // of a layer, so also the number of partials)
+  if (prev_partial) grid_reduce<NT>(prev_partial, prev_out, (int)gridDim.x, P);
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    const size_t sb = (size_t)b * V;
+    const float gld = g_ld_vec ? (float)(-g_ld_vec[b]) : g_ld;
+    for (int q = threadIdx.x; q < V / 4; q += NT) {
+      const int n0 = 4 * q;
+      const f32x4 g = reinterpret_cast<const f32x4*>(gy + sb)[q];
+      const f32x4 x = reinterpret_cast<const f32x4*>(xin + sb)[q];
+      const f32x4 sv = reinterpret_cast<const f32x4*>(ss + sb)[q];
+      f32x4 gxv;
+      u32x4 gov;
+      // sites n0 + i alternate in parity along the row; the frozen ones get g_o = 0
+      // and a placeholder g_x, which the transpose kernel overwrites
+      const int a0 = G::parity(n0) == fpar ? 1 : 0;  // first active offset
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if ((i & 1) == a0) {
+          const float s = sv[i], es = fast_exp(s);
+          const float gs = g[i] * x[i] * es + gld;
+          const float go0 = final_tanh ? gs * (1.f - s * s) : gs;
+          db3s += go0;
+          db3t += g[i];
+          gxv[i] = g[i] * es;
+          gov[i] = pack_bf16(go0, g[i]);
+        } else {
+          gxv[i] = 0.f;
+          gov[i] = 0u;
+        }
+      }
+      reinterpret_cast<f32x4*>(gx + sb)[q] = gxv;
+      reinterpret_cast<u32x4*>(go + sb)[q] = gov;
     }
   }
   db3s = block_sum(db3s, red);
@@ -827,9 +865,8 @@ bool set_lds(K kern, size_t bytes) {
 
 template <int L, int C>
 int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved,
-               const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params, float* g_z,
-               char* ws,
-               hipStream_t st) {
+               const unsigned char* hsave, const float* g_phi, double g_logq, const double* g_logq_vec,
+               float* g_params, float* g_z, char* ws, hipStream_t st) {
   using Cfg = RbCfg<L, C>;
   const int grid = rb_grid<L, C>(B);
   const FragTable tab = bwd_table(g, true, false);
@@ -858,11 +895,13 @@ int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved
   hipLaunchKernelGGL((kf_prep<true>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st,
                      params, g.N, g.T, (int)g.P_layer, tab, frags);
   auto ka = kr_recompute<L, C, Cfg::NT_A>;
+  auto kaff = kr_affine<L, 256>;
   auto kb = kr_transpose<L, C, Cfg::NT_B>;
   auto kc = kr_wgrad<L, C, Cfg::NT_C>;
   if (!set_lds(ka, Cfg::LDS_A) || !set_lds(kb, Cfg::LDS_B) || !set_lds(kc, Cfg::LDS_C))
     return LFS_EDEVICE;
   const int P = Cfg::P_LAYER;
+  const RingSave rs((size_t)B, C, Cfg::V);
   const float* gy = g_phi;
   int which = 0;
   for (int l = g.N - 1; l >= 0; --l) {
@@ -873,19 +912,31 @@ int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved
     const int fpar = g.frozen_parity(l);
     const bool first = l == g.N - 1;
     float* partial = partials[l & 1];
-    hipLaunchKernelGGL(ka, dim3(grid), dim3(Cfg::NT_A), Cfg::LDS_A, st, fl, pl, (int)g.off_b1,
-                       (int)g.off_b2, (int)g.off_b3, fpar, g.final_tanh, (float)(-g_logq), g_logq_vec, B, xl,
-                        gy,
-                       gx, h1c, h2c, m1, m2, go, partial, P,
-                       first ? nullptr : (const float*)partials[(l + 1) & 1],
-                       first ? nullptr : g_params + (size_t)(l + 1) * g.P_layer);
+    const float* prev = first ? nullptr : (const float*)partials[(l + 1) & 1];
+    float* prev_out = first ? nullptr : g_params + (size_t)(l + 1) * g.P_layer;
+    const uint16_t *h1l = h1c, *h2l = h2c;
+    const uint32_t *m1l = m1, *m2l = m2;
+    if (hsave) {
+      // the training forward's h1, h2, sign words and s: only the affine backward is left
+      const unsigned char* hl = hsave + (size_t)l * rs.layer;
+      h1l = reinterpret_cast<const uint16_t*>(hl + rs.h1);
+      h2l = reinterpret_cast<const uint16_t*>(hl + rs.h2);
+      m1l = reinterpret_cast<const uint32_t*>(hl + rs.m1);
+      m2l = reinterpret_cast<const uint32_t*>(hl + rs.m2);
+      hipLaunchKernelGGL(kaff, dim3(grid), dim3(256), 0, st, fpar, g.final_tanh, (float)(-g_logq), g_logq_vec,
+                         B, xl, gy, reinterpret_cast<const float*>(hl + rs.s), gx, go, partial, P,
+                         (int)g.off_b3, prev, prev_out);
+    } else {
+      hipLaunchKernelGGL(ka, dim3(grid), dim3(Cfg::NT_A), Cfg::LDS_A, st, fl, pl, (int)g.off_b1,
+                         (int)g.off_b2, (int)g.off_b3, fpar, g.final_tanh, (float)(-g_logq), g_logq_vec, B,
+                         xl, gy, gx, h1c, h2c, m1, m2, go, partial, P, prev, prev_out);
+    }
     hipLaunchKernelGGL(kb, dim3(grid), dim3(Cfg::NT_B), Cfg::LDS_B, st, fl, fpar, B,
-                       (const uint32_t*)go, (const uint32_t*)m1, (const uint32_t*)m2, gy, gx,
-                       ga2c, ga1c, partial, P, (int)g.off_b1, (int)g.off_b2);
-    hipLaunchKernelGGL(kc, dim3(grid), dim3(Cfg::NT_C), Cfg::LDS_C, st, fpar, B, xl,
-                       (const uint16_t*)h1c, (const uint16_t*)h2c, (const uint32_t*)go,
-                       (const uint16_t*)ga2c, (const uint16_t*)ga1c, partial, P, (int)g.off_W1,
-                       (int)g.off_W2, (int)g.off_W3);
+                       (const uint32_t*)go, m1l, m2l, gy, gx, ga2c, ga1c, partial, P, (int)g.off_b1,
+                       (int)g.off_b2);
+    hipLaunchKernelGGL(kc, dim3(grid), dim3(Cfg::NT_C), Cfg::LDS_C, st, fpar, B, xl, h1l, h2l,
+                       (const uint32_t*)go, (const uint16_t*)ga2c, (const uint16_t*)ga1c, partial, P,
+                       (int)g.off_W1, (int)g.off_W2, (int)g.off_W3);
     gy = gx;
     which ^= 1;
   }
@@ -899,8 +950,8 @@ int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved
 
 struct RbEntry {
   int L, C;
-  int32_t (*fn)(const FlowGeom&, const float*, int, const float*, const float*, double,
-                const double*, float*, float*, char*, hipStream_t);
+  int32_t (*fn)(const FlowGeom&, const float*, int, const float*, const unsigned char*, const float*,
+                double, const double*, float*, float*, char*, hipStream_t);
   size_t (*ws)(const FlowGeom&, int);
 };
 
@@ -922,12 +973,11 @@ size_t ring_bwd_ws_bytes(const FlowGeom& g, int B) {
   return e ? e->ws(g, B) : 0;
 }
 int32_t ring_bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
-                     const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
-                     float* g_z, char* ws,
-                     hipStream_t st) {
+                     const unsigned char* hsave, const float* g_phi, double g_logq,
+                     const double* g_logq_vec, float* g_params, float* g_z, char* ws, hipStream_t st) {
   const RbEntry* e = find_rb(g);
   if (!e) return LFS_EUNSUPPORTED;
-  return e->fn(g, params, B, saved, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
+  return e->fn(g, params, B, saved, hsave, g_phi, g_logq, g_logq_vec, g_params, g_z, ws, st);
 }
 
 }  // namespace fused

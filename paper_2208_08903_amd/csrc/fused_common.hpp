@@ -334,6 +334,25 @@ struct HSave {
   __host__ __device__ static constexpr int off4(int n, int ch0) { return ((ch0 >> 2) * V + n) * 4; }
 };
 
+// Activations the plane-streaming training forward (3D, BF16 convolutions) saves
+// for the backward, which then skips recomputing them; one block per layer of a
+// batch of B samples, V sites, C channels: h1 and h2 channel-major BF16
+// [B][C][V], the LeakyReLU sign word of every site of h1 and of h2 [B][V] (bit c
+// set iff channel c's output is >= 0), and s at the active sites [B][V] FP32
+// (frozen entries not written).  Byte offsets within a layer's block.
+struct RingSave {
+  size_t h1, h2, m1, m2, s, layer;
+  __host__ __device__ RingSave(size_t B, int C, int V) {
+    const size_t hb = B * (size_t)C * V * 2, wb = B * (size_t)V * 4;
+    h1 = 0;
+    h2 = hb;
+    m1 = 2 * hb;
+    m2 = 2 * hb + wb;
+    s = 2 * hb + 2 * wb;
+    layer = 2 * hb + 3 * wb;
+  }
+};
+
 // Parity of |delta_t|_1: a neighbour at tap t has parity p(n) ^ todd(t).
 template <int DIM>
 __device__ __forceinline__ int todd(int t) {

@@ -273,6 +273,29 @@ __device__ __forceinline__ u32x2 store_hidden(HElem<BF16>* h, int n, int ct, int
   return store4<LY, C, BF16>(h, n, co0, v);
 }
 
+// Four channels co0..co0+3 (BF16 pairs in hv) of site n of a channel-major tensor.
+template <int C, int V>
+__device__ __forceinline__ void store_cm_global(uint16_t* t, int n, int co0, const u32x2& hv) {
+  if (co0 >= C) return;
+  t[(size_t)(co0 + 0) * V + n] = (uint16_t)hv[0];
+  t[(size_t)(co0 + 1) * V + n] = (uint16_t)(hv[0] >> 16);
+  t[(size_t)(co0 + 2) * V + n] = (uint16_t)hv[1];
+  t[(size_t)(co0 + 3) * V + n] = (uint16_t)(hv[1] >> 16);
+}
+
+// LeakyReLU' mask word of one 16-channel tile: bit k set iff channel k's output
+// h >= 0 (then leaky' = 1, else the slope; -0 counts as >= 0, like the float
+// comparison).  Lane j holds channels 4j..4j+3 (BF16 pairs in hv); the four
+// lanes that share m combine their nibbles, so every lane returns the word.
+__device__ __forceinline__ uint32_t sign_mask16(const u32x2& hv, int j) {
+  const uint32_t nib = (uint32_t)(bf16_lo(hv[0]) >= 0.f) | (uint32_t)(bf16_hi(hv[0]) >= 0.f) << 1 |
+                       (uint32_t)(bf16_lo(hv[1]) >= 0.f) << 2 | (uint32_t)(bf16_hi(hv[1]) >= 0.f) << 3;
+  uint32_t w = nib << (4 * j);
+  w |= __shfl_xor(w, 16, 64);
+  w |= __shfl_xor(w, 32, 64);
+  return w;
+}
+
 // store4 for lane m of a 16-site tile: all stored copies of its site (HALO), or
 // only the interior one, the halo being filled afterwards by fill_halo.
 template <class LY, int C, bool BF16, bool HALO = true>

@@ -70,9 +70,10 @@ int32_t net_backward_bn(const FlowGeom& g, const float* params, int B, const flo
 // Fused kernels: LDS-resident per-sample lattices, matrix-core convolutions.
 bool fused_supported(const FlowGeom& g, int for_backward);
 size_t fused_ws_bytes(const FlowGeom& g, int B, int for_backward);
-// hsave (nullable): the training forward's saved h2 of every layer, in the
-// shape's HSave image ([N][B] samples); fused_hsave_bytes gives its size (0:
-// the shape's backward recomputes h2, and hsave is ignored)
+// hsave (nullable): the training forward's saved activations of every layer
+// (the resident kernels' HSave images of h2, [N][B] samples, or the
+// plane-streaming kernels' RingSave blocks); fused_hsave_bytes gives its size
+// (0: the shape's backward recomputes them, and hsave is ignored)
 int32_t fused_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
                       double* logq, double* logdet, float* saved, float* hsave, char* ws,
                       hipStream_t st);
@@ -87,8 +88,12 @@ namespace fused {
 // keep resident), implemented next to its kernel.
 bool ring_supported(const FlowGeom& g);
 size_t ring_ws_bytes(const FlowGeom& g);
+// hsave (nullable): the activations saved for the plane-streaming backward
+// (RingSave layout, ring_hsave_bytes of them; 0 bytes: not saved for this shape)
 int32_t ring_forward(const FlowGeom& g, const float* params, int B, const float* z, float* phi,
-                     double* logq, double* logdet, float* saved, char* ws, hipStream_t st);
+                     double* logq, double* logdet, float* saved, unsigned char* hsave, char* ws,
+                     hipStream_t st);
+size_t ring_hsave_bytes(const FlowGeom& g, int B);
 // Fused backward (one launch per layer), implemented next to its kernels.
 bool bwd_supported(const FlowGeom& g);
 size_t bwd_ws_bytes(const FlowGeom& g, int B);
@@ -100,9 +105,8 @@ int32_t bwd_run(const FlowGeom& g, const float* params, int B, const float* save
 bool ring_bwd_supported(const FlowGeom& g);
 size_t ring_bwd_ws_bytes(const FlowGeom& g, int B);
 int32_t ring_bwd_run(const FlowGeom& g, const float* params, int B, const float* saved,
-                     const float* g_phi, double g_logq, const double* g_logq_vec, float* g_params,
-                     float* g_z, char* ws,
-                     hipStream_t st);
+                     const unsigned char* hsave, const float* g_phi, double g_logq,
+                     const double* g_logq_vec, float* g_params, float* g_z, char* ws, hipStream_t st);
 }  // namespace fused
 
 }  // namespace lfs

@@ -210,14 +210,20 @@ def test_null_and_shape_arguments_rejected_before_any_launch():
 
 def test_saved_h_bytes_and_validation():
     """The training pair's saved activations: N B C V FP32 values on 2D L = 32, hidden 16,
-    plain FP32; none elsewhere; missing buffers are rejected before any launch."""
+    plain FP32; h1, h2, sign words and s on 3D L = 16 (BF16, hidden 16 or 32); none
+    elsewhere; missing buffers are rejected before any launch."""
     lib = lfs.load()
     d = lfs.make_desc(2, 32, 3, 16)
     assert lfs.saved_h_bytes(d, 5) == 3 * 5 * 16 * 1024 * 4
     assert lfs.saved_h_bytes(d, 0) == 0
+    # 3D L = 16, BF16 (plane-streaming): h1, h2 BF16 channel-major, two sign words and s per site
+    for C in (16, 32):
+        d3 = lfs.make_desc(3, 16, 2, C, precision=lfs.LFS_BF16_CONV)
+        assert lfs.saved_h_bytes(d3, 4) == 2 * (2 * 4 * C * 4096 * 2 + 3 * 4 * 4096 * 4)
     for other in (lfs.make_desc(2, 8, 2, 16), lfs.make_desc(2, 32, 2, 8),
                   lfs.make_desc(2, 32, 2, 16, precision=lfs.LFS_BF16_CONV),
-                  lfs.make_desc(3, 16, 2, 32, precision=lfs.LFS_BF16_CONV),
+                  lfs.make_desc(3, 16, 2, 8, precision=lfs.LFS_BF16_CONV),
+                  lfs.make_desc(3, 16, 2, 16),
                   lfs.make_desc(2, 32, 2, 16, algo=lfs.ALGO_GENERIC)):
         assert lfs.saved_h_bytes(other, 4) == 0
     out = ctypes.c_size_t(0)
