@@ -260,12 +260,12 @@ int32_t lfs_flow_backward_vec(const lfs_flow_desc* desc, const float* params, in
  *
  * lfs_saved_h_bytes: bytes of the saved activations at batch size B, written
  * to *bytes, for the shapes whose fused backward reads them: 2D L = 32,
- * hidden 16, plain FP32: h2, N B C V x 4; 3D L = 16, hidden 16 or 32, BF16
+ * hidden 16, plain FP32: h2 and s, N B (C V + V / 2) x 4; 3D L = 16, hidden 16 or 32, BF16
  * convolutions (plane-streaming kernels): h1 and h2 in BF16, a LeakyReLU
  * sign word of each and s per site, N B V (4 C + 12).  0 for every other flow
  * (its backward recomputes; saved_h below is then ignored and may be NULL).
- * The 3D backward then runs the affine backward instead of recomputing the
- * network.
+ * With s saved the backward runs the affine backward instead of recomputing
+ * the third convolution.
  * Errors: EINVAL (desc, B < 0, bytes NULL). */
 int32_t lfs_saved_h_bytes(const lfs_flow_desc* desc, int32_t B, size_t* bytes);
 

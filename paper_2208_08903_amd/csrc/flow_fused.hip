@@ -192,6 +192,8 @@ __global__ void __launch_bounds__(NT) kf_forward(
             const float xn = xs[p] * fast_exp(s) + o[1];
             LY::copies(n, [&](int q) { xs[q] = xn; });
             ld += (R)s;
+            if constexpr (HS::ok)
+              if (hsave) hsave[HS::s_off(N, B, layer, b) + a] = s;  // training: s for the backward
           }
         }
       } else if constexpr (Cfg::X4) {
@@ -315,7 +317,7 @@ template <int DIM, int L, int C, bool BF16>
 constexpr FwdEntry fwd_entry() {
   using HS = HSave<DIM, L, C, BF16>;
   return FwdEntry{DIM, L, C, BF16, &launch_forward<DIM, L, C, BF16>,
-                  (size_t)FwdCfg<DIM, L, C, BF16>::LF.total * 64 * 16, HS::ok ? HS::sample_bytes : 0};
+                  (size_t)FwdCfg<DIM, L, C, BF16>::LF.total * 64 * 16, HS::ok ? HS::sample_bytes + HS::s_bytes : 0};
 }
 
 // Shapes with a fused forward: the whole sample (field + two hidden tensors)

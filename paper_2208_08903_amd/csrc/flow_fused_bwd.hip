@@ -270,8 +270,9 @@ __device__ __forceinline__ void load_h2_async(const unsigned char* src, unsigned
 
 // ---- the kernel -------------------------------------------------------------
 
-// HS: h2 is read from the training forward's saved copy (hsv, this layer's
-// [B] HSave images) instead of being recomputed.
+// HS: h2 and s are read from the training forward's saved copies (hsv, this
+// layer's [B] HSave images; hss, its [B][V / 2] s at the active sites) instead
+// of being recomputed.
 template <int DIM, int L, int C, bool BF16, int NT, bool HS = false>
 __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backward(
     const u32x4* frags, const float* __restrict__ pl, int off_b1, int off_b2,
@@ -279,7 +280,7 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
     const double* __restrict__ g_ld_vec, int B,
     const float* __restrict__ xin, const float* __restrict__ gy, float* __restrict__ gx,
     float* __restrict__ partial, const float* __restrict__ prev_partial, float* __restrict__ prev_out,
-    int n_parts, const unsigned char* __restrict__ hsv) {
+    int n_parts, const unsigned char* __restrict__ hsv, const float* __restrict__ hss) {
   using Cfg = BwdCfg<DIM, L, C, BF16>;
   using G = Geo<DIM, L>;
   using HT = HElem<BF16>;
@@ -369,8 +370,14 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
   constexpr int NPX = PF ? (VS + NT - 1) / NT : 1, NPG = PF && GYL ? (V / 4 + NT - 1) / NT : 1;
   float pfx[NPX];
   f32x4 pfg[NPG];
+  // HS: the wave's s values of the next sample (one active site per lane; one
+  // 64-site group per wave)
+  constexpr int NGS = (V / 2 + 63) / 64;
+  static_assert(!HS || NGS == NW, "one group of active sites per wave");
+  float pfs = 0.f;
   auto prefetch = [&](int bb) {
     if (bb >= B) return;
+    if constexpr (HS) pfs = hss[(size_t)bb * (V / 2) + w * 64 + lane];
     const size_t s0 = (size_t)bb * V;
 #pragma unroll
     for (int i = 0; i < NPX; ++i) {
@@ -512,9 +519,10 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
     if constexpr (LY::padded) __syncthreads();
     {
       // affine backward at active site n from conv3's s pre-activation o0
-      auto affine_bwd = [&](int n, float o0) {
+      // (is_s: o0 already is s)
+      auto affine_bwd = [&](int n, float o0, bool is_s = false) {
         const int p = LY::idx(n);
-        const float s = final_tanh ? fast_tanh(o0) : o0;
+        const float s = is_s ? o0 : final_tanh ? fast_tanh(o0) : o0;
         const float es = fast_exp(s);
         const float g = GYL ? gys[n] : gy[sb + n];
         const float gs = g * xs[p] * es + gld;
@@ -535,7 +543,12 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
         }
       };
       const float bs = pl[off_b3];
-      if constexpr (!BF16) {
+      if constexpr (HS) {
+        // s saved by the forward (prefetched), one active site per lane
+        const int a = w * 64 + lane;
+        const float s = pfs;
+        if (a < V / 2) affine_bwd(G::half_site(a, apar), s, true);
+      } else if constexpr (!BF16) {
         // 64 active sites per wave pass, one per lane (4x4 blocks: o0 in register 0)
         constexpr int NG = (V / 2 + 63) / 64;
         const f32x4 b3{bs, 0.f, 0.f, 0.f};
@@ -1074,7 +1087,8 @@ int32_t launch_backward(const FlowGeom& g, const float* params, int B, const flo
                        first ? nullptr : (const float*)partial[(l + 1) & 1],
                        first ? nullptr : g_params + (size_t)(l + 1) * g.P_layer, grid,
                        hsave ? reinterpret_cast<const unsigned char*>(hsave) + (size_t)l * B * HSv::sample_bytes
-                             : nullptr);
+                             : nullptr,
+                       hsave ? hsave + HSv::s_off(g.N, B, l, 0) : nullptr);
     gy = gx;
     which ^= 1;
   }

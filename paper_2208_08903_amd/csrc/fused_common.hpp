@@ -318,9 +318,11 @@ __device__ __forceinline__ int tile_p(int tile, int m) {
 // quad-major.  A sample's entry is the image of the backward's h2 slot
 // restricted to the lattice sites: C / 4 contiguous segments (segment q holds
 // channels 4q .. 4q + 3 of site n at 4 n), which the backward copies into LDS
-// as 1 KB chunks (64 lanes x 16 bytes).  (The BF16 2D L = 32 step was slower
-// this way: without conv2 its backward still waits on the copy, and its conv1
-// loses the row triples built in the h2 slot.)
+// as 1 KB chunks (64 lanes x 16 bytes).  After the N B images: s at the active
+// sites, [N][B][V / 2] FP32 in half-site order, so that the backward also skips
+// conv3.  (The BF16 2D L = 32 step was slower this way: without conv2 its
+// backward still waits on the copy, and its conv1 loses the row triples built
+// in the h2 slot.)
 template <int DIM, int L, int C, bool BF16>
 struct HSave {
   static constexpr int V = DIM == 2 ? L * L : L * L * L;
@@ -329,7 +331,12 @@ struct HSave {
   static constexpr int SEG_BYTES = 16 * V;
   static constexpr int CHUNKS = SEGS * SEG_BYTES / 1024;
   static constexpr size_t sample_bytes = (size_t)SEGS * SEG_BYTES;
+  static constexpr size_t s_bytes = (size_t)V / 2 * 4;  // per sample and layer
   static_assert(SEG_BYTES % 1024 == 0, "whole 1 KB chunks per segment");
+  // float offset of the s block of (layer, sample b), N layers of B samples
+  __host__ __device__ static constexpr size_t s_off(int N, int B, int layer, int b) {
+    return ((size_t)N * B * sample_bytes + ((size_t)layer * B + b) * s_bytes) / 4;
+  }
   // float offset of channels ch0 .. ch0 + 3 (ch0 % 4 == 0) of site n in a sample
   __host__ __device__ static constexpr int off4(int n, int ch0) { return ((ch0 >> 2) * V + n) * 4; }
 };

@@ -209,12 +209,12 @@ def test_null_and_shape_arguments_rejected_before_any_launch():
 
 
 def test_saved_h_bytes_and_validation():
-    """The training pair's saved activations: N B C V FP32 values on 2D L = 32, hidden 16,
-    plain FP32; h1, h2, sign words and s on 3D L = 16 (BF16, hidden 16 or 32); none
-    elsewhere; missing buffers are rejected before any launch."""
+    """The training pair's saved activations: h2 and s, N B (C V + V / 2) FP32 values, on
+    2D L = 32, hidden 16, plain FP32; h1, h2, sign words and s on 3D L = 16 (BF16, hidden
+    16 or 32); none elsewhere; missing buffers are rejected before any launch."""
     lib = lfs.load()
     d = lfs.make_desc(2, 32, 3, 16)
-    assert lfs.saved_h_bytes(d, 5) == 3 * 5 * 16 * 1024 * 4
+    assert lfs.saved_h_bytes(d, 5) == 3 * 5 * (16 * 1024 + 512) * 4
     assert lfs.saved_h_bytes(d, 0) == 0
     # 3D L = 16, BF16 (plane-streaming): h1, h2 BF16 channel-major, two sign words and s per site
     for C in (16, 32):

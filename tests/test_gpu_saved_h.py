@@ -62,7 +62,7 @@ def _backward_saved(desc, fwd, g_phi_np, g_logq):
 
 def test_saved_bytes():
     desc, *_ = _case(4, N=3)
-    assert lfs.saved_h_bytes(desc, 5) == 3 * 5 * 16 * 1024 * 4
+    assert lfs.saved_h_bytes(desc, 5) == 3 * 5 * (16 * 1024 + 512) * 4
     assert lfs.saved_h_bytes(desc, 0) == 0
     for other in (lfs.make_desc(2, 8, 2, 16), lfs.make_desc(2, 32, 2, 8),
                   lfs.make_desc(2, 32, 2, 16, precision=lfs.LFS_BF16_CONV),
@@ -80,22 +80,28 @@ def test_forward_train_outputs_and_saved_h():
     for k in ("phi", "logq", "logdet", "saved"):
         assert torch.equal(a[k], t[k]), k
     N, C, V = fs.n_layers, fs.hidden, 1024
-    # [N][B][C/4][V][4] -> [N][B][C][V]
-    hs = host(t["saved_h"]).view(np.float32).reshape(N, B, C // 4, V, 4).transpose(0, 1, 2, 4, 3)
+    raw = host(t["saved_h"]).view(np.float32)
+    # h2: [N][B][C/4][V][4] -> [N][B][C][V]; then s: [N][B][V/2] at the active sites
+    hs = raw[:N * B * C * V].reshape(N, B, C // 4, V, 4).transpose(0, 1, 2, 4, 3)
     hs = hs.reshape(N, B, C, V).astype(np.float64)
+    ss = raw[N * B * C * V:].reshape(N, B, V // 2).astype(np.float64)
     rows = [0, 1, 255, 256, 511, 519]
     saved = host(t["saved"]).reshape(N + 1, B, V).astype(np.float64)
     layers = of.unpack(params, fs)
     for l in range(N):
         # the oracle's network on the kernel's own layer input (FP32 values, exact in FP64)
         x = of.as_lattice(saved[l, rows], fs)
-        _, hl, *_ = of.net(x, layers[l], of.frozen_mask(fs, l), fs)
+        mF = of.frozen_mask(fs, l)
+        _, hl, _, s, _ = of.net(x, layers[l], mF, fs)
         h2 = hl[2].reshape(len(rows), C, V)
         got = hs[l, rows]
         # FP32 sums of 9 and 144 terms: well inside the forward's 1e-5 (1 + |phi|)
         err = np.max(np.abs(got - h2) / (1 + np.abs(h2)))
-        print(f"  layer {l}: saved h2 vs oracle {err:.2e}", flush=True)
-        assert err <= 1e-5, (l, err)
+        # s at the active sites in half-site order (row-major among the active sites)
+        s_act = s.reshape(len(rows), V)[:, mF.reshape(-1) == 0]
+        err_s = np.max(np.abs(ss[l, rows] - s_act))
+        print(f"  layer {l}: saved h2 vs oracle {err:.2e}, s {err_s:.2e}", flush=True)
+        assert err <= 1e-5 and err_s <= 1e-5, (l, err, err_s)
 
 
 @pytest.mark.parametrize("B", [520, 4])
