@@ -150,8 +150,9 @@ struct BwdCfg {
   static constexpr bool KEXACT = NKC % NW == 0;
   static constexpr int KPW = NKC / NW;
   // unroll of the dW3 and dW1 chunk loops, 2D L=32 C=16 only (measured about
-  // 1 % faster; elsewhere unrolling costs registers, spills in 3D): dW1 by 4,
-  // dW3 by 4 in BF16 and not in FP32, where it would spill
+  // 1 % faster; elsewhere unrolling costs registers, spills in 3D): dW1 by 4
+  // (by 2 in the FP32 kernel that recomputes h2, which would spill), dW3 by 4
+  // in BF16 and not in FP32, where it would spill
   static constexpr bool DWX = DIM == 2 && L == 32 && C == 16;
   static constexpr int DWU3 = DWX && BF16 ? 4 : 1, DWU1 = DWX ? 4 : 1;
   // Weight-gradient output tiles; every wave accumulates all of them over its
@@ -649,7 +650,9 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
 #pragma unroll
             for (int nt = 0; nt < NTL3; ++nt) {
               const int col = nt * 16 + m, tap = col >> 1, co = col & 1;
-              const u32x4 bb = tap < T ? load8_shift<DIM, L>(goc + co * CSTR, s0, tap, -1) : u32x4{0u, 0u, 0u, 0u};
+              // branch-free: columns past the taps read tap 0 and select zero
+              const u32x4 bv = load8_shift<DIM, L>(goc + co * CSTR, s0, tap < T ? tap : 0, -1);
+              const u32x4 bb = tap < T ? bv : u32x4{0u, 0u, 0u, 0u};
               acc3[mt * NTL3 + nt] = mfma(as_bf16x8(a), as_bf16x8(bb), acc3[mt * NTL3 + nt]);
             }
           } else {
@@ -845,7 +848,7 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
     // tiles (mt, nt): rows c = mt*16 + i, columns tap = nt*16 + m
     {
       const uint16_t* h0c = reinterpret_cast<const uint16_t*>(smem + M::OFF_H0C);
-#pragma unroll(Cfg::DWU1)
+#pragma unroll(HS || BF16 ? Cfg::DWU1 : (Cfg::DWU1 > 2 ? 2 : Cfg::DWU1))
       for (int kc = kc0, kk_ = 0; kk_ < (Cfg::KEXACT ? Cfg::KPW : kc1 - kc0); ++kk_, ++kc) {
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -856,7 +859,8 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
 #pragma unroll
             for (int nt = 0; nt < NTL1; ++nt) {
               const int tap = nt * 16 + m;
-              const u32x4 bb = tap < T ? load8_shift<DIM, L>(h0c, s0, tap, 1) : u32x4{0u, 0u, 0u, 0u};
+              const u32x4 bv = load8_shift<DIM, L>(h0c, s0, tap < T ? tap : 0, 1);  // branch-free
+              const u32x4 bb = tap < T ? bv : u32x4{0u, 0u, 0u, 0u};
               acc1[mt * NTL1 + nt] = mfma(as_bf16x8(a), as_bf16x8(bb), acc1[mt * NTL1 + nt]);
             }
           } else {
@@ -866,12 +870,13 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
               const float a = c < C ? ga1s[LY::template off<C>(px, c)] : 0.f;
 #pragma unroll
               for (int nt = 0; nt < NTL1; ++nt) {
-                const int tap = nt * 16 + m;
-                float bb = 0.f;
-                if (tap < T) {
-                  const float xv = xs[LY::nbr(sx, px, tap, 1)];
-                  bb = (G::parity(sx) ^ todd<DIM>(tap)) == fpar ? xv : 0.f;
-                }
+                // branch-free: columns past the T taps read a valid neighbour and
+                // multiply it by 0 (the field is finite; a select would be turned back
+                // into a branch around the read), so the reads of the unrolled chunks
+                // stay in flight together
+                const int tap = nt * 16 + m, tc = tap < T ? tap : 0;
+                const float xv = xs[LY::nbr(sx, px, tc, 1)];
+                const float bb = xv * (tap < T && (G::parity(sx) ^ todd<DIM>(tc)) == fpar ? 1.f : 0.f);
                 acc1[mt * NTL1 + nt] = mfma(a, bb, acc1[mt * NTL1 + nt]);
               }
             }
