@@ -671,7 +671,8 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
         }
         if constexpr (Cfg::Q8) {
           const int sq = kc * 16 + (lane >> 2), pq = LY::idx(sq), c4 = lane & 3;
-          const float bq = c4 < 2 ? gos_f[2 * LY::nbr(sq, pq, T - 1, -1) + c4] : 0.f;
+          // branch-free: lanes c4 >= 2 read channel c4 - 2 and zero it
+          const float bq = gos_f[2 * LY::nbr(sq, pq, T - 1, -1) + (c4 & 1)] * (c4 < 2 ? 1.f : 0.f);
 #pragma unroll
           for (int g = 0; g < C / 4; ++g) acc8[g] = mfma4(h2s[LY::template off<C>(pq, 4 * g + c4)], bq, acc8[g]);
         }
