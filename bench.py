@@ -624,7 +624,7 @@ def roofline_of(phase, fwd_ms, w, B, prec_name):
     peak = PEAK["fp32_mfma_tflops"] if prec_name == "fp32" else PEAK["bf16_mfma_tflops"]
     if phase["backward"] > fwd_ms:
         name = ("flow_backward (per layer launch)" if w["dim"] == 2 else
-                "flow_backward (per layer: kr_recompute + kr_transpose + kr_wgrad)")
+                "flow_backward (per layer: kr_affine + kr_transpose + kr_wgrad)")
         ms = phase["backward"] / w["n_layers"]
         flops = 2 * fl_flops * B
         traffic = recorded_traffic(prec_name) if w is WORKLOAD else None
