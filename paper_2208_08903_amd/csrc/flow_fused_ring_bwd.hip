@@ -895,7 +895,8 @@ int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved
   hipLaunchKernelGGL((kf_prep<true>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st,
                      params, g.N, g.T, (int)g.P_layer, tab, frags);
   auto ka = kr_recompute<L, C, Cfg::NT_A>;
-  auto kaff = kr_affine<L, 256>;
+  // (512 threads: the fused reduction then reads whole 128-byte lines of every partial row)
+  auto kaff = kr_affine<L, 512>;
   auto kb = kr_transpose<L, C, Cfg::NT_B>;
   auto kc = kr_wgrad<L, C, Cfg::NT_C>;
   if (!set_lds(ka, Cfg::LDS_A) || !set_lds(kb, Cfg::LDS_B) || !set_lds(kc, Cfg::LDS_C))
@@ -923,7 +924,7 @@ int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved
       h2l = reinterpret_cast<const uint16_t*>(hl + rs.h2);
       m1l = reinterpret_cast<const uint32_t*>(hl + rs.m1);
       m2l = reinterpret_cast<const uint32_t*>(hl + rs.m2);
-      hipLaunchKernelGGL(kaff, dim3(grid), dim3(256), 0, st, fpar, g.final_tanh, (float)(-g_logq), g_logq_vec,
+      hipLaunchKernelGGL(kaff, dim3(grid), dim3(512), 0, st, fpar, g.final_tanh, (float)(-g_logq), g_logq_vec,
                          B, xl, gy, reinterpret_cast<const float*>(hl + rs.s), gx, go, partial, P,
                          (int)g.off_b3, prev, prev_out);
     } else {
