@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(NT) kf_forward(
     const u32x4* __restrict__ frags, const float* __restrict__ params, int P_layer, int off_b1,
     int off_b2, int off_b3, int N, int parity0, int final_tanh, int B, const float* __restrict__ z,
     float* __restrict__ phi, float* __restrict__ saved, double* __restrict__ logq,
-    double* __restrict__ logdet, float* __restrict__ hsave) {
+    double* __restrict__ logdet, float* __restrict__ hsave, int off_W1) {
   using Cfg = FwdCfg<DIM, L, C, BF16>;
   using G = Geo<DIM, L>;
   using LY = typename Cfg::LY;
@@ -42,6 +42,10 @@ __global__ void __launch_bounds__(NT) kf_forward(
   HT* h1 = reinterpret_cast<HT*>(smem + ((LY::VSZ * 4 + 15) / 16) * 16);
   HT* h2 = h1 + LY::template elems<C>();
   u32x4* qt = reinterpret_cast<u32x4*>(h2 + LY::template elems<C>());  // FP32: the layer's conv3 A table
+  // C1V: conv1's weights and biases, tap-major (the first layer's staged here, the
+  // next layer's during conv3; visible after the layer-start barrier)
+  float* w1t = reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(qt) + Cfg::QT_BYTES);
+  if constexpr (Cfg::C1V) stage_w1t<C, NT>(w1t, params, off_W1, off_b1);
   for (int q = threadIdx.x; q < C; q += NT) h1[LY::template off<C>(LY::ZS, q)] = 0, h2[LY::template off<C>(LY::ZS, q)] = 0;
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
   const size_t BV = (size_t)B * V;
@@ -99,7 +103,7 @@ __global__ void __launch_bounds__(NT) kf_forward(
         }
       };
       if constexpr (Cfg::PFA) {
-        load_a1();
+        if constexpr (!Cfg::C1V) load_a1();
         load_a2();
       }
       // conv1 operands: row triples of the masked field, built in the (dead) h2
@@ -109,7 +113,9 @@ __global__ void __launch_bounds__(NT) kf_forward(
         __syncthreads();
       }
       // conv1 over all sites
-      {
+      if constexpr (Cfg::C1V) {
+        conv1_valu<LY, C, NT>(xs, h1, w1t, fpar);
+      } else {
         if constexpr (!Cfg::PFA) load_a1();
         f32x4 bias[LF.nct];
 #pragma unroll
@@ -175,6 +181,8 @@ __global__ void __launch_bounds__(NT) kf_forward(
       }
       // conv3 at the active sites, affine update and log-det
       if constexpr (!Cfg::PFA) load_a3();
+      if constexpr (Cfg::C1V)  // the next layer's (or next sample's first) conv1 weights
+        stage_w1t<C, NT>(w1t, params + (size_t)(layer + 1 < N ? layer + 1 : 0) * P_layer, off_W1, off_b1);
       if constexpr (Cfg::Q3) {
         // FP32: 64 active sites per wave pass, one per lane, on the 4x4 blocks; every
         // lane updates its own site
@@ -298,7 +306,7 @@ int32_t launch_forward(const FlowGeom& g, const float* params, int B, const floa
   hipLaunchKernelGGL(kern, dim3(B), dim3(Cfg::NT), Cfg::lds_bytes, st, frags, params,
                      (int)g.P_layer, (int)g.off_b1, (int)g.off_b2, (int)g.off_b3, g.N, g.parity0,
                      g.final_tanh, B, z, phi, saved, logq, logdet,
-                     HSave<DIM, L, C, BF16>::ok ? hsave : nullptr);
+                     HSave<DIM, L, C, BF16>::ok ? hsave : nullptr, (int)g.off_W1);
   return launch_status();
 }
 

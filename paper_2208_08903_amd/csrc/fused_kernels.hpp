@@ -273,6 +273,62 @@ __device__ __forceinline__ u32x2 store_hidden(HElem<BF16>* h, int n, int ct, int
   return store4<LY, C, BF16>(h, n, co0, v);
 }
 
+// conv1 on the vector ALUs (FP32, 2D, 3x3 taps): h1 = leaky(W1 * mask_F x + b1) at
+// every site, each thread on one active and one frozen site per step.  The masked
+// field is nonzero only at the frozen sites, so an active site sees just its four
+// axis neighbours and a frozen site itself and its four diagonal neighbours: the
+// other taps' zeros are skipped rather than multiplied.  Each output sums the bias,
+// then the taps in increasing order.  Only the interior copy is written (a padded
+// layout's halo is filled afterwards).  wt: the layer's weights and biases staged
+// tap-major in LDS (stage_w1t), read by every lane at the same address (broadcast).
+constexpr int w1t_floats(int C) { return 10 * C; }
+
+// [9][C] weights (tap-major) then [C] biases of the first convolution, into LDS
+template <int C, int NT>
+__device__ __forceinline__ void stage_w1t(float* wt, const float* __restrict__ pl, int off_W1, int off_b1) {
+  for (int i = threadIdx.x; i < 10 * C; i += NT) {
+    const int t = i / C, co = i - t * C;
+    wt[i] = t < 9 ? pl[off_W1 + co * 9 + t] : pl[off_b1 + co];
+  }
+}
+
+template <class LY, int C, int NT>
+__device__ __forceinline__ void conv1_valu(const float* xs, float* h1, const float* wt, int fpar) {
+  using G = typename LY::G;
+  static_assert(G::Dim == 2 && G::T == 9 && C % 4 == 0, "2D lattice, 3x3 taps, channel quads");
+  constexpr int taps_f[5] = {0, 2, 4, 6, 8}, taps_a[4] = {1, 3, 5, 7};
+  const f32x4* wt4 = reinterpret_cast<const f32x4*>(wt);
+  for (int a = threadIdx.x; a < G::V / 2; a += NT) {
+    const int na = G::half_site(a, fpar ^ 1), nf = G::half_site(a, fpar);
+    const int pa = LY::idx(na), pf = LY::idx(nf);
+    float va[4], vf[5];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) va[i] = xs[LY::nbr(na, pa, taps_a[i], 1)];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) vf[i] = xs[LY::nbr(nf, pf, taps_f[i], 1)];
+#pragma unroll
+    for (int q = 0; q < C / 4; ++q) {
+      // the quad's nine tap weights and its biases, all read before the sums
+      f32x4 w[10];
+#pragma unroll
+      for (int t = 0; t < 10; ++t) w[t] = wt4[t * (C / 4) + q];
+      f32x4 sa = w[9], sf = w[9];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sa[r] += w[taps_a[i]][r] * va[i];
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sf[r] += w[taps_f[i]][r] * vf[i];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sa[r] = leaky(sa[r]), sf[r] = leaky(sf[r]);
+      *reinterpret_cast<f32x4*>(h1 + LY::template off<C>(pa, 4 * q)) = sa;
+      *reinterpret_cast<f32x4*>(h1 + LY::template off<C>(pf, 4 * q)) = sf;
+    }
+  }
+}
+
 // Four channels co0..co0+3 (BF16 pairs in hv) of site n of a channel-major tensor.
 template <int C, int V>
 __device__ __forceinline__ void store_cm_global(uint16_t* t, int n, int co0, const u32x2& hv) {
@@ -420,10 +476,15 @@ struct FwdCfg {
   static constexpr size_t QT_BYTES = BF16 ? 0 : (size_t)(T * C / 4) * 4 * 16;
   // FP32 2D L = 32: activations quad-major (conflict-free gathers and stores)
   static constexpr bool QM = !BF16 && DIM == 2 && L == 32;
+  // FP32 2D L = 32: conv1 on the vector ALUs (conv1_valu: forward 0.948 -> 0.907 ms per
+  // training step), its weights in an LDS table after conv3's (the next layer's staged
+  // during conv3).  The backward keeps its matrix-core conv1, which was faster there.
+  static constexpr bool C1V = !BF16 && DIM == 2 && L == 32;
+  static constexpr size_t W1T_BYTES = C1V ? (size_t)w1t_floats(C) * 4 : 0;
   template <class LYX>
   static constexpr size_t bytes_of() {
     return ((size_t)LYX::VSZ * 4 + 15) / 16 * 16 + 2 * (size_t)LYX::template elems<C>() * sizeof(HElem<BF16>) +
-           QT_BYTES;
+           QT_BYTES + W1T_BYTES;
   }
   static constexpr bool PAD = bytes_of<Lay<DIM, L, true, QM>>() <= 156 * 1024;
   using LY = Lay<DIM, L, PAD, QM>;

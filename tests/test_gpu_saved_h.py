@@ -10,8 +10,9 @@ samples:
   - the saved h2 of every layer and sample equals the oracle's h2 of that layer's
     input field within 1e-5 (1 + |h2|) (FP32 sums of 9 and 144 terms);
   - the backward equals the recomputing backward within 1e-6 relative (measured:
-    bitwise), and at a small batch the oracle within the FP32 bounds of the parity
-    tests;
+    1e-7; the forward's conv1 runs on the vector ALUs and sums in another order than
+    the recomputing backward's matrix-core conv1), and at a small batch the oracle
+    within the FP32 bounds of the parity tests;
   - scalar and per-sample log q cotangents give the same bits;
   - on a shape without a saved layout the pair reports 0 bytes and falls back to
     the plain entry points' results.
