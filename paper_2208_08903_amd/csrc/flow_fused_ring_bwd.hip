@@ -668,9 +668,11 @@ __global__ void __launch_bounds__(NT) kr_wgrad(
   using G = typename Cfg::G;
   constexpr int V = Cfg::V, PLANE = Cfg::PLANE, T = Cfg::T, RT = Cfg::RT, NW = NT / 64;
   static_assert(L == 16, "rows of two 8-site halves");
-  // dW2 jobs: (row tile of ci, row offset (dz, dy), 16 channels co): the three
-  // x offsets share the A operand and the two loads of the source row
-  constexpr int NCO = C / 16, J2 = RT * 9 * NCO, JS2 = (J2 + NW - 1) / NW;
+  // dW2 jobs: (row offset (dz, dy), 16 channels co), each over every row tile of ci:
+  // the three x offsets and the row tiles share the two loads of the source row (the
+  // dW2 pass is bound by LDS reads: 4 KB per six MFMAs at C = 32, 6 KB when the row
+  // tiles were separate jobs)
+  constexpr int NCO = C / 16, J2 = 9 * NCO, JS2 = (J2 + NW - 1) / NW;
   // single tiles: dW3 (row tile, 16 (tap, co) columns), then dW1 (row tile, 16 taps)
   constexpr int N3 = Cfg::N3, J31 = Cfg::N3 + Cfg::N1, JS31 = (J31 + NW - 1) / NW;
   constexpr int CS = Cfg::CS;
@@ -685,9 +687,11 @@ __global__ void __launch_bounds__(NT) kr_wgrad(
   uint16_t* rh0 = rgo + 3 * 2 * CS;                    // mask_F x ring [3][PLANE]
   const int lane = threadIdx.x & 63, w = wave_id(), j = lane >> 4, m = lane & 15;
   const int h = j & 1, jr = j >> 1;  // the lane's half row and row within a K chunk
-  f32x4 acc2[JS2][3], acc31[JS31];
+  f32x4 acc2[JS2][RT][3], acc31[JS31];
 #pragma unroll
-  for (int k = 0; k < JS2; ++k) acc2[k][0] = acc2[k][1] = acc2[k][2] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < JS2; ++k)
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) acc2[k][rt][0] = acc2[k][rt][1] = acc2[k][rt][2] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int k = 0; k < JS31; ++k) acc31[k] = f32x4{0.f, 0.f, 0.f, 0.f};
 
@@ -768,19 +772,22 @@ __global__ void __launch_bounds__(NT) kr_wgrad(
       for (int k = 0; k < JS2; ++k) {
         const int id = k * NW + w;
         if (id < J2) {
-          const int rt = id % RT, r9 = id / RT % 9, cot = id / (RT * 9);
+          const int r9 = id % 9, cot = id / 9;
           const int dz = r9 / 3 - 1, dy = r9 % 3 - 1;
           const uint16_t* src = rg2 + (mod3(z - dz) * C + cot * 16 + m) * CS;
-          const uint16_t* ap = pa1 + (rt * 16 + m) * CS + 8 * j;
 #pragma unroll 2
           for (int c = 0; c < PLANE / 32; ++c) {
-            const bf16x8 a = as_bf16x8(*reinterpret_cast<const u32x4*>(ap + 32 * c));
             const uint16_t* row = src + ((2 * c + jr - dy) & (L - 1)) * L;
             const u32x4 p = *reinterpret_cast<const u32x4*>(row + 8 * h);
             const u32x4 o = *reinterpret_cast<const u32x4*>(row + 8 - 8 * h);
-            acc2[k][0] = mfma(a, as_bf16x8(shift_p1(p, o)), acc2[k][0]);  // dx = -1: x + 1
-            acc2[k][1] = mfma(a, as_bf16x8(p), acc2[k][1]);
-            acc2[k][2] = mfma(a, as_bf16x8(shift_m1(p, o)), acc2[k][2]);  // dx = +1: x - 1
+            const bf16x8 bp = as_bf16x8(shift_p1(p, o)), b0 = as_bf16x8(p), bm = as_bf16x8(shift_m1(p, o));
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+              const bf16x8 a = as_bf16x8(*reinterpret_cast<const u32x4*>(pa1 + (rt * 16 + m) * CS + 8 * j + 32 * c));
+              acc2[k][rt][0] = mfma(a, bp, acc2[k][rt][0]);  // dx = -1: x + 1
+              acc2[k][rt][1] = mfma(a, b0, acc2[k][rt][1]);
+              acc2[k][rt][2] = mfma(a, bm, acc2[k][rt][2]);  // dx = +1: x - 1
+            }
           }
         }
       }
@@ -816,12 +823,14 @@ __global__ void __launch_bounds__(NT) kr_wgrad(
   for (int k = 0; k < JS2; ++k) {
     const int id = k * NW + w;
     if (id < J2) {
-      const int rt = id % RT, r9 = id / RT % 9, cot = id / (RT * 9), co = cot * 16 + m;
+      const int r9 = id % 9, cot = id / 9, co = cot * 16 + m;
 #pragma unroll
-      for (int dxi = 0; dxi < 3; ++dxi)
+      for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          out[off_W2 + (co * C + rt * 16 + 4 * j + i) * T + 3 * r9 + dxi] = acc2[k][dxi][i];
+        for (int dxi = 0; dxi < 3; ++dxi)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            out[off_W2 + (co * C + rt * 16 + 4 * j + i) * T + 3 * r9 + dxi] = acc2[k][rt][dxi][i];
     }
   }
 #pragma unroll
