@@ -4,12 +4,14 @@
 // fused_common.hpp).  Paper Sec. 1, coupling-layer and composition equations.
 //
 // Per layer l (frozen parity f = (l + parity0) mod 2, active parity 1 - f):
-//   conv1: h1 = leaky(W1 * mask_F x + b1)   over all V sites   (K = T taps)
+//   conv1: h1 = leaky(W1 * mask_F x + b1)   over all V sites   (K = T taps; FP32 2D
+//          L = 32 on the vector ALUs, see conv1_valu)
 //   conv2: h2 = leaky(W2 * h1 + b2)         over all V sites   (K = T C)
 //   conv3: (o0, o1) = W3 * h2 + b3          at the V/2 active sites only (FP32: on the
 //          4x4 matrix-core blocks, see quad_conv)
 //          x <- x exp(s) + t, s = tanh(o0) (or o0), t = o1; logdet += sum s
-// Three workgroup barriers per layer separate the phases.
+// Three workgroup barriers per layer separate the phases.  The training forward
+// (FP32 2D L = 32) also writes h2 and s for the backward (HSave).
 #include <type_traits>
 
 #include "fused_kernels.hpp"

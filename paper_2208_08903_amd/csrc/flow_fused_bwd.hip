@@ -5,7 +5,9 @@
 //
 //   recompute  h1 = leaky(W1 * mask_F x + b1), h2 = leaky(W2 * h1 + b2),
 //              (o0, o1) = W3 * h2 + b3 at the active sites, s = tanh(o0), t = o1
-//              (FP32: conv3 and conv1^T on the 4x4 matrix-core blocks, quad_conv)
+//              (FP32: conv3 and conv1^T on the 4x4 matrix-core blocks, quad_conv;
+//              in training at 2D L = 32 h2 and s come from the forward's saved
+//              copies instead, HS)
 //   affine     g_t = g_y, g_s = g_y x e^s + g_logdet, g_o0 = g_s (1 - s^2),
 //              g_x(active) = g_y e^s
 //   conv3^T    g_a2 = leaky'(h2) (W3^T * g_o)        dW3 += g_o (x) h2

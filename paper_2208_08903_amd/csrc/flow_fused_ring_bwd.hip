@@ -20,6 +20,9 @@
 //              of three planes (a +-1 shift along the 16-site rows is a funnel
 //              shift of the row's two 8-site halves, periodic).
 //
+// In training the forward saves h1, h2, their sign words and s (RingSave), and a
+// fourth kernel, the element-wise affine backward, takes the recompute's place.
+//
 // The three kernels run on the same grid, each workgroup looping over the same
 // samples, and write disjoint slots of one partial per workgroup; the
 // fixed-order reduction then sums the partials, so the gradient is bitwise
@@ -888,7 +891,8 @@ int32_t rb_run(const FlowGeom& g, const float* params, int B, const float* saved
     return r;
   };
   u32x4* frags = reinterpret_cast<u32x4*>(take((size_t)Cfg::FRAGS * 64 * 16 * g.N));
-  // two partial buffers: a layer's recompute reduces the previous layer's partials
+  // two partial buffers: a layer's first launch (recompute or affine backward)
+  // reduces the previous layer's partials
   float* partials[2] = {reinterpret_cast<float*>(take((size_t)grid * Cfg::P_LAYER * 4)),
                         reinterpret_cast<float*>(take((size_t)grid * Cfg::P_LAYER * 4))};
   float* gbuf[2] = {reinterpret_cast<float*>(take(BV * 4)), reinterpret_cast<float*>(take(BV * 4))};
