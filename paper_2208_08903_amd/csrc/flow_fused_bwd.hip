@@ -159,10 +159,13 @@ struct BwdCfg {
   static constexpr int DWU3 = DWX && BF16 ? 4 : 1, DWU1 = DWX ? 4 : 1;
   // Weight-gradient output tiles; every wave accumulates all of them over its
   // contiguous range of K chunks, and the waves are summed in a fixed order.
-  // FP32 2D: dW3's last tap (columns 16 and 17 of 18) on the 4x4 blocks (Q8), so its
-  // 16x16x4 tiles cover the first sixteen columns only
-  static constexpr bool Q8 = !BF16 && DIM == 2 && 2 * T == 18 && C % 4 == 0;
-  static constexpr int NTL3 = Q8 ? 1 : (2 * T + 15) / 16, NTL1 = (T + 15) / 16;
+  // FP32 2D (PS3): g_o is zero at the frozen sites, so in conv3^T and dW3 an active
+  // site meets it only through the five taps of even |delta|_1 and a frozen site
+  // only through the four odd ones: both passes run the two halves of the sites
+  // apart, each with its own taps (dW3: one tile per half, columns (tap, co) of
+  // that half's taps; conv3^T: K = 10 and 8 instead of 18).
+  static constexpr bool PS3 = !BF16 && DIM == 2 && T == 9;
+  static constexpr int NTL3 = PS3 ? 2 : (2 * T + 15) / 16, NTL1 = (T + 15) / 16;
   static constexpr int I3 = MT * NTL3;
   static constexpr int I2 = MT * T * MT;
   static constexpr int I1 = MT * NTL1;
@@ -346,13 +349,6 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
 
   constexpr int NTL3 = Cfg::NTL3, NTL1 = Cfg::NTL1;
   f32x4 acc3[Cfg::I3], acc2[Cfg::I2], acc1[Cfg::I1];
-  // Q8: block b (lanes 4b .. 4b + 3) of a 4x4 MFMA takes site 16 kc + b; lane 4b + r gives
-  // h2 channel 4g + r (A) and lane 4b + c the last tap's g_o channel c (B, c < 2), and lane
-  // 4b + c receives D[4g + r][c] in register r: block-wise partial sums, added over the
-  // blocks after the sample loop
-  f32x4 acc8[Cfg::Q8 ? C / 4 : 1];
-#pragma unroll
-  for (int g = 0; g < (Cfg::Q8 ? C / 4 : 1); ++g) acc8[g] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < Cfg::I3; ++i) acc3[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -640,6 +636,34 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
     // FP32 and SPLIT write g_a2 over h2, which dW3 reads, so dW3 goes first; the
     // other BF16 layouts keep them apart and run dW3 after conv3^T, next to g_a2's
     // halo fill.
+    // PS3: the two halves of the sites (kind 0: active, kind 1: frozen), 16-site
+    // chunks of each split evenly over the waves; column m of tile (mt, kind) is
+    // (tap, co) = (2 (m >> 1) + kind, m & 1)
+    auto dw3_ps = [&]() {
+      constexpr int KH = V / 32;
+      static_for<0, 2>([&](auto KIND) {
+        constexpr int kind = decltype(KIND)::value;
+        const int par = apar ^ kind;
+        const int tap = 2 * (m >> 1) + kind, co = m & 1;
+        const bool tv = tap < T;
+        const int tc = tv ? tap : kind;
+        const float tm = tv ? 1.f : 0.f;
+#pragma unroll 1
+        for (int kc = w * KH / NW; kc < (w + 1) * KH / NW; ++kc) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int sx = G::half_site(kc * 16 + 4 * j + r, par), px = LY::idx(sx);
+            const float bb = load1_shift<LY, 2>(gos_f, sx, co, tc, -1) * tm;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+              const int ci = mt * 16 + m;
+              const float a = ci < C ? h2s[LY::template off<C>(px, ci)] : 0.f;
+              acc3[mt * 2 + kind] = mfma(a, bb, acc3[mt * 2 + kind]);
+            }
+          }
+        }
+      });
+    };
     auto dw3 = [&]() {
 #pragma unroll(Cfg::DWU3)
       for (int kc = kc0, kk_ = 0; kk_ < (Cfg::KEXACT ? Cfg::KPW : kc1 - kc0); ++kk_, ++kc) {
@@ -671,16 +695,12 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
             }
           }
         }
-        if constexpr (Cfg::Q8) {
-          const int sq = kc * 16 + (lane >> 2), pq = LY::idx(sq), c4 = lane & 3;
-          // branch-free: lanes c4 >= 2 read channel c4 - 2 and zero it
-          const float bq = gos_f[2 * LY::nbr(sq, pq, T - 1, -1) + (c4 & 1)] * (c4 < 2 ? 1.f : 0.f);
-#pragma unroll
-          for (int g = 0; g < C / 4; ++g) acc8[g] = mfma4(h2s[LY::template off<C>(pq, 4 * g + c4)], bq, acc8[g]);
-        }
       }
     };
-    if constexpr (!BF16 || Cfg::SPLIT) {
+    if constexpr (Cfg::PS3) {
+      dw3_ps();
+      __syncthreads();
+    } else if constexpr (!BF16 || Cfg::SPLIT) {
       dw3();
       __syncthreads();
     }
@@ -689,7 +709,48 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
     HT* ga2s = BF16 && !Cfg::SPLIT ? reinterpret_cast<HT*>(smem + M::OFF_S2) : h2s;
     uint16_t* ga2c = reinterpret_cast<uint16_t*>(smem + M::OFF_S3);
     if constexpr (Cfg::SPLIT) build_h0c();  // over g_o's channel-major rows, dead after dW3
-    {
+    if constexpr (Cfg::PS3) {
+      // the active half's tiles with the even taps (MFMA r: k = 4 r + j, (tap, co) =
+      // (2 (2 r + (j >> 1)) + kind, j & 1); k < 10: three MFMAs), then the frozen
+      // half's with the odd taps (k < 8: two)
+      const f32x4 zero[LF.nct] = {};
+      static_for<0, 2>([&](auto KIND) {
+        constexpr int kind = decltype(KIND)::value;
+        const int par = apar ^ kind;
+        u32x4 A[LF.nct][1];
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct) A[ct][0] = fr[(Cfg::OFF3T + ct * Cfg::KT3 + kind) * 64];
+        mma_tiles<Cfg::TU, LF.nct, 1, false, kind ? 2 : 3>(
+            V / 32, w, NW, A, zero,
+            [&](int tile, int) {
+              const int n = G::half_site(tile * 16 + m, par), p = LY::idx(n);
+              u32x4 bop;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int t = 2 * (2 * r + (j >> 1)) + kind;
+                const int nb = t < T ? LY::nbr(n, p, t, -1) : LY::ZS;
+                bop[r] = __float_as_uint(gos_f[2 * nb + (j & 1)]);
+              }
+              return bop;
+            },
+            [&](int tile, const f32x4(&acc)[LF.nct]) {
+              const int p = LY::idx(G::half_site(tile * 16 + m, par));
+#pragma unroll
+              for (int ct = 0; ct < LF.nct; ++ct) {
+                const int c0 = ct * 16 + 4 * j;
+                if (c0 < C) {
+                  const f32x4 hh = *reinterpret_cast<const f32x4*>(h2s + LY::template off<C>(p, c0));
+                  f32x4 v;
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) v[i] = acc[ct][i] * leaky_grad_from_out(hh[i]);
+                  *reinterpret_cast<f32x4*>(ga2s + LY::template off<C>(p, c0)) = v;
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) db2[ct][i] += v[i];
+                }
+              }
+            });
+      });
+    } else {
       u32x4 A[LF.nct][Cfg::KT3];
 #pragma unroll
       for (int ct = 0; ct < LF.nct; ++ct)
@@ -843,7 +904,11 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
           });
     }
     __syncthreads();
-    load_h2(b + gridDim.x);  // S1 (g_a2) is dead from here on
+    // S1 (g_a2) is dead from here on.  The vector-memory loads still in flight
+    // (weight fragments) are waited for before the copy is issued: a later wait
+    // for any of them would otherwise also wait for the whole copy.
+    if constexpr (HS) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    load_h2(b + gridDim.x);
     // g_a1's halo (for conv1^T's gathers) is filled alongside dW1, which reads
     // interior sites only
     fill_halo<LY, C, BF16, NT>(ga1s);
@@ -953,15 +1018,6 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
       }
   db3s = wave_sum(db3s);
   db3t = wave_sum(db3t);
-  if constexpr (Cfg::Q8) {
-    // the 16 blocks' partial sums of the last tap's columns, fixed xor order
-#pragma unroll
-    for (int g = 0; g < C / 4; ++g)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int o = 4; o < 64; o <<= 1) acc8[g][i] += __shfl_xor(acc8[g][i], o, 64);
-  }
   __syncthreads();
   for (int ww = 0; ww < NW; ++ww) {
     if (w == ww) {
@@ -969,7 +1025,8 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NTL3; ++nt) {
-          const int col = nt * 16 + m, tap = col >> 1, co = col & 1;
+          const int col = nt * 16 + m, co = col & 1;
+          const int tap = Cfg::PS3 ? 2 * (m >> 1) + nt : col >> 1;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int ci = mt * 16 + 4 * j + i;
@@ -1016,14 +1073,6 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
       if (lane == 0) {
         red[off_b3] += db3s;
         red[off_b3 + 1] += db3t;
-      }
-      if constexpr (Cfg::Q8) {
-        if (lane < 2) {
-#pragma unroll
-          for (int g = 0; g < C / 4; ++g)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) red[off_W3 + (lane * C + 4 * g + i) * T + (T - 1)] += acc8[g][i];
-        }
       }
     }
     __syncthreads();

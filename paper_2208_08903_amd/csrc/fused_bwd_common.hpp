@@ -97,7 +97,9 @@ inline FragTable bwd_table(const FlowGeom& g, bool bf16, bool x4, bool quad = fa
   if (lf.x4)
     for (int u = 1; u < 4; ++u)
       t.s[n++] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, lf.k2, lf.off3q + (u - 1) * lf.k2, 0, 4 * u, 0};
-  t.s[n++] = FragSpec{1, (int)g.off_W3, C, 2, C, lf.nct, kt3, lf.total, 0, 0, 0};
+  // FP32 2D: conv3^T by site parity (one chunk per parity of the taps)
+  const int ps = !bf16 && T == 9 ? 1 : 0;
+  t.s[n++] = FragSpec{1, (int)g.off_W3, C, 2, C, lf.nct, kt3, lf.total, 0, 0, 0, ps};
   t.s[n++] = FragSpec{1, (int)g.off_W2, C, C, C, lf.nct, lf.k2, lf.total + lf.nct * kt3, 0, 0, 0};
   t.s[n++] = FragSpec{1, (int)g.off_W1, 1, C, 1, 1, k1t, lf.total + lf.nct * kt3 + lf.nct * lf.k2, 0, 0, q};
   t.count = n;

@@ -20,6 +20,9 @@ namespace fused {
 // k = 4c .. 4c + 3 (each of the 16 blocks of 4 lanes has the same A).
 struct FragSpec {
   int transposed, woff, cin, cout, rows, nct, nk, off, tri, shift, quad;
+  // psplit (FP32, 2D): chunk c holds the taps t = 2 i + c (those of one parity of
+  // |delta_t|_1) and MFMA r of the chunk takes k = 4 r + j (its k = i kdiv + ch)
+  int psplit;
 };
 constexpr int kMaxSpecs = 9;
 struct FragTable {
@@ -61,6 +64,14 @@ __global__ void kf_prep(const float* __restrict__ params, int N, int T, int P_la
   if constexpr (BF16) {
     const int k0 = 32 * c + 8 * j;
     for (int q = 0; q < 4; ++q) out[q] = pack_bf16(w_at(k0 + 2 * q), w_at(k0 + 2 * q + 1));
+  } else if (sp.psplit) {
+    for (int q = 0; q < 4; ++q) {
+      const int kk = 4 * q + j, tap = 2 * (kk / kdiv) + c, ch = kk % kdiv;
+      const bool ok = row >= 0 && row < sp.rows && tap < T;
+      out[q] = __float_as_uint(!ok ? 0.f
+                               : sp.transposed ? W[(ch * sp.cin + row) * T + tap]
+                                               : W[(row * sp.cin + ch) * T + tap]);
+    }
   } else {
     const int k0 = sp.quad ? 4 * c : 16 * c + 4 * j;
     for (int q = 0; q < 4; ++q) out[q] = __float_as_uint(w_at(k0 + q));
