@@ -107,7 +107,11 @@ struct BwdCfg {
   using LY = typename M::LY;
   static constexpr int CSTR = M::CSTR;
   // LDS of the sample state (and, after the sample loop, of the partial sums)
-  static constexpr size_t lds_main = cmaxz(M::MAIN + (BF16 ? 0 : 16 + (size_t)(T * C / 4) * 2 * 4 * 16),
+  // with saved activations: conv1's A fragments in LDS too (staged once per
+  // launch), so that no global load waits behind the asynchronous h2 copy
+  static constexpr bool A1L = HSave<DIM, L, C, BF16>::ok;
+  static constexpr size_t A1_BYTES = A1L ? (size_t)((C + 15) / 16) * kblocks_f32(k_tri(T)) * 64 * 16 : 0;
+  static constexpr size_t lds_main = cmaxz(M::MAIN + (BF16 ? 0 : 16 + (size_t)(T * C / 4) * 2 * 4 * 16) + A1_BYTES,
                                            (size_t)P_LAYER * 4);
   // 3D shapes need more than the 256 registers a lane gets at 2 waves per SIMD.
   static constexpr int NT = (lds_main > 80 * 1024 && DIM == 2) ? 512 : 256;
@@ -140,7 +144,8 @@ struct BwdCfg {
   // chunk), staged in LDS once per launch after the sample state
   static constexpr size_t OFF_QT = align16(M::MAIN);
   static constexpr size_t QT_BYTES = BF16 ? 0 : (size_t)(LF.k3 + K1T) * 4 * 16;
-  static constexpr size_t OFF_FRAG = align16(OFF_QT + QT_BYTES);
+  static constexpr size_t OFF_A1 = align16(OFF_QT + QT_BYTES);
+  static constexpr size_t OFF_FRAG = align16(OFF_A1 + A1_BYTES);
   static constexpr int per_cu(size_t bytes) { return bytes > 160 * 1024 ? 0 : cmin(8, (int)(160 * 1024 / bytes)); }
   static constexpr bool FRAG_LDS = OFF_FRAG + FRAG_BYTES + RED_STATIC <= 158 * 1024 &&
                                    per_cu(OFF_FRAG + FRAG_BYTES + RED_STATIC) == per_cu(lds_main + RED_STATIC);
@@ -274,6 +279,13 @@ __device__ __forceinline__ void load_h2_async(const unsigned char* src, unsigned
   }
 }
 
+// Workgroup barrier over LDS only: waits for the wave's LDS operations but not
+// for its vector-memory ones, so that the asynchronous copy of the next sample's
+// h2 stays in flight across it (a fenced barrier waits for it: the copy writes
+// LDS).  Used only between passes that neither read the copy's destination nor
+// exchange global memory.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // ---- the kernel -------------------------------------------------------------
 
 // HS: h2 and s are read from the training forward's saved copies (hsv, this
@@ -319,6 +331,12 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
       q[i] = frags[(c < LF.k3 ? LF.off3 + c : Cfg::OFF1T + c - LF.k3) * 64 + (i & 3)];
     }
   }
+  const u32x4* a1s = reinterpret_cast<const u32x4*>(smem + Cfg::OFF_A1);
+  if constexpr (Cfg::A1L) {
+    static_assert(Cfg::A1_BYTES == (size_t)LF.nct * LF.k1 * 64 * 16, "conv1 fragments");
+    u32x4* a1 = reinterpret_cast<u32x4*>(smem + Cfg::OFF_A1);
+    for (int i = threadIdx.x; i < LF.nct * LF.k1 * 64; i += NT) a1[i] = frags[LF.off1 * 64 + i];
+  }
 
   // The extra zero site of the site-major slots and of g_o: cleared once, never
   // written afterwards (every later store goes to a lattice site or its mirror).
@@ -345,7 +363,6 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
       if (bb < B) load_h2_async<HSv, NW>(hsv + (size_t)bb * HSv::sample_bytes, smem + M::OFF_S1, LY::QSZ * 4, w, lane);
     }
   };
-  load_h2(blockIdx.x);
 
   constexpr int NTL3 = Cfg::NTL3, NTL1 = Cfg::NTL1;
   f32x4 acc3[Cfg::I3], acc2[Cfg::I2], acc1[Cfg::I1];
@@ -403,6 +420,11 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
   }
   // the previous launch's (next layer's) weight gradient, while the prefetch is in flight
   if (prev_partial) grid_reduce<NT>(prev_partial, prev_out, n_parts, Cfg::P_LAYER);
+  // the first sample's h2, issued once the prefetched values have landed (the
+  // reduction above has waited for them already where it ran), so that staging
+  // them does not wait for the copy
+  if constexpr (HS) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  load_h2(blockIdx.x);
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     // Weight fragments are reloaded per phase (from LDS, or L1/L2 hits) rather than
@@ -427,7 +449,10 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
       for (int q = threadIdx.x; q < V / 4; q += NT)
         reinterpret_cast<f32x4*>(gys)[q] = reinterpret_cast<const f32x4*>(gy + sb)[q];
     }
-    __syncthreads();
+    if constexpr (HS)
+      lds_barrier();
+    else
+      __syncthreads();
     // masked field, channel-major, for dW1 (SPLIT: built after dW3, over g_o's rows)
     auto build_h0c = [&]() {
       uint16_t* h0c = reinterpret_cast<uint16_t*>(smem + M::OFF_H0C);
@@ -449,7 +474,8 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
       for (int ct = 0; ct < LF.nct; ++ct) {
         bias1[ct] = HB ? hb1[ct] : load_bias4<C>(pl + off_b1, ct, j);
 #pragma unroll
-        for (int c = 0; c < LF.k1; ++c) A[ct][c] = fr[(LF.off1 + ct * LF.k1 + c) * 64];
+        for (int c = 0; c < LF.k1; ++c)
+          A[ct][c] = Cfg::A1L ? a1s[(ct * LF.k1 + c) * 64 + lane] : fr[(LF.off1 + ct * LF.k1 + c) * 64];
       }
       mma_tiles<Cfg::TU, LF.nct, LF.k1, BF16, k_tri(T), true>(
           V / 16, w, NW, A, bias1,
@@ -999,7 +1025,10 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
     }
     // SPLIT: the next sample's staging writes only the field, which the tail passes
     // (dW1, conv1^T) do not read; its first barrier comes before any other write
-    if constexpr (!Cfg::SPLIT) __syncthreads();
+    if constexpr (HS)
+      lds_barrier();
+    else if constexpr (!Cfg::SPLIT)
+      __syncthreads();
   }
   if constexpr (Cfg::SPLIT) __syncthreads();  // the partial sums below overwrite the sample state
 
