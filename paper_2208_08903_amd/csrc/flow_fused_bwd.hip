@@ -110,7 +110,8 @@ struct BwdCfg {
   // with saved activations: conv1's A fragments in LDS too (staged once per
   // launch), so that no global load waits behind the asynchronous h2 copy
   static constexpr bool A1L = HSave<DIM, L, C, BF16>::ok;
-  static constexpr size_t A1_BYTES = A1L ? (size_t)((C + 15) / 16) * kblocks_f32(k_tri(T)) * 64 * 16 : 0;
+  static constexpr size_t A1_BYTES =
+      A1L ? (size_t)((C + 15) / 16) * (!BF16 && DIM == 2 ? 2 : kblocks_f32(k_tri(T))) * 64 * 16 : 0;
   static constexpr size_t lds_main = cmaxz(M::MAIN + (BF16 ? 0 : 16 + (size_t)(T * C / 4) * 2 * 4 * 16) + A1_BYTES,
                                            (size_t)P_LAYER * 4);
   // 3D shapes need more than the 256 registers a lane gets at 2 waves per SIMD.
@@ -128,7 +129,11 @@ struct BwdCfg {
   static constexpr int QU3 = !(T == 9 && BF16) ? 1 : (NT == 256 && !SPLIT && TPW3 >= 4) ? 4 : (TPW3 >= 2 ? 2 : 1);
   // FP32: conv3 (recompute) and conv1^T (one output channel) on the 4x4 matrix-core
   // blocks (quad fragments), every lane with its own site's result
-  static constexpr LayerFrags LF = layer_frags(T, C, BF16, QU3 == 4, !BF16);
+  // FP32 2D (PS1): conv1 by site parity -- a frozen site meets the masked field
+  // only through the five taps of even |delta|_1, an active site only through the
+  // four odd ones (K = 5 and 4 instead of the nine taps' row triples)
+  static constexpr bool PS1 = !BF16 && DIM == 2 && T == 9;
+  static constexpr LayerFrags LF = layer_frags(T, C, BF16, QU3 == 4, !BF16, PS1);
   static constexpr int K1T = BF16 ? LF.k2 : T * C / 4;  // conv1^T fragments
   static constexpr int OFF3T = LF.total;
   static constexpr int OFF2T = OFF3T + LF.nct * KT3;
@@ -462,12 +467,53 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
     if constexpr (BF16 && !Cfg::SPLIT) build_h0c();
     // conv1 operands (row triples of the masked field) in the (not yet written) h2
     // slot; HS: gathered from the field by every tile
-    if constexpr (!HS) {
+    if constexpr (!HS && !Cfg::PS1) {
       build_tri<LY, BF16, NT>(h2s, xs, fpar);
       __syncthreads();
     }
     // ---- recompute conv1 -> h1 ----
-    {
+    if constexpr (Cfg::PS1) {
+      // the frozen half's tiles with the even taps, then the active half's with the
+      // odd ones: fragment block c holds the taps 2 i + c, MFMA r takes k = 4 r + j
+      // (tap 2 (4 r + j) + c), so K = 5 needs two MFMAs and K = 4 one
+      static_for<0, 2>([&](auto CK) {
+        constexpr int c = decltype(CK)::value;
+        const int par = c == 0 ? fpar : apar;
+        u32x4 A[LF.nct][1];
+        f32x4 bias1[LF.nct];
+#pragma unroll
+        for (int ct = 0; ct < LF.nct; ++ct) {
+          bias1[ct] = HB ? hb1[ct] : load_bias4<C>(pl + off_b1, ct, j);
+          A[ct][0] = Cfg::A1L ? a1s[(ct * LF.k1 + c) * 64 + lane] : fr[(LF.off1 + ct * LF.k1 + c) * 64];
+        }
+        mma_tiles<Cfg::TU, LF.nct, 1, false, c == 0 ? 2 : 1>(
+            V / 32, w, NW, A, bias1,
+            [&](int tile, int) {
+              const int n = G::half_site(tile * 16 + m, par), p = LY::idx(n);
+              u32x4 bop;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int t = 2 * (4 * r + j) + c;
+                const bool ok = t < T;
+                bop[r] = __float_as_uint(xs[LY::nbr(n, p, ok ? t : c, 1)] * (ok ? 1.f : 0.f));
+              }
+              return bop;
+            },
+            [&](int tile, const f32x4(&acc)[LF.nct]) {
+              const int p = LY::idx(G::half_site(tile * 16 + m, par));
+#pragma unroll
+              for (int ct = 0; ct < LF.nct; ++ct) {
+                const int c0 = ct * 16 + 4 * j;
+                if (c0 < C) {
+                  f32x4 v;
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) v[i] = leaky(acc[ct][i]);
+                  *reinterpret_cast<f32x4*>(h1s + LY::template off<C>(p, c0)) = v;
+                }
+              }
+            });
+      });
+    } else {
       u32x4 A[LF.nct][LF.k1];
       f32x4 bias1[LF.nct];
 #pragma unroll

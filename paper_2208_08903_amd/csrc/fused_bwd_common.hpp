@@ -85,20 +85,20 @@ __global__ void kf_gz(int64_t n, const float* __restrict__ gx, const float* __re
 // quad (FP32 fused backward): conv3 and conv1^T in the 4x4-block layout
 inline FragTable bwd_table(const FlowGeom& g, bool bf16, bool x4, bool quad = false) {
   const int T = g.T, C = g.C;
-  const LayerFrags lf = layer_frags(T, C, bf16, x4, quad);
+  // FP32 2D: conv1 and conv3^T by site parity (one block per parity of the taps)
+  const int ps = !bf16 && T == 9 ? 1 : 0;
+  const LayerFrags lf = layer_frags(T, C, bf16, x4, quad, ps);
   const int kt3 = bf16 ? kchunks_bf16(2 * T) : kblocks_f32(2 * T);
   const int k1t = quad ? T * C / 4 : lf.k2;
   const int q = quad ? 1 : 0;
   FragTable t{};
   int n = 0;
-  t.s[n++] = FragSpec{0, (int)g.off_W1, 1, C, C, lf.nct, lf.k1, lf.off1, 1, 0, 0};
+  t.s[n++] = FragSpec{0, (int)g.off_W1, 1, C, C, lf.nct, lf.k1, lf.off1, ps ? 0 : 1, 0, 0, ps};
   t.s[n++] = FragSpec{0, (int)g.off_W2, C, C, C, lf.nct, lf.k2, lf.off2, 0, 0, 0};
   t.s[n++] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, lf.k3, lf.off3, 0, 0, q};
   if (lf.x4)
     for (int u = 1; u < 4; ++u)
       t.s[n++] = FragSpec{0, (int)g.off_W3, C, 2, 2, 1, lf.k2, lf.off3q + (u - 1) * lf.k2, 0, 4 * u, 0};
-  // FP32 2D: conv3^T by site parity (one chunk per parity of the taps)
-  const int ps = !bf16 && T == 9 ? 1 : 0;
   t.s[n++] = FragSpec{1, (int)g.off_W3, C, 2, C, lf.nct, kt3, lf.total, 0, 0, 0, ps};
   t.s[n++] = FragSpec{1, (int)g.off_W2, C, C, C, lf.nct, lf.k2, lf.total + lf.nct * kt3, 0, 0, 0};
   t.s[n++] = FragSpec{1, (int)g.off_W1, 1, C, 1, 1, k1t, lf.total + lf.nct * kt3 + lf.nct * lf.k2, 0, 0, q};

@@ -391,11 +391,12 @@ struct LayerFrags {
   int off3q;
 };
 
+// ps1 (FP32 2D backward): conv1's fragments split by tap parity, one block each
 __host__ __device__ constexpr LayerFrags layer_frags(int T, int C, bool bf16, bool x4 = false,
-                                                     bool quad = false) {
+                                                     bool quad = false, bool ps1 = false) {
   LayerFrags f{};
   f.nct = C >= 16 ? C / 16 : 1;
-  f.k1 = bf16 ? kchunks_bf16(k_tri(T)) : kblocks_f32(k_tri(T));
+  f.k1 = ps1 ? 2 : bf16 ? kchunks_bf16(k_tri(T)) : kblocks_f32(k_tri(T));
   f.k2 = bf16 ? kchunks_bf16(T * C) : kblocks_f32(T * C);
   f.quad = quad;
   f.k3 = quad ? T * C / 4 : f.k2;
