@@ -912,6 +912,28 @@ __global__ void __launch_bounds__(NT, (BwdCfg<DIM, L, C, BF16>::MINW)) kf_backwa
               acc2[(mt * T + TAP) * MT + nt] = mfma(as_bf16x8(a), as_bf16x8(bb), acc2[(mt * T + TAP) * MT + nt]);
             }
           });
+        } else if constexpr (DIM == 2 && LY::quad_major && !LY::padded && L % 16 == 0 && C == 16) {
+          // A 16-site chunk lies in one row: the lane's four sites x0 .. x0 + 3 and,
+          // per tap row, the six columns x0 - 1 .. x0 + 4 they reach, read once each
+          // (four sites of one channel are 16 bytes apart, so the middle four are two
+          // paired reads; only the two edge columns wrap)
+          const int y = (kc * 16) / L, x0 = (kc * 16) % L + 4 * j;
+          const float* ap = h1s + LY::template off<C>(y * L + x0, m);
+          const float av[4] = {ap[0], ap[4], ap[8], ap[12]};
+          static_for<0, 3>([&](auto DY) {
+            constexpr int dyi = decltype(DY)::value;  // taps 3 dyi .. 3 dyi + 2: row offset dyi - 1
+            const int rs = ((y - (dyi - 1)) & (L - 1)) * L;
+            const float* bp = ga2s + LY::template off<C>(rs + x0, m);
+            const float bv[6] = {ga2s[LY::template off<C>(rs + ((x0 - 1) & (L - 1)), m)], bp[0], bp[4], bp[8], bp[12],
+                                 ga2s[LY::template off<C>(rs + ((x0 + 4) & (L - 1)), m)]};
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+              for (int dxi = 0; dxi < 3; ++dxi) {
+                // site x0 + r minus the tap's column offset dxi - 1: column index r - dxi + 2 of bv
+                acc2[3 * dyi + dxi] = mfma(av[r], bv[r - dxi + 2], acc2[3 * dyi + dxi]);
+              }
+          });
         } else {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
